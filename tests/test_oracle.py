@@ -1,0 +1,308 @@
+"""Pins for the CPU oracle (no GPU).
+
+Each check ties the oracle to something other than itself: values printed in
+the paper's worked examples (tests/golden/paper_examples.json), Theorem 1 on
+random inputs, brute-force polynomial arithmetic on tiny inputs, scipy's
+grey-scale morphology routines, the paper's own FFT formulation of Steps
+1-3, and the algebraic invariants of dilation/erosion.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+import scipy.ndimage as ndi
+
+import oracle
+from paper_2305_03018_amd import synthetic
+
+GOLD = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "paper_examples.json")))
+
+
+def embed_1d(values, origin):
+    """A 1-D SE with an arbitrary origin -> the centre row of a k x k SE
+    (odd k, origin at the centre), other rows masked out."""
+    n = len(values)
+    r = max(origin, n - 1 - origin)
+    k = 2 * r + 1
+    mask = np.zeros((k, k), np.uint8)
+    off = np.zeros((k, k), np.int32)
+    for idx, v in enumerate(values):
+        if v is None:
+            continue
+        j = idx - origin + r
+        mask[r, j] = 1
+        off[r, j] = v
+    return mask, off
+
+
+def ex2():
+    e = GOLD["example2"]
+    f = np.array([e["f"]], np.int32)
+    mask, off = embed_1d(e["b"], e["b_origin"])
+    return f, mask, off
+
+
+# ----------------------------------------------------------------------------
+# worked examples printed in the paper
+# ----------------------------------------------------------------------------
+def test_example2_dilation_all_oracles():
+    f, mask, off = ex2()
+    want = GOLD["example2"]["dilation"]
+    assert oracle.dilate(f, mask, off)[0].tolist() == want
+    assert oracle.poly_dilate(f, mask, off)[0].tolist() == want
+    assert oracle.method_dilate(f, mask, off)[0].tolist() == want
+
+
+def test_example2_erosion_hand_derived():
+    f, mask, off = ex2()
+    L = 8  # tonal range {0..7} of Example 2's image
+    assert oracle.erode(f, mask, off, L)[0].tolist() == GOLD["example2_erosion_derived"]["erosion"]
+
+
+def test_example3_umbras():
+    e3 = GOLD["example3"]
+    f = np.array(GOLD["example2"]["f"])
+    b = GOLD["example2"]["b"]
+    fU = oracle.umbra(f, np.ones(f.shape, bool), e3["lR"])          # (6, 10)
+    assert np.array_equal(fU.T[::-1].astype(int), np.array(e3["f_um_printed"]))
+    bvals = np.array([0 if v is None else v for v in b])
+    bvalid = np.array([v is not None for v in b])
+    bU = oracle.umbra(bvals, bvalid, e3["lR"])
+    assert np.array_equal(bU.T[::-1].astype(int), np.array(e3["b_um_printed"]))
+
+
+def test_example4_and_5_coefficients():
+    f, mask, off = ex2()
+    nd = GOLD["example3"]["lR"] + 1
+    c = oracle.counts(f, mask, off, nd)[0]                      # (6, 10)
+    printed = np.array(GOLD["example5"]["conv_printed"])        # (10, 6), top = grey 9
+    assert np.array_equal(c.T[::-1], printed)
+    x = GOLD["example4"]["x"]
+    assert c[x][::-1].tolist() == GOLD["example4"]["column_printed"]
+    conv, lR = oracle.method_umbra_conv(f, mask, off)
+    assert lR == GOLD["example3"]["lR"]
+    assert np.array_equal(np.rint(conv[0]).astype(int).T[::-1], printed)
+
+
+# ----------------------------------------------------------------------------
+# Theorem 1 and brute-force polynomial products
+# ----------------------------------------------------------------------------
+def test_theorem1_random():
+    rng = np.random.default_rng(5)
+    for _ in range(300):
+        m = int(rng.integers(2, 9))
+        a = [float("-inf") if rng.random() < 0.2 else int(v) for v in rng.integers(0, 12, m)]
+        b = [float("-inf") if rng.random() < 0.2 else int(v) for v in rng.integers(0, 12, m)]
+        want = max(x + y for x, y in zip(a, b))
+        assert oracle.maxplus_by_polynomials(a, b) == want
+
+
+def test_degree_and_inverse():
+    assert oracle.delta([]) == float("-inf")
+    assert oracle.delta([0, 0]) == float("-inf")
+    assert oracle.delta([3, 0, 2, 0]) == 2
+    for a in [float("-inf"), 0, 1, 7]:
+        assert oracle.delta(oracle.delta_inv(a)) == a
+    assert oracle.poly_mul([1, 2], [3, 0, 1]) == [3, 6, 1, 2]
+
+
+def test_definition_matches_polynomials_tiny():
+    rng = np.random.default_rng(11)
+    for _ in range(60):
+        H, W = (int(v) for v in rng.integers(1, 6, 2))
+        k = int(rng.integers(0, 3)) * 2 + 1
+        L = int(rng.integers(2, 7))
+        job = synthetic.random_job(rng, H, W, L, k, p=float(rng.uniform(0.2, 1.0)),
+                                   max_off=int(rng.integers(0, 4)))
+        d = oracle.dilate(job.img, job.mask, job.off)
+        assert np.array_equal(d, oracle.poly_dilate(job.img, job.mask, job.off))
+        if job.mask.any():
+            assert np.array_equal(d, oracle.method_dilate(job.img, job.mask, job.off))
+
+
+def test_method_fft_matches_definition_small():
+    rng = np.random.default_rng(12)
+    for _ in range(8):
+        H, W = (int(v) for v in rng.integers(8, 40, 2))
+        k = int(rng.integers(1, 5)) * 2 + 1
+        job = synthetic.random_job(rng, H, W, 16, k, p=0.6, max_off=5)
+        if not job.mask.any():
+            continue
+        assert np.array_equal(oracle.dilate(job.img, job.mask, job.off),
+                              oracle.method_dilate(job.img, job.mask, job.off))
+
+
+# ----------------------------------------------------------------------------
+# library routines
+# ----------------------------------------------------------------------------
+def test_nonflat_vs_scipy_grey_morphology():
+    rng = np.random.default_rng(3)
+    for _ in range(25):
+        H, W = (int(v) for v in rng.integers(5, 30, 2))
+        k = int(rng.integers(0, 4)) * 2 + 1
+        L = 32
+        job = synthetic.random_job(rng, H, W, L, k, p=0.6, max_off=9)
+        job.mask[k // 2, k // 2] = 1     # scipy needs a non-empty window everywhere
+        fp = job.mask.astype(bool)
+        g = ndi.grey_dilation(job.img.astype(np.float64), footprint=fp,
+                              structure=job.off.astype(np.float64), mode="constant", cval=-1e9)
+        assert np.array_equal(oracle.dilate(job.img, job.mask, job.off), g.astype(np.int32))
+        e = ndi.grey_erosion(job.img.astype(np.float64), footprint=fp,
+                             structure=job.off.astype(np.float64), mode="constant", cval=1e9)
+        assert np.array_equal(oracle.erode(job.img, job.mask, job.off, L), e.astype(np.int32))
+
+
+def test_flat_square_is_moving_max():
+    rng = np.random.default_rng(4)
+    img = rng.integers(0, 256, (37, 53)).astype(np.int32)
+    for k in (1, 3, 7, 11):
+        mask = np.ones((k, k), np.uint8)
+        off = np.zeros((k, k), np.int32)
+        mx = ndi.maximum_filter(img, size=k, mode="constant", cval=-1)
+        mn = ndi.minimum_filter(img, size=k, mode="constant", cval=1 << 20)
+        assert np.array_equal(oracle.dilate(img, mask, off), mx)
+        assert np.array_equal(oracle.erode(img, mask, off, 256), mn)
+
+
+# ----------------------------------------------------------------------------
+# invariants
+# ----------------------------------------------------------------------------
+def test_identity_and_constant_shift_1x1():
+    rng = np.random.default_rng(6)
+    img = rng.integers(0, 64, (20, 31)).astype(np.int32)
+    one = np.ones((1, 1), np.uint8)
+    assert np.array_equal(oracle.dilate(img, one, np.zeros((1, 1), np.int32)), img)
+    assert np.array_equal(oracle.erode(img, one, np.zeros((1, 1), np.int32), 64), img)
+    assert np.array_equal(oracle.dilate(img, one, np.full((1, 1), 5, np.int32)), img + 5)
+    assert np.array_equal(oracle.erode(img, one, np.full((1, 1), 5, np.int32), 64), img - 5)
+
+
+def test_duality_both_forms():
+    rng = np.random.default_rng(7)
+    for trial in range(20):
+        H, W = (int(v) for v in rng.integers(4, 25, 2))
+        k = int(rng.integers(0, 4)) * 2 + 1
+        L = int(rng.choice([4, 16, 256]))
+        job = synthetic.random_job(rng, H, W, L, k, p=0.5, max_off=L // 4)
+        refl_m, refl_o = job.mask[::-1, ::-1].copy(), job.off[::-1, ::-1].copy()
+        ero = oracle.erode(job.img, job.mask, job.off, L)
+        # complement form (Sec. 2.1): (-f) = l - f; holds for every mask
+        comp = (L - 1) - oracle.dilate((L - 1) - job.img, refl_m, refl_o)
+        assert np.array_equal(ero, comp)
+        # plain negation form: holds wherever the window is non-empty
+        job.mask[k // 2, k // 2] = 1
+        refl_m = job.mask[::-1, ::-1].copy()
+        ero = oracle.erode(job.img, job.mask, job.off, L)
+        neg = -oracle.dilate(-job.img, refl_m, refl_o)
+        assert np.array_equal(ero, neg)
+
+
+def test_empty_windows_and_empty_mask():
+    img = np.arange(12, dtype=np.int32).reshape(2, 6) % 7
+    mask = np.zeros((5, 5), np.uint8)
+    mask[0, 0] = 1          # y = (-2, -2): x - y is outside a 2-row image for every x
+    off = np.zeros((5, 5), np.int32)
+    assert (oracle.dilate(img, mask, off) == 0).all()
+    assert (oracle.erode(img, mask, off, 7) == 6).all()
+    zero = np.zeros((3, 3), np.uint8)
+    assert (oracle.dilate(img, zero, np.zeros((3, 3), np.int32)) == 0).all()
+    assert (oracle.erode(img, zero, np.zeros((3, 3), np.int32), 7) == 6).all()
+
+
+def test_monotone_in_image_and_se():
+    rng = np.random.default_rng(8)
+    for _ in range(10):
+        job = synthetic.random_job(rng, 19, 23, 16, 5, p=0.7, max_off=4)
+        g = job.img + rng.integers(0, 3, job.img.shape).astype(np.int32)
+        assert (oracle.dilate(job.img, job.mask, job.off) <= oracle.dilate(g, job.mask, job.off)).all()
+        off2 = job.off + rng.integers(0, 3, job.off.shape).astype(np.int32) * job.mask
+        assert (oracle.dilate(job.img, job.mask, job.off) <= oracle.dilate(job.img, job.mask, off2)).all()
+        m2 = np.maximum(job.mask, (rng.random(job.mask.shape) < 0.3).astype(np.uint8))
+        assert (oracle.dilate(job.img, job.mask, job.off) <= oracle.dilate(job.img, m2, job.off * job.mask)).all()
+
+
+def test_translation_invariance_interior():
+    rng = np.random.default_rng(9)
+    job = synthetic.random_job(rng, 40, 40, 32, 7, p=0.6, max_off=8)
+    dy, dx = 3, -2
+    shifted = np.roll(job.img, (dy, dx), axis=(0, 1))
+    a = oracle.dilate(job.img, job.mask, job.off)
+    b = oracle.dilate(shifted, job.mask, job.off)
+    m = 10  # far enough from the border and from the wrapped rows/columns
+    assert np.array_equal(np.roll(a, (dy, dx), axis=(0, 1))[m:-m, m:-m], b[m:-m, m:-m])
+
+
+def test_grey_shift():
+    rng = np.random.default_rng(10)
+    job = synthetic.random_job(rng, 21, 17, 16, 5, p=0.6, max_off=3)
+    job.mask[2, 2] = 1
+    a = oracle.dilate(job.img, job.mask, job.off)
+    assert np.array_equal(oracle.dilate(job.img + 4, job.mask, job.off), a + 4)
+    assert np.array_equal(oracle.dilate(job.img, job.mask, job.off + 3 * job.mask), a + 3)
+
+
+# ----------------------------------------------------------------------------
+# exact coefficients, sampled evaluation, range spectrum reference
+# ----------------------------------------------------------------------------
+def test_counts_invariants_and_fft_method():
+    rng = np.random.default_rng(13)
+    job = synthetic.random_job(rng, 23, 29, 16, 7, p=0.6, max_off=4)
+    job.mask[3, 3] = 1
+    nd = 16 + 4
+    c = oracle.counts(job.img, job.mask, job.off, nd)
+    assert (c >= 0).all()
+    # sum over degrees = number of SE cells whose x - y lies in the image
+    H, W = job.img.shape
+    inside = ndi.correlate(np.ones((H, W), np.int64), job.mask[::-1, ::-1].astype(np.int64),
+                           mode="constant", cval=0)
+    assert np.array_equal(c.sum(-1), inside)
+    top = nd - 1 - np.argmax((c > 0)[..., ::-1], axis=-1)
+    assert np.array_equal(top, oracle.dilate(job.img, job.mask, job.off))
+    conv, lR = oracle.method_umbra_conv(job.img, job.mask, job.off)
+    assert np.array_equal(np.rint(conv).astype(np.int32), c[..., :lR + 1])
+    assert (c[..., lR + 1:] == 0).all()
+
+
+def test_at_matches_full():
+    rng = np.random.default_rng(14)
+    job = synthetic.random_job(rng, 31, 45, 32, 9, p=0.5, max_off=8)
+    ys = rng.integers(0, 31, 200)
+    xs = rng.integers(0, 45, 200)
+    d = oracle.dilate(job.img, job.mask, job.off)
+    e = oracle.erode(job.img, job.mask, job.off, 32)
+    assert np.array_equal(oracle.at(job.img, job.mask, job.off, 32, 0, ys, xs), d[ys, xs])
+    assert np.array_equal(oracle.at(job.img, job.mask, job.off, 32, 1, ys, xs), e[ys, xs])
+
+
+def test_range_spectrum_ref():
+    rng = np.random.default_rng(15)
+    c = rng.integers(0, 5, (7, 13)).astype(np.float64)
+    nr = 20
+    Y = oracle.range_spectrum_ref(c, nr)
+    assert Y.shape == (7, nr // 2 + 1)
+    assert np.allclose(Y[:, 0], c.sum(-1))
+    padded = np.zeros((7, nr))
+    padded[:, :13] = c
+    assert np.allclose(Y, np.fft.fft(padded, axis=-1)[:, :nr // 2 + 1])
+    # inverse by the real-signal sum recovers the coefficients
+    m = np.arange(nr // 2 + 1)
+    w = np.where((m == 0) | (m == nr // 2), 1.0, 2.0)
+    d = np.arange(nr)
+    rec = (Y * w) @ np.exp(2j * np.pi * np.outer(m, d) / nr) / nr
+    assert np.allclose(rec.real[:, :13], c) and np.allclose(rec.real[:, 13:], 0)
+
+
+def test_synthetic_recipes_shapes():
+    j = synthetic.small_uniform()
+    assert j.img.shape == (64, 64) and j.img.max() <= 15 and j.k == 7 and j.off.max() <= 3
+    j = synthetic.blurred_512()
+    assert j.img.shape == (512, 512) and j.img.min() == 0 and j.img.max() == 15
+    assert int(j.mask.sum()) == 149 and j.off.max() <= 7
+    assert int(synthetic.disk_mask(31).sum()) == 709 and int(synthetic.disk_mask(41).sum()) == 1257
+    jobs = synthetic.uneven_batch(0, 16)
+    for jb in jobs:
+        assert 128 <= jb.img.shape[0] <= 1024 and 128 <= jb.img.shape[1] <= 1024
+        assert jb.L in (8, 16, 32, 64) and jb.img.max() < jb.L
+        assert jb.k % 2 == 1 and 3 <= jb.k <= 41 and jb.off.max() <= jb.L // 4
+        assert (jb.off[jb.mask == 0] == 0).all()
