@@ -1,0 +1,162 @@
+/*
+ * md.h -- exact grey-scale morphological dilation / erosion on AMD Instinct
+ * MI355X (gfx950) through the max-plus -> polynomial homomorphism of
+ * Sridhar, Shahin, Breuss, Reichenbach, "The Polynomial Connection between
+ * Morphological Dilation and Discrete Convolution" (arXiv 2305.03018).
+ *
+ * Method (Sec. 3, Steps 1-3): each grey value v becomes the monomial t^v
+ * (the one-hot "umbra" column of Eqs. (7)-(8)); image and structuring
+ * element (SE) are multiplied as polynomials by a linear convolution over the
+ * two image axes and the grey ("range") axis (Step 2, computed here with
+ * FFTs); the dilated value of a pixel is the highest degree whose rounded
+ * coefficient is non-zero (Step 3, Eq. (9)).  Theorem 1 (Sec. 2.2) makes the
+ * result exact: it equals max { f(x-y) + b(y) : y in B, x-y in F }
+ * (Sec. 2.1, Eq. (6new)), and 0 where that set is empty (Eq. (6)).
+ * Erosion follows by the duality of Sec. 2.1.
+ *
+ * Conventions shared by every entry point
+ *   - Images are row-major H x W int32 arrays in DEVICE memory (a HIP
+ *     allocation on the current device); `out` has the same shape and must
+ *     not overlap `img`.  The caller owns both.
+ *   - The SE is given as two k x k row-major HOST arrays: `se_mask` (uint8,
+ *     non-zero = the cell belongs to the SE domain B) and `se_offsets`
+ *     (int32 additive offsets b(y) >= 0, ignored where the mask is 0).  k is
+ *     odd and the origin is the centre cell, so cell (i, j) is the offset
+ *     y = (i - r, j - r), r = (k-1)/2.  A non-flat SE has offsets > 0, a flat
+ *     one has all offsets 0 (Sec. 2.1).  The library copies what it needs;
+ *     the host arrays may be freed when the call returns.
+ *   - Image values must lie in [0, L-1], L >= 2 (the tonal range of
+ *     Sec. 2.1, l = L-1).
+ *   - Dilation:  out(x) = max { img(x-y) + b(y) : y in B, x-y in image },
+ *                 0 where no cell qualifies (Eq. (6new), Eq. (6)).
+ *     Erosion:   out(x) = min { img(x+y) - b(y) : y in B, x+y in image },
+ *                 L-1 where no cell qualifies (Eq. (Erosion); the empty case
+ *                 is not fixed by the paper and is chosen so that
+ *                 erosion(f, b) = (L-1) - dilation((L-1) - f, reflected b)
+ *                 holds everywhere, the complement duality of Sec. 2.1).
+ *                 Erosion values can be negative, down to -max(b).
+ *   - Results are exact integers for every precision setting.
+ *   - Work is enqueued on the stream set by md_set_stream (default: the null
+ *     stream).  With MD_OPT_SYNC = 1 (default) a call waits for its work and
+ *     reports device-side errors and statistics; with 0 it returns after
+ *     enqueueing (statistics then refer to the previous synchronised call).
+ *   - Every function returns an md_status (0 = success).  No C++ exception
+ *     crosses this interface.  On MD_ERR_ARG / MD_ERR_RANGE detected on the
+ *     host nothing is enqueued and `out` is untouched.  An image value outside
+ *     [0, L-1] is detected on the device: the call returns MD_ERR_RANGE (when
+ *     synchronous) and the contents of `out` are unspecified.
+ *   - The library is not thread-safe: serialise calls from several host
+ *     threads.
+ */
+#ifndef MD_H_
+#define MD_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    MD_OK = 0,
+    MD_ERR_ARG = -1,          /* bad shape, pointer, k, L or option value        */
+    MD_ERR_RANGE = -2,        /* image value outside [0, L-1] or negative offset */
+    MD_ERR_NOMEM = -3,        /* device allocation failed                        */
+    MD_ERR_DEVICE = -4,       /* a HIP runtime call failed                       */
+    MD_ERR_UNSUPPORTED = -5   /* no plan covers this shape / forced setting      */
+} md_status;
+
+/* Option keys for md_set_option / md_get_option. */
+typedef enum {
+    MD_OPT_PRECISION = 0,  /* 0: FP32 transforms with split hi/lo twiddles and FP64
+                              recompute of ambiguous tiles (default);
+                              1: plain FP64 transforms everywhere                */
+    MD_OPT_BAND = 1,       /* ambiguity band: a tile whose decoded coefficient c
+                              has |c - rint(c)| >= band is recomputed (default
+                              0.25; 0 forces every tile through the recompute)   */
+    MD_OPT_PATH = 2,       /* 0: auto (cost model), 1: FFT convolution of umbras,
+                              2: direct max-plus window (classical, Eq. (6new)) */
+    MD_OPT_TILE = 3,       /* 0: auto, else the spatial FFT length per tile axis
+                              (16, 32, 64 or 128; 128 only in FP32)             */
+    MD_OPT_NR = 4,         /* 0: auto, else the range-axis DFT length; must be at
+                              least (L-1) + max offset + 1                       */
+    MD_OPT_SYNC = 5,       /* 1 (default): wait for completion in every call    */
+    MD_OPT_GRAPH = 6,      /* 1 (default): md_dilate_batch captures its launches
+                              in a HIP graph per batch signature and replays it  */
+    MD_OPT_WORKSPACE_MB = 7/* cap on the transform-domain scratch per launch
+                              group, MiB (default 8192)                           */
+} md_option;
+
+/* Dilation of one image (see the conventions above). */
+int md_dilate(const int32_t *img, int H, int W, int L, const uint8_t *se_mask,
+              const int32_t *se_offsets, int k, int32_t *out);
+
+/* Erosion of one image (see the conventions above). */
+int md_erode(const int32_t *img, int H, int W, int L, const uint8_t *se_mask,
+             const int32_t *se_offsets, int k, int32_t *out);
+
+/* One job of a batch.  Pointer and ownership rules as for md_dilate. */
+typedef struct {
+    const int32_t *img;          /* device, H x W                 */
+    int H, W, L;
+    const uint8_t *se_mask;      /* host, k x k                   */
+    const int32_t *se_offsets;   /* host, k x k                   */
+    int k;
+    int32_t *out;                /* device, H x W                 */
+    int op;                      /* 0 = dilation, 1 = erosion     */
+} md_job;
+
+/* Many images of uneven size, tonal range and SE in one go.  The planner
+ * picks per job the transform lengths, tile shape and the FFT-versus-direct
+ * path; the launches are stage-wise persistent kernels over device work
+ * queues.  With MD_OPT_GRAPH = 1 they are captured once per batch signature
+ * (shapes, L, k, SEs, op) into a HIP graph and replayed; image and output
+ * pointers may change between calls with the same signature.  n >= 1.
+ * `jobs` is a host array read during the call only. */
+int md_dilate_batch(const md_job *jobs, int n);
+
+/* Stream for subsequent calls (a hipStream_t, or NULL for the null stream). */
+int md_set_stream(void *hip_stream);
+
+int md_set_option(int key, double value);
+double md_get_option(int key);  /* NaN for an unknown key */
+
+/* Statistics of the last synchronised call. */
+typedef struct {
+    double max_residual;      /* max |c - rint(c)| over decoded coefficients (FFT path) */
+    long long tiles;          /* FFT tiles processed                                     */
+    long long fallback_tiles; /* tiles recomputed by the exact fallback                  */
+    long long unresolved_tiles; /* tiles that hit the band with no recompute available
+                                 (FP64 mode); 0 in every measured run                   */
+    long long direct_jobs;    /* jobs that took the direct path                          */
+    long long fft_jobs;       /* jobs that took the FFT path                             */
+    int path, n_t, n_r;       /* plan of the last job: path 1 FFT / 2 direct, lengths    */
+    int precision;            /* 0 FP32 + fallback, 1 FP64                               */
+} md_stats;
+
+int md_get_stats(md_stats *stats);
+
+/* Text of the last error (never NULL; empty after success). */
+const char *md_last_error(void);
+
+/* Release every device buffer, cached plan, spectrum and graph. */
+int md_release(void);
+
+/* Test hook: per-bin transform-domain values of one tile just before the
+ * inverse range transform, for measuring spectrum error against an FP64
+ * reference.  Runs the FFT path of md_dilate (op 0) on `img` with the given
+ * plan (n_t, n_r must be valid for k and L) and copies, for tile (ty, tx),
+ * the values Y[m][p], m < n_r/2+1, p < T*T (T = n_t - k + 1, row-major over
+ * the tile's T x T outputs starting at pixel (ty*T, tx*T)), scaled by
+ * 1/n_t^2, into the HOST array `dst` as interleaved (re, im) doubles.
+ * `dst` must hold 2*(n_r/2+1)*T*T doubles.  precision: 0 FP32, 1 FP64. */
+int md_debug_tile_values(const int32_t *img, int H, int W, int L, const uint8_t *se_mask,
+                         const int32_t *se_offsets, int k, int n_t, int n_r, int precision,
+                         int ty, int tx, double *dst);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MD_H_ */

@@ -1,0 +1,32 @@
+"""Exact grey-scale dilation / erosion on MI355X (gfx950) by the polynomial
+(umbra) convolution method of arXiv 2305.03018.
+
+This package is a thin binding over the C ABI of ``include/md.h`` (library
+``libmd.so`` built by ``build.py``): it marshals torch device tensors and
+numpy SE arrays into the C calls; every step of the computation runs in the
+library's HIP kernels.  There is no CPU fallback: calling into the library
+without a built ``libmd.so`` raises.
+"""
+from ._binding import (  # noqa: F401
+    MDError,
+    OPT_BAND,
+    OPT_GRAPH,
+    OPT_NR,
+    OPT_PATH,
+    OPT_PRECISION,
+    OPT_SYNC,
+    OPT_TILE,
+    OPT_WORKSPACE_MB,
+    debug_tile_values,
+    dilate,
+    dilate_batch,
+    erode,
+    exported_symbols,
+    get_option,
+    get_stats,
+    library_path,
+    load,
+    options,
+    release,
+    set_option,
+)

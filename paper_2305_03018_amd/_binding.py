@@ -1,0 +1,233 @@
+"""ctypes binding of libmd.so (include/md.h).  Argument marshalling only."""
+from __future__ import annotations
+
+import contextlib
+import ctypes
+import os
+import re
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_PKG, "libmd.so")
+_HEADER = os.path.join(os.path.dirname(_PKG), "include", "md.h")
+_lib = None
+
+OPT_PRECISION, OPT_BAND, OPT_PATH, OPT_TILE, OPT_NR, OPT_SYNC, OPT_GRAPH, OPT_WORKSPACE_MB = range(8)
+_OPT_NAMES = {"precision": OPT_PRECISION, "band": OPT_BAND, "path": OPT_PATH, "tile": OPT_TILE,
+              "nr": OPT_NR, "sync": OPT_SYNC, "graph": OPT_GRAPH, "workspace_mb": OPT_WORKSPACE_MB}
+_STATUS = {0: "MD_OK", -1: "MD_ERR_ARG", -2: "MD_ERR_RANGE", -3: "MD_ERR_NOMEM",
+           -4: "MD_ERR_DEVICE", -5: "MD_ERR_UNSUPPORTED"}
+
+
+class MDError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{_STATUS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class _Job(ctypes.Structure):
+    _fields_ = [("img", ctypes.c_void_p), ("H", ctypes.c_int), ("W", ctypes.c_int), ("L", ctypes.c_int),
+                ("se_mask", ctypes.c_void_p), ("se_offsets", ctypes.c_void_p), ("k", ctypes.c_int),
+                ("out", ctypes.c_void_p), ("op", ctypes.c_int)]
+
+
+class _Stats(ctypes.Structure):
+    _fields_ = [("max_residual", ctypes.c_double), ("tiles", ctypes.c_longlong),
+                ("fallback_tiles", ctypes.c_longlong), ("unresolved_tiles", ctypes.c_longlong),
+                ("direct_jobs", ctypes.c_longlong), ("fft_jobs", ctypes.c_longlong),
+                ("path", ctypes.c_int), ("n_t", ctypes.c_int), ("n_r", ctypes.c_int),
+                ("precision", ctypes.c_int)]
+
+
+def library_path() -> str:
+    return _LIB_PATH
+
+
+def load():
+    """Load libmd.so; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB_PATH):
+        raise MDError(-4, f"{_LIB_PATH} is not built (run __graft_entry__.build())")
+    lib = ctypes.CDLL(_LIB_PATH)
+    vp, i, u8 = ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p
+    for name in ("md_dilate", "md_erode"):
+        f = getattr(lib, name)
+        f.argtypes = [vp, i, i, i, u8, vp, i, vp]
+        f.restype = i
+    lib.md_dilate_batch.argtypes = [ctypes.POINTER(_Job), i]
+    lib.md_dilate_batch.restype = i
+    lib.md_set_stream.argtypes = [vp]
+    lib.md_set_stream.restype = i
+    lib.md_set_option.argtypes = [i, ctypes.c_double]
+    lib.md_set_option.restype = i
+    lib.md_get_option.argtypes = [i]
+    lib.md_get_option.restype = ctypes.c_double
+    lib.md_get_stats.argtypes = [ctypes.POINTER(_Stats)]
+    lib.md_get_stats.restype = i
+    lib.md_last_error.argtypes = []
+    lib.md_last_error.restype = ctypes.c_char_p
+    lib.md_release.argtypes = []
+    lib.md_release.restype = i
+    lib.md_debug_tile_values.argtypes = [vp, i, i, i, u8, vp, i, i, i, i, i, i, vp]
+    lib.md_debug_tile_values.restype = i
+    _lib = lib
+    return lib
+
+
+def header_symbols() -> list[str]:
+    """Function names declared in include/md.h."""
+    text = open(_HEADER).read()
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?\w+\s*\*?\s*(md_\w+)\s*\(", text, re.M)))
+
+
+def exported_symbols() -> dict[str, bool]:
+    lib = load()
+    out = {}
+    for name in header_symbols():
+        try:
+            getattr(lib, name)
+            out[name] = True
+        except AttributeError:
+            out[name] = False
+    return out
+
+
+def _check(rc: int):
+    if rc != 0:
+        raise MDError(rc, load().md_last_error().decode())
+
+
+def _se_arrays(mask, off):
+    mask = np.ascontiguousarray(np.asarray(mask), dtype=np.uint8)
+    off = np.ascontiguousarray(np.asarray(off), dtype=np.int32)
+    if mask.ndim != 2 or mask.shape != off.shape or mask.shape[0] != mask.shape[1]:
+        raise ValueError("mask and offsets must be k x k arrays of the same shape")
+    return mask, off
+
+
+def _device_image(img):
+    import torch
+
+    if not isinstance(img, torch.Tensor) or not img.is_cuda:
+        raise TypeError("image must be a torch tensor on a HIP device")
+    if img.dtype != torch.int32 or img.dim() != 2:
+        raise TypeError("image must be a 2-D torch.int32 tensor")
+    return img.contiguous()
+
+
+def _bind_stream(dev):
+    import torch
+
+    load().md_set_stream(ctypes.c_void_p(torch.cuda.current_stream(dev).cuda_stream))
+
+
+def _run_single(fname, img, mask, off, L, out):
+    import torch
+
+    lib = load()
+    img = _device_image(img)
+    mask, off = _se_arrays(mask, off)
+    if out is None:
+        out = torch.empty_like(img)
+    elif out.shape != img.shape or out.dtype != torch.int32 or not out.is_contiguous():
+        raise ValueError("out must be a contiguous int32 tensor shaped like the image")
+    with torch.cuda.device(img.device):
+        _bind_stream(img.device)
+        rc = getattr(lib, fname)(img.data_ptr(), img.shape[0], img.shape[1], int(L),
+                                 mask.ctypes.data, off.ctypes.data, mask.shape[0], out.data_ptr())
+    _check(rc)
+    return out
+
+
+def dilate(img, mask, off, L: int, out=None):
+    """Exact dilation: max over the SE of img(x-y) + b(y), 0 on empty windows."""
+    return _run_single("md_dilate", img, mask, off, L, out)
+
+
+def erode(img, mask, off, L: int, out=None):
+    """Exact erosion: min over the SE of img(x+y) - b(y), L-1 on empty windows."""
+    return _run_single("md_erode", img, mask, off, L, out)
+
+
+def dilate_batch(jobs, outs=None):
+    """jobs: sequence of (img, mask, off, L, op) with op 0 = dilation, 1 =
+    erosion; images are int32 device tensors.  Returns the output tensors."""
+    import torch
+
+    lib = load()
+    n = len(jobs)
+    arr = (_Job * n)()
+    keep = []
+    res = []
+    dev = None
+    for q, (img, mask, off, L, op) in enumerate(jobs):
+        img = _device_image(img)
+        dev = img.device if dev is None else dev
+        mask, off = _se_arrays(mask, off)
+        out = torch.empty_like(img) if outs is None else outs[q]
+        keep.append((img, mask, off))
+        res.append(out)
+        arr[q] = _Job(img.data_ptr(), img.shape[0], img.shape[1], int(L), mask.ctypes.data,
+                      off.ctypes.data, mask.shape[0], out.data_ptr(), int(op))
+    with torch.cuda.device(dev):
+        _bind_stream(dev)
+        rc = lib.md_dilate_batch(arr, n)
+    _check(rc)
+    return res
+
+
+def set_option(key, value: float):
+    key = _OPT_NAMES.get(key, key)
+    _check(load().md_set_option(int(key), float(value)))
+
+
+def get_option(key) -> float:
+    key = _OPT_NAMES.get(key, key)
+    return float(load().md_get_option(int(key)))
+
+
+@contextlib.contextmanager
+def options(**kw):
+    """Temporarily set options by name, e.g. options(precision=1, path=1)."""
+    saved = {k: get_option(k) for k in kw}
+    try:
+        for k, v in kw.items():
+            set_option(k, v)
+        yield
+    finally:
+        for k, v in saved.items():
+            set_option(k, v)
+
+
+def get_stats() -> dict:
+    st = _Stats()
+    _check(load().md_get_stats(ctypes.byref(st)))
+    return {f: getattr(st, f) for f, _ in _Stats._fields_}
+
+
+def release():
+    _check(load().md_release())
+
+
+def debug_tile_values(img, mask, off, L: int, n_t: int, n_r: int, precision: int, ty: int, tx: int):
+    """Per-bin values of one tile before the inverse range transform
+    (see md_debug_tile_values); returns complex128 (n_r//2+1, T*T)."""
+    import torch
+
+    lib = load()
+    img = _device_image(img)
+    mask, off = _se_arrays(mask, off)
+    k = mask.shape[0]
+    T = n_t - k + 1
+    bins = n_r // 2 + 1
+    dst = np.zeros(2 * bins * T * T, np.float64)
+    with torch.cuda.device(img.device):
+        _bind_stream(img.device)
+        rc = lib.md_debug_tile_values(img.data_ptr(), img.shape[0], img.shape[1], int(L), mask.ctypes.data,
+                                      off.ctypes.data, k, int(n_t), int(n_r), int(precision), int(ty), int(tx),
+                                      dst.ctypes.data)
+    _check(rc)
+    return (dst[0::2] + 1j * dst[1::2]).reshape(bins, T * T)

@@ -1,0 +1,110 @@
+// Internal declarations shared by the HIP kernels (md_kernels.hip) and the
+// host runtime (md_runtime.hip).  Not part of the public interface.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace md {
+
+// Length of the full-circle FP64 twiddle table; every spatial FFT length
+// divides it (spatial lengths are powers of two up to kTwN/8).
+constexpr int kTwN = 1024;
+
+// "Minus infinity" of the direct max-plus path: an out-of-image pixel or a
+// masked-out SE cell.  Two of them still sum without overflow.
+constexpr int32_t kNeg = -(1 << 29);
+
+// Geometry of the direct max-plus kernel: each block produces a
+// kDirBH x kDirBW output tile, each thread kDirRX consecutive outputs of a row.
+constexpr int kDirRX = 8;
+constexpr int kDirBW = 128;
+constexpr int kDirBH = 16;
+constexpr int kDirThreads = (kDirBW / kDirRX) * kDirBH;   // 256
+
+// Decode kernel geometry: 64 pixels per block, kDecTPP waves per pixel group.
+constexpr int kDecTPP = 4;
+constexpr int kDecThreads = 64 * kDecTPP;
+
+// FP32 twiddle stored as an unevaluated sum hi + lo of two floats, so that
+// hi + lo carries about 48 significant bits of exp(-2 pi i j / kTwN).
+struct TwF {
+    float2 hi, lo;
+};
+
+enum : int { kPathFFT = 1, kPathDirect = 2 };
+enum : int { kFbNone = 0, kFbFFT64 = 1, kFbDirect = 2 };
+
+// One job as the kernels see it.  Complex arrays are float2 in the FP32 form
+// and double2 in the FP64 form (the `dbl` flag of the job's plan).
+struct JobDev {
+    const int32_t *img;
+    int32_t *out;
+    int H, W, L, k, op;          // op 0 dilation, 1 erosion (complement + reflected SE)
+    int path;                    // kPathFFT / kPathDirect
+    // transform plan
+    int nt, T, nr, bins, tiles_x, tiles_y;
+    int dbl;                     // 1: transforms in FP64
+    double scale;                // 1 / (nt^2 * nr)
+    const void *se_spec;         // [bins][nt][nt] spectrum of the SE umbra
+    const void *enc;             // [bins][L]  exp(-2 pi i (v m mod nr) / nr)
+    const void *dec;             // [nr][bins] w_m exp(+2 pi i d m / nr), w = 1 or 2
+    long long flag0;             // first entry of this job in the tile-flag array
+    // exact recompute of ambiguous tiles
+    int fb_mode;                 // kFbNone / kFbFFT64 / kFbDirect
+    int nt64, T64;
+    double scale64;
+    const double2 *se_spec64;    // [bins][nt64][nt64]
+    const double2 *enc64;        // [bins][L]
+    const double2 *dec64;        // [nr][bins]
+    // direct max-plus path (also the recompute of kFbDirect)
+    const int32_t *sek;          // [k][kpad] offsets in correlation order, kNeg where masked
+    int kpad;
+    int dir_bx, dir_by;          // direct-path blocks per row / column
+};
+
+// A contiguous run of work items of one job.  FFT segments cover
+// ntiles * bins items (tile index fastest), decode segments ntiles * pblocks
+// items, direct segments dir_bx * dir_by items.
+struct Seg {
+    long long item0;             // first global item index of the segment
+    int job;
+    int tile0, ntiles;           // tile range (FFT / decode)
+    int pblocks;                 // decode: ceil(T*T / 64)
+    void *y;                     // transform-domain buffer [ntiles][bins][T*T]
+};
+
+struct StatsDev {
+    unsigned int max_res_bits;   // float bits of the largest rounding residual
+    unsigned int range_err;      // non-zero if an image value was outside [0, L-1]
+    unsigned int fb_count;       // ambiguous tiles appended to the recompute list
+    unsigned int pad;
+};
+
+// ---------------------------------------------------------------------------
+// launchers (md_kernels.hip); all enqueue on `s` and return the launch status
+// ---------------------------------------------------------------------------
+hipError_t launch_twiddles(double2 *tw64, TwF *tw32, hipStream_t s);
+hipError_t launch_range_tables(int nr, int L, float2 *enc32, double2 *enc64, float2 *dec32,
+                               double2 *dec64, hipStream_t s);
+hipError_t launch_se_spectrum(const uint8_t *mask_d, const int32_t *off_d, int k, int nt, int nr,
+                              const double2 *tw64, double2 *work, double2 *spec64, float2 *spec32,
+                              hipStream_t s);
+hipError_t launch_zero(void *p, size_t bytes, hipStream_t s);
+hipError_t launch_fft(int nt, int dbl, const JobDev *jobs, const Seg *segs, int nseg, long long nitems,
+                      int grid, const TwF *tw32, const double2 *tw64, StatsDev *st, hipStream_t s);
+hipError_t launch_decode(int big, int dbl, const JobDev *jobs, const Seg *segs, int nseg,
+                         long long nitems, int grid, float band, unsigned int *tile_flags,
+                         int2 *fb_list, StatsDev *st, hipStream_t s);
+hipError_t launch_direct(const JobDev *jobs, const Seg *segs, int nseg, long long nitems, int grid,
+                         size_t lds_bytes, StatsDev *st, hipStream_t s);
+hipError_t launch_fallback(int nt64, const JobDev *jobs, const int2 *fb_list, const StatsDev *st,
+                           double2 *slots, size_t slot_elems, int grid, const double2 *tw64,
+                           hipStream_t s);
+hipError_t launch_fallback_direct(const JobDev *jobs, const int2 *fb_list, const StatsDev *st,
+                                  int grid, size_t lds_bytes, hipStream_t s);
+size_t direct_lds_bytes(int k, int kpad);
+int fft_block_threads(int nt, int dbl);
+
+}  // namespace md

@@ -1,0 +1,918 @@
+// Host runtime behind the C ABI of include/md.h: argument checks, the
+// planner / cost model, caches of twiddle tables, range tables and SE
+// spectra, the stage-wise executor over device work queues, HIP-graph
+// capture of whole batches, and statistics.
+#include <hip/hip_runtime.h>
+
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <algorithm>
+#include <chrono>
+#include <map>
+#include <memory>
+#include <string>
+#include <unordered_map>
+#include <vector>
+
+#include "md.h"
+#include "md_internal.h"
+
+namespace md {
+namespace {
+
+std::string g_err;
+
+int fail(int code, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+#define MD_HIP(call)                                                                       \
+    do {                                                                                   \
+        hipError_t e_ = (call);                                                            \
+        if (e_ != hipSuccess)                                                              \
+            return fail(e_ == hipErrorOutOfMemory ? MD_ERR_NOMEM : MD_ERR_DEVICE,          \
+                        "%s failed: %s (%s:%d)", #call, hipGetErrorString(e_), __FILE__, __LINE__); \
+    } while (0)
+
+#define MD_TRY(expr)             \
+    do {                         \
+        int rc_ = (expr);        \
+        if (rc_ != MD_OK) return rc_; \
+    } while (0)
+
+struct Options {
+    int precision = 0;
+    double band = 0.25;
+    int path = 0;
+    int tile = 0;
+    int nr = 0;
+    int sync = 1;
+    int graph = 1;
+    double ws_mb = 8192.0;
+};
+
+// Device buffer that only grows.
+struct DevBuf {
+    void *p = nullptr;
+    size_t bytes = 0;
+    int ensure(size_t n) {
+        if (n <= bytes) return MD_OK;
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        bytes = 0;
+        if (n == 0) return MD_OK;
+        MD_HIP(hipMalloc(&p, n));
+        bytes = n;
+        return MD_OK;
+    }
+    void release() {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        bytes = 0;
+    }
+};
+
+struct RangeTables {
+    DevBuf enc32, enc64, dec32, dec64;
+};
+
+struct SESpec {
+    DevBuf s32, s64;
+};
+
+struct DirSE {
+    DevBuf sek;
+    int kpad = 0;
+};
+
+// Per-job plan.
+struct Plan {
+    int path = kPathFFT;
+    int dbl = 0;
+    int nt = 0, T = 0, nr = 0, bins = 0, tiles_x = 0, tiles_y = 0;
+    int fb_mode = kFbNone, nt64 = 0, T64 = 0;
+    double cost_fft = 0, cost_dir = 0;
+};
+
+struct Group {
+    int nt = 0, dbl = 0, big = 0;
+    std::vector<Seg> segs;
+    long long nitems = 0;
+    Seg *segs_d = nullptr;
+    int grid = 0;
+};
+
+struct Wave {
+    std::vector<Group> fft;
+    std::vector<Group> dec;
+};
+
+struct Exec {
+    std::vector<JobDev> jobs_h;
+    std::vector<Plan> plans;
+    JobDev *jobs_d = nullptr;
+    JobDev *jobs_pin = nullptr;
+    hipEvent_t copy_done = nullptr;
+    bool copy_pending = false;
+    Group direct;
+    size_t direct_lds = 0;
+    std::vector<Wave> waves;
+    DevBuf segbuf, ybuf, flags, list, slots;
+    long long nflags = 0;
+    std::vector<int> fb_classes;
+    bool fb_direct = false;
+    size_t fb_direct_lds = 0;
+    size_t slot_elems = 0;
+    int fb_grid = 0;
+    long long fft_tiles = 0;
+    int n_direct = 0, n_fft = 0;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t gexec = nullptr;
+    hipStream_t graph_stream = nullptr;
+    ~Exec() {
+        if (gexec) (void)hipGraphExecDestroy(gexec);
+        if (graph) (void)hipGraphDestroy(graph);
+        if (copy_done) (void)hipEventDestroy(copy_done);
+        if (jobs_pin) (void)hipHostFree(jobs_pin);
+        if (jobs_d) (void)hipFree(jobs_d);
+        segbuf.release();
+        ybuf.release();
+        flags.release();
+        list.release();
+        slots.release();
+    }
+};
+
+// Cost model (nanoseconds of whole-GPU time).  The constants are replaced by
+// measured rates when the autotuner has run on this device.
+struct CostModel {
+    double fft_item[2][8] = {{0, 0, 0, 0, 2.0, 8.0, 30.0, 130.0}, {0, 0, 0, 0, 5.0, 20.0, 75.0, 0.0}};
+    double dec_unit[2] = {1.5e-4, 3.0e-4};   // per pixel * nr * bins
+    double dir_unit = 1.0e-4;                // per pixel * k * kpad
+    double launch = 3000.0;                  // fixed cost per job class
+};
+
+struct Ctx {
+    bool inited = false;
+    int device = -1;
+    int cu = 256;
+    hipStream_t stream = nullptr;
+    Options opt;
+    double2 *tw64 = nullptr;
+    TwF *tw32 = nullptr;
+    StatsDev *st_d = nullptr;
+    StatsDev *st_h = nullptr;
+    md_stats last{};
+    CostModel cost;
+    std::map<std::pair<int, int>, std::unique_ptr<RangeTables>> ranges;
+    std::unordered_map<std::string, std::unique_ptr<SESpec>> spectra;
+    std::unordered_map<std::string, std::unique_ptr<DirSE>> dirse;
+    std::unordered_map<std::string, std::unique_ptr<Exec>> execs;
+    DevBuf se_work, se_in;
+};
+
+Ctx g;
+
+int ilog2i(int n) {
+    int l = 0;
+    while ((1 << l) < n) ++l;
+    return l;
+}
+
+int init() {
+    int dev = 0;
+    MD_HIP(hipGetDevice(&dev));
+    if (g.inited && g.device == dev) return MD_OK;
+    if (g.inited && g.device != dev)
+        return fail(MD_ERR_UNSUPPORTED, "the library was initialised on device %d, now %d is current; call md_release first",
+                    g.device, dev);
+    hipDeviceProp_t prop;
+    MD_HIP(hipGetDeviceProperties(&prop, dev));
+    g.cu = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
+    MD_HIP(hipMalloc(&g.tw64, sizeof(double2) * kTwN));
+    MD_HIP(hipMalloc(&g.tw32, sizeof(TwF) * (kTwN / 2)));
+    MD_HIP(hipMalloc(&g.st_d, sizeof(StatsDev)));
+    MD_HIP(hipHostMalloc((void **)&g.st_h, sizeof(StatsDev), 0));
+    MD_HIP(launch_twiddles(g.tw64, g.tw32, nullptr));
+    MD_HIP(launch_zero(g.st_d, sizeof(StatsDev), nullptr));
+    MD_HIP(hipDeviceSynchronize());
+    g.device = dev;
+    g.inited = true;
+    return MD_OK;
+}
+
+// ---------------------------------------------------------------------------
+// caches
+// ---------------------------------------------------------------------------
+int get_range(int nr, int L, RangeTables **out) {
+    auto key = std::make_pair(nr, L);
+    auto it = g.ranges.find(key);
+    if (it != g.ranges.end()) {
+        *out = it->second.get();
+        return MD_OK;
+    }
+    auto rt = std::make_unique<RangeTables>();
+    const size_t bins = nr / 2 + 1;
+    const size_t ne = bins * (size_t)L, nd = (size_t)nr * bins;
+    MD_TRY(rt->enc32.ensure(ne * sizeof(float2)));
+    MD_TRY(rt->enc64.ensure(ne * sizeof(double2)));
+    MD_TRY(rt->dec32.ensure(nd * sizeof(float2)));
+    MD_TRY(rt->dec64.ensure(nd * sizeof(double2)));
+    MD_HIP(launch_range_tables(nr, L, (float2 *)rt->enc32.p, (double2 *)rt->enc64.p, (float2 *)rt->dec32.p,
+                               (double2 *)rt->dec64.p, g.stream));
+    *out = rt.get();
+    g.ranges[key] = std::move(rt);
+    return MD_OK;
+}
+
+// Effective SE as the transform path uses it: the SE itself for dilation,
+// its reflection for erosion (duality, Sec. 2.1).
+struct SEData {
+    int k = 0;
+    std::vector<uint8_t> mask;
+    std::vector<int32_t> off;   // zero where masked out
+    int maxoff = 0;
+    int ncells = 0;
+    std::string key;
+};
+
+void make_se(const uint8_t *mask, const int32_t *off, int k, int op, SEData &se) {
+    se.k = k;
+    se.mask.assign((size_t)k * k, 0);
+    se.off.assign((size_t)k * k, 0);
+    se.maxoff = 0;
+    se.ncells = 0;
+    for (int i = 0; i < k; ++i)
+        for (int j = 0; j < k; ++j) {
+            const int si = op ? (k - 1 - i) : i, sj = op ? (k - 1 - j) : j;
+            const size_t src = (size_t)si * k + sj, dst = (size_t)i * k + j;
+            if (mask[src]) {
+                se.mask[dst] = 1;
+                se.off[dst] = off[src];
+                se.maxoff = std::max(se.maxoff, (int)off[src]);
+                ++se.ncells;
+            }
+        }
+    se.key.assign((const char *)&k, sizeof k);
+    se.key.append((const char *)se.mask.data(), se.mask.size());
+    se.key.append((const char *)se.off.data(), se.off.size() * sizeof(int32_t));
+}
+
+int get_spectrum(const SEData &se, int nt, int nr, bool need32, bool need64, SESpec **out) {
+    std::string key = se.key;
+    key.append((const char *)&nt, sizeof nt);
+    key.append((const char *)&nr, sizeof nr);
+    auto it = g.spectra.find(key);
+    SESpec *sp = nullptr;
+    if (it != g.spectra.end()) {
+        sp = it->second.get();
+        if ((!need32 || sp->s32.p) && (!need64 || sp->s64.p)) {
+            *out = sp;
+            return MD_OK;
+        }
+    } else {
+        auto n = std::make_unique<SESpec>();
+        sp = n.get();
+        g.spectra[key] = std::move(n);
+    }
+    const int k = se.k, bins = nr / 2 + 1;
+    const size_t nspec = (size_t)bins * nt * nt;
+    if (need32) MD_TRY(sp->s32.ensure(nspec * sizeof(float2)));
+    if (need64) MD_TRY(sp->s64.ensure(nspec * sizeof(double2)));
+    MD_TRY(g.se_work.ensure((size_t)bins * k * nt * sizeof(double2)));
+    const size_t kk = (size_t)k * k;
+    MD_TRY(g.se_in.ensure(kk * (sizeof(int32_t) + 1) + 64));
+    MD_HIP(hipStreamSynchronize(g.stream));   // se_in may still be read by an earlier build
+    int32_t *off_d = (int32_t *)g.se_in.p;
+    uint8_t *mask_d = (uint8_t *)((char *)g.se_in.p + kk * sizeof(int32_t));
+    MD_HIP(hipMemcpy(off_d, se.off.data(), kk * sizeof(int32_t), hipMemcpyHostToDevice));
+    MD_HIP(hipMemcpy(mask_d, se.mask.data(), kk, hipMemcpyHostToDevice));
+    MD_HIP(launch_se_spectrum(mask_d, off_d, k, nt, nr, g.tw64, (double2 *)g.se_work.p,
+                              need64 ? (double2 *)sp->s64.p : nullptr, need32 ? (float2 *)sp->s32.p : nullptr,
+                              g.stream));
+    MD_HIP(hipStreamSynchronize(g.stream));
+    *out = sp;
+    return MD_OK;
+}
+
+// Correlation-order offsets for the direct window: reflect the effective SE.
+int get_dirse(const SEData &se, DirSE **out) {
+    auto it = g.dirse.find(se.key);
+    if (it != g.dirse.end()) {
+        *out = it->second.get();
+        return MD_OK;
+    }
+    auto d = std::make_unique<DirSE>();
+    const int k = se.k;
+    d->kpad = (k + kDirRX - 1) / kDirRX * kDirRX;
+    std::vector<int32_t> h((size_t)k * d->kpad, kNeg);
+    for (int i = 0; i < k; ++i)
+        for (int j = 0; j < k; ++j) {
+            const size_t src = (size_t)(k - 1 - i) * k + (k - 1 - j);
+            if (se.mask[src]) h[(size_t)i * d->kpad + j] = se.off[src];
+        }
+    MD_TRY(d->sek.ensure(h.size() * sizeof(int32_t)));
+    MD_HIP(hipMemcpy(d->sek.p, h.data(), h.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+    *out = d.get();
+    g.dirse[se.key] = std::move(d);
+    return MD_OK;
+}
+
+// ---------------------------------------------------------------------------
+// planner
+// ---------------------------------------------------------------------------
+int check_job(const md_job &j) {
+    if (!j.img || !j.out) return fail(MD_ERR_ARG, "null image or output pointer");
+    if ((const void *)j.img == (const void *)j.out) return fail(MD_ERR_ARG, "output must not alias the input");
+    if (!j.se_mask || !j.se_offsets) return fail(MD_ERR_ARG, "null SE array");
+    if (j.H < 1 || j.W < 1) return fail(MD_ERR_ARG, "image shape %dx%d", j.H, j.W);
+    if ((long long)j.H * j.W > 0x7fffffffLL) return fail(MD_ERR_ARG, "image has more than 2^31-1 pixels");
+    if (j.L < 2 || j.L > (1 << 24)) return fail(MD_ERR_ARG, "L=%d outside [2, 2^24]", j.L);
+    if (j.k < 1 || j.k > 127 || (j.k % 2) == 0) return fail(MD_ERR_ARG, "k=%d must be odd in [1,127]", j.k);
+    if (j.op != 0 && j.op != 1) return fail(MD_ERR_ARG, "op=%d must be 0 (dilation) or 1 (erosion)", j.op);
+    for (int q = 0; q < j.k * j.k; ++q)
+        if (j.se_mask[q] && (j.se_offsets[q] < 0 || j.se_offsets[q] > (1 << 24)))
+            return fail(MD_ERR_RANGE, "SE offset %d at cell %d outside [0, 2^24]", j.se_offsets[q], q);
+    return MD_OK;
+}
+
+double fft_cost(const md_job &j, int nt, int nr, int dbl) {
+    const int T = nt - j.k + 1;
+    if (T < 1) return INFINITY;
+    const long long tiles = (long long)((j.H + T - 1) / T) * ((j.W + T - 1) / T);
+    const int bins = nr / 2 + 1;
+    const double item = g.cost.fft_item[dbl][ilog2i(nt)];
+    if (item <= 0) return INFINITY;
+    return tiles * (double)bins * item + (double)tiles * T * T * nr * bins * g.cost.dec_unit[dbl];
+}
+
+int plan_job(const md_job &j, const SEData &se, Plan &p) {
+    const long long nr_min = (long long)(j.L - 1) + se.maxoff + 1;
+    int nr = (int)std::min<long long>(nr_min, 1 << 30);
+    if (g.opt.nr > 0) {
+        if (g.opt.nr < nr_min)
+            return fail(MD_ERR_ARG, "forced range length %d < (L-1)+max offset+1 = %lld", g.opt.nr, nr_min);
+        nr = g.opt.nr;
+    }
+    const int dbl = g.opt.precision == 1 ? 1 : 0;
+    p = Plan();
+    p.dbl = dbl;
+    p.nr = nr;
+    p.bins = nr / 2 + 1;
+    const int kpad = (j.k + kDirRX - 1) / kDirRX * kDirRX;
+    p.cost_dir = (double)j.H * j.W * j.k * kpad * g.cost.dir_unit;
+    // transform plan: best spatial length by the cost model
+    double best = INFINITY;
+    int best_nt = 0;
+    const int cands32[4] = {16, 32, 64, 128}, cands64[3] = {16, 32, 64};
+    const int *cands = dbl ? cands64 : cands32;
+    const int ncand = dbl ? 3 : 4;
+    const bool fft_ok = nr_min <= 4096 && se.ncells > 0;
+    for (int c = 0; fft_ok && c < ncand; ++c) {
+        const int nt = cands[c];
+        if (g.opt.tile > 0 && nt != g.opt.tile) continue;
+        const double cst = fft_cost(j, nt, nr, dbl);
+        if (cst < best) {
+            best = cst;
+            best_nt = nt;
+        }
+    }
+    p.cost_fft = best;
+    if (g.opt.path == kPathFFT) {
+        if (!fft_ok) return fail(MD_ERR_UNSUPPORTED, "FFT path needs 1 <= SE cells and (L-1)+max offset+1 <= 4096");
+        if (!best_nt) return fail(MD_ERR_UNSUPPORTED, "no FFT tile length fits k=%d (precision %d, tile %d)", j.k, dbl, g.opt.tile);
+        p.path = kPathFFT;
+    } else if (g.opt.path == kPathDirect) {
+        p.path = kPathDirect;
+    } else {
+        p.path = (best_nt && best < p.cost_dir) ? kPathFFT : kPathDirect;
+    }
+    if (p.path == kPathDirect) return MD_OK;
+    p.nt = best_nt;
+    p.T = best_nt - j.k + 1;
+    p.tiles_x = (j.W + p.T - 1) / p.T;
+    p.tiles_y = (j.H + p.T - 1) / p.T;
+    if (!dbl) {
+        // exact recompute of ambiguous tiles: FP64 transforms on the smallest
+        // LDS-resident length whose tile covers the FP32 tile, else on 64 when
+        // it still yields >= 16 outputs per side, else the direct window.
+        p.fb_mode = kFbDirect;
+        for (int nt64 : {16, 32, 64}) {
+            if (nt64 - j.k + 1 >= p.T) {
+                p.fb_mode = kFbFFT64;
+                p.nt64 = nt64;
+                break;
+            }
+        }
+        if (p.fb_mode == kFbDirect && 64 - j.k + 1 >= 16) {
+            p.fb_mode = kFbFFT64;
+            p.nt64 = 64;
+        }
+        if (p.fb_mode == kFbFFT64) p.T64 = p.nt64 - j.k + 1;
+    }
+    return MD_OK;
+}
+
+// ---------------------------------------------------------------------------
+// executor
+// ---------------------------------------------------------------------------
+int occupancy_grid(long long nitems, size_t lds, int threads) {
+    int per_cu = 2048 / threads;
+    if (lds > 0) per_cu = std::min<int>(per_cu, (int)((160 * 1024) / lds));
+    per_cu = std::max(per_cu, 1);
+    const long long cap = (long long)g.cu * per_cu;
+    return (int)std::max<long long>(1, std::min(nitems, cap));
+}
+
+Group *find_group(std::vector<Group> &v, int nt, int dbl, int big) {
+    for (auto &gr : v)
+        if (gr.nt == nt && gr.dbl == dbl && gr.big == big) return &gr;
+    v.push_back(Group());
+    v.back().nt = nt;
+    v.back().dbl = dbl;
+    v.back().big = big;
+    return &v.back();
+}
+
+std::string signature(const md_job *jobs, int n, const std::vector<SEData> &ses) {
+    std::string s;
+    const Options &o = g.opt;
+    s.append((const char *)&o.precision, sizeof o.precision);
+    s.append((const char *)&o.band, sizeof o.band);
+    s.append((const char *)&o.path, sizeof o.path);
+    s.append((const char *)&o.tile, sizeof o.tile);
+    s.append((const char *)&o.nr, sizeof o.nr);
+    s.append((const char *)&o.ws_mb, sizeof o.ws_mb);
+    for (int i = 0; i < n; ++i) {
+        const int hdr[5] = {jobs[i].H, jobs[i].W, jobs[i].L, jobs[i].k, jobs[i].op};
+        s.append((const char *)hdr, sizeof hdr);
+        s.append(ses[i].key);
+    }
+    return s;
+}
+
+int build_exec(const md_job *jobs, int n, const std::vector<SEData> &ses, Exec &ex) {
+    ex.jobs_h.resize(n);
+    ex.plans.resize(n);
+    size_t max_dir_lds = 0, max_fbdir_lds = 0;
+    long long flag_total = 0;
+    const size_t cap_bytes = (size_t)std::max(1.0, g.opt.ws_mb) * 1024 * 1024;
+    // per-job plans and device descriptors
+    for (int i = 0; i < n; ++i) {
+        const md_job &j = jobs[i];
+        Plan &p = ex.plans[i];
+        MD_TRY(plan_job(j, ses[i], p));
+        JobDev &d = ex.jobs_h[i];
+        memset(&d, 0, sizeof d);
+        d.img = j.img;
+        d.out = j.out;
+        d.H = j.H;
+        d.W = j.W;
+        d.L = j.L;
+        d.k = j.k;
+        d.op = j.op;
+        d.path = p.path;
+        if (p.path == kPathDirect || p.fb_mode == kFbDirect) {
+            DirSE *ds = nullptr;
+            MD_TRY(get_dirse(ses[i], &ds));
+            d.sek = (const int32_t *)ds->sek.p;
+            d.kpad = ds->kpad;
+            d.dir_bx = (j.W + kDirBW - 1) / kDirBW;
+            d.dir_by = (j.H + kDirBH - 1) / kDirBH;
+            const size_t lds = direct_lds_bytes(j.k, ds->kpad);
+            if (p.path == kPathDirect) max_dir_lds = std::max(max_dir_lds, lds);
+            else max_fbdir_lds = std::max(max_fbdir_lds, lds);
+        }
+        if (p.path == kPathDirect) {
+            ++ex.n_direct;
+            continue;
+        }
+        ++ex.n_fft;
+        RangeTables *rt = nullptr;
+        MD_TRY(get_range(p.nr, j.L, &rt));
+        SESpec *sp = nullptr;
+        MD_TRY(get_spectrum(ses[i], p.nt, p.nr, !p.dbl, p.dbl != 0, &sp));
+        d.nt = p.nt;
+        d.T = p.T;
+        d.nr = p.nr;
+        d.bins = p.bins;
+        d.tiles_x = p.tiles_x;
+        d.tiles_y = p.tiles_y;
+        d.dbl = p.dbl;
+        d.scale = 1.0 / ((double)p.nt * p.nt * p.nr);
+        d.se_spec = p.dbl ? sp->s64.p : sp->s32.p;
+        d.enc = p.dbl ? rt->enc64.p : rt->enc32.p;
+        d.dec = p.dbl ? rt->dec64.p : rt->dec32.p;
+        d.flag0 = flag_total;
+        flag_total += (long long)p.tiles_x * p.tiles_y;
+        ex.fft_tiles += (long long)p.tiles_x * p.tiles_y;
+        d.fb_mode = p.fb_mode;
+        if (p.fb_mode == kFbFFT64) {
+            SESpec *sp64 = nullptr;
+            MD_TRY(get_spectrum(ses[i], p.nt64, p.nr, false, true, &sp64));
+            d.nt64 = p.nt64;
+            d.T64 = p.T64;
+            d.scale64 = 1.0 / ((double)p.nt64 * p.nt64 * p.nr);
+            d.se_spec64 = (const double2 *)sp64->s64.p;
+            d.enc64 = (const double2 *)rt->enc64.p;
+            d.dec64 = (const double2 *)rt->dec64.p;
+            ex.slot_elems = std::max(ex.slot_elems, (size_t)p.bins * p.T64 * p.T64);
+            if (std::find(ex.fb_classes.begin(), ex.fb_classes.end(), p.nt64) == ex.fb_classes.end())
+                ex.fb_classes.push_back(p.nt64);
+        } else if (p.fb_mode == kFbDirect) {
+            ex.fb_direct = true;
+        }
+    }
+    // direct group: one segment per direct job
+    for (int i = 0; i < n; ++i) {
+        if (ex.plans[i].path != kPathDirect) continue;
+        Seg s{};
+        s.item0 = ex.direct.nitems;
+        s.job = i;
+        ex.direct.segs.push_back(s);
+        ex.direct.nitems += (long long)ex.jobs_h[i].dir_bx * ex.jobs_h[i].dir_by;
+    }
+    ex.direct_lds = max_dir_lds;
+    ex.fb_direct_lds = max_fbdir_lds;
+    // FFT jobs: split tile ranges into waves bounded by the workspace cap
+    std::vector<std::vector<std::pair<int, std::pair<int, int>>>> wave_chunks(1);   // (job, (tile0, ntiles))
+    std::vector<size_t> wave_bytes(1, 0);
+    for (int i = 0; i < n; ++i) {
+        const Plan &p = ex.plans[i];
+        if (p.path != kPathFFT) continue;
+        const size_t per_tile = (size_t)p.bins * p.T * p.T * (p.dbl ? sizeof(double2) : sizeof(float2));
+        const int ntiles = p.tiles_x * p.tiles_y;
+        int t = 0;
+        while (t < ntiles) {
+            size_t room = cap_bytes > wave_bytes.back() ? cap_bytes - wave_bytes.back() : 0;
+            int fit = (int)std::min<size_t>((size_t)(ntiles - t), room / per_tile);
+            if (fit == 0) {
+                if (wave_bytes.back() == 0) fit = 1;   // a single tile larger than the cap
+                else {
+                    wave_chunks.emplace_back();
+                    wave_bytes.push_back(0);
+                    continue;
+                }
+            }
+            wave_chunks.back().push_back({i, {t, fit}});
+            wave_bytes.back() += per_tile * fit;
+            t += fit;
+        }
+    }
+    size_t ymax = 0;
+    for (size_t w = 0; w < wave_chunks.size(); ++w) ymax = std::max(ymax, wave_bytes[w]);
+    MD_TRY(ex.ybuf.ensure(ymax));
+    for (size_t w = 0; w < wave_chunks.size(); ++w) {
+        if (wave_chunks[w].empty()) continue;
+        Wave wv;
+        size_t off = 0;
+        for (auto &ch : wave_chunks[w]) {
+            const int i = ch.first, tile0 = ch.second.first, nt_ = ch.second.second;
+            const Plan &p = ex.plans[i];
+            const size_t per_tile = (size_t)p.bins * p.T * p.T * (p.dbl ? sizeof(double2) : sizeof(float2));
+            Seg s{};
+            s.job = i;
+            s.tile0 = tile0;
+            s.ntiles = nt_;
+            s.pblocks = (p.T * p.T + 63) / 64;
+            s.y = (char *)ex.ybuf.p + off;
+            off += per_tile * nt_;
+            Group *gf = find_group(wv.fft, p.nt, p.dbl, 0);
+            s.item0 = gf->nitems;
+            gf->segs.push_back(s);
+            gf->nitems += (long long)nt_ * p.bins;
+            Group *gd = find_group(wv.dec, 0, p.dbl, p.nr > 32 ? 1 : 0);
+            s.item0 = gd->nitems;
+            gd->segs.push_back(s);
+            gd->nitems += (long long)nt_ * s.pblocks;
+        }
+        ex.waves.push_back(std::move(wv));
+    }
+    // device copies of the segment tables
+    size_t nseg_total = ex.direct.segs.size();
+    for (auto &wv : ex.waves) {
+        for (auto &gr : wv.fft) nseg_total += gr.segs.size();
+        for (auto &gr : wv.dec) nseg_total += gr.segs.size();
+    }
+    MD_TRY(ex.segbuf.ensure(std::max<size_t>(1, nseg_total) * sizeof(Seg)));
+    std::vector<Seg> all;
+    all.reserve(nseg_total);
+    auto place = [&](Group &gr, int threads, size_t lds) {
+        gr.segs_d = (Seg *)ex.segbuf.p + all.size();
+        all.insert(all.end(), gr.segs.begin(), gr.segs.end());
+        gr.grid = occupancy_grid(gr.nitems, lds, threads);
+    };
+    if (!ex.direct.segs.empty()) place(ex.direct, kDirThreads, ex.direct_lds);
+    for (auto &wv : ex.waves) {
+        for (auto &gr : wv.fft) {
+            const size_t lds = (size_t)gr.nt * (gr.nt + 1) * (gr.dbl ? sizeof(double2) : sizeof(float2));
+            place(gr, fft_block_threads(gr.nt, gr.dbl), lds);
+        }
+        for (auto &gr : wv.dec) place(gr, kDecThreads, 0);
+    }
+    if (!all.empty()) MD_HIP(hipMemcpy(ex.segbuf.p, all.data(), all.size() * sizeof(Seg), hipMemcpyHostToDevice));
+    // recompute resources
+    ex.nflags = flag_total;
+    MD_TRY(ex.flags.ensure(std::max<long long>(1, flag_total) * sizeof(unsigned int)));
+    MD_TRY(ex.list.ensure(std::max<long long>(1, flag_total) * sizeof(int2)));
+    if (!ex.fb_classes.empty()) {
+        ex.fb_grid = (int)std::max<long long>(1, std::min<long long>(flag_total, std::min(g.cu, 128)));
+        MD_TRY(ex.slots.ensure((size_t)ex.fb_grid * ex.slot_elems * sizeof(double2)));
+    }
+    // job table
+    MD_HIP(hipMalloc(&ex.jobs_d, sizeof(JobDev) * n));
+    MD_HIP(hipHostMalloc((void **)&ex.jobs_pin, sizeof(JobDev) * n, 0));
+    MD_HIP(hipEventCreateWithFlags(&ex.copy_done, hipEventDisableTiming));
+    memcpy(ex.jobs_pin, ex.jobs_h.data(), sizeof(JobDev) * n);
+    MD_HIP(hipMemcpy(ex.jobs_d, ex.jobs_pin, sizeof(JobDev) * n, hipMemcpyHostToDevice));
+    return MD_OK;
+}
+
+// Stream-ordered launches of one batch.
+int enqueue(Exec &ex, hipStream_t s, bool skip_decode = false) {
+    MD_HIP(launch_zero(g.st_d, sizeof(StatsDev), s));
+    if (ex.nflags > 0) MD_HIP(launch_zero(ex.flags.p, ex.nflags * sizeof(unsigned int), s));
+    if (ex.direct.nitems > 0)
+        MD_HIP(launch_direct(ex.jobs_d, ex.direct.segs_d, (int)ex.direct.segs.size(), ex.direct.nitems,
+                             ex.direct.grid, ex.direct_lds, g.st_d, s));
+    const float band = (float)g.opt.band;
+    for (auto &wv : ex.waves) {
+        for (auto &gr : wv.fft)
+            MD_HIP(launch_fft(gr.nt, gr.dbl, ex.jobs_d, gr.segs_d, (int)gr.segs.size(), gr.nitems, gr.grid, g.tw32,
+                              g.tw64, g.st_d, s));
+        if (skip_decode) continue;
+        for (auto &gr : wv.dec)
+            MD_HIP(launch_decode(gr.big, gr.dbl, ex.jobs_d, gr.segs_d, (int)gr.segs.size(), gr.nitems, gr.grid,
+                                 band, (unsigned int *)ex.flags.p, (int2 *)ex.list.p, g.st_d, s));
+    }
+    if (skip_decode) return MD_OK;
+    for (int nt64 : ex.fb_classes)
+        MD_HIP(launch_fallback(nt64, ex.jobs_d, (const int2 *)ex.list.p, g.st_d, (double2 *)ex.slots.p,
+                               ex.slot_elems, ex.fb_grid, g.tw64, s));
+    if (ex.fb_direct)
+        MD_HIP(launch_fallback_direct(ex.jobs_d, (const int2 *)ex.list.p, g.st_d, g.cu, ex.fb_direct_lds, s));
+    return MD_OK;
+}
+
+int collect_stats(Exec &ex, int *range_err) {
+    MD_HIP(hipStreamSynchronize(g.stream));
+    MD_HIP(hipMemcpy(g.st_h, g.st_d, sizeof(StatsDev), hipMemcpyDeviceToHost));
+    md_stats &st = g.last;
+    float res;
+    memcpy(&res, &g.st_h->max_res_bits, sizeof res);
+    st.max_residual = res;
+    st.tiles = ex.fft_tiles;
+    st.fallback_tiles = g.st_h->fb_count;
+    st.unresolved_tiles = g.st_h->pad;
+    st.direct_jobs = ex.n_direct;
+    st.fft_jobs = ex.n_fft;
+    const Plan &p = ex.plans.back();
+    st.path = p.path;
+    st.n_t = p.nt;
+    st.n_r = p.path == kPathFFT ? p.nr : 0;
+    st.precision = g.opt.precision;
+    *range_err = g.st_h->range_err != 0;
+    return MD_OK;
+}
+
+int run(const md_job *jobs, int n, bool use_graph) {
+    MD_TRY(init());
+    if (n < 1 || !jobs) return fail(MD_ERR_ARG, "empty batch");
+    std::vector<SEData> ses(n);
+    for (int i = 0; i < n; ++i) {
+        MD_TRY(check_job(jobs[i]));
+        make_se(jobs[i].se_mask, jobs[i].se_offsets, jobs[i].k, jobs[i].op, ses[i]);
+    }
+    const std::string sig = signature(jobs, n, ses);
+    auto it = g.execs.find(sig);
+    Exec *ex = nullptr;
+    if (it == g.execs.end()) {
+        auto e = std::make_unique<Exec>();
+        const int rc = build_exec(jobs, n, ses, *e);
+        if (rc != MD_OK) return rc;
+        ex = e.get();
+        if (g.execs.size() > 64) g.execs.clear();
+        g.execs[sig] = std::move(e);
+    } else {
+        ex = it->second.get();
+    }
+    // refresh image / output pointers in the device job table if they moved
+    bool changed = false;
+    for (int i = 0; i < n; ++i) {
+        if (ex->jobs_h[i].img != jobs[i].img || ex->jobs_h[i].out != jobs[i].out) {
+            ex->jobs_h[i].img = jobs[i].img;
+            ex->jobs_h[i].out = jobs[i].out;
+            changed = true;
+        }
+    }
+    if (changed) {
+        if (ex->copy_pending) MD_HIP(hipEventSynchronize(ex->copy_done));
+        memcpy(ex->jobs_pin, ex->jobs_h.data(), sizeof(JobDev) * n);
+        MD_HIP(hipMemcpyAsync(ex->jobs_d, ex->jobs_pin, sizeof(JobDev) * n, hipMemcpyHostToDevice, g.stream));
+        MD_HIP(hipEventRecord(ex->copy_done, g.stream));
+        ex->copy_pending = true;
+    }
+    const bool graph = use_graph && g.opt.graph && g.stream != nullptr;
+    if (graph) {
+        if (!ex->gexec || ex->graph_stream != g.stream) {
+            if (ex->gexec) (void)hipGraphExecDestroy(ex->gexec);
+            if (ex->graph) (void)hipGraphDestroy(ex->graph);
+            ex->gexec = nullptr;
+            ex->graph = nullptr;
+            MD_HIP(hipStreamBeginCapture(g.stream, hipStreamCaptureModeThreadLocal));
+            const int rc = enqueue(*ex, g.stream);
+            hipGraph_t gr = nullptr;
+            const hipError_t ee = hipStreamEndCapture(g.stream, &gr);
+            if (rc != MD_OK) {
+                if (gr) (void)hipGraphDestroy(gr);
+                return rc;
+            }
+            MD_HIP(ee);
+            ex->graph = gr;
+            MD_HIP(hipGraphInstantiate(&ex->gexec, gr, nullptr, nullptr, 0));
+            ex->graph_stream = g.stream;
+        }
+        MD_HIP(hipGraphLaunch(ex->gexec, g.stream));
+    } else {
+        MD_TRY(enqueue(*ex, g.stream));
+    }
+    if (g.opt.sync) {
+        int range_err = 0;
+        MD_TRY(collect_stats(*ex, &range_err));
+        if (range_err) return fail(MD_ERR_RANGE, "an image value lies outside [0, L-1]");
+    }
+    g_err.clear();
+    return MD_OK;
+}
+
+}  // namespace
+}  // namespace md
+
+using namespace md;
+
+extern "C" {
+
+int md_dilate(const int32_t *img, int H, int W, int L, const uint8_t *se_mask, const int32_t *se_offsets, int k,
+              int32_t *out) {
+    md_job j{img, H, W, L, se_mask, se_offsets, k, out, 0};
+    return run(&j, 1, false);
+}
+
+int md_erode(const int32_t *img, int H, int W, int L, const uint8_t *se_mask, const int32_t *se_offsets, int k,
+             int32_t *out) {
+    md_job j{img, H, W, L, se_mask, se_offsets, k, out, 1};
+    return run(&j, 1, false);
+}
+
+int md_dilate_batch(const md_job *jobs, int n) { return run(jobs, n, true); }
+
+int md_set_stream(void *hip_stream) {
+    g.stream = (hipStream_t)hip_stream;
+    return MD_OK;
+}
+
+int md_set_option(int key, double v) {
+    Options &o = g.opt;
+    switch (key) {
+        case MD_OPT_PRECISION:
+            if (v != 0 && v != 1) return fail(MD_ERR_ARG, "precision must be 0 or 1");
+            o.precision = (int)v;
+            break;
+        case MD_OPT_BAND:
+            if (!(v >= 0 && v <= 0.5)) return fail(MD_ERR_ARG, "band must lie in [0, 0.5]");
+            o.band = v;
+            break;
+        case MD_OPT_PATH:
+            if (v != 0 && v != 1 && v != 2) return fail(MD_ERR_ARG, "path must be 0, 1 or 2");
+            o.path = (int)v;
+            break;
+        case MD_OPT_TILE:
+            if (v != 0 && v != 16 && v != 32 && v != 64 && v != 128) return fail(MD_ERR_ARG, "tile must be 0, 16, 32, 64 or 128");
+            o.tile = (int)v;
+            break;
+        case MD_OPT_NR:
+            if (v < 0 || v > 4096 || v != floor(v)) return fail(MD_ERR_ARG, "range length must be an integer in [0, 4096]");
+            o.nr = (int)v;
+            break;
+        case MD_OPT_SYNC: o.sync = v != 0; break;
+        case MD_OPT_GRAPH: o.graph = v != 0; break;
+        case MD_OPT_WORKSPACE_MB:
+            if (!(v >= 1)) return fail(MD_ERR_ARG, "workspace cap must be >= 1 MiB");
+            o.ws_mb = v;
+            break;
+        default: return fail(MD_ERR_ARG, "unknown option %d", key);
+    }
+    g_err.clear();
+    return MD_OK;
+}
+
+double md_get_option(int key) {
+    const Options &o = g.opt;
+    switch (key) {
+        case MD_OPT_PRECISION: return o.precision;
+        case MD_OPT_BAND: return o.band;
+        case MD_OPT_PATH: return o.path;
+        case MD_OPT_TILE: return o.tile;
+        case MD_OPT_NR: return o.nr;
+        case MD_OPT_SYNC: return o.sync;
+        case MD_OPT_GRAPH: return o.graph;
+        case MD_OPT_WORKSPACE_MB: return o.ws_mb;
+        default: return NAN;
+    }
+}
+
+int md_get_stats(md_stats *s) {
+    if (!s) return fail(MD_ERR_ARG, "null stats pointer");
+    *s = g.last;
+    return MD_OK;
+}
+
+const char *md_last_error(void) { return g_err.c_str(); }
+
+int md_release(void) {
+    if (!g.inited) return MD_OK;
+    (void)hipDeviceSynchronize();
+    g.execs.clear();
+    g.spectra.clear();
+    g.dirse.clear();
+    g.ranges.clear();
+    g.se_work.release();
+    g.se_in.release();
+    if (g.tw64) (void)hipFree(g.tw64);
+    if (g.tw32) (void)hipFree(g.tw32);
+    if (g.st_d) (void)hipFree(g.st_d);
+    if (g.st_h) (void)hipHostFree(g.st_h);
+    g.tw64 = nullptr;
+    g.tw32 = nullptr;
+    g.st_d = nullptr;
+    g.st_h = nullptr;
+    g.inited = false;
+    g.device = -1;
+    return MD_OK;
+}
+
+int md_debug_tile_values(const int32_t *img, int H, int W, int L, const uint8_t *se_mask, const int32_t *se_offsets,
+                         int k, int n_t, int n_r, int precision, int ty, int tx, double *dst) {
+    MD_TRY(init());
+    if (!dst) return fail(MD_ERR_ARG, "null destination");
+    const Options saved = g.opt;
+    g.opt.path = kPathFFT;
+    g.opt.tile = n_t;
+    g.opt.nr = n_r;
+    g.opt.precision = precision;
+    g.opt.ws_mb = 1e9;
+    md_job j{img, H, W, L, se_mask, se_offsets, k, nullptr, 0};
+    int32_t dummy_out_marker = 0;
+    (void)dummy_out_marker;
+    std::vector<SEData> ses(1);
+    int rc = MD_OK;
+    Exec ex;
+    do {
+        if (!img || !se_mask || !se_offsets) { rc = fail(MD_ERR_ARG, "null pointer"); break; }
+        j.out = (int32_t *)(uintptr_t)1;   // never written: decode is skipped
+        rc = check_job(j);
+        if (rc != MD_OK) break;
+        make_se(se_mask, se_offsets, k, 0, ses[0]);
+        rc = build_exec(&j, 1, ses, ex);
+        if (rc != MD_OK) break;
+        const Plan &p = ex.plans[0];
+        if (ty < 0 || ty >= p.tiles_y || tx < 0 || tx >= p.tiles_x) { rc = fail(MD_ERR_ARG, "tile index out of range"); break; }
+        rc = enqueue(ex, g.stream, true);
+        if (rc != MD_OK) break;
+        if (hipStreamSynchronize(g.stream) != hipSuccess) { rc = fail(MD_ERR_DEVICE, "synchronise failed"); break; }
+        const int tile = ty * p.tiles_x + tx;
+        const Seg &s = ex.waves[0].fft[0].segs[0];
+        const size_t TT = (size_t)p.T * p.T, n = (size_t)p.bins * TT;
+        const double sc = 1.0 / ((double)p.nt * p.nt);
+        const size_t esz = p.dbl ? sizeof(double2) : sizeof(float2);
+        std::vector<char> h(n * esz);
+        const char *src = (const char *)s.y + (size_t)(tile - s.tile0) * n * esz;
+        if (hipMemcpy(h.data(), src, n * esz, hipMemcpyDeviceToHost) != hipSuccess) { rc = fail(MD_ERR_DEVICE, "copy failed"); break; }
+        for (size_t q = 0; q < n; ++q) {
+            if (p.dbl) {
+                const double2 v = ((const double2 *)h.data())[q];
+                dst[2 * q] = v.x * sc;
+                dst[2 * q + 1] = v.y * sc;
+            } else {
+                const float2 v = ((const float2 *)h.data())[q];
+                dst[2 * q] = v.x * sc;
+                dst[2 * q + 1] = v.y * sc;
+            }
+        }
+    } while (0);
+    g.opt = saved;
+    if (rc == MD_OK) g_err.clear();
+    return rc;
+}
+
+}  // extern "C"

@@ -1,0 +1,38 @@
+"""CPU checks of the C-ABI library: it loads without a GPU, exports every
+function include/md.h declares, and its host-only option handling works."""
+import math
+
+import pytest
+
+import paper_2305_03018_amd as md
+
+
+def test_library_exports_every_header_symbol():
+    syms = md.exported_symbols()
+    assert len(syms) >= 10
+    missing = [k for k, ok in syms.items() if not ok]
+    assert not missing, missing
+
+
+def test_options_roundtrip_and_errors():
+    with md.options(band=0.1, path=2, tile=64, nr=40, precision=1):
+        assert md.get_option("band") == pytest.approx(0.1)
+        assert md.get_option("path") == 2
+        assert md.get_option("tile") == 64
+        assert md.get_option("nr") == 40
+        assert md.get_option("precision") == 1
+    assert md.get_option("band") == pytest.approx(0.25)
+    assert md.get_option("path") == 0
+    assert math.isnan(md.get_option(99))
+    for key, bad in (("band", 0.7), ("band", -1), ("path", 3), ("tile", 48), ("precision", 2),
+                     ("nr", 4097), ("nr", 2.5), ("workspace_mb", 0), (99, 1)):
+        with pytest.raises(md.MDError) as ei:
+            md.set_option(key, bad)
+        assert ei.value.code == -1
+
+
+def test_binding_requires_device_tensors():
+    import numpy as np
+
+    with pytest.raises(TypeError):
+        md.dilate(np.zeros((4, 4), np.int32), np.ones((3, 3)), np.zeros((3, 3)), 4)

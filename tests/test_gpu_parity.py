@@ -1,0 +1,323 @@
+"""GPU parity: the HIP library (through its C ABI) against the CPU oracle.
+
+Dilation and erosion results are integers, so every comparison is bit-exact
+(numpy array_equal), for every path (FFT of umbras / direct window), every
+precision (FP64, FP32 + exact recompute) and every tile length.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import paper_2305_03018_amd as md
+from paper_2305_03018_amd import synthetic
+
+pytestmark = pytest.mark.gpu
+
+FFT64 = dict(precision=1, path=1)
+FFT32 = dict(precision=0, path=1)
+DIRECT = dict(path=2)
+MODES = {"fft64": FFT64, "fft32": FFT32, "direct": DIRECT}
+
+
+@pytest.fixture(scope="module")
+def dev():
+    import torch
+
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    md.load()
+    return torch.device("cuda:0")
+
+
+def _say(msg):
+    print(msg, flush=True)
+
+
+def run_job(job, dev, **opts):
+    import torch
+
+    img = torch.from_numpy(job.img).to(dev)
+    with md.options(**opts):
+        f = md.dilate if job.op == 0 else md.erode
+        out = f(img, job.mask, job.off, job.L)
+        st = md.get_stats()
+    return out.cpu().numpy(), st
+
+
+def assert_parity(job, dev, want=None, **opts):
+    if want is None:
+        want = oracle.run_job(job)
+    _say(f"  case {job.name} op={job.op} opts={opts}")
+    got, st = run_job(job, dev, **opts)
+    bad = got != want
+    assert not bad.any(), (f"{job.name} op={job.op} {opts}: {int(bad.sum())} of {bad.size} pixels differ; "
+                           f"first at {np.argwhere(bad)[0].tolist()} got {got[bad][0]} want {want[bad][0]}")
+    return st
+
+
+def embed_1d(values, origin):
+    n = len(values)
+    r = max(origin, n - 1 - origin)
+    k = 2 * r + 1
+    mask = np.zeros((k, k), np.uint8)
+    off = np.zeros((k, k), np.int32)
+    for idx, v in enumerate(values):
+        if v is not None:
+            mask[r, idx - origin + r] = 1
+            off[r, idx - origin + r] = v
+    return mask, off
+
+
+# ----------------------------------------------------------------------------
+# the paper's worked example (Sec. 2.1, Example 2; Sec. 3, Example 5)
+# ----------------------------------------------------------------------------
+@pytest.mark.parametrize("mode", ["fft64", "fft32", "direct"])
+@pytest.mark.parametrize("tile", [0, 16, 64])
+def test_paper_example2(dev, mode, tile):
+    mask, off = embed_1d([1, 2, None, 0], 1)
+    job = synthetic.Job(np.array([[3, 0, 7, 6, 2, 7]], np.int32), 8, mask, off, 0, "example2")
+    got, _ = run_job(job, dev, tile=tile, **MODES[mode])
+    assert got[0].tolist() == [5, 8, 9, 8, 8, 9]
+    job.op = 1
+    got, _ = run_job(job, dev, tile=tile, **MODES[mode])
+    assert got[0].tolist() == [1, -2, -1, 4, 0, 1]
+
+
+# ----------------------------------------------------------------------------
+# seeded random cases spanning several tiles and ragged tails
+# ----------------------------------------------------------------------------
+RANDOM_CASES = [
+    # H, W, L, k, p, max_off, op
+    (150, 203, 16, 7, 0.7, 3, 0),
+    (150, 203, 16, 7, 0.7, 3, 1),
+    (97, 131, 2, 3, 1.0, 0, 0),
+    (61, 300, 64, 15, 0.5, 16, 0),
+    (61, 300, 64, 15, 0.5, 16, 1),
+    (257, 129, 8, 1, 1.0, 5, 0),
+    (33, 33, 32, 31, 0.4, 8, 1),
+    (200, 45, 256, 11, 0.6, 40, 0),
+]
+
+
+@pytest.mark.parametrize("case", RANDOM_CASES, ids=lambda c: "x".join(map(str, c)))
+def test_random_parity(dev, case):
+    H, W, L, k, p, max_off, op = case
+    rng = np.random.default_rng(abs(hash(case)) % (2 ** 32))
+    job = synthetic.random_job(rng, H, W, L, k, p=p, max_off=max_off, op=op)
+    want = oracle.run_job(job)
+    for name, opts in MODES.items():
+        tiles = [0] if name == "direct" else [t for t in (16, 32, 64, 128) if t >= k and not (t == 128 and name == "fft64")]
+        for t in tiles:
+            assert_parity(job, dev, want=want, tile=t, **opts)
+
+
+def test_forced_nr_lengths(dev):
+    rng = np.random.default_rng(21)
+    job = synthetic.random_job(rng, 120, 90, 16, 9, p=0.6, max_off=6)
+    want = oracle.run_job(job)
+    nr_min = 15 + int(job.off.max()) + 1
+    for nr in (nr_min, nr_min + 1, 32, 77):
+        for opts in (FFT32, FFT64):
+            assert_parity(job, dev, want=want, nr=nr, **opts)
+    with pytest.raises(md.MDError):
+        run_job(job, dev, nr=nr_min - 1, **FFT32)
+
+
+# ----------------------------------------------------------------------------
+# exact recompute of ambiguous tiles
+# ----------------------------------------------------------------------------
+def test_forced_recompute_all_and_none(dev):
+    job = synthetic.blurred_512(0)
+    want = oracle.run_job(job)
+    st = assert_parity(job, dev, want=want, band=0.0, **FFT32)
+    assert st["fallback_tiles"] == st["tiles"] > 0
+    st = assert_parity(job, dev, want=want, band=0.5, **FFT32)
+    assert st["fallback_tiles"] == 0
+
+
+def test_recompute_by_direct_window_for_large_se(dev):
+    rng = np.random.default_rng(22)
+    job = synthetic.random_job(rng, 140, 170, 8, 61, p=0.5, max_off=2)
+    want = oracle.run_job(job)
+    st = assert_parity(job, dev, want=want, band=0.0, **FFT32)
+    assert st["fallback_tiles"] == st["tiles"] > 0
+
+
+# ----------------------------------------------------------------------------
+# edge cases
+# ----------------------------------------------------------------------------
+def test_edge_shapes_and_masks(dev):
+    rng = np.random.default_rng(23)
+    cases = []
+    for H, W in ((1, 1), (1, 37), (41, 1), (2, 2)):
+        cases.append(synthetic.random_job(rng, H, W, 16, 5, p=0.8, max_off=3))
+    j = synthetic.random_job(rng, 40, 50, 16, 7, p=0.5, max_off=3)
+    j.mask[:] = 0
+    j.off[:] = 0
+    j.name = "empty_mask"
+    cases.append(j)
+    j = synthetic.random_job(rng, 3, 70, 16, 9, p=0.5, max_off=3)
+    j.mask[4, 4] = 0
+    j.mask[:, :] = 0
+    j.mask[0, 0] = 1      # only y = (-4, -4): every window of a 3-row image is empty
+    j.off[:] = 0
+    j.name = "all_windows_empty"
+    cases.append(j)
+    j = synthetic.random_job(rng, 64, 64, 16, 1, p=1.0, max_off=0)
+    j.name = "identity_1x1"
+    cases.append(j)
+    for job in cases:
+        for op in (0, 1):
+            job.op = op
+            want = oracle.run_job(job)
+            for name, opts in MODES.items():
+                if name != "direct" and not job.mask.any():
+                    continue   # the FFT path needs at least one SE cell
+                assert_parity(job, dev, want=want, **opts)
+            assert_parity(job, dev, want=want)
+
+
+def test_largest_se_and_widest_range(dev):
+    rng = np.random.default_rng(24)
+    job = synthetic.random_job(rng, 300, 280, 4, 127, p=0.3, max_off=1)
+    want = oracle.run_job(job)
+    assert_parity(job, dev, want=want, **DIRECT)
+    assert_parity(job, dev, want=want, **FFT32)          # 128-point tiles, 2 outputs per side
+    job = synthetic.random_job(rng, 70, 90, 4000, 3, p=1.0, max_off=90)   # nr up to 4090
+    want = oracle.run_job(job)
+    assert_parity(job, dev, want=want, **FFT32)
+    assert_parity(job, dev, want=want, **FFT64)
+    assert_parity(job, dev, want=want)
+
+
+def test_errors(dev):
+    import torch
+
+    job = synthetic.small_uniform(0)
+    img = torch.from_numpy(job.img).to(dev)
+    bad = img.clone()
+    bad[3, 5] = 16
+    for opts in (FFT32, FFT64, DIRECT):
+        with md.options(**opts), pytest.raises(md.MDError) as ei:
+            md.dilate(bad, job.mask, job.off, 16)
+        assert ei.value.code == -2
+    neg = job.off.copy()
+    neg[0, 0] = -1
+    with pytest.raises(md.MDError) as ei:
+        md.dilate(img, job.mask, neg, 16)
+    assert ei.value.code == -2
+    with pytest.raises(md.MDError) as ei:
+        md.dilate(img, np.ones((4, 4)), np.zeros((4, 4)), 16)
+    assert ei.value.code == -1
+    with pytest.raises(md.MDError) as ei:
+        md.dilate(img, job.mask, job.off, 1)
+    assert ei.value.code == -1
+    out = torch.full_like(img, 123)
+    with pytest.raises(md.MDError):
+        md.dilate(img, np.ones((4, 4)), np.zeros((4, 4)), 16, out=out)
+    assert (out == 123).all()
+    # the library still works after errors
+    assert_parity(job, dev)
+
+
+# ----------------------------------------------------------------------------
+# transform-domain values against the FP64 reference
+# ----------------------------------------------------------------------------
+def test_spectrum_error_report(dev):
+    import torch
+
+    job = synthetic.blurred_512(0)
+    img = torch.from_numpy(job.img).to(dev)
+    nt, nr = 64, 24
+    T = nt - job.k + 1
+    ty, tx = 2, 3
+    ys, xs = np.divmod(np.arange(T * T), T)
+    counts = oracle.counts_at(job.img, job.mask, job.off, ty * T + ys, tx * T + xs, nr)
+    ref = oracle.range_spectrum_ref(counts, nr).T           # (bins, T*T)
+    for prec, tol in ((0, 2e-5), (1, 1e-12)):
+        got = md.debug_tile_values(img, job.mask, job.off, job.L, nt, nr, prec, ty, tx)
+        rel = np.linalg.norm(got - ref) / np.linalg.norm(ref)
+        mx = np.abs(got - ref).max()
+        _say(f"  precision={prec}: relative L2 {rel:.3e}, max abs {mx:.3e}")
+        assert rel < tol
+
+
+def test_repeatable(dev):
+    job = synthetic.blurred_512(0)
+    a, sa = run_job(job, dev, **FFT32)
+    b, sb = run_job(job, dev, **FFT32)
+    assert np.array_equal(a, b) and sa["max_residual"] == sb["max_residual"]
+
+
+# ----------------------------------------------------------------------------
+# named workloads
+# ----------------------------------------------------------------------------
+@pytest.mark.parametrize("mode", ["fft64", "fft32", "direct"])
+def test_small_uniform_64(dev, mode):
+    job = synthetic.small_uniform(0)
+    assert_parity(job, dev, **MODES[mode])
+
+
+@pytest.mark.parametrize("op", [0, 1])
+def test_blurred_512(dev, op):
+    job = synthetic.blurred_512(0, op=op)
+    want = oracle.run_job(job)
+    for name, opts in MODES.items():
+        assert_parity(job, dev, want=want, **opts)
+    for tile in (32, 64, 128):
+        assert_parity(job, dev, want=want, tile=tile, **FFT32)
+    st = assert_parity(job, dev, want=want)   # auto plan
+    assert st["unresolved_tiles"] == 0
+
+
+@pytest.mark.parametrize("flat", [True, False])
+def test_large_random_mask_2048(dev, flat):
+    job = synthetic.large_random_mask(0, flat=flat)
+    want = oracle.run_job(job)
+    st = assert_parity(job, dev, want=want, **FFT32)
+    _say(f"  stats {st}")
+    assert st["max_residual"] < 0.25
+    assert_parity(job, dev, want=want, **DIRECT)
+
+
+def test_octave_noise_4096(dev):
+    job = synthetic.octave_noise_4096(0)
+    want = oracle.run_job(job)
+    st = assert_parity(job, dev, want=want, **FFT32)
+    _say(f"  stats {st}")
+    assert_parity(job, dev, want=want, **DIRECT)
+    assert_parity(job, dev, want=want)
+
+
+def _batch_parity(jobs, outs, sample_rng, full_every=16):
+    for q, (job, out) in enumerate(zip(jobs, outs)):
+        got = out.cpu().numpy()
+        if q % full_every == 0:
+            want = oracle.run_job(job)
+            assert np.array_equal(got, want), f"{job.name}: {int((got != want).sum())} pixels differ"
+        else:
+            H, W = job.img.shape
+            n = 4096
+            ys = np.concatenate([sample_rng.integers(0, H, n), [0, H - 1, 0, H - 1]])
+            xs = np.concatenate([sample_rng.integers(0, W, n), [0, 0, W - 1, W - 1]])
+            want = oracle.at(job.img, job.mask, job.off, job.L, job.op, ys, xs)
+            assert np.array_equal(got[ys, xs], want), f"{job.name}: sampled pixels differ"
+
+
+@pytest.mark.parametrize("mode", ["auto", "fft32", "fft64"])
+def test_uneven_batch_256(dev, mode):
+    import torch
+
+    jobs = synthetic.uneven_batch(0, 256)
+    imgs = [torch.from_numpy(j.img).to(dev) for j in jobs]
+    opts = {"auto": {}, "fft32": FFT32, "fft64": FFT64}[mode]
+    _say(f"  batch of {len(jobs)} mode={mode}")
+    with md.options(**opts):
+        outs = md.dilate_batch([(im, j.mask, j.off, j.L, j.op) for im, j in zip(imgs, jobs)])
+        st = md.get_stats()
+        _say(f"  stats {st}")
+        _batch_parity(jobs, outs, np.random.default_rng(1))
+        # replay with new output buffers (same signature -> graph replay)
+        outs2 = [torch.full_like(o, -7) for o in outs]
+        md.dilate_batch([(im, j.mask, j.off, j.L, j.op) for im, j in zip(imgs, jobs)], outs=outs2)
+        for a, b in zip(outs, outs2):
+            assert torch.equal(a, b)
