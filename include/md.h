@@ -84,8 +84,14 @@ typedef enum {
     MD_OPT_SYNC = 5,       /* 1 (default): wait for completion in every call    */
     MD_OPT_GRAPH = 6,      /* 1 (default): md_dilate_batch captures its launches
                               in a HIP graph per batch signature and replays it  */
-    MD_OPT_WORKSPACE_MB = 7/* cap on the transform-domain scratch per launch
+    MD_OPT_WORKSPACE_MB = 7,/* cap on the transform-domain scratch per launch
                               group, MiB (default 8192)                           */
+    MD_OPT_PROFILE = 8,    /* 1: bracket every kernel launch of a non-graph call
+                              with HIP events and accumulate per-stage times
+                              (read with md_profile_get); default 0              */
+    MD_OPT_AUTOTUNE = 9    /* 1 (default): the first auto-path call on a device
+                              measures the kernels' rates and feeds them to the
+                              cost model; 0 keeps the built-in estimates         */
 } md_option;
 
 /* Dilation of one image (see the conventions above). */
@@ -142,6 +148,31 @@ const char *md_last_error(void);
 
 /* Release every device buffer, cached plan, spectrum and graph. */
 int md_release(void);
+
+/* Per-stage launch timing collected while MD_OPT_PROFILE = 1 (HIP events on
+ * the library's stream, synchronised calls only).  `alg_bytes` / `alg_ops`
+ * are the algorithmic DRAM bytes and arithmetic operations the stage has to
+ * perform for the work it was given (the figures a roofline is drawn with),
+ * summed over its launches.  Stage names: "fft32_nN", "fft64_nN",
+ * "decode32", "decode64", "direct", "recompute64_nN", "recompute_direct". */
+typedef struct {
+    char name[32];
+    double ms;                /* summed event time                        */
+    long long launches;
+    double alg_bytes;
+    double alg_ops;           /* flops (FFT/decode) or int ops (direct)   */
+} md_stage_time;
+
+/* Copies up to `max` stage records into `out` and the number available into
+ * *n.  Host pointers. */
+int md_profile_get(md_stage_time *out, int max, int *n);
+int md_profile_reset(void);
+
+/* Cost-model constants in use (ns): direct per pixel*k*kpad, decode per
+ * pixel*nr*bins (FP32, FP64), FFT per (tile, bin) item for spatial lengths
+ * 16..128 in FP32 then 16..64 in FP64 (11 values into `dst`).  Returns
+ * MD_OK; *measured = 1 if they come from the autotuner. */
+int md_cost_model(double *dst, int *measured);
 
 /* Test hook: per-bin transform-domain values of one tile just before the
  * inverse range transform, for measuring spectrum error against an FP64

@@ -9,11 +9,13 @@ without a built ``libmd.so`` raises.
 """
 from ._binding import (  # noqa: F401
     MDError,
+    OPT_AUTOTUNE,
     OPT_BAND,
     OPT_GRAPH,
     OPT_NR,
     OPT_PATH,
     OPT_PRECISION,
+    OPT_PROFILE,
     OPT_SYNC,
     OPT_TILE,
     OPT_WORKSPACE_MB,
@@ -24,9 +26,12 @@ from ._binding import (  # noqa: F401
     exported_symbols,
     get_option,
     get_stats,
+    cost_model,
     library_path,
     load,
     options,
+    profile_get,
+    profile_reset,
     release,
     set_option,
 )

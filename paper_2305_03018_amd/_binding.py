@@ -13,9 +13,11 @@ _LIB_PATH = os.path.join(_PKG, "libmd.so")
 _HEADER = os.path.join(os.path.dirname(_PKG), "include", "md.h")
 _lib = None
 
-OPT_PRECISION, OPT_BAND, OPT_PATH, OPT_TILE, OPT_NR, OPT_SYNC, OPT_GRAPH, OPT_WORKSPACE_MB = range(8)
+(OPT_PRECISION, OPT_BAND, OPT_PATH, OPT_TILE, OPT_NR, OPT_SYNC, OPT_GRAPH, OPT_WORKSPACE_MB,
+ OPT_PROFILE, OPT_AUTOTUNE) = range(10)
 _OPT_NAMES = {"precision": OPT_PRECISION, "band": OPT_BAND, "path": OPT_PATH, "tile": OPT_TILE,
-              "nr": OPT_NR, "sync": OPT_SYNC, "graph": OPT_GRAPH, "workspace_mb": OPT_WORKSPACE_MB}
+              "nr": OPT_NR, "sync": OPT_SYNC, "graph": OPT_GRAPH, "workspace_mb": OPT_WORKSPACE_MB,
+              "profile": OPT_PROFILE, "autotune": OPT_AUTOTUNE}
 _STATUS = {0: "MD_OK", -1: "MD_ERR_ARG", -2: "MD_ERR_RANGE", -3: "MD_ERR_NOMEM",
            -4: "MD_ERR_DEVICE", -5: "MD_ERR_UNSUPPORTED"}
 
@@ -38,6 +40,11 @@ class _Stats(ctypes.Structure):
                 ("direct_jobs", ctypes.c_longlong), ("fft_jobs", ctypes.c_longlong),
                 ("path", ctypes.c_int), ("n_t", ctypes.c_int), ("n_r", ctypes.c_int),
                 ("precision", ctypes.c_int)]
+
+
+class _StageTime(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char * 32), ("ms", ctypes.c_double), ("launches", ctypes.c_longlong),
+                ("alg_bytes", ctypes.c_double), ("alg_ops", ctypes.c_double)]
 
 
 def library_path() -> str:
@@ -73,6 +80,12 @@ def load():
     lib.md_release.restype = i
     lib.md_debug_tile_values.argtypes = [vp, i, i, i, u8, vp, i, i, i, i, i, i, vp]
     lib.md_debug_tile_values.restype = i
+    lib.md_profile_get.argtypes = [ctypes.POINTER(_StageTime), i, ctypes.POINTER(ctypes.c_int)]
+    lib.md_profile_get.restype = i
+    lib.md_profile_reset.argtypes = []
+    lib.md_profile_reset.restype = i
+    lib.md_cost_model.argtypes = [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int)]
+    lib.md_cost_model.restype = i
     _lib = lib
     return lib
 
@@ -210,6 +223,34 @@ def get_stats() -> dict:
 
 def release():
     _check(load().md_release())
+
+
+def profile_reset():
+    _check(load().md_profile_reset())
+
+
+def profile_get() -> dict:
+    """Per-stage totals collected while the 'profile' option is 1:
+    {name: {ms, launches, alg_bytes, alg_ops}}."""
+    lib = load()
+    n = ctypes.c_int(0)
+    _check(lib.md_profile_get(None, 0, ctypes.byref(n)))
+    arr = (_StageTime * max(1, n.value))()
+    _check(lib.md_profile_get(arr, n.value, ctypes.byref(n)))
+    return {arr[q].name.decode(): {"ms": arr[q].ms, "launches": arr[q].launches,
+                                   "alg_bytes": arr[q].alg_bytes, "alg_ops": arr[q].alg_ops}
+            for q in range(n.value)}
+
+
+def cost_model() -> dict:
+    """Cost-model constants in use (ns per work unit) and whether the
+    autotuner measured them."""
+    v = (ctypes.c_double * 11)()
+    measured = ctypes.c_int(0)
+    _check(load().md_cost_model(v, ctypes.byref(measured)))
+    return {"direct_per_px_k_kpad": v[0], "decode32_per_px_nr_bins": v[1], "decode64_per_px_nr_bins": v[2],
+            "fft32_item": {16: v[3], 32: v[4], 64: v[5], 128: v[6]},
+            "fft64_item": {16: v[7], 32: v[8], 64: v[9]}, "measured": bool(measured.value)}
 
 
 def debug_tile_values(img, mask, off, L: int, n_t: int, n_r: int, precision: int, ty: int, tx: int):

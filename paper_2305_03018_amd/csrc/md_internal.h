@@ -23,9 +23,8 @@ constexpr int kDirBW = 128;
 constexpr int kDirBH = 16;
 constexpr int kDirThreads = (kDirBW / kDirRX) * kDirBH;   // 256
 
-// Decode kernel geometry: 64 pixels per block, kDecTPP waves per pixel group.
-constexpr int kDecTPP = 4;
-constexpr int kDecThreads = 64 * kDecTPP;
+// Decode kernel geometry: one pixel per thread, kDecThreads pixels per block.
+constexpr int kDecThreads = 256;
 
 // FP32 twiddle stored as an unevaluated sum hi + lo of two floats, so that
 // hi + lo carries about 48 significant bits of exp(-2 pi i j / kTwN).
@@ -49,7 +48,7 @@ struct JobDev {
     double scale;                // 1 / (nt^2 * nr)
     const void *se_spec;         // [bins][nt][nt] spectrum of the SE umbra
     const void *enc;             // [bins][L]  exp(-2 pi i (v m mod nr) / nr)
-    const void *dec;             // [nr][bins] w_m exp(+2 pi i d m / nr), w = 1 or 2
+    const void *dec;             // [bins][bins] w_m exp(+2 pi i d m / nr), d <= nr/2, w = 1 or 2
     long long flag0;             // first entry of this job in the tile-flag array
     // exact recompute of ambiguous tiles
     int fb_mode;                 // kFbNone / kFbFFT64 / kFbDirect
@@ -57,10 +56,13 @@ struct JobDev {
     double scale64;
     const double2 *se_spec64;    // [bins][nt64][nt64]
     const double2 *enc64;        // [bins][L]
-    const double2 *dec64;        // [nr][bins]
+    const double2 *dec64;        // [bins][bins]
     // direct max-plus path (also the recompute of kFbDirect)
     const int32_t *sek;          // [k][kpad] offsets in correlation order, kNeg where masked
+    const int32_t *sek16;        // same, as two equal 16-bit lanes per word, -16384 where masked
+    const int32_t *sek_rows;     // [k][2] first and last active column of each row (first > last: none)
     int kpad;
+    int dir_pack;                // 1: 16-bit packed form (all sums fit in int16)
     int dir_bx, dir_by;          // direct-path blocks per row / column
 };
 
@@ -71,7 +73,7 @@ struct Seg {
     long long item0;             // first global item index of the segment
     int job;
     int tile0, ntiles;           // tile range (FFT / decode)
-    int pblocks;                 // decode: ceil(T*T / 64)
+    int pblocks;                 // decode: ceil(T*T / kDecThreads)
     void *y;                     // transform-domain buffer [ntiles][bins][T*T]
 };
 
@@ -92,19 +94,22 @@ hipError_t launch_se_spectrum(const uint8_t *mask_d, const int32_t *off_d, int k
                               const double2 *tw64, double2 *work, double2 *spec64, float2 *spec32,
                               hipStream_t s);
 hipError_t launch_zero(void *p, size_t bytes, hipStream_t s);
+hipError_t launch_fill_hash(int32_t *p, size_t n, int L, unsigned int seed, hipStream_t s);
 hipError_t launch_fft(int nt, int dbl, const JobDev *jobs, const Seg *segs, int nseg, long long nitems,
                       int grid, const TwF *tw32, const double2 *tw64, StatsDev *st, hipStream_t s);
 hipError_t launch_decode(int big, int dbl, const JobDev *jobs, const Seg *segs, int nseg,
                          long long nitems, int grid, float band, unsigned int *tile_flags,
                          int2 *fb_list, StatsDev *st, hipStream_t s);
-hipError_t launch_direct(const JobDev *jobs, const Seg *segs, int nseg, long long nitems, int grid,
-                         size_t lds_bytes, StatsDev *st, hipStream_t s);
+hipError_t launch_direct(int pack, int sel, const JobDev *jobs, const Seg *segs, int nseg, long long nitems,
+                         int grid, size_t lds_bytes, StatsDev *st, hipStream_t s);
 hipError_t launch_fallback(int nt64, const JobDev *jobs, const int2 *fb_list, const StatsDev *st,
                            double2 *slots, size_t slot_elems, int grid, const double2 *tw64,
                            hipStream_t s);
 hipError_t launch_fallback_direct(const JobDev *jobs, const int2 *fb_list, const StatsDev *st,
                                   int grid, size_t lds_bytes, hipStream_t s);
-size_t direct_lds_bytes(int k, int kpad);
+size_t direct_lds_bytes(int k, int kpad, int pack, int sel);
+constexpr size_t kLdsBytes = 160 * 1024;
+int direct_block_rows(int pack);
 int fft_block_threads(int nt, int dbl);
 
 }  // namespace md

@@ -55,6 +55,57 @@ __device__ __forceinline__ C cmul(C a, C b) {
 template <typename C>
 __device__ __forceinline__ C czero() { C r; r.x = 0; r.y = 0; return r; }
 
+// Address-space views: tables that every lane of a wavefront reads at the
+// same index go through the constant space (scalar loads); per-lane data
+// through the global space (no flat addressing).
+template <class T>
+__device__ __forceinline__ const __attribute__((address_space(4))) T *cst(const T *p) {
+    return (const __attribute__((address_space(4))) T *)(p);
+}
+template <class T>
+__device__ __forceinline__ const __attribute__((address_space(1))) T *gld(const T *p) {
+    return (const __attribute__((address_space(1))) T *)(p);
+}
+template <class T>
+__device__ __forceinline__ __attribute__((address_space(1))) T *gst(T *p) {
+    return (__attribute__((address_space(1))) T *)(p);
+}
+
+// Complex loads/stores through those spaces, as clang vectors (HIP's vector
+// structs do not copy out of address-space-qualified storage).
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+typedef double f64x2 __attribute__((ext_vector_type(2)));
+template <class C> struct VecOf;
+template <> struct VecOf<float2> { using T = f32x2; };
+template <> struct VecOf<double2> { using T = f64x2; };
+
+template <class C>
+__device__ __forceinline__ C ldg(const C *p, size_t i) {
+    using V = typename VecOf<C>::T;
+    const V v = ((const __attribute__((address_space(1))) V *)p)[i];
+    C r;
+    r.x = v.x;
+    r.y = v.y;
+    return r;
+}
+template <class C>
+__device__ __forceinline__ C ldc(const C *p, size_t i) {
+    using V = typename VecOf<C>::T;
+    const V v = ((const __attribute__((address_space(4))) V *)p)[i];
+    C r;
+    r.x = v.x;
+    r.y = v.y;
+    return r;
+}
+template <class C>
+__device__ __forceinline__ void stg(C *p, size_t i, C v) {
+    using V = typename VecOf<C>::T;
+    V w;
+    w.x = v.x;
+    w.y = v.y;
+    ((__attribute__((address_space(1))) V *)p)[i] = w;
+}
+
 // a * exp(-+2 pi i idx / kTwN) with the twiddle held as hi + lo floats: the lo
 // products are formed first so they are not lost against the hi products.
 struct Tw32 {
@@ -83,6 +134,20 @@ struct Tw64 {
         return r;
     }
 };
+
+// x * w^(+-) where w = exp(-2 pi i idx / kTwN); when idx is known to be 0 or
+// kTwN/4 (w = 1 or -i) no multiply is needed.
+template <typename TW, typename C>
+__device__ __forceinline__ C twmul(const TW &tw, C x, int idx, bool idx_known, bool inv) {
+    if (idx_known && idx == 0) return x;
+    if (idx_known && idx == kTwN / 4) {
+        C r;
+        if (inv) { r.x = -x.y; r.y = x.x; }   // * (+i)
+        else { r.x = x.y; r.y = -x.x; }       // * (-i)
+        return r;
+    }
+    return tw.mul(x, idx, inv);
+}
 
 template <typename R> struct TwSel;
 template <> struct TwSel<float> { using T = Tw32; };
@@ -124,7 +189,7 @@ __device__ __forceinline__ void pass_dit(typename Cx<R>::T *lds, const typename 
                 if (t & hu) continue;
                 const int j = o + (t & (hu - 1)) * H0;            // index inside the 2h block
                 const int idx = j * (kTwN / (2 * (H0 << s)));
-                const C b = tw.mul(x[t + hu], idx, INV);
+                const C b = twmul(tw, x[t + hu], idx, H0 == 1, INV);
                 const C a = x[t];
                 x[t] = cadd(a, b);
                 x[t + hu] = csub(a, b);
@@ -161,7 +226,7 @@ __device__ __forceinline__ void pass_dif(typename Cx<R>::T *lds, const typename 
                 const int idx = j * (kTwN / (2 * hu * HMIN));
                 const C a = x[t], b = x[t + hu];
                 x[t] = cadd(a, b);
-                x[t + hu] = tw.mul(csub(a, b), idx, INV);
+                x[t + hu] = twmul(tw, csub(a, b), idx, HMIN == 1, INV);
             }
         }
 #pragma unroll
@@ -212,13 +277,13 @@ __device__ __forceinline__ void fft_tile_bin(typename Cx<R>::T *lds, const int32
         const int gy = iy0 + i, gx = ix0 + j;
         C v = czero<C>();
         if (gy >= 0 && gy < H && gx >= 0 && gx < W) {
-            int val = img[(size_t)gy * W + gx];
+            int val = gld(img)[(size_t)gy * W + gx];
             if ((unsigned)val >= (unsigned)L) {
                 bad = true;
                 val = val < 0 ? 0 : L - 1;
             }
             if (op) val = L - 1 - val;
-            v = enc_m[val];
+            v = ldg(enc_m, val);
         }
         lds[brev<LG>(i) * P + brev<LG>(j)] = v;
     }
@@ -228,14 +293,14 @@ __device__ __forceinline__ void fft_tile_bin(typename Cx<R>::T *lds, const int32
     dit_axis<R, N, 1, BS, false>(lds, tw);
     for (int q = threadIdx.x; q < N * N; q += BS) {
         C *e = lds + (q >> LG) * P + (q & (N - 1));
-        *e = cmul(*e, spec_m[q]);
+        *e = cmul(*e, ldg(spec_m, q));
     }
     __syncthreads();
     dif_axis<R, N, 1, BS, true>(lds, tw);
     dif_axis<R, N, 0, BS, true>(lds, tw);
     for (int q = threadIdx.x; q < T * T; q += BS) {
         const int i = q / T + (k - 1), j = q % T + (k - 1);
-        ydst[q] = lds[brev<LG>(i) * P + brev<LG>(j)];
+        stg(ydst, q, lds[brev<LG>(i) * P + brev<LG>(j)]);
     }
     __syncthreads();
 }
@@ -272,42 +337,70 @@ __global__ __launch_bounds__(BS) void k_fft(const JobDev *__restrict__ jobs, con
     }
 }
 
-// Inverse real DFT over the range axis for one pixel per lane, and Step 3.
-// Wave w of the block handles the degrees d = d0 + w + kDecTPP * j.  The
-// twiddle index depends only on (w, j, m), so it is wave-uniform.
-template <typename R, int DPT>
-__device__ __forceinline__ void decode_px(const typename Cx<R>::T *__restrict__ X, size_t mstride, int p,
-                                          bool valid, const typename Cx<R>::T *__restrict__ dec, int nr,
-                                          int bins, R scale, int &top, R &res) {
+template <typename R>
+__device__ __forceinline__ void band_update(R c, int d, int &top, R &res) {
+    const R rc = rint(c);
+    res = fmax(res, fabs(c - rc));
+    if (rc != R(0)) top = max(top, d);
+}
+
+// One block of kDecDC degrees x kDecMC bins of the inverse real DFT.
+// A_d += w_m Re(X_m) cos(2 pi d m / nr), B_d += w_m Im(X_m) sin(2 pi d m / nr);
+// the twiddle index depends only on (d, m), so it is a scalar load.
+constexpr int kDecDC = 16, kDecMC = 8;
+
+template <typename R, bool GUARD>
+__device__ __forceinline__ void decode_chunk(const typename Cx<R>::T (&x)[kDecMC], R (&A)[kDecDC], R (&B)[kDecDC],
+                                             const typename Cx<R>::T *W, int d0, int m0, int dh, int bins) {
+#pragma unroll
+    for (int mm = 0; mm < kDecMC; ++mm) {
+        if (GUARD && m0 + mm >= bins) break;
+        const typename Cx<R>::T *row = W + (size_t)(m0 + mm) * bins + d0;   // bins == nr/2 + 1 == dh + 1
+#pragma unroll
+        for (int dd = 0; dd < kDecDC; ++dd) {
+            if (GUARD && d0 + dd > dh) break;
+            const typename Cx<R>::T w = ldc(row, dd);
+            A[dd] = fma(x[mm].x, w.x, A[dd]);
+            B[dd] = fma(x[mm].y, w.y, B[dd]);
+        }
+    }
+}
+
+// Inverse real DFT over the range axis for one pixel per lane and Step 3:
+// c_d = A_d - B_d and c_{nr-d} = A_d + B_d for d <= nr/2 (the coefficient
+// vector is real), then the top degree with rint(c_d) != 0 and the largest
+// distance |c_d - rint(c_d)| over all degrees.
+template <typename R>
+__device__ __forceinline__ void decode_pixel(const typename Cx<R>::T *X, size_t mstride, int p, bool valid,
+                                             const typename Cx<R>::T *dec, int nr, int bins, R scale, int &top,
+                                             R &res) {
     using C = typename Cx<R>::T;
-    const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const C *W = dec;
+    const int dh = nr >> 1;
     top = -1;
     res = 0;
-    for (int d0 = 0; d0 < nr; d0 += kDecTPP * DPT) {
-        R acc[DPT];
+    for (int d0 = 0; d0 <= dh; d0 += kDecDC) {
+        R A[kDecDC], B[kDecDC];
 #pragma unroll
-        for (int j = 0; j < DPT; ++j) acc[j] = 0;
-        for (int m = 0; m < bins; ++m) {
-            C x = czero<C>();
-            if (valid) x = X[(size_t)m * mstride + p];
+        for (int dd = 0; dd < kDecDC; ++dd) A[dd] = B[dd] = 0;
+        for (int m0 = 0; m0 < bins; m0 += kDecMC) {
+            C x[kDecMC];
 #pragma unroll
-            for (int j = 0; j < DPT; ++j) {
-                const int d = d0 + w + kDecTPP * j;
-                if (d < nr) {
-                    const C c = dec[(size_t)d * bins + m];
-                    acc[j] = fma(x.x, c.x, fma(-x.y, c.y, acc[j]));
-                }
+            for (int mm = 0; mm < kDecMC; ++mm) {
+                x[mm] = czero<C>();
+                if (valid && m0 + mm < bins) x[mm] = ldg(X, (size_t)(m0 + mm) * mstride + p);
             }
+            if (d0 + kDecDC - 1 <= dh && m0 + kDecMC <= bins)
+                decode_chunk<R, false>(x, A, B, W, d0, m0, dh, bins);
+            else
+                decode_chunk<R, true>(x, A, B, W, d0, m0, dh, bins);
         }
 #pragma unroll
-        for (int j = 0; j < DPT; ++j) {
-            const int d = d0 + w + kDecTPP * j;
-            if (d < nr) {
-                const R c = acc[j] * scale;
-                const R rc = rint(c);
-                res = fmax(res, fabs(c - rc));
-                if (rc != R(0)) top = max(top, d);
-            }
+        for (int dd = 0; dd < kDecDC; ++dd) {
+            const int d = d0 + dd;
+            if (d > dh) break;
+            band_update<R>((A[dd] - B[dd]) * scale, d, top, res);
+            if (d > 0 && 2 * d != nr) band_update<R>((A[dd] + B[dd]) * scale, nr - d, top, res);
         }
     }
 }
@@ -318,16 +411,26 @@ __device__ __forceinline__ float wave_max(float v) {
     return v;
 }
 
-template <typename R, int DPT>
+// Block-wide max of a float (kDecThreads threads); result valid in thread 0.
+__device__ __forceinline__ float block_max(float v, float *sh) {
+    v = wave_max(v);
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+    __syncthreads();
+    float r = sh[0];
+#pragma unroll
+    for (int q = 1; q < kDecThreads / 64; ++q) r = fmaxf(r, sh[q]);
+    __syncthreads();
+    return r;
+}
+
+template <typename R>
 __global__ __launch_bounds__(kDecThreads) void k_decode(const JobDev *__restrict__ jobs,
                                                         const Seg *__restrict__ segs, int nseg,
                                                         long long nitems, float band,
                                                         unsigned int *tile_flags, int2 *fb_list,
                                                         StatsDev *st) {
     using C = typename Cx<R>::T;
-    __shared__ int s_top[kDecTPP][64];
-    __shared__ float s_res[kDecTPP][64];
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    __shared__ float s_red[kDecThreads / 64];
     for (long long it = blockIdx.x; it < nitems; it += gridDim.x) {
         const Seg S = segs[find_seg(segs, nseg, it)];
         const JobDev &J = jobs[S.job];
@@ -336,7 +439,7 @@ __global__ __launch_bounds__(kDecThreads) void k_decode(const JobDev *__restrict
         const int tile = S.tile0 + tl;
         const int T = J.T;
         const int ty = tile / J.tiles_x, tx = tile - ty * J.tiles_x;
-        const int p = pb * 64 + lane;
+        const int p = pb * kDecThreads + threadIdx.x;
         const int ly = p / T, lx = p - ly * T;
         const int gy = ty * T + ly, gx = tx * T + lx;
         const bool valid = p < T * T && gy < J.H && gx < J.W;
@@ -344,110 +447,214 @@ __global__ __launch_bounds__(kDecThreads) void k_decode(const JobDev *__restrict
         const C *X = (const C *)S.y + (size_t)tl * J.bins * TT;
         int top;
         R res;
-        decode_px<R, DPT>(X, TT, p, valid, (const C *)J.dec, J.nr, J.bins, (R)J.scale, top, res);
-        s_top[w][lane] = top;
-        s_res[w][lane] = (float)res;
-        __syncthreads();
-        if (w == 0) {
-            float rr = (float)res;
-#pragma unroll
-            for (int v = 1; v < kDecTPP; ++v) {
-                top = max(top, s_top[v][lane]);
-                rr = fmaxf(rr, s_res[v][lane]);
-            }
-            if (valid) {
-                const int d = top < 0 ? 0 : top;
-                J.out[(size_t)gy * J.W + gx] = J.op ? (J.L - 1 - d) : d;
-            }
-            const float rm = wave_max(rr);
-            if (lane == 0) {
-                atomicMax(&st->max_res_bits, __float_as_uint(rm));
-                if (rm >= band) {
-                    if (J.fb_mode == kFbNone) {
-                        atomicAdd(&st->pad, 1u);
-                    } else if (atomicCAS(&tile_flags[J.flag0 + tile], 0u, 1u) == 0u) {
-                        const unsigned idx = atomicAdd(&st->fb_count, 1u);
-                        fb_list[idx] = make_int2(S.job, tile);
-                    }
+        decode_pixel<R>(X, TT, p, valid, (const C *)J.dec, J.nr, J.bins, (R)J.scale, top, res);
+        if (valid) {
+            const int d = top < 0 ? 0 : top;
+            gst(J.out)[(size_t)gy * J.W + gx] = J.op ? (J.L - 1 - d) : d;
+        }
+        const float rm = block_max((float)res, s_red);
+        if (threadIdx.x == 0) {
+            atomicMax(&st->max_res_bits, __float_as_uint(rm));
+            if (rm >= band) {
+                if (J.fb_mode == kFbNone) {
+                    atomicAdd(&st->pad, 1u);
+                } else if (atomicCAS(&tile_flags[J.flag0 + tile], 0u, 1u) == 0u) {
+                    const unsigned idx = atomicAdd(&st->fb_count, 1u);
+                    fb_list[idx] = make_int2(S.job, tile);
                 }
             }
         }
-        __syncthreads();
     }
 }
 
-// Direct max-plus window over one kDirBH x kDirBW block of outputs, clipped
-// to [.., ye) x [.., xe).  The image block plus halo is staged in LDS as
-// int32 with kNeg outside the image; the SE is held in correlation order
-// (reflected for dilation) with kNeg on masked cells, so the inner loop is
-// branch-free: acc = max(acc, in + b).  Erosion runs on the complement
-// L-1-f with the unreflected SE and complements the result (Sec. 2.1).
-__device__ __forceinline__ void direct_block(const JobDev &J, int by0, int bx0, int ye, int xe,
-                                             int32_t *tile, unsigned int *range_err) {
+// Direct max-plus window (the classical form of Eq. (6new)).  The image
+// block plus halo is staged in LDS with "minus infinity" outside the image;
+// the SE is held in correlation order (reflected for dilation) with minus
+// infinity on masked cells, so the inner loop is branch-free:
+// acc = max(acc, in + b).  Erosion runs on the complement L-1-f with the
+// unreflected SE and complements the result (Sec. 2.1).
+//
+// Two element formats: plain int32, or two 16-bit lanes per 32-bit word
+// holding vertically adjacent rows (LDS word (r, c) = rows r and r+1 of column
+// c), so one packed add and one packed max advance two outputs.  The packed
+// form is used when every reachable sum fits: values and offsets <= 16383
+// with minus infinity = -16384 (sums stay within [-32768, 16383]).
+typedef short s16x2 __attribute__((ext_vector_type(2)));
+constexpr int kNeg16 = -16384;
+
+template <bool PACK> struct DirT;
+template <> struct DirT<false> {
+    using V = int;
+    static constexpr int BH = kDirBH;
+    __device__ static V word(int w) { return w; }
+    __device__ static V vmax(V a, V b) { return max(a, b); }
+};
+template <> struct DirT<true> {
+    using V = s16x2;
+    static constexpr int BH = 2 * kDirBH;
+    __device__ static V word(int w) { return __builtin_bit_cast(s16x2, w); }
+    __device__ static V vmax(V a, V b) { return __builtin_elementwise_max(a, b); }
+};
+
+template <bool PACK>
+__device__ __forceinline__ int dir_pix(const JobDev &J, int gy, int gx, bool &bad) {
+    const int neg = PACK ? kNeg16 : kNeg;
+    if (gy < 0 || gy >= J.H || gx < 0 || gx >= J.W) return neg;
+    int v = gld(J.img)[(size_t)gy * J.W + gx];
+    if ((unsigned)v >= (unsigned)J.L) {
+        bad = true;
+        v = v < 0 ? 0 : J.L - 1;
+    }
+    return J.op ? J.L - 1 - v : v;
+}
+
+// 16 image words (this thread's 8 outputs plus the next 8 SE columns) and the
+// 8 SE offsets of one 8-cell step.
+struct DirBuf {
+    int4 w0, w1, w2, w3, b0, b1;
+};
+
+// SEL: the SE offsets are staged in LDS (else read with scalar loads from
+// global memory, for SEs too large to share the LDS with the image block).
+template <bool SEL>
+__device__ __forceinline__ void dir_load(DirBuf &B, const int32_t *trow, const int32_t *brow, int jb) {
+    B.w0 = *(const int4 *)(trow + jb);
+    B.w1 = *(const int4 *)(trow + jb + 4);
+    B.w2 = *(const int4 *)(trow + jb + 8);
+    B.w3 = *(const int4 *)(trow + jb + 12);
+    if constexpr (SEL) {
+        B.b0 = *(const int4 *)(brow + jb);
+        B.b1 = *(const int4 *)(brow + jb + 4);
+    } else {
+        const auto c = cst(brow + jb);
+        B.b0 = make_int4(c[0], c[1], c[2], c[3]);
+        B.b1 = make_int4(c[4], c[5], c[6], c[7]);
+    }
+}
+
+template <bool PACK>
+__device__ __forceinline__ void dir_step(typename DirT<PACK>::V (&acc)[kDirRX], const DirBuf &B) {
+    using D = DirT<PACK>;
+    using V = typename D::V;
+    const V in[2 * kDirRX] = {D::word(B.w0.x), D::word(B.w0.y), D::word(B.w0.z), D::word(B.w0.w),
+                              D::word(B.w1.x), D::word(B.w1.y), D::word(B.w1.z), D::word(B.w1.w),
+                              D::word(B.w2.x), D::word(B.w2.y), D::word(B.w2.z), D::word(B.w2.w),
+                              D::word(B.w3.x), D::word(B.w3.y), D::word(B.w3.z), D::word(B.w3.w)};
+    const V b[kDirRX] = {D::word(B.b0.x), D::word(B.b0.y), D::word(B.b0.z), D::word(B.b0.w),
+                         D::word(B.b1.x), D::word(B.b1.y), D::word(B.b1.z), D::word(B.b1.w)};
+    // all sums of one SE column first, then the maxima: a packed op that reads
+    // the result of the instruction right before it costs a wait state
+#pragma unroll
+    for (int sj = 0; sj < kDirRX; ++sj) {
+        V sum[kDirRX];
+#pragma unroll
+        for (int t = 0; t < kDirRX; ++t) sum[t] = in[t + sj] + b[sj];
+#pragma unroll
+        for (int t = 0; t < kDirRX; ++t) acc[t] = D::vmax(acc[t], sum[t]);
+    }
+}
+
+// LDS layout of one direct block: the image words (PR rows of TWD), then each
+// SE row's [first, last] active column, then (SEL) the SE offsets in
+// correlation order (k rows of kpad words, packed or not).
+template <bool PACK, bool SEL>
+__device__ __forceinline__ void direct_block(const JobDev &J, int by0, int bx0, int ye, int xe, int32_t *tile,
+                                             unsigned int *range_err) {
+    using D = DirT<PACK>;
+    using V = typename D::V;
+    constexpr int BH = D::BH;
     const int k = J.k, r = (k - 1) >> 1, kpad = J.kpad;
-    const int TWD = kDirBW + kpad, TH = kDirBH + k - 1;
-    const int H = J.H, W = J.W, L = J.L;
+    const int TWD = kDirBW + kpad;
+    const int TH = BH + k - 1;                       // image rows the block reads
+    const int PR = PACK ? TH - 1 : TH;               // LDS word rows
+    int32_t *rowL = tile + PR * TWD;
+    int32_t *seL = rowL + ((2 * k + 3) & ~3);        // 16-byte aligned for the b128 reads
+    const int32_t *sek = PACK ? J.sek16 : J.sek;
+    if (SEL)
+        for (int q = threadIdx.x; q < k * kpad; q += kDirThreads) seL[q] = gld(sek)[q];
+    for (int q = threadIdx.x; q < 2 * k; q += kDirThreads) rowL[q] = gld(J.sek_rows)[q];
     bool bad = false;
-    for (int q = threadIdx.x; q < TH * TWD; q += kDirThreads) {
-        const int a = q / TWD, c = q - a * TWD;
-        const int gy = by0 - r + a, gx = bx0 - r + c;
-        int v = kNeg;
-        if (gy >= 0 && gy < H && gx >= 0 && gx < W && c < kDirBW + k - 1) {
-            v = J.img[(size_t)gy * W + gx];
-            if ((unsigned)v >= (unsigned)L) {
-                bad = true;
-                v = v < 0 ? 0 : L - 1;
-            }
-            if (J.op) v = L - 1 - v;
+    // staging: 64 lanes of a wave cover consecutive columns (up to 4 x 64 per
+    // row, TWD <= 256), the waves of the block interleave rows; the 4 loads of
+    // a row are independent and in flight together
+    constexpr int kRowsPerPass = kDirThreads / 64;
+    const int lane = threadIdx.x & 63;
+    for (int a = threadIdx.x >> 6; a < TH; a += kRowsPerPass) {
+        const int gy = by0 - r + a;
+        int v[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int c = lane + 64 * u;
+            v[u] = (c < kDirBW + k - 1) ? dir_pix<PACK>(J, gy, bx0 - r + c, bad) : (PACK ? kNeg16 : kNeg);
         }
-        tile[q] = v;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int c = lane + 64 * u;
+            if (c >= TWD) break;
+            if (PACK) {
+                short *h = (short *)tile;
+                if (a < PR) h[2 * (a * TWD + c)] = (short)v[u];            // low half of word row a
+                if (a > 0) h[2 * ((a - 1) * TWD + c) + 1] = (short)v[u];   // high half of word row a-1
+            } else {
+                tile[a * TWD + c] = v[u];
+            }
+        }
     }
     if (bad && range_err) atomicOr(range_err, 1u);
     __syncthreads();
-    const int ly = threadIdx.x / (kDirBW / kDirRX);
+    const int trow0 = (threadIdx.x / (kDirBW / kDirRX)) * (PACK ? 2 : 1);   // first output row of this thread
     const int lx0 = (threadIdx.x % (kDirBW / kDirRX)) * kDirRX;
-    int acc[kDirRX];
+    V acc[kDirRX];
 #pragma unroll
-    for (int t = 0; t < kDirRX; ++t) acc[t] = kNeg;
+    for (int t = 0; t < kDirRX; ++t) acc[t] = D::word(PACK ? (int)(((unsigned)kNeg16 & 0xffffu) * 0x10001u) : kNeg);
     for (int i = 0; i < k; ++i) {
-        const int32_t *trow = tile + (ly + i) * TWD + lx0;
-        const int32_t *brow = J.sek + (size_t)i * kpad;
-        int in[2 * kDirRX];
-#pragma unroll
-        for (int t = 0; t < kDirRX; t += 4) {
-            const int4 v = *(const int4 *)(trow + t);
-            in[t] = v.x; in[t + 1] = v.y; in[t + 2] = v.z; in[t + 3] = v.w;
-        }
-        for (int jb = 0; jb < kpad; jb += kDirRX) {
-#pragma unroll
-            for (int t = 0; t < kDirRX; t += 4) {
-                const int4 v = *(const int4 *)(trow + jb + kDirRX + t);
-                in[kDirRX + t] = v.x; in[kDirRX + t + 1] = v.y; in[kDirRX + t + 2] = v.z; in[kDirRX + t + 3] = v.w;
-            }
-#pragma unroll
-            for (int s = 0; s < kDirRX; ++s) {
-                const int b = brow[jb + s];
-#pragma unroll
-                for (int t = 0; t < kDirRX; ++t) acc[t] = max(acc[t], in[t + s] + b);
-            }
-#pragma unroll
-            for (int t = 0; t < kDirRX; ++t) in[t] = in[t + kDirRX];
+        const int jlo = rowL[2 * i], jhi = rowL[2 * i + 1];   // active cells of SE row i (LDS broadcast)
+        if (jlo > jhi) continue;
+        const int jb0 = jlo & ~(kDirRX - 1);
+        const int32_t *trow = tile + (trow0 + i) * TWD + lx0;
+        const int32_t *brow = (SEL ? seL : sek) + i * kpad;
+        // two register buffers in ping-pong: the LDS words and offsets of the
+        // next 8-cell step are in flight while the current step computes.  The
+        // prefetch is unconditional; it may read up to 16 words past the
+        // active span, which the padding of the LDS block and of the SE
+        // arrays keeps in bounds (those values are never used).
+        // (scheduling barriers keep the compiler from sinking the prefetch
+        // next to its use)
+        DirBuf A, B;
+        dir_load<SEL>(A, trow, brow, jb0);
+        for (int jb = jb0;; jb += 2 * kDirRX) {
+            dir_load<SEL>(B, trow, brow, jb + kDirRX);
+            __builtin_amdgcn_sched_barrier(0);
+            dir_step<PACK>(acc, A);
+            __builtin_amdgcn_sched_barrier(0);
+            if (jb + kDirRX > jhi) break;
+            dir_load<SEL>(A, trow, brow, jb + 2 * kDirRX);
+            __builtin_amdgcn_sched_barrier(0);
+            dir_step<PACK>(acc, B);
+            __builtin_amdgcn_sched_barrier(0);
+            if (jb + 2 * kDirRX > jhi) break;
         }
     }
-    const int gy = by0 + ly;
-    if (gy < ye) {
+    const int L = J.L, W = J.W;
+#pragma unroll
+    for (int hh = 0; hh < (PACK ? 2 : 1); ++hh) {
+        const int gy = by0 + trow0 + hh;
+        if (gy >= ye) continue;
 #pragma unroll
         for (int t = 0; t < kDirRX; ++t) {
             const int gx = bx0 + lx0 + t;
-            if (gx < xe) {
-                const int d = acc[t] < 0 ? 0 : acc[t];
-                J.out[(size_t)gy * W + gx] = J.op ? (L - 1 - d) : d;
-            }
+            if (gx >= xe) continue;
+            int v;
+            if constexpr (PACK) v = hh ? acc[t].y : acc[t].x;
+            else v = acc[t];
+            const int d = v < 0 ? 0 : v;
+            gst(J.out)[(size_t)gy * W + gx] = J.op ? (L - 1 - d) : d;
         }
     }
     __syncthreads();
 }
 
+template <bool PACK, bool SEL>
 __global__ __launch_bounds__(kDirThreads) void k_direct(const JobDev *__restrict__ jobs,
                                                         const Seg *__restrict__ segs, int nseg,
                                                         long long nitems, StatsDev *st) {
@@ -455,22 +662,20 @@ __global__ __launch_bounds__(kDirThreads) void k_direct(const JobDev *__restrict
     for (long long it = blockIdx.x; it < nitems; it += gridDim.x) {
         const Seg S = segs[find_seg(segs, nseg, it)];
         const JobDev &J = jobs[S.job];
-        const long long local = it - S.item0;
-        const int byi = (int)(local / J.dir_bx), bxi = (int)(local % J.dir_bx);
-        direct_block(J, byi * kDirBH, bxi * kDirBW, J.H, J.W, dyn_lds, &st->range_err);
+        const int local = (int)(it - S.item0);
+        const int byi = local / J.dir_bx, bxi = local - byi * J.dir_bx;
+        direct_block<PACK, SEL>(J, byi * DirT<PACK>::BH, bxi * kDirBW, J.H, J.W, dyn_lds, &st->range_err);
     }
 }
 
 // Exact recompute of the tiles listed by the decode: FP64 transforms on
 // nt64-sized sub-tiles, each decoded from this block's slot.
 template <int N>
-__global__ __launch_bounds__(256) void k_fallback(const JobDev *__restrict__ jobs,
+__global__ __launch_bounds__(kDecThreads) void k_fallback(const JobDev *__restrict__ jobs,
                                                   const int2 *__restrict__ fb_list,
                                                   const StatsDev *__restrict__ st, double2 *slots,
                                                   size_t slot_elems, const double2 *__restrict__ tw64) {
     __shared__ double2 lds[N * (N + 1)];
-    __shared__ int s_top[kDecTPP][64];
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     Tw64 tw;
     tw.p = tw64;
     const unsigned cnt = __builtin_amdgcn_readfirstlane(*(volatile const unsigned *)&st->fb_count);
@@ -492,25 +697,19 @@ __global__ __launch_bounds__(256) void k_fallback(const JobDev *__restrict__ job
                                                  J.enc64 + (size_t)m * J.L, J.se_spec64 + (size_t)m * N * N,
                                                  slot + m * TT, tw, nullptr);
                 const int sh = min(T64, oh - sy), sw = min(T64, ow - sx);
-                for (int p0 = 0; p0 < (int)TT; p0 += 64) {
-                    const int p = p0 + lane;
+                for (int p0 = 0; p0 < (int)TT; p0 += kDecThreads) {
+                    const int p = p0 + threadIdx.x;
                     const int ly = p / T64, lx = p - ly * T64;
                     const bool valid = p < (int)TT && ly < sh && lx < sw;
                     int top;
                     double res;
-                    decode_px<double, 24>(slot, TT, p, valid, J.dec64, J.nr, J.bins, J.scale64, top, res);
-                    s_top[w][lane] = top;
-                    __syncthreads();
-                    if (w == 0) {
-#pragma unroll
-                        for (int v = 1; v < kDecTPP; ++v) top = max(top, s_top[v][lane]);
-                        if (valid) {
-                            const int d = top < 0 ? 0 : top;
-                            J.out[(size_t)(oy0 + sy + ly) * J.W + (ox0 + sx + lx)] = J.op ? (J.L - 1 - d) : d;
-                        }
+                    decode_pixel<double>(slot, TT, p, valid, J.dec64, J.nr, J.bins, J.scale64, top, res);
+                    if (valid) {
+                        const int d = top < 0 ? 0 : top;
+                        gst(J.out)[(size_t)(oy0 + sy + ly) * J.W + (ox0 + sx + lx)] = J.op ? (J.L - 1 - d) : d;
                     }
-                    __syncthreads();
                 }
+                __syncthreads();   // the slot is rewritten by the next sub-tile
             }
         }
     }
@@ -531,8 +730,15 @@ __global__ __launch_bounds__(kDirThreads) void k_fallback_direct(const JobDev *_
         const int ty = tile / J.tiles_x, tx = tile - ty * J.tiles_x;
         const int oy0 = ty * J.T, ox0 = tx * J.T;
         const int ye = min(oy0 + J.T, J.H), xe = min(ox0 + J.T, J.W);
-        for (int by0 = oy0; by0 < ye; by0 += kDirBH)
-            for (int bx0 = ox0; bx0 < xe; bx0 += kDirBW) direct_block(J, by0, bx0, ye, xe, dyn_lds, nullptr);
+        if (J.dir_pack) {
+            for (int by0 = oy0; by0 < ye; by0 += DirT<true>::BH)
+                for (int bx0 = ox0; bx0 < xe; bx0 += kDirBW)
+                    direct_block<true, false>(J, by0, bx0, ye, xe, dyn_lds, nullptr);
+        } else {
+            for (int by0 = oy0; by0 < ye; by0 += DirT<false>::BH)
+                for (int bx0 = ox0; bx0 < xe; bx0 += kDirBW)
+                    direct_block<false, false>(J, by0, bx0, ye, xe, dyn_lds, nullptr);
+        }
     }
 }
 
@@ -554,12 +760,13 @@ __global__ void k_twiddles(double2 *tw64, TwF *tw32) {
 }
 
 // enc[m][v] = exp(-2 pi i (v m mod nr) / nr): range-axis DFT of the one-hot
-// column of grey value v (Eq. (7)).  dec[d][m] = w_m exp(+2 pi i (d m mod nr)
-// / nr), w_m = 1 for m = 0 and m = nr/2, 2 otherwise: the inverse real DFT
-// from the kept half of the bins (unscaled).
+// column of grey value v (Eq. (7)).  dec[m][d] = w_m exp(+2 pi i (d m mod nr)
+// / nr) for d <= nr/2, w_m = 1 for m = 0 and m = nr/2, 2 otherwise: the inverse
+// real DFT from the kept half of the bins (unscaled); degrees above nr/2
+// follow by symmetry in the decode.
 __global__ void k_range_tables(int nr, int L, int bins, float2 *enc32, double2 *enc64, float2 *dec32,
                                double2 *dec64) {
-    const long long ne = (long long)bins * L, nd = (long long)nr * bins;
+    const long long ne = (long long)bins * L, nd = (long long)bins * bins;
     for (long long q = blockIdx.x * (long long)blockDim.x + threadIdx.x; q < ne + nd;
          q += (long long)gridDim.x * blockDim.x) {
         double s, c;
@@ -571,7 +778,7 @@ __global__ void k_range_tables(int nr, int L, int bins, float2 *enc32, double2 *
             enc32[q] = make_float2((float)c, (float)s);
         } else {
             const long long e = q - ne;
-            const long long d = e / bins, m = e % bins;
+            const long long m = e / bins, d = e % bins;
             const long long ph = (d * m) % nr;
             sincospi(2.0 * (double)ph / nr, &s, &c);
             const double wt = (m == 0 || 2 * m == nr) ? 1.0 : 2.0;
@@ -622,6 +829,20 @@ __global__ void k_se_cols(const double2 *__restrict__ G, int k, int nt, const do
     }
 }
 
+// Pseudo-random grey values in [0, L) from a 32-bit integer hash of the
+// index (calibration images of the autotuner).
+__global__ void k_fill_hash(int32_t *p, size_t n, int L, unsigned int seed) {
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+        unsigned int h = (unsigned int)i * 0x9E3779B1u ^ seed;
+        h ^= h >> 16;
+        h *= 0x85EBCA6Bu;
+        h ^= h >> 13;
+        h *= 0xC2B2AE35u;
+        h ^= h >> 16;
+        p[i] = (int32_t)(h % (unsigned int)L);
+    }
+}
+
 __global__ void k_zero(uint32_t *p, size_t n) {
     for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
         p[i] = 0u;
@@ -650,7 +871,7 @@ hipError_t launch_twiddles(double2 *tw64, TwF *tw32, hipStream_t s) {
 hipError_t launch_range_tables(int nr, int L, float2 *enc32, double2 *enc64, float2 *dec32, double2 *dec64,
                                hipStream_t s) {
     const int bins = nr / 2 + 1;
-    const long long n = (long long)bins * L + (long long)nr * bins;
+    const long long n = (long long)bins * L + (long long)bins * bins;
     const int grid = (int)std::min<long long>((n + 255) / 256, 4096);
     k_range_tables<<<grid, 256, 0, s>>>(nr, L, bins, enc32, enc64, dec32, dec64);
     return hipGetLastError();
@@ -665,6 +886,12 @@ hipError_t launch_se_spectrum(const uint8_t *mask_d, const int32_t *off_d, int k
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     k_se_cols<<<bins * nt, threads, 0, s>>>(work, k, nt, tw64, spec64, spec32);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_hash(int32_t *p, size_t n, int L, unsigned int seed, hipStream_t s) {
+    const int grid = (int)std::min<size_t>((n + 255) / 256, 2048);
+    k_fill_hash<<<grid, 256, 0, s>>>(p, n, L, seed);
     return hipGetLastError();
 }
 
@@ -704,34 +931,37 @@ hipError_t launch_fft(int nt, int dbl, const JobDev *jobs, const Seg *segs, int 
 hipError_t launch_decode(int big, int dbl, const JobDev *jobs, const Seg *segs, int nseg, long long nitems,
                          int grid, float band, unsigned int *tile_flags, int2 *fb_list, StatsDev *st,
                          hipStream_t s) {
+    (void)big;
     if (nitems <= 0) return hipSuccess;
-    if (!dbl) {
-        if (big) k_decode<float, 24><<<grid, kDecThreads, 0, s>>>(jobs, segs, nseg, nitems, band, tile_flags, fb_list, st);
-        else k_decode<float, 8><<<grid, kDecThreads, 0, s>>>(jobs, segs, nseg, nitems, band, tile_flags, fb_list, st);
-    } else {
-        if (big) k_decode<double, 24><<<grid, kDecThreads, 0, s>>>(jobs, segs, nseg, nitems, band, tile_flags, fb_list, st);
-        else k_decode<double, 8><<<grid, kDecThreads, 0, s>>>(jobs, segs, nseg, nitems, band, tile_flags, fb_list, st);
-    }
+    if (!dbl) k_decode<float><<<grid, kDecThreads, 0, s>>>(jobs, segs, nseg, nitems, band, tile_flags, fb_list, st);
+    else k_decode<double><<<grid, kDecThreads, 0, s>>>(jobs, segs, nseg, nitems, band, tile_flags, fb_list, st);
     return hipGetLastError();
 }
 
-size_t direct_lds_bytes(int k, int kpad) {
-    return (size_t)(kDirBH + k - 1) * (kDirBW + kpad) * sizeof(int32_t);
+int direct_block_rows(int pack) { return pack ? DirT<true>::BH : DirT<false>::BH; }
+
+size_t direct_lds_bytes(int k, int kpad, int pack, int sel) {
+    const int rows = pack ? DirT<true>::BH + k - 2 : DirT<false>::BH + k - 1;
+    return ((size_t)rows * (kDirBW + kpad) + (sel ? (size_t)k * kpad : 0) + (size_t)((2 * k + 3) & ~3) + 16) *
+           sizeof(int32_t);
 }
 
-hipError_t launch_direct(const JobDev *jobs, const Seg *segs, int nseg, long long nitems, int grid,
-                         size_t lds_bytes, StatsDev *st, hipStream_t s) {
+hipError_t launch_direct(int pack, int sel, const JobDev *jobs, const Seg *segs, int nseg, long long nitems,
+                         int grid, size_t lds_bytes, StatsDev *st, hipStream_t s) {
     if (nitems <= 0) return hipSuccess;
-    k_direct<<<grid, kDirThreads, lds_bytes, s>>>(jobs, segs, nseg, nitems, st);
+    if (pack && sel) k_direct<true, true><<<grid, kDirThreads, lds_bytes, s>>>(jobs, segs, nseg, nitems, st);
+    else if (pack) k_direct<true, false><<<grid, kDirThreads, lds_bytes, s>>>(jobs, segs, nseg, nitems, st);
+    else if (sel) k_direct<false, true><<<grid, kDirThreads, lds_bytes, s>>>(jobs, segs, nseg, nitems, st);
+    else k_direct<false, false><<<grid, kDirThreads, lds_bytes, s>>>(jobs, segs, nseg, nitems, st);
     return hipGetLastError();
 }
 
 hipError_t launch_fallback(int nt64, const JobDev *jobs, const int2 *fb_list, const StatsDev *st,
                            double2 *slots, size_t slot_elems, int grid, const double2 *tw64, hipStream_t s) {
     switch (nt64) {
-        case 16: k_fallback<16><<<grid, 256, 0, s>>>(jobs, fb_list, st, slots, slot_elems, tw64); break;
-        case 32: k_fallback<32><<<grid, 256, 0, s>>>(jobs, fb_list, st, slots, slot_elems, tw64); break;
-        case 64: k_fallback<64><<<grid, 256, 0, s>>>(jobs, fb_list, st, slots, slot_elems, tw64); break;
+        case 16: k_fallback<16><<<grid, kDecThreads, 0, s>>>(jobs, fb_list, st, slots, slot_elems, tw64); break;
+        case 32: k_fallback<32><<<grid, kDecThreads, 0, s>>>(jobs, fb_list, st, slots, slot_elems, tw64); break;
+        case 64: k_fallback<64><<<grid, kDecThreads, 0, s>>>(jobs, fb_list, st, slots, slot_elems, tw64); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

@@ -59,6 +59,8 @@ struct Options {
     int sync = 1;
     int graph = 1;
     double ws_mb = 8192.0;
+    int profile = 0;
+    int autotune = 1;
 };
 
 // Device buffer that only grows.
@@ -91,7 +93,7 @@ struct SESpec {
 };
 
 struct DirSE {
-    DevBuf sek;
+    DevBuf sek, sek16, rows;
     int kpad = 0;
 };
 
@@ -110,6 +112,9 @@ struct Group {
     long long nitems = 0;
     Seg *segs_d = nullptr;
     int grid = 0;
+    // algorithmic DRAM bytes / operations of the whole launch, and the work
+    // units the cost model prices it by
+    double alg_bytes = 0, alg_ops = 0, units = 0;
 };
 
 struct Wave {
@@ -124,8 +129,8 @@ struct Exec {
     JobDev *jobs_pin = nullptr;
     hipEvent_t copy_done = nullptr;
     bool copy_pending = false;
-    Group direct;
-    size_t direct_lds = 0;
+    Group direct[4];              // index pack + 2*sel: int32 / packed 16-bit form, SE in LDS or not
+    size_t direct_lds[4] = {0, 0, 0, 0};
     std::vector<Wave> waves;
     DevBuf segbuf, ybuf, flags, list, slots;
     long long nflags = 0;
@@ -179,6 +184,21 @@ struct Ctx {
     std::unordered_map<std::string, std::unique_ptr<DirSE>> dirse;
     std::unordered_map<std::string, std::unique_ptr<Exec>> execs;
     DevBuf se_work, se_in;
+    // profiling
+    struct Pending {
+        std::string name;
+        hipEvent_t a, b;
+        double bytes, ops, units;
+    };
+    struct Total {
+        double ms = 0;
+        long long launches = 0;
+        double bytes = 0, ops = 0, units = 0;
+    };
+    std::vector<Pending> pending;
+    std::map<std::string, Total> prof;
+    std::vector<hipEvent_t> evpool;
+    bool tuned = false, tuning = false, cost_measured = false;
 };
 
 Ctx g;
@@ -223,7 +243,7 @@ int get_range(int nr, int L, RangeTables **out) {
     }
     auto rt = std::make_unique<RangeTables>();
     const size_t bins = nr / 2 + 1;
-    const size_t ne = bins * (size_t)L, nd = (size_t)nr * bins;
+    const size_t ne = bins * (size_t)L, nd = bins * bins;
     MD_TRY(rt->enc32.ensure(ne * sizeof(float2)));
     MD_TRY(rt->enc64.ensure(ne * sizeof(double2)));
     MD_TRY(rt->dec32.ensure(nd * sizeof(float2)));
@@ -305,7 +325,9 @@ int get_spectrum(const SEData &se, int nt, int nr, bool need32, bool need64, SES
     return MD_OK;
 }
 
-// Correlation-order offsets for the direct window: reflect the effective SE.
+// Correlation-order offsets for the direct window (the effective SE
+// reflected), as int32 and as packed 16-bit pairs, plus each row's span of
+// active cells.
 int get_dirse(const SEData &se, DirSE **out) {
     auto it = g.dirse.find(se.key);
     if (it != g.dirse.end()) {
@@ -315,14 +337,31 @@ int get_dirse(const SEData &se, DirSE **out) {
     auto d = std::make_unique<DirSE>();
     const int k = se.k;
     d->kpad = (k + kDirRX - 1) / kDirRX * kDirRX;
-    std::vector<int32_t> h((size_t)k * d->kpad, kNeg);
-    for (int i = 0; i < k; ++i)
+    // 16 words of padding after the last row: the direct kernel prefetches
+    // past the end of a row's active span
+    std::vector<int32_t> h((size_t)k * d->kpad + 16, kNeg), h16((size_t)k * d->kpad + 16), rows((size_t)2 * k);
+    const uint32_t neg16 = 0xC000C000u;   // -16384 in both lanes
+    for (size_t q = 0; q < h16.size(); ++q) h16[q] = (int32_t)neg16;
+    for (int i = 0; i < k; ++i) {
+        int lo = k, hi = -1;
         for (int j = 0; j < k; ++j) {
             const size_t src = (size_t)(k - 1 - i) * k + (k - 1 - j);
-            if (se.mask[src]) h[(size_t)i * d->kpad + j] = se.off[src];
+            if (!se.mask[src]) continue;
+            const int32_t b = se.off[src];
+            h[(size_t)i * d->kpad + j] = b;
+            h16[(size_t)i * d->kpad + j] = (int32_t)(((uint32_t)b & 0xffffu) * 0x10001u);
+            lo = std::min(lo, j);
+            hi = std::max(hi, j);
         }
+        rows[2 * i] = lo;
+        rows[2 * i + 1] = hi;
+    }
     MD_TRY(d->sek.ensure(h.size() * sizeof(int32_t)));
+    MD_TRY(d->sek16.ensure(h16.size() * sizeof(int32_t)));
+    MD_TRY(d->rows.ensure(rows.size() * sizeof(int32_t)));
     MD_HIP(hipMemcpy(d->sek.p, h.data(), h.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+    MD_HIP(hipMemcpy(d->sek16.p, h16.data(), h16.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+    MD_HIP(hipMemcpy(d->rows.p, rows.data(), rows.size() * sizeof(int32_t), hipMemcpyHostToDevice));
     *out = d.get();
     g.dirse[se.key] = std::move(d);
     return MD_OK;
@@ -370,7 +409,8 @@ int plan_job(const md_job &j, const SEData &se, Plan &p) {
     p.nr = nr;
     p.bins = nr / 2 + 1;
     const int kpad = (j.k + kDirRX - 1) / kDirRX * kDirRX;
-    p.cost_dir = (double)j.H * j.W * j.k * kpad * g.cost.dir_unit;
+    const bool pack16 = (long long)(j.L - 1) + se.maxoff <= 16383;
+    p.cost_dir = (double)j.H * j.W * j.k * kpad * g.cost.dir_unit * (pack16 ? 1.0 : 2.0);
     // transform plan: best spatial length by the cost model
     double best = INFINITY;
     int best_nt = 0;
@@ -464,7 +504,8 @@ std::string signature(const md_job *jobs, int n, const std::vector<SEData> &ses)
 int build_exec(const md_job *jobs, int n, const std::vector<SEData> &ses, Exec &ex) {
     ex.jobs_h.resize(n);
     ex.plans.resize(n);
-    size_t max_dir_lds = 0, max_fbdir_lds = 0;
+    size_t max_dir_lds[4] = {0, 0, 0, 0}, max_fbdir_lds = 0;
+    std::vector<int> dir_cls(n, 0);
     long long flag_total = 0;
     const size_t cap_bytes = (size_t)std::max(1.0, g.opt.ws_mb) * 1024 * 1024;
     // per-job plans and device descriptors
@@ -486,12 +527,18 @@ int build_exec(const md_job *jobs, int n, const std::vector<SEData> &ses, Exec &
             DirSE *ds = nullptr;
             MD_TRY(get_dirse(ses[i], &ds));
             d.sek = (const int32_t *)ds->sek.p;
+            d.sek16 = (const int32_t *)ds->sek16.p;
+            d.sek_rows = (const int32_t *)ds->rows.p;
             d.kpad = ds->kpad;
+            d.dir_pack = (long long)(j.L - 1) + ses[i].maxoff <= 16383 ? 1 : 0;
             d.dir_bx = (j.W + kDirBW - 1) / kDirBW;
-            d.dir_by = (j.H + kDirBH - 1) / kDirBH;
-            const size_t lds = direct_lds_bytes(j.k, ds->kpad);
-            if (p.path == kPathDirect) max_dir_lds = std::max(max_dir_lds, lds);
-            else max_fbdir_lds = std::max(max_fbdir_lds, lds);
+            d.dir_by = (j.H + direct_block_rows(d.dir_pack) - 1) / direct_block_rows(d.dir_pack);
+            const int sel = direct_lds_bytes(j.k, ds->kpad, d.dir_pack, 1) <= kLdsBytes ? 1 : 0;
+            dir_cls[i] = d.dir_pack + 2 * sel;
+            const size_t lds = direct_lds_bytes(j.k, ds->kpad, d.dir_pack, sel);
+            if (lds > kLdsBytes) return fail(MD_ERR_UNSUPPORTED, "direct window for k=%d exceeds the LDS", j.k);
+            if (p.path == kPathDirect) max_dir_lds[dir_cls[i]] = std::max(max_dir_lds[dir_cls[i]], lds);
+            else max_fbdir_lds = std::max(max_fbdir_lds, direct_lds_bytes(j.k, ds->kpad, d.dir_pack, 0));
         }
         if (p.path == kPathDirect) {
             ++ex.n_direct;
@@ -533,16 +580,21 @@ int build_exec(const md_job *jobs, int n, const std::vector<SEData> &ses, Exec &
             ex.fb_direct = true;
         }
     }
-    // direct group: one segment per direct job
+    // direct groups (int32 / packed): one segment per direct job
     for (int i = 0; i < n; ++i) {
         if (ex.plans[i].path != kPathDirect) continue;
+        Group &gr = ex.direct[dir_cls[i]];
         Seg s{};
-        s.item0 = ex.direct.nitems;
+        s.item0 = gr.nitems;
         s.job = i;
-        ex.direct.segs.push_back(s);
-        ex.direct.nitems += (long long)ex.jobs_h[i].dir_bx * ex.jobs_h[i].dir_by;
+        gr.segs.push_back(s);
+        gr.nitems += (long long)ex.jobs_h[i].dir_bx * ex.jobs_h[i].dir_by;
+        const double px = (double)jobs[i].H * jobs[i].W;
+        gr.alg_bytes += px * 8.0;
+        gr.alg_ops += px * ses[i].ncells * 2.0;
+        gr.units += px * jobs[i].k * ex.jobs_h[i].kpad;
     }
-    ex.direct_lds = max_dir_lds;
+    for (int c = 0; c < 4; ++c) ex.direct_lds[c] = max_dir_lds[c];
     ex.fb_direct_lds = max_fbdir_lds;
     // FFT jobs: split tile ranges into waves bounded by the workspace cap
     std::vector<std::vector<std::pair<int, std::pair<int, int>>>> wave_chunks(1);   // (job, (tile0, ntiles))
@@ -584,22 +636,37 @@ int build_exec(const md_job *jobs, int n, const std::vector<SEData> &ses, Exec &
             s.job = i;
             s.tile0 = tile0;
             s.ntiles = nt_;
-            s.pblocks = (p.T * p.T + 63) / 64;
+            s.pblocks = (p.T * p.T + kDecThreads - 1) / kDecThreads;
             s.y = (char *)ex.ybuf.p + off;
             off += per_tile * nt_;
+            const double esz = p.dbl ? 16.0 : 8.0, N2 = (double)p.nt * p.nt, TT = (double)p.T * p.T;
+            const double items = (double)nt_ * p.bins;
             Group *gf = find_group(wv.fft, p.nt, p.dbl, 0);
             s.item0 = gf->nitems;
             gf->segs.push_back(s);
             gf->nitems += (long long)nt_ * p.bins;
+            gf->alg_bytes += items * TT * esz + (double)nt_ * N2 * 4.0;
+            gf->alg_ops += items * (2.0 * 5.0 * N2 * log2(N2) + 6.0 * N2);
+            gf->units += items;
             Group *gd = find_group(wv.dec, 0, p.dbl, p.nr > 32 ? 1 : 0);
             s.item0 = gd->nitems;
             gd->segs.push_back(s);
             gd->nitems += (long long)nt_ * s.pblocks;
+            // pixels of these tiles that lie inside the image
+            double inside = 0;
+            for (int t = tile0; t < tile0 + nt_; ++t) {
+                const int ty = t / p.tiles_x, tx = t % p.tiles_x;
+                inside += (double)std::min(p.T, jobs[i].H - ty * p.T) * std::min(p.T, jobs[i].W - tx * p.T);
+            }
+            gd->alg_bytes += inside * (p.bins * esz + 4.0);
+            gd->alg_ops += inside * p.nr * p.bins * 4.0;
+            gd->units += (double)nt_ * TT * p.nr * p.bins;
         }
         ex.waves.push_back(std::move(wv));
     }
     // device copies of the segment tables
-    size_t nseg_total = ex.direct.segs.size();
+    size_t nseg_total = 0;
+    for (int c = 0; c < 4; ++c) nseg_total += ex.direct[c].segs.size();
     for (auto &wv : ex.waves) {
         for (auto &gr : wv.fft) nseg_total += gr.segs.size();
         for (auto &gr : wv.dec) nseg_total += gr.segs.size();
@@ -612,7 +679,8 @@ int build_exec(const md_job *jobs, int n, const std::vector<SEData> &ses, Exec &
         all.insert(all.end(), gr.segs.begin(), gr.segs.end());
         gr.grid = occupancy_grid(gr.nitems, lds, threads);
     };
-    if (!ex.direct.segs.empty()) place(ex.direct, kDirThreads, ex.direct_lds);
+    for (int c = 0; c < 4; ++c)
+        if (!ex.direct[c].segs.empty()) place(ex.direct[c], kDirThreads, ex.direct_lds[c]);
     for (auto &wv : ex.waves) {
         for (auto &gr : wv.fft) {
             const size_t lds = (size_t)gr.nt * (gr.nt + 1) * (gr.dbl ? sizeof(double2) : sizeof(float2));
@@ -638,34 +706,104 @@ int build_exec(const md_job *jobs, int n, const std::vector<SEData> &ses, Exec &
     return MD_OK;
 }
 
+hipEvent_t ev_get() {
+    if (!g.evpool.empty()) {
+        hipEvent_t e = g.evpool.back();
+        g.evpool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+// Event pair around one launch when profiling (never inside a capture).
+struct ProfScope {
+    bool on;
+    hipStream_t s;
+    hipEvent_t a = nullptr;
+    std::string name;
+    double bytes, ops, units;
+    ProfScope(bool on_, hipStream_t s_, std::string n, double b, double o, double u)
+        : on(on_), s(s_), name(std::move(n)), bytes(b), ops(o), units(u) {
+        if (on && (a = ev_get())) (void)hipEventRecord(a, s);
+    }
+    void done() {
+        if (!on || !a) return;
+        hipEvent_t b = ev_get();
+        if (!b) return;
+        (void)hipEventRecord(b, s);
+        g.pending.push_back({name, a, b, bytes, ops, units});
+        a = nullptr;
+    }
+};
+
+void resolve_profile() {
+    for (auto &p : g.pending) {
+        float ms = 0;
+        if (hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
+            auto &t = g.prof[p.name];
+            t.ms += ms;
+            t.launches += 1;
+            t.bytes += p.bytes;
+            t.ops += p.ops;
+            t.units += p.units;
+        }
+        g.evpool.push_back(p.a);
+        g.evpool.push_back(p.b);
+    }
+    g.pending.clear();
+}
+
 // Stream-ordered launches of one batch.
-int enqueue(Exec &ex, hipStream_t s, bool skip_decode = false) {
+int enqueue(Exec &ex, hipStream_t s, bool skip_decode = false, bool capturing = false) {
+    const bool prof = g.opt.profile && !capturing;
     MD_HIP(launch_zero(g.st_d, sizeof(StatsDev), s));
     if (ex.nflags > 0) MD_HIP(launch_zero(ex.flags.p, ex.nflags * sizeof(unsigned int), s));
-    if (ex.direct.nitems > 0)
-        MD_HIP(launch_direct(ex.jobs_d, ex.direct.segs_d, (int)ex.direct.segs.size(), ex.direct.nitems,
-                             ex.direct.grid, ex.direct_lds, g.st_d, s));
+    for (int c = 0; c < 4; ++c) {
+        Group &gr = ex.direct[c];
+        if (gr.nitems <= 0) continue;
+        const int pk = c & 1, sel = c >> 1;
+        ProfScope ps(prof, s, pk ? "direct16" : "direct32", gr.alg_bytes, gr.alg_ops, gr.units);
+        MD_HIP(launch_direct(pk, sel, ex.jobs_d, gr.segs_d, (int)gr.segs.size(), gr.nitems, gr.grid, ex.direct_lds[c],
+                             g.st_d, s));
+        ps.done();
+    }
     const float band = (float)g.opt.band;
     for (auto &wv : ex.waves) {
-        for (auto &gr : wv.fft)
+        for (auto &gr : wv.fft) {
+            ProfScope ps(prof, s, std::string(gr.dbl ? "fft64_n" : "fft32_n") + std::to_string(gr.nt), gr.alg_bytes,
+                         gr.alg_ops, gr.units);
             MD_HIP(launch_fft(gr.nt, gr.dbl, ex.jobs_d, gr.segs_d, (int)gr.segs.size(), gr.nitems, gr.grid, g.tw32,
                               g.tw64, g.st_d, s));
+            ps.done();
+        }
         if (skip_decode) continue;
-        for (auto &gr : wv.dec)
+        for (auto &gr : wv.dec) {
+            ProfScope ps(prof, s, gr.dbl ? "decode64" : "decode32", gr.alg_bytes, gr.alg_ops, gr.units);
             MD_HIP(launch_decode(gr.big, gr.dbl, ex.jobs_d, gr.segs_d, (int)gr.segs.size(), gr.nitems, gr.grid,
                                  band, (unsigned int *)ex.flags.p, (int2 *)ex.list.p, g.st_d, s));
+            ps.done();
+        }
     }
     if (skip_decode) return MD_OK;
-    for (int nt64 : ex.fb_classes)
+    for (int nt64 : ex.fb_classes) {
+        ProfScope ps(prof, s, "recompute64_n" + std::to_string(nt64), 0, 0, 0);
         MD_HIP(launch_fallback(nt64, ex.jobs_d, (const int2 *)ex.list.p, g.st_d, (double2 *)ex.slots.p,
                                ex.slot_elems, ex.fb_grid, g.tw64, s));
-    if (ex.fb_direct)
+        ps.done();
+    }
+    if (ex.fb_direct) {
+        ProfScope ps(prof, s, "recompute_direct", 0, 0, 0);
         MD_HIP(launch_fallback_direct(ex.jobs_d, (const int2 *)ex.list.p, g.st_d, g.cu, ex.fb_direct_lds, s));
+        ps.done();
+    }
     return MD_OK;
 }
 
 int collect_stats(Exec &ex, int *range_err) {
     MD_HIP(hipStreamSynchronize(g.stream));
+    resolve_profile();
     MD_HIP(hipMemcpy(g.st_h, g.st_d, sizeof(StatsDev), hipMemcpyDeviceToHost));
     md_stats &st = g.last;
     float res;
@@ -685,8 +823,122 @@ int collect_stats(Exec &ex, int *range_err) {
     return MD_OK;
 }
 
+int run(const md_job *jobs, int n, bool use_graph);
+
+// Autotuner: time each kernel family on calibration images on this device
+// and replace the cost model's built-in estimates with the measured rates.
+int autotune_body() {
+    const int H = 1024, W = 1024, L = 16;
+    DevBuf img, out;
+    MD_TRY(img.ensure((size_t)H * W * 4));
+    MD_TRY(out.ensure((size_t)H * W * 4));
+    MD_HIP(launch_fill_hash((int32_t *)img.p, (size_t)H * W, L, 12345u, g.stream));
+    g.opt.sync = 1;
+    g.opt.graph = 0;
+    g.opt.profile = 1;
+    g.opt.nr = 0;
+    g.opt.band = 0.25;
+    auto measure = [&](int k, int path, int prec, int tile, const std::string &stage, double *per_unit,
+                       const std::string &stage2, double *per_unit2) -> int {
+        std::vector<uint8_t> mask((size_t)k * k, 1);
+        std::vector<int32_t> off((size_t)k * k);
+        for (size_t q = 0; q < off.size(); ++q) off[q] = (int32_t)(q % 4);
+        md_job j{(const int32_t *)img.p, H, W, L, mask.data(), off.data(), k, (int32_t *)out.p, 0};
+        g.opt.path = path;
+        g.opt.precision = prec;
+        g.opt.tile = tile;
+        MD_TRY(run(&j, 1, false));
+        g.prof.clear();
+        for (int r = 0; r < 3; ++r) MD_TRY(run(&j, 1, false));
+        auto get = [&](const std::string &name, double *dst) {
+            auto it = g.prof.find(name);
+            if (dst && it != g.prof.end() && it->second.units > 0) *dst = it->second.ms * 1e6 / it->second.units;
+        };
+        get(stage, per_unit);
+        if (!stage2.empty()) get(stage2, per_unit2);
+        return MD_OK;
+    };
+    MD_TRY(measure(15, kPathDirect, 0, 0, "direct16", &g.cost.dir_unit, "", nullptr));
+    for (int nt : {16, 32, 64, 128})
+        MD_TRY(measure(nt / 8 * 2 + 1, kPathFFT, 0, nt, "fft32_n" + std::to_string(nt), &g.cost.fft_item[0][ilog2i(nt)],
+                       "decode32", &g.cost.dec_unit[0]));
+    for (int nt : {16, 32, 64})
+        MD_TRY(measure(nt / 8 * 2 + 1, kPathFFT, 1, nt, "fft64_n" + std::to_string(nt), &g.cost.fft_item[1][ilog2i(nt)],
+                       "decode64", &g.cost.dec_unit[1]));
+    return MD_OK;
+}
+
+// Persisted cost model: MD_TUNE_FILE names a text file of "key value" lines,
+// valid for the device whose name and compute-unit count it records.
+std::string device_key() {
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, g.device) != hipSuccess) return "unknown";
+    return std::string(prop.gcnArchName) + "/" + std::to_string(prop.multiProcessorCount);
+}
+
+bool load_tune_file() {
+    const char *path = getenv("MD_TUNE_FILE");
+    if (!path || !*path) return false;
+    FILE *f = fopen(path, "r");
+    if (!f) return false;
+    char key[128], dev[256] = {0};
+    double v;
+    CostModel c = g.cost;
+    int got = 0;
+    bool dev_ok = false;
+    if (fscanf(f, "device %255s", dev) == 1 && device_key() == dev) dev_ok = true;
+    while (dev_ok && fscanf(f, "%127s %lf", key, &v) == 2) {
+        const std::string k(key);
+        if (k == "direct") c.dir_unit = v, ++got;
+        else if (k == "decode32") c.dec_unit[0] = v, ++got;
+        else if (k == "decode64") c.dec_unit[1] = v, ++got;
+        else if (k.rfind("fft32_n", 0) == 0) c.fft_item[0][ilog2i(atoi(k.c_str() + 7))] = v, ++got;
+        else if (k.rfind("fft64_n", 0) == 0) c.fft_item[1][ilog2i(atoi(k.c_str() + 7))] = v, ++got;
+    }
+    fclose(f);
+    if (!dev_ok || got < 10) return false;
+    g.cost = c;
+    return true;
+}
+
+void save_tune_file() {
+    const char *path = getenv("MD_TUNE_FILE");
+    if (!path || !*path) return;
+    FILE *f = fopen(path, "w");
+    if (!f) return;
+    fprintf(f, "device %s\n", device_key().c_str());
+    fprintf(f, "direct %.9g\ndecode32 %.9g\ndecode64 %.9g\n", g.cost.dir_unit, g.cost.dec_unit[0], g.cost.dec_unit[1]);
+    for (int nt : {16, 32, 64, 128}) fprintf(f, "fft32_n%d %.9g\n", nt, g.cost.fft_item[0][ilog2i(nt)]);
+    for (int nt : {16, 32, 64}) fprintf(f, "fft64_n%d %.9g\n", nt, g.cost.fft_item[1][ilog2i(nt)]);
+    fclose(f);
+}
+
+int autotune() {
+    if (g.tuned || g.tuning) return MD_OK;
+    if (load_tune_file()) {
+        g.tuned = true;
+        g.cost_measured = true;
+        return MD_OK;
+    }
+    g.tuning = true;
+    const Options saved = g.opt;
+    const auto saved_prof = g.prof;
+    const md_stats saved_stats = g.last;
+    const int rc = autotune_body();
+    g.opt = saved;
+    g.prof = saved_prof;
+    g.last = saved_stats;
+    g.execs.clear();
+    g.tuning = false;
+    g.tuned = rc == MD_OK;
+    g.cost_measured = rc == MD_OK;
+    if (rc == MD_OK) save_tune_file();
+    return rc;
+}
+
 int run(const md_job *jobs, int n, bool use_graph) {
     MD_TRY(init());
+    if (g.opt.path == 0 && g.opt.autotune && !g.tuned && !g.tuning) MD_TRY(autotune());
     if (n < 1 || !jobs) return fail(MD_ERR_ARG, "empty batch");
     std::vector<SEData> ses(n);
     for (int i = 0; i < n; ++i) {
@@ -730,7 +982,7 @@ int run(const md_job *jobs, int n, bool use_graph) {
             ex->gexec = nullptr;
             ex->graph = nullptr;
             MD_HIP(hipStreamBeginCapture(g.stream, hipStreamCaptureModeThreadLocal));
-            const int rc = enqueue(*ex, g.stream);
+            const int rc = enqueue(*ex, g.stream, false, true);
             hipGraph_t gr = nullptr;
             const hipError_t ee = hipStreamEndCapture(g.stream, &gr);
             if (rc != MD_OK) {
@@ -810,6 +1062,8 @@ int md_set_option(int key, double v) {
             if (!(v >= 1)) return fail(MD_ERR_ARG, "workspace cap must be >= 1 MiB");
             o.ws_mb = v;
             break;
+        case MD_OPT_PROFILE: o.profile = v != 0; break;
+        case MD_OPT_AUTOTUNE: o.autotune = v != 0; break;
         default: return fail(MD_ERR_ARG, "unknown option %d", key);
     }
     g_err.clear();
@@ -827,6 +1081,8 @@ double md_get_option(int key) {
         case MD_OPT_SYNC: return o.sync;
         case MD_OPT_GRAPH: return o.graph;
         case MD_OPT_WORKSPACE_MB: return o.ws_mb;
+        case MD_OPT_PROFILE: return o.profile;
+        case MD_OPT_AUTOTUNE: return o.autotune;
         default: return NAN;
     }
 }
@@ -838,6 +1094,50 @@ int md_get_stats(md_stats *s) {
 }
 
 const char *md_last_error(void) { return g_err.c_str(); }
+
+int md_profile_get(md_stage_time *out, int max, int *n) {
+    if (!n || (max > 0 && !out)) return fail(MD_ERR_ARG, "null pointer");
+    if (g.inited && !g.pending.empty()) {
+        MD_HIP(hipStreamSynchronize(g.stream));
+        resolve_profile();
+    }
+    int q = 0;
+    for (auto &kv : g.prof) {
+        if (q < max) {
+            md_stage_time &t = out[q];
+            memset(&t, 0, sizeof t);
+            snprintf(t.name, sizeof t.name, "%s", kv.first.c_str());
+            t.ms = kv.second.ms;
+            t.launches = kv.second.launches;
+            t.alg_bytes = kv.second.bytes;
+            t.alg_ops = kv.second.ops;
+        }
+        ++q;
+    }
+    *n = q;
+    return MD_OK;
+}
+
+int md_profile_reset(void) {
+    if (g.inited && !g.pending.empty()) {
+        MD_HIP(hipStreamSynchronize(g.stream));
+        resolve_profile();
+    }
+    g.prof.clear();
+    return MD_OK;
+}
+
+int md_cost_model(double *dst, int *measured) {
+    if (!dst || !measured) return fail(MD_ERR_ARG, "null pointer");
+    dst[0] = g.cost.dir_unit;
+    dst[1] = g.cost.dec_unit[0];
+    dst[2] = g.cost.dec_unit[1];
+    for (int q = 0; q < 4; ++q) dst[3 + q] = g.cost.fft_item[0][4 + q];
+    for (int q = 0; q < 3; ++q) dst[7 + q] = g.cost.fft_item[1][4 + q];
+    dst[10] = 0;
+    *measured = g.cost_measured ? 1 : 0;
+    return MD_OK;
+}
 
 int md_release(void) {
     if (!g.inited) return MD_OK;
