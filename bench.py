@@ -205,6 +205,7 @@ def main():
         log("bench: timing the CPU oracle")
         line["cpu_baseline"] = cpu_baseline(jobs, args.cpu_budget)
     print(json.dumps(line), flush=True)
+    md.release()
 
 
 if __name__ == "__main__":

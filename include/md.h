@@ -21,7 +21,8 @@
  *   - The SE is given as two k x k row-major HOST arrays: `se_mask` (uint8,
  *     non-zero = the cell belongs to the SE domain B) and `se_offsets`
  *     (int32 additive offsets b(y) >= 0, ignored where the mask is 0).  k is
- *     odd and the origin is the centre cell, so cell (i, j) is the offset
+ *     odd, 1 <= k <= 1023 (the direct window path covers k <= 127, the FFT
+ *     path every k), and the origin is the centre cell, so cell (i, j) is the offset
  *     y = (i - r, j - r), r = (k-1)/2.  A non-flat SE has offsets > 0, a flat
  *     one has all offsets 0 (Sec. 2.1).  The library copies what it needs;
  *     the host arrays may be freed when the call returns.
@@ -77,8 +78,8 @@ typedef enum {
                               0.25; 0 forces every tile through the recompute)   */
     MD_OPT_PATH = 2,       /* 0: auto (cost model), 1: FFT convolution of umbras,
                               2: direct max-plus window (classical, Eq. (6new)) */
-    MD_OPT_TILE = 3,       /* 0: auto, else the spatial FFT length per tile axis
-                              (16, 32, 64 or 128; 128 only in FP32)             */
+    MD_OPT_TILE = 3,       /* 0: auto, else the spatial FFT length per tile axis,
+                              a power of two in [16, 1024]                      */
     MD_OPT_NR = 4,         /* 0: auto, else the range-axis DFT length; must be at
                               least (L-1) + max offset + 1                       */
     MD_OPT_SYNC = 5,       /* 1 (default): wait for completion in every call    */
@@ -168,10 +169,11 @@ typedef struct {
 int md_profile_get(md_stage_time *out, int max, int *n);
 int md_profile_reset(void);
 
-/* Cost-model constants in use (ns): direct per pixel*k*kpad, decode per
- * pixel*nr*bins (FP32, FP64), FFT per (tile, bin) item for spatial lengths
- * 16..128 in FP32 then 16..64 in FP64 (11 values into `dst`).  Returns
- * MD_OK; *measured = 1 if they come from the autotuner. */
+/* Cost-model constants in use (ns per work unit): direct window per
+ * pixel*k*kpad, decode per pixel*nr*bins (FP32, FP64), then the FFT stage per
+ * (tile, bin) item for spatial lengths 16, 32, ..., 1024 in FP32 (7 values)
+ * and in FP64 (7 values): 17 values into the host array `dst`.  *measured = 1
+ * if they come from the autotuner. */
 int md_cost_model(double *dst, int *measured);
 
 /* Test hook: per-bin transform-domain values of one tile just before the

@@ -245,12 +245,13 @@ def profile_get() -> dict:
 def cost_model() -> dict:
     """Cost-model constants in use (ns per work unit) and whether the
     autotuner measured them."""
-    v = (ctypes.c_double * 11)()
+    v = (ctypes.c_double * 17)()
     measured = ctypes.c_int(0)
     _check(load().md_cost_model(v, ctypes.byref(measured)))
+    lens = [16 << q for q in range(7)]
     return {"direct_per_px_k_kpad": v[0], "decode32_per_px_nr_bins": v[1], "decode64_per_px_nr_bins": v[2],
-            "fft32_item": {16: v[3], 32: v[4], 64: v[5], 128: v[6]},
-            "fft64_item": {16: v[7], 32: v[8], 64: v[9]}, "measured": bool(measured.value)}
+            "fft32_item": {n: v[3 + q] for q, n in enumerate(lens)},
+            "fft64_item": {n: v[10 + q] for q, n in enumerate(lens)}, "measured": bool(measured.value)}
 
 
 def debug_tile_values(img, mask, off, L: int, n_t: int, n_r: int, precision: int, ty: int, tx: int):

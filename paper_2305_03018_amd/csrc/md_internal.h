@@ -9,8 +9,16 @@
 namespace md {
 
 // Length of the full-circle FP64 twiddle table; every spatial FFT length
-// divides it (spatial lengths are powers of two up to kTwN/8).
+// divides it (spatial lengths are powers of two up to kTwN).
 constexpr int kTwN = 1024;
+
+// Spatial FFT lengths: LDS-resident up to kMaxLdsN32 (FP32) / kMaxLdsN64
+// (FP64) points per side, through a per-block global slab beyond, up to kMaxN.
+constexpr int kMaxLdsN32 = 128;
+constexpr int kMaxLdsN64 = 64;
+constexpr int kMaxN = 1024;
+constexpr int kBigThreads = 256;
+constexpr int kMaxDirectK = 127;
 
 // "Minus infinity" of the direct max-plus path: an out-of-image pixel or a
 // masked-out SE cell.  Two of them still sum without overflow.
@@ -23,8 +31,10 @@ constexpr int kDirBW = 128;
 constexpr int kDirBH = 16;
 constexpr int kDirThreads = (kDirBW / kDirRX) * kDirBH;   // 256
 
-// Decode kernel geometry: one pixel per thread, kDecThreads pixels per block.
+// Decode kernel geometry: kDecThreads threads per block, each decoding
+// kDecPixPerThread pixels of a work item.
 constexpr int kDecThreads = 256;
+constexpr int kDecPixPerThread = 4;
 
 // FP32 twiddle stored as an unevaluated sum hi + lo of two floats, so that
 // hi + lo carries about 48 significant bits of exp(-2 pi i j / kTwN).
@@ -33,7 +43,7 @@ struct TwF {
 };
 
 enum : int { kPathFFT = 1, kPathDirect = 2 };
-enum : int { kFbNone = 0, kFbFFT64 = 1, kFbDirect = 2 };
+enum : int { kFbNone = 0, kFbFFT64 = 1 };
 
 // One job as the kernels see it.  Complex arrays are float2 in the FP32 form
 // and double2 in the FP64 form (the `dbl` flag of the job's plan).
@@ -51,13 +61,13 @@ struct JobDev {
     const void *dec;             // [bins][bins] w_m exp(+2 pi i d m / nr), d <= nr/2, w = 1 or 2
     long long flag0;             // first entry of this job in the tile-flag array
     // exact recompute of ambiguous tiles
-    int fb_mode;                 // kFbNone / kFbFFT64 / kFbDirect
+    int fb_mode;                 // kFbNone / kFbFFT64
     int nt64, T64;
     double scale64;
     const double2 *se_spec64;    // [bins][nt64][nt64]
     const double2 *enc64;        // [bins][L]
     const double2 *dec64;        // [bins][bins]
-    // direct max-plus path (also the recompute of kFbDirect)
+    // direct max-plus path
     const int32_t *sek;          // [k][kpad] offsets in correlation order, kNeg where masked
     const int32_t *sek16;        // same, as two equal 16-bit lanes per word, -16384 where masked
     const int32_t *sek_rows;     // [k][2] first and last active column of each row (first > last: none)
@@ -73,7 +83,7 @@ struct Seg {
     long long item0;             // first global item index of the segment
     int job;
     int tile0, ntiles;           // tile range (FFT / decode)
-    int pblocks;                 // decode: ceil(T*T / kDecThreads)
+    int pblocks;                 // decode: ceil(T*T / (kDecThreads * kDecPixPerThread))
     void *y;                     // transform-domain buffer [ntiles][bins][T*T]
 };
 
@@ -96,20 +106,19 @@ hipError_t launch_se_spectrum(const uint8_t *mask_d, const int32_t *off_d, int k
 hipError_t launch_zero(void *p, size_t bytes, hipStream_t s);
 hipError_t launch_fill_hash(int32_t *p, size_t n, int L, unsigned int seed, hipStream_t s);
 hipError_t launch_fft(int nt, int dbl, const JobDev *jobs, const Seg *segs, int nseg, long long nitems,
-                      int grid, const TwF *tw32, const double2 *tw64, StatsDev *st, hipStream_t s);
+                      int grid, const TwF *tw32, const double2 *tw64, void *slabs, StatsDev *st, hipStream_t s);
 hipError_t launch_decode(int big, int dbl, const JobDev *jobs, const Seg *segs, int nseg,
                          long long nitems, int grid, float band, unsigned int *tile_flags,
                          int2 *fb_list, StatsDev *st, hipStream_t s);
 hipError_t launch_direct(int pack, int sel, const JobDev *jobs, const Seg *segs, int nseg, long long nitems,
                          int grid, size_t lds_bytes, StatsDev *st, hipStream_t s);
 hipError_t launch_fallback(int nt64, const JobDev *jobs, const int2 *fb_list, const StatsDev *st,
-                           double2 *slots, size_t slot_elems, int grid, const double2 *tw64,
+                           double2 *slots, size_t slot_elems, int grid, const double2 *tw64, double2 *slabs,
                            hipStream_t s);
-hipError_t launch_fallback_direct(const JobDev *jobs, const int2 *fb_list, const StatsDev *st,
-                                  int grid, size_t lds_bytes, hipStream_t s);
 size_t direct_lds_bytes(int k, int kpad, int pack, int sel);
 constexpr size_t kLdsBytes = 160 * 1024;
 int direct_block_rows(int pack);
 int fft_block_threads(int nt, int dbl);
+size_t fft_lds_bytes(int nt, int dbl);
 
 }  // namespace md

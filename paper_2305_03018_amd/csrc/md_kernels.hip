@@ -164,17 +164,18 @@ template <int LG>
 __device__ __forceinline__ int brev(int i) { return (int)(__brev((unsigned)i) >> (32 - LG)); }
 
 // One fused decimation-in-time pass: radix-2 stages with half-sizes
-// H0, 2 H0, ..., 2^(Q-1) H0 on every line of the N x N LDS array.
-// AXIS 0 transforms along rows (contiguous), AXIS 1 along columns.
-template <typename R, int N, int Q, int H0, int AXIS, int BS, bool INV>
+// H0, 2 H0, ..., 2^(Q-1) H0 on each of LINES lines of length N in an LDS
+// array of row pitch N+1.  AXIS 0 transforms along rows (contiguous), AXIS 1
+// along columns (then LINES == N).
+template <typename R, int N, int Q, int H0, int AXIS, int BS, bool INV, int LINES = N>
 __device__ __forceinline__ void pass_dit(typename Cx<R>::T *lds, const typename TwSel<R>::T &tw) {
     using C = typename Cx<R>::T;
-    constexpr int P = N + 1, RAD = 1 << Q, UNITS = N * (N / RAD);
+    constexpr int P = N + 1, RAD = 1 << Q, UNITS = LINES * (N / RAD);
     constexpr int ES = AXIS == 0 ? 1 : P, LS = AXIS == 0 ? P : 1;
     for (int u = threadIdx.x; u < UNITS; u += BS) {
-        const int line = u & (N - 1);
-        int gi = u / N;
-        if constexpr (N >= 64) gi = __builtin_amdgcn_readfirstlane(gi);   // uniform per wavefront
+        const int line = u & (LINES - 1);
+        int gi = u / LINES;
+        if constexpr (LINES >= 64) gi = __builtin_amdgcn_readfirstlane(gi);   // uniform per wavefront
         const int o = gi % H0;
         const int base = (gi / H0) * (RAD * H0) + o;
         C *p = lds + line * LS + base * ES;
@@ -201,15 +202,15 @@ __device__ __forceinline__ void pass_dit(typename Cx<R>::T *lds, const typename 
 }
 
 // One fused decimation-in-frequency pass: half-sizes 2^(Q-1) HMIN, ..., HMIN.
-template <typename R, int N, int Q, int HMIN, int AXIS, int BS, bool INV>
+template <typename R, int N, int Q, int HMIN, int AXIS, int BS, bool INV, int LINES = N>
 __device__ __forceinline__ void pass_dif(typename Cx<R>::T *lds, const typename TwSel<R>::T &tw) {
     using C = typename Cx<R>::T;
-    constexpr int P = N + 1, RAD = 1 << Q, UNITS = N * (N / RAD);
+    constexpr int P = N + 1, RAD = 1 << Q, UNITS = LINES * (N / RAD);
     constexpr int ES = AXIS == 0 ? 1 : P, LS = AXIS == 0 ? P : 1;
     for (int u = threadIdx.x; u < UNITS; u += BS) {
-        const int line = u & (N - 1);
-        int gi = u / N;
-        if constexpr (N >= 64) gi = __builtin_amdgcn_readfirstlane(gi);
+        const int line = u & (LINES - 1);
+        int gi = u / LINES;
+        if constexpr (LINES >= 64) gi = __builtin_amdgcn_readfirstlane(gi);
         const int o = gi % HMIN;
         const int base = (gi / HMIN) * (RAD * HMIN) + o;
         C *p = lds + line * LS + base * ES;
@@ -234,23 +235,24 @@ __device__ __forceinline__ void pass_dif(typename Cx<R>::T *lds, const typename 
     }
 }
 
-template <typename R, int N, int AXIS, int BS, bool INV, int PASS = 0>
+template <typename R, int N, int AXIS, int BS, bool INV, int LINES = N, int PASS = 0>
 __device__ __forceinline__ void dit_axis(typename Cx<R>::T *lds, const typename TwSel<R>::T &tw) {
     constexpr int lg = ilog2c(N);
     if constexpr (PASS < npass(lg)) {
-        pass_dit<R, N, passq(lg, PASS), (1 << stages_before(lg, PASS)), AXIS, BS, INV>(lds, tw);
+        pass_dit<R, N, passq(lg, PASS), (1 << stages_before(lg, PASS)), AXIS, BS, INV, LINES>(lds, tw);
         __syncthreads();
-        dit_axis<R, N, AXIS, BS, INV, PASS + 1>(lds, tw);
+        dit_axis<R, N, AXIS, BS, INV, LINES, PASS + 1>(lds, tw);
     }
 }
 
-template <typename R, int N, int AXIS, int BS, bool INV, int PASS = 0>
+template <typename R, int N, int AXIS, int BS, bool INV, int LINES = N, int PASS = 0>
 __device__ __forceinline__ void dif_axis(typename Cx<R>::T *lds, const typename TwSel<R>::T &tw) {
     constexpr int lg = ilog2c(N);
     if constexpr (PASS < npass(lg)) {
-        pass_dif<R, N, passq(lg, PASS), (N >> (stages_before(lg, PASS) + passq(lg, PASS))), AXIS, BS, INV>(lds, tw);
+        pass_dif<R, N, passq(lg, PASS), (N >> (stages_before(lg, PASS) + passq(lg, PASS))), AXIS, BS, INV, LINES>(lds,
+                                                                                                            tw);
         __syncthreads();
-        dif_axis<R, N, AXIS, BS, INV, PASS + 1>(lds, tw);
+        dif_axis<R, N, AXIS, BS, INV, LINES, PASS + 1>(lds, tw);
     }
 }
 
@@ -305,6 +307,98 @@ __device__ __forceinline__ void fft_tile_bin(typename Cx<R>::T *lds, const int32
     __syncthreads();
 }
 
+// Lines of length N held in LDS at a time by the large-tile transform
+// (64 KiB of complex values, so two blocks fit a CU).
+template <typename R, int N>
+constexpr int big_lines() { return (sizeof(R) == 4 ? 8192 : 4096) / N; }
+
+// One (tile, bin) of Step 2 for spatial lengths whose N x N array does not
+// fit the LDS.  Same overlap-save geometry and bit-reversal bookkeeping as
+// fft_tile_bin; the array lives in this block's scratch slab in global
+// memory (mostly in L2 / Infinity Cache) and passes through the LDS in
+// batches of LB lines:
+//   1. encode LB image rows, forward DIT along x, write row i to slab row
+//      brev(i) (the column transform then reads bit-reversed input);
+//   2. LB slab columns: forward DIT along y, multiply by the SE spectrum,
+//      inverse DIF along y (slab row r' then holds output row brev(r'));
+//   3. LB slab rows: inverse DIF along x, write the valid outputs.
+template <typename R, int N, int BS>
+__device__ __forceinline__ void fft_big_tile_bin(typename Cx<R>::T *lds, typename Cx<R>::T *slab,
+                                                 const int32_t *__restrict__ img, int H, int W, int L, int op,
+                                                 int k, int oy0, int ox0, const typename Cx<R>::T *__restrict__ enc_m,
+                                                 const typename Cx<R>::T *__restrict__ spec_m,
+                                                 typename Cx<R>::T *__restrict__ ydst,
+                                                 const typename TwSel<R>::T &tw, unsigned int *range_err) {
+    using C = typename Cx<R>::T;
+    constexpr int LB = big_lines<R, N>();
+    constexpr int P = N + 1, LG = ilog2c(N), LLB = ilog2c(LB);
+    const int r = (k - 1) >> 1, T = N - k + 1;
+    const int iy0 = oy0 - r, ix0 = ox0 - r;
+    bool bad = false;
+    // 1. rows
+    for (int rb = 0; rb < N; rb += LB) {
+        for (int q = threadIdx.x; q < LB * N; q += BS) {
+            const int l = q >> LG, j = q & (N - 1);
+            const int gy = iy0 + rb + l, gx = ix0 + j;
+            C v = czero<C>();
+            if (gy >= 0 && gy < H && gx >= 0 && gx < W) {
+                int val = gld(img)[(size_t)gy * W + gx];
+                if ((unsigned)val >= (unsigned)L) {
+                    bad = true;
+                    val = val < 0 ? 0 : L - 1;
+                }
+                if (op) val = L - 1 - val;
+                v = ldg(enc_m, val);
+            }
+            lds[l * P + brev<LG>(j)] = v;
+        }
+        __syncthreads();
+        dit_axis<R, N, 0, BS, false, LB>(lds, tw);
+        for (int q = threadIdx.x; q < LB * N; q += BS) {
+            const int l = q >> LG, v = q & (N - 1);
+            stg(slab, (size_t)brev<LG>(rb + l) * N + v, lds[l * P + v]);
+        }
+        __syncthreads();
+    }
+    if (bad && range_err) atomicOr(range_err, 1u);
+    // 2. columns: multiply and back
+    for (int cb = 0; cb < N; cb += LB) {
+        for (int q = threadIdx.x; q < LB * N; q += BS) {
+            const int rr = q >> LLB, l = q & (LB - 1);
+            lds[l * P + rr] = ldg(slab, (size_t)rr * N + cb + l);
+        }
+        __syncthreads();
+        dit_axis<R, N, 0, BS, false, LB>(lds, tw);
+        for (int q = threadIdx.x; q < LB * N; q += BS) {
+            const int u = q >> LLB, l = q & (LB - 1);
+            C *e = lds + l * P + u;
+            *e = cmul(*e, ldg(spec_m, (size_t)u * N + cb + l));
+        }
+        __syncthreads();
+        dif_axis<R, N, 0, BS, true, LB>(lds, tw);
+        for (int q = threadIdx.x; q < LB * N; q += BS) {
+            const int rr = q >> LLB, l = q & (LB - 1);
+            stg(slab, (size_t)rr * N + cb + l, lds[l * P + rr]);
+        }
+        __syncthreads();
+    }
+    // 3. rows back; slab row rb+l is output row y = brev(rb+l)
+    for (int rb = 0; rb < N; rb += LB) {
+        for (int q = threadIdx.x; q < LB * N; q += BS) {
+            const int l = q >> LG, v = q & (N - 1);
+            lds[l * P + v] = ldg(slab, (size_t)(rb + l) * N + v);
+        }
+        __syncthreads();
+        dif_axis<R, N, 0, BS, true, LB>(lds, tw);
+        for (int q = threadIdx.x; q < LB * T; q += BS) {
+            const int l = q / T, xo = q - l * T;
+            const int y = brev<LG>(rb + l);
+            if (y >= k - 1) stg(ydst, (size_t)(y - (k - 1)) * T + xo, lds[l * P + brev<LG>(xo + k - 1)]);
+        }
+        __syncthreads();
+    }
+}
+
 __device__ __forceinline__ int find_seg(const Seg *__restrict__ segs, int nseg, long long it) {
     int lo = 0, hi = nseg - 1;
     while (lo < hi) {
@@ -342,6 +436,30 @@ __device__ __forceinline__ void band_update(R c, int d, int &top, R &res) {
     const R rc = rint(c);
     res = fmax(res, fabs(c - rc));
     if (rc != R(0)) top = max(top, d);
+}
+
+template <typename R, int N, int BS>
+__global__ __launch_bounds__(BS) void k_fft_big(const JobDev *__restrict__ jobs, const Seg *__restrict__ segs,
+                                                int nseg, long long nitems, const TwF *__restrict__ tw32,
+                                                const double2 *__restrict__ tw64, void *slabs, StatsDev *st) {
+    using C = typename Cx<R>::T;
+    __shared__ C lds[big_lines<R, N>() * (N + 1)];
+    typename TwSel<R>::T tw;
+    if constexpr (sizeof(R) == 4) tw.p = tw32; else tw.p = tw64;
+    C *slab = (C *)slabs + (size_t)blockIdx.x * N * N;
+    for (long long it = blockIdx.x; it < nitems; it += gridDim.x) {
+        const Seg S = segs[find_seg(segs, nseg, it)];
+        const JobDev &J = jobs[S.job];
+        const long long local = it - S.item0;
+        const int m = (int)(local / S.ntiles), tl = (int)(local % S.ntiles);
+        const int tile = S.tile0 + tl;
+        const int ty = tile / J.tiles_x, tx = tile - ty * J.tiles_x;
+        const size_t TT = (size_t)J.T * J.T;
+        C *ydst = (C *)S.y + ((size_t)tl * J.bins + m) * TT;
+        fft_big_tile_bin<R, N, BS>(lds, slab, J.img, J.H, J.W, J.L, J.op, J.k, ty * J.T, tx * J.T,
+                                   (const C *)J.enc + (size_t)m * J.L, (const C *)J.se_spec + (size_t)m * N * N, ydst,
+                                   tw, m == 0 ? &st->range_err : nullptr);
+    }
 }
 
 // One block of kDecDC degrees x kDecMC bins of the inverse real DFT.
@@ -431,40 +549,47 @@ __global__ __launch_bounds__(kDecThreads) void k_decode(const JobDev *__restrict
                                                         StatsDev *st) {
     using C = typename Cx<R>::T;
     __shared__ float s_red[kDecThreads / 64];
+    float run_max = 0.f;          // largest residual this thread has seen (stats)
     for (long long it = blockIdx.x; it < nitems; it += gridDim.x) {
         const Seg S = segs[find_seg(segs, nseg, it)];
         const JobDev &J = jobs[S.job];
-        const long long local = it - S.item0;
-        const int tl = (int)(local / S.pblocks), pb = (int)(local % S.pblocks);
+        const int local = (int)(it - S.item0);
+        const int tl = local / S.pblocks, pb = local - tl * S.pblocks;
         const int tile = S.tile0 + tl;
         const int T = J.T;
         const int ty = tile / J.tiles_x, tx = tile - ty * J.tiles_x;
-        const int p = pb * kDecThreads + threadIdx.x;
-        const int ly = p / T, lx = p - ly * T;
-        const int gy = ty * T + ly, gx = tx * T + lx;
-        const bool valid = p < T * T && gy < J.H && gx < J.W;
         const size_t TT = (size_t)T * T;
         const C *X = (const C *)S.y + (size_t)tl * J.bins * TT;
-        int top;
-        R res;
-        decode_pixel<R>(X, TT, p, valid, (const C *)J.dec, J.nr, J.bins, (R)J.scale, top, res);
-        if (valid) {
-            const int d = top < 0 ? 0 : top;
-            gst(J.out)[(size_t)gy * J.W + gx] = J.op ? (J.L - 1 - d) : d;
+        bool hit = false;
+        // kDecPixPerThread pixels per thread per item amortise the item setup
+#pragma unroll 1
+        for (int q = 0; q < kDecPixPerThread; ++q) {
+            const int p = (pb * kDecPixPerThread + q) * kDecThreads + threadIdx.x;
+            const int ly = p / T, lx = p - ly * T;
+            const int gy = ty * T + ly, gx = tx * T + lx;
+            const bool valid = p < (int)TT && gy < J.H && gx < J.W;
+            int top;
+            R res;
+            decode_pixel<R>(X, TT, p, valid, (const C *)J.dec, J.nr, J.bins, (R)J.scale, top, res);
+            if (valid) {
+                const int d = top < 0 ? 0 : top;
+                gst(J.out)[(size_t)gy * J.W + gx] = J.op ? (J.L - 1 - d) : d;
+            }
+            run_max = fmaxf(run_max, (float)res);
+            hit |= (float)res >= band;
         }
-        const float rm = block_max((float)res, s_red);
-        if (threadIdx.x == 0) {
-            atomicMax(&st->max_res_bits, __float_as_uint(rm));
-            if (rm >= band) {
-                if (J.fb_mode == kFbNone) {
-                    atomicAdd(&st->pad, 1u);
-                } else if (atomicCAS(&tile_flags[J.flag0 + tile], 0u, 1u) == 0u) {
-                    const unsigned idx = atomicAdd(&st->fb_count, 1u);
-                    fb_list[idx] = make_int2(S.job, tile);
-                }
+        // a wave whose pixels hit the band flags the tile (rare); no barrier
+        if (__any(hit) && (threadIdx.x & 63) == 0 && atomicCAS(&tile_flags[J.flag0 + tile], 0u, 1u) == 0u) {
+            if (J.fb_mode == kFbNone) {
+                atomicAdd(&st->pad, 1u);   // counted once per tile
+            } else {
+                const unsigned idx = atomicAdd(&st->fb_count, 1u);
+                fb_list[idx] = make_int2(S.job, tile);
             }
         }
     }
+    const float rm = block_max(run_max, s_red);
+    if (threadIdx.x == 0 && rm > 0.f) atomicMax(&st->max_res_bits, __float_as_uint(rm));
 }
 
 // Direct max-plus window (the classical form of Eq. (6new)).  The image
@@ -509,19 +634,26 @@ __device__ __forceinline__ int dir_pix(const JobDev &J, int gy, int gx, bool &ba
 }
 
 // 16 image words (this thread's 8 outputs plus the next 8 SE columns) and the
-// 8 SE offsets of one 8-cell step.
+// 8 SE offsets of one 8-cell step; x0..x3 hold the words of the next LDS word
+// row when a packed pair straddles two word rows (see direct_block).
 struct DirBuf {
-    int4 w0, w1, w2, w3, b0, b1;
+    int4 w0, w1, w2, w3, x0, x1, x2, x3, b0, b1;
 };
 
 // SEL: the SE offsets are staged in LDS (else read with scalar loads from
 // global memory, for SEs too large to share the LDS with the image block).
-template <bool SEL>
-__device__ __forceinline__ void dir_load(DirBuf &B, const int32_t *trow, const int32_t *brow, int jb) {
+template <bool SEL, bool ODD>
+__device__ __forceinline__ void dir_load(DirBuf &B, const int32_t *trow, int twd, const int32_t *brow, int jb) {
     B.w0 = *(const int4 *)(trow + jb);
     B.w1 = *(const int4 *)(trow + jb + 4);
     B.w2 = *(const int4 *)(trow + jb + 8);
     B.w3 = *(const int4 *)(trow + jb + 12);
+    if constexpr (ODD) {
+        B.x0 = *(const int4 *)(trow + twd + jb);
+        B.x1 = *(const int4 *)(trow + twd + jb + 4);
+        B.x2 = *(const int4 *)(trow + twd + jb + 8);
+        B.x3 = *(const int4 *)(trow + twd + jb + 12);
+    }
     if constexpr (SEL) {
         B.b0 = *(const int4 *)(brow + jb);
         B.b1 = *(const int4 *)(brow + jb + 4);
@@ -532,20 +664,33 @@ __device__ __forceinline__ void dir_load(DirBuf &B, const int32_t *trow, const i
     }
 }
 
-template <bool PACK>
+// high 16 bits of lo-word, low 16 bits of hi-word: the packed pair of image
+// rows (2p+1, 2p+2) from word rows p and p+1
+__device__ __forceinline__ int straddle(int lo, int hi) {
+    return (int)__builtin_amdgcn_alignbit((unsigned)hi, (unsigned)lo, 16u);
+}
+
+template <bool PACK, bool ODD, int NS = kDirRX>
 __device__ __forceinline__ void dir_step(typename DirT<PACK>::V (&acc)[kDirRX], const DirBuf &B) {
     using D = DirT<PACK>;
     using V = typename D::V;
-    const V in[2 * kDirRX] = {D::word(B.w0.x), D::word(B.w0.y), D::word(B.w0.z), D::word(B.w0.w),
-                              D::word(B.w1.x), D::word(B.w1.y), D::word(B.w1.z), D::word(B.w1.w),
-                              D::word(B.w2.x), D::word(B.w2.y), D::word(B.w2.z), D::word(B.w2.w),
-                              D::word(B.w3.x), D::word(B.w3.y), D::word(B.w3.z), D::word(B.w3.w)};
+    int w[2 * kDirRX] = {B.w0.x, B.w0.y, B.w0.z, B.w0.w, B.w1.x, B.w1.y, B.w1.z, B.w1.w,
+                         B.w2.x, B.w2.y, B.w2.z, B.w2.w, B.w3.x, B.w3.y, B.w3.z, B.w3.w};
+    if constexpr (ODD) {
+        const int x[2 * kDirRX] = {B.x0.x, B.x0.y, B.x0.z, B.x0.w, B.x1.x, B.x1.y, B.x1.z, B.x1.w,
+                                   B.x2.x, B.x2.y, B.x2.z, B.x2.w, B.x3.x, B.x3.y, B.x3.z, B.x3.w};
+#pragma unroll
+        for (int t = 0; t < 2 * kDirRX; ++t) w[t] = straddle(w[t], x[t]);
+    }
+    V in[2 * kDirRX];
+#pragma unroll
+    for (int t = 0; t < 2 * kDirRX; ++t) in[t] = D::word(w[t]);
     const V b[kDirRX] = {D::word(B.b0.x), D::word(B.b0.y), D::word(B.b0.z), D::word(B.b0.w),
                          D::word(B.b1.x), D::word(B.b1.y), D::word(B.b1.z), D::word(B.b1.w)};
     // all sums of one SE column first, then the maxima: a packed op that reads
     // the result of the instruction right before it costs a wait state
 #pragma unroll
-    for (int sj = 0; sj < kDirRX; ++sj) {
+    for (int sj = 0; sj < NS; ++sj) {
         V sum[kDirRX];
 #pragma unroll
         for (int t = 0; t < kDirRX; ++t) sum[t] = in[t + sj] + b[sj];
@@ -554,9 +699,77 @@ __device__ __forceinline__ void dir_step(typename DirT<PACK>::V (&acc)[kDirRX], 
     }
 }
 
-// LDS layout of one direct block: the image words (PR rows of TWD), then each
-// SE row's [first, last] active column, then (SEL) the SE offsets in
-// correlation order (k rows of kpad words, packed or not).
+// One SE row over this thread's outputs: 8-cell steps from the row's first to
+// its last active column.  Two register buffers in ping-pong: the LDS words
+// and offsets of the next step are in flight while the current step computes
+// (scheduling barriers keep the compiler from sinking the prefetch next to
+// its use).  The prefetch is unconditional; it may read up to 16 words past
+// the active span, which the padding of the LDS block and of the SE arrays
+// keeps in bounds (those values are never used).
+template <bool PACK, bool SEL, bool ODD>
+__device__ __forceinline__ void dir_row(typename DirT<PACK>::V (&acc)[kDirRX], const int32_t *trow, int twd,
+                                        const int32_t *brow, int jb0, int jhi) {
+    DirBuf A, B;
+    dir_load<SEL, ODD>(A, trow, twd, brow, jb0);
+    for (int jb = jb0;; jb += 2 * kDirRX) {
+        dir_load<SEL, ODD>(B, trow, twd, brow, jb + kDirRX);
+        __builtin_amdgcn_sched_barrier(0);
+        dir_step<PACK, ODD>(acc, A);
+        __builtin_amdgcn_sched_barrier(0);
+        if (jb + kDirRX > jhi) break;
+        dir_load<SEL, ODD>(A, trow, twd, brow, jb + 2 * kDirRX);
+        __builtin_amdgcn_sched_barrier(0);
+        dir_step<PACK, ODD>(acc, B);
+        __builtin_amdgcn_sched_barrier(0);
+        if (jb + 2 * kDirRX > jhi) break;
+    }
+}
+
+// Packed form, SE rows i (even) and i+1 together: both read word rows
+// (y+i)/2 and (y+i)/2+1 -- row i uses the first whole, row i+1 the straddling
+// halves -- so one set of LDS reads feeds 256 packed ops.  The column span is
+// the union of the two rows' spans (masked cells carry minus infinity).
+template <bool SEL, int NS>
+__device__ __forceinline__ void dir_pair_step(s16x2 (&acc)[kDirRX], const int32_t *trow, int twd, const int32_t *brow0,
+                                              const int32_t *brow1, int jb) {
+    DirBuf A, B;
+    dir_load<SEL, true>(A, trow, twd, brow0, jb);
+    if constexpr (SEL) {
+        B.b0 = *(const int4 *)(brow1 + jb);
+        B.b1 = *(const int4 *)(brow1 + jb + 4);
+    } else {
+        const auto c = cst(brow1 + jb);
+        B.b0 = make_int4(c[0], c[1], c[2], c[3]);
+        B.b1 = make_int4(c[4], c[5], c[6], c[7]);
+    }
+    B.w0 = A.w0; B.w1 = A.w1; B.w2 = A.w2; B.w3 = A.w3;
+    B.x0 = A.x0; B.x1 = A.x1; B.x2 = A.x2; B.x3 = A.x3;
+    dir_step<true, false, NS>(acc, A);
+    dir_step<true, true, NS>(acc, B);
+}
+
+// Packed form, SE rows i (even) and i+1 together: both read word rows
+// (y+i)/2 and (y+i)/2+1 -- row i uses the first whole, row i+1 the straddling
+// halves -- so one set of LDS reads feeds 256 packed ops.  The column span is
+// the union of the two rows' spans (masked cells carry minus infinity); it is
+// covered by 8-column steps and, for a remainder of at most 4, a 4-column step.
+template <bool SEL>
+__device__ __forceinline__ void dir_pair(s16x2 (&acc)[kDirRX], const int32_t *trow, int twd, const int32_t *brow0,
+                                         const int32_t *brow1, int jb0, int jhi) {
+    int jb = jb0;
+    for (; jb + kDirRX - 1 <= jhi; jb += kDirRX) dir_pair_step<SEL, kDirRX>(acc, trow, twd, brow0, brow1, jb);
+    if (jb <= jhi) {
+        if (jhi - jb < kDirRX / 2) dir_pair_step<SEL, kDirRX / 2>(acc, trow, twd, brow0, brow1, jb);
+        else dir_pair_step<SEL, kDirRX>(acc, trow, twd, brow0, brow1, jb);
+    }
+}
+
+// LDS layout of one direct block: the image words, then each SE row's
+// [first, last] active column, then (SEL) the SE offsets in correlation order
+// (k rows of kpad words, packed or not).  Packed form: word row p holds image
+// rows 2p (low half) and 2p+1 (high half); a thread owns output rows (y, y+1)
+// with y even, so SE row i needs image rows (y+i, y+i+1): a whole word for
+// even i, halves of two word rows for odd i.
 template <bool PACK, bool SEL>
 __device__ __forceinline__ void direct_block(const JobDev &J, int by0, int bx0, int ye, int xe, int32_t *tile,
                                              unsigned int *range_err) {
@@ -566,7 +779,7 @@ __device__ __forceinline__ void direct_block(const JobDev &J, int by0, int bx0, 
     const int k = J.k, r = (k - 1) >> 1, kpad = J.kpad;
     const int TWD = kDirBW + kpad;
     const int TH = BH + k - 1;                       // image rows the block reads
-    const int PR = PACK ? TH - 1 : TH;               // LDS word rows
+    const int PR = PACK ? (TH + 1) >> 1 : TH;        // LDS word rows
     int32_t *rowL = tile + PR * TWD;
     int32_t *seL = rowL + ((2 * k + 3) & ~3);        // 16-byte aligned for the b128 reads
     const int32_t *sek = PACK ? J.sek16 : J.sek;
@@ -591,13 +804,8 @@ __device__ __forceinline__ void direct_block(const JobDev &J, int by0, int bx0, 
         for (int u = 0; u < 4; ++u) {
             const int c = lane + 64 * u;
             if (c >= TWD) break;
-            if (PACK) {
-                short *h = (short *)tile;
-                if (a < PR) h[2 * (a * TWD + c)] = (short)v[u];            // low half of word row a
-                if (a > 0) h[2 * ((a - 1) * TWD + c) + 1] = (short)v[u];   // high half of word row a-1
-            } else {
-                tile[a * TWD + c] = v[u];
-            }
+            if (PACK) ((short *)tile)[2 * ((a >> 1) * TWD + c) + (a & 1)] = (short)v[u];
+            else tile[a * TWD + c] = v[u];
         }
     }
     if (bad && range_err) atomicOr(range_err, 1u);
@@ -607,32 +815,30 @@ __device__ __forceinline__ void direct_block(const JobDev &J, int by0, int bx0, 
     V acc[kDirRX];
 #pragma unroll
     for (int t = 0; t < kDirRX; ++t) acc[t] = D::word(PACK ? (int)(((unsigned)kNeg16 & 0xffffu) * 0x10001u) : kNeg);
-    for (int i = 0; i < k; ++i) {
-        const int jlo = rowL[2 * i], jhi = rowL[2 * i + 1];   // active cells of SE row i (LDS broadcast)
-        if (jlo > jhi) continue;
-        const int jb0 = jlo & ~(kDirRX - 1);
-        const int32_t *trow = tile + (trow0 + i) * TWD + lx0;
-        const int32_t *brow = (SEL ? seL : sek) + i * kpad;
-        // two register buffers in ping-pong: the LDS words and offsets of the
-        // next 8-cell step are in flight while the current step computes.  The
-        // prefetch is unconditional; it may read up to 16 words past the
-        // active span, which the padding of the LDS block and of the SE
-        // arrays keeps in bounds (those values are never used).
-        // (scheduling barriers keep the compiler from sinking the prefetch
-        // next to its use)
-        DirBuf A, B;
-        dir_load<SEL>(A, trow, brow, jb0);
-        for (int jb = jb0;; jb += 2 * kDirRX) {
-            dir_load<SEL>(B, trow, brow, jb + kDirRX);
-            __builtin_amdgcn_sched_barrier(0);
-            dir_step<PACK>(acc, A);
-            __builtin_amdgcn_sched_barrier(0);
-            if (jb + kDirRX > jhi) break;
-            dir_load<SEL>(A, trow, brow, jb + 2 * kDirRX);
-            __builtin_amdgcn_sched_barrier(0);
-            dir_step<PACK>(acc, B);
-            __builtin_amdgcn_sched_barrier(0);
-            if (jb + 2 * kDirRX > jhi) break;
+    const int32_t *sebase = SEL ? seL : sek;
+    if constexpr (PACK) {
+        for (int i = 0; i < k; i += 2) {
+            int jlo = rowL[2 * i], jhi = rowL[2 * i + 1];     // active cells of SE row i (LDS broadcast)
+            const int32_t *trow = tile + ((trow0 + i) >> 1) * TWD + lx0;   // word row of image row y+i
+            if (i + 1 < k) {
+                const int lo1 = rowL[2 * i + 2], hi1 = rowL[2 * i + 3];
+                if (lo1 <= hi1) {
+                    jlo = min(jlo, lo1);
+                    jhi = max(jhi, hi1);
+                }
+                if (jlo > jhi) continue;
+                dir_pair<SEL>(acc, trow, TWD, sebase + i * kpad, sebase + (i + 1) * kpad, jlo & ~(kDirRX - 1), jhi);
+            } else {
+                if (jlo > jhi) continue;
+                dir_row<true, SEL, false>(acc, trow, TWD, sebase + i * kpad, jlo & ~(kDirRX - 1), jhi);
+            }
+        }
+    } else {
+        for (int i = 0; i < k; ++i) {
+            const int jlo = rowL[2 * i], jhi = rowL[2 * i + 1];
+            if (jlo > jhi) continue;
+            dir_row<false, SEL, false>(acc, tile + (trow0 + i) * TWD + lx0, TWD, sebase + i * kpad,
+                                       jlo & ~(kDirRX - 1), jhi);
         }
     }
     const int L = J.L, W = J.W;
@@ -669,17 +875,21 @@ __global__ __launch_bounds__(kDirThreads) void k_direct(const JobDev *__restrict
 }
 
 // Exact recompute of the tiles listed by the decode: FP64 transforms on
-// nt64-sized sub-tiles, each decoded from this block's slot.
+// nt64-sized sub-tiles (LDS-resident up to 64, through this block's slab
+// beyond), each decoded from this block's slot.
 template <int N>
 __global__ __launch_bounds__(kDecThreads) void k_fallback(const JobDev *__restrict__ jobs,
-                                                  const int2 *__restrict__ fb_list,
-                                                  const StatsDev *__restrict__ st, double2 *slots,
-                                                  size_t slot_elems, const double2 *__restrict__ tw64) {
-    __shared__ double2 lds[N * (N + 1)];
+                                                          const int2 *__restrict__ fb_list,
+                                                          const StatsDev *__restrict__ st, double2 *slots,
+                                                          size_t slot_elems, const double2 *__restrict__ tw64,
+                                                          double2 *slabs) {
+    constexpr bool BIG = N > kMaxLdsN64;
+    __shared__ double2 lds[BIG ? big_lines<double, N>() * (N + 1) : N * (N + 1)];
     Tw64 tw;
     tw.p = tw64;
     const unsigned cnt = __builtin_amdgcn_readfirstlane(*(volatile const unsigned *)&st->fb_count);
     double2 *slot = slots + (size_t)blockIdx.x * slot_elems;
+    double2 *slab = BIG ? slabs + (size_t)blockIdx.x * N * N : nullptr;
     for (unsigned i = blockIdx.x; i < cnt; i += gridDim.x) {
         const int2 e = fb_list[i];
         const JobDev &J = jobs[e.x];
@@ -692,10 +902,17 @@ __global__ __launch_bounds__(kDecThreads) void k_fallback(const JobDev *__restri
         const size_t TT = (size_t)T64 * T64;
         for (int sy = 0; sy < oh; sy += T64) {
             for (int sx = 0; sx < ow; sx += T64) {
-                for (int m = 0; m < J.bins; ++m)
-                    fft_tile_bin<double, N, 256>(lds, J.img, J.H, J.W, J.L, J.op, J.k, oy0 + sy, ox0 + sx,
-                                                 J.enc64 + (size_t)m * J.L, J.se_spec64 + (size_t)m * N * N,
-                                                 slot + m * TT, tw, nullptr);
+                for (int m = 0; m < J.bins; ++m) {
+                    if constexpr (BIG)
+                        fft_big_tile_bin<double, N, kDecThreads>(lds, slab, J.img, J.H, J.W, J.L, J.op, J.k, oy0 + sy,
+                                                                 ox0 + sx, J.enc64 + (size_t)m * J.L,
+                                                                 J.se_spec64 + (size_t)m * N * N, slot + m * TT, tw,
+                                                                 nullptr);
+                    else
+                        fft_tile_bin<double, N, kDecThreads>(lds, J.img, J.H, J.W, J.L, J.op, J.k, oy0 + sy, ox0 + sx,
+                                                             J.enc64 + (size_t)m * J.L, J.se_spec64 + (size_t)m * N * N,
+                                                             slot + m * TT, tw, nullptr);
+                }
                 const int sh = min(T64, oh - sy), sw = min(T64, ow - sx);
                 for (int p0 = 0; p0 < (int)TT; p0 += kDecThreads) {
                     const int p = p0 + threadIdx.x;
@@ -711,33 +928,6 @@ __global__ __launch_bounds__(kDecThreads) void k_fallback(const JobDev *__restri
                 }
                 __syncthreads();   // the slot is rewritten by the next sub-tile
             }
-        }
-    }
-}
-
-// Exact recompute by the direct window, for plans whose FP64 tiles would be
-// too small to be worth transforming.
-__global__ __launch_bounds__(kDirThreads) void k_fallback_direct(const JobDev *__restrict__ jobs,
-                                                                 const int2 *__restrict__ fb_list,
-                                                                 const StatsDev *__restrict__ st) {
-    extern __shared__ int32_t dyn_lds[];
-    const unsigned cnt = __builtin_amdgcn_readfirstlane(*(volatile const unsigned *)&st->fb_count);
-    for (unsigned i = blockIdx.x; i < cnt; i += gridDim.x) {
-        const int2 e = fb_list[i];
-        const JobDev &J = jobs[e.x];
-        if (J.fb_mode != kFbDirect) continue;
-        const int tile = e.y;
-        const int ty = tile / J.tiles_x, tx = tile - ty * J.tiles_x;
-        const int oy0 = ty * J.T, ox0 = tx * J.T;
-        const int ye = min(oy0 + J.T, J.H), xe = min(ox0 + J.T, J.W);
-        if (J.dir_pack) {
-            for (int by0 = oy0; by0 < ye; by0 += DirT<true>::BH)
-                for (int bx0 = ox0; bx0 < xe; bx0 += kDirBW)
-                    direct_block<true, false>(J, by0, bx0, ye, xe, dyn_lds, nullptr);
-        } else {
-            for (int by0 = oy0; by0 < ye; by0 += DirT<false>::BH)
-                for (int bx0 = ox0; bx0 < xe; bx0 += kDirBW)
-                    direct_block<false, false>(J, by0, bx0, ye, xe, dyn_lds, nullptr);
         }
     }
 }
@@ -854,13 +1044,20 @@ __global__ void k_zero(uint32_t *p, size_t n) {
 // launchers
 // ---------------------------------------------------------------------------
 int fft_block_threads(int nt, int dbl) {
+    if (nt > (dbl ? kMaxLdsN64 : kMaxLdsN32)) return nt <= kMaxN ? kBigThreads : 0;
     switch (nt) {
         case 16: return 64;
         case 32: return 128;
         case 64: return 256;
-        case 128: return dbl ? 0 : 1024;
+        case 128: return 1024;
         default: return 0;
     }
+}
+
+size_t fft_lds_bytes(int nt, int dbl) {
+    const size_t esz = dbl ? sizeof(double2) : sizeof(float2);
+    if (nt > (dbl ? kMaxLdsN64 : kMaxLdsN32)) return (size_t)((dbl ? 4096 : 8192) / nt) * (nt + 1) * esz;
+    return (size_t)nt * (nt + 1) * esz;
 }
 
 hipError_t launch_twiddles(double2 *tw64, TwF *tw32, hipStream_t s) {
@@ -904,16 +1101,21 @@ hipError_t launch_zero(void *p, size_t bytes, hipStream_t s) {
 }
 
 hipError_t launch_fft(int nt, int dbl, const JobDev *jobs, const Seg *segs, int nseg, long long nitems,
-                      int grid, const TwF *tw32, const double2 *tw64, StatsDev *st, hipStream_t s) {
+                      int grid, const TwF *tw32, const double2 *tw64, void *slabs, StatsDev *st, hipStream_t s) {
     if (nitems <= 0) return hipSuccess;
 #define MD_FFT_CASE(R, N, BS) \
     k_fft<R, N, BS><<<grid, BS, 0, s>>>(jobs, segs, nseg, nitems, tw32, tw64, st); break;
+#define MD_FFT_BIG(R, N) \
+    k_fft_big<R, N, kBigThreads><<<grid, kBigThreads, 0, s>>>(jobs, segs, nseg, nitems, tw32, tw64, slabs, st); break;
     if (!dbl) {
         switch (nt) {
             case 16: MD_FFT_CASE(float, 16, 64)
             case 32: MD_FFT_CASE(float, 32, 128)
             case 64: MD_FFT_CASE(float, 64, 256)
             case 128: MD_FFT_CASE(float, 128, 1024)
+            case 256: MD_FFT_BIG(float, 256)
+            case 512: MD_FFT_BIG(float, 512)
+            case 1024: MD_FFT_BIG(float, 1024)
             default: return hipErrorInvalidValue;
         }
     } else {
@@ -921,10 +1123,15 @@ hipError_t launch_fft(int nt, int dbl, const JobDev *jobs, const Seg *segs, int 
             case 16: MD_FFT_CASE(double, 16, 64)
             case 32: MD_FFT_CASE(double, 32, 128)
             case 64: MD_FFT_CASE(double, 64, 256)
+            case 128: MD_FFT_BIG(double, 128)
+            case 256: MD_FFT_BIG(double, 256)
+            case 512: MD_FFT_BIG(double, 512)
+            case 1024: MD_FFT_BIG(double, 1024)
             default: return hipErrorInvalidValue;
         }
     }
 #undef MD_FFT_CASE
+#undef MD_FFT_BIG
     return hipGetLastError();
 }
 
@@ -941,7 +1148,7 @@ hipError_t launch_decode(int big, int dbl, const JobDev *jobs, const Seg *segs, 
 int direct_block_rows(int pack) { return pack ? DirT<true>::BH : DirT<false>::BH; }
 
 size_t direct_lds_bytes(int k, int kpad, int pack, int sel) {
-    const int rows = pack ? DirT<true>::BH + k - 2 : DirT<false>::BH + k - 1;
+    const int rows = pack ? (DirT<true>::BH + k) / 2 : DirT<false>::BH + k - 1;
     return ((size_t)rows * (kDirBW + kpad) + (sel ? (size_t)k * kpad : 0) + (size_t)((2 * k + 3) & ~3) + 16) *
            sizeof(int32_t);
 }
@@ -957,20 +1164,22 @@ hipError_t launch_direct(int pack, int sel, const JobDev *jobs, const Seg *segs,
 }
 
 hipError_t launch_fallback(int nt64, const JobDev *jobs, const int2 *fb_list, const StatsDev *st,
-                           double2 *slots, size_t slot_elems, int grid, const double2 *tw64, hipStream_t s) {
+                           double2 *slots, size_t slot_elems, int grid, const double2 *tw64, double2 *slabs,
+                           hipStream_t s) {
+#define MD_FB(N) k_fallback<N><<<grid, kDecThreads, 0, s>>>(jobs, fb_list, st, slots, slot_elems, tw64, slabs); break;
     switch (nt64) {
-        case 16: k_fallback<16><<<grid, kDecThreads, 0, s>>>(jobs, fb_list, st, slots, slot_elems, tw64); break;
-        case 32: k_fallback<32><<<grid, kDecThreads, 0, s>>>(jobs, fb_list, st, slots, slot_elems, tw64); break;
-        case 64: k_fallback<64><<<grid, kDecThreads, 0, s>>>(jobs, fb_list, st, slots, slot_elems, tw64); break;
+        case 16: MD_FB(16)
+        case 32: MD_FB(32)
+        case 64: MD_FB(64)
+        case 128: MD_FB(128)
+        case 256: MD_FB(256)
+        case 512: MD_FB(512)
+        case 1024: MD_FB(1024)
         default: return hipErrorInvalidValue;
     }
+#undef MD_FB
     return hipGetLastError();
 }
 
-hipError_t launch_fallback_direct(const JobDev *jobs, const int2 *fb_list, const StatsDev *st, int grid,
-                                  size_t lds_bytes, hipStream_t s) {
-    k_fallback_direct<<<grid, kDirThreads, lds_bytes, s>>>(jobs, fb_list, st);
-    return hipGetLastError();
-}
 
 }  // namespace md

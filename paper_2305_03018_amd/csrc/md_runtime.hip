@@ -108,6 +108,9 @@ struct Plan {
 
 struct Group {
     int nt = 0, dbl = 0, big = 0;
+    int pack = 0, sel = 0;        // direct groups: element form, SE staged in LDS
+    size_t lds = 0;               // dynamic LDS per block (direct groups)
+    void *slabs = nullptr;        // large-tile FFT groups: grid x nt x nt complex
     std::vector<Seg> segs;
     long long nitems = 0;
     Seg *segs_d = nullptr;
@@ -129,15 +132,17 @@ struct Exec {
     JobDev *jobs_pin = nullptr;
     hipEvent_t copy_done = nullptr;
     bool copy_pending = false;
-    Group direct[4];              // index pack + 2*sel: int32 / packed 16-bit form, SE in LDS or not
-    size_t direct_lds[4] = {0, 0, 0, 0};
+    // direct-window launches, one per (element form, SE in LDS, blocks per CU
+    // allowed by the LDS footprint): small windows are not held to the
+    // occupancy of the largest one
+    std::vector<Group> direct;
     std::vector<Wave> waves;
     DevBuf segbuf, ybuf, flags, list, slots;
     long long nflags = 0;
     std::vector<int> fb_classes;
-    bool fb_direct = false;
-    size_t fb_direct_lds = 0;
     size_t slot_elems = 0;
+    std::vector<std::unique_ptr<DevBuf>> slabbufs;   // per-block slabs of large-tile groups
+    DevBuf fb_slabs;
     int fb_grid = 0;
     long long fft_tiles = 0;
     int n_direct = 0, n_fft = 0;
@@ -155,13 +160,17 @@ struct Exec {
         flags.release();
         list.release();
         slots.release();
+        fb_slabs.release();
+        for (auto &b : slabbufs) b->release();
     }
 };
 
 // Cost model (nanoseconds of whole-GPU time).  The constants are replaced by
 // measured rates when the autotuner has run on this device.
 struct CostModel {
-    double fft_item[2][8] = {{0, 0, 0, 0, 2.0, 8.0, 30.0, 130.0}, {0, 0, 0, 0, 5.0, 20.0, 75.0, 0.0}};
+    // per (tile, bin) item, index log2(nt): FP32 / FP64
+    double fft_item[2][11] = {{0, 0, 0, 0, 2.0, 8.0, 30.0, 130.0, 700.0, 3200.0, 14000.0},
+                              {0, 0, 0, 0, 5.0, 20.0, 75.0, 900.0, 3800.0, 16000.0, 70000.0}};
     double dec_unit[2] = {1.5e-4, 3.0e-4};   // per pixel * nr * bins
     double dir_unit = 1.0e-4;                // per pixel * k * kpad
     double launch = 3000.0;                  // fixed cost per job class
@@ -201,7 +210,10 @@ struct Ctx {
     bool tuned = false, tuning = false, cost_measured = false;
 };
 
-Ctx g;
+// The context lives until the process ends and is never destroyed: its
+// destructor would free device memory and graphs after the HIP runtime has
+// been torn down at exit.  md_release frees everything explicitly.
+Ctx &g = *new Ctx;
 
 int ilog2i(int n) {
     int l = 0;
@@ -228,6 +240,13 @@ int init() {
     MD_HIP(hipDeviceSynchronize());
     g.device = dev;
     g.inited = true;
+    // registered after the HIP runtime is up, so it runs before the runtime's
+    // own exit handlers: graphs and buffers are released while HIP still works
+    static bool exit_hook = false;
+    if (!exit_hook) {
+        exit_hook = true;
+        atexit([] { md_release(); });
+    }
     return MD_OK;
 }
 
@@ -377,7 +396,7 @@ int check_job(const md_job &j) {
     if (j.H < 1 || j.W < 1) return fail(MD_ERR_ARG, "image shape %dx%d", j.H, j.W);
     if ((long long)j.H * j.W > 0x7fffffffLL) return fail(MD_ERR_ARG, "image has more than 2^31-1 pixels");
     if (j.L < 2 || j.L > (1 << 24)) return fail(MD_ERR_ARG, "L=%d outside [2, 2^24]", j.L);
-    if (j.k < 1 || j.k > 127 || (j.k % 2) == 0) return fail(MD_ERR_ARG, "k=%d must be odd in [1,127]", j.k);
+    if (j.k < 1 || j.k > kMaxN - 1 || (j.k % 2) == 0) return fail(MD_ERR_ARG, "k=%d must be odd in [1,%d]", j.k, kMaxN - 1);
     if (j.op != 0 && j.op != 1) return fail(MD_ERR_ARG, "op=%d must be 0 (dilation) or 1 (erosion)", j.op);
     for (int q = 0; q < j.k * j.k; ++q)
         if (j.se_mask[q] && (j.se_offsets[q] < 0 || j.se_offsets[q] > (1 << 24)))
@@ -410,16 +429,13 @@ int plan_job(const md_job &j, const SEData &se, Plan &p) {
     p.bins = nr / 2 + 1;
     const int kpad = (j.k + kDirRX - 1) / kDirRX * kDirRX;
     const bool pack16 = (long long)(j.L - 1) + se.maxoff <= 16383;
-    p.cost_dir = (double)j.H * j.W * j.k * kpad * g.cost.dir_unit * (pack16 ? 1.0 : 2.0);
+    const bool dir_ok = j.k <= kMaxDirectK;
+    p.cost_dir = dir_ok ? (double)j.H * j.W * j.k * kpad * g.cost.dir_unit * (pack16 ? 1.0 : 2.0) : INFINITY;
     // transform plan: best spatial length by the cost model
     double best = INFINITY;
     int best_nt = 0;
-    const int cands32[4] = {16, 32, 64, 128}, cands64[3] = {16, 32, 64};
-    const int *cands = dbl ? cands64 : cands32;
-    const int ncand = dbl ? 3 : 4;
     const bool fft_ok = nr_min <= 4096 && se.ncells > 0;
-    for (int c = 0; fft_ok && c < ncand; ++c) {
-        const int nt = cands[c];
+    for (int nt = 16; fft_ok && nt <= kMaxN; nt *= 2) {
         if (g.opt.tile > 0 && nt != g.opt.tile) continue;
         const double cst = fft_cost(j, nt, nr, dbl);
         if (cst < best) {
@@ -430,11 +446,13 @@ int plan_job(const md_job &j, const SEData &se, Plan &p) {
     p.cost_fft = best;
     if (g.opt.path == kPathFFT) {
         if (!fft_ok) return fail(MD_ERR_UNSUPPORTED, "FFT path needs 1 <= SE cells and (L-1)+max offset+1 <= 4096");
-        if (!best_nt) return fail(MD_ERR_UNSUPPORTED, "no FFT tile length fits k=%d (precision %d, tile %d)", j.k, dbl, g.opt.tile);
+        if (!best_nt) return fail(MD_ERR_UNSUPPORTED, "no FFT tile length fits k=%d (tile %d)", j.k, g.opt.tile);
         p.path = kPathFFT;
     } else if (g.opt.path == kPathDirect) {
+        if (!dir_ok) return fail(MD_ERR_UNSUPPORTED, "the direct window supports k <= %d (k=%d)", kMaxDirectK, j.k);
         p.path = kPathDirect;
     } else {
+        if (!best_nt && !dir_ok) return fail(MD_ERR_UNSUPPORTED, "no path covers k=%d with an empty SE", j.k);
         p.path = (best_nt && best < p.cost_dir) ? kPathFFT : kPathDirect;
     }
     if (p.path == kPathDirect) return MD_OK;
@@ -443,22 +461,16 @@ int plan_job(const md_job &j, const SEData &se, Plan &p) {
     p.tiles_x = (j.W + p.T - 1) / p.T;
     p.tiles_y = (j.H + p.T - 1) / p.T;
     if (!dbl) {
-        // exact recompute of ambiguous tiles: FP64 transforms on the smallest
-        // LDS-resident length whose tile covers the FP32 tile, else on 64 when
-        // it still yields >= 16 outputs per side, else the direct window.
-        p.fb_mode = kFbDirect;
-        for (int nt64 : {16, 32, 64}) {
+        // exact recompute of ambiguous tiles in FP64: the smallest length
+        // whose tile covers the FP32 tile, else the largest
+        p.fb_mode = kFbFFT64;
+        p.nt64 = kMaxN;
+        for (int nt64 = 16; nt64 <= kMaxN; nt64 *= 2)
             if (nt64 - j.k + 1 >= p.T) {
-                p.fb_mode = kFbFFT64;
                 p.nt64 = nt64;
                 break;
             }
-        }
-        if (p.fb_mode == kFbDirect && 64 - j.k + 1 >= 16) {
-            p.fb_mode = kFbFFT64;
-            p.nt64 = 64;
-        }
-        if (p.fb_mode == kFbFFT64) p.T64 = p.nt64 - j.k + 1;
+        p.T64 = p.nt64 - j.k + 1;
     }
     return MD_OK;
 }
@@ -504,8 +516,8 @@ std::string signature(const md_job *jobs, int n, const std::vector<SEData> &ses)
 int build_exec(const md_job *jobs, int n, const std::vector<SEData> &ses, Exec &ex) {
     ex.jobs_h.resize(n);
     ex.plans.resize(n);
-    size_t max_dir_lds[4] = {0, 0, 0, 0}, max_fbdir_lds = 0;
-    std::vector<int> dir_cls(n, 0);
+    std::vector<size_t> dir_lds(n, 0);
+    std::vector<int> dir_sel(n, 0);
     long long flag_total = 0;
     const size_t cap_bytes = (size_t)std::max(1.0, g.opt.ws_mb) * 1024 * 1024;
     // per-job plans and device descriptors
@@ -523,7 +535,7 @@ int build_exec(const md_job *jobs, int n, const std::vector<SEData> &ses, Exec &
         d.k = j.k;
         d.op = j.op;
         d.path = p.path;
-        if (p.path == kPathDirect || p.fb_mode == kFbDirect) {
+        if (p.path == kPathDirect) {
             DirSE *ds = nullptr;
             MD_TRY(get_dirse(ses[i], &ds));
             d.sek = (const int32_t *)ds->sek.p;
@@ -534,11 +546,9 @@ int build_exec(const md_job *jobs, int n, const std::vector<SEData> &ses, Exec &
             d.dir_bx = (j.W + kDirBW - 1) / kDirBW;
             d.dir_by = (j.H + direct_block_rows(d.dir_pack) - 1) / direct_block_rows(d.dir_pack);
             const int sel = direct_lds_bytes(j.k, ds->kpad, d.dir_pack, 1) <= kLdsBytes ? 1 : 0;
-            dir_cls[i] = d.dir_pack + 2 * sel;
-            const size_t lds = direct_lds_bytes(j.k, ds->kpad, d.dir_pack, sel);
-            if (lds > kLdsBytes) return fail(MD_ERR_UNSUPPORTED, "direct window for k=%d exceeds the LDS", j.k);
-            if (p.path == kPathDirect) max_dir_lds[dir_cls[i]] = std::max(max_dir_lds[dir_cls[i]], lds);
-            else max_fbdir_lds = std::max(max_fbdir_lds, direct_lds_bytes(j.k, ds->kpad, d.dir_pack, 0));
+            dir_sel[i] = sel;
+            dir_lds[i] = direct_lds_bytes(j.k, ds->kpad, d.dir_pack, sel);
+            if (dir_lds[i] > kLdsBytes) return fail(MD_ERR_UNSUPPORTED, "direct window for k=%d exceeds the LDS", j.k);
         }
         if (p.path == kPathDirect) {
             ++ex.n_direct;
@@ -576,14 +586,25 @@ int build_exec(const md_job *jobs, int n, const std::vector<SEData> &ses, Exec &
             ex.slot_elems = std::max(ex.slot_elems, (size_t)p.bins * p.T64 * p.T64);
             if (std::find(ex.fb_classes.begin(), ex.fb_classes.end(), p.nt64) == ex.fb_classes.end())
                 ex.fb_classes.push_back(p.nt64);
-        } else if (p.fb_mode == kFbDirect) {
-            ex.fb_direct = true;
         }
     }
-    // direct groups (int32 / packed): one segment per direct job
+    // direct groups: one segment per direct job
     for (int i = 0; i < n; ++i) {
         if (ex.plans[i].path != kPathDirect) continue;
-        Group &gr = ex.direct[dir_cls[i]];
+        const int pack = ex.jobs_h[i].dir_pack, sel = dir_sel[i];
+        const int per_cu = std::max(1, std::min(2048 / kDirThreads, (int)(kLdsBytes / dir_lds[i])));
+        Group *grp = nullptr;
+        for (auto &gq : ex.direct)
+            if (gq.pack == pack && gq.sel == sel && gq.big == per_cu) grp = &gq;
+        if (!grp) {
+            ex.direct.push_back(Group());
+            grp = &ex.direct.back();
+            grp->pack = pack;
+            grp->sel = sel;
+            grp->big = per_cu;
+        }
+        Group &gr = *grp;
+        gr.lds = std::max(gr.lds, dir_lds[i]);
         Seg s{};
         s.item0 = gr.nitems;
         s.job = i;
@@ -594,8 +615,7 @@ int build_exec(const md_job *jobs, int n, const std::vector<SEData> &ses, Exec &
         gr.alg_ops += px * ses[i].ncells * 2.0;
         gr.units += px * jobs[i].k * ex.jobs_h[i].kpad;
     }
-    for (int c = 0; c < 4; ++c) ex.direct_lds[c] = max_dir_lds[c];
-    ex.fb_direct_lds = max_fbdir_lds;
+
     // FFT jobs: split tile ranges into waves bounded by the workspace cap
     std::vector<std::vector<std::pair<int, std::pair<int, int>>>> wave_chunks(1);   // (job, (tile0, ntiles))
     std::vector<size_t> wave_bytes(1, 0);
@@ -636,7 +656,7 @@ int build_exec(const md_job *jobs, int n, const std::vector<SEData> &ses, Exec &
             s.job = i;
             s.tile0 = tile0;
             s.ntiles = nt_;
-            s.pblocks = (p.T * p.T + kDecThreads - 1) / kDecThreads;
+            s.pblocks = (p.T * p.T + kDecThreads * kDecPixPerThread - 1) / (kDecThreads * kDecPixPerThread);
             s.y = (char *)ex.ybuf.p + off;
             off += per_tile * nt_;
             const double esz = p.dbl ? 16.0 : 8.0, N2 = (double)p.nt * p.nt, TT = (double)p.T * p.T;
@@ -666,7 +686,7 @@ int build_exec(const md_job *jobs, int n, const std::vector<SEData> &ses, Exec &
     }
     // device copies of the segment tables
     size_t nseg_total = 0;
-    for (int c = 0; c < 4; ++c) nseg_total += ex.direct[c].segs.size();
+    for (auto &gr : ex.direct) nseg_total += gr.segs.size();
     for (auto &wv : ex.waves) {
         for (auto &gr : wv.fft) nseg_total += gr.segs.size();
         for (auto &gr : wv.dec) nseg_total += gr.segs.size();
@@ -679,12 +699,16 @@ int build_exec(const md_job *jobs, int n, const std::vector<SEData> &ses, Exec &
         all.insert(all.end(), gr.segs.begin(), gr.segs.end());
         gr.grid = occupancy_grid(gr.nitems, lds, threads);
     };
-    for (int c = 0; c < 4; ++c)
-        if (!ex.direct[c].segs.empty()) place(ex.direct[c], kDirThreads, ex.direct_lds[c]);
+    for (auto &gr : ex.direct) place(gr, kDirThreads, gr.lds);
     for (auto &wv : ex.waves) {
         for (auto &gr : wv.fft) {
-            const size_t lds = (size_t)gr.nt * (gr.nt + 1) * (gr.dbl ? sizeof(double2) : sizeof(float2));
-            place(gr, fft_block_threads(gr.nt, gr.dbl), lds);
+            place(gr, fft_block_threads(gr.nt, gr.dbl), fft_lds_bytes(gr.nt, gr.dbl));
+            if (gr.nt > (gr.dbl ? kMaxLdsN64 : kMaxLdsN32)) {
+                auto b = std::make_unique<DevBuf>();
+                MD_TRY(b->ensure((size_t)gr.grid * gr.nt * gr.nt * (gr.dbl ? sizeof(double2) : sizeof(float2))));
+                gr.slabs = b->p;
+                ex.slabbufs.push_back(std::move(b));
+            }
         }
         for (auto &gr : wv.dec) place(gr, kDecThreads, 0);
     }
@@ -694,8 +718,15 @@ int build_exec(const md_job *jobs, int n, const std::vector<SEData> &ses, Exec &
     MD_TRY(ex.flags.ensure(std::max<long long>(1, flag_total) * sizeof(unsigned int)));
     MD_TRY(ex.list.ensure(std::max<long long>(1, flag_total) * sizeof(int2)));
     if (!ex.fb_classes.empty()) {
-        ex.fb_grid = (int)std::max<long long>(1, std::min<long long>(flag_total, std::min(g.cu, 128)));
+        int big64 = 0;
+        for (int nt64 : ex.fb_classes)
+            if (nt64 > kMaxLdsN64) big64 = std::max(big64, nt64);
+        // recompute blocks: bounded so slots and slabs stay under ~1 GiB
+        const double per_block = (double)ex.slot_elems * sizeof(double2) + (double)big64 * big64 * sizeof(double2);
+        const int cap = (int)std::max(1.0, std::min((double)std::min(g.cu, 128), (1 << 30) / per_block));
+        ex.fb_grid = (int)std::max<long long>(1, std::min<long long>(flag_total, cap));
         MD_TRY(ex.slots.ensure((size_t)ex.fb_grid * ex.slot_elems * sizeof(double2)));
+        if (big64) MD_TRY(ex.fb_slabs.ensure((size_t)ex.fb_grid * big64 * big64 * sizeof(double2)));
     }
     // job table
     MD_HIP(hipMalloc(&ex.jobs_d, sizeof(JobDev) * n));
@@ -760,12 +791,10 @@ int enqueue(Exec &ex, hipStream_t s, bool skip_decode = false, bool capturing = 
     const bool prof = g.opt.profile && !capturing;
     MD_HIP(launch_zero(g.st_d, sizeof(StatsDev), s));
     if (ex.nflags > 0) MD_HIP(launch_zero(ex.flags.p, ex.nflags * sizeof(unsigned int), s));
-    for (int c = 0; c < 4; ++c) {
-        Group &gr = ex.direct[c];
+    for (auto &gr : ex.direct) {
         if (gr.nitems <= 0) continue;
-        const int pk = c & 1, sel = c >> 1;
-        ProfScope ps(prof, s, pk ? "direct16" : "direct32", gr.alg_bytes, gr.alg_ops, gr.units);
-        MD_HIP(launch_direct(pk, sel, ex.jobs_d, gr.segs_d, (int)gr.segs.size(), gr.nitems, gr.grid, ex.direct_lds[c],
+        ProfScope ps(prof, s, gr.pack ? "direct16" : "direct32", gr.alg_bytes, gr.alg_ops, gr.units);
+        MD_HIP(launch_direct(gr.pack, gr.sel, ex.jobs_d, gr.segs_d, (int)gr.segs.size(), gr.nitems, gr.grid, gr.lds,
                              g.st_d, s));
         ps.done();
     }
@@ -775,7 +804,7 @@ int enqueue(Exec &ex, hipStream_t s, bool skip_decode = false, bool capturing = 
             ProfScope ps(prof, s, std::string(gr.dbl ? "fft64_n" : "fft32_n") + std::to_string(gr.nt), gr.alg_bytes,
                          gr.alg_ops, gr.units);
             MD_HIP(launch_fft(gr.nt, gr.dbl, ex.jobs_d, gr.segs_d, (int)gr.segs.size(), gr.nitems, gr.grid, g.tw32,
-                              g.tw64, g.st_d, s));
+                              g.tw64, gr.slabs, g.st_d, s));
             ps.done();
         }
         if (skip_decode) continue;
@@ -790,12 +819,7 @@ int enqueue(Exec &ex, hipStream_t s, bool skip_decode = false, bool capturing = 
     for (int nt64 : ex.fb_classes) {
         ProfScope ps(prof, s, "recompute64_n" + std::to_string(nt64), 0, 0, 0);
         MD_HIP(launch_fallback(nt64, ex.jobs_d, (const int2 *)ex.list.p, g.st_d, (double2 *)ex.slots.p,
-                               ex.slot_elems, ex.fb_grid, g.tw64, s));
-        ps.done();
-    }
-    if (ex.fb_direct) {
-        ProfScope ps(prof, s, "recompute_direct", 0, 0, 0);
-        MD_HIP(launch_fallback_direct(ex.jobs_d, (const int2 *)ex.list.p, g.st_d, g.cu, ex.fb_direct_lds, s));
+                               ex.slot_elems, ex.fb_grid, g.tw64, (double2 *)ex.fb_slabs.p, s));
         ps.done();
     }
     return MD_OK;
@@ -828,11 +852,14 @@ int run(const md_job *jobs, int n, bool use_graph);
 // Autotuner: time each kernel family on calibration images on this device
 // and replace the cost model's built-in estimates with the measured rates.
 int autotune_body() {
-    const int H = 1024, W = 1024, L = 16;
+    // calibration images: 1024^2 for the LDS-resident lengths, 2048^2 for the
+    // large ones (enough (tile, bin) items to load the whole GPU)
+    const int HS = 2048, L = 16;
+    int H = 1024, W = 1024;
     DevBuf img, out;
-    MD_TRY(img.ensure((size_t)H * W * 4));
-    MD_TRY(out.ensure((size_t)H * W * 4));
-    MD_HIP(launch_fill_hash((int32_t *)img.p, (size_t)H * W, L, 12345u, g.stream));
+    MD_TRY(img.ensure((size_t)HS * HS * 4));
+    MD_TRY(out.ensure((size_t)HS * HS * 4));
+    MD_HIP(launch_fill_hash((int32_t *)img.p, (size_t)HS * HS, L, 12345u, g.stream));
     g.opt.sync = 1;
     g.opt.graph = 0;
     g.opt.profile = 1;
@@ -843,6 +870,7 @@ int autotune_body() {
         std::vector<uint8_t> mask((size_t)k * k, 1);
         std::vector<int32_t> off((size_t)k * k);
         for (size_t q = 0; q < off.size(); ++q) off[q] = (int32_t)(q % 4);
+        H = W = (tile > (prec ? kMaxLdsN64 : kMaxLdsN32)) ? HS : 1024;
         md_job j{(const int32_t *)img.p, H, W, L, mask.data(), off.data(), k, (int32_t *)out.p, 0};
         g.opt.path = path;
         g.opt.precision = prec;
@@ -859,12 +887,19 @@ int autotune_body() {
         return MD_OK;
     };
     MD_TRY(measure(15, kPathDirect, 0, 0, "direct16", &g.cost.dir_unit, "", nullptr));
-    for (int nt : {16, 32, 64, 128})
-        MD_TRY(measure(nt / 8 * 2 + 1, kPathFFT, 0, nt, "fft32_n" + std::to_string(nt), &g.cost.fft_item[0][ilog2i(nt)],
-                       "decode32", &g.cost.dec_unit[0]));
-    for (int nt : {16, 32, 64})
-        MD_TRY(measure(nt / 8 * 2 + 1, kPathFFT, 1, nt, "fft64_n" + std::to_string(nt), &g.cost.fft_item[1][ilog2i(nt)],
-                       "decode64", &g.cost.dec_unit[1]));
+    // SE side nt/8*2+1 up to 33 (the item cost does not depend on it; the
+    // spectrum build does); lengths above 512 (FP32) / 256 (FP64) are
+    // extrapolated by the N^2 log N^2 work of one item
+    for (int nt : {16, 32, 64, 128, 256, 512})
+        MD_TRY(measure(std::min(nt / 8 * 2 + 1, 33), kPathFFT, 0, nt, "fft32_n" + std::to_string(nt),
+                       &g.cost.fft_item[0][ilog2i(nt)], "decode32", &g.cost.dec_unit[0]));
+    for (int nt : {16, 32, 64, 128, 256})
+        MD_TRY(measure(std::min(nt / 8 * 2 + 1, 33), kPathFFT, 1, nt, "fft64_n" + std::to_string(nt),
+                       &g.cost.fft_item[1][ilog2i(nt)], "decode64", &g.cost.dec_unit[1]));
+    auto extrap = [](double c, int lg) { return c * 4.0 * (lg + 1.0) / lg; };   // nt -> 2 nt
+    g.cost.fft_item[0][10] = extrap(g.cost.fft_item[0][9], 9);
+    g.cost.fft_item[1][9] = extrap(g.cost.fft_item[1][8], 8);
+    g.cost.fft_item[1][10] = extrap(g.cost.fft_item[1][9], 9);
     return MD_OK;
 }
 
@@ -896,7 +931,7 @@ bool load_tune_file() {
         else if (k.rfind("fft64_n", 0) == 0) c.fft_item[1][ilog2i(atoi(k.c_str() + 7))] = v, ++got;
     }
     fclose(f);
-    if (!dev_ok || got < 10) return false;
+    if (!dev_ok || got < 17) return false;
     g.cost = c;
     return true;
 }
@@ -908,8 +943,8 @@ void save_tune_file() {
     if (!f) return;
     fprintf(f, "device %s\n", device_key().c_str());
     fprintf(f, "direct %.9g\ndecode32 %.9g\ndecode64 %.9g\n", g.cost.dir_unit, g.cost.dec_unit[0], g.cost.dec_unit[1]);
-    for (int nt : {16, 32, 64, 128}) fprintf(f, "fft32_n%d %.9g\n", nt, g.cost.fft_item[0][ilog2i(nt)]);
-    for (int nt : {16, 32, 64}) fprintf(f, "fft64_n%d %.9g\n", nt, g.cost.fft_item[1][ilog2i(nt)]);
+    for (int nt = 16; nt <= kMaxN; nt *= 2) fprintf(f, "fft32_n%d %.9g\n", nt, g.cost.fft_item[0][ilog2i(nt)]);
+    for (int nt = 16; nt <= kMaxN; nt *= 2) fprintf(f, "fft64_n%d %.9g\n", nt, g.cost.fft_item[1][ilog2i(nt)]);
     fclose(f);
 }
 
@@ -1049,7 +1084,8 @@ int md_set_option(int key, double v) {
             o.path = (int)v;
             break;
         case MD_OPT_TILE:
-            if (v != 0 && v != 16 && v != 32 && v != 64 && v != 128) return fail(MD_ERR_ARG, "tile must be 0, 16, 32, 64 or 128");
+            if (v != 0 && !(v >= 16 && v <= kMaxN && v == floor(v) && ((int)v & ((int)v - 1)) == 0))
+                return fail(MD_ERR_ARG, "tile must be 0 or a power of two in [16, %d]", kMaxN);
             o.tile = (int)v;
             break;
         case MD_OPT_NR:
@@ -1132,9 +1168,8 @@ int md_cost_model(double *dst, int *measured) {
     dst[0] = g.cost.dir_unit;
     dst[1] = g.cost.dec_unit[0];
     dst[2] = g.cost.dec_unit[1];
-    for (int q = 0; q < 4; ++q) dst[3 + q] = g.cost.fft_item[0][4 + q];
-    for (int q = 0; q < 3; ++q) dst[7 + q] = g.cost.fft_item[1][4 + q];
-    dst[10] = 0;
+    for (int q = 0; q < 7; ++q) dst[3 + q] = g.cost.fft_item[0][4 + q];
+    for (int q = 0; q < 7; ++q) dst[10 + q] = g.cost.fft_item[1][4 + q];
     *measured = g.cost_measured ? 1 : 0;
     return MD_OK;
 }

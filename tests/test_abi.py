@@ -36,3 +36,11 @@ def test_binding_requires_device_tensors():
 
     with pytest.raises(TypeError):
         md.dilate(np.zeros((4, 4), np.int32), np.ones((3, 3)), np.zeros((3, 3)), 4)
+
+
+def test_cost_model_shape():
+    cm = md.cost_model()
+    assert sorted(cm["fft32_item"]) == [16, 32, 64, 128, 256, 512, 1024]
+    assert sorted(cm["fft64_item"]) == [16, 32, 64, 128, 256, 512, 1024]
+    assert all(v > 0 for v in cm["fft32_item"].values())
+    assert cm["direct_per_px_k_kpad"] > 0

@@ -134,7 +134,7 @@ def test_forced_recompute_all_and_none(dev):
     assert st["fallback_tiles"] == 0
 
 
-def test_recompute_by_direct_window_for_large_se(dev):
+def test_recompute_large_se_fp64_large_tile(dev):
     rng = np.random.default_rng(22)
     job = synthetic.random_job(rng, 140, 170, 8, 61, p=0.5, max_off=2)
     want = oracle.run_job(job)
@@ -187,6 +187,41 @@ def test_largest_se_and_widest_range(dev):
     assert_parity(job, dev, want=want, **FFT32)
     assert_parity(job, dev, want=want, **FFT64)
     assert_parity(job, dev, want=want)
+
+
+def test_large_se_fft_only(dev):
+    """SEs beyond the direct window's limit (k > 127) go through the FFT path
+    with spatial tiles larger than the LDS (256 to 1024 points per side)."""
+    rng = np.random.default_rng(25)
+    job = synthetic.random_job(rng, 520, 610, 8, 151, p=0.5, max_off=2)
+    want = oracle.run_job(job)
+    for t in (256, 512, 1024):
+        assert_parity(job, dev, want=want, tile=t, **FFT32)
+    for t in (256, 512):
+        assert_parity(job, dev, want=want, tile=t, **FFT64)
+    st = assert_parity(job, dev, want=want)              # auto: must take the FFT path
+    assert st["fft_jobs"] == 1 and st["n_t"] >= 256
+    job.op = 1
+    want = oracle.run_job(job)
+    assert_parity(job, dev, want=want, tile=256, **FFT32)
+    with pytest.raises(md.MDError) as ei:
+        run_job(job, dev, **DIRECT)
+    assert ei.value.code == -5
+
+
+def test_large_tiles_mid_se_and_recompute(dev):
+    """Large tiles for moderate SEs, in both precisions, and the FP64
+    recompute on large tiles (every tile forced through it)."""
+    rng = np.random.default_rng(26)
+    job = synthetic.random_job(rng, 700, 333, 16, 41, p=0.6, max_off=4)
+    want = oracle.run_job(job)
+    assert_parity(job, dev, want=want, tile=256, **FFT32)
+    assert_parity(job, dev, want=want, tile=128, **FFT64)
+    assert_parity(job, dev, want=want, tile=256, **FFT64)
+    st = assert_parity(job, dev, want=want, tile=256, band=0.0, **FFT32)
+    assert st["fallback_tiles"] == st["tiles"] > 0
+    st = assert_parity(job, dev, want=want, tile=128, band=0.0, **FFT32)
+    assert st["fallback_tiles"] == st["tiles"] > 0
 
 
 def test_errors(dev):
@@ -277,6 +312,8 @@ def test_large_random_mask_2048(dev, flat):
     _say(f"  stats {st}")
     assert st["max_residual"] < 0.25
     assert_parity(job, dev, want=want, **DIRECT)
+    if flat:
+        assert_parity(job, dev, want=want, **FFT64)
 
 
 def test_octave_noise_4096(dev):
