@@ -58,7 +58,8 @@ struct JobDev {
     double scale;                // 1 / (nt^2 * nr)
     const void *se_spec;         // [bins][nt][nt] spectrum of the SE umbra
     const void *enc;             // [bins][L]  exp(-2 pi i (v m mod nr) / nr)
-    const void *dec;             // [bins][bins] w_m exp(+2 pi i d m / nr), d <= nr/2, w = 1 or 2
+    const void *dec;             // [dp][dp] w_m exp(+2 pi i d m / nr) for m, d < bins, zero beyond
+    int dec_pitch;               // dp: bins rounded up to a multiple of 32
     long long flag0;             // first entry of this job in the tile-flag array
     // exact recompute of ambiguous tiles
     int fb_mode;                 // kFbNone / kFbFFT64
@@ -66,7 +67,7 @@ struct JobDev {
     double scale64;
     const double2 *se_spec64;    // [bins][nt64][nt64]
     const double2 *enc64;        // [bins][L]
-    const double2 *dec64;        // [bins][bins]
+    const double2 *dec64;        // [dp][dp]
     // direct max-plus path
     const int32_t *sek;          // [k][kpad] offsets in correlation order, kNeg where masked
     const int32_t *sek16;        // same, as two equal 16-bit lanes per word, -16384 where masked
@@ -107,7 +108,11 @@ hipError_t launch_zero(void *p, size_t bytes, hipStream_t s);
 hipError_t launch_fill_hash(int32_t *p, size_t n, int L, unsigned int seed, hipStream_t s);
 hipError_t launch_fft(int nt, int dbl, const JobDev *jobs, const Seg *segs, int nseg, long long nitems,
                       int grid, const TwF *tw32, const double2 *tw64, void *slabs, StatsDev *st, hipStream_t s);
-hipError_t launch_decode(int big, int dbl, const JobDev *jobs, const Seg *segs, int nseg,
+// decode kernel variant for a job's kept-bin count, and the zero-padded pitch
+// (both dimensions) of the [bin][degree] decode table for a range length
+int decode_group_variant(int bins, int dbl);
+int dec_pitch(int nr);
+hipError_t launch_decode(int var, int dbl, const JobDev *jobs, const Seg *segs, int nseg,
                          long long nitems, int grid, float band, unsigned int *tile_flags,
                          int2 *fb_list, StatsDev *st, hipStream_t s);
 hipError_t launch_direct(int pack, int sel, const JobDev *jobs, const Seg *segs, int nseg, long long nitems,

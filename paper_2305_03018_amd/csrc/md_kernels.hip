@@ -462,65 +462,77 @@ __global__ __launch_bounds__(BS) void k_fft_big(const JobDev *__restrict__ jobs,
     }
 }
 
-// One block of kDecDC degrees x kDecMC bins of the inverse real DFT.
-// A_d += w_m Re(X_m) cos(2 pi d m / nr), B_d += w_m Im(X_m) sin(2 pi d m / nr);
-// the twiddle index depends only on (d, m), so it is a scalar load.
-constexpr int kDecDC = 16, kDecMC = 8;
-
-template <typename R, bool GUARD>
-__device__ __forceinline__ void decode_chunk(const typename Cx<R>::T (&x)[kDecMC], R (&A)[kDecDC], R (&B)[kDecDC],
-                                             const typename Cx<R>::T *W, int d0, int m0, int dh, int bins) {
+// Inverse real DFT over the range axis for one pixel per lane, and Step 3:
+// c_d = A_d - B_d and c_{nr-d} = A_d + B_d for d <= nr/2 (the coefficient
+// vector is real), with A_d = sum_m w_m Re(X_m) cos(2 pi d m / nr) and
+// B_d = sum_m w_m Im(X_m) sin(2 pi d m / nr); then the top degree with
+// rint(c_d) != 0 and the largest distance |c_d - rint(c_d)| over all degrees.
+//
+// The [bin][degree] table is zero-padded (pitch `dp`, a multiple of 32, in
+// both dimensions), so MB bins x DC degrees are accumulated per block with no
+// branch: padded bins and degrees add zeros.  The twiddle index depends only
+// on (bin, degree), so the table arrives through wave-uniform scalar loads.
+// With bins <= MB and nr/2 < DC one pass covers the pixel and its bin values
+// are loaded once.
+template <typename R, int MB, int DC>
+__device__ __forceinline__ void decode_px(const typename Cx<R>::T *X, size_t mstride, int p, bool valid,
+                                          const typename Cx<R>::T *dec, int dp, int nr, int bins, R scale, int &top,
+                                          R &res) {
+    using C = typename Cx<R>::T;
+    const int dh = nr >> 1;
+    top = -1;
+    res = 0;
+    if (!__any(valid)) return;   // the whole wave lies outside the image
+    for (int d0 = 0; d0 <= dh; d0 += DC) {
+        R A[DC], B[DC];
 #pragma unroll
-    for (int mm = 0; mm < kDecMC; ++mm) {
-        if (GUARD && m0 + mm >= bins) break;
-        const typename Cx<R>::T *row = W + (size_t)(m0 + mm) * bins + d0;   // bins == nr/2 + 1 == dh + 1
+        for (int dd = 0; dd < DC; ++dd) A[dd] = B[dd] = 0;
+        for (int m0 = 0; m0 < bins; m0 += MB) {
+            C x[MB];
 #pragma unroll
-        for (int dd = 0; dd < kDecDC; ++dd) {
-            if (GUARD && d0 + dd > dh) break;
-            const typename Cx<R>::T w = ldc(row, dd);
-            A[dd] = fma(x[mm].x, w.x, A[dd]);
-            B[dd] = fma(x[mm].y, w.y, B[dd]);
+            for (int mm = 0; mm < MB; ++mm) {
+                x[mm] = czero<C>();
+                if (valid && m0 + mm < bins) x[mm] = ldg(X, (size_t)(m0 + mm) * mstride + p);
+            }
+            const C *blk = dec + (size_t)m0 * dp + d0;
+#pragma unroll
+            for (int mm = 0; mm < MB; ++mm) {
+#pragma unroll
+                for (int dd = 0; dd < DC; ++dd) {
+                    const C w = ldc(blk, (size_t)mm * dp + dd);
+                    A[dd] = fma(x[mm].x, w.x, A[dd]);
+                    B[dd] = fma(x[mm].y, w.y, B[dd]);
+                }
+            }
+        }
+#pragma unroll
+        for (int dd = 0; dd < DC; ++dd) {
+            const int d = d0 + dd;
+            if (d <= dh) {
+                band_update<R>((A[dd] - B[dd]) * scale, d, top, res);
+                if (d > 0 && 2 * d != nr) band_update<R>((A[dd] + B[dd]) * scale, nr - d, top, res);
+            }
         }
     }
 }
 
-// Inverse real DFT over the range axis for one pixel per lane and Step 3:
-// c_d = A_d - B_d and c_{nr-d} = A_d + B_d for d <= nr/2 (the coefficient
-// vector is real), then the top degree with rint(c_d) != 0 and the largest
-// distance |c_d - rint(c_d)| over all degrees.
-template <typename R>
-__device__ __forceinline__ void decode_pixel(const typename Cx<R>::T *X, size_t mstride, int p, bool valid,
-                                             const typename Cx<R>::T *dec, int nr, int bins, R scale, int &top,
-                                             R &res) {
-    using C = typename Cx<R>::T;
-    const C *W = dec;
-    const int dh = nr >> 1;
-    top = -1;
-    res = 0;
-    for (int d0 = 0; d0 <= dh; d0 += kDecDC) {
-        R A[kDecDC], B[kDecDC];
-#pragma unroll
-        for (int dd = 0; dd < kDecDC; ++dd) A[dd] = B[dd] = 0;
-        for (int m0 = 0; m0 < bins; m0 += kDecMC) {
-            C x[kDecMC];
-#pragma unroll
-            for (int mm = 0; mm < kDecMC; ++mm) {
-                x[mm] = czero<C>();
-                if (valid && m0 + mm < bins) x[mm] = ldg(X, (size_t)(m0 + mm) * mstride + p);
-            }
-            if (d0 + kDecDC - 1 <= dh && m0 + kDecMC <= bins)
-                decode_chunk<R, false>(x, A, B, W, d0, m0, dh, bins);
-            else
-                decode_chunk<R, true>(x, A, B, W, d0, m0, dh, bins);
-        }
-#pragma unroll
-        for (int dd = 0; dd < kDecDC; ++dd) {
-            const int d = d0 + dd;
-            if (d > dh) break;
-            band_update<R>((A[dd] - B[dd]) * scale, d, top, res);
-            if (d > 0 && 2 * d != nr) band_update<R>((A[dd] + B[dd]) * scale, nr - d, top, res);
-        }
-    }
+// Decode variants by kept-bin count: one register pass for bins <= 8, <= 12
+// and (FP32) <= 24; else blocks of 16 x 16 (FP32) or 8 x 8 (FP64).
+enum : int { kDec8 = 0, kDec12 = 1, kDec24 = 2, kDecBlk = 3 };
+
+__host__ __device__ constexpr int decode_variant(int bins, int dbl) {
+    return bins <= 8 ? kDec8 : bins <= 12 ? kDec12 : (bins <= 24 && !dbl) ? kDec24 : kDecBlk;
+}
+
+template <typename R, int V>
+__device__ __forceinline__ void decode_var(const typename Cx<R>::T *X, size_t mstride, int p, bool valid,
+                                           const typename Cx<R>::T *dec, int dp, int nr, int bins, R scale, int &top,
+                                           R &res) {
+    if constexpr (V == kDec8) decode_px<R, 8, 8>(X, mstride, p, valid, dec, dp, nr, bins, scale, top, res);
+    else if constexpr (V == kDec12) decode_px<R, 12, 12>(X, mstride, p, valid, dec, dp, nr, bins, scale, top, res);
+    else if constexpr (V == kDec24) decode_px<R, 24, 24>(X, mstride, p, valid, dec, dp, nr, bins, scale, top, res);
+    else if constexpr (sizeof(R) == 4) decode_px<R, 16, 16>(X, mstride, p, valid, dec, dp, nr, bins, scale, top, res);
+    else decode_px<R, 8, 8>(X, mstride, p, valid, dec, dp, nr, bins, scale, top, res);
 }
 
 __device__ __forceinline__ float wave_max(float v) {
@@ -541,7 +553,7 @@ __device__ __forceinline__ float block_max(float v, float *sh) {
     return r;
 }
 
-template <typename R>
+template <typename R, int V>
 __global__ __launch_bounds__(kDecThreads) void k_decode(const JobDev *__restrict__ jobs,
                                                         const Seg *__restrict__ segs, int nseg,
                                                         long long nitems, float band,
@@ -570,7 +582,7 @@ __global__ __launch_bounds__(kDecThreads) void k_decode(const JobDev *__restrict
             const bool valid = p < (int)TT && gy < J.H && gx < J.W;
             int top;
             R res;
-            decode_pixel<R>(X, TT, p, valid, (const C *)J.dec, J.nr, J.bins, (R)J.scale, top, res);
+            decode_var<R, V>(X, TT, p, valid, (const C *)J.dec, J.dec_pitch, J.nr, J.bins, (R)J.scale, top, res);
             if (valid) {
                 const int d = top < 0 ? 0 : top;
                 gst(J.out)[(size_t)gy * J.W + gx] = J.op ? (J.L - 1 - d) : d;
@@ -920,7 +932,19 @@ __global__ __launch_bounds__(kDecThreads) void k_fallback(const JobDev *__restri
                     const bool valid = p < (int)TT && ly < sh && lx < sw;
                     int top;
                     double res;
-                    decode_pixel<double>(slot, TT, p, valid, J.dec64, J.nr, J.bins, J.scale64, top, res);
+                    switch (decode_variant(J.bins, 1)) {
+                        case kDec8:
+                            decode_var<double, kDec8>(slot, TT, p, valid, J.dec64, J.dec_pitch, J.nr, J.bins,
+                                                      J.scale64, top, res);
+                            break;
+                        case kDec12:
+                            decode_var<double, kDec12>(slot, TT, p, valid, J.dec64, J.dec_pitch, J.nr, J.bins,
+                                                       J.scale64, top, res);
+                            break;
+                        default:
+                            decode_var<double, kDecBlk>(slot, TT, p, valid, J.dec64, J.dec_pitch, J.nr, J.bins,
+                                                        J.scale64, top, res);
+                    }
                     if (valid) {
                         const int d = top < 0 ? 0 : top;
                         gst(J.out)[(size_t)(oy0 + sy + ly) * J.W + (ox0 + sx + lx)] = J.op ? (J.L - 1 - d) : d;
@@ -951,12 +975,13 @@ __global__ void k_twiddles(double2 *tw64, TwF *tw32) {
 
 // enc[m][v] = exp(-2 pi i (v m mod nr) / nr): range-axis DFT of the one-hot
 // column of grey value v (Eq. (7)).  dec[m][d] = w_m exp(+2 pi i (d m mod nr)
-// / nr) for d <= nr/2, w_m = 1 for m = 0 and m = nr/2, 2 otherwise: the inverse
-// real DFT from the kept half of the bins (unscaled); degrees above nr/2
-// follow by symmetry in the decode.
-__global__ void k_range_tables(int nr, int L, int bins, float2 *enc32, double2 *enc64, float2 *dec32,
+// / nr) for m, d < bins = nr/2+1 (w_m = 1 for m = 0 and m = nr/2, 2
+// otherwise), zero-padded to dp x dp with dp = dec_pitch(nr): the inverse real
+// DFT from the kept half of the bins (unscaled); degrees above nr/2 follow by
+// symmetry in the decode.
+__global__ void k_range_tables(int nr, int L, int bins, int dp, float2 *enc32, double2 *enc64, float2 *dec32,
                                double2 *dec64) {
-    const long long ne = (long long)bins * L, nd = (long long)bins * bins;
+    const long long ne = (long long)bins * L, nd = (long long)dp * dp;
     for (long long q = blockIdx.x * (long long)blockDim.x + threadIdx.x; q < ne + nd;
          q += (long long)gridDim.x * blockDim.x) {
         double s, c;
@@ -968,12 +993,17 @@ __global__ void k_range_tables(int nr, int L, int bins, float2 *enc32, double2 *
             enc32[q] = make_float2((float)c, (float)s);
         } else {
             const long long e = q - ne;
-            const long long m = e / bins, d = e % bins;
-            const long long ph = (d * m) % nr;
-            sincospi(2.0 * (double)ph / nr, &s, &c);
-            const double wt = (m == 0 || 2 * m == nr) ? 1.0 : 2.0;
-            dec64[e] = make_double2(wt * c, wt * s);
-            dec32[e] = make_float2((float)(wt * c), (float)(wt * s));
+            const long long m = e / dp, d = e % dp;
+            double wc = 0, ws = 0;
+            if (m < bins && d < bins) {
+                const long long ph = (d * m) % nr;
+                sincospi(2.0 * (double)ph / nr, &s, &c);
+                const double wt = (m == 0 || 2 * m == nr) ? 1.0 : 2.0;
+                wc = wt * c;
+                ws = wt * s;
+            }
+            dec64[e] = make_double2(wc, ws);
+            dec32[e] = make_float2((float)wc, (float)ws);
         }
     }
 }
@@ -1067,10 +1097,10 @@ hipError_t launch_twiddles(double2 *tw64, TwF *tw32, hipStream_t s) {
 
 hipError_t launch_range_tables(int nr, int L, float2 *enc32, double2 *enc64, float2 *dec32, double2 *dec64,
                                hipStream_t s) {
-    const int bins = nr / 2 + 1;
-    const long long n = (long long)bins * L + (long long)bins * bins;
+    const int bins = nr / 2 + 1, dp = dec_pitch(nr);
+    const long long n = (long long)bins * L + (long long)dp * dp;
     const int grid = (int)std::min<long long>((n + 255) / 256, 4096);
-    k_range_tables<<<grid, 256, 0, s>>>(nr, L, bins, enc32, enc64, dec32, dec64);
+    k_range_tables<<<grid, 256, 0, s>>>(nr, L, bins, dp, enc32, enc64, dec32, dec64);
     return hipGetLastError();
 }
 
@@ -1135,15 +1165,33 @@ hipError_t launch_fft(int nt, int dbl, const JobDev *jobs, const Seg *segs, int 
     return hipGetLastError();
 }
 
-hipError_t launch_decode(int big, int dbl, const JobDev *jobs, const Seg *segs, int nseg, long long nitems,
+hipError_t launch_decode(int var, int dbl, const JobDev *jobs, const Seg *segs, int nseg, long long nitems,
                          int grid, float band, unsigned int *tile_flags, int2 *fb_list, StatsDev *st,
                          hipStream_t s) {
-    (void)big;
     if (nitems <= 0) return hipSuccess;
-    if (!dbl) k_decode<float><<<grid, kDecThreads, 0, s>>>(jobs, segs, nseg, nitems, band, tile_flags, fb_list, st);
-    else k_decode<double><<<grid, kDecThreads, 0, s>>>(jobs, segs, nseg, nitems, band, tile_flags, fb_list, st);
+#define MD_DEC(R, V) \
+    k_decode<R, V><<<grid, kDecThreads, 0, s>>>(jobs, segs, nseg, nitems, band, tile_flags, fb_list, st); break
+    if (!dbl) {
+        switch (var) {
+            case kDec8: MD_DEC(float, kDec8);
+            case kDec12: MD_DEC(float, kDec12);
+            case kDec24: MD_DEC(float, kDec24);
+            default: MD_DEC(float, kDecBlk);
+        }
+    } else {
+        switch (var) {
+            case kDec8: MD_DEC(double, kDec8);
+            case kDec12: MD_DEC(double, kDec12);
+            default: MD_DEC(double, kDecBlk);
+        }
+    }
+#undef MD_DEC
     return hipGetLastError();
 }
+
+int decode_group_variant(int bins, int dbl) { return decode_variant(bins, dbl); }
+
+int dec_pitch(int nr) { return ((nr / 2 + 1) + 31) / 32 * 32; }
 
 int direct_block_rows(int pack) { return pack ? DirT<true>::BH : DirT<false>::BH; }
 

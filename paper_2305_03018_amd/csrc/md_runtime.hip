@@ -107,7 +107,7 @@ struct Plan {
 };
 
 struct Group {
-    int nt = 0, dbl = 0, big = 0;
+    int nt = 0, dbl = 0, big = 0;   // big: decode variant (decode groups), blocks per CU (direct groups)
     int pack = 0, sel = 0;        // direct groups: element form, SE staged in LDS
     size_t lds = 0;               // dynamic LDS per block (direct groups)
     void *slabs = nullptr;        // large-tile FFT groups: grid x nt x nt complex
@@ -262,7 +262,7 @@ int get_range(int nr, int L, RangeTables **out) {
     }
     auto rt = std::make_unique<RangeTables>();
     const size_t bins = nr / 2 + 1;
-    const size_t ne = bins * (size_t)L, nd = bins * bins;
+    const size_t ne = bins * (size_t)L, nd = (size_t)dec_pitch(nr) * dec_pitch(nr);
     MD_TRY(rt->enc32.ensure(ne * sizeof(float2)));
     MD_TRY(rt->enc64.ensure(ne * sizeof(double2)));
     MD_TRY(rt->dec32.ensure(nd * sizeof(float2)));
@@ -570,6 +570,7 @@ int build_exec(const md_job *jobs, int n, const std::vector<SEData> &ses, Exec &
         d.se_spec = p.dbl ? sp->s64.p : sp->s32.p;
         d.enc = p.dbl ? rt->enc64.p : rt->enc32.p;
         d.dec = p.dbl ? rt->dec64.p : rt->dec32.p;
+        d.dec_pitch = dec_pitch(p.nr);
         d.flag0 = flag_total;
         flag_total += (long long)p.tiles_x * p.tiles_y;
         ex.fft_tiles += (long long)p.tiles_x * p.tiles_y;
@@ -668,7 +669,7 @@ int build_exec(const md_job *jobs, int n, const std::vector<SEData> &ses, Exec &
             gf->alg_bytes += items * TT * esz + (double)nt_ * N2 * 4.0;
             gf->alg_ops += items * (2.0 * 5.0 * N2 * log2(N2) + 6.0 * N2);
             gf->units += items;
-            Group *gd = find_group(wv.dec, 0, p.dbl, p.nr > 32 ? 1 : 0);
+            Group *gd = find_group(wv.dec, 0, p.dbl, decode_group_variant(p.bins, p.dbl));
             s.item0 = gd->nitems;
             gd->segs.push_back(s);
             gd->nitems += (long long)nt_ * s.pblocks;
