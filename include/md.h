@@ -169,12 +169,18 @@ typedef struct {
 int md_profile_get(md_stage_time *out, int max, int *n);
 int md_profile_reset(void);
 
-/* Cost-model constants in use (ns per work unit): direct window per
- * pixel*k*kpad, decode per pixel*nr*bins (FP32, FP64), then the FFT stage per
- * (tile, bin) item for spatial lengths 16, 32, ..., 1024 in FP32 (7 values)
- * and in FP64 (7 values): 17 values into the host array `dst`.  *measured = 1
- * if they come from the autotuner. */
-int md_cost_model(double *dst, int *measured);
+/* Cost-model constants in use, in ns per work unit, into the host array
+ * `dst` of capacity `n` (at least 19):
+ *   [0] direct window, 16-bit packed form, per output pixel per SE cell
+ *       stepped through (active row spans in 8-column steps)
+ *   [1] the same, 32-bit form
+ *   [2] direct window, per staged image word (block plus halo)
+ *   [3] decode FP32, per pixel per (padded kept bins)^2
+ *   [4] decode FP64, the same
+ *   [5..11]  FFT stage per (tile, bin) item, FP32, lengths 16, 32, ..., 1024
+ *   [12..18] the same, FP64
+ * *measured = 1 if they come from the autotuner.  MD_ERR_ARG if n < 19. */
+int md_cost_model(double *dst, int n, int *measured);
 
 /* Test hook: per-bin transform-domain values of one tile just before the
  * inverse range transform, for measuring spectrum error against an FP64

@@ -84,7 +84,7 @@ def load():
     lib.md_profile_get.restype = i
     lib.md_profile_reset.argtypes = []
     lib.md_profile_reset.restype = i
-    lib.md_cost_model.argtypes = [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int)]
+    lib.md_cost_model.argtypes = [ctypes.POINTER(ctypes.c_double), i, ctypes.POINTER(ctypes.c_int)]
     lib.md_cost_model.restype = i
     _lib = lib
     return lib
@@ -245,13 +245,15 @@ def profile_get() -> dict:
 def cost_model() -> dict:
     """Cost-model constants in use (ns per work unit) and whether the
     autotuner measured them."""
-    v = (ctypes.c_double * 17)()
+    n = 19
+    v = (ctypes.c_double * n)()
     measured = ctypes.c_int(0)
-    _check(load().md_cost_model(v, ctypes.byref(measured)))
+    _check(load().md_cost_model(v, n, ctypes.byref(measured)))
     lens = [16 << q for q in range(7)]
-    return {"direct_per_px_k_kpad": v[0], "decode32_per_px_nr_bins": v[1], "decode64_per_px_nr_bins": v[2],
-            "fft32_item": {n: v[3 + q] for q, n in enumerate(lens)},
-            "fft64_item": {n: v[10 + q] for q, n in enumerate(lens)}, "measured": bool(measured.value)}
+    return {"direct16_per_px_cell": v[0], "direct32_per_px_cell": v[1], "direct_per_staged_word": v[2],
+            "decode32_per_px_bins2": v[3], "decode64_per_px_bins2": v[4],
+            "fft32_item": {n: v[5 + q] for q, n in enumerate(lens)},
+            "fft64_item": {n: v[12 + q] for q, n in enumerate(lens)}, "measured": bool(measured.value)}
 
 
 def debug_tile_values(img, mask, off, L: int, n_t: int, n_r: int, precision: int, ty: int, tx: int):

@@ -167,12 +167,18 @@ struct Exec {
 
 // Cost model (nanoseconds of whole-GPU time).  The constants are replaced by
 // measured rates when the autotuner has run on this device.
+// values reported by md_cost_model and persisted in the tune file
+constexpr int kCostValues = 19;
+
 struct CostModel {
     // per (tile, bin) item, index log2(nt): FP32 / FP64
     double fft_item[2][11] = {{0, 0, 0, 0, 2.0, 8.0, 30.0, 130.0, 700.0, 3200.0, 14000.0},
                               {0, 0, 0, 0, 5.0, 20.0, 75.0, 900.0, 3800.0, 16000.0, 70000.0}};
-    double dec_unit[2] = {1.5e-4, 3.0e-4};   // per pixel * nr * bins
-    double dir_unit = 1.0e-4;                // per pixel * k * kpad
+    double dec_unit[2] = {1.5e-3, 3.0e-3};   // per pixel * (padded bins)^2
+    // direct window: per output pixel * SE cells stepped through (16-bit
+    // packed / 32-bit form), and per staged image word
+    double dir_cell[2] = {2.5e-5, 5.0e-5};
+    double dir_stage = 2.0e-3;
     double launch = 3000.0;                  // fixed cost per job class
 };
 
@@ -283,7 +289,72 @@ struct SEData {
     int maxoff = 0;
     int ncells = 0;
     std::string key;
+    double dir_cells[2] = {0, 0};   // cells the direct window steps through per output pixel (packed, 32-bit)
 };
+
+// SE cells per output pixel that the direct window steps through: in its
+// correlation order (row i, column j <-> SE cell (k-1-i, k-1-j)), each row's
+// active span from its first column rounded down to 8, in 8-column steps;
+// the packed form takes SE rows in pairs over the union of their spans, with
+// a 4-column final step where it suffices.
+void dir_work(SEData &se) {
+    const int k = se.k;
+    std::vector<int> lo(k, k), hi(k, -1);
+    for (int i = 0; i < k; ++i)
+        for (int j = 0; j < k; ++j)
+            if (se.mask[(size_t)(k - 1 - i) * k + (k - 1 - j)]) {
+                lo[i] = std::min(lo[i], j);
+                hi[i] = std::max(hi[i], j);
+            }
+    auto steps = [](int a, int b, bool tail4) -> double {
+        if (a > b) return 0;
+        int jb = a & ~(kDirRX - 1);
+        double c = 0;
+        for (; jb + kDirRX - 1 <= b; jb += kDirRX) c += kDirRX;
+        if (jb <= b) c += (tail4 && b - jb < kDirRX / 2) ? kDirRX / 2 : kDirRX;
+        return c;
+    };
+    double e16 = 0, e32 = 0;
+    for (int i = 0; i < k; ++i) e32 += steps(lo[i], hi[i], false);
+    for (int i = 0; i < k; i += 2) {
+        if (i + 1 < k) {
+            int a = lo[i], b = hi[i];
+            if (lo[i + 1] <= hi[i + 1]) {
+                a = std::min(a, lo[i + 1]);
+                b = std::max(b, hi[i + 1]);
+            }
+            e16 += 2 * steps(a, b, true);
+        } else {
+            e16 += steps(lo[i], hi[i], false);
+        }
+    }
+    se.dir_cells[0] = e16;
+    se.dir_cells[1] = e32;
+}
+
+// Image words the direct window stages per output pixel (block plus halo).
+double dir_staged(int k, int pack) {
+    const int bh = direct_block_rows(pack), kpad = (k + kDirRX - 1) / kDirRX * kDirRX;
+    return (double)(bh + k - 1) * (kDirBW + kpad) / ((double)bh * kDirBW);
+}
+
+double dir_cost(const md_job &j, const SEData &se, int pack) {
+    const double px = (double)j.H * j.W;
+    return px * (dir_staged(j.k, pack) * g.cost.dir_stage + se.dir_cells[pack ? 0 : 1] * g.cost.dir_cell[pack ? 0 : 1]);
+}
+
+// Kept bins rounded up as the decode variant for that count accumulates them.
+double dec_padded_bins(int bins, int dbl) {
+    switch (decode_group_variant(bins, dbl)) {
+        case 0: return 8;
+        case 1: return 12;
+        case 2: return 24;
+        default: {
+            const int b = dbl ? 8 : 16;
+            return (double)((bins + b - 1) / b * b);
+        }
+    }
+}
 
 void make_se(const uint8_t *mask, const int32_t *off, int k, int op, SEData &se) {
     se.k = k;
@@ -305,6 +376,7 @@ void make_se(const uint8_t *mask, const int32_t *off, int k, int op, SEData &se)
     se.key.assign((const char *)&k, sizeof k);
     se.key.append((const char *)se.mask.data(), se.mask.size());
     se.key.append((const char *)se.off.data(), se.off.size() * sizeof(int32_t));
+    dir_work(se);
 }
 
 int get_spectrum(const SEData &se, int nt, int nr, bool need32, bool need64, SESpec **out) {
@@ -411,7 +483,8 @@ double fft_cost(const md_job &j, int nt, int nr, int dbl) {
     const int bins = nr / 2 + 1;
     const double item = g.cost.fft_item[dbl][ilog2i(nt)];
     if (item <= 0) return INFINITY;
-    return tiles * (double)bins * item + (double)tiles * T * T * nr * bins * g.cost.dec_unit[dbl];
+    const double pb = dec_padded_bins(bins, dbl);
+    return tiles * (double)bins * item + (double)tiles * T * T * pb * pb * g.cost.dec_unit[dbl];
 }
 
 int plan_job(const md_job &j, const SEData &se, Plan &p) {
@@ -427,10 +500,9 @@ int plan_job(const md_job &j, const SEData &se, Plan &p) {
     p.dbl = dbl;
     p.nr = nr;
     p.bins = nr / 2 + 1;
-    const int kpad = (j.k + kDirRX - 1) / kDirRX * kDirRX;
     const bool pack16 = (long long)(j.L - 1) + se.maxoff <= 16383;
     const bool dir_ok = j.k <= kMaxDirectK;
-    p.cost_dir = dir_ok ? (double)j.H * j.W * j.k * kpad * g.cost.dir_unit * (pack16 ? 1.0 : 2.0) : INFINITY;
+    p.cost_dir = dir_ok ? dir_cost(j, se, pack16 ? 1 : 0) : INFINITY;
     // transform plan: best spatial length by the cost model
     double best = INFINITY;
     int best_nt = 0;
@@ -614,7 +686,7 @@ int build_exec(const md_job *jobs, int n, const std::vector<SEData> &ses, Exec &
         const double px = (double)jobs[i].H * jobs[i].W;
         gr.alg_bytes += px * 8.0;
         gr.alg_ops += px * ses[i].ncells * 2.0;
-        gr.units += px * jobs[i].k * ex.jobs_h[i].kpad;
+        gr.units += px * ses[i].dir_cells[gr.pack ? 0 : 1];
     }
 
     // FFT jobs: split tile ranges into waves bounded by the workspace cap
@@ -681,7 +753,8 @@ int build_exec(const md_job *jobs, int n, const std::vector<SEData> &ses, Exec &
             }
             gd->alg_bytes += inside * (p.bins * esz + 4.0);
             gd->alg_ops += inside * p.nr * p.bins * 4.0;
-            gd->units += (double)nt_ * TT * p.nr * p.bins;
+            const double pb = dec_padded_bins(p.bins, p.dbl);
+            gd->units += (double)nt_ * TT * pb * pb;
         }
         ex.waves.push_back(std::move(wv));
     }
@@ -853,50 +926,78 @@ int run(const md_job *jobs, int n, bool use_graph);
 // Autotuner: time each kernel family on calibration images on this device
 // and replace the cost model's built-in estimates with the measured rates.
 int autotune_body() {
-    // calibration images: 1024^2 for the LDS-resident lengths, 2048^2 for the
-    // large ones (enough (tile, bin) items to load the whole GPU)
-    const int HS = 2048, L = 16;
-    int H = 1024, W = 1024;
+    // calibration images: 1024^2 for the direct window and the LDS-resident
+    // lengths, 2048^2 for the large ones (enough (tile, bin) items to load the
+    // whole GPU); grey values in [0, 16)
+    const int HS = 2048;
     DevBuf img, out;
     MD_TRY(img.ensure((size_t)HS * HS * 4));
     MD_TRY(out.ensure((size_t)HS * HS * 4));
-    MD_HIP(launch_fill_hash((int32_t *)img.p, (size_t)HS * HS, L, 12345u, g.stream));
+    MD_HIP(launch_fill_hash((int32_t *)img.p, (size_t)HS * HS, 16, 12345u, g.stream));
     g.opt.sync = 1;
     g.opt.graph = 0;
     g.opt.profile = 1;
     g.opt.nr = 0;
     g.opt.band = 0.25;
-    auto measure = [&](int k, int path, int prec, int tile, const std::string &stage, double *per_unit,
-                       const std::string &stage2, double *per_unit2) -> int {
+    // runs one job 3 times after a warm-up; *ms = mean time of `stage` per
+    // run, *per_unit = the same per work unit
+    auto measure = [&](int k, int L, int side, int path, int prec, int tile, const std::string &stage, double *ms,
+                       double *per_unit, SEData *se_out) -> int {
         std::vector<uint8_t> mask((size_t)k * k, 1);
         std::vector<int32_t> off((size_t)k * k);
         for (size_t q = 0; q < off.size(); ++q) off[q] = (int32_t)(q % 4);
-        H = W = (tile > (prec ? kMaxLdsN64 : kMaxLdsN32)) ? HS : 1024;
-        md_job j{(const int32_t *)img.p, H, W, L, mask.data(), off.data(), k, (int32_t *)out.p, 0};
+        if (se_out) make_se(mask.data(), off.data(), k, 0, *se_out);
+        md_job j{(const int32_t *)img.p, side, side, L, mask.data(), off.data(), k, (int32_t *)out.p, 0};
         g.opt.path = path;
         g.opt.precision = prec;
         g.opt.tile = tile;
         MD_TRY(run(&j, 1, false));
         g.prof.clear();
         for (int r = 0; r < 3; ++r) MD_TRY(run(&j, 1, false));
-        auto get = [&](const std::string &name, double *dst) {
-            auto it = g.prof.find(name);
-            if (dst && it != g.prof.end() && it->second.units > 0) *dst = it->second.ms * 1e6 / it->second.units;
-        };
-        get(stage, per_unit);
-        if (!stage2.empty()) get(stage2, per_unit2);
+        auto it = g.prof.find(stage);
+        if (it == g.prof.end() || it->second.units <= 0) return fail(MD_ERR_DEVICE, "calibration: no %s stage", stage.c_str());
+        if (ms) *ms = it->second.ms / 3.0;
+        if (per_unit) *per_unit = it->second.ms * 1e6 / it->second.units;
         return MD_OK;
     };
-    MD_TRY(measure(15, kPathDirect, 0, 0, "direct16", &g.cost.dir_unit, "", nullptr));
-    // SE side nt/8*2+1 up to 33 (the item cost does not depend on it; the
-    // spectrum build does); lengths above 512 (FP32) / 256 (FP64) are
-    // extrapolated by the N^2 log N^2 work of one item
-    for (int nt : {16, 32, 64, 128, 256, 512})
-        MD_TRY(measure(std::min(nt / 8 * 2 + 1, 33), kPathFFT, 0, nt, "fft32_n" + std::to_string(nt),
-                       &g.cost.fft_item[0][ilog2i(nt)], "decode32", &g.cost.dec_unit[0]));
-    for (int nt : {16, 32, 64, 128, 256})
-        MD_TRY(measure(std::min(nt / 8 * 2 + 1, 33), kPathFFT, 1, nt, "fft64_n" + std::to_string(nt),
-                       &g.cost.fft_item[1][ilog2i(nt)], "decode64", &g.cost.dec_unit[1]));
+    // direct window: staging and per-cell costs from a small and a large SE
+    // (16-bit packed form), then the 32-bit per-cell cost (L = 32768)
+    {
+        const int side = 1024;
+        const double px = (double)side * side;
+        SEData s3, s41, s15;
+        double t3 = 0, t41 = 0, t15 = 0;
+        MD_TRY(measure(3, 16, side, kPathDirect, 0, 0, "direct16", &t3, nullptr, &s3));
+        MD_TRY(measure(41, 16, side, kPathDirect, 0, 0, "direct16", &t41, nullptr, &s41));
+        MD_TRY(measure(15, 32768, side, kPathDirect, 0, 0, "direct32", &t15, nullptr, &s15));
+        const double a1 = dir_staged(3, 1), b1 = s3.dir_cells[0], y1 = t3 * 1e6 / px;
+        const double a2 = dir_staged(41, 1), b2 = s41.dir_cells[0], y2 = t41 * 1e6 / px;
+        double cc = (y2 - y1 * a2 / a1) / (b2 - b1 * a2 / a1);
+        double cs = (y1 - b1 * cc) / a1;
+        if (!(cc > 0) || !(cs > 0)) {   // degenerate fit: all of it per cell
+            cs = 0;
+            cc = y2 / b2;
+        }
+        g.cost.dir_cell[0] = cc;
+        g.cost.dir_stage = cs;
+        const double y3 = t15 * 1e6 / px - dir_staged(15, 0) * cs;
+        g.cost.dir_cell[1] = y3 > 0 ? y3 / s15.dir_cells[1] : 2 * cc;
+    }
+    // FFT lengths: SE side nt/8*2+1 up to 33 (the item cost does not depend
+    // on it; the spectrum build does); lengths above 512 (FP32) / 256 (FP64)
+    // are extrapolated by the N^2 log N^2 work of one item
+    for (int nt : {16, 32, 64, 128, 256, 512}) {
+        const int side = nt > kMaxLdsN32 ? HS : 1024;
+        MD_TRY(measure(std::min(nt / 8 * 2 + 1, 33), 16, side, kPathFFT, 0, nt, "fft32_n" + std::to_string(nt),
+                       nullptr, &g.cost.fft_item[0][ilog2i(nt)], nullptr));
+        if (nt == 64) MD_TRY(measure(17, 16, side, kPathFFT, 0, nt, "decode32", nullptr, &g.cost.dec_unit[0], nullptr));
+    }
+    for (int nt : {16, 32, 64, 128, 256}) {
+        const int side = nt > kMaxLdsN64 ? HS : 1024;
+        MD_TRY(measure(std::min(nt / 8 * 2 + 1, 33), 16, side, kPathFFT, 1, nt, "fft64_n" + std::to_string(nt),
+                       nullptr, &g.cost.fft_item[1][ilog2i(nt)], nullptr));
+        if (nt == 64) MD_TRY(measure(17, 16, side, kPathFFT, 1, nt, "decode64", nullptr, &g.cost.dec_unit[1], nullptr));
+    }
     auto extrap = [](double c, int lg) { return c * 4.0 * (lg + 1.0) / lg; };   // nt -> 2 nt
     g.cost.fft_item[0][10] = extrap(g.cost.fft_item[0][9], 9);
     g.cost.fft_item[1][9] = extrap(g.cost.fft_item[1][8], 8);
@@ -925,14 +1026,16 @@ bool load_tune_file() {
     if (fscanf(f, "device %255s", dev) == 1 && device_key() == dev) dev_ok = true;
     while (dev_ok && fscanf(f, "%127s %lf", key, &v) == 2) {
         const std::string k(key);
-        if (k == "direct") c.dir_unit = v, ++got;
+        if (k == "direct16_cell") c.dir_cell[0] = v, ++got;
+        else if (k == "direct32_cell") c.dir_cell[1] = v, ++got;
+        else if (k == "direct_stage") c.dir_stage = v, ++got;
         else if (k == "decode32") c.dec_unit[0] = v, ++got;
         else if (k == "decode64") c.dec_unit[1] = v, ++got;
         else if (k.rfind("fft32_n", 0) == 0) c.fft_item[0][ilog2i(atoi(k.c_str() + 7))] = v, ++got;
         else if (k.rfind("fft64_n", 0) == 0) c.fft_item[1][ilog2i(atoi(k.c_str() + 7))] = v, ++got;
     }
     fclose(f);
-    if (!dev_ok || got < 17) return false;
+    if (!dev_ok || got < kCostValues) return false;
     g.cost = c;
     return true;
 }
@@ -943,7 +1046,8 @@ void save_tune_file() {
     FILE *f = fopen(path, "w");
     if (!f) return;
     fprintf(f, "device %s\n", device_key().c_str());
-    fprintf(f, "direct %.9g\ndecode32 %.9g\ndecode64 %.9g\n", g.cost.dir_unit, g.cost.dec_unit[0], g.cost.dec_unit[1]);
+    fprintf(f, "direct16_cell %.9g\ndirect32_cell %.9g\ndirect_stage %.9g\ndecode32 %.9g\ndecode64 %.9g\n",
+            g.cost.dir_cell[0], g.cost.dir_cell[1], g.cost.dir_stage, g.cost.dec_unit[0], g.cost.dec_unit[1]);
     for (int nt = 16; nt <= kMaxN; nt *= 2) fprintf(f, "fft32_n%d %.9g\n", nt, g.cost.fft_item[0][ilog2i(nt)]);
     for (int nt = 16; nt <= kMaxN; nt *= 2) fprintf(f, "fft64_n%d %.9g\n", nt, g.cost.fft_item[1][ilog2i(nt)]);
     fclose(f);
@@ -1164,13 +1268,16 @@ int md_profile_reset(void) {
     return MD_OK;
 }
 
-int md_cost_model(double *dst, int *measured) {
+int md_cost_model(double *dst, int n, int *measured) {
     if (!dst || !measured) return fail(MD_ERR_ARG, "null pointer");
-    dst[0] = g.cost.dir_unit;
-    dst[1] = g.cost.dec_unit[0];
-    dst[2] = g.cost.dec_unit[1];
-    for (int q = 0; q < 7; ++q) dst[3 + q] = g.cost.fft_item[0][4 + q];
-    for (int q = 0; q < 7; ++q) dst[10 + q] = g.cost.fft_item[1][4 + q];
+    if (n < kCostValues) return fail(MD_ERR_ARG, "cost model needs %d values (n=%d)", kCostValues, n);
+    dst[0] = g.cost.dir_cell[0];
+    dst[1] = g.cost.dir_cell[1];
+    dst[2] = g.cost.dir_stage;
+    dst[3] = g.cost.dec_unit[0];
+    dst[4] = g.cost.dec_unit[1];
+    for (int q = 0; q < 7; ++q) dst[5 + q] = g.cost.fft_item[0][4 + q];
+    for (int q = 0; q < 7; ++q) dst[12 + q] = g.cost.fft_item[1][4 + q];
     *measured = g.cost_measured ? 1 : 0;
     return MD_OK;
 }

@@ -43,4 +43,4 @@ def test_cost_model_shape():
     assert sorted(cm["fft32_item"]) == [16, 32, 64, 128, 256, 512, 1024]
     assert sorted(cm["fft64_item"]) == [16, 32, 64, 128, 256, 512, 1024]
     assert all(v > 0 for v in cm["fft32_item"].values())
-    assert cm["direct_per_px_k_kpad"] > 0
+    assert cm["direct16_per_px_cell"] > 0 and cm["direct32_per_px_cell"] > 0 and cm["direct_per_staged_word"] > 0
