@@ -633,16 +633,20 @@ template <> struct DirT<true> {
     __device__ static V vmax(V a, V b) { return __builtin_elementwise_max(a, b); }
 };
 
+// One staged pixel: minus infinity outside the image, else the grey value
+// (complemented for erosion); a value outside [0, L-1] sets `bad`.  Branch
+// free: outside the image the load reads pixel 0 and its value is dropped,
+// so the loads of a staging pass are all in flight together.
 template <bool PACK>
 __device__ __forceinline__ int dir_pix(const JobDev &J, int gy, int gx, bool &bad) {
     const int neg = PACK ? kNeg16 : kNeg;
-    if (gy < 0 || gy >= J.H || gx < 0 || gx >= J.W) return neg;
-    int v = gld(J.img)[(size_t)gy * J.W + gx];
-    if ((unsigned)v >= (unsigned)J.L) {
-        bad = true;
-        v = v < 0 ? 0 : J.L - 1;
-    }
-    return J.op ? J.L - 1 - v : v;
+    const bool in = (unsigned)gy < (unsigned)J.H && (unsigned)gx < (unsigned)J.W;
+    const size_t idx = in ? (size_t)gy * J.W + gx : 0;
+    int v = gld(J.img)[idx];
+    bad |= in && (unsigned)v >= (unsigned)J.L;
+    v = min(max(v, 0), J.L - 1);
+    v = J.op ? J.L - 1 - v : v;
+    return in ? v : neg;
 }
 
 // 16 image words (this thread's 8 outputs plus the next 8 SE columns) and the
@@ -883,6 +887,225 @@ __global__ __launch_bounds__(kDirThreads) void k_direct(const JobDev *__restrict
         const int local = (int)(it - S.item0);
         const int byi = local / J.dir_bx, bxi = local - byi * J.dir_bx;
         direct_block<PACK, SEL>(J, byi * DirT<PACK>::BH, bxi * kDirBW, J.H, J.W, dyn_lds, &st->range_err);
+    }
+}
+
+// Packed direct window, register-blocked over output rows.  A block of
+// 256 threads covers kD16BH x kDirBW outputs as 2 x 2 waves of 8 x 8 lanes;
+// a lane owns 8 consecutive columns of kD16R packed output row pairs.  The
+// loop runs over 8- (or 4-) column steps of the SE, and inside a step over
+// SE row pairs (2s, 2s+1): output pair r reads LDS word row q+r+s (SE row 2s,
+// whole words) and the straddle of word rows q+r+s, q+r+s+1 (SE row 2s+1),
+// so the kD16R+1 word rows in registers slide down by one word row per SE row
+// pair -- one new word row (16 words) is read from LDS per 2 x kD16R x 64
+// packed add/max pairs.  The SE words (uniform across the wave) come through
+// scalar loads.  Per column step, only the SE row pairs with an active cell
+// in those columns are visited (sek_cols), so disk-shaped SEs skip their
+// empty corners.
+constexpr int kD16R = 2;
+constexpr int kD16BH = 32 * kD16R;
+
+template <int NS> struct D16 {
+    static constexpr int NW = NS == 8 ? 16 : 12;   // words read per word row (NS + 7 used)
+};
+
+template <int NW>
+__device__ __forceinline__ void d16_load(int (&w)[NW], const int32_t *p) {
+#pragma unroll
+    for (int u = 0; u < NW / 4; ++u) {
+        const int4 v = *(const int4 *)(p + 4 * u);
+        w[4 * u] = v.x;
+        w[4 * u + 1] = v.y;
+        w[4 * u + 2] = v.z;
+        w[4 * u + 3] = v.w;
+    }
+}
+
+// acc = max(acc, in[t + sj] + b[sj]) over the NS SE columns of one SE row;
+// all sums of a column before their maxima (a packed op that reads the result
+// of the instruction right before it costs a wait state)
+template <int NS>
+__device__ __forceinline__ void d16_row(s16x2 (&acc)[kDirRX], const s16x2 *in, const s16x2 (&b)[NS]) {
+#pragma unroll
+    for (int sj = 0; sj < NS; ++sj) {
+        s16x2 sum[kDirRX];
+#pragma unroll
+        for (int t = 0; t < kDirRX; ++t) sum[t] = in[t + sj] + b[sj];
+#pragma unroll
+        for (int t = 0; t < kDirRX; ++t) acc[t] = __builtin_elementwise_max(acc[t], sum[t]);
+    }
+}
+
+// One SE row pair (ODD) or the last, even SE row alone (!ODD) over the
+// thread's kD16R output pairs.  be / bo: SE rows 2s and 2s+1 at the step's
+// first column.
+template <int NS, bool ODD>
+__device__ __forceinline__ void d16_pair(s16x2 (&acc)[kD16R][kDirRX], const int (&win)[kD16R + 1][D16<NS>::NW],
+                                         const int32_t *be, const int32_t *bo) {
+    constexpr int NU = NS + kDirRX - 1;
+    const auto ce = cst(be);
+    s16x2 b[NS];
+#pragma unroll
+    for (int sj = 0; sj < NS; ++sj) b[sj] = __builtin_bit_cast(s16x2, ce[sj]);
+#pragma unroll
+    for (int r = 0; r < kD16R; ++r) {
+        s16x2 in[NU];
+#pragma unroll
+        for (int t = 0; t < NU; ++t) in[t] = __builtin_bit_cast(s16x2, win[r][t]);
+        d16_row<NS>(acc[r], in, b);
+    }
+    if constexpr (ODD) {
+        const auto co = cst(bo);
+#pragma unroll
+        for (int sj = 0; sj < NS; ++sj) b[sj] = __builtin_bit_cast(s16x2, co[sj]);
+#pragma unroll
+        for (int r = 0; r < kD16R; ++r) {
+            s16x2 in[NU];
+#pragma unroll
+            for (int t = 0; t < NU; ++t) in[t] = __builtin_bit_cast(s16x2, straddle(win[r][t], win[r + 1][t]));
+            d16_row<NS>(acc[r], in, b);
+        }
+    }
+}
+
+// SE row pairs s0..s1 of one column step.  trow: LDS word row q of the
+// thread at the step's first column; se: SE row 0 at that column.  Word row
+// q+s+kD16R+1 is fetched while pair s computes (one row past the staged
+// block at most, which the LDS allocation covers).
+template <int NS>
+__device__ __forceinline__ void d16_column(s16x2 (&acc)[kD16R][kDirRX], const int32_t *trow, int P,
+                                           const int32_t *se, int kpad, int k, int s0, int s1) {
+    constexpr int NW = D16<NS>::NW;
+    int win[kD16R + 1][NW];
+#pragma unroll
+    for (int r = 0; r <= kD16R; ++r) d16_load<NW>(win[r], trow + (s0 + r) * P);
+    const int sfull = min(s1, (k - 3) >> 1);   // pairs with both rows inside the SE
+    int s = s0;
+#pragma unroll 2
+    for (; s <= sfull; ++s) {
+        int nxt[NW];
+        d16_load<NW>(nxt, trow + (s + kD16R + 1) * P);
+        d16_pair<NS, true>(acc, win, se + 2 * s * kpad, se + (2 * s + 1) * kpad);
+#pragma unroll
+        for (int r = 0; r < kD16R; ++r)
+#pragma unroll
+            for (int t = 0; t < NW; ++t) win[r][t] = win[r + 1][t];
+#pragma unroll
+        for (int t = 0; t < NW; ++t) win[kD16R][t] = nxt[t];
+    }
+    if (s <= s1) d16_pair<NS, false>(acc, win, se + 2 * s * kpad, nullptr);   // s = (k-1)/2: SE row k-1
+}
+
+// LDS words of one packed block: word rows of image rows 2p, 2p+1 (low,
+// high half), one spare word row for the prefetch, pitch P = kDirBW + kpad + 4.
+__host__ __device__ constexpr int d16_pitch(int kpad) { return kDirBW + kpad + 4; }
+__host__ __device__ constexpr int d16_rows(int k) { return (kD16BH + k - 1) / 2 + 1; }
+
+__device__ __forceinline__ void direct16_block(const JobDev &J, int by0, int bx0, int32_t *tile,
+                                               unsigned int *range_err) {
+    const int k = J.k, rad = (k - 1) >> 1, kpad = J.kpad;
+    const int P = d16_pitch(kpad);
+    const int TH = kD16BH + k - 1;                 // image rows the block reads (even: k is odd)
+    const int TC = kDirBW + k - 1;                 // image columns the block reads
+    // staging: the 64 lanes of a wave cover consecutive columns (4 x 64 per
+    // row hold the P <= 260 words a row needs: columns past kDirBW + kpad are
+    // never read), the waves take 4 consecutive rows each per pass.  The 16
+    // loads of a pass are unconditional (pixel 0 stands in outside the image
+    // and outside the block) and issued together before any of them is used.
+    const int lane = threadIdx.x & 63;
+    const auto img = gld(J.img);
+    const int H = J.H, W = J.W, L = J.L, op = J.op;
+    int badv = 0;
+    for (int a0 = (threadIdx.x >> 6) * 4; a0 < TH; a0 += kDirThreads / 16) {
+        int raw[4][4];
+        bool in[4][4];
+#pragma unroll
+        for (int h = 0; h < 4; ++h) {
+            const int gy = by0 - rad + a0 + h;
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int c = lane + 64 * u, gx = bx0 - rad + c;
+                in[h][u] = a0 + h < TH && c < TC && (unsigned)gy < (unsigned)H && (unsigned)gx < (unsigned)W;
+                raw[h][u] = img[in[h][u] ? (size_t)gy * W + gx : 0];
+            }
+        }
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int h = 0; h < 4; ++h) {
+            const int a = a0 + h;
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int c = lane + 64 * u;
+                int v = raw[h][u];
+                badv |= (int)(in[h][u] && (unsigned)v >= (unsigned)L);
+                v = min(max(v, 0), L - 1);
+                v = op ? L - 1 - v : v;
+                if (a < TH && c < P) ((short *)tile)[2 * ((a >> 1) * P + c) + (a & 1)] = (short)(in[h][u] ? v : kNeg16);
+            }
+        }
+    }
+    const bool bad = badv != 0;
+    if (bad && range_err) atomicOr(range_err, 1u);
+    __syncthreads();
+    const int wv = threadIdx.x >> 6, wx = wv & 1, wy = wv >> 1;
+    const int cg = lane & 7, rg = lane >> 3;
+    const int lx0 = wx * 64 + cg * kDirRX;         // first output column of the lane
+    const int q = wy * 8 * kD16R + rg * kD16R;     // LDS word row = first output row / 2
+    // a wave whose outputs all lie outside the image skips the window
+    if (bx0 + wx * 64 < J.W && by0 + wy * 16 * kD16R < J.H) {
+        s16x2 acc[kD16R][kDirRX];
+        const int neg = (int)(((unsigned)kNeg16 & 0xffffu) * 0x10001u);
+#pragma unroll
+        for (int r = 0; r < kD16R; ++r)
+#pragma unroll
+            for (int t = 0; t < kDirRX; ++t) acc[r][t] = __builtin_bit_cast(s16x2, neg);
+        const auto cols = cst(J.sek_cols);
+        const int nc4 = kpad >> 2;
+        const int32_t *base = tile + q * P + lx0;
+        for (int g4 = 0; g4 < nc4;) {
+            const int2 a = make_int2(cols[2 * g4], cols[2 * g4 + 1]);
+            if (g4 + 1 < nc4) {
+                const int2 b = make_int2(cols[2 * g4 + 2], cols[2 * g4 + 3]);
+                if (a.x <= a.y && b.x <= b.y) {
+                    d16_column<8>(acc, base + 4 * g4, P, J.sek16 + 4 * g4, kpad, k, min(a.x, b.x), max(a.y, b.y));
+                    g4 += 2;
+                    continue;
+                }
+            }
+            if (a.x <= a.y) d16_column<4>(acc, base + 4 * g4, P, J.sek16 + 4 * g4, kpad, k, a.x, a.y);
+            ++g4;
+        }
+        const int L = J.L, W = J.W;
+#pragma unroll
+        for (int r = 0; r < kD16R; ++r) {
+#pragma unroll
+            for (int hh = 0; hh < 2; ++hh) {
+                const int gy = by0 + 2 * (q + r) + hh;
+                if (gy >= J.H) continue;
+#pragma unroll
+                for (int t = 0; t < kDirRX; ++t) {
+                    const int gx = bx0 + lx0 + t;
+                    if (gx >= W) continue;
+                    const int v = hh ? acc[r][t].y : acc[r][t].x;
+                    const int d = v < 0 ? 0 : v;
+                    gst(J.out)[(size_t)gy * W + gx] = J.op ? (L - 1 - d) : d;
+                }
+            }
+        }
+    }
+    __syncthreads();   // the LDS block is restaged by the next item
+}
+
+__global__ __launch_bounds__(kDirThreads) void k_direct16(const JobDev *__restrict__ jobs,
+                                                          const Seg *__restrict__ segs, int nseg,
+                                                          long long nitems, StatsDev *st) {
+    extern __shared__ int32_t dyn_lds[];
+    for (long long it = blockIdx.x; it < nitems; it += gridDim.x) {
+        const Seg S = segs[find_seg(segs, nseg, it)];
+        const JobDev &J = jobs[S.job];
+        const int local = (int)(it - S.item0);
+        const int byi = local / J.dir_bx, bxi = local - byi * J.dir_bx;
+        direct16_block(J, byi * kD16BH, bxi * kDirBW, dyn_lds, &st->range_err);
     }
 }
 
@@ -1193,10 +1416,11 @@ int decode_group_variant(int bins, int dbl) { return decode_variant(bins, dbl); 
 
 int dec_pitch(int nr) { return ((nr / 2 + 1) + 31) / 32 * 32; }
 
-int direct_block_rows(int pack) { return pack ? DirT<true>::BH : DirT<false>::BH; }
+int direct_block_rows(int pack) { return pack ? kD16BH : DirT<false>::BH; }
 
 size_t direct_lds_bytes(int k, int kpad, int pack, int sel) {
-    const int rows = pack ? (DirT<true>::BH + k) / 2 : DirT<false>::BH + k - 1;
+    if (pack) return (size_t)d16_rows(k) * d16_pitch(kpad) * sizeof(int32_t);
+    const int rows = DirT<false>::BH + k - 1;
     return ((size_t)rows * (kDirBW + kpad) + (sel ? (size_t)k * kpad : 0) + (size_t)((2 * k + 3) & ~3) + 16) *
            sizeof(int32_t);
 }
@@ -1204,8 +1428,7 @@ size_t direct_lds_bytes(int k, int kpad, int pack, int sel) {
 hipError_t launch_direct(int pack, int sel, const JobDev *jobs, const Seg *segs, int nseg, long long nitems,
                          int grid, size_t lds_bytes, StatsDev *st, hipStream_t s) {
     if (nitems <= 0) return hipSuccess;
-    if (pack && sel) k_direct<true, true><<<grid, kDirThreads, lds_bytes, s>>>(jobs, segs, nseg, nitems, st);
-    else if (pack) k_direct<true, false><<<grid, kDirThreads, lds_bytes, s>>>(jobs, segs, nseg, nitems, st);
+    if (pack) k_direct16<<<grid, kDirThreads, lds_bytes, s>>>(jobs, segs, nseg, nitems, st);
     else if (sel) k_direct<false, true><<<grid, kDirThreads, lds_bytes, s>>>(jobs, segs, nseg, nitems, st);
     else k_direct<false, false><<<grid, kDirThreads, lds_bytes, s>>>(jobs, segs, nseg, nitems, st);
     return hipGetLastError();

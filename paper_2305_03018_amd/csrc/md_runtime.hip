@@ -93,7 +93,7 @@ struct SESpec {
 };
 
 struct DirSE {
-    DevBuf sek, sek16, rows;
+    DevBuf sek, sek16, rows, cols;
     int kpad = 0;
 };
 
@@ -297,8 +297,53 @@ struct SEData {
 // active span from its first column rounded down to 8, in 8-column steps;
 // the packed form takes SE rows in pairs over the union of their spans, with
 // a 4-column final step where it suffices.
+// For each 4-column group g of the SE in the direct window's correlation
+// order (row i, column j <-> SE cell (k-1-i, k-1-j)): the first and last
+// row pair (2s, 2s+1) with an active cell in columns 4g..4g+3 (first > last:
+// none).  `cols` holds 2 * kpad/4 values.
+void dir_col_pairs(const SEData &se, std::vector<int32_t> &cols) {
+    const int k = se.k, nc4 = (int)cols.size() / 2;
+    for (int g4 = 0; g4 < nc4; ++g4) {
+        int lo = k, hi = -1;
+        for (int i = 0; i < k; ++i)
+            for (int j = 4 * g4; j < std::min(k, 4 * g4 + 4); ++j)
+                if (se.mask[(size_t)(k - 1 - i) * k + (k - 1 - j)]) {
+                    lo = std::min(lo, i / 2);
+                    hi = std::max(hi, i / 2);
+                }
+        cols[2 * g4] = lo;
+        cols[2 * g4 + 1] = hi;
+    }
+}
+
+// SE cells per output pixel that the direct window steps through.  Packed
+// form: 8-column steps where two adjacent 4-column groups are both active,
+// else 4-column steps, each over its range of SE row pairs (the last row of
+// an odd SE alone).  32-bit form: each row's active span from its first
+// column rounded down to 8, in 8-column steps.
 void dir_work(SEData &se) {
-    const int k = se.k;
+    const int k = se.k, kpad = (k + kDirRX - 1) / kDirRX * kDirRX;
+    std::vector<int32_t> cols((size_t)2 * (kpad / 4));
+    dir_col_pairs(se, cols);
+    const int nc4 = kpad / 4, last = (k - 1) / 2, sfull_max = (k - 3) / 2;
+    double e16 = 0;
+    auto column = [&](int ns, int s0, int s1) {
+        const int nfull = std::max(0, std::min(s1, sfull_max) - s0 + 1);
+        e16 += (double)ns * (2 * nfull + (s1 == last && 2 * last + 1 == k ? 1 : 0));
+    };
+    for (int g4 = 0; g4 < nc4;) {
+        const int alo = cols[2 * g4], ahi = cols[2 * g4 + 1];
+        if (g4 + 1 < nc4) {
+            const int blo = cols[2 * g4 + 2], bhi = cols[2 * g4 + 3];
+            if (alo <= ahi && blo <= bhi) {
+                column(8, std::min(alo, blo), std::max(ahi, bhi));
+                g4 += 2;
+                continue;
+            }
+        }
+        if (alo <= ahi) column(4, alo, ahi);
+        ++g4;
+    }
     std::vector<int> lo(k, k), hi(k, -1);
     for (int i = 0; i < k; ++i)
         for (int j = 0; j < k; ++j)
@@ -306,27 +351,11 @@ void dir_work(SEData &se) {
                 lo[i] = std::min(lo[i], j);
                 hi[i] = std::max(hi[i], j);
             }
-    auto steps = [](int a, int b, bool tail4) -> double {
-        if (a > b) return 0;
-        int jb = a & ~(kDirRX - 1);
-        double c = 0;
-        for (; jb + kDirRX - 1 <= b; jb += kDirRX) c += kDirRX;
-        if (jb <= b) c += (tail4 && b - jb < kDirRX / 2) ? kDirRX / 2 : kDirRX;
-        return c;
-    };
-    double e16 = 0, e32 = 0;
-    for (int i = 0; i < k; ++i) e32 += steps(lo[i], hi[i], false);
-    for (int i = 0; i < k; i += 2) {
-        if (i + 1 < k) {
-            int a = lo[i], b = hi[i];
-            if (lo[i + 1] <= hi[i + 1]) {
-                a = std::min(a, lo[i + 1]);
-                b = std::max(b, hi[i + 1]);
-            }
-            e16 += 2 * steps(a, b, true);
-        } else {
-            e16 += steps(lo[i], hi[i], false);
-        }
+    double e32 = 0;
+    for (int i = 0; i < k; ++i) {
+        if (lo[i] > hi[i]) continue;
+        const int jb = lo[i] & ~(kDirRX - 1);
+        e32 += (double)kDirRX * ((hi[i] - jb) / kDirRX + 1);
     }
     se.dir_cells[0] = e16;
     se.dir_cells[1] = e32;
@@ -447,9 +476,14 @@ int get_dirse(const SEData &se, DirSE **out) {
         rows[2 * i] = lo;
         rows[2 * i + 1] = hi;
     }
+    // per 4-column group: the SE row pairs with an active cell there
+    std::vector<int32_t> cols((size_t)2 * (d->kpad / 4));
+    dir_col_pairs(se, cols);
     MD_TRY(d->sek.ensure(h.size() * sizeof(int32_t)));
     MD_TRY(d->sek16.ensure(h16.size() * sizeof(int32_t)));
     MD_TRY(d->rows.ensure(rows.size() * sizeof(int32_t)));
+    MD_TRY(d->cols.ensure(cols.size() * sizeof(int32_t)));
+    MD_HIP(hipMemcpy(d->cols.p, cols.data(), cols.size() * sizeof(int32_t), hipMemcpyHostToDevice));
     MD_HIP(hipMemcpy(d->sek.p, h.data(), h.size() * sizeof(int32_t), hipMemcpyHostToDevice));
     MD_HIP(hipMemcpy(d->sek16.p, h16.data(), h16.size() * sizeof(int32_t), hipMemcpyHostToDevice));
     MD_HIP(hipMemcpy(d->rows.p, rows.data(), rows.size() * sizeof(int32_t), hipMemcpyHostToDevice));
@@ -613,11 +647,14 @@ int build_exec(const md_job *jobs, int n, const std::vector<SEData> &ses, Exec &
             d.sek = (const int32_t *)ds->sek.p;
             d.sek16 = (const int32_t *)ds->sek16.p;
             d.sek_rows = (const int32_t *)ds->rows.p;
+            d.sek_cols = (const int32_t *)ds->cols.p;
             d.kpad = ds->kpad;
             d.dir_pack = (long long)(j.L - 1) + ses[i].maxoff <= 16383 ? 1 : 0;
             d.dir_bx = (j.W + kDirBW - 1) / kDirBW;
             d.dir_by = (j.H + direct_block_rows(d.dir_pack) - 1) / direct_block_rows(d.dir_pack);
-            const int sel = direct_lds_bytes(j.k, ds->kpad, d.dir_pack, 1) <= kLdsBytes ? 1 : 0;
+            // the packed form reads the SE through scalar loads; the 32-bit form
+            // stages it in LDS when it fits
+            const int sel = !d.dir_pack && direct_lds_bytes(j.k, ds->kpad, 0, 1) <= kLdsBytes ? 1 : 0;
             dir_sel[i] = sel;
             dir_lds[i] = direct_lds_bytes(j.k, ds->kpad, d.dir_pack, sel);
             if (dir_lds[i] > kLdsBytes) return fail(MD_ERR_UNSUPPORTED, "direct window for k=%d exceeds the LDS", j.k);
@@ -661,9 +698,17 @@ int build_exec(const md_job *jobs, int n, const std::vector<SEData> &ses, Exec &
                 ex.fb_classes.push_back(p.nt64);
         }
     }
-    // direct groups: one segment per direct job
-    for (int i = 0; i < n; ++i) {
-        if (ex.plans[i].path != kPathDirect) continue;
+    // direct groups: one segment per direct job, in decreasing cost per
+    // block, so that the persistent blocks end on the cheapest items
+    std::vector<int> dir_order;
+    for (int i = 0; i < n; ++i)
+        if (ex.plans[i].path == kPathDirect) dir_order.push_back(i);
+    auto block_cost = [&](int i) {
+        const int pk = ex.jobs_h[i].dir_pack;
+        return dir_staged(jobs[i].k, pk) * g.cost.dir_stage + ses[i].dir_cells[pk ? 0 : 1] * g.cost.dir_cell[pk ? 0 : 1];
+    };
+    std::stable_sort(dir_order.begin(), dir_order.end(), [&](int a, int b) { return block_cost(a) > block_cost(b); });
+    for (int i : dir_order) {
         const int pack = ex.jobs_h[i].dir_pack, sel = dir_sel[i];
         const int per_cu = std::max(1, std::min(2048 / kDirThreads, (int)(kLdsBytes / dir_lds[i])));
         Group *grp = nullptr;
