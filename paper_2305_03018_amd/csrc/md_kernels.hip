@@ -1052,13 +1052,14 @@ __device__ __forceinline__ void direct16_block(const JobDev &J, int by0, int bx0
     const int lx0 = wx * 64 + cg * kDirRX;         // first output column of the lane
     const int q = wy * 8 * kD16R + rg * kD16R;     // LDS word row = first output row / 2
     // a wave whose outputs all lie outside the image skips the window
-    if (bx0 + wx * 64 < J.W && by0 + wy * 16 * kD16R < J.H) {
-        s16x2 acc[kD16R][kDirRX];
-        const int neg = (int)(((unsigned)kNeg16 & 0xffffu) * 0x10001u);
+    const bool live = bx0 + wx * 64 < J.W && by0 + wy * 16 * kD16R < J.H;
+    s16x2 acc[kD16R][kDirRX];
+    const int neg = (int)(((unsigned)kNeg16 & 0xffffu) * 0x10001u);
 #pragma unroll
-        for (int r = 0; r < kD16R; ++r)
+    for (int r = 0; r < kD16R; ++r)
 #pragma unroll
-            for (int t = 0; t < kDirRX; ++t) acc[r][t] = __builtin_bit_cast(s16x2, neg);
+        for (int t = 0; t < kDirRX; ++t) acc[r][t] = __builtin_bit_cast(s16x2, neg);
+    if (live) {
         const auto cols = cst(J.sek_cols);
         const int nc4 = kpad >> 2;
         const int32_t *base = tile + q * P + lx0;
@@ -1075,21 +1076,42 @@ __device__ __forceinline__ void direct16_block(const JobDev &J, int by0, int bx0
             if (a.x <= a.y) d16_column<4>(acc, base + 4 * g4, P, J.sek16 + 4 * g4, kpad, k, a.x, a.y);
             ++g4;
         }
-        const int L = J.L, W = J.W;
+    }
+    // results (clamped at 0: a negative maximum is an empty window) go to LDS
+    // as 16-bit values, one row of 8 per b128 write, once every wave has
+    // finished reading the image block
+    __syncthreads();
+    if (live) {
+        uint16_t *ob = (uint16_t *)tile;
 #pragma unroll
         for (int r = 0; r < kD16R; ++r) {
+            s16x2 c[kDirRX];
+#pragma unroll
+            for (int t = 0; t < kDirRX; ++t) c[t] = __builtin_elementwise_max(acc[r][t], (s16x2){0, 0});
 #pragma unroll
             for (int hh = 0; hh < 2; ++hh) {
-                const int gy = by0 + 2 * (q + r) + hh;
-                if (gy >= J.H) continue;
-#pragma unroll
-                for (int t = 0; t < kDirRX; ++t) {
-                    const int gx = bx0 + lx0 + t;
-                    if (gx >= W) continue;
-                    const int v = hh ? acc[r][t].y : acc[r][t].x;
-                    const int d = v < 0 ? 0 : v;
-                    gst(J.out)[(size_t)gy * W + gx] = J.op ? (L - 1 - d) : d;
-                }
+                int4 w;
+                const unsigned sel = hh ? 0x07060302u : 0x05040100u;   // high or low halves of two words
+                w.x = (int)__builtin_amdgcn_perm(__builtin_bit_cast(unsigned, c[1]), __builtin_bit_cast(unsigned, c[0]), sel);
+                w.y = (int)__builtin_amdgcn_perm(__builtin_bit_cast(unsigned, c[3]), __builtin_bit_cast(unsigned, c[2]), sel);
+                w.z = (int)__builtin_amdgcn_perm(__builtin_bit_cast(unsigned, c[5]), __builtin_bit_cast(unsigned, c[4]), sel);
+                w.w = (int)__builtin_amdgcn_perm(__builtin_bit_cast(unsigned, c[7]), __builtin_bit_cast(unsigned, c[6]), sel);
+                *(int4 *)(ob + (2 * (q + r) + hh) * kDirBW + lx0) = w;
+            }
+        }
+    }
+    __syncthreads();
+    // rows of the block to global memory, 64 consecutive columns per wave store
+    {
+        const uint16_t *ob = (const uint16_t *)tile;
+        const int L = J.L, W = J.W, op = J.op;
+        const int cx = threadIdx.x & (kDirBW - 1), gx = bx0 + cx;
+        if (gx < W) {
+            for (int y = threadIdx.x / kDirBW; y < kD16BH; y += kDirThreads / kDirBW) {
+                const int gy = by0 + y;
+                if (gy >= J.H) break;
+                const int d = ob[y * kDirBW + cx];
+                gst(J.out)[(size_t)gy * W + gx] = op ? (L - 1 - d) : d;
             }
         }
     }

@@ -133,8 +133,7 @@ struct Exec {
     hipEvent_t copy_done = nullptr;
     bool copy_pending = false;
     // direct-window launches, one per (element form, SE in LDS, blocks per CU
-    // allowed by the LDS footprint): small windows are not held to the
-    // occupancy of the largest one
+    // allowed by the LDS footprint, capped at 4)
     std::vector<Group> direct;
     std::vector<Wave> waves;
     DevBuf segbuf, ybuf, flags, list, slots;
@@ -710,7 +709,10 @@ int build_exec(const md_job *jobs, int n, const std::vector<SEData> &ses, Exec &
     std::stable_sort(dir_order.begin(), dir_order.end(), [&](int a, int b) { return block_cost(a) > block_cost(b); });
     for (int i : dir_order) {
         const int pack = ex.jobs_h[i].dir_pack, sel = dir_sel[i];
-        const int per_cu = std::max(1, std::min(2048 / kDirThreads, (int)(kLdsBytes / dir_lds[i])));
+        // blocks per CU the job's LDS footprint allows; footprints that allow 4
+        // or more share one launch at 4 (16 waves per CU keep the VALU busy),
+        // so the batch drains through one tail instead of one per class
+        const int per_cu = std::max(1, std::min(4, (int)(kLdsBytes / dir_lds[i])));
         Group *grp = nullptr;
         for (auto &gq : ex.direct)
             if (gq.pack == pack && gq.sel == sel && gq.big == per_cu) grp = &gq;
