@@ -74,22 +74,60 @@ def timed_steps(md, torch, stream, args_list, outs, steps, warmup, **opts):
     return t0.elapsed_time(t1) / steps
 
 
-def roofline_for(stage, prof):
+def kernel_of(stage):
+    """HIP kernel that a profiled stage launches."""
+    if stage == "direct16":
+        return "k_direct16"
+    if stage == "direct32":
+        return "k_direct<false>"
+    if stage.startswith("fft"):
+        prec, n = ("float" if stage.startswith("fft32") else "double"), int(stage.split("_n")[1])
+        big = n > (128 if prec == "float" else 64)
+        return f"k_fft{'_big' if big else ''}<{prec}, {n}>"
+    if stage.startswith("decode"):
+        return f"k_decode<{'float' if stage == 'decode32' else 'double'}>"
+    if stage.startswith("recompute64"):
+        return f"k_fallback<{stage.split('_n')[1]}>"
+    return stage
+
+
+def measured_traffic(kernel, workload):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    record (FETCH_SIZE and WRITE_SIZE, scaled by the copy-probe factors), or
+    None when there is no record or the kernel source changed since it was
+    taken."""
+    import hashlib
+
+    path = os.path.join(ROOT, "profiles", f"{kernel}_{workload}_traffic.txt")
+    if not os.path.exists(path):
+        return None
+    rec = {}
+    for line in open(path):
+        line = line.strip()
+        if line and not line.startswith("#"):
+            key, val = line.split(None, 1)
+            rec[key] = val
+    src = os.path.join(ROOT, rec["source"])
+    if not os.path.exists(src) or hashlib.sha256(open(src, "rb").read()).hexdigest() != rec["source_sha256"]:
+        return None
+    return 1024.0 * (float(rec["fetch_kib"]) * float(rec["fetch_scale"]) +
+                     float(rec["write_kib"]) * float(rec["write_scale"]))
+
+
+def roofline_for(stage, prof, workload):
     rec = prof[stage]
     per_launch_ms = rec["ms"] / rec["launches"]
     ops = rec["alg_ops"] / rec["launches"]
+    achieved = ops / (per_launch_ms * 1e-3) / 1e12
+    kernel = kernel_of(stage)
+    base = {"achieved": achieved, "traffic": measured_traffic(kernel, workload), "kernel": kernel,
+            "stage": stage, "avg_launch_ms": per_launch_ms,
+            "alg_bytes_per_launch": rec["alg_bytes"] / rec["launches"]}
     if stage.startswith("direct"):
         peak = INT16X2_ALU_TOPS if stage == "direct16" else INT32_ALU_TOPS
-        achieved = ops / (per_launch_ms * 1e-3) / 1e12
-        return {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TOP/s",
-                "frac": achieved / peak, "traffic": None,
-                "kernel": "k_direct<true>" if stage == "direct16" else "k_direct<false>",
-                "stage": stage, "avg_launch_ms": per_launch_ms}
+        return {"bound": "alu", "peak": peak, "unit": "TOP/s", "frac": achieved / peak, **base}
     peak = FP64_VECTOR_TFLOPS if "64" in stage else FP32_VECTOR_TFLOPS
-    achieved = ops / (per_launch_ms * 1e-3) / 1e12
-    kernel = "k_fft" if stage.startswith("fft") else ("k_decode" if stage.startswith("decode") else stage)
-    return {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
-            "traffic": None, "kernel": kernel, "stage": stage, "avg_launch_ms": per_launch_ms}
+    return {"bound": "alu", "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak, **base}
 
 
 def cpu_baseline(jobs, budget_s):
@@ -118,6 +156,8 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=12.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-compare", action="store_true")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="first run one plain device copy of 256 MiB (a known-size reference for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the path shards by tiles/images "
@@ -129,6 +169,13 @@ def main():
     import paper_2305_03018_amd as md
 
     dev = torch.device("cuda:0")
+    if args.copy_probe:
+        src = torch.arange(64 << 20, dtype=torch.int32, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"bench: copy probe {src.numel() * 4} bytes read, {dst.numel() * 4} bytes written")
+        del src, dst
     jobs = build_workload(args.workload)
     total_px = sum(j.img.size for j in jobs)
     log(f"bench: workload {args.workload}: {len(jobs)} jobs, {total_px / 1e6:.2f} Mpx")
@@ -173,7 +220,7 @@ def main():
         md.profile_reset()
         log(f"bench: profile {json.dumps(prof)}")
     dominant = max(prof, key=lambda k: prof[k]["ms"])
-    roof = roofline_for(dominant, prof)
+    roof = roofline_for(dominant, prof, args.workload)
     value = total_px / (res["headline_ms"] * 1e-3) / 1e6
     line = {
         "metric": "exact dilated Mpixels/s, batched FP32+fallback vs FP64 FFT path, 1 MI355X",

@@ -1,0 +1,425 @@
+// Direct max-plus window kernels for gfx950 (the classical form of the
+// dilation, Eq. (6new); erosion by the complement duality of Sec. 2.1): the
+// path a measured cost model picks over the transform path when the SE is
+// small relative to the tonal range.
+#include "md_device.h"
+
+namespace md {
+namespace {
+
+// Direct max-plus window (the classical form of Eq. (6new)).  The image
+// block plus halo is staged in LDS with "minus infinity" outside the image;
+// the SE is held in correlation order (reflected for dilation) with minus
+// infinity on masked cells, so the inner loop is branch-free:
+// acc = max(acc, in + b).  Erosion runs on the complement L-1-f with the
+// unreflected SE and complements the result (Sec. 2.1).
+//
+// Two element formats: two 16-bit lanes per 32-bit word holding vertically
+// adjacent image rows, so one packed add and one packed max advance two
+// outputs (k_direct16, used when every reachable sum fits: values and offsets
+// <= 16383 with minus infinity = -16384, so sums stay within [-32768,
+// 16383]), and plain int32 (k_direct32) for wider tonal ranges.
+typedef short s16x2 __attribute__((ext_vector_type(2)));
+constexpr int kNeg16 = -16384;
+
+// high 16 bits of lo-word, low 16 bits of hi-word: the packed pair of image
+// rows (2p+1, 2p+2) from word rows p and p+1
+__device__ __forceinline__ int straddle(int lo, int hi) {
+    return (int)__builtin_amdgcn_alignbit((unsigned)hi, (unsigned)lo, 16u);
+}
+
+// Stages image rows [by0 - rad, by0 - rad + TH) x columns [bx0 - rad,
+// bx0 - rad + TC) into LDS (columns up to `pitch`, minus infinity outside the
+// image and past TC), complemented for erosion.  The 64 lanes of a wave cover
+// consecutive columns (4 x 64 per row, pitch <= 256 + 4: words past 256 are
+// never read), the waves take 4 consecutive rows each per pass.  The 16 loads
+// of a pass are unconditional (pixel 0 stands in outside the image and the
+// block) and issued together before any of them is used.  PACK: LDS word
+// (p, c) holds image rows 2p (low half) and 2p+1 (high half).  Returns
+// non-zero if an in-image value lies outside [0, L-1].
+template <bool PACK>
+__device__ __forceinline__ int dir_stage(const JobDev &J, int by0, int bx0, int rad, int TH, int TC, int pitch,
+                                         int32_t *tile) {
+    const int lane = threadIdx.x & 63;
+    const auto img = gld(J.img);
+    const int H = J.H, W = J.W, L = J.L, op = J.op;
+    const int neg = PACK ? kNeg16 : kNeg;
+    int badv = 0;
+    for (int a0 = (threadIdx.x >> 6) * 4; a0 < TH; a0 += kDirThreads / 16) {
+        int raw[4][4];
+        bool in[4][4];
+#pragma unroll
+        for (int h = 0; h < 4; ++h) {
+            const int gy = by0 - rad + a0 + h;
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int c = lane + 64 * u, gx = bx0 - rad + c;
+                in[h][u] = a0 + h < TH && c < TC && (unsigned)gy < (unsigned)H && (unsigned)gx < (unsigned)W;
+                raw[h][u] = img[in[h][u] ? (size_t)gy * W + gx : 0];
+            }
+        }
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int h = 0; h < 4; ++h) {
+            const int a = a0 + h;
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int c = lane + 64 * u;
+                int v = raw[h][u];
+                badv |= (int)(in[h][u] && (unsigned)v >= (unsigned)L);
+                v = min(max(v, 0), L - 1);
+                v = op ? L - 1 - v : v;
+                v = in[h][u] ? v : neg;
+                if (a < TH && c < pitch) {
+                    if (PACK) ((short *)tile)[2 * ((a >> 1) * pitch + c) + (a & 1)] = (short)v;
+                    else tile[a * pitch + c] = v;
+                }
+            }
+        }
+    }
+    return badv;
+}
+
+// ---- 32-bit form: 128 x 16 outputs per 256-thread block, 8 consecutive
+// outputs of one row per thread, SE rows one at a time over their active
+// column span in 8-column steps ----
+
+// 16 image words (this thread's 8 outputs plus the next 8 SE columns) and the
+// 8 SE offsets of one 8-cell step
+struct DirBuf {
+    int4 w0, w1, w2, w3, b0, b1;
+};
+
+// SEL: the SE offsets are staged in LDS (else read with scalar loads from
+// global memory, for SEs too large to share the LDS with the image block)
+template <bool SEL>
+__device__ __forceinline__ void dir_load(DirBuf &B, const int32_t *trow, const int32_t *brow, int jb) {
+    B.w0 = *(const int4 *)(trow + jb);
+    B.w1 = *(const int4 *)(trow + jb + 4);
+    B.w2 = *(const int4 *)(trow + jb + 8);
+    B.w3 = *(const int4 *)(trow + jb + 12);
+    if constexpr (SEL) {
+        B.b0 = *(const int4 *)(brow + jb);
+        B.b1 = *(const int4 *)(brow + jb + 4);
+    } else {
+        const auto c = cst(brow + jb);
+        B.b0 = make_int4(c[0], c[1], c[2], c[3]);
+        B.b1 = make_int4(c[4], c[5], c[6], c[7]);
+    }
+}
+
+__device__ __forceinline__ void dir_step(int (&acc)[kDirRX], const DirBuf &B) {
+    const int in[2 * kDirRX] = {B.w0.x, B.w0.y, B.w0.z, B.w0.w, B.w1.x, B.w1.y, B.w1.z, B.w1.w,
+                                B.w2.x, B.w2.y, B.w2.z, B.w2.w, B.w3.x, B.w3.y, B.w3.z, B.w3.w};
+    const int b[kDirRX] = {B.b0.x, B.b0.y, B.b0.z, B.b0.w, B.b1.x, B.b1.y, B.b1.z, B.b1.w};
+#pragma unroll
+    for (int sj = 0; sj < kDirRX; ++sj)
+#pragma unroll
+        for (int t = 0; t < kDirRX; ++t) acc[t] = max(acc[t], in[t + sj] + b[sj]);
+}
+
+// One SE row over this thread's outputs: 8-cell steps from the row's first to
+// its last active column, two register buffers in ping-pong (the next step's
+// LDS words and offsets are in flight while the current step computes).  The
+// prefetch may read up to 16 words past the active span, which the padding of
+// the LDS block and of the SE arrays keeps in bounds (those values are never
+// used).
+template <bool SEL>
+__device__ __forceinline__ void dir_row(int (&acc)[kDirRX], const int32_t *trow, const int32_t *brow, int jb0,
+                                        int jhi) {
+    DirBuf A, B;
+    dir_load<SEL>(A, trow, brow, jb0);
+    for (int jb = jb0;; jb += 2 * kDirRX) {
+        dir_load<SEL>(B, trow, brow, jb + kDirRX);
+        __builtin_amdgcn_sched_barrier(0);
+        dir_step(acc, A);
+        __builtin_amdgcn_sched_barrier(0);
+        if (jb + kDirRX > jhi) break;
+        dir_load<SEL>(A, trow, brow, jb + 2 * kDirRX);
+        __builtin_amdgcn_sched_barrier(0);
+        dir_step(acc, B);
+        __builtin_amdgcn_sched_barrier(0);
+        if (jb + 2 * kDirRX > jhi) break;
+    }
+}
+
+// LDS of one 32-bit block: the image words (pitch kDirBW + kpad), each SE
+// row's [first, last] active column, then (SEL) the SE offsets in correlation
+// order (k rows of kpad words).
+template <bool SEL>
+__device__ __forceinline__ void direct32_block(const JobDev &J, int by0, int bx0, int32_t *tile,
+                                               unsigned int *range_err) {
+    const int k = J.k, rad = (k - 1) >> 1, kpad = J.kpad;
+    const int TWD = kDirBW + kpad;
+    const int TH = kDirBH + k - 1;
+    int32_t *rowL = tile + TH * TWD;
+    int32_t *seL = rowL + ((2 * k + 3) & ~3);        // 16-byte aligned for the b128 reads
+    if (SEL)
+        for (int q = threadIdx.x; q < k * kpad; q += kDirThreads) seL[q] = gld(J.sek)[q];
+    for (int q = threadIdx.x; q < 2 * k; q += kDirThreads) rowL[q] = gld(J.sek_rows)[q];
+    const int bad = dir_stage<false>(J, by0, bx0, rad, TH, kDirBW + k - 1, TWD, tile);
+    if (bad && range_err) atomicOr(range_err, 1u);
+    __syncthreads();
+    const int trow0 = threadIdx.x / (kDirBW / kDirRX);
+    const int lx0 = (threadIdx.x % (kDirBW / kDirRX)) * kDirRX;
+    int acc[kDirRX];
+#pragma unroll
+    for (int t = 0; t < kDirRX; ++t) acc[t] = kNeg;
+    const int32_t *sebase = SEL ? seL : J.sek;
+    for (int i = 0; i < k; ++i) {
+        const int jlo = rowL[2 * i], jhi = rowL[2 * i + 1];
+        if (jlo > jhi) continue;
+        dir_row<SEL>(acc, tile + (trow0 + i) * TWD + lx0, sebase + i * kpad, jlo & ~(kDirRX - 1), jhi);
+    }
+    const int gy = by0 + trow0, L = J.L, W = J.W;
+    if (gy < J.H) {
+#pragma unroll
+        for (int t = 0; t < kDirRX; ++t) {
+            const int gx = bx0 + lx0 + t;
+            if (gx >= W) continue;
+            const int d = acc[t] < 0 ? 0 : acc[t];
+            gst(J.out)[(size_t)gy * W + gx] = J.op ? (L - 1 - d) : d;
+        }
+    }
+    __syncthreads();   // the LDS block is restaged by the next item
+}
+
+template <bool SEL>
+__global__ __launch_bounds__(kDirThreads) void k_direct32(const JobDev *__restrict__ jobs,
+                                                          const Seg *__restrict__ segs, int nseg,
+                                                          long long nitems, StatsDev *st) {
+    extern __shared__ int32_t dyn_lds[];
+    for (long long it = blockIdx.x; it < nitems; it += gridDim.x) {
+        const Seg S = segs[find_seg(segs, nseg, it)];
+        const JobDev &J = jobs[S.job];
+        const int local = (int)(it - S.item0);
+        const int byi = local / J.dir_bx, bxi = local - byi * J.dir_bx;
+        direct32_block<SEL>(J, byi * kDirBH, bxi * kDirBW, dyn_lds, &st->range_err);
+    }
+}
+
+// Packed direct window, register-blocked over output rows.  A block of
+// 256 threads covers kD16BH x kDirBW outputs as 2 x 2 waves of 8 x 8 lanes;
+// a lane owns 8 consecutive columns of kD16R packed output row pairs.  The
+// loop runs over 8- (or 4-) column steps of the SE, and inside a step over
+// SE row pairs (2s, 2s+1): output pair r reads LDS word row q+r+s (SE row 2s,
+// whole words) and the straddle of word rows q+r+s, q+r+s+1 (SE row 2s+1),
+// so the kD16R+1 word rows in registers slide down by one word row per SE row
+// pair -- one new word row (16 words) is read from LDS per 2 x kD16R x 64
+// packed add/max pairs.  The SE words (uniform across the wave) come through
+// scalar loads.  Per column step, only the SE row pairs with an active cell
+// in those columns are visited (sek_cols), so disk-shaped SEs skip their
+// empty corners.
+constexpr int kD16R = 2;
+constexpr int kD16BH = 32 * kD16R;
+
+template <int NS> struct D16 {
+    static constexpr int NW = NS == 8 ? 16 : 12;   // words read per word row (NS + 7 used)
+};
+
+template <int NW>
+__device__ __forceinline__ void d16_load(int (&w)[NW], const int32_t *p) {
+#pragma unroll
+    for (int u = 0; u < NW / 4; ++u) {
+        const int4 v = *(const int4 *)(p + 4 * u);
+        w[4 * u] = v.x;
+        w[4 * u + 1] = v.y;
+        w[4 * u + 2] = v.z;
+        w[4 * u + 3] = v.w;
+    }
+}
+
+// acc = max(acc, in[t + sj] + b[sj]) over the NS SE columns of one SE row;
+// all sums of a column before their maxima (a packed op that reads the result
+// of the instruction right before it costs a wait state)
+template <int NS>
+__device__ __forceinline__ void d16_row(s16x2 (&acc)[kDirRX], const s16x2 *in, const s16x2 (&b)[NS]) {
+#pragma unroll
+    for (int sj = 0; sj < NS; ++sj) {
+        s16x2 sum[kDirRX];
+#pragma unroll
+        for (int t = 0; t < kDirRX; ++t) sum[t] = in[t + sj] + b[sj];
+#pragma unroll
+        for (int t = 0; t < kDirRX; ++t) acc[t] = __builtin_elementwise_max(acc[t], sum[t]);
+    }
+}
+
+// One SE row pair (ODD) or the last, even SE row alone (!ODD) over the
+// thread's kD16R output pairs.  be / bo: SE rows 2s and 2s+1 at the step's
+// first column.
+template <int NS, bool ODD>
+__device__ __forceinline__ void d16_pair(s16x2 (&acc)[kD16R][kDirRX], const int (&win)[kD16R + 1][D16<NS>::NW],
+                                         const int32_t *be, const int32_t *bo) {
+    constexpr int NU = NS + kDirRX - 1;
+    const auto ce = cst(be);
+    s16x2 b[NS];
+#pragma unroll
+    for (int sj = 0; sj < NS; ++sj) b[sj] = __builtin_bit_cast(s16x2, ce[sj]);
+#pragma unroll
+    for (int r = 0; r < kD16R; ++r) {
+        s16x2 in[NU];
+#pragma unroll
+        for (int t = 0; t < NU; ++t) in[t] = __builtin_bit_cast(s16x2, win[r][t]);
+        d16_row<NS>(acc[r], in, b);
+    }
+    if constexpr (ODD) {
+        const auto co = cst(bo);
+#pragma unroll
+        for (int sj = 0; sj < NS; ++sj) b[sj] = __builtin_bit_cast(s16x2, co[sj]);
+#pragma unroll
+        for (int r = 0; r < kD16R; ++r) {
+            s16x2 in[NU];
+#pragma unroll
+            for (int t = 0; t < NU; ++t) in[t] = __builtin_bit_cast(s16x2, straddle(win[r][t], win[r + 1][t]));
+            d16_row<NS>(acc[r], in, b);
+        }
+    }
+}
+
+// SE row pairs s0..s1 of one column step.  trow: LDS word row q of the
+// thread at the step's first column; se: SE row 0 at that column.  Word row
+// q+s+kD16R+1 is fetched while pair s computes (one row past the staged
+// block at most, which the LDS allocation covers).
+template <int NS>
+__device__ __forceinline__ void d16_column(s16x2 (&acc)[kD16R][kDirRX], const int32_t *trow, int P,
+                                           const int32_t *se, int kpad, int k, int s0, int s1) {
+    constexpr int NW = D16<NS>::NW;
+    int win[kD16R + 1][NW];
+#pragma unroll
+    for (int r = 0; r <= kD16R; ++r) d16_load<NW>(win[r], trow + (s0 + r) * P);
+    const int sfull = min(s1, (k - 3) >> 1);   // pairs with both rows inside the SE
+    int s = s0;
+#pragma unroll 2
+    for (; s <= sfull; ++s) {
+        int nxt[NW];
+        d16_load<NW>(nxt, trow + (s + kD16R + 1) * P);
+        d16_pair<NS, true>(acc, win, se + 2 * s * kpad, se + (2 * s + 1) * kpad);
+#pragma unroll
+        for (int r = 0; r < kD16R; ++r)
+#pragma unroll
+            for (int t = 0; t < NW; ++t) win[r][t] = win[r + 1][t];
+#pragma unroll
+        for (int t = 0; t < NW; ++t) win[kD16R][t] = nxt[t];
+    }
+    if (s <= s1) d16_pair<NS, false>(acc, win, se + 2 * s * kpad, nullptr);   // s = (k-1)/2: SE row k-1
+}
+
+// LDS words of one packed block: word rows of image rows 2p, 2p+1 (low,
+// high half), one spare word row for the prefetch, pitch P = kDirBW + kpad + 4.
+__host__ __device__ constexpr int d16_pitch(int kpad) { return kDirBW + kpad + 4; }
+__host__ __device__ constexpr int d16_rows(int k) { return (kD16BH + k - 1) / 2 + 1; }
+
+__device__ __forceinline__ void direct16_block(const JobDev &J, int by0, int bx0, int32_t *tile,
+                                               unsigned int *range_err) {
+    const int k = J.k, rad = (k - 1) >> 1, kpad = J.kpad;
+    const int P = d16_pitch(kpad);
+    const int TH = kD16BH + k - 1;                 // image rows the block reads (even: k is odd)
+    const int TC = kDirBW + k - 1;                 // image columns the block reads
+    const int bad = dir_stage<true>(J, by0, bx0, rad, TH, TC, P, tile);
+    if (bad && range_err) atomicOr(range_err, 1u);
+    __syncthreads();
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, wx = wv & 1, wy = wv >> 1;
+    const int cg = lane & 7, rg = lane >> 3;
+    const int lx0 = wx * 64 + cg * kDirRX;         // first output column of the lane
+    const int q = wy * 8 * kD16R + rg * kD16R;     // LDS word row = first output row / 2
+    // a wave whose outputs all lie outside the image skips the window
+    const bool live = bx0 + wx * 64 < J.W && by0 + wy * 16 * kD16R < J.H;
+    s16x2 acc[kD16R][kDirRX];
+    const int neg = (int)(((unsigned)kNeg16 & 0xffffu) * 0x10001u);
+#pragma unroll
+    for (int r = 0; r < kD16R; ++r)
+#pragma unroll
+        for (int t = 0; t < kDirRX; ++t) acc[r][t] = __builtin_bit_cast(s16x2, neg);
+    if (live) {
+        const auto cols = cst(J.sek_cols);
+        const int nc4 = kpad >> 2;
+        const int32_t *base = tile + q * P + lx0;
+        for (int g4 = 0; g4 < nc4;) {
+            const int2 a = make_int2(cols[2 * g4], cols[2 * g4 + 1]);
+            if (g4 + 1 < nc4) {
+                const int2 b = make_int2(cols[2 * g4 + 2], cols[2 * g4 + 3]);
+                if (a.x <= a.y && b.x <= b.y) {
+                    d16_column<8>(acc, base + 4 * g4, P, J.sek16 + 4 * g4, kpad, k, min(a.x, b.x), max(a.y, b.y));
+                    g4 += 2;
+                    continue;
+                }
+            }
+            if (a.x <= a.y) d16_column<4>(acc, base + 4 * g4, P, J.sek16 + 4 * g4, kpad, k, a.x, a.y);
+            ++g4;
+        }
+    }
+    // results (clamped at 0: a negative maximum is an empty window) go to LDS
+    // as 16-bit values, one row of 8 per b128 write, once every wave has
+    // finished reading the image block
+    __syncthreads();
+    if (live) {
+        uint16_t *ob = (uint16_t *)tile;
+#pragma unroll
+        for (int r = 0; r < kD16R; ++r) {
+            s16x2 c[kDirRX];
+#pragma unroll
+            for (int t = 0; t < kDirRX; ++t) c[t] = __builtin_elementwise_max(acc[r][t], (s16x2){0, 0});
+#pragma unroll
+            for (int hh = 0; hh < 2; ++hh) {
+                int4 w;
+                const unsigned sel = hh ? 0x07060302u : 0x05040100u;   // high or low halves of two words
+                w.x = (int)__builtin_amdgcn_perm(__builtin_bit_cast(unsigned, c[1]), __builtin_bit_cast(unsigned, c[0]), sel);
+                w.y = (int)__builtin_amdgcn_perm(__builtin_bit_cast(unsigned, c[3]), __builtin_bit_cast(unsigned, c[2]), sel);
+                w.z = (int)__builtin_amdgcn_perm(__builtin_bit_cast(unsigned, c[5]), __builtin_bit_cast(unsigned, c[4]), sel);
+                w.w = (int)__builtin_amdgcn_perm(__builtin_bit_cast(unsigned, c[7]), __builtin_bit_cast(unsigned, c[6]), sel);
+                *(int4 *)(ob + (2 * (q + r) + hh) * kDirBW + lx0) = w;
+            }
+        }
+    }
+    __syncthreads();
+    // rows of the block to global memory, 64 consecutive columns per wave store
+    {
+        const uint16_t *ob = (const uint16_t *)tile;
+        const int L = J.L, W = J.W, op = J.op;
+        const int cx = threadIdx.x & (kDirBW - 1), gx = bx0 + cx;
+        if (gx < W) {
+            for (int y = threadIdx.x / kDirBW; y < kD16BH; y += kDirThreads / kDirBW) {
+                const int gy = by0 + y;
+                if (gy >= J.H) break;
+                const int d = ob[y * kDirBW + cx];
+                gst(J.out)[(size_t)gy * W + gx] = op ? (L - 1 - d) : d;
+            }
+        }
+    }
+    __syncthreads();   // the LDS block is restaged by the next item
+}
+
+__global__ __launch_bounds__(kDirThreads) void k_direct16(const JobDev *__restrict__ jobs,
+                                                          const Seg *__restrict__ segs, int nseg,
+                                                          long long nitems, StatsDev *st) {
+    extern __shared__ int32_t dyn_lds[];
+    for (long long it = blockIdx.x; it < nitems; it += gridDim.x) {
+        const Seg S = segs[find_seg(segs, nseg, it)];
+        const JobDev &J = jobs[S.job];
+        const int local = (int)(it - S.item0);
+        const int byi = local / J.dir_bx, bxi = local - byi * J.dir_bx;
+        direct16_block(J, byi * kD16BH, bxi * kDirBW, dyn_lds, &st->range_err);
+    }
+}
+
+}  // namespace
+
+int direct_block_rows(int pack) { return pack ? kD16BH : kDirBH; }
+
+size_t direct_lds_bytes(int k, int kpad, int pack, int sel) {
+    if (pack) return (size_t)d16_rows(k) * d16_pitch(kpad) * sizeof(int32_t);
+    const int rows = kDirBH + k - 1;
+    return ((size_t)rows * (kDirBW + kpad) + (sel ? (size_t)k * kpad : 0) + (size_t)((2 * k + 3) & ~3) + 16) *
+           sizeof(int32_t);
+}
+
+hipError_t launch_direct(int pack, int sel, const JobDev *jobs, const Seg *segs, int nseg, long long nitems,
+                         int grid, size_t lds_bytes, StatsDev *st, hipStream_t s) {
+    if (nitems <= 0) return hipSuccess;
+    if (pack) k_direct16<<<grid, kDirThreads, lds_bytes, s>>>(jobs, segs, nseg, nitems, st);
+    else if (sel) k_direct32<true><<<grid, kDirThreads, lds_bytes, s>>>(jobs, segs, nseg, nitems, st);
+    else k_direct32<false><<<grid, kDirThreads, lds_bytes, s>>>(jobs, segs, nseg, nitems, st);
+    return hipGetLastError();
+}
+
+}  // namespace md

@@ -18,8 +18,12 @@
 //   * Decode.  Per pixel, the inverse real DFT over the bins gives the
 //     coefficients c_d; the output is the largest d with rint(c_d) != 0 and
 //     the distance |c_d - rint(c_d)| is checked against the ambiguity band.
-//   * Ambiguous tiles are recomputed exactly: FP64 transforms, or the direct
-//     max-plus window when the FP64 tile would be too small.
+//   * Ambiguous tiles are recomputed exactly with FP64 transforms.
+//   * Large tiles (FP32 256-1024, FP64 128-1024 points per side) run the
+//     same steps through a per-block slab in global memory, a batch of lines
+//     at a time in LDS.
+//   * The classical max-plus window (direct path) is a separate kernel; a
+//     measured cost model picks it or the transform path per job.
 //
 // LDS FFT layout: an N x N complex array with row pitch N + 1.  The forward
 // transform is decimation-in-time with bit-reversed input (the encode writes
@@ -28,7 +32,7 @@
 // so no explicit permutation pass is needed.  Each pass fuses q <= 3
 // radix-2 stages in registers; lanes of a wavefront walk the batch axis so
 // both row and column passes touch consecutive LDS words.
-#include "md_internal.h"
+#include "md_device.h"
 
 #include <math.h>
 
@@ -36,75 +40,6 @@
 
 namespace md {
 namespace {
-
-template <typename R> struct Cx;
-template <> struct Cx<float> { using T = float2; };
-template <> struct Cx<double> { using T = double2; };
-
-template <typename C>
-__device__ __forceinline__ C cadd(C a, C b) { C r; r.x = a.x + b.x; r.y = a.y + b.y; return r; }
-template <typename C>
-__device__ __forceinline__ C csub(C a, C b) { C r; r.x = a.x - b.x; r.y = a.y - b.y; return r; }
-template <typename C>
-__device__ __forceinline__ C cmul(C a, C b) {
-    C r;
-    r.x = a.x * b.x - a.y * b.y;
-    r.y = a.x * b.y + a.y * b.x;
-    return r;
-}
-template <typename C>
-__device__ __forceinline__ C czero() { C r; r.x = 0; r.y = 0; return r; }
-
-// Address-space views: tables that every lane of a wavefront reads at the
-// same index go through the constant space (scalar loads); per-lane data
-// through the global space (no flat addressing).
-template <class T>
-__device__ __forceinline__ const __attribute__((address_space(4))) T *cst(const T *p) {
-    return (const __attribute__((address_space(4))) T *)(p);
-}
-template <class T>
-__device__ __forceinline__ const __attribute__((address_space(1))) T *gld(const T *p) {
-    return (const __attribute__((address_space(1))) T *)(p);
-}
-template <class T>
-__device__ __forceinline__ __attribute__((address_space(1))) T *gst(T *p) {
-    return (__attribute__((address_space(1))) T *)(p);
-}
-
-// Complex loads/stores through those spaces, as clang vectors (HIP's vector
-// structs do not copy out of address-space-qualified storage).
-typedef float f32x2 __attribute__((ext_vector_type(2)));
-typedef double f64x2 __attribute__((ext_vector_type(2)));
-template <class C> struct VecOf;
-template <> struct VecOf<float2> { using T = f32x2; };
-template <> struct VecOf<double2> { using T = f64x2; };
-
-template <class C>
-__device__ __forceinline__ C ldg(const C *p, size_t i) {
-    using V = typename VecOf<C>::T;
-    const V v = ((const __attribute__((address_space(1))) V *)p)[i];
-    C r;
-    r.x = v.x;
-    r.y = v.y;
-    return r;
-}
-template <class C>
-__device__ __forceinline__ C ldc(const C *p, size_t i) {
-    using V = typename VecOf<C>::T;
-    const V v = ((const __attribute__((address_space(4))) V *)p)[i];
-    C r;
-    r.x = v.x;
-    r.y = v.y;
-    return r;
-}
-template <class C>
-__device__ __forceinline__ void stg(C *p, size_t i, C v) {
-    using V = typename VecOf<C>::T;
-    V w;
-    w.x = v.x;
-    w.y = v.y;
-    ((__attribute__((address_space(1))) V *)p)[i] = w;
-}
 
 // a * exp(-+2 pi i idx / kTwN) with the twiddle held as hi + lo floats: the lo
 // products are formed first so they are not lost against the hi products.
@@ -399,14 +334,6 @@ __device__ __forceinline__ void fft_big_tile_bin(typename Cx<R>::T *lds, typenam
     }
 }
 
-__device__ __forceinline__ int find_seg(const Seg *__restrict__ segs, int nseg, long long it) {
-    int lo = 0, hi = nseg - 1;
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (segs[mid].item0 <= it) lo = mid; else hi = mid - 1;
-    }
-    return lo;
-}
 
 template <typename R, int N, int BS>
 __global__ __launch_bounds__(BS) void k_fft(const JobDev *__restrict__ jobs, const Seg *__restrict__ segs,
@@ -602,533 +529,6 @@ __global__ __launch_bounds__(kDecThreads) void k_decode(const JobDev *__restrict
     }
     const float rm = block_max(run_max, s_red);
     if (threadIdx.x == 0 && rm > 0.f) atomicMax(&st->max_res_bits, __float_as_uint(rm));
-}
-
-// Direct max-plus window (the classical form of Eq. (6new)).  The image
-// block plus halo is staged in LDS with "minus infinity" outside the image;
-// the SE is held in correlation order (reflected for dilation) with minus
-// infinity on masked cells, so the inner loop is branch-free:
-// acc = max(acc, in + b).  Erosion runs on the complement L-1-f with the
-// unreflected SE and complements the result (Sec. 2.1).
-//
-// Two element formats: plain int32, or two 16-bit lanes per 32-bit word
-// holding vertically adjacent rows (LDS word (r, c) = rows r and r+1 of column
-// c), so one packed add and one packed max advance two outputs.  The packed
-// form is used when every reachable sum fits: values and offsets <= 16383
-// with minus infinity = -16384 (sums stay within [-32768, 16383]).
-typedef short s16x2 __attribute__((ext_vector_type(2)));
-constexpr int kNeg16 = -16384;
-
-template <bool PACK> struct DirT;
-template <> struct DirT<false> {
-    using V = int;
-    static constexpr int BH = kDirBH;
-    __device__ static V word(int w) { return w; }
-    __device__ static V vmax(V a, V b) { return max(a, b); }
-};
-template <> struct DirT<true> {
-    using V = s16x2;
-    static constexpr int BH = 2 * kDirBH;
-    __device__ static V word(int w) { return __builtin_bit_cast(s16x2, w); }
-    __device__ static V vmax(V a, V b) { return __builtin_elementwise_max(a, b); }
-};
-
-// One staged pixel: minus infinity outside the image, else the grey value
-// (complemented for erosion); a value outside [0, L-1] sets `bad`.  Branch
-// free: outside the image the load reads pixel 0 and its value is dropped,
-// so the loads of a staging pass are all in flight together.
-template <bool PACK>
-__device__ __forceinline__ int dir_pix(const JobDev &J, int gy, int gx, bool &bad) {
-    const int neg = PACK ? kNeg16 : kNeg;
-    const bool in = (unsigned)gy < (unsigned)J.H && (unsigned)gx < (unsigned)J.W;
-    const size_t idx = in ? (size_t)gy * J.W + gx : 0;
-    int v = gld(J.img)[idx];
-    bad |= in && (unsigned)v >= (unsigned)J.L;
-    v = min(max(v, 0), J.L - 1);
-    v = J.op ? J.L - 1 - v : v;
-    return in ? v : neg;
-}
-
-// 16 image words (this thread's 8 outputs plus the next 8 SE columns) and the
-// 8 SE offsets of one 8-cell step; x0..x3 hold the words of the next LDS word
-// row when a packed pair straddles two word rows (see direct_block).
-struct DirBuf {
-    int4 w0, w1, w2, w3, x0, x1, x2, x3, b0, b1;
-};
-
-// SEL: the SE offsets are staged in LDS (else read with scalar loads from
-// global memory, for SEs too large to share the LDS with the image block).
-template <bool SEL, bool ODD>
-__device__ __forceinline__ void dir_load(DirBuf &B, const int32_t *trow, int twd, const int32_t *brow, int jb) {
-    B.w0 = *(const int4 *)(trow + jb);
-    B.w1 = *(const int4 *)(trow + jb + 4);
-    B.w2 = *(const int4 *)(trow + jb + 8);
-    B.w3 = *(const int4 *)(trow + jb + 12);
-    if constexpr (ODD) {
-        B.x0 = *(const int4 *)(trow + twd + jb);
-        B.x1 = *(const int4 *)(trow + twd + jb + 4);
-        B.x2 = *(const int4 *)(trow + twd + jb + 8);
-        B.x3 = *(const int4 *)(trow + twd + jb + 12);
-    }
-    if constexpr (SEL) {
-        B.b0 = *(const int4 *)(brow + jb);
-        B.b1 = *(const int4 *)(brow + jb + 4);
-    } else {
-        const auto c = cst(brow + jb);
-        B.b0 = make_int4(c[0], c[1], c[2], c[3]);
-        B.b1 = make_int4(c[4], c[5], c[6], c[7]);
-    }
-}
-
-// high 16 bits of lo-word, low 16 bits of hi-word: the packed pair of image
-// rows (2p+1, 2p+2) from word rows p and p+1
-__device__ __forceinline__ int straddle(int lo, int hi) {
-    return (int)__builtin_amdgcn_alignbit((unsigned)hi, (unsigned)lo, 16u);
-}
-
-template <bool PACK, bool ODD, int NS = kDirRX>
-__device__ __forceinline__ void dir_step(typename DirT<PACK>::V (&acc)[kDirRX], const DirBuf &B) {
-    using D = DirT<PACK>;
-    using V = typename D::V;
-    int w[2 * kDirRX] = {B.w0.x, B.w0.y, B.w0.z, B.w0.w, B.w1.x, B.w1.y, B.w1.z, B.w1.w,
-                         B.w2.x, B.w2.y, B.w2.z, B.w2.w, B.w3.x, B.w3.y, B.w3.z, B.w3.w};
-    if constexpr (ODD) {
-        const int x[2 * kDirRX] = {B.x0.x, B.x0.y, B.x0.z, B.x0.w, B.x1.x, B.x1.y, B.x1.z, B.x1.w,
-                                   B.x2.x, B.x2.y, B.x2.z, B.x2.w, B.x3.x, B.x3.y, B.x3.z, B.x3.w};
-#pragma unroll
-        for (int t = 0; t < 2 * kDirRX; ++t) w[t] = straddle(w[t], x[t]);
-    }
-    V in[2 * kDirRX];
-#pragma unroll
-    for (int t = 0; t < 2 * kDirRX; ++t) in[t] = D::word(w[t]);
-    const V b[kDirRX] = {D::word(B.b0.x), D::word(B.b0.y), D::word(B.b0.z), D::word(B.b0.w),
-                         D::word(B.b1.x), D::word(B.b1.y), D::word(B.b1.z), D::word(B.b1.w)};
-    // all sums of one SE column first, then the maxima: a packed op that reads
-    // the result of the instruction right before it costs a wait state
-#pragma unroll
-    for (int sj = 0; sj < NS; ++sj) {
-        V sum[kDirRX];
-#pragma unroll
-        for (int t = 0; t < kDirRX; ++t) sum[t] = in[t + sj] + b[sj];
-#pragma unroll
-        for (int t = 0; t < kDirRX; ++t) acc[t] = D::vmax(acc[t], sum[t]);
-    }
-}
-
-// One SE row over this thread's outputs: 8-cell steps from the row's first to
-// its last active column.  Two register buffers in ping-pong: the LDS words
-// and offsets of the next step are in flight while the current step computes
-// (scheduling barriers keep the compiler from sinking the prefetch next to
-// its use).  The prefetch is unconditional; it may read up to 16 words past
-// the active span, which the padding of the LDS block and of the SE arrays
-// keeps in bounds (those values are never used).
-template <bool PACK, bool SEL, bool ODD>
-__device__ __forceinline__ void dir_row(typename DirT<PACK>::V (&acc)[kDirRX], const int32_t *trow, int twd,
-                                        const int32_t *brow, int jb0, int jhi) {
-    DirBuf A, B;
-    dir_load<SEL, ODD>(A, trow, twd, brow, jb0);
-    for (int jb = jb0;; jb += 2 * kDirRX) {
-        dir_load<SEL, ODD>(B, trow, twd, brow, jb + kDirRX);
-        __builtin_amdgcn_sched_barrier(0);
-        dir_step<PACK, ODD>(acc, A);
-        __builtin_amdgcn_sched_barrier(0);
-        if (jb + kDirRX > jhi) break;
-        dir_load<SEL, ODD>(A, trow, twd, brow, jb + 2 * kDirRX);
-        __builtin_amdgcn_sched_barrier(0);
-        dir_step<PACK, ODD>(acc, B);
-        __builtin_amdgcn_sched_barrier(0);
-        if (jb + 2 * kDirRX > jhi) break;
-    }
-}
-
-// Packed form, SE rows i (even) and i+1 together: both read word rows
-// (y+i)/2 and (y+i)/2+1 -- row i uses the first whole, row i+1 the straddling
-// halves -- so one set of LDS reads feeds 256 packed ops.  The column span is
-// the union of the two rows' spans (masked cells carry minus infinity).
-template <bool SEL, int NS>
-__device__ __forceinline__ void dir_pair_step(s16x2 (&acc)[kDirRX], const int32_t *trow, int twd, const int32_t *brow0,
-                                              const int32_t *brow1, int jb) {
-    DirBuf A, B;
-    dir_load<SEL, true>(A, trow, twd, brow0, jb);
-    if constexpr (SEL) {
-        B.b0 = *(const int4 *)(brow1 + jb);
-        B.b1 = *(const int4 *)(brow1 + jb + 4);
-    } else {
-        const auto c = cst(brow1 + jb);
-        B.b0 = make_int4(c[0], c[1], c[2], c[3]);
-        B.b1 = make_int4(c[4], c[5], c[6], c[7]);
-    }
-    B.w0 = A.w0; B.w1 = A.w1; B.w2 = A.w2; B.w3 = A.w3;
-    B.x0 = A.x0; B.x1 = A.x1; B.x2 = A.x2; B.x3 = A.x3;
-    dir_step<true, false, NS>(acc, A);
-    dir_step<true, true, NS>(acc, B);
-}
-
-// Packed form, SE rows i (even) and i+1 together: both read word rows
-// (y+i)/2 and (y+i)/2+1 -- row i uses the first whole, row i+1 the straddling
-// halves -- so one set of LDS reads feeds 256 packed ops.  The column span is
-// the union of the two rows' spans (masked cells carry minus infinity); it is
-// covered by 8-column steps and, for a remainder of at most 4, a 4-column step.
-template <bool SEL>
-__device__ __forceinline__ void dir_pair(s16x2 (&acc)[kDirRX], const int32_t *trow, int twd, const int32_t *brow0,
-                                         const int32_t *brow1, int jb0, int jhi) {
-    int jb = jb0;
-    for (; jb + kDirRX - 1 <= jhi; jb += kDirRX) dir_pair_step<SEL, kDirRX>(acc, trow, twd, brow0, brow1, jb);
-    if (jb <= jhi) {
-        if (jhi - jb < kDirRX / 2) dir_pair_step<SEL, kDirRX / 2>(acc, trow, twd, brow0, brow1, jb);
-        else dir_pair_step<SEL, kDirRX>(acc, trow, twd, brow0, brow1, jb);
-    }
-}
-
-// LDS layout of one direct block: the image words, then each SE row's
-// [first, last] active column, then (SEL) the SE offsets in correlation order
-// (k rows of kpad words, packed or not).  Packed form: word row p holds image
-// rows 2p (low half) and 2p+1 (high half); a thread owns output rows (y, y+1)
-// with y even, so SE row i needs image rows (y+i, y+i+1): a whole word for
-// even i, halves of two word rows for odd i.
-template <bool PACK, bool SEL>
-__device__ __forceinline__ void direct_block(const JobDev &J, int by0, int bx0, int ye, int xe, int32_t *tile,
-                                             unsigned int *range_err) {
-    using D = DirT<PACK>;
-    using V = typename D::V;
-    constexpr int BH = D::BH;
-    const int k = J.k, r = (k - 1) >> 1, kpad = J.kpad;
-    const int TWD = kDirBW + kpad;
-    const int TH = BH + k - 1;                       // image rows the block reads
-    const int PR = PACK ? (TH + 1) >> 1 : TH;        // LDS word rows
-    int32_t *rowL = tile + PR * TWD;
-    int32_t *seL = rowL + ((2 * k + 3) & ~3);        // 16-byte aligned for the b128 reads
-    const int32_t *sek = PACK ? J.sek16 : J.sek;
-    if (SEL)
-        for (int q = threadIdx.x; q < k * kpad; q += kDirThreads) seL[q] = gld(sek)[q];
-    for (int q = threadIdx.x; q < 2 * k; q += kDirThreads) rowL[q] = gld(J.sek_rows)[q];
-    bool bad = false;
-    // staging: 64 lanes of a wave cover consecutive columns (up to 4 x 64 per
-    // row, TWD <= 256), the waves of the block interleave rows; the 4 loads of
-    // a row are independent and in flight together
-    constexpr int kRowsPerPass = kDirThreads / 64;
-    const int lane = threadIdx.x & 63;
-    for (int a = threadIdx.x >> 6; a < TH; a += kRowsPerPass) {
-        const int gy = by0 - r + a;
-        int v[4];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            const int c = lane + 64 * u;
-            v[u] = (c < kDirBW + k - 1) ? dir_pix<PACK>(J, gy, bx0 - r + c, bad) : (PACK ? kNeg16 : kNeg);
-        }
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            const int c = lane + 64 * u;
-            if (c >= TWD) break;
-            if (PACK) ((short *)tile)[2 * ((a >> 1) * TWD + c) + (a & 1)] = (short)v[u];
-            else tile[a * TWD + c] = v[u];
-        }
-    }
-    if (bad && range_err) atomicOr(range_err, 1u);
-    __syncthreads();
-    const int trow0 = (threadIdx.x / (kDirBW / kDirRX)) * (PACK ? 2 : 1);   // first output row of this thread
-    const int lx0 = (threadIdx.x % (kDirBW / kDirRX)) * kDirRX;
-    V acc[kDirRX];
-#pragma unroll
-    for (int t = 0; t < kDirRX; ++t) acc[t] = D::word(PACK ? (int)(((unsigned)kNeg16 & 0xffffu) * 0x10001u) : kNeg);
-    const int32_t *sebase = SEL ? seL : sek;
-    if constexpr (PACK) {
-        for (int i = 0; i < k; i += 2) {
-            int jlo = rowL[2 * i], jhi = rowL[2 * i + 1];     // active cells of SE row i (LDS broadcast)
-            const int32_t *trow = tile + ((trow0 + i) >> 1) * TWD + lx0;   // word row of image row y+i
-            if (i + 1 < k) {
-                const int lo1 = rowL[2 * i + 2], hi1 = rowL[2 * i + 3];
-                if (lo1 <= hi1) {
-                    jlo = min(jlo, lo1);
-                    jhi = max(jhi, hi1);
-                }
-                if (jlo > jhi) continue;
-                dir_pair<SEL>(acc, trow, TWD, sebase + i * kpad, sebase + (i + 1) * kpad, jlo & ~(kDirRX - 1), jhi);
-            } else {
-                if (jlo > jhi) continue;
-                dir_row<true, SEL, false>(acc, trow, TWD, sebase + i * kpad, jlo & ~(kDirRX - 1), jhi);
-            }
-        }
-    } else {
-        for (int i = 0; i < k; ++i) {
-            const int jlo = rowL[2 * i], jhi = rowL[2 * i + 1];
-            if (jlo > jhi) continue;
-            dir_row<false, SEL, false>(acc, tile + (trow0 + i) * TWD + lx0, TWD, sebase + i * kpad,
-                                       jlo & ~(kDirRX - 1), jhi);
-        }
-    }
-    const int L = J.L, W = J.W;
-#pragma unroll
-    for (int hh = 0; hh < (PACK ? 2 : 1); ++hh) {
-        const int gy = by0 + trow0 + hh;
-        if (gy >= ye) continue;
-#pragma unroll
-        for (int t = 0; t < kDirRX; ++t) {
-            const int gx = bx0 + lx0 + t;
-            if (gx >= xe) continue;
-            int v;
-            if constexpr (PACK) v = hh ? acc[t].y : acc[t].x;
-            else v = acc[t];
-            const int d = v < 0 ? 0 : v;
-            gst(J.out)[(size_t)gy * W + gx] = J.op ? (L - 1 - d) : d;
-        }
-    }
-    __syncthreads();
-}
-
-template <bool PACK, bool SEL>
-__global__ __launch_bounds__(kDirThreads) void k_direct(const JobDev *__restrict__ jobs,
-                                                        const Seg *__restrict__ segs, int nseg,
-                                                        long long nitems, StatsDev *st) {
-    extern __shared__ int32_t dyn_lds[];
-    for (long long it = blockIdx.x; it < nitems; it += gridDim.x) {
-        const Seg S = segs[find_seg(segs, nseg, it)];
-        const JobDev &J = jobs[S.job];
-        const int local = (int)(it - S.item0);
-        const int byi = local / J.dir_bx, bxi = local - byi * J.dir_bx;
-        direct_block<PACK, SEL>(J, byi * DirT<PACK>::BH, bxi * kDirBW, J.H, J.W, dyn_lds, &st->range_err);
-    }
-}
-
-// Packed direct window, register-blocked over output rows.  A block of
-// 256 threads covers kD16BH x kDirBW outputs as 2 x 2 waves of 8 x 8 lanes;
-// a lane owns 8 consecutive columns of kD16R packed output row pairs.  The
-// loop runs over 8- (or 4-) column steps of the SE, and inside a step over
-// SE row pairs (2s, 2s+1): output pair r reads LDS word row q+r+s (SE row 2s,
-// whole words) and the straddle of word rows q+r+s, q+r+s+1 (SE row 2s+1),
-// so the kD16R+1 word rows in registers slide down by one word row per SE row
-// pair -- one new word row (16 words) is read from LDS per 2 x kD16R x 64
-// packed add/max pairs.  The SE words (uniform across the wave) come through
-// scalar loads.  Per column step, only the SE row pairs with an active cell
-// in those columns are visited (sek_cols), so disk-shaped SEs skip their
-// empty corners.
-constexpr int kD16R = 2;
-constexpr int kD16BH = 32 * kD16R;
-
-template <int NS> struct D16 {
-    static constexpr int NW = NS == 8 ? 16 : 12;   // words read per word row (NS + 7 used)
-};
-
-template <int NW>
-__device__ __forceinline__ void d16_load(int (&w)[NW], const int32_t *p) {
-#pragma unroll
-    for (int u = 0; u < NW / 4; ++u) {
-        const int4 v = *(const int4 *)(p + 4 * u);
-        w[4 * u] = v.x;
-        w[4 * u + 1] = v.y;
-        w[4 * u + 2] = v.z;
-        w[4 * u + 3] = v.w;
-    }
-}
-
-// acc = max(acc, in[t + sj] + b[sj]) over the NS SE columns of one SE row;
-// all sums of a column before their maxima (a packed op that reads the result
-// of the instruction right before it costs a wait state)
-template <int NS>
-__device__ __forceinline__ void d16_row(s16x2 (&acc)[kDirRX], const s16x2 *in, const s16x2 (&b)[NS]) {
-#pragma unroll
-    for (int sj = 0; sj < NS; ++sj) {
-        s16x2 sum[kDirRX];
-#pragma unroll
-        for (int t = 0; t < kDirRX; ++t) sum[t] = in[t + sj] + b[sj];
-#pragma unroll
-        for (int t = 0; t < kDirRX; ++t) acc[t] = __builtin_elementwise_max(acc[t], sum[t]);
-    }
-}
-
-// One SE row pair (ODD) or the last, even SE row alone (!ODD) over the
-// thread's kD16R output pairs.  be / bo: SE rows 2s and 2s+1 at the step's
-// first column.
-template <int NS, bool ODD>
-__device__ __forceinline__ void d16_pair(s16x2 (&acc)[kD16R][kDirRX], const int (&win)[kD16R + 1][D16<NS>::NW],
-                                         const int32_t *be, const int32_t *bo) {
-    constexpr int NU = NS + kDirRX - 1;
-    const auto ce = cst(be);
-    s16x2 b[NS];
-#pragma unroll
-    for (int sj = 0; sj < NS; ++sj) b[sj] = __builtin_bit_cast(s16x2, ce[sj]);
-#pragma unroll
-    for (int r = 0; r < kD16R; ++r) {
-        s16x2 in[NU];
-#pragma unroll
-        for (int t = 0; t < NU; ++t) in[t] = __builtin_bit_cast(s16x2, win[r][t]);
-        d16_row<NS>(acc[r], in, b);
-    }
-    if constexpr (ODD) {
-        const auto co = cst(bo);
-#pragma unroll
-        for (int sj = 0; sj < NS; ++sj) b[sj] = __builtin_bit_cast(s16x2, co[sj]);
-#pragma unroll
-        for (int r = 0; r < kD16R; ++r) {
-            s16x2 in[NU];
-#pragma unroll
-            for (int t = 0; t < NU; ++t) in[t] = __builtin_bit_cast(s16x2, straddle(win[r][t], win[r + 1][t]));
-            d16_row<NS>(acc[r], in, b);
-        }
-    }
-}
-
-// SE row pairs s0..s1 of one column step.  trow: LDS word row q of the
-// thread at the step's first column; se: SE row 0 at that column.  Word row
-// q+s+kD16R+1 is fetched while pair s computes (one row past the staged
-// block at most, which the LDS allocation covers).
-template <int NS>
-__device__ __forceinline__ void d16_column(s16x2 (&acc)[kD16R][kDirRX], const int32_t *trow, int P,
-                                           const int32_t *se, int kpad, int k, int s0, int s1) {
-    constexpr int NW = D16<NS>::NW;
-    int win[kD16R + 1][NW];
-#pragma unroll
-    for (int r = 0; r <= kD16R; ++r) d16_load<NW>(win[r], trow + (s0 + r) * P);
-    const int sfull = min(s1, (k - 3) >> 1);   // pairs with both rows inside the SE
-    int s = s0;
-#pragma unroll 2
-    for (; s <= sfull; ++s) {
-        int nxt[NW];
-        d16_load<NW>(nxt, trow + (s + kD16R + 1) * P);
-        d16_pair<NS, true>(acc, win, se + 2 * s * kpad, se + (2 * s + 1) * kpad);
-#pragma unroll
-        for (int r = 0; r < kD16R; ++r)
-#pragma unroll
-            for (int t = 0; t < NW; ++t) win[r][t] = win[r + 1][t];
-#pragma unroll
-        for (int t = 0; t < NW; ++t) win[kD16R][t] = nxt[t];
-    }
-    if (s <= s1) d16_pair<NS, false>(acc, win, se + 2 * s * kpad, nullptr);   // s = (k-1)/2: SE row k-1
-}
-
-// LDS words of one packed block: word rows of image rows 2p, 2p+1 (low,
-// high half), one spare word row for the prefetch, pitch P = kDirBW + kpad + 4.
-__host__ __device__ constexpr int d16_pitch(int kpad) { return kDirBW + kpad + 4; }
-__host__ __device__ constexpr int d16_rows(int k) { return (kD16BH + k - 1) / 2 + 1; }
-
-__device__ __forceinline__ void direct16_block(const JobDev &J, int by0, int bx0, int32_t *tile,
-                                               unsigned int *range_err) {
-    const int k = J.k, rad = (k - 1) >> 1, kpad = J.kpad;
-    const int P = d16_pitch(kpad);
-    const int TH = kD16BH + k - 1;                 // image rows the block reads (even: k is odd)
-    const int TC = kDirBW + k - 1;                 // image columns the block reads
-    // staging: the 64 lanes of a wave cover consecutive columns (4 x 64 per
-    // row hold the P <= 260 words a row needs: columns past kDirBW + kpad are
-    // never read), the waves take 4 consecutive rows each per pass.  The 16
-    // loads of a pass are unconditional (pixel 0 stands in outside the image
-    // and outside the block) and issued together before any of them is used.
-    const int lane = threadIdx.x & 63;
-    const auto img = gld(J.img);
-    const int H = J.H, W = J.W, L = J.L, op = J.op;
-    int badv = 0;
-    for (int a0 = (threadIdx.x >> 6) * 4; a0 < TH; a0 += kDirThreads / 16) {
-        int raw[4][4];
-        bool in[4][4];
-#pragma unroll
-        for (int h = 0; h < 4; ++h) {
-            const int gy = by0 - rad + a0 + h;
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                const int c = lane + 64 * u, gx = bx0 - rad + c;
-                in[h][u] = a0 + h < TH && c < TC && (unsigned)gy < (unsigned)H && (unsigned)gx < (unsigned)W;
-                raw[h][u] = img[in[h][u] ? (size_t)gy * W + gx : 0];
-            }
-        }
-        __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-        for (int h = 0; h < 4; ++h) {
-            const int a = a0 + h;
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                const int c = lane + 64 * u;
-                int v = raw[h][u];
-                badv |= (int)(in[h][u] && (unsigned)v >= (unsigned)L);
-                v = min(max(v, 0), L - 1);
-                v = op ? L - 1 - v : v;
-                if (a < TH && c < P) ((short *)tile)[2 * ((a >> 1) * P + c) + (a & 1)] = (short)(in[h][u] ? v : kNeg16);
-            }
-        }
-    }
-    const bool bad = badv != 0;
-    if (bad && range_err) atomicOr(range_err, 1u);
-    __syncthreads();
-    const int wv = threadIdx.x >> 6, wx = wv & 1, wy = wv >> 1;
-    const int cg = lane & 7, rg = lane >> 3;
-    const int lx0 = wx * 64 + cg * kDirRX;         // first output column of the lane
-    const int q = wy * 8 * kD16R + rg * kD16R;     // LDS word row = first output row / 2
-    // a wave whose outputs all lie outside the image skips the window
-    const bool live = bx0 + wx * 64 < J.W && by0 + wy * 16 * kD16R < J.H;
-    s16x2 acc[kD16R][kDirRX];
-    const int neg = (int)(((unsigned)kNeg16 & 0xffffu) * 0x10001u);
-#pragma unroll
-    for (int r = 0; r < kD16R; ++r)
-#pragma unroll
-        for (int t = 0; t < kDirRX; ++t) acc[r][t] = __builtin_bit_cast(s16x2, neg);
-    if (live) {
-        const auto cols = cst(J.sek_cols);
-        const int nc4 = kpad >> 2;
-        const int32_t *base = tile + q * P + lx0;
-        for (int g4 = 0; g4 < nc4;) {
-            const int2 a = make_int2(cols[2 * g4], cols[2 * g4 + 1]);
-            if (g4 + 1 < nc4) {
-                const int2 b = make_int2(cols[2 * g4 + 2], cols[2 * g4 + 3]);
-                if (a.x <= a.y && b.x <= b.y) {
-                    d16_column<8>(acc, base + 4 * g4, P, J.sek16 + 4 * g4, kpad, k, min(a.x, b.x), max(a.y, b.y));
-                    g4 += 2;
-                    continue;
-                }
-            }
-            if (a.x <= a.y) d16_column<4>(acc, base + 4 * g4, P, J.sek16 + 4 * g4, kpad, k, a.x, a.y);
-            ++g4;
-        }
-    }
-    // results (clamped at 0: a negative maximum is an empty window) go to LDS
-    // as 16-bit values, one row of 8 per b128 write, once every wave has
-    // finished reading the image block
-    __syncthreads();
-    if (live) {
-        uint16_t *ob = (uint16_t *)tile;
-#pragma unroll
-        for (int r = 0; r < kD16R; ++r) {
-            s16x2 c[kDirRX];
-#pragma unroll
-            for (int t = 0; t < kDirRX; ++t) c[t] = __builtin_elementwise_max(acc[r][t], (s16x2){0, 0});
-#pragma unroll
-            for (int hh = 0; hh < 2; ++hh) {
-                int4 w;
-                const unsigned sel = hh ? 0x07060302u : 0x05040100u;   // high or low halves of two words
-                w.x = (int)__builtin_amdgcn_perm(__builtin_bit_cast(unsigned, c[1]), __builtin_bit_cast(unsigned, c[0]), sel);
-                w.y = (int)__builtin_amdgcn_perm(__builtin_bit_cast(unsigned, c[3]), __builtin_bit_cast(unsigned, c[2]), sel);
-                w.z = (int)__builtin_amdgcn_perm(__builtin_bit_cast(unsigned, c[5]), __builtin_bit_cast(unsigned, c[4]), sel);
-                w.w = (int)__builtin_amdgcn_perm(__builtin_bit_cast(unsigned, c[7]), __builtin_bit_cast(unsigned, c[6]), sel);
-                *(int4 *)(ob + (2 * (q + r) + hh) * kDirBW + lx0) = w;
-            }
-        }
-    }
-    __syncthreads();
-    // rows of the block to global memory, 64 consecutive columns per wave store
-    {
-        const uint16_t *ob = (const uint16_t *)tile;
-        const int L = J.L, W = J.W, op = J.op;
-        const int cx = threadIdx.x & (kDirBW - 1), gx = bx0 + cx;
-        if (gx < W) {
-            for (int y = threadIdx.x / kDirBW; y < kD16BH; y += kDirThreads / kDirBW) {
-                const int gy = by0 + y;
-                if (gy >= J.H) break;
-                const int d = ob[y * kDirBW + cx];
-                gst(J.out)[(size_t)gy * W + gx] = op ? (L - 1 - d) : d;
-            }
-        }
-    }
-    __syncthreads();   // the LDS block is restaged by the next item
-}
-
-__global__ __launch_bounds__(kDirThreads) void k_direct16(const JobDev *__restrict__ jobs,
-                                                          const Seg *__restrict__ segs, int nseg,
-                                                          long long nitems, StatsDev *st) {
-    extern __shared__ int32_t dyn_lds[];
-    for (long long it = blockIdx.x; it < nitems; it += gridDim.x) {
-        const Seg S = segs[find_seg(segs, nseg, it)];
-        const JobDev &J = jobs[S.job];
-        const int local = (int)(it - S.item0);
-        const int byi = local / J.dir_bx, bxi = local - byi * J.dir_bx;
-        direct16_block(J, byi * kD16BH, bxi * kDirBW, dyn_lds, &st->range_err);
-    }
 }
 
 // Exact recompute of the tiles listed by the decode: FP64 transforms on
@@ -1437,24 +837,6 @@ hipError_t launch_decode(int var, int dbl, const JobDev *jobs, const Seg *segs, 
 int decode_group_variant(int bins, int dbl) { return decode_variant(bins, dbl); }
 
 int dec_pitch(int nr) { return ((nr / 2 + 1) + 31) / 32 * 32; }
-
-int direct_block_rows(int pack) { return pack ? kD16BH : DirT<false>::BH; }
-
-size_t direct_lds_bytes(int k, int kpad, int pack, int sel) {
-    if (pack) return (size_t)d16_rows(k) * d16_pitch(kpad) * sizeof(int32_t);
-    const int rows = DirT<false>::BH + k - 1;
-    return ((size_t)rows * (kDirBW + kpad) + (sel ? (size_t)k * kpad : 0) + (size_t)((2 * k + 3) & ~3) + 16) *
-           sizeof(int32_t);
-}
-
-hipError_t launch_direct(int pack, int sel, const JobDev *jobs, const Seg *segs, int nseg, long long nitems,
-                         int grid, size_t lds_bytes, StatsDev *st, hipStream_t s) {
-    if (nitems <= 0) return hipSuccess;
-    if (pack) k_direct16<<<grid, kDirThreads, lds_bytes, s>>>(jobs, segs, nseg, nitems, st);
-    else if (sel) k_direct<false, true><<<grid, kDirThreads, lds_bytes, s>>>(jobs, segs, nseg, nitems, st);
-    else k_direct<false, false><<<grid, kDirThreads, lds_bytes, s>>>(jobs, segs, nseg, nitems, st);
-    return hipGetLastError();
-}
 
 hipError_t launch_fallback(int nt64, const JobDev *jobs, const int2 *fb_list, const StatsDev *st,
                            double2 *slots, size_t slot_elems, int grid, const double2 *tw64, double2 *slabs,

@@ -1,4 +1,4 @@
-// Internal declarations shared by the HIP kernels (md_kernels.hip) and the
+// Internal declarations shared by the HIP kernels (md_fft.hip, md_direct.hip) and the
 // host runtime (md_runtime.hip).  Not part of the public interface.
 #pragma once
 
@@ -98,7 +98,7 @@ struct StatsDev {
 };
 
 // ---------------------------------------------------------------------------
-// launchers (md_kernels.hip); all enqueue on `s` and return the launch status
+// launchers (md_fft.hip, md_direct.hip); all enqueue on `s` and return the launch status
 // ---------------------------------------------------------------------------
 hipError_t launch_twiddles(double2 *tw64, TwF *tw32, hipStream_t s);
 hipError_t launch_range_tables(int nr, int L, float2 *enc32, double2 *enc64, float2 *dec32,

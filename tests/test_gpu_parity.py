@@ -189,6 +189,21 @@ def test_largest_se_and_widest_range(dev):
     assert_parity(job, dev, want=want)
 
 
+def test_direct_32bit_form(dev):
+    """Tonal ranges where (L-1) + max offset exceeds 16383 take the int32 form
+    of the direct window (SE staged in LDS up to the LDS size, else read
+    through scalar loads); the transform path does not cover them."""
+    rng = np.random.default_rng(27)
+    cases = [(77, 190, 20000, 7, 0.7, 100, 0), (77, 190, 20000, 7, 0.7, 100, 1),
+             (130, 260, 1 << 20, 41, 0.5, 1000, 0), (40, 300, 30000, 127, 0.2, 5, 1),
+             (1, 129, 17000, 3, 1.0, 0, 0)]
+    for H, W, L, k, p, max_off, op in cases:
+        job = synthetic.random_job(rng, H, W, L, k, p=p, max_off=max_off, op=op)
+        want = oracle.run_job(job)
+        assert_parity(job, dev, want=want, **DIRECT)
+        assert_parity(job, dev, want=want)
+
+
 def test_large_se_fft_only(dev):
     """SEs beyond the direct window's limit (k > 127) go through the FFT path
     with spatial tiles larger than the LDS (256 to 1024 points per side)."""
