@@ -29,7 +29,7 @@
 // transform is decimation-in-time with bit-reversed input (the encode writes
 // bit-reversed positions) and natural-order output; the inverse is
 // decimation-in-frequency with natural-order input and bit-reversed output,
-// so no explicit permutation pass is needed.  Each pass fuses q <= 3
+// so no explicit permutation pass is needed.  Each pass fuses q <= 4
 // radix-2 stages in registers; lanes of a wavefront walk the batch axis so
 // both row and column passes touch consecutive LDS words.
 #include "md_device.h"
@@ -90,10 +90,12 @@ template <> struct TwSel<double> { using T = Tw64; };
 
 constexpr int ilog2c(int n) { return n <= 1 ? 0 : 1 + ilog2c(n >> 1); }
 // Passes per 1-D transform of length 2^lg and the radix-2 stages fused into
-// pass p (balanced, at most 3 per pass).
-constexpr int npass(int lg) { return (lg + 2) / 3; }
-constexpr int passq(int lg, int p) { return lg / npass(lg) + (p < lg % npass(lg) ? 1 : 0); }
-constexpr int stages_before(int lg, int p) { return p == 0 ? 0 : stages_before(lg, p - 1) + passq(lg, p - 1); }
+// pass p (balanced, at most qm per pass: each pass is one LDS round trip;
+// qm = 4 in FP32, 3 in FP64, whose 16-point registers would cost occupancy).
+constexpr int npass(int lg, int qm) { return (lg + qm - 1) / qm; }
+constexpr int passq(int lg, int qm, int p) { return lg / npass(lg, qm) + (p < lg % npass(lg, qm) ? 1 : 0); }
+template <typename R> constexpr int max_q() { return sizeof(R) == 4 ? 4 : 3; }
+constexpr int stages_before(int lg, int qm, int p) { return p == 0 ? 0 : stages_before(lg, qm, p - 1) + passq(lg, qm, p - 1); }
 
 template <int LG>
 __device__ __forceinline__ int brev(int i) { return (int)(__brev((unsigned)i) >> (32 - LG)); }
@@ -173,8 +175,9 @@ __device__ __forceinline__ void pass_dif(typename Cx<R>::T *lds, const typename 
 template <typename R, int N, int AXIS, int BS, bool INV, int LINES = N, int PASS = 0>
 __device__ __forceinline__ void dit_axis(typename Cx<R>::T *lds, const typename TwSel<R>::T &tw) {
     constexpr int lg = ilog2c(N);
-    if constexpr (PASS < npass(lg)) {
-        pass_dit<R, N, passq(lg, PASS), (1 << stages_before(lg, PASS)), AXIS, BS, INV, LINES>(lds, tw);
+    constexpr int qm = max_q<R>();
+    if constexpr (PASS < npass(lg, qm)) {
+        pass_dit<R, N, passq(lg, qm, PASS), (1 << stages_before(lg, qm, PASS)), AXIS, BS, INV, LINES>(lds, tw);
         __syncthreads();
         dit_axis<R, N, AXIS, BS, INV, LINES, PASS + 1>(lds, tw);
     }
@@ -183,12 +186,78 @@ __device__ __forceinline__ void dit_axis(typename Cx<R>::T *lds, const typename 
 template <typename R, int N, int AXIS, int BS, bool INV, int LINES = N, int PASS = 0>
 __device__ __forceinline__ void dif_axis(typename Cx<R>::T *lds, const typename TwSel<R>::T &tw) {
     constexpr int lg = ilog2c(N);
-    if constexpr (PASS < npass(lg)) {
-        pass_dif<R, N, passq(lg, PASS), (N >> (stages_before(lg, PASS) + passq(lg, PASS))), AXIS, BS, INV, LINES>(lds,
-                                                                                                            tw);
+    constexpr int qm = max_q<R>();
+    if constexpr (PASS < npass(lg, qm)) {
+        pass_dif<R, N, passq(lg, qm, PASS), (N >> (stages_before(lg, qm, PASS) + passq(lg, qm, PASS))), AXIS, BS, INV,
+                 LINES>(lds, tw);
         __syncthreads();
         dif_axis<R, N, AXIS, BS, INV, LINES, PASS + 1>(lds, tw);
     }
+}
+
+// Runs use(q, load(q)) for q = threadIdx.x + e * BS < n, with the loads of
+// CH consecutive iterations issued before any of them is used (a loop that
+// loads and uses one element at a time waits a full memory latency per
+// element).  `load` must accept any q < n.
+template <int BS, int CH, typename LoadF, typename UseF>
+__device__ __forceinline__ void batched(int n, LoadF load, UseF use) {
+    for (int q0 = threadIdx.x; q0 < n; q0 += CH * BS) {
+        decltype(load(0)) v[CH];
+#pragma unroll
+        for (int e = 0; e < CH; ++e) {
+            const int q = q0 + e * BS;
+            v[e] = load(q < n ? q : q0);
+        }
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int e = 0; e < CH; ++e) {
+            const int q = q0 + e * BS;
+            if (q < n) use(q, v[e]);
+        }
+    }
+}
+
+// Step 1 for `rows` x N input pixels starting at image pixel (gy0, gx0):
+// out-of-image pixels are the zero polynomial, in-image grey values
+// (complemented for erosion) become their range-DFT column enc_m[v].
+// Calls put(l, j, value) for row l < rows, column j < N.  The pixel loads of
+// CH elements go out together, then their table gathers; returns non-zero if
+// an in-image value lies outside [0, L-1].
+template <typename R, int N, int BS, int CH, typename PutF>
+__device__ __forceinline__ int encode_rows(int rows, const int32_t *__restrict__ img, int H, int W, int L, int op,
+                                           int gy0, int gx0, const typename Cx<R>::T *__restrict__ enc_m, PutF put) {
+    using C = typename Cx<R>::T;
+    constexpr int LG = ilog2c(N);
+    const int n = rows * N;
+    const auto im = gld(img);
+    int badv = 0;
+    for (int q0 = threadIdx.x; q0 < n; q0 += CH * BS) {
+        int val[CH];
+        bool in[CH];
+#pragma unroll
+        for (int e = 0; e < CH; ++e) {
+            const int q = q0 + e * BS;
+            const int gy = gy0 + (q >> LG), gx = gx0 + (q & (N - 1));
+            in[e] = q < n && (unsigned)gy < (unsigned)H && (unsigned)gx < (unsigned)W;
+            val[e] = im[in[e] ? (size_t)gy * W + gx : 0];
+        }
+        __builtin_amdgcn_sched_barrier(0);
+        C v[CH];
+#pragma unroll
+        for (int e = 0; e < CH; ++e) {
+            badv |= (int)(in[e] && (unsigned)val[e] >= (unsigned)L);
+            int w = min(max(val[e], 0), L - 1);
+            w = op ? L - 1 - w : w;
+            v[e] = ldg(enc_m, in[e] ? w : 0);
+        }
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int e = 0; e < CH; ++e) {
+            const int q = q0 + e * BS;
+            if (q < n) put(q >> LG, q & (N - 1), in[e] ? v[e] : czero<C>());
+        }
+    }
+    return badv;
 }
 
 // One (tile, bin) of Step 2.  The tile's outputs start at pixel (oy0, ox0);
@@ -206,32 +275,22 @@ __device__ __forceinline__ void fft_tile_bin(typename Cx<R>::T *lds, const int32
                                              const typename TwSel<R>::T &tw, unsigned int *range_err) {
     using C = typename Cx<R>::T;
     constexpr int P = N + 1, LG = ilog2c(N);
+    constexpr int CH = N * N / BS < 16 ? N * N / BS : 16;
     const int r = (k - 1) >> 1, T = N - k + 1;
     const int iy0 = oy0 - r, ix0 = ox0 - r;
-    bool bad = false;
-    for (int q = threadIdx.x; q < N * N; q += BS) {
-        const int i = q >> LG, j = q & (N - 1);
-        const int gy = iy0 + i, gx = ix0 + j;
-        C v = czero<C>();
-        if (gy >= 0 && gy < H && gx >= 0 && gx < W) {
-            int val = gld(img)[(size_t)gy * W + gx];
-            if ((unsigned)val >= (unsigned)L) {
-                bad = true;
-                val = val < 0 ? 0 : L - 1;
-            }
-            if (op) val = L - 1 - val;
-            v = ldg(enc_m, val);
-        }
+    const int bad = encode_rows<R, N, BS, CH>(N, img, H, W, L, op, iy0, ix0, enc_m, [&](int i, int j, C v) {
         lds[brev<LG>(i) * P + brev<LG>(j)] = v;
-    }
+    });
     if (bad && range_err) atomicOr(range_err, 1u);
     __syncthreads();
     dit_axis<R, N, 0, BS, false>(lds, tw);
     dit_axis<R, N, 1, BS, false>(lds, tw);
-    for (int q = threadIdx.x; q < N * N; q += BS) {
-        C *e = lds + (q >> LG) * P + (q & (N - 1));
-        *e = cmul(*e, ldg(spec_m, q));
-    }
+    batched<BS, CH>(
+        N * N, [&](int q) { return ldg(spec_m, q); },
+        [&](int q, C sv) {
+            C *e = lds + (q >> LG) * P + (q & (N - 1));
+            *e = cmul(*e, sv);
+        });
     __syncthreads();
     dif_axis<R, N, 1, BS, true>(lds, tw);
     dif_axis<R, N, 0, BS, true>(lds, tw);
@@ -267,26 +326,14 @@ __device__ __forceinline__ void fft_big_tile_bin(typename Cx<R>::T *lds, typenam
     using C = typename Cx<R>::T;
     constexpr int LB = big_lines<R, N>();
     constexpr int P = N + 1, LG = ilog2c(N), LLB = ilog2c(LB);
+    constexpr int CH = LB * N / BS < 16 ? LB * N / BS : 16;
     const int r = (k - 1) >> 1, T = N - k + 1;
     const int iy0 = oy0 - r, ix0 = ox0 - r;
-    bool bad = false;
+    int bad = 0;
     // 1. rows
     for (int rb = 0; rb < N; rb += LB) {
-        for (int q = threadIdx.x; q < LB * N; q += BS) {
-            const int l = q >> LG, j = q & (N - 1);
-            const int gy = iy0 + rb + l, gx = ix0 + j;
-            C v = czero<C>();
-            if (gy >= 0 && gy < H && gx >= 0 && gx < W) {
-                int val = gld(img)[(size_t)gy * W + gx];
-                if ((unsigned)val >= (unsigned)L) {
-                    bad = true;
-                    val = val < 0 ? 0 : L - 1;
-                }
-                if (op) val = L - 1 - val;
-                v = ldg(enc_m, val);
-            }
-            lds[l * P + brev<LG>(j)] = v;
-        }
+        bad |= encode_rows<R, N, BS, CH>(LB, img, H, W, L, op, iy0 + rb, ix0, enc_m,
+                                         [&](int l, int j, C v) { lds[l * P + brev<LG>(j)] = v; });
         __syncthreads();
         dit_axis<R, N, 0, BS, false, LB>(lds, tw);
         for (int q = threadIdx.x; q < LB * N; q += BS) {
@@ -298,17 +345,17 @@ __device__ __forceinline__ void fft_big_tile_bin(typename Cx<R>::T *lds, typenam
     if (bad && range_err) atomicOr(range_err, 1u);
     // 2. columns: multiply and back
     for (int cb = 0; cb < N; cb += LB) {
-        for (int q = threadIdx.x; q < LB * N; q += BS) {
-            const int rr = q >> LLB, l = q & (LB - 1);
-            lds[l * P + rr] = ldg(slab, (size_t)rr * N + cb + l);
-        }
+        batched<BS, CH>(
+            LB * N, [&](int q) { return ldg(slab, (size_t)(q >> LLB) * N + cb + (q & (LB - 1))); },
+            [&](int q, C v) { lds[(q & (LB - 1)) * P + (q >> LLB)] = v; });
         __syncthreads();
         dit_axis<R, N, 0, BS, false, LB>(lds, tw);
-        for (int q = threadIdx.x; q < LB * N; q += BS) {
-            const int u = q >> LLB, l = q & (LB - 1);
-            C *e = lds + l * P + u;
-            *e = cmul(*e, ldg(spec_m, (size_t)u * N + cb + l));
-        }
+        batched<BS, CH>(
+            LB * N, [&](int q) { return ldg(spec_m, (size_t)(q >> LLB) * N + cb + (q & (LB - 1))); },
+            [&](int q, C sv) {
+                C *e = lds + (q & (LB - 1)) * P + (q >> LLB);
+                *e = cmul(*e, sv);
+            });
         __syncthreads();
         dif_axis<R, N, 0, BS, true, LB>(lds, tw);
         for (int q = threadIdx.x; q < LB * N; q += BS) {
@@ -319,10 +366,9 @@ __device__ __forceinline__ void fft_big_tile_bin(typename Cx<R>::T *lds, typenam
     }
     // 3. rows back; slab row rb+l is output row y = brev(rb+l)
     for (int rb = 0; rb < N; rb += LB) {
-        for (int q = threadIdx.x; q < LB * N; q += BS) {
-            const int l = q >> LG, v = q & (N - 1);
-            lds[l * P + v] = ldg(slab, (size_t)(rb + l) * N + v);
-        }
+        batched<BS, CH>(
+            LB * N, [&](int q) { return ldg(slab, (size_t)(rb + (q >> LG)) * N + (q & (N - 1))); },
+            [&](int q, C v) { lds[(q >> LG) * P + (q & (N - 1))] = v; });
         __syncthreads();
         dif_axis<R, N, 0, BS, true, LB>(lds, tw);
         for (int q = threadIdx.x; q < LB * T; q += BS) {
