@@ -213,8 +213,12 @@ __global__ __launch_bounds__(kDirThreads) void k_direct32(const JobDev *__restri
 constexpr int kD16R = 2;
 constexpr int kD16BH = 32 * kD16R;
 
-template <int NS> struct D16 {
-    static constexpr int NW = NS == 8 ? 16 : 12;   // words read per word row (NS + 7 used)
+// A column step covers NS SE columns starting at jb; the thread's LDS reads
+// start O words earlier (O = 2 for a 2-column step at jb = 2 mod 4) so that
+// every b128 read is 16-byte aligned, and take NW words: the 8 outputs plus
+// NS - 1 columns, rounded up to whole b128 reads.
+template <int NS, int O> struct D16 {
+    static constexpr int NW = (O + NS + kDirRX - 1 + 3) & ~3;
 };
 
 template <int NW>
@@ -247,8 +251,8 @@ __device__ __forceinline__ void d16_row(s16x2 (&acc)[kDirRX], const s16x2 *in, c
 // One SE row pair (ODD) or the last, even SE row alone (!ODD) over the
 // thread's kD16R output pairs.  be / bo: SE rows 2s and 2s+1 at the step's
 // first column.
-template <int NS, bool ODD>
-__device__ __forceinline__ void d16_pair(s16x2 (&acc)[kD16R][kDirRX], const int (&win)[kD16R + 1][D16<NS>::NW],
+template <int NS, int O, bool ODD>
+__device__ __forceinline__ void d16_pair(s16x2 (&acc)[kD16R][kDirRX], const int (&win)[kD16R + 1][D16<NS, O>::NW],
                                          const int32_t *be, const int32_t *bo) {
     constexpr int NU = NS + kDirRX - 1;
     const auto ce = cst(be);
@@ -259,7 +263,7 @@ __device__ __forceinline__ void d16_pair(s16x2 (&acc)[kD16R][kDirRX], const int 
     for (int r = 0; r < kD16R; ++r) {
         s16x2 in[NU];
 #pragma unroll
-        for (int t = 0; t < NU; ++t) in[t] = __builtin_bit_cast(s16x2, win[r][t]);
+        for (int t = 0; t < NU; ++t) in[t] = __builtin_bit_cast(s16x2, win[r][O + t]);
         d16_row<NS>(acc[r], in, b);
     }
     if constexpr (ODD) {
@@ -270,20 +274,21 @@ __device__ __forceinline__ void d16_pair(s16x2 (&acc)[kD16R][kDirRX], const int 
         for (int r = 0; r < kD16R; ++r) {
             s16x2 in[NU];
 #pragma unroll
-            for (int t = 0; t < NU; ++t) in[t] = __builtin_bit_cast(s16x2, straddle(win[r][t], win[r + 1][t]));
+            for (int t = 0; t < NU; ++t)
+                in[t] = __builtin_bit_cast(s16x2, straddle(win[r][O + t], win[r + 1][O + t]));
             d16_row<NS>(acc[r], in, b);
         }
     }
 }
 
 // SE row pairs s0..s1 of one column step.  trow: LDS word row q of the
-// thread at the step's first column; se: SE row 0 at that column.  Word row
-// q+s+kD16R+1 is fetched while pair s computes (one row past the staged
-// block at most, which the LDS allocation covers).
-template <int NS>
+// thread at the step's first column minus O; se: SE row 0 at the step's
+// first column.  Word row q+s+kD16R+1 is fetched while pair s computes (one
+// row past the staged block at most, which the LDS allocation covers).
+template <int NS, int O>
 __device__ __forceinline__ void d16_column(s16x2 (&acc)[kD16R][kDirRX], const int32_t *trow, int P,
                                            const int32_t *se, int kpad, int k, int s0, int s1) {
-    constexpr int NW = D16<NS>::NW;
+    constexpr int NW = D16<NS, O>::NW;
     int win[kD16R + 1][NW];
 #pragma unroll
     for (int r = 0; r <= kD16R; ++r) d16_load<NW>(win[r], trow + (s0 + r) * P);
@@ -293,7 +298,7 @@ __device__ __forceinline__ void d16_column(s16x2 (&acc)[kD16R][kDirRX], const in
     for (; s <= sfull; ++s) {
         int nxt[NW];
         d16_load<NW>(nxt, trow + (s + kD16R + 1) * P);
-        d16_pair<NS, true>(acc, win, se + 2 * s * kpad, se + (2 * s + 1) * kpad);
+        d16_pair<NS, O, true>(acc, win, se + 2 * s * kpad, se + (2 * s + 1) * kpad);
 #pragma unroll
         for (int r = 0; r < kD16R; ++r)
 #pragma unroll
@@ -301,7 +306,7 @@ __device__ __forceinline__ void d16_column(s16x2 (&acc)[kD16R][kDirRX], const in
 #pragma unroll
         for (int t = 0; t < NW; ++t) win[kD16R][t] = nxt[t];
     }
-    if (s <= s1) d16_pair<NS, false>(acc, win, se + 2 * s * kpad, nullptr);   // s = (k-1)/2: SE row k-1
+    if (s <= s1) d16_pair<NS, O, false>(acc, win, se + 2 * s * kpad, nullptr);   // s = (k-1)/2: SE row k-1
 }
 
 // LDS words of one packed block: word rows of image rows 2p, 2p+1 (low,
@@ -331,21 +336,20 @@ __device__ __forceinline__ void direct16_block(const JobDev &J, int by0, int bx0
 #pragma unroll
         for (int t = 0; t < kDirRX; ++t) acc[r][t] = __builtin_bit_cast(s16x2, neg);
     if (live) {
-        const auto cols = cst(J.sek_cols);
-        const int nc4 = kpad >> 2;
+        // the SE's column steps: (first column, kind, first and last row pair);
+        // kind 0: 8 columns, 1: 4 columns, 2: 2 columns, 3: 2 columns at a
+        // first column = 2 mod 4
+        const auto steps = cst(J.sek_steps);
         const int32_t *base = tile + q * P + lx0;
-        for (int g4 = 0; g4 < nc4;) {
-            const int2 a = make_int2(cols[2 * g4], cols[2 * g4 + 1]);
-            if (g4 + 1 < nc4) {
-                const int2 b = make_int2(cols[2 * g4 + 2], cols[2 * g4 + 3]);
-                if (a.x <= a.y && b.x <= b.y) {
-                    d16_column<8>(acc, base + 4 * g4, P, J.sek16 + 4 * g4, kpad, k, min(a.x, b.x), max(a.y, b.y));
-                    g4 += 2;
-                    continue;
-                }
+        for (int i = 0; i < J.dir_nsteps; ++i) {
+            const int jb = steps[4 * i], kind = steps[4 * i + 1], s0 = steps[4 * i + 2], s1 = steps[4 * i + 3];
+            const int32_t *se = J.sek16 + jb;
+            switch (kind) {
+                case 0: d16_column<8, 0>(acc, base + jb, P, se, kpad, k, s0, s1); break;
+                case 1: d16_column<4, 0>(acc, base + jb, P, se, kpad, k, s0, s1); break;
+                case 2: d16_column<2, 0>(acc, base + jb, P, se, kpad, k, s0, s1); break;
+                default: d16_column<2, 2>(acc, base + jb - 2, P, se, kpad, k, s0, s1); break;
             }
-            if (a.x <= a.y) d16_column<4>(acc, base + 4 * g4, P, J.sek16 + 4 * g4, kpad, k, a.x, a.y);
-            ++g4;
         }
     }
     // results (clamped at 0: a negative maximum is an empty window) go to LDS

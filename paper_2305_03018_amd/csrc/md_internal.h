@@ -72,8 +72,10 @@ struct JobDev {
     const int32_t *sek;          // [k][kpad] offsets in correlation order, kNeg where masked
     const int32_t *sek16;        // same, as two equal 16-bit lanes per word, -16384 where masked
     const int32_t *sek_rows;     // [k][2] first and last active column of each row (first > last: none)
-    const int32_t *sek_cols;     // [kpad/4][2] first and last SE row pair (2s, 2s+1) with an active cell in
-                                 // columns 4g..4g+3 (first > last: none)
+    const int32_t *sek_steps;    // packed form: [dir_nsteps][4] column steps (first column, kind, first
+                                 // and last SE row pair (2s, 2s+1)); kind 0/1/2: 8/4/2 columns, 3: 2
+                                 // columns starting at a column = 2 mod 4
+    int dir_nsteps;
     int kpad;
     int dir_pack;                // 1: 16-bit packed form (all sums fit in int16)
     int dir_bx, dir_by;          // direct-path blocks per row / column

@@ -93,8 +93,8 @@ struct SESpec {
 };
 
 struct DirSE {
-    DevBuf sek, sek16, rows, cols;
-    int kpad = 0;
+    DevBuf sek, sek16, rows, steps;
+    int kpad = 0, nsteps = 0;
 };
 
 // Per-job plan.
@@ -296,52 +296,73 @@ struct SEData {
 // active span from its first column rounded down to 8, in 8-column steps;
 // the packed form takes SE rows in pairs over the union of their spans, with
 // a 4-column final step where it suffices.
-// For each 4-column group g of the SE in the direct window's correlation
-// order (row i, column j <-> SE cell (k-1-i, k-1-j)): the first and last
-// row pair (2s, 2s+1) with an active cell in columns 4g..4g+3 (first > last:
-// none).  `cols` holds 2 * kpad/4 values.
-void dir_col_pairs(const SEData &se, std::vector<int32_t> &cols) {
-    const int k = se.k, nc4 = (int)cols.size() / 2;
-    for (int g4 = 0; g4 < nc4; ++g4) {
-        int lo = k, hi = -1;
-        for (int i = 0; i < k; ++i)
-            for (int j = 4 * g4; j < std::min(k, 4 * g4 + 4); ++j)
-                if (se.mask[(size_t)(k - 1 - i) * k + (k - 1 - j)]) {
-                    lo = std::min(lo, i / 2);
-                    hi = std::max(hi, i / 2);
-                }
-        cols[2 * g4] = lo;
-        cols[2 * g4 + 1] = hi;
+// Column steps of the packed direct window for one SE, in its correlation
+// order (row i, column j <-> SE cell (k-1-i, k-1-j)).  Each 2-column group
+// g (columns 2g, 2g+1) has the range of SE row pairs (2s, 2s+1) with an
+// active cell there; runs of groups with the same range become steps of 8, 4
+// and 2 columns (8- and 4-column steps start at a multiple of 4, so a run
+// that starts at 2 mod 4 opens with a 2-column step).  Each step is
+// {first column, kind, first pair, last pair}, kind 0/1/2 = 8/4/2 columns,
+// 3 = 2 columns at 2 mod 4.
+std::vector<int32_t> dir_steps(const SEData &se) {
+    const int k = se.k, kpad = (k + kDirRX - 1) / kDirRX * kDirRX, ng = kpad / 2;
+    std::vector<int> lo(ng, k), hi(ng, -1);
+    for (int i = 0; i < k; ++i)
+        for (int j = 0; j < k; ++j)
+            if (se.mask[(size_t)(k - 1 - i) * k + (k - 1 - j)]) {
+                lo[j / 2] = std::min(lo[j / 2], i / 2);
+                hi[j / 2] = std::max(hi[j / 2], i / 2);
+            }
+    std::vector<int32_t> st;
+    auto emit = [&](int jb, int kind, int s0, int s1) {
+        st.push_back(jb);
+        st.push_back(kind);
+        st.push_back(s0);
+        st.push_back(s1);
+    };
+    for (int g = 0; g < ng;) {
+        if (lo[g] > hi[g]) {
+            ++g;
+            continue;
+        }
+        int n = 1;
+        while (g + n < ng && lo[g + n] == lo[g] && hi[g + n] == hi[g]) ++n;
+        const int s0 = lo[g], s1 = hi[g];
+        int c = 2 * g;                       // first column of the run
+        const int end = 2 * (g + n);
+        if (c % 4 == 2) {
+            emit(c, 3, s0, s1);
+            c += 2;
+        }
+        while (end - c >= 8) {
+            emit(c, 0, s0, s1);
+            c += 8;
+        }
+        if (end - c >= 4) {
+            emit(c, 1, s0, s1);
+            c += 4;
+        }
+        if (end - c >= 2) {
+            emit(c, 2, s0, s1);
+            c += 2;
+        }
+        g += n;
     }
+    return st;
 }
 
 // SE cells per output pixel that the direct window steps through.  Packed
-// form: 8-column steps where two adjacent 4-column groups are both active,
-// else 4-column steps, each over its range of SE row pairs (the last row of
-// an odd SE alone).  32-bit form: each row's active span from its first
-// column rounded down to 8, in 8-column steps.
+// form: over the column steps of dir_steps, NS columns x (both rows of each
+// full pair + the last row of an odd SE alone).  32-bit form: each row's
+// active span from its first column rounded down to 8, in 8-column steps.
 void dir_work(SEData &se) {
-    const int k = se.k, kpad = (k + kDirRX - 1) / kDirRX * kDirRX;
-    std::vector<int32_t> cols((size_t)2 * (kpad / 4));
-    dir_col_pairs(se, cols);
-    const int nc4 = kpad / 4, last = (k - 1) / 2, sfull_max = (k - 3) / 2;
+    const int k = se.k, last = (k - 1) / 2, sfull_max = (k - 3) / 2;
+    const std::vector<int32_t> st = dir_steps(se);
     double e16 = 0;
-    auto column = [&](int ns, int s0, int s1) {
+    for (size_t i = 0; i < st.size(); i += 4) {
+        const int ns = st[i + 1] == 0 ? 8 : st[i + 1] == 1 ? 4 : 2, s0 = st[i + 2], s1 = st[i + 3];
         const int nfull = std::max(0, std::min(s1, sfull_max) - s0 + 1);
         e16 += (double)ns * (2 * nfull + (s1 == last && 2 * last + 1 == k ? 1 : 0));
-    };
-    for (int g4 = 0; g4 < nc4;) {
-        const int alo = cols[2 * g4], ahi = cols[2 * g4 + 1];
-        if (g4 + 1 < nc4) {
-            const int blo = cols[2 * g4 + 2], bhi = cols[2 * g4 + 3];
-            if (alo <= ahi && blo <= bhi) {
-                column(8, std::min(alo, blo), std::max(ahi, bhi));
-                g4 += 2;
-                continue;
-            }
-        }
-        if (alo <= ahi) column(4, alo, ahi);
-        ++g4;
     }
     std::vector<int> lo(k, k), hi(k, -1);
     for (int i = 0; i < k; ++i)
@@ -475,14 +496,14 @@ int get_dirse(const SEData &se, DirSE **out) {
         rows[2 * i] = lo;
         rows[2 * i + 1] = hi;
     }
-    // per 4-column group: the SE row pairs with an active cell there
-    std::vector<int32_t> cols((size_t)2 * (d->kpad / 4));
-    dir_col_pairs(se, cols);
+    const std::vector<int32_t> steps = dir_steps(se);
+    d->nsteps = (int)steps.size() / 4;
     MD_TRY(d->sek.ensure(h.size() * sizeof(int32_t)));
     MD_TRY(d->sek16.ensure(h16.size() * sizeof(int32_t)));
     MD_TRY(d->rows.ensure(rows.size() * sizeof(int32_t)));
-    MD_TRY(d->cols.ensure(cols.size() * sizeof(int32_t)));
-    MD_HIP(hipMemcpy(d->cols.p, cols.data(), cols.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+    MD_TRY(d->steps.ensure(std::max<size_t>(1, steps.size()) * sizeof(int32_t)));
+    if (!steps.empty())
+        MD_HIP(hipMemcpy(d->steps.p, steps.data(), steps.size() * sizeof(int32_t), hipMemcpyHostToDevice));
     MD_HIP(hipMemcpy(d->sek.p, h.data(), h.size() * sizeof(int32_t), hipMemcpyHostToDevice));
     MD_HIP(hipMemcpy(d->sek16.p, h16.data(), h16.size() * sizeof(int32_t), hipMemcpyHostToDevice));
     MD_HIP(hipMemcpy(d->rows.p, rows.data(), rows.size() * sizeof(int32_t), hipMemcpyHostToDevice));
@@ -646,7 +667,8 @@ int build_exec(const md_job *jobs, int n, const std::vector<SEData> &ses, Exec &
             d.sek = (const int32_t *)ds->sek.p;
             d.sek16 = (const int32_t *)ds->sek16.p;
             d.sek_rows = (const int32_t *)ds->rows.p;
-            d.sek_cols = (const int32_t *)ds->cols.p;
+            d.sek_steps = (const int32_t *)ds->steps.p;
+            d.dir_nsteps = ds->nsteps;
             d.kpad = ds->kpad;
             d.dir_pack = (long long)(j.L - 1) + ses[i].maxoff <= 16383 ? 1 : 0;
             d.dir_bx = (j.W + kDirBW - 1) / kDirBW;
