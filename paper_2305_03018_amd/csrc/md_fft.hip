@@ -41,8 +41,9 @@
 namespace md {
 namespace {
 
-// a * exp(-+2 pi i idx / kTwN) with the twiddle held as hi + lo floats: the lo
-// products are formed first so they are not lost against the hi products.
+// a * exp(-+2 pi i idx / kTwN), 0 <= idx < kTwN (both tables hold the full
+// circle), with the twiddle held as hi + lo floats: the lo products are
+// formed first so they are not lost against the hi products.
 struct Tw32 {
     const TwF *__restrict__ p;
     __device__ __forceinline__ float2 mul(float2 a, int idx, bool inv) const {
@@ -70,8 +71,8 @@ struct Tw64 {
     }
 };
 
-// x * w^(+-) where w = exp(-2 pi i idx / kTwN); when idx is known to be 0 or
-// kTwN/4 (w = 1 or -i) no multiply is needed.
+// x * w^(+-) where w = exp(-2 pi i idx / kTwN); when idx is a compile-time
+// constant 0 or kTwN/4 (w = 1 or -i) no multiply is needed.
 template <typename TW, typename C>
 __device__ __forceinline__ C twmul(const TW &tw, C x, int idx, bool idx_known, bool inv) {
     if (idx_known && idx == 0) return x;
@@ -100,10 +101,17 @@ constexpr int stages_before(int lg, int qm, int p) { return p == 0 ? 0 : stages_
 template <int LG>
 __device__ __forceinline__ int brev(int i) { return (int)(__brev((unsigned)i) >> (32 - LG)); }
 
+// q-bit reversal of a compile-time index
+constexpr int brevc(int t, int q) { return q == 0 ? 0 : ((t & 1) << (q - 1)) | brevc(t >> 1, q - 1); }
+
 // One fused decimation-in-time pass: radix-2 stages with half-sizes
-// H0, 2 H0, ..., 2^(Q-1) H0 on each of LINES lines of length N in an LDS
-// array of row pitch N+1.  AXIS 0 transforms along rows (contiguous), AXIS 1
-// along columns (then LINES == N).
+// H0, 2 H0, ..., 2^(Q-1) H0 on each of LINES >= 64 lines of length N in an
+// LDS array of row pitch N+1.  AXIS 0 transforms along rows (contiguous), AXIS 1
+// along columns (then LINES == N).  Each thread combines RAD = 2^Q blocks of
+// length H0 at offset o inside them: with the blocks in bit-reversed order,
+// the q stages equal one twiddle per element, w_{RAD H0}^(o brev(t)), then a
+// RAD-point DIT network whose twiddles w_{2h}^(t mod h) are compile-time
+// constants (1 and -i cost no multiply).
 template <typename R, int N, int Q, int H0, int AXIS, int BS, bool INV, int LINES = N>
 __device__ __forceinline__ void pass_dit(typename Cx<R>::T *lds, const typename TwSel<R>::T &tw) {
     using C = typename Cx<R>::T;
@@ -111,8 +119,87 @@ __device__ __forceinline__ void pass_dit(typename Cx<R>::T *lds, const typename 
     constexpr int ES = AXIS == 0 ? 1 : P, LS = AXIS == 0 ? P : 1;
     for (int u = threadIdx.x; u < UNITS; u += BS) {
         const int line = u & (LINES - 1);
-        int gi = u / LINES;
-        if constexpr (LINES >= 64) gi = __builtin_amdgcn_readfirstlane(gi);   // uniform per wavefront
+        const int gi = __builtin_amdgcn_readfirstlane(u / LINES);   // LINES >= 64: uniform per wavefront
+        const int o = gi % H0;
+        const int base = (gi / H0) * (RAD * H0) + o;
+        C *p = lds + line * LS + base * ES;
+        C x[RAD];
+#pragma unroll
+        for (int t = 0; t < RAD; ++t) x[t] = p[t * H0 * ES];
+        if constexpr (H0 > 1) {
+            if (o != 0) {   // wave-uniform
+#pragma unroll
+                for (int t = 1; t < RAD; ++t) x[t] = tw.mul(x[t], o * brevc(t, Q) * (kTwN / (RAD * H0)), INV);
+            }
+        }
+#pragma unroll
+        for (int s = 0; s < Q; ++s) {
+            const int hu = 1 << s;
+#pragma unroll
+            for (int t = 0; t < RAD; ++t) {
+                if (t & hu) continue;
+                const C b = twmul(tw, x[t + hu], (t & (hu - 1)) * (kTwN / (2 * hu)), true, INV);
+                const C a = x[t];
+                x[t] = cadd(a, b);
+                x[t + hu] = csub(a, b);
+            }
+        }
+#pragma unroll
+        for (int t = 0; t < RAD; ++t) p[t * H0 * ES] = x[t];
+    }
+}
+
+// One fused decimation-in-frequency pass: half-sizes 2^(Q-1) HMIN, ..., HMIN;
+// the transpose of pass_dit: the RAD-point DIF network with constant
+// twiddles, then w_{RAD HMIN}^(o brev(t)) per element.
+template <typename R, int N, int Q, int HMIN, int AXIS, int BS, bool INV, int LINES = N>
+__device__ __forceinline__ void pass_dif(typename Cx<R>::T *lds, const typename TwSel<R>::T &tw) {
+    using C = typename Cx<R>::T;
+    constexpr int P = N + 1, RAD = 1 << Q, UNITS = LINES * (N / RAD);
+    constexpr int ES = AXIS == 0 ? 1 : P, LS = AXIS == 0 ? P : 1;
+    for (int u = threadIdx.x; u < UNITS; u += BS) {
+        const int line = u & (LINES - 1);
+        const int gi = __builtin_amdgcn_readfirstlane(u / LINES);
+        const int o = gi % HMIN;
+        const int base = (gi / HMIN) * (RAD * HMIN) + o;
+        C *p = lds + line * LS + base * ES;
+        C x[RAD];
+#pragma unroll
+        for (int t = 0; t < RAD; ++t) x[t] = p[t * HMIN * ES];
+#pragma unroll
+        for (int s = 0; s < Q; ++s) {
+            const int hu = RAD >> (s + 1);
+#pragma unroll
+            for (int t = 0; t < RAD; ++t) {
+                if (t & hu) continue;
+                const C a = x[t], b = x[t + hu];
+                x[t] = cadd(a, b);
+                x[t + hu] = twmul(tw, csub(a, b), (t & (hu - 1)) * (kTwN / (2 * hu)), true, INV);
+            }
+        }
+        if constexpr (HMIN > 1) {
+            if (o != 0) {   // wave-uniform
+#pragma unroll
+                for (int t = 1; t < RAD; ++t) x[t] = tw.mul(x[t], o * brevc(t, Q) * (kTwN / (RAD * HMIN)), INV);
+            }
+        }
+#pragma unroll
+        for (int t = 0; t < RAD; ++t) p[t * HMIN * ES] = x[t];
+    }
+}
+
+// The same passes as radix-2 stages with their own twiddles
+// w_{2h}^(o + (t mod h') H0): used when fewer than 64 lines share a pass, so
+// the offset o varies inside a wavefront and every twiddle is a per-lane
+// table read -- fewer of them are live at once than in the factored form.
+template <typename R, int N, int Q, int H0, int AXIS, int BS, bool INV, int LINES>
+__device__ __forceinline__ void pass_dit_staged(typename Cx<R>::T *lds, const typename TwSel<R>::T &tw) {
+    using C = typename Cx<R>::T;
+    constexpr int P = N + 1, RAD = 1 << Q, UNITS = LINES * (N / RAD);
+    constexpr int ES = AXIS == 0 ? 1 : P, LS = AXIS == 0 ? P : 1;
+    for (int u = threadIdx.x; u < UNITS; u += BS) {
+        const int line = u & (LINES - 1);
+        const int gi = u / LINES;
         const int o = gi % H0;
         const int base = (gi / H0) * (RAD * H0) + o;
         C *p = lds + line * LS + base * ES;
@@ -126,8 +213,7 @@ __device__ __forceinline__ void pass_dit(typename Cx<R>::T *lds, const typename 
             for (int t = 0; t < RAD; ++t) {
                 if (t & hu) continue;
                 const int j = o + (t & (hu - 1)) * H0;            // index inside the 2h block
-                const int idx = j * (kTwN / (2 * (H0 << s)));
-                const C b = twmul(tw, x[t + hu], idx, H0 == 1, INV);
+                const C b = twmul(tw, x[t + hu], j * (kTwN / (2 * (H0 << s))), H0 == 1, INV);
                 const C a = x[t];
                 x[t] = cadd(a, b);
                 x[t + hu] = csub(a, b);
@@ -138,16 +224,14 @@ __device__ __forceinline__ void pass_dit(typename Cx<R>::T *lds, const typename 
     }
 }
 
-// One fused decimation-in-frequency pass: half-sizes 2^(Q-1) HMIN, ..., HMIN.
-template <typename R, int N, int Q, int HMIN, int AXIS, int BS, bool INV, int LINES = N>
-__device__ __forceinline__ void pass_dif(typename Cx<R>::T *lds, const typename TwSel<R>::T &tw) {
+template <typename R, int N, int Q, int HMIN, int AXIS, int BS, bool INV, int LINES>
+__device__ __forceinline__ void pass_dif_staged(typename Cx<R>::T *lds, const typename TwSel<R>::T &tw) {
     using C = typename Cx<R>::T;
     constexpr int P = N + 1, RAD = 1 << Q, UNITS = LINES * (N / RAD);
     constexpr int ES = AXIS == 0 ? 1 : P, LS = AXIS == 0 ? P : 1;
     for (int u = threadIdx.x; u < UNITS; u += BS) {
         const int line = u & (LINES - 1);
-        int gi = u / LINES;
-        if constexpr (LINES >= 64) gi = __builtin_amdgcn_readfirstlane(gi);
+        const int gi = u / LINES;
         const int o = gi % HMIN;
         const int base = (gi / HMIN) * (RAD * HMIN) + o;
         C *p = lds + line * LS + base * ES;
@@ -161,10 +245,9 @@ __device__ __forceinline__ void pass_dif(typename Cx<R>::T *lds, const typename 
             for (int t = 0; t < RAD; ++t) {
                 if (t & hu) continue;
                 const int j = o + (t & (hu - 1)) * HMIN;
-                const int idx = j * (kTwN / (2 * hu * HMIN));
                 const C a = x[t], b = x[t + hu];
                 x[t] = cadd(a, b);
-                x[t + hu] = twmul(tw, csub(a, b), idx, HMIN == 1, INV);
+                x[t + hu] = twmul(tw, csub(a, b), j * (kTwN / (2 * hu * HMIN)), HMIN == 1, INV);
             }
         }
 #pragma unroll
@@ -177,7 +260,9 @@ __device__ __forceinline__ void dit_axis(typename Cx<R>::T *lds, const typename 
     constexpr int lg = ilog2c(N);
     constexpr int qm = max_q<R>();
     if constexpr (PASS < npass(lg, qm)) {
-        pass_dit<R, N, passq(lg, qm, PASS), (1 << stages_before(lg, qm, PASS)), AXIS, BS, INV, LINES>(lds, tw);
+        constexpr int Q = passq(lg, qm, PASS), H0 = 1 << stages_before(lg, qm, PASS);
+        if constexpr (LINES >= 64) pass_dit<R, N, Q, H0, AXIS, BS, INV, LINES>(lds, tw);
+        else pass_dit_staged<R, N, Q, H0, AXIS, BS, INV, LINES>(lds, tw);
         __syncthreads();
         dit_axis<R, N, AXIS, BS, INV, LINES, PASS + 1>(lds, tw);
     }
@@ -188,8 +273,9 @@ __device__ __forceinline__ void dif_axis(typename Cx<R>::T *lds, const typename 
     constexpr int lg = ilog2c(N);
     constexpr int qm = max_q<R>();
     if constexpr (PASS < npass(lg, qm)) {
-        pass_dif<R, N, passq(lg, qm, PASS), (N >> (stages_before(lg, qm, PASS) + passq(lg, qm, PASS))), AXIS, BS, INV,
-                 LINES>(lds, tw);
+        constexpr int Q = passq(lg, qm, PASS), HMIN = N >> (stages_before(lg, qm, PASS) + Q);
+        if constexpr (LINES >= 64) pass_dif<R, N, Q, HMIN, AXIS, BS, INV, LINES>(lds, tw);
+        else pass_dif_staged<R, N, Q, HMIN, AXIS, BS, INV, LINES>(lds, tw);
         __syncthreads();
         dif_axis<R, N, AXIS, BS, INV, LINES, PASS + 1>(lds, tw);
     }
@@ -656,12 +742,10 @@ __global__ void k_twiddles(double2 *tw64, TwF *tw32) {
     double s, c;
     sincospi(-2.0 * q / kTwN, &s, &c);
     tw64[q] = make_double2(c, s);
-    if (q < kTwN / 2) {
-        TwF t;
-        t.hi = make_float2((float)c, (float)s);
-        t.lo = make_float2((float)(c - (double)t.hi.x), (float)(s - (double)t.hi.y));
-        tw32[q] = t;
-    }
+    TwF t;
+    t.hi = make_float2((float)c, (float)s);
+    t.lo = make_float2((float)(c - (double)t.hi.x), (float)(s - (double)t.hi.y));
+    tw32[q] = t;
 }
 
 // enc[m][v] = exp(-2 pi i (v m mod nr) / nr): range-axis DFT of the one-hot

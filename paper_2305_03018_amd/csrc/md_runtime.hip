@@ -237,7 +237,7 @@ int init() {
     MD_HIP(hipGetDeviceProperties(&prop, dev));
     g.cu = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
     MD_HIP(hipMalloc(&g.tw64, sizeof(double2) * kTwN));
-    MD_HIP(hipMalloc(&g.tw32, sizeof(TwF) * (kTwN / 2)));
+    MD_HIP(hipMalloc(&g.tw32, sizeof(TwF) * kTwN));
     MD_HIP(hipMalloc(&g.st_d, sizeof(StatsDev)));
     MD_HIP(hipHostMalloc((void **)&g.st_h, sizeof(StatsDev), 0));
     MD_HIP(launch_twiddles(g.tw64, g.tw32, nullptr));
