@@ -126,7 +126,8 @@ def roofline_for(stage, prof, workload):
     if stage.startswith("direct"):
         peak = INT16X2_ALU_TOPS if stage == "direct16" else INT32_ALU_TOPS
         return {"bound": "alu", "peak": peak, "unit": "TOP/s", "frac": achieved / peak, **base}
-    peak = FP64_VECTOR_TFLOPS if "64" in stage else FP32_VECTOR_TFLOPS
+    fp64 = stage.startswith(("fft64", "decode64", "recompute64"))
+    peak = FP64_VECTOR_TFLOPS if fp64 else FP32_VECTOR_TFLOPS
     return {"bound": "alu", "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak, **base}
 
 
@@ -210,6 +211,16 @@ def main():
                                ("direct", dict(precision=0, path=2))):
                 m = timed_steps(md, torch, stream, arglist, outs, max(3, args.steps // 4), 1, **opts)
                 cmp[name] = {"ms_per_step": m, "mpx_s": total_px / (m * 1e-3) / 1e6}
+                # per-stage figures of this path (events around every launch)
+                md.profile_reset()
+                with md.options(profile=1, graph=0, sync=1, **opts):
+                    for _ in range(2):
+                        md.dilate_batch(arglist, outs=outs)
+                sp = md.profile_get()
+                md.profile_reset()
+                cmp[name]["stages"] = {
+                    st: {k: v for k, v in roofline_for(st, sp, args.workload).items() if k != "traffic"}
+                    for st in sp if sp[st]["alg_ops"] > 0}
                 log(f"bench: {name} {m:.3f} ms/step")
         # profiled pass for the roofline (events around every launch, no graph)
         md.profile_reset()

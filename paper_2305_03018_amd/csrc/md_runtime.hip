@@ -996,9 +996,9 @@ int run(const md_job *jobs, int n, bool use_graph);
 // and replace the cost model's built-in estimates with the measured rates.
 int autotune_body() {
     // calibration images: 1024^2 for the direct window and the LDS-resident
-    // lengths, 2048^2 for the large ones (enough (tile, bin) items to load the
-    // whole GPU); grey values in [0, 16)
-    const int HS = 2048;
+    // lengths, 2048^2 for 256 (FP32) / 128-256 (FP64), 4096^2 for 512 and 1024
+    // (enough (tile, bin) items to load the whole GPU); grey values in [0, 16)
+    const int HS = 4096;
     DevBuf img, out;
     MD_TRY(img.ensure((size_t)HS * HS * 4));
     MD_TRY(out.ensure((size_t)HS * HS * 4));
@@ -1053,24 +1053,18 @@ int autotune_body() {
         g.cost.dir_cell[1] = y3 > 0 ? y3 / s15.dir_cells[1] : 2 * cc;
     }
     // FFT lengths: SE side nt/8*2+1 up to 33 (the item cost does not depend
-    // on it; the spectrum build does); lengths above 512 (FP32) / 256 (FP64)
-    // are extrapolated by the N^2 log N^2 work of one item
-    for (int nt : {16, 32, 64, 128, 256, 512}) {
-        const int side = nt > kMaxLdsN32 ? HS : 1024;
-        MD_TRY(measure(std::min(nt / 8 * 2 + 1, 33), 16, side, kPathFFT, 0, nt, "fft32_n" + std::to_string(nt),
-                       nullptr, &g.cost.fft_item[0][ilog2i(nt)], nullptr));
-        if (nt == 64) MD_TRY(measure(17, 16, side, kPathFFT, 0, nt, "decode32", nullptr, &g.cost.dec_unit[0], nullptr));
+    // on it; the spectrum build does)
+    auto side_for = [](int nt, int prec) { return nt >= 512 ? 4096 : nt > (prec ? kMaxLdsN64 : kMaxLdsN32) ? 2048 : 1024; };
+    for (int prec = 0; prec < 2; ++prec) {
+        const std::string pre = prec ? "fft64_n" : "fft32_n";
+        for (int nt = 16; nt <= kMaxN; nt *= 2) {
+            MD_TRY(measure(std::min(nt / 8 * 2 + 1, 33), 16, side_for(nt, prec), kPathFFT, prec, nt,
+                           pre + std::to_string(nt), nullptr, &g.cost.fft_item[prec][ilog2i(nt)], nullptr));
+            if (nt == 64)
+                MD_TRY(measure(17, 16, 1024, kPathFFT, prec, nt, prec ? "decode64" : "decode32", nullptr,
+                               &g.cost.dec_unit[prec], nullptr));
+        }
     }
-    for (int nt : {16, 32, 64, 128, 256}) {
-        const int side = nt > kMaxLdsN64 ? HS : 1024;
-        MD_TRY(measure(std::min(nt / 8 * 2 + 1, 33), 16, side, kPathFFT, 1, nt, "fft64_n" + std::to_string(nt),
-                       nullptr, &g.cost.fft_item[1][ilog2i(nt)], nullptr));
-        if (nt == 64) MD_TRY(measure(17, 16, side, kPathFFT, 1, nt, "decode64", nullptr, &g.cost.dec_unit[1], nullptr));
-    }
-    auto extrap = [](double c, int lg) { return c * 4.0 * (lg + 1.0) / lg; };   // nt -> 2 nt
-    g.cost.fft_item[0][10] = extrap(g.cost.fft_item[0][9], 9);
-    g.cost.fft_item[1][9] = extrap(g.cost.fft_item[1][8], 8);
-    g.cost.fft_item[1][10] = extrap(g.cost.fft_item[1][9], 9);
     return MD_OK;
 }
 
