@@ -62,6 +62,10 @@ def _load():
                                   ctypes.c_int, ctypes.c_int, ctypes.c_int, _i32p, _i32p, _i32p]
         lib.oracle_counts_at.argtypes = [_i32p, ctypes.c_int, ctypes.c_int, _u8p, _i32p, ctypes.c_int,
                                          ctypes.c_int, _i32p, _i32p, ctypes.c_int, _i32p, _i64p]
+        lib.oracle_dilate_e.argtypes = [_i32p, ctypes.c_int, ctypes.c_int, _u8p, _i32p, ctypes.c_int,
+                                        ctypes.c_int32, _i32p]
+        lib.oracle_erode_e.argtypes = [_i32p, ctypes.c_int, ctypes.c_int, _u8p, _i32p, ctypes.c_int,
+                                       ctypes.c_int32, _i32p]
         lib.oracle_num_threads.restype = ctypes.c_int
         lib.oracle_set_threads.argtypes = [ctypes.c_int]
         _lib = lib
@@ -145,6 +149,75 @@ def counts(img, mask, off, nd: int) -> np.ndarray:
     H, W = np.asarray(img).shape
     ys, xs = np.divmod(np.arange(H * W, dtype=np.int64), W)
     return counts_at(img, mask, off, ys, xs, nd).reshape(H, W, nd)
+
+
+# ----------------------------------------------------------------------------
+# compositions (Sec. 5: opening, closing, Beucher gradient "combined" from the
+# exact dilation and erosion)
+# ----------------------------------------------------------------------------
+def dilate_e(img, mask, off, empty: int) -> np.ndarray:
+    """Dilation of any int32 image, `empty` where the window is empty."""
+    img, mask, off = _prep(img, mask, off)
+    out = np.empty_like(img)
+    _load().oracle_dilate_e(_p(img, _i32p), img.shape[0], img.shape[1], _p(mask, _u8p), _p(off, _i32p),
+                            mask.shape[0], int(empty), _p(out, _i32p))
+    return out
+
+
+def erode_e(img, mask, off, empty: int) -> np.ndarray:
+    """Erosion of any int32 image, `empty` where the window is empty."""
+    img, mask, off = _prep(img, mask, off)
+    out = np.empty_like(img)
+    _load().oracle_erode_e(_p(img, _i32p), img.shape[0], img.shape[1], _p(mask, _u8p), _p(off, _i32p),
+                           mask.shape[0], int(empty), _p(out, _i32p))
+    return out
+
+
+def max_offset(mask, off) -> int:
+    """Largest offset over the active SE cells (0 for an empty SE)."""
+    m = np.asarray(mask) != 0
+    return int(np.asarray(off)[m].max()) if m.any() else 0
+
+
+# An empty window takes the bottom (dilation) or the top (erosion) of the range
+# its operand can span: [0, L-1] for an input image (the 0 / L-1 rules),
+# [-m, L-1] for an erosion result and [0, L-1+m] for a dilation result, with
+# m the largest SE offset.
+def opening(img, mask, off, L: int) -> np.ndarray:
+    """(f erosion b) dilation b."""
+    m = max_offset(mask, off)
+    return dilate_e(erode_e(img, mask, off, L - 1), mask, off, -m)
+
+
+def closing(img, mask, off, L: int) -> np.ndarray:
+    """(f dilation b) erosion b."""
+    m = max_offset(mask, off)
+    return erode_e(dilate_e(img, mask, off, 0), mask, off, L - 1 + m)
+
+
+def gradient(img, mask, off, L: int) -> np.ndarray:
+    """Beucher gradient: dilation minus erosion."""
+    return dilate(img, mask, off) - erode(img, mask, off, L)
+
+
+def tophat(img, mask, off, L: int) -> np.ndarray:
+    """White top-hat: f minus its opening."""
+    return np.asarray(img, np.int32) - opening(img, mask, off, L)
+
+
+def blackhat(img, mask, off, L: int) -> np.ndarray:
+    """Black top-hat: the closing minus f."""
+    return closing(img, mask, off, L) - np.asarray(img, np.int32)
+
+
+MORPH = {0: lambda f, m, o, L: dilate(f, m, o), 1: erode, 2: opening, 3: closing, 4: gradient, 5: tophat,
+         6: blackhat}
+
+
+def morph(op: int, img, mask, off, L: int) -> np.ndarray:
+    """Operation `op`: 0 dilation, 1 erosion, 2 opening, 3 closing, 4 Beucher
+    gradient, 5 white top-hat, 6 black top-hat."""
+    return MORPH[op](img, mask, off, L)
 
 
 def run_job(job) -> np.ndarray:

@@ -10,6 +10,8 @@
  *   erosion    (f (-) b)(x) = min { f(x+y) - b(y) : y in B, x+y in F }   Sec. 2.1, Eq. (Erosion)
  *              and L-1 when that set is empty (the paper leaves this case
  *              open; L-1 is the complement-duality image of the 0 rule)
+ *   compositions (Sec. 5 names them; assembled in the Python layer from the
+ *              two definitions above with explicit empty-window values)
  *   counts     c_x(d) = #{ y in B : x-y in F, f(x-y) + b(y) = d }
  *              = the integer coefficients of the polynomial that the
  *              umbra convolution yields at pixel x (Sec. 3.1, Eq. (Obs7)
@@ -74,26 +76,41 @@ static int ero_px(const int32_t *f, int H, int W, const uint8_t *mask,
     return any;
 }
 
-void oracle_dilate(const int32_t *f, int H, int W, const uint8_t *mask,
-                   const int32_t *off, int k, int32_t *out)
+/* Dilation / erosion of an image with any int32 values (an intermediate of a
+   composition may be negative or exceed L-1), `empty` where the window is
+   empty. */
+void oracle_dilate_e(const int32_t *f, int H, int W, const uint8_t *mask,
+                     const int32_t *off, int k, int32_t empty, int32_t *out)
 {
 #pragma omp parallel for schedule(dynamic, 1)
     for (int x0 = 0; x0 < H; ++x0)
         for (int x1 = 0; x1 < W; ++x1) {
             int64_t v;
-            out[(size_t)x0 * W + x1] = dil_px(f, H, W, mask, off, k, x0, x1, &v) ? (int32_t)v : 0;
+            out[(size_t)x0 * W + x1] = dil_px(f, H, W, mask, off, k, x0, x1, &v) ? (int32_t)v : empty;
         }
+}
+
+void oracle_erode_e(const int32_t *f, int H, int W, const uint8_t *mask,
+                    const int32_t *off, int k, int32_t empty, int32_t *out)
+{
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int x0 = 0; x0 < H; ++x0)
+        for (int x1 = 0; x1 < W; ++x1) {
+            int64_t v;
+            out[(size_t)x0 * W + x1] = ero_px(f, H, W, mask, off, k, x0, x1, &v) ? (int32_t)v : empty;
+        }
+}
+
+void oracle_dilate(const int32_t *f, int H, int W, const uint8_t *mask,
+                   const int32_t *off, int k, int32_t *out)
+{
+    oracle_dilate_e(f, H, W, mask, off, k, 0, out);
 }
 
 void oracle_erode(const int32_t *f, int H, int W, int L, const uint8_t *mask,
                   const int32_t *off, int k, int32_t *out)
 {
-#pragma omp parallel for schedule(dynamic, 1)
-    for (int x0 = 0; x0 < H; ++x0)
-        for (int x1 = 0; x1 < W; ++x1) {
-            int64_t v;
-            out[(size_t)x0 * W + x1] = ero_px(f, H, W, mask, off, k, x0, x1, &v) ? (int32_t)v : L - 1;
-        }
+    oracle_erode_e(f, H, W, mask, off, k, L - 1, out);
 }
 
 /* Dilation (op 0) or erosion (op 1) at n listed pixels (ys[i], xs[i]). */

@@ -306,3 +306,95 @@ def test_synthetic_recipes_shapes():
         assert jb.L in (8, 16, 32, 64) and jb.img.max() < jb.L
         assert jb.k % 2 == 1 and 3 <= jb.k <= 41 and jb.off.max() <= jb.L // 4
         assert (jb.off[jb.mask == 0] == 0).all()
+
+
+# ----------------------------------------------------------------------------
+# compositions (Sec. 5 names opening, closing and the Beucher gradient)
+# ----------------------------------------------------------------------------
+def _interior(a, r):
+    return a[2 * r:a.shape[0] - 2 * r, 2 * r:a.shape[1] - 2 * r]
+
+
+def test_compositions_flat_vs_scipy_interior():
+    """Flat symmetric SEs: scipy's own opening / closing / gradient / top-hats
+    agree away from the border (scipy pads where the definitions here restrict
+    the window to the image)."""
+    rng = np.random.default_rng(31)
+    for trial in range(12):
+        H, W = (int(v) for v in rng.integers(20, 48, 2))
+        k = int(rng.choice([3, 5, 7]))
+        L = 64
+        img = rng.integers(0, L, (H, W)).astype(np.int32)
+        mask = synthetic.square_mask(k) if trial % 2 else synthetic.disk_mask(k)
+        off = np.zeros((k, k), np.int32)
+        fp = mask.astype(bool)
+        r = k // 2
+        f = img.astype(np.float64)
+        pairs = [(oracle.opening, ndi.grey_opening(f, footprint=fp)),
+                 (oracle.closing, ndi.grey_closing(f, footprint=fp)),
+                 (oracle.gradient, ndi.morphological_gradient(f, footprint=fp)),
+                 (oracle.tophat, ndi.white_tophat(f, footprint=fp)),
+                 (oracle.blackhat, ndi.black_tophat(f, footprint=fp))]
+        for fn, want in pairs:
+            got = fn(img, mask, off, L)
+            assert np.array_equal(_interior(got, r), _interior(want, r).astype(np.int32)), fn.__name__
+
+
+def test_compositions_nonflat_vs_scipy():
+    """Non-flat SEs containing the centre (no empty windows): the opening is
+    scipy's erosion followed by scipy's dilation, the closing the reverse."""
+    rng = np.random.default_rng(32)
+    for _ in range(20):
+        H, W = (int(v) for v in rng.integers(5, 30, 2))
+        k = int(rng.integers(0, 4)) * 2 + 1
+        L = 32
+        job = synthetic.random_job(rng, H, W, L, k, p=0.6, max_off=9)
+        job.mask[k // 2, k // 2] = 1
+        fp, st = job.mask.astype(bool), job.off.astype(np.float64)
+        f = job.img.astype(np.float64)
+        ero = ndi.grey_erosion(f, footprint=fp, structure=st, mode="constant", cval=1e9)
+        dil = ndi.grey_dilation(f, footprint=fp, structure=st, mode="constant", cval=-1e9)
+        op = ndi.grey_dilation(ero, footprint=fp, structure=st, mode="constant", cval=-1e9)
+        cl = ndi.grey_erosion(dil, footprint=fp, structure=st, mode="constant", cval=1e9)
+        assert np.array_equal(oracle.opening(job.img, job.mask, job.off, L), op.astype(np.int32))
+        assert np.array_equal(oracle.closing(job.img, job.mask, job.off, L), cl.astype(np.int32))
+        assert np.array_equal(oracle.gradient(job.img, job.mask, job.off, L), (dil - ero).astype(np.int32))
+
+
+def test_composition_algebra():
+    """Opening is anti-extensive and idempotent, closing extensive and
+    idempotent, and they are dual under the complement with the reflected SE
+    -- for every mask, with the empty-window values of the operand's range."""
+    rng = np.random.default_rng(33)
+    for trial in range(60):
+        H, W = (int(v) for v in rng.integers(3, 22, 2))
+        k = int(rng.integers(0, 4)) * 2 + 1
+        L = int(rng.choice([4, 16, 64]))
+        job = synthetic.random_job(rng, H, W, L, k, p=0.5, max_off=L // 4)
+        f, mk, of = job.img, job.mask, job.off
+        m = oracle.max_offset(mk, of)
+        op, cl = oracle.opening(f, mk, of, L), oracle.closing(f, mk, of, L)
+        assert (op <= f).all() and (cl >= f).all()
+        assert np.array_equal(oracle.dilate_e(oracle.erode_e(op, mk, of, L - 1), mk, of, -m), op)
+        assert np.array_equal(oracle.erode_e(oracle.dilate_e(cl, mk, of, 0), mk, of, L - 1 + m), cl)
+        refl_m, refl_o = mk[::-1, ::-1].copy(), of[::-1, ::-1].copy()
+        assert np.array_equal(cl, (L - 1) - oracle.opening((L - 1) - f, refl_m, refl_o, L))
+        assert (oracle.tophat(f, mk, of, L) >= 0).all() and (oracle.blackhat(f, mk, of, L) >= 0).all()
+        if mk[k // 2, k // 2]:
+            assert (oracle.gradient(f, mk, of, L) >= 2 * of[k // 2, k // 2]).all()
+
+
+def test_composition_empty_windows():
+    rng = np.random.default_rng(34)
+    img = rng.integers(0, 16, (9, 11)).astype(np.int32)
+    mask = np.zeros((5, 5), np.uint8)
+    off = np.zeros((5, 5), np.int32)
+    assert (oracle.opening(img, mask, off, 16) == 0).all()        # erosion: L-1, then dilation: -m = 0
+    assert (oracle.closing(img, mask, off, 16) == 15).all()       # dilation: 0, then erosion: L-1+m = 15
+    img = rng.integers(0, 16, (3, 40)).astype(np.int32)
+    mask = np.zeros((9, 9), np.uint8)
+    mask[0, 0] = 1
+    off = np.zeros((9, 9), np.int32)
+    off[0, 0] = 3                                                  # every window of a 3-row image is empty
+    assert (oracle.opening(img, mask, off, 16) == -3).all()
+    assert (oracle.closing(img, mask, off, 16) == 15 + 3).all()
