@@ -103,6 +103,41 @@ int md_dilate(const int32_t *img, int H, int W, int L, const uint8_t *se_mask,
 int md_erode(const int32_t *img, int H, int W, int L, const uint8_t *se_mask,
              const int32_t *se_offsets, int k, int32_t *out);
 
+/* Compositions of the exact dilation and erosion (the combinations named in
+ * the paper's Sec. 5: opening, closing, Beucher gradient; and the top-hats).
+ * With (+) dilation and (-) erosion by the SE b:
+ *   MD_OPEN      (f (-) b) (+) b
+ *   MD_CLOSE     (f (+) b) (-) b
+ *   MD_GRADIENT  (f (+) b) - (f (-) b)
+ *   MD_TOPHAT    f - open(f)
+ *   MD_BLACKHAT  close(f) - f
+ * An empty window takes the bottom (dilation) or top (erosion) of the range
+ * its operand spans: [0, L-1] for the input (the 0 / L-1 rules of
+ * md_dilate / md_erode), [-m, L-1] for an erosion result and [0, L-1+m] for a
+ * dilation result, m = the largest offset of an active SE cell.  So the
+ * opening of a pixel whose dilation window is empty is -m, the closing of a
+ * pixel whose erosion window is empty is L-1+m; with these values opening is
+ * anti-extensive and idempotent, closing extensive and idempotent, and the
+ * two are dual under the complement with the reflected SE.
+ * Arguments, layout and ownership as for md_dilate; the outputs are int32 in
+ * [-m, L-1+m] (gradient and top-hats: differences of those).  Runs on the
+ * library stream through two device intermediates of H x W int32 that the
+ * library owns (kept for later calls, freed by md_release).  MD_ERR_ARG for
+ * an unknown op; MD_ERR_RANGE if L + m exceeds 2^24.  Every path, precision
+ * and option of md_dilate applies to each step. */
+typedef enum {
+    MD_DILATE = 0,
+    MD_ERODE = 1,
+    MD_OPEN = 2,
+    MD_CLOSE = 3,
+    MD_GRADIENT = 4,
+    MD_TOPHAT = 5,
+    MD_BLACKHAT = 6
+} md_op;
+
+int md_morph(int op, const int32_t *img, int H, int W, int L, const uint8_t *se_mask,
+             const int32_t *se_offsets, int k, int32_t *out);
+
 /* One job of a batch.  Pointer and ownership rules as for md_dilate. */
 typedef struct {
     const int32_t *img;          /* device, H x W                 */

@@ -8,7 +8,14 @@ library's HIP kernels.  There is no CPU fallback: calling into the library
 without a built ``libmd.so`` raises.
 """
 from ._binding import (  # noqa: F401
+    BLACKHAT,
+    CLOSE,
+    DILATE,
+    ERODE,
+    GRADIENT,
     MDError,
+    OPEN,
+    TOPHAT,
     OPT_AUTOTUNE,
     OPT_BAND,
     OPT_GRAPH,
@@ -26,7 +33,13 @@ from ._binding import (  # noqa: F401
     exported_symbols,
     get_option,
     get_stats,
+    blackhat,
+    closing,
     cost_model,
+    gradient,
+    morph,
+    opening,
+    tophat,
     library_path,
     load,
     options,

@@ -84,6 +84,8 @@ def load():
     lib.md_profile_get.restype = i
     lib.md_profile_reset.argtypes = []
     lib.md_profile_reset.restype = i
+    lib.md_morph.argtypes = [i, vp, i, i, i, u8, vp, i, vp]
+    lib.md_morph.restype = i
     lib.md_cost_model.argtypes = [ctypes.POINTER(ctypes.c_double), i, ctypes.POINTER(ctypes.c_int)]
     lib.md_cost_model.restype = i
     _lib = lib
@@ -163,6 +165,56 @@ def dilate(img, mask, off, L: int, out=None):
 def erode(img, mask, off, L: int, out=None):
     """Exact erosion: min over the SE of img(x+y) - b(y), L-1 on empty windows."""
     return _run_single("md_erode", img, mask, off, L, out)
+
+
+# md_op codes of include/md.h
+DILATE, ERODE, OPEN, CLOSE, GRADIENT, TOPHAT, BLACKHAT = range(7)
+
+
+def morph(op: int, img, mask, off, L: int, out=None):
+    """Dilation, erosion or one of their compositions (md_morph): op 0
+    dilation, 1 erosion, 2 opening, 3 closing, 4 Beucher gradient, 5 white
+    top-hat, 6 black top-hat."""
+    import torch
+
+    lib = load()
+    img = _device_image(img)
+    mask, off = _se_arrays(mask, off)
+    if out is None:
+        out = torch.empty_like(img)
+    elif out.shape != img.shape or out.dtype != torch.int32 or not out.is_contiguous():
+        raise ValueError("out must be a contiguous int32 tensor shaped like the image")
+    with torch.cuda.device(img.device):
+        _bind_stream(img.device)
+        rc = lib.md_morph(int(op), img.data_ptr(), img.shape[0], img.shape[1], int(L), mask.ctypes.data,
+                          off.ctypes.data, mask.shape[0], out.data_ptr())
+    _check(rc)
+    return out
+
+
+def opening(img, mask, off, L: int, out=None):
+    """(img erosion b) dilation b; -m where the dilation window is empty."""
+    return morph(OPEN, img, mask, off, L, out)
+
+
+def closing(img, mask, off, L: int, out=None):
+    """(img dilation b) erosion b; L-1+m where the erosion window is empty."""
+    return morph(CLOSE, img, mask, off, L, out)
+
+
+def gradient(img, mask, off, L: int, out=None):
+    """Beucher gradient: dilation minus erosion."""
+    return morph(GRADIENT, img, mask, off, L, out)
+
+
+def tophat(img, mask, off, L: int, out=None):
+    """White top-hat: img minus its opening."""
+    return morph(TOPHAT, img, mask, off, L, out)
+
+
+def blackhat(img, mask, off, L: int, out=None):
+    """Black top-hat: the closing minus img."""
+    return morph(BLACKHAT, img, mask, off, L, out)
 
 
 def dilate_batch(jobs, outs=None):

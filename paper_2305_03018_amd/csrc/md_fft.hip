@@ -838,6 +838,18 @@ __global__ void k_fill_hash(int32_t *p, size_t n, int L, unsigned int seed) {
     }
 }
 
+// Elementwise steps of the compositions (grid-stride, one int32 per lane per
+// step: these passes are bound by HBM and small next to the dilations).
+__global__ void k_add_const(int32_t *out, const int32_t *in, int32_t c, size_t n) {
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        out[i] = in[i] + c;
+}
+
+__global__ void k_sub(int32_t *out, const int32_t *x, const int32_t *y, size_t n) {
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        out[i] = x[i] - y[i];
+}
+
 __global__ void k_zero(uint32_t *p, size_t n) {
     for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
         p[i] = 0u;
@@ -863,6 +875,20 @@ size_t fft_lds_bytes(int nt, int dbl) {
     const size_t esz = dbl ? sizeof(double2) : sizeof(float2);
     if (nt > (dbl ? kMaxLdsN64 : kMaxLdsN32)) return (size_t)((dbl ? 4096 : 8192) / nt) * (nt + 1) * esz;
     return (size_t)nt * (nt + 1) * esz;
+}
+
+hipError_t launch_add_const(int32_t *out, const int32_t *in, int32_t c, size_t n, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    const int grid = (int)std::min<size_t>((n + 255) / 256, 4096);
+    k_add_const<<<grid, 256, 0, s>>>(out, in, c, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_sub(int32_t *out, const int32_t *x, const int32_t *y, size_t n, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    const int grid = (int)std::min<size_t>((n + 255) / 256, 4096);
+    k_sub<<<grid, 256, 0, s>>>(out, x, y, n);
+    return hipGetLastError();
 }
 
 hipError_t launch_twiddles(double2 *tw64, TwF *tw32, hipStream_t s) {

@@ -109,6 +109,9 @@ hipError_t launch_se_spectrum(const uint8_t *mask_d, const int32_t *off_d, int k
                               const double2 *tw64, double2 *work, double2 *spec64, float2 *spec32,
                               hipStream_t s);
 hipError_t launch_zero(void *p, size_t bytes, hipStream_t s);
+// out[i] = in[i] + c  /  out[i] = x[i] - y[i], i < n (int32; out may alias)
+hipError_t launch_add_const(int32_t *out, const int32_t *in, int32_t c, size_t n, hipStream_t s);
+hipError_t launch_sub(int32_t *out, const int32_t *x, const int32_t *y, size_t n, hipStream_t s);
 hipError_t launch_fill_hash(int32_t *p, size_t n, int L, unsigned int seed, hipStream_t s);
 hipError_t launch_fft(int nt, int dbl, const JobDev *jobs, const Seg *segs, int nseg, long long nitems,
                       int grid, const TwF *tw32, const double2 *tw64, void *slabs, StatsDev *st, hipStream_t s);

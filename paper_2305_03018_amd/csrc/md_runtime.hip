@@ -198,6 +198,7 @@ struct Ctx {
     std::unordered_map<std::string, std::unique_ptr<DirSE>> dirse;
     std::unordered_map<std::string, std::unique_ptr<Exec>> execs;
     DevBuf se_work, se_in;
+    DevBuf morph_a, morph_b;      // intermediates of md_morph
     // profiling
     struct Pending {
         std::string name;
@@ -1210,6 +1211,71 @@ int run(const md_job *jobs, int n, bool use_graph) {
     return MD_OK;
 }
 
+// One dilation (op 0) or erosion (op 1) of an image whose values lie in
+// [0, L-1], through the same planner and kernels as md_dilate.
+int single(int op, const int32_t *img, int H, int W, int L, const uint8_t *mask, const int32_t *off, int k,
+           int32_t *out) {
+    md_job j{img, H, W, L, mask, off, k, out, op};
+    return run(&j, 1, false);
+}
+
+// (f erosion b) dilation b into dst (tmp: H x W scratch): the erosion lies in
+// [-m, L-1]; shifted by m it is an image of range L+m, whose dilation (0 on
+// an empty window) shifted back gives -m there.
+int opening_into(const int32_t *img, int H, int W, int L, const uint8_t *mask, const int32_t *off, int k, int m,
+                 int32_t *tmp, int32_t *dst) {
+    const size_t n = (size_t)H * W;
+    MD_TRY(single(1, img, H, W, L, mask, off, k, tmp));
+    if (m) MD_HIP(launch_add_const(tmp, tmp, m, n, g.stream));
+    MD_TRY(single(0, tmp, H, W, L + m, mask, off, k, dst));
+    if (m) MD_HIP(launch_add_const(dst, dst, -m, n, g.stream));
+    return MD_OK;
+}
+
+// (f dilation b) erosion b into dst: the dilation lies in [0, L-1+m], an image
+// of range L+m, whose erosion gives L-1+m on an empty window.
+int closing_into(const int32_t *img, int H, int W, int L, const uint8_t *mask, const int32_t *off, int k, int m,
+                 int32_t *tmp, int32_t *dst) {
+    MD_TRY(single(0, img, H, W, L, mask, off, k, tmp));
+    return single(1, tmp, H, W, L + m, mask, off, k, dst);
+}
+
+int morph(int op, const int32_t *img, int H, int W, int L, const uint8_t *mask, const int32_t *off, int k,
+          int32_t *out) {
+    if (op == MD_DILATE || op == MD_ERODE) return single(op, img, H, W, L, mask, off, k, out);
+    if (op < MD_OPEN || op > MD_BLACKHAT) return fail(MD_ERR_ARG, "unknown morphological operation %d", op);
+    md_job j{img, H, W, L, mask, off, k, out, 0};
+    MD_TRY(check_job(j));
+    MD_TRY(init());
+    int m = 0;
+    for (int q = 0; q < k * k; ++q)
+        if (mask[q]) m = std::max(m, (int)off[q]);
+    if ((long long)L + m > (1 << 24)) return fail(MD_ERR_RANGE, "L + max offset = %lld exceeds 2^24", (long long)L + m);
+    const size_t n = (size_t)H * W;
+    MD_TRY(g.morph_a.ensure(n * sizeof(int32_t)));
+    MD_TRY(g.morph_b.ensure(n * sizeof(int32_t)));
+    int32_t *a = (int32_t *)g.morph_a.p, *b = (int32_t *)g.morph_b.p;
+    switch (op) {
+        case MD_OPEN: return opening_into(img, H, W, L, mask, off, k, m, a, out);
+        case MD_CLOSE: return closing_into(img, H, W, L, mask, off, k, m, a, out);
+        case MD_GRADIENT:
+            MD_TRY(single(0, img, H, W, L, mask, off, k, a));
+            MD_TRY(single(1, img, H, W, L, mask, off, k, b));
+            MD_HIP(launch_sub(out, a, b, n, g.stream));
+            break;
+        case MD_TOPHAT:
+            MD_TRY(opening_into(img, H, W, L, mask, off, k, m, a, b));
+            MD_HIP(launch_sub(out, img, b, n, g.stream));
+            break;
+        default:   // MD_BLACKHAT
+            MD_TRY(closing_into(img, H, W, L, mask, off, k, m, a, b));
+            MD_HIP(launch_sub(out, b, img, n, g.stream));
+            break;
+    }
+    if (g.opt.sync) MD_HIP(hipStreamSynchronize(g.stream));
+    return MD_OK;
+}
+
 }  // namespace
 }  // namespace md
 
@@ -1230,6 +1296,11 @@ int md_erode(const int32_t *img, int H, int W, int L, const uint8_t *se_mask, co
 }
 
 int md_dilate_batch(const md_job *jobs, int n) { return run(jobs, n, true); }
+
+int md_morph(int op, const int32_t *img, int H, int W, int L, const uint8_t *se_mask, const int32_t *se_offsets,
+             int k, int32_t *out) {
+    return morph(op, img, H, W, L, se_mask, se_offsets, k, out);
+}
 
 int md_set_stream(void *hip_stream) {
     g.stream = (hipStream_t)hip_stream;
@@ -1354,6 +1425,8 @@ int md_release(void) {
     g.ranges.clear();
     g.se_work.release();
     g.se_in.release();
+    g.morph_a.release();
+    g.morph_b.release();
     if (g.tw64) (void)hipFree(g.tw64);
     if (g.tw32) (void)hipFree(g.tw32);
     if (g.st_d) (void)hipFree(g.st_d);
