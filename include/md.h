@@ -72,7 +72,11 @@ typedef enum {
 typedef enum {
     MD_OPT_PRECISION = 0,  /* 0: FP32 transforms with split hi/lo twiddles and FP64
                               recompute of ambiguous tiles (default);
-                              1: plain FP64 transforms everywhere                */
+                              1: plain FP64 transforms everywhere;
+                              2: exact number-theoretic transforms modulo the
+                              prime 7340033 (no rounding, no recompute): tiles
+                              of 16..128 points, range lengths 2^a or 7*2^a up
+                              to 1024, so (L-1) + max offset < 1024           */
     MD_OPT_BAND = 1,       /* ambiguity band: a tile whose decoded coefficient c
                               has |c - rint(c)| >= band is recomputed (default
                               0.25; 0 forces every tile through the recompute)   */
@@ -205,7 +209,7 @@ int md_profile_get(md_stage_time *out, int max, int *n);
 int md_profile_reset(void);
 
 /* Cost-model constants in use, in ns per work unit, into the host array
- * `dst` of capacity `n` (at least 19):
+ * `dst` of capacity `n` (at least 24):
  *   [0] direct window, 16-bit packed form, per output pixel per SE cell
  *       stepped through (active row spans in 8-column steps)
  *   [1] the same, 32-bit form
@@ -214,7 +218,10 @@ int md_profile_reset(void);
  *   [4] decode FP64, the same
  *   [5..11]  FFT stage per (tile, bin) item, FP32, lengths 16, 32, ..., 1024
  *   [12..18] the same, FP64
- * *measured = 1 if they come from the autotuner.  MD_ERR_ARG if n < 19. */
+ *   [19..22] exact (mod p) transform stage per (tile, bin) item, lengths
+ *            16, 32, 64, 128
+ *   [23]     exact decode, per pixel per range bin (one block of degrees)
+ * *measured = 1 if they come from the autotuner.  MD_ERR_ARG if n < 24. */
 int md_cost_model(double *dst, int n, int *measured);
 
 /* Test hook: per-bin transform-domain values of one tile just before the
@@ -224,7 +231,10 @@ int md_cost_model(double *dst, int n, int *measured);
  * the values Y[m][p], m < n_r/2+1, p < T*T (T = n_t - k + 1, row-major over
  * the tile's T x T outputs starting at pixel (ty*T, tx*T)), scaled by
  * 1/n_t^2, into the HOST array `dst` as interleaved (re, im) doubles.
- * `dst` must hold 2*(n_r/2+1)*T*T doubles.  precision: 0 FP32, 1 FP64. */
+ * `dst` must hold 2*(n_r/2+1)*T*T doubles.  precision: 0 FP32, 1 FP64.
+ * precision 2 (exact path, n_r a valid range length of that path): the n_r
+ * bins Y[m][p] are residues mod 7340033 (already scaled by n_t^-2), copied
+ * as (value, 0) pairs; `dst` must hold 2*n_r*T*T doubles. */
 int md_debug_tile_values(const int32_t *img, int H, int W, int L, const uint8_t *se_mask,
                          const int32_t *se_offsets, int k, int n_t, int n_r, int precision,
                          int ty, int tx, double *dst);

@@ -297,7 +297,7 @@ def profile_get() -> dict:
 def cost_model() -> dict:
     """Cost-model constants in use (ns per work unit) and whether the
     autotuner measured them."""
-    n = 19
+    n = 24
     v = (ctypes.c_double * n)()
     measured = ctypes.c_int(0)
     _check(load().md_cost_model(v, n, ctypes.byref(measured)))
@@ -305,7 +305,9 @@ def cost_model() -> dict:
     return {"direct16_per_px_cell": v[0], "direct32_per_px_cell": v[1], "direct_per_staged_word": v[2],
             "decode32_per_px_bins2": v[3], "decode64_per_px_bins2": v[4],
             "fft32_item": {n: v[5 + q] for q, n in enumerate(lens)},
-            "fft64_item": {n: v[12 + q] for q, n in enumerate(lens)}, "measured": bool(measured.value)}
+            "fft64_item": {n: v[12 + q] for q, n in enumerate(lens)},
+            "ntt_item": {n: v[19 + q] for q, n in enumerate(lens[:4])}, "decode_ntt_per_px_bin": v[23],
+            "measured": bool(measured.value)}
 
 
 def debug_tile_values(img, mask, off, L: int, n_t: int, n_r: int, precision: int, ty: int, tx: int):
@@ -318,7 +320,7 @@ def debug_tile_values(img, mask, off, L: int, n_t: int, n_r: int, precision: int
     mask, off = _se_arrays(mask, off)
     k = mask.shape[0]
     T = n_t - k + 1
-    bins = n_r // 2 + 1
+    bins = n_r if int(precision) == 2 else n_r // 2 + 1
     dst = np.zeros(2 * bins * T * T, np.float64)
     with torch.cuda.device(img.device):
         _bind_stream(img.device)

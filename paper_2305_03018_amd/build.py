@@ -11,7 +11,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 BUILD = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libmd.so")
-SOURCES = ["md_fft.hip", "md_direct.hip", "md_runtime.hip"]
+SOURCES = ["md_fft.hip", "md_direct.hip", "md_ntt.hip", "md_runtime.hip"]
 
 HIP_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall",

@@ -42,7 +42,18 @@ struct TwF {
     float2 hi, lo;
 };
 
+// Exact transform path modulo the prime kNttP = 7 * 2^20 + 1 (primitive root
+// kNttG): spatial lengths 16..kNttMaxN in LDS, range lengths n | kNttP - 1
+// (2^a or 7 * 2^a) up to kNttMaxNr; the spatial twiddles are powers of a
+// primitive kNttTw-th root of unity.
+constexpr uint32_t kNttP = 7340033u;
+constexpr uint32_t kNttG = 3u;
+constexpr int kNttTw = 1024;
+constexpr int kNttMaxN = 128;
+constexpr int kNttMaxNr = 1024;
+
 enum : int { kPathFFT = 1, kPathDirect = 2 };
+enum : int { kPrecFP32 = 0, kPrecFP64 = 1, kPrecNTT = 2 };
 enum : int { kFbNone = 0, kFbFFT64 = 1 };
 
 // One job as the kernels see it.  Complex arrays are float2 in the FP32 form
@@ -54,7 +65,7 @@ struct JobDev {
     int path;                    // kPathFFT / kPathDirect
     // transform plan
     int nt, T, nr, bins, tiles_x, tiles_y;
-    int dbl;                     // 1: transforms in FP64
+    int dbl;                     // kPrecFP32 / kPrecFP64 / kPrecNTT (transform arithmetic)
     double scale;                // 1 / (nt^2 * nr)
     const void *se_spec;         // [bins][nt][nt] spectrum of the SE umbra
     const void *enc;             // [bins][L]  exp(-2 pi i (v m mod nr) / nr)
@@ -78,6 +89,11 @@ struct JobDev {
     int dir_nsteps;
     int kpad;
     int dir_pack;                // 1: 16-bit packed form (all sums fit in int16)
+    // exact transform path (dbl == kPrecNTT): se_spec / enc / dec hold uint32
+    // residues mod kNttP, nr == bins == n, dec_pitch = n rounded up to 8
+    const uint32_t *ntt_spec_s;  // Shoup companions of se_spec
+    const uint32_t *ntt_dec_s;   // Shoup companions of dec
+    int ntt_dtop;                // largest possible degree: (L-1) + max offset
     int dir_bx, dir_by;          // direct-path blocks per row / column
 };
 
@@ -128,6 +144,16 @@ hipError_t launch_fallback(int nt64, const JobDev *jobs, const int2 *fb_list, co
                            double2 *slots, size_t slot_elems, int grid, const double2 *tw64, double2 *slabs,
                            hipStream_t s);
 size_t direct_lds_bytes(int k, int kpad, int pack, int sel);
+// exact transform path (md_ntt.hip)
+int ntt_block_threads(int nt);
+size_t ntt_lds_bytes(int nt);
+hipError_t launch_ntt(int nt, const JobDev *jobs, const Seg *segs, int nseg, long long nitems, int grid,
+                      const uint32_t *tw, const uint32_t *tws, StatsDev *st, hipStream_t s);
+hipError_t launch_ntt_decode(const JobDev *jobs, const Seg *segs, int nseg, long long nitems, int grid,
+                             hipStream_t s);
+hipError_t launch_ntt_se_spectrum(const uint8_t *mask_d, const int32_t *off_d, int k, int nt, int n,
+                                  const uint32_t *rpow, const uint32_t *tw, uint32_t scale, uint32_t *work,
+                                  uint32_t *spec, uint32_t *spec_s, hipStream_t s);
 constexpr size_t kLdsBytes = 160 * 1024;
 int direct_block_rows(int pack);
 int fft_block_threads(int nt, int dbl);

@@ -92,6 +92,17 @@ struct SESpec {
     DevBuf s32, s64;
 };
 
+// Exact transform path: range-axis tables for (n, L) and an SE spectrum per
+// (SE, nt, n), residues mod kNttP with Shoup companions.
+struct NttRange {
+    DevBuf enc, rpow, dec, dec_s;   // enc [n][L]; rpow [n] = w_n^e; dec [rows][dp] = n^-1 w_n^(-d m)
+    int dp = 0;
+};
+
+struct NttSpec {
+    DevBuf spec, spec_s;            // [n][nt][nt]
+};
+
 struct DirSE {
     DevBuf sek, sek16, rows, steps;
     int kpad = 0, nsteps = 0;
@@ -167,13 +178,16 @@ struct Exec {
 // Cost model (nanoseconds of whole-GPU time).  The constants are replaced by
 // measured rates when the autotuner has run on this device.
 // values reported by md_cost_model and persisted in the tune file
-constexpr int kCostValues = 19;
+constexpr int kCostValues = 24;
 
 struct CostModel {
     // per (tile, bin) item, index log2(nt): FP32 / FP64
-    double fft_item[2][11] = {{0, 0, 0, 0, 2.0, 8.0, 30.0, 130.0, 700.0, 3200.0, 14000.0},
-                              {0, 0, 0, 0, 5.0, 20.0, 75.0, 900.0, 3800.0, 16000.0, 70000.0}};
-    double dec_unit[2] = {1.5e-3, 3.0e-3};   // per pixel * (padded bins)^2
+    // index 0 FP32, 1 FP64, 2 exact (mod p; lengths up to kNttMaxN)
+    double fft_item[3][11] = {{0, 0, 0, 0, 2.0, 8.0, 30.0, 130.0, 700.0, 3200.0, 14000.0},
+                              {0, 0, 0, 0, 5.0, 20.0, 75.0, 900.0, 3800.0, 16000.0, 70000.0},
+                              {0, 0, 0, 0, 3.0, 12.0, 45.0, 200.0, 0, 0, 0}};
+    // FP: per pixel * (padded bins)^2; exact: per pixel * n (one degree block)
+    double dec_unit[3] = {1.5e-3, 3.0e-3, 5.0e-2};
     // direct window: per output pixel * SE cells stepped through (16-bit
     // packed / 32-bit form), and per staged image word
     double dir_cell[2] = {2.5e-5, 5.0e-5};
@@ -195,6 +209,9 @@ struct Ctx {
     CostModel cost;
     std::map<std::pair<int, int>, std::unique_ptr<RangeTables>> ranges;
     std::unordered_map<std::string, std::unique_ptr<SESpec>> spectra;
+    std::map<std::pair<int, int>, std::unique_ptr<NttRange>> nranges;
+    std::unordered_map<std::string, std::unique_ptr<NttSpec>> nspectra;
+    uint32_t *ntw = nullptr, *ntws = nullptr;   // w_kNttTw^j and Shoup companions
     std::unordered_map<std::string, std::unique_ptr<DirSE>> dirse;
     std::unordered_map<std::string, std::unique_ptr<Exec>> execs;
     DevBuf se_work, se_in;
@@ -221,6 +238,33 @@ struct Ctx {
 // been torn down at exit.  md_release frees everything explicitly.
 Ctx &g = *new Ctx;
 
+// arithmetic mod kNttP on the host (table generation)
+uint32_t pmul(uint64_t a, uint64_t b) { return (uint32_t)(a * b % kNttP); }
+uint32_t ppow(uint64_t a, uint64_t e) {
+    uint64_t r = 1;
+    a %= kNttP;
+    while (e) {
+        if (e & 1) r = r * a % kNttP;
+        a = a * a % kNttP;
+        e >>= 1;
+    }
+    return (uint32_t)r;
+}
+uint32_t pinv(uint32_t a) { return ppow(a, kNttP - 2); }
+uint32_t shoup(uint32_t w) { return (uint32_t)(((uint64_t)w << 32) / kNttP); }
+
+// Smallest range length n >= nmin that divides kNttP - 1 = 7 * 2^20 (a power
+// of two or 7 times one), 0 if it would exceed kNttMaxNr.
+int ntt_length(long long nmin) {
+    int best = 0;
+    for (int a = 0; a <= 20; ++a)
+        for (int c : {1, 7}) {
+            const long long n = (long long)c << a;
+            if (n >= nmin && n <= kNttMaxNr && (best == 0 || n < best)) best = (int)n;
+        }
+    return best;
+}
+
 int ilog2i(int n) {
     int l = 0;
     while ((1 << l) < n) ++l;
@@ -242,6 +286,22 @@ int init() {
     MD_HIP(hipMalloc(&g.st_d, sizeof(StatsDev)));
     MD_HIP(hipHostMalloc((void **)&g.st_h, sizeof(StatsDev), 0));
     MD_HIP(launch_twiddles(g.tw64, g.tw32, nullptr));
+    {
+        // spatial twiddles of the exact path: powers of a primitive
+        // kNttTw-th root of unity mod kNttP
+        std::vector<uint32_t> w(kNttTw), ws(kNttTw);
+        const uint32_t root = ppow(kNttG, (kNttP - 1) / kNttTw);
+        uint32_t x = 1;
+        for (int j = 0; j < kNttTw; ++j) {
+            w[j] = x;
+            ws[j] = shoup(x);
+            x = pmul(x, root);
+        }
+        MD_HIP(hipMalloc(&g.ntw, sizeof(uint32_t) * kNttTw));
+        MD_HIP(hipMalloc(&g.ntws, sizeof(uint32_t) * kNttTw));
+        MD_HIP(hipMemcpy(g.ntw, w.data(), sizeof(uint32_t) * kNttTw, hipMemcpyHostToDevice));
+        MD_HIP(hipMemcpy(g.ntws, ws.data(), sizeof(uint32_t) * kNttTw, hipMemcpyHostToDevice));
+    }
     MD_HIP(launch_zero(g.st_d, sizeof(StatsDev), nullptr));
     MD_HIP(hipDeviceSynchronize());
     g.device = dev;
@@ -466,6 +526,83 @@ int get_spectrum(const SEData &se, int nt, int nr, bool need32, bool need64, SES
     return MD_OK;
 }
 
+// Range-axis tables of the exact path for range length n and L grey values:
+// enc[m][v] = w_n^(v m), rpow[e] = w_n^e, dec[m][d] = n^-1 w_n^(-d m) with
+// pitch dp = n rounded up to 8 and rows padded to a multiple of 16 (zeros).
+int get_nrange(int n, int L, NttRange **out) {
+    auto key = std::make_pair(n, L);
+    auto it = g.nranges.find(key);
+    if (it != g.nranges.end()) {
+        *out = it->second.get();
+        return MD_OK;
+    }
+    auto rt = std::make_unique<NttRange>();
+    const uint32_t wn = ppow(kNttG, (kNttP - 1) / n), ninv = pinv((uint32_t)n);
+    std::vector<uint32_t> pw(n);
+    uint32_t x = 1;
+    for (int e = 0; e < n; ++e) {
+        pw[e] = x;
+        x = pmul(x, wn);
+    }
+    std::vector<uint32_t> enc((size_t)n * L);
+    for (int m = 0; m < n; ++m)
+        for (int v = 0; v < L; ++v) enc[(size_t)m * L + v] = pw[(size_t)((long long)v * m % n)];
+    rt->dp = (n + 7) / 8 * 8;
+    const int rows = (n + 15) / 16 * 16;
+    std::vector<uint32_t> dec((size_t)rows * rt->dp, 0), decs((size_t)rows * rt->dp, 0);
+    for (int m = 0; m < n; ++m)
+        for (int d = 0; d < n; ++d) {
+            const uint32_t w = pmul(ninv, pw[(size_t)((n - (long long)d * m % n) % n)]);
+            dec[(size_t)m * rt->dp + d] = w;
+            decs[(size_t)m * rt->dp + d] = shoup(w);
+        }
+    MD_TRY(rt->enc.ensure(enc.size() * 4));
+    MD_TRY(rt->rpow.ensure(pw.size() * 4));
+    MD_TRY(rt->dec.ensure(dec.size() * 4));
+    MD_TRY(rt->dec_s.ensure(decs.size() * 4));
+    MD_HIP(hipMemcpy(rt->enc.p, enc.data(), enc.size() * 4, hipMemcpyHostToDevice));
+    MD_HIP(hipMemcpy(rt->rpow.p, pw.data(), pw.size() * 4, hipMemcpyHostToDevice));
+    MD_HIP(hipMemcpy(rt->dec.p, dec.data(), dec.size() * 4, hipMemcpyHostToDevice));
+    MD_HIP(hipMemcpy(rt->dec_s.p, decs.data(), decs.size() * 4, hipMemcpyHostToDevice));
+    *out = rt.get();
+    g.nranges[key] = std::move(rt);
+    return MD_OK;
+}
+
+// SE spectrum of the exact path at spatial length nt and range length n,
+// scaled by nt^-2.
+int get_nspectrum(const SEData &se, int nt, int n, const NttRange *rt, NttSpec **out) {
+    std::string key = se.key;
+    key.append((const char *)&nt, sizeof nt);
+    key.append((const char *)&n, sizeof n);
+    auto it = g.nspectra.find(key);
+    if (it != g.nspectra.end()) {
+        *out = it->second.get();
+        return MD_OK;
+    }
+    auto sp = std::make_unique<NttSpec>();
+    const int k = se.k;
+    const size_t nspec = (size_t)n * nt * nt;
+    MD_TRY(sp->spec.ensure(nspec * 4));
+    MD_TRY(sp->spec_s.ensure(nspec * 4));
+    MD_TRY(g.se_work.ensure((size_t)n * k * nt * 4));
+    const size_t kk = (size_t)k * k;
+    MD_TRY(g.se_in.ensure(kk * (sizeof(int32_t) + 1) + 64));
+    MD_HIP(hipStreamSynchronize(g.stream));   // se_in may still be read by an earlier build
+    int32_t *off_d = (int32_t *)g.se_in.p;
+    uint8_t *mask_d = (uint8_t *)((char *)g.se_in.p + kk * sizeof(int32_t));
+    MD_HIP(hipMemcpy(off_d, se.off.data(), kk * sizeof(int32_t), hipMemcpyHostToDevice));
+    MD_HIP(hipMemcpy(mask_d, se.mask.data(), kk, hipMemcpyHostToDevice));
+    const uint32_t scale = pinv(pmul((uint32_t)nt, (uint32_t)nt));
+    MD_HIP(launch_ntt_se_spectrum(mask_d, off_d, k, nt, n, (const uint32_t *)rt->rpow.p, g.ntw, scale,
+                                  (uint32_t *)g.se_work.p, (uint32_t *)sp->spec.p, (uint32_t *)sp->spec_s.p,
+                                  g.stream));
+    MD_HIP(hipStreamSynchronize(g.stream));
+    *out = sp.get();
+    g.nspectra[key] = std::move(sp);
+    return MD_OK;
+}
+
 // Correlation-order offsets for the direct window (the effective SE
 // reflected), as int32 and as packed 16-bit pairs, plus each row's span of
 // active cells.
@@ -535,6 +672,12 @@ double fft_cost(const md_job &j, int nt, int nr, int dbl) {
     const int T = nt - j.k + 1;
     if (T < 1) return INFINITY;
     const long long tiles = (long long)((j.H + T - 1) / T) * ((j.W + T - 1) / T);
+    if (dbl == kPrecNTT) {
+        if (nt > kNttMaxN) return INFINITY;
+        const double item = g.cost.fft_item[2][ilog2i(nt)];
+        if (item <= 0) return INFINITY;
+        return tiles * (double)nr * item + (double)tiles * T * T * nr * g.cost.dec_unit[2];
+    }
     const int bins = nr / 2 + 1;
     const double item = g.cost.fft_item[dbl][ilog2i(nt)];
     if (item <= 0) return INFINITY;
@@ -550,18 +693,29 @@ int plan_job(const md_job &j, const SEData &se, Plan &p) {
             return fail(MD_ERR_ARG, "forced range length %d < (L-1)+max offset+1 = %lld", g.opt.nr, nr_min);
         nr = g.opt.nr;
     }
-    const int dbl = g.opt.precision == 1 ? 1 : 0;
+    const int dbl = g.opt.precision;   // kPrecFP32 / kPrecFP64 / kPrecNTT
+    bool ntt_ok = true;
+    if (dbl == kPrecNTT) {
+        // a range length that divides p - 1 (forced lengths must, too)
+        if (g.opt.nr > 0) {
+            if (ntt_length(nr) != nr)
+                return fail(MD_ERR_ARG, "range length %d of the exact path must be 2^a or 7*2^a, <= %d", nr, kNttMaxNr);
+        } else {
+            nr = ntt_length(nr_min);
+        }
+        ntt_ok = nr > 0;
+    }
     p = Plan();
     p.dbl = dbl;
     p.nr = nr;
-    p.bins = nr / 2 + 1;
+    p.bins = dbl == kPrecNTT ? nr : nr / 2 + 1;
     const bool pack16 = (long long)(j.L - 1) + se.maxoff <= 16383;
     const bool dir_ok = j.k <= kMaxDirectK;
     p.cost_dir = dir_ok ? dir_cost(j, se, pack16 ? 1 : 0) : INFINITY;
     // transform plan: best spatial length by the cost model
     double best = INFINITY;
     int best_nt = 0;
-    const bool fft_ok = nr_min <= 4096 && se.ncells > 0;
+    const bool fft_ok = nr_min <= 4096 && se.ncells > 0 && ntt_ok;
     for (int nt = 16; fft_ok && nt <= kMaxN; nt *= 2) {
         if (g.opt.tile > 0 && nt != g.opt.tile) continue;
         const double cst = fft_cost(j, nt, nr, dbl);
@@ -572,7 +726,9 @@ int plan_job(const md_job &j, const SEData &se, Plan &p) {
     }
     p.cost_fft = best;
     if (g.opt.path == kPathFFT) {
-        if (!fft_ok) return fail(MD_ERR_UNSUPPORTED, "FFT path needs 1 <= SE cells and (L-1)+max offset+1 <= 4096");
+        if (!fft_ok)
+            return fail(MD_ERR_UNSUPPORTED, "FFT path needs 1 <= SE cells and (L-1)+max offset+1 <= %d",
+                        dbl == kPrecNTT ? kNttMaxNr : 4096);
         if (!best_nt) return fail(MD_ERR_UNSUPPORTED, "no FFT tile length fits k=%d (tile %d)", j.k, g.opt.tile);
         p.path = kPathFFT;
     } else if (g.opt.path == kPathDirect) {
@@ -587,7 +743,7 @@ int plan_job(const md_job &j, const SEData &se, Plan &p) {
     p.T = best_nt - j.k + 1;
     p.tiles_x = (j.W + p.T - 1) / p.T;
     p.tiles_y = (j.H + p.T - 1) / p.T;
-    if (!dbl) {
+    if (dbl == kPrecFP32) {
         // exact recompute of ambiguous tiles in FP64: the smallest length
         // whose tile covers the FP32 tile, else the largest
         p.fb_mode = kFbFFT64;
@@ -605,6 +761,11 @@ int plan_job(const md_job &j, const SEData &se, Plan &p) {
 // ---------------------------------------------------------------------------
 // executor
 // ---------------------------------------------------------------------------
+// bytes of one transform-domain value
+size_t elem_bytes(int dbl) {
+    return dbl == kPrecNTT ? sizeof(uint32_t) : dbl == kPrecFP64 ? sizeof(double2) : sizeof(float2);
+}
+
 int occupancy_grid(long long nitems, size_t lds, int threads) {
     int per_cu = 2048 / threads;
     if (lds > 0) per_cu = std::min<int>(per_cu, (int)((160 * 1024) / lds));
@@ -686,6 +847,29 @@ int build_exec(const md_job *jobs, int n, const std::vector<SEData> &ses, Exec &
             continue;
         }
         ++ex.n_fft;
+        if (p.dbl == kPrecNTT) {
+            NttRange *nrt = nullptr;
+            MD_TRY(get_nrange(p.nr, j.L, &nrt));
+            NttSpec *nsp = nullptr;
+            MD_TRY(get_nspectrum(ses[i], p.nt, p.nr, nrt, &nsp));
+            d.nt = p.nt;
+            d.T = p.T;
+            d.nr = p.nr;
+            d.bins = p.bins;
+            d.tiles_x = p.tiles_x;
+            d.tiles_y = p.tiles_y;
+            d.dbl = kPrecNTT;
+            d.se_spec = nsp->spec.p;
+            d.ntt_spec_s = (const uint32_t *)nsp->spec_s.p;
+            d.enc = nrt->enc.p;
+            d.dec = nrt->dec.p;
+            d.ntt_dec_s = (const uint32_t *)nrt->dec_s.p;
+            d.dec_pitch = nrt->dp;
+            d.ntt_dtop = (j.L - 1) + ses[i].maxoff;
+            d.fb_mode = kFbNone;
+            ex.fft_tiles += (long long)p.tiles_x * p.tiles_y;
+            continue;
+        }
         RangeTables *rt = nullptr;
         MD_TRY(get_range(p.nr, j.L, &rt));
         SESpec *sp = nullptr;
@@ -765,7 +949,7 @@ int build_exec(const md_job *jobs, int n, const std::vector<SEData> &ses, Exec &
     for (int i = 0; i < n; ++i) {
         const Plan &p = ex.plans[i];
         if (p.path != kPathFFT) continue;
-        const size_t per_tile = (size_t)p.bins * p.T * p.T * (p.dbl ? sizeof(double2) : sizeof(float2));
+        const size_t per_tile = (size_t)p.bins * p.T * p.T * elem_bytes(p.dbl);
         const int ntiles = p.tiles_x * p.tiles_y;
         int t = 0;
         while (t < ntiles) {
@@ -794,7 +978,7 @@ int build_exec(const md_job *jobs, int n, const std::vector<SEData> &ses, Exec &
         for (auto &ch : wave_chunks[w]) {
             const int i = ch.first, tile0 = ch.second.first, nt_ = ch.second.second;
             const Plan &p = ex.plans[i];
-            const size_t per_tile = (size_t)p.bins * p.T * p.T * (p.dbl ? sizeof(double2) : sizeof(float2));
+            const size_t per_tile = (size_t)p.bins * p.T * p.T * elem_bytes(p.dbl);
             Seg s{};
             s.job = i;
             s.tile0 = tile0;
@@ -802,16 +986,19 @@ int build_exec(const md_job *jobs, int n, const std::vector<SEData> &ses, Exec &
             s.pblocks = (p.T * p.T + kDecThreads * kDecPixPerThread - 1) / (kDecThreads * kDecPixPerThread);
             s.y = (char *)ex.ybuf.p + off;
             off += per_tile * nt_;
-            const double esz = p.dbl ? 16.0 : 8.0, N2 = (double)p.nt * p.nt, TT = (double)p.T * p.T;
+            const bool ntt = p.dbl == kPrecNTT;
+            const double esz = (double)elem_bytes(p.dbl), N2 = (double)p.nt * p.nt, TT = (double)p.T * p.T;
             const double items = (double)nt_ * p.bins;
             Group *gf = find_group(wv.fft, p.nt, p.dbl, 0);
             s.item0 = gf->nitems;
             gf->segs.push_back(s);
             gf->nitems += (long long)nt_ * p.bins;
             gf->alg_bytes += items * TT * esz + (double)nt_ * N2 * 4.0;
-            gf->alg_ops += items * (2.0 * 5.0 * N2 * log2(N2) + 6.0 * N2);
+            // FP: flops of the forward and inverse 2-D FFTs and the product;
+            // exact: modular products (one per butterfly and per point)
+            gf->alg_ops += ntt ? items * (N2 * log2(N2) + N2) : items * (2.0 * 5.0 * N2 * log2(N2) + 6.0 * N2);
             gf->units += items;
-            Group *gd = find_group(wv.dec, 0, p.dbl, decode_group_variant(p.bins, p.dbl));
+            Group *gd = find_group(wv.dec, 0, p.dbl, ntt ? 0 : decode_group_variant(p.bins, p.dbl));
             s.item0 = gd->nitems;
             gd->segs.push_back(s);
             gd->nitems += (long long)nt_ * s.pblocks;
@@ -822,9 +1009,15 @@ int build_exec(const md_job *jobs, int n, const std::vector<SEData> &ses, Exec &
                 inside += (double)std::min(p.T, jobs[i].H - ty * p.T) * std::min(p.T, jobs[i].W - tx * p.T);
             }
             gd->alg_bytes += inside * (p.bins * esz + 4.0);
-            gd->alg_ops += inside * p.nr * p.bins * 4.0;
-            const double pb = dec_padded_bins(p.bins, p.dbl);
-            gd->units += (double)nt_ * TT * pb * pb;
+            if (ntt) {
+                // one block of 8 degrees per pixel, over all n bins
+                gd->alg_ops += inside * p.nr * 8.0;
+                gd->units += (double)nt_ * TT * p.nr;
+            } else {
+                gd->alg_ops += inside * p.nr * p.bins * 4.0;
+                const double pb = dec_padded_bins(p.bins, p.dbl);
+                gd->units += (double)nt_ * TT * pb * pb;
+            }
         }
         ex.waves.push_back(std::move(wv));
     }
@@ -846,6 +1039,10 @@ int build_exec(const md_job *jobs, int n, const std::vector<SEData> &ses, Exec &
     for (auto &gr : ex.direct) place(gr, kDirThreads, gr.lds);
     for (auto &wv : ex.waves) {
         for (auto &gr : wv.fft) {
+            if (gr.dbl == kPrecNTT) {
+                place(gr, ntt_block_threads(gr.nt), ntt_lds_bytes(gr.nt));
+                continue;
+            }
             place(gr, fft_block_threads(gr.nt, gr.dbl), fft_lds_bytes(gr.nt, gr.dbl));
             if (gr.nt > (gr.dbl ? kMaxLdsN64 : kMaxLdsN32)) {
                 auto b = std::make_unique<DevBuf>();
@@ -945,6 +1142,13 @@ int enqueue(Exec &ex, hipStream_t s, bool skip_decode = false, bool capturing = 
     const float band = (float)g.opt.band;
     for (auto &wv : ex.waves) {
         for (auto &gr : wv.fft) {
+            if (gr.dbl == kPrecNTT) {
+                ProfScope ps(prof, s, "ntt_n" + std::to_string(gr.nt), gr.alg_bytes, gr.alg_ops, gr.units);
+                MD_HIP(launch_ntt(gr.nt, ex.jobs_d, gr.segs_d, (int)gr.segs.size(), gr.nitems, gr.grid, g.ntw, g.ntws,
+                                  g.st_d, s));
+                ps.done();
+                continue;
+            }
             ProfScope ps(prof, s, std::string(gr.dbl ? "fft64_n" : "fft32_n") + std::to_string(gr.nt), gr.alg_bytes,
                          gr.alg_ops, gr.units);
             MD_HIP(launch_fft(gr.nt, gr.dbl, ex.jobs_d, gr.segs_d, (int)gr.segs.size(), gr.nitems, gr.grid, g.tw32,
@@ -953,6 +1157,12 @@ int enqueue(Exec &ex, hipStream_t s, bool skip_decode = false, bool capturing = 
         }
         if (skip_decode) continue;
         for (auto &gr : wv.dec) {
+            if (gr.dbl == kPrecNTT) {
+                ProfScope ps(prof, s, "decode_ntt", gr.alg_bytes, gr.alg_ops, gr.units);
+                MD_HIP(launch_ntt_decode(ex.jobs_d, gr.segs_d, (int)gr.segs.size(), gr.nitems, gr.grid, s));
+                ps.done();
+                continue;
+            }
             ProfScope ps(prof, s, gr.dbl ? "decode64" : "decode32", gr.alg_bytes, gr.alg_ops, gr.units);
             MD_HIP(launch_decode(gr.big, gr.dbl, ex.jobs_d, gr.segs_d, (int)gr.segs.size(), gr.nitems, gr.grid,
                                  band, (unsigned int *)ex.flags.p, (int2 *)ex.list.p, g.st_d, s));
@@ -1066,6 +1276,13 @@ int autotune_body() {
                                &g.cost.dec_unit[prec], nullptr));
         }
     }
+    // exact path: lengths 16..128 and its decode
+    for (int nt = 16; nt <= kNttMaxN; nt *= 2) {
+        MD_TRY(measure(std::min(nt / 8 * 2 + 1, 33), 16, 1024, kPathFFT, kPrecNTT, nt, "ntt_n" + std::to_string(nt),
+                       nullptr, &g.cost.fft_item[2][ilog2i(nt)], nullptr));
+        if (nt == 64)
+            MD_TRY(measure(17, 16, 1024, kPathFFT, kPrecNTT, nt, "decode_ntt", nullptr, &g.cost.dec_unit[2], nullptr));
+    }
     return MD_OK;
 }
 
@@ -1095,6 +1312,8 @@ bool load_tune_file() {
         else if (k == "direct_stage") c.dir_stage = v, ++got;
         else if (k == "decode32") c.dec_unit[0] = v, ++got;
         else if (k == "decode64") c.dec_unit[1] = v, ++got;
+        else if (k == "decode_ntt") c.dec_unit[2] = v, ++got;
+        else if (k.rfind("ntt_n", 0) == 0) c.fft_item[2][ilog2i(atoi(k.c_str() + 5))] = v, ++got;
         else if (k.rfind("fft32_n", 0) == 0) c.fft_item[0][ilog2i(atoi(k.c_str() + 7))] = v, ++got;
         else if (k.rfind("fft64_n", 0) == 0) c.fft_item[1][ilog2i(atoi(k.c_str() + 7))] = v, ++got;
     }
@@ -1114,6 +1333,8 @@ void save_tune_file() {
             g.cost.dir_cell[0], g.cost.dir_cell[1], g.cost.dir_stage, g.cost.dec_unit[0], g.cost.dec_unit[1]);
     for (int nt = 16; nt <= kMaxN; nt *= 2) fprintf(f, "fft32_n%d %.9g\n", nt, g.cost.fft_item[0][ilog2i(nt)]);
     for (int nt = 16; nt <= kMaxN; nt *= 2) fprintf(f, "fft64_n%d %.9g\n", nt, g.cost.fft_item[1][ilog2i(nt)]);
+    for (int nt = 16; nt <= kNttMaxN; nt *= 2) fprintf(f, "ntt_n%d %.9g\n", nt, g.cost.fft_item[2][ilog2i(nt)]);
+    fprintf(f, "decode_ntt %.9g\n", g.cost.dec_unit[2]);
     fclose(f);
 }
 
@@ -1311,7 +1532,7 @@ int md_set_option(int key, double v) {
     Options &o = g.opt;
     switch (key) {
         case MD_OPT_PRECISION:
-            if (v != 0 && v != 1) return fail(MD_ERR_ARG, "precision must be 0 or 1");
+            if (v != 0 && v != 1 && v != 2) return fail(MD_ERR_ARG, "precision must be 0, 1 or 2");
             o.precision = (int)v;
             break;
         case MD_OPT_BAND:
@@ -1412,6 +1633,8 @@ int md_cost_model(double *dst, int n, int *measured) {
     dst[4] = g.cost.dec_unit[1];
     for (int q = 0; q < 7; ++q) dst[5 + q] = g.cost.fft_item[0][4 + q];
     for (int q = 0; q < 7; ++q) dst[12 + q] = g.cost.fft_item[1][4 + q];
+    for (int q = 0; q < 4; ++q) dst[19 + q] = g.cost.fft_item[2][4 + q];
+    dst[23] = g.cost.dec_unit[2];
     *measured = g.cost_measured ? 1 : 0;
     return MD_OK;
 }
@@ -1429,6 +1652,11 @@ int md_release(void) {
     g.morph_b.release();
     if (g.tw64) (void)hipFree(g.tw64);
     if (g.tw32) (void)hipFree(g.tw32);
+    if (g.ntw) (void)hipFree(g.ntw);
+    if (g.ntws) (void)hipFree(g.ntws);
+    g.ntw = g.ntws = nullptr;
+    g.nranges.clear();
+    g.nspectra.clear();
     if (g.st_d) (void)hipFree(g.st_d);
     if (g.st_h) (void)hipHostFree(g.st_h);
     g.tw64 = nullptr;
@@ -1473,12 +1701,15 @@ int md_debug_tile_values(const int32_t *img, int H, int W, int L, const uint8_t 
         const Seg &s = ex.waves[0].fft[0].segs[0];
         const size_t TT = (size_t)p.T * p.T, n = (size_t)p.bins * TT;
         const double sc = 1.0 / ((double)p.nt * p.nt);
-        const size_t esz = p.dbl ? sizeof(double2) : sizeof(float2);
+        const size_t esz = elem_bytes(p.dbl);
         std::vector<char> h(n * esz);
         const char *src = (const char *)s.y + (size_t)(tile - s.tile0) * n * esz;
         if (hipMemcpy(h.data(), src, n * esz, hipMemcpyDeviceToHost) != hipSuccess) { rc = fail(MD_ERR_DEVICE, "copy failed"); break; }
         for (size_t q = 0; q < n; ++q) {
-            if (p.dbl) {
+            if (p.dbl == kPrecNTT) {   // residues mod p, already scaled by n_t^-2
+                dst[2 * q] = ((const uint32_t *)h.data())[q];
+                dst[2 * q + 1] = 0;
+            } else if (p.dbl) {
                 const double2 v = ((const double2 *)h.data())[q];
                 dst[2 * q] = v.x * sc;
                 dst[2 * q + 1] = v.y * sc;

@@ -21,10 +21,12 @@ def test_options_roundtrip_and_errors():
         assert md.get_option("tile") == 64
         assert md.get_option("nr") == 40
         assert md.get_option("precision") == 1
+    with md.options(precision=2):
+        assert md.get_option("precision") == 2
     assert md.get_option("band") == pytest.approx(0.25)
     assert md.get_option("path") == 0
     assert math.isnan(md.get_option(99))
-    for key, bad in (("band", 0.7), ("band", -1), ("path", 3), ("tile", 48), ("precision", 2),
+    for key, bad in (("band", 0.7), ("band", -1), ("path", 3), ("tile", 48), ("precision", 3),
                      ("nr", 4097), ("nr", 2.5), ("workspace_mb", 0), (99, 1)):
         with pytest.raises(md.MDError) as ei:
             md.set_option(key, bad)

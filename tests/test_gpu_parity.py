@@ -16,7 +16,8 @@ pytestmark = pytest.mark.gpu
 FFT64 = dict(precision=1, path=1)
 FFT32 = dict(precision=0, path=1)
 DIRECT = dict(path=2)
-MODES = {"fft64": FFT64, "fft32": FFT32, "direct": DIRECT}
+NTT = dict(precision=2, path=1)
+MODES = {"fft64": FFT64, "fft32": FFT32, "direct": DIRECT, "ntt": NTT}
 
 
 @pytest.fixture(scope="module")
@@ -70,7 +71,7 @@ def embed_1d(values, origin):
 # ----------------------------------------------------------------------------
 # the paper's worked example (Sec. 2.1, Example 2; Sec. 3, Example 5)
 # ----------------------------------------------------------------------------
-@pytest.mark.parametrize("mode", ["fft64", "fft32", "direct"])
+@pytest.mark.parametrize("mode", ["fft64", "fft32", "direct", "ntt"])
 @pytest.mark.parametrize("tile", [0, 16, 64])
 def test_paper_example2(dev, mode, tile):
     mask, off = embed_1d([1, 2, None, 0], 1)
@@ -291,6 +292,31 @@ def test_spectrum_error_report(dev):
         assert rel < tol
 
 
+def test_ntt_exact_counts(dev):
+    """The exact path's transform-domain values of one tile, inverted over
+    the range axis on the host with Python integers, are the exact polynomial
+    coefficients c_x(d) of every degree (not only the top one)."""
+    import torch
+
+    p, g = 7340033, 3
+    job = synthetic.blurred_512(0)
+    img = torch.from_numpy(job.img).to(dev)
+    nt, n = 64, 28                      # (L-1) + max offset + 1 = 23 <= 28 = 7 * 4
+    T = nt - job.k + 1
+    for ty, tx in ((0, 0), (2, 3), (7, 9)):
+        y = md.debug_tile_values(img, job.mask, job.off, job.L, nt, n, 2, ty, tx).real.astype(np.int64)
+        assert y.shape == (n, T * T) and y.min() >= 0 and y.max() < p
+        w = pow(g, (p - 1) // n, p)
+        ninv = pow(n, p - 2, p)
+        ys, xs = np.divmod(np.arange(T * T), T)
+        want = oracle.counts_at(job.img, job.mask, job.off, ty * T + ys, tx * T + xs, n)
+        yl = [[int(v) for v in row] for row in y]
+        for q in range(0, T * T, 7):
+            for d in range(n):
+                c = sum(yl[m][q] * pow(w, (n - d * m % n) % n, p) for m in range(n)) % p * ninv % p
+                assert c == want[q, d], (ty, tx, q, d, c, want[q, d])
+
+
 def test_repeatable(dev):
     job = synthetic.blurred_512(0)
     a, sa = run_job(job, dev, **FFT32)
@@ -355,13 +381,13 @@ def _batch_parity(jobs, outs, sample_rng, full_every=16):
             assert np.array_equal(got[ys, xs], want), f"{job.name}: sampled pixels differ"
 
 
-@pytest.mark.parametrize("mode", ["auto", "fft32", "fft64"])
+@pytest.mark.parametrize("mode", ["auto", "fft32", "fft64", "ntt"])
 def test_uneven_batch_256(dev, mode):
     import torch
 
     jobs = synthetic.uneven_batch(0, 256)
     imgs = [torch.from_numpy(j.img).to(dev) for j in jobs]
-    opts = {"auto": {}, "fft32": FFT32, "fft64": FFT64}[mode]
+    opts = {"auto": {}, "fft32": FFT32, "fft64": FFT64, "ntt": NTT}[mode]
     _say(f"  batch of {len(jobs)} mode={mode}")
     with md.options(**opts):
         outs = md.dilate_batch([(im, j.mask, j.off, j.L, j.op) for im, j in zip(imgs, jobs)])
