@@ -84,6 +84,10 @@ def kernel_of(stage):
         prec, n = ("float" if stage.startswith("fft32") else "double"), int(stage.split("_n")[1])
         big = n > (128 if prec == "float" else 64)
         return f"k_fft{'_big' if big else ''}<{prec}, {n}>"
+    if stage == "decode_ntt":
+        return "k_ntt_decode"
+    if stage.startswith("ntt"):
+        return f"k_ntt<{stage.split('_n')[1]}>"
     if stage.startswith("decode"):
         return f"k_decode<{'float' if stage == 'decode32' else 'double'}>"
     if stage.startswith("recompute64"):
@@ -126,6 +130,12 @@ def roofline_for(stage, prof, workload):
     if stage.startswith("direct"):
         peak = INT16X2_ALU_TOPS if stage == "direct16" else INT32_ALU_TOPS
         return {"bound": "alu", "peak": peak, "unit": "TOP/s", "frac": achieved / peak, **base}
+    if stage.startswith(("ntt", "decode_ntt")):
+        # modular products (Shoup): one 32-bit high multiply (4 issue slots at
+        # quarter rate), two 24-bit multiplies, a subtract and a two-op
+        # reduction on the int32 ALU -- 9 slots each
+        peak = INT32_ALU_TOPS / 9.0
+        return {"bound": "alu", "peak": peak, "unit": "T modmul/s", "frac": achieved / peak, **base}
     fp64 = stage.startswith(("fft64", "decode64", "recompute64"))
     peak = FP64_VECTOR_TFLOPS if fp64 else FP32_VECTOR_TFLOPS
     return {"bound": "alu", "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak, **base}
@@ -208,7 +218,7 @@ def main():
         cmp = {}
         if not args.no_compare:
             for name, opts in (("fft64", dict(precision=1, path=1)), ("fft32", dict(precision=0, path=1)),
-                               ("direct", dict(precision=0, path=2))):
+                               ("ntt", dict(precision=2, path=1)), ("direct", dict(precision=0, path=2))):
                 m = timed_steps(md, torch, stream, arglist, outs, max(3, args.steps // 4), 1, **opts)
                 cmp[name] = {"ms_per_step": m, "mpx_s": total_px / (m * 1e-3) / 1e6}
                 # per-stage figures of this path (events around every launch)
@@ -259,6 +269,7 @@ def main():
     if cmp:
         line["speedup_vs_fp64_fft"] = cmp["fft64"]["ms_per_step"] / res["headline_ms"]
         line["fp32_fft_vs_fp64_fft"] = cmp["fft64"]["ms_per_step"] / cmp["fft32"]["ms_per_step"]
+        line["exact_ntt_vs_fp64_fft"] = cmp["fft64"]["ms_per_step"] / cmp["ntt"]["ms_per_step"]
     if not args.no_cpu:
         log("bench: timing the CPU oracle")
         line["cpu_baseline"] = cpu_baseline(jobs, args.cpu_budget)
