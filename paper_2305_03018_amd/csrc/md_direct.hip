@@ -248,28 +248,43 @@ __device__ __forceinline__ void d16_row(s16x2 (&acc)[kDirRX], const s16x2 *in, c
     }
 }
 
+// NS SE offsets of one row at the step's first column (wave-uniform: scalar
+// loads)
+template <int NS>
+__device__ __forceinline__ void d16_se(int (&b)[NS], const int32_t *p) {
+    const auto c = cst(p);
+#pragma unroll
+    for (int sj = 0; sj < NS; ++sj) b[sj] = c[sj];
+}
+
 // One SE row pair (ODD) or the last, even SE row alone (!ODD) over the
-// thread's kD16R output pairs.  be / bo: SE rows 2s and 2s+1 at the step's
-// first column.
-template <int NS, int O, bool ODD>
+// thread's kD16R output pairs, with the offsets be / bo of SE rows 2s and
+// 2s+1 already in registers.  issue() runs after the first output pair: its
+// arithmetic is the first use of the registers that the previous call's
+// issue() filled, so their wait comes before the loads that issue() starts,
+// and those loads stay in flight over the rest of the pair.
+template <int NS, int O, bool ODD, typename F>
 __device__ __forceinline__ void d16_pair(s16x2 (&acc)[kD16R][kDirRX], const int (&win)[kD16R + 1][D16<NS, O>::NW],
-                                         const int32_t *be, const int32_t *bo) {
+                                         const int (&be)[NS], const int (&bo)[NS], F &&issue) {
     constexpr int NU = NS + kDirRX - 1;
-    const auto ce = cst(be);
     s16x2 b[NS];
 #pragma unroll
-    for (int sj = 0; sj < NS; ++sj) b[sj] = __builtin_bit_cast(s16x2, ce[sj]);
+    for (int sj = 0; sj < NS; ++sj) b[sj] = __builtin_bit_cast(s16x2, be[sj]);
 #pragma unroll
     for (int r = 0; r < kD16R; ++r) {
+        if (r == 1) {
+            __builtin_amdgcn_sched_barrier(0);
+            issue();
+            __builtin_amdgcn_sched_barrier(0);
+        }
         s16x2 in[NU];
 #pragma unroll
         for (int t = 0; t < NU; ++t) in[t] = __builtin_bit_cast(s16x2, win[r][O + t]);
         d16_row<NS>(acc[r], in, b);
     }
     if constexpr (ODD) {
-        const auto co = cst(bo);
 #pragma unroll
-        for (int sj = 0; sj < NS; ++sj) b[sj] = __builtin_bit_cast(s16x2, co[sj]);
+        for (int sj = 0; sj < NS; ++sj) b[sj] = __builtin_bit_cast(s16x2, bo[sj]);
 #pragma unroll
         for (int r = 0; r < kD16R; ++r) {
             s16x2 in[NU];
@@ -283,8 +298,11 @@ __device__ __forceinline__ void d16_pair(s16x2 (&acc)[kD16R][kDirRX], const int 
 
 // SE row pairs s0..s1 of one column step.  trow: LDS word row q of the
 // thread at the step's first column minus O; se: SE row 0 at the step's
-// first column.  Word row q+s+kD16R+1 is fetched while pair s computes (one
-// row past the staged block at most, which the LDS allocation covers).
+// first column.  Word row q+s+kD16R+1 and the offsets of SE rows 2s+2,
+// 2s+3 are fetched while pair s computes, so the one wait per pair (LDS and
+// scalar loads share a counter) comes after its arithmetic.  The fetches
+// reach one word row past the staged block and SE row k at most, which the
+// LDS allocation and the SE array's extra row cover.
 template <int NS, int O>
 __device__ __forceinline__ void d16_column(s16x2 (&acc)[kD16R][kDirRX], const int32_t *trow, int P,
                                            const int32_t *se, int kpad, int k, int s0, int s1) {
@@ -293,20 +311,41 @@ __device__ __forceinline__ void d16_column(s16x2 (&acc)[kD16R][kDirRX], const in
 #pragma unroll
     for (int r = 0; r <= kD16R; ++r) d16_load<NW>(win[r], trow + (s0 + r) * P);
     const int sfull = min(s1, (k - 3) >> 1);   // pairs with both rows inside the SE
+    int be[NS], bo[NS];
+    d16_se<NS>(be, se + 2 * s0 * kpad);
+    d16_se<NS>(bo, se + (2 * s0 + 1) * kpad);
     int s = s0;
-#pragma unroll 2
-    for (; s <= sfull; ++s) {
+    // one pair: offsets in (ce, co), those of the next pair fetched into (ne, no)
+    auto step = [&](const int (&ce)[NS], const int (&co)[NS], int (&ne)[NS], int (&no)[NS]) {
         int nxt[NW];
-        d16_load<NW>(nxt, trow + (s + kD16R + 1) * P);
-        d16_pair<NS, O, true>(acc, win, se + 2 * s * kpad, se + (2 * s + 1) * kpad);
+        d16_pair<NS, O, true>(acc, win, ce, co, [&] {
+            d16_load<NW>(nxt, trow + (s + kD16R + 1) * P);
+            d16_se<NS>(ne, se + (2 * s + 2) * kpad);
+            d16_se<NS>(no, se + (2 * s + 3) * kpad);
+        });
 #pragma unroll
         for (int r = 0; r < kD16R; ++r)
 #pragma unroll
             for (int t = 0; t < NW; ++t) win[r][t] = win[r + 1][t];
 #pragma unroll
         for (int t = 0; t < NW; ++t) win[kD16R][t] = nxt[t];
+        ++s;
+    };
+    // two pairs per trip, the offset registers alternating between them
+    int be2[NS], bo2[NS];
+    while (s < sfull) {
+        step(be, bo, be2, bo2);
+        step(be2, bo2, be, bo);
     }
-    if (s <= s1) d16_pair<NS, O, false>(acc, win, se + 2 * s * kpad, nullptr);   // s = (k-1)/2: SE row k-1
+    if (s == sfull) {
+        step(be, bo, be2, bo2);
+#pragma unroll
+        for (int sj = 0; sj < NS; ++sj) {
+            be[sj] = be2[sj];
+            bo[sj] = bo2[sj];
+        }
+    }
+    if (s <= s1) d16_pair<NS, O, false>(acc, win, be, bo, [] {});   // s = (k-1)/2: SE row k-1 alone
 }
 
 // LDS words of one packed block: word rows of image rows 2p, 2p+1 (low,

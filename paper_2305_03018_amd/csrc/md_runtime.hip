@@ -616,8 +616,9 @@ int get_dirse(const SEData &se, DirSE **out) {
     const int k = se.k;
     d->kpad = (k + kDirRX - 1) / kDirRX * kDirRX;
     // 16 words of padding after the last row: the direct kernel prefetches
-    // past the end of a row's active span
-    std::vector<int32_t> h((size_t)k * d->kpad + 16, kNeg), h16((size_t)k * d->kpad + 16), rows((size_t)2 * k);
+    // past the end of a row's active span; the packed form also reads one
+    // whole row past the SE (SE row k, all minus infinity) ahead of use
+    std::vector<int32_t> h((size_t)k * d->kpad + 16, kNeg), h16((size_t)(k + 1) * d->kpad + 16), rows((size_t)2 * k);
     const uint32_t neg16 = 0xC000C000u;   // -16384 in both lanes
     for (size_t q = 0; q < h16.size(); ++q) h16[q] = (int32_t)neg16;
     for (int i = 0; i < k; ++i) {
