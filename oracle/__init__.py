@@ -66,6 +66,11 @@ def _load():
                                         ctypes.c_int32, _i32p]
         lib.oracle_erode_e.argtypes = [_i32p, ctypes.c_int, ctypes.c_int, _u8p, _i32p, ctypes.c_int,
                                        ctypes.c_int32, _i32p]
+        lib.oracle_dilate3_e.argtypes = [_i32p, ctypes.c_int, ctypes.c_int, ctypes.c_int, _u8p, _i32p,
+                                         ctypes.c_int, ctypes.c_int32, _i32p]
+        lib.oracle_erode3_e.argtypes = lib.oracle_dilate3_e.argtypes
+        lib.oracle_at3.argtypes = [_i32p, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, _u8p, _i32p,
+                                   ctypes.c_int, ctypes.c_int, ctypes.c_int, _i32p, _i32p, _i32p, _i32p]
         lib.oracle_num_threads.restype = ctypes.c_int
         lib.oracle_set_threads.argtypes = [ctypes.c_int]
         _lib = lib
@@ -220,6 +225,58 @@ def morph(op: int, img, mask, off, L: int) -> np.ndarray:
     return MORPH[op](img, mask, off, L)
 
 
+# ----------------------------------------------------------------------------
+# volumes (N = 3: the definitions of Sec. 2.1 for three image axes)
+# ----------------------------------------------------------------------------
+def _prep3(vol, mask, off):
+    vol = np.ascontiguousarray(vol, dtype=np.int32)
+    mask = np.ascontiguousarray(mask, dtype=np.uint8)
+    off = np.ascontiguousarray(off, dtype=np.int32)
+    if vol.ndim != 3 or mask.ndim != 3 or mask.shape != off.shape or len(set(mask.shape)) != 1:
+        raise ValueError("vol must be 3-D and mask/off k x k x k")
+    if mask.shape[0] % 2 != 1:
+        raise ValueError("SE side must be odd")
+    return vol, mask, off
+
+
+def dilate3_e(vol, mask, off, empty: int = 0) -> np.ndarray:
+    """Eq. (6new) over three axes: max of f(x-y)+b(y), `empty` (Eq. (6): 0)
+    where the window is empty."""
+    vol, mask, off = _prep3(vol, mask, off)
+    out = np.empty_like(vol)
+    _load().oracle_dilate3_e(_p(vol, _i32p), *vol.shape, _p(mask, _u8p), _p(off, _i32p), mask.shape[0],
+                             int(empty), _p(out, _i32p))
+    return out
+
+
+def erode3_e(vol, mask, off, empty: int) -> np.ndarray:
+    """Eq. (Erosion) over three axes: min of f(x+y)-b(y), `empty` where the
+    window is empty."""
+    vol, mask, off = _prep3(vol, mask, off)
+    out = np.empty_like(vol)
+    _load().oracle_erode3_e(_p(vol, _i32p), *vol.shape, _p(mask, _u8p), _p(off, _i32p), mask.shape[0],
+                            int(empty), _p(out, _i32p))
+    return out
+
+
+def dilate3(vol, mask, off) -> np.ndarray:
+    return dilate3_e(vol, mask, off, 0)
+
+
+def erode3(vol, mask, off, L: int) -> np.ndarray:
+    return erode3_e(vol, mask, off, L - 1)
+
+
+def at3(vol, mask, off, L: int, op: int, zs, ys, xs) -> np.ndarray:
+    """Volume dilation (op 0) or erosion (op 1) at the listed voxels only."""
+    vol, mask, off = _prep3(vol, mask, off)
+    zs, ys, xs = (np.ascontiguousarray(a, dtype=np.int32) for a in (zs, ys, xs))
+    out = np.empty(zs.shape[0], np.int32)
+    _load().oracle_at3(_p(vol, _i32p), *vol.shape, int(L), _p(mask, _u8p), _p(off, _i32p), mask.shape[0],
+                       int(op), zs.shape[0], _p(zs, _i32p), _p(ys, _i32p), _p(xs, _i32p), _p(out, _i32p))
+    return out
+
+
 def run_job(job) -> np.ndarray:
     """Oracle result for a ``synthetic.Job``."""
     if job.op == 0:
@@ -338,6 +395,57 @@ def method_dilate(img, mask, off) -> np.ndarray:
     conv, lR = method_umbra_conv(img, mask, off)
     c = np.rint(conv)
     hit = c >= 1
+    top = (lR - np.argmax(hit[..., ::-1], axis=-1)).astype(np.int32)
+    return np.where(hit.any(axis=-1), top, 0).astype(np.int32)
+
+
+def poly_dilate_nd(img, mask, off) -> np.ndarray:
+    """poly_dilate for any number of image axes N (the SE has the same N
+    axes, each of odd length, origin at the centre): Theorem 1 applied voxel
+    by voxel.  Tiny inputs only."""
+    img = np.asarray(img)
+    mask = np.asarray(mask)
+    r = np.array([(s - 1) // 2 for s in mask.shape])
+    out = np.zeros(img.shape, np.int32)
+    cells = list(np.ndindex(*mask.shape))
+    for x in np.ndindex(*img.shape):
+        a_list, b_list = [], []
+        for c in cells:
+            s = tuple(np.array(x) - (np.array(c) - r))
+            inside = all(0 <= s[d] < img.shape[d] for d in range(img.ndim))
+            a_list.append(int(img[s]) if inside else NEG_INF)
+            b_list.append(int(off[c]) if mask[c] else NEG_INF)
+        d = maxplus_by_polynomials(a_list, b_list)
+        out[x] = 0 if d == NEG_INF else int(d)
+    return out
+
+
+def method_umbra_conv_nd(img, mask, off) -> tuple[np.ndarray, int]:
+    """Steps 1-2 for N image axes (Sec. 3: an N-dimensional image gives an
+    (N+1)-dimensional umbra): one-hot umbras with lR = max f + max b, full-mode
+    convolution over the N domain axes and the range axis by numpy's fftn in
+    fp64.  Returns the convolution restricted to x in F and lR."""
+    img = np.asarray(img, np.int64)
+    mask = np.asarray(mask).astype(bool)
+    off = np.asarray(off, np.int64)
+    n = img.ndim
+    r = [(s - 1) // 2 for s in mask.shape]
+    lR = int(img.max()) + int(off[mask].max() if mask.any() else 0)
+    fU = umbra(img, np.ones(img.shape, bool), lR)
+    bU = umbra(off, mask, lR)
+    full = tuple(img.shape[d] + mask.shape[d] - 1 for d in range(n)) + (2 * lR + 1,)
+    ax = tuple(range(n + 1))
+    conv = np.fft.ifftn(np.fft.fftn(fU, full, axes=ax) * np.fft.fftn(bU, full, axes=ax), axes=ax).real
+    # the full-mode output index along a domain axis is x + r for the voxel x
+    sl = tuple(slice(r[d], r[d] + img.shape[d]) for d in range(n)) + (slice(0, lR + 1),)
+    return conv[sl], lR
+
+
+def method_dilate_nd(img, mask, off) -> np.ndarray:
+    """Steps 1-3 for N image axes: the umbra convolution, then Eq. (9) -- the
+    highest degree whose rounded coefficient is >= 1, 0 where none is."""
+    conv, lR = method_umbra_conv_nd(img, mask, off)
+    hit = np.rint(conv) >= 1
     top = (lR - np.argmax(hit[..., ::-1], axis=-1)).astype(np.int32)
     return np.where(hit.any(axis=-1), top, 0).astype(np.int32)
 

@@ -155,3 +155,79 @@ void oracle_counts_at(const int32_t *f, int H, int W, const uint8_t *mask,
     }
     *overflow = ovf;
 }
+
+/* ---- volumes (N = 3; Sec. 2.1 states the definitions for N-dimensional
+   images) --------------------------------------------------------------
+   Volumes are D x H x W int32, z slowest; the SE is a k x k x k array (k
+   odd, origin at the centre cell (r, r, r)), cell (a, i, j) is the offset
+   y = (a - r, i - r, j - r), mask[(a*k + i)*k + j] != 0 marks y in B and
+   off[...] is b(y).  Dilation / erosion as above, with x - y (x + y) taken
+   over all three axes. */
+static int vol_px(const int32_t *f, int D, int H, int W, const uint8_t *mask,
+                  const int32_t *off, int k, int sgn, int z, int y, int x, int64_t *v)
+{
+    const int r = (k - 1) / 2;
+    int any = 0;
+    int64_t best = 0;
+    for (int a = 0; a < k; ++a) {
+        const int s0 = z - sgn * (a - r);
+        if (s0 < 0 || s0 >= D) continue;
+        for (int i = 0; i < k; ++i) {
+            const int s1 = y - sgn * (i - r);
+            if (s1 < 0 || s1 >= H) continue;
+            for (int j = 0; j < k; ++j) {
+                const size_t c = ((size_t)a * k + i) * k + j;
+                if (!mask[c]) continue;
+                const int s2 = x - sgn * (j - r);
+                if (s2 < 0 || s2 >= W) continue;
+                const int64_t fv = f[((size_t)s0 * H + s1) * W + s2];
+                /* dilation (sgn = +1): f(x-y) + b(y), largest;
+                   erosion (sgn = -1): f(x+y) - b(y), smallest */
+                const int64_t val = sgn > 0 ? fv + off[c] : fv - off[c];
+                if (!any || (sgn > 0 ? val > best : val < best)) { best = val; any = 1; }
+            }
+        }
+    }
+    *v = best;
+    return any;
+}
+
+void oracle_dilate3_e(const int32_t *f, int D, int H, int W, const uint8_t *mask,
+                      const int32_t *off, int k, int32_t empty, int32_t *out)
+{
+#pragma omp parallel for collapse(2) schedule(dynamic, 1)
+    for (int z = 0; z < D; ++z)
+        for (int y = 0; y < H; ++y)
+            for (int x = 0; x < W; ++x) {
+                int64_t v;
+                out[((size_t)z * H + y) * W + x] =
+                    vol_px(f, D, H, W, mask, off, k, 1, z, y, x, &v) ? (int32_t)v : empty;
+            }
+}
+
+void oracle_erode3_e(const int32_t *f, int D, int H, int W, const uint8_t *mask,
+                     const int32_t *off, int k, int32_t empty, int32_t *out)
+{
+#pragma omp parallel for collapse(2) schedule(dynamic, 1)
+    for (int z = 0; z < D; ++z)
+        for (int y = 0; y < H; ++y)
+            for (int x = 0; x < W; ++x) {
+                int64_t v;
+                out[((size_t)z * H + y) * W + x] =
+                    vol_px(f, D, H, W, mask, off, k, -1, z, y, x, &v) ? (int32_t)v : empty;
+            }
+}
+
+/* Dilation (op 0, 0 if empty) or erosion (op 1, L-1 if empty) at n listed
+   voxels (zs[i], ys[i], xs[i]). */
+void oracle_at3(const int32_t *f, int D, int H, int W, int L, const uint8_t *mask,
+                const int32_t *off, int k, int op, int n, const int32_t *zs,
+                const int32_t *ys, const int32_t *xs, int32_t *out)
+{
+#pragma omp parallel for schedule(static)
+    for (int i = 0; i < n; ++i) {
+        int64_t v;
+        const int any = vol_px(f, D, H, W, mask, off, k, op == 0 ? 1 : -1, zs[i], ys[i], xs[i], &v);
+        out[i] = any ? (int32_t)v : (op == 0 ? 0 : L - 1);
+    }
+}

@@ -181,6 +181,77 @@ def random_job(rng: np.random.Generator, H: int, W: int, L: int, k: int,
     return Job(img, L, mask, off, op, f"rand_{H}x{W}_L{L}_k{k}")
 
 
+# ----------------------------------------------------------------------------
+# volumes (three image axes; SE arrays k x k x k, origin at the centre cell)
+# ----------------------------------------------------------------------------
+@dataclass
+class VolJob:
+    """One volume dilation (op=0) or erosion (op=1) request."""
+
+    vol: np.ndarray          # (D, H, W) int32, values in [0, L-1]
+    L: int
+    mask: np.ndarray         # (k, k, k) uint8
+    off: np.ndarray          # (k, k, k) int32 >= 0, zero where mask == 0
+    op: int = 0
+    name: str = ""
+
+    @property
+    def k(self) -> int:
+        return int(self.mask.shape[0])
+
+
+def ball_mask3(k: int) -> np.ndarray:
+    """Cells (a, i, j) within distance r = (k-1)/2 of the centre."""
+    r = (k - 1) // 2
+    a, i, j = np.mgrid[0:k, 0:k, 0:k]
+    return (((a - r) ** 2 + (i - r) ** 2 + (j - r) ** 2) <= r * r).astype(np.uint8)
+
+
+def cube_mask3(k: int) -> np.ndarray:
+    return np.ones((k, k, k), np.uint8)
+
+
+def bernoulli_mask3(rng: np.random.Generator, k: int, p: float, centre: bool) -> np.ndarray:
+    m = (rng.random((k, k, k)) < p).astype(np.uint8)
+    if centre:
+        m[k // 2, k // 2, k // 2] = 1
+    return m
+
+
+def _offsets3(rng: np.random.Generator, k: int, hi_inclusive: int, mask: np.ndarray) -> np.ndarray:
+    off = rng.integers(0, hi_inclusive + 1, (k, k, k)).astype(np.int32)
+    off[mask == 0] = 0
+    return off
+
+
+def random_vol_job(rng: np.random.Generator, D: int, H: int, W: int, L: int, k: int,
+                   p: float = 0.7, max_off: int | None = None, op: int = 0) -> VolJob:
+    """Generic random volume case for parity tests: i.i.d. uniform voxels,
+    Bernoulli(p) mask (centre not forced), offsets uniform in [0, max_off]."""
+    if max_off is None:
+        max_off = max(1, L // 4)
+    vol = rng.integers(0, L, (D, H, W)).astype(np.int32)
+    mask = bernoulli_mask3(rng, k, p, centre=False)
+    off = _offsets3(rng, k, max_off, mask)
+    return VolJob(vol, L, mask, off, op, f"vol_{D}x{H}x{W}_L{L}_k{k}")
+
+
+def blurred_volume(seed: int = 0, shape=(128, 256, 256), L: int = 16, k: int = 7,
+                   max_off: int = 3, op: int = 0) -> VolJob:
+    """A D x H x W volume with L grey levels: Gaussian-blurred (sigma 2)
+    uniform noise, min-max quantised; k x k x k ball SE with offsets uniform
+    in [0, max_off].  The volume counterpart of blurred_512."""
+    from scipy.ndimage import gaussian_filter
+
+    rng = np.random.default_rng(seed)
+    g = gaussian_filter(rng.random(shape), 2.0, mode="reflect", truncate=3.0)
+    vol = _normalise_to_levels(g, L)
+    mask = ball_mask3(k)
+    off = _offsets3(rng, k, max_off, mask)
+    D, H, W = shape
+    return VolJob(vol, L, mask, off, op, f"blurred_vol_{D}x{H}x{W}_L{L}_ball{k}")
+
+
 WORKLOADS = {
     "small_uniform": small_uniform,
     "blurred_512": blurred_512,
