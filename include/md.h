@@ -83,7 +83,8 @@ typedef enum {
     MD_OPT_PATH = 2,       /* 0: auto (cost model), 1: FFT convolution of umbras,
                               2: direct max-plus window (classical, Eq. (6new)) */
     MD_OPT_TILE = 3,       /* 0: auto, else the spatial FFT length per tile axis,
-                              a power of two in [16, 1024]                      */
+                              a power of two in [8, 1024] (images use 16 and
+                              up, volumes 8, 16 or 32)                           */
     MD_OPT_NR = 4,         /* 0: auto, else the range-axis DFT length; must be at
                               least (L-1) + max offset + 1                       */
     MD_OPT_SYNC = 5,       /* 1 (default): wait for completion in every call    */
@@ -141,6 +142,38 @@ typedef enum {
 
 int md_morph(int op, const int32_t *img, int H, int W, int L, const uint8_t *se_mask,
              const int32_t *se_offsets, int k, int32_t *out);
+
+/* Volumes: dilation and erosion of a three-axis image.  Sec. 2.1 defines
+ * both for N-dimensional images and Sec. 3 turns the N-dimensional dilation
+ * into an (N+1)-dimensional umbra convolution, here a 4-dimensional one.
+ *   - `vol` and `out` are D x H x W int32 DEVICE arrays, z slowest (voxel
+ *     (z, y, x) at (z*H + y)*W + x), owned by the caller; they must not
+ *     overlap.  Values in [0, L-1], 2 <= L <= 2^24.
+ *   - The SE is two k x k x k HOST arrays, (a, i, j) row-major: `se_mask`
+ *     (non-zero = in B) and `se_offsets` (b(y) >= 0 where the mask is set);
+ *     k odd, 1 <= k <= 31, cell (a, i, j) is the offset
+ *     y = (a-r, i-r, j-r), r = (k-1)/2.
+ *   - Dilation: out(x) = max { vol(x-y) + b(y) : y in B, x-y in the volume },
+ *     0 where no cell qualifies; erosion: min { vol(x+y) - b(y) }, L-1 where
+ *     none does (the conventions of md_dilate / md_erode over three axes).
+ *   - Paths (MD_OPT_PATH): the direct window, one 2-D window pass per active
+ *     SE slab, accumulated in registers; or the transform path, which is
+ *     exact: the 4-D umbra convolution by number-theoretic transforms modulo
+ *     7*2^20+1 over cubic tiles of 8, 16 or 32 points per side (MD_OPT_TILE
+ *     forces one) and a range length n >= L + max b of the form 2^a or 7*2^a,
+ *     n <= 1024 (MD_OPT_NR forces one).  MD_OPT_PRECISION does not apply:
+ *     volume transforms always run in the prime field.  Auto (0) picks by the
+ *     cost model.  MD_ERR_UNSUPPORTED if the forced path has no plan.
+ *   - Runs on the library stream after the work already on it (the call
+ *     waits for that work before it rewrites its device tables); with
+ *     MD_OPT_SYNC = 1 it waits for its own work and reports MD_ERR_RANGE for
+ *     a voxel outside [0, L-1] that lies in some output's window (voxels in
+ *     no window affect no output and may go unchecked).  Error behaviour
+ *     otherwise as for md_dilate. */
+int md_dilate3(const int32_t *vol, int D, int H, int W, int L, const uint8_t *se_mask,
+               const int32_t *se_offsets, int k, int32_t *out);
+int md_erode3(const int32_t *vol, int D, int H, int W, int L, const uint8_t *se_mask,
+              const int32_t *se_offsets, int k, int32_t *out);
 
 /* One job of a batch.  Pointer and ownership rules as for md_dilate. */
 typedef struct {

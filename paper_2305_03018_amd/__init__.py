@@ -28,8 +28,10 @@ from ._binding import (  # noqa: F401
     OPT_WORKSPACE_MB,
     debug_tile_values,
     dilate,
+    dilate3,
     dilate_batch,
     erode,
+    erode3,
     exported_symbols,
     get_option,
     get_stats,

@@ -64,6 +64,10 @@ def load():
         f = getattr(lib, name)
         f.argtypes = [vp, i, i, i, u8, vp, i, vp]
         f.restype = i
+    for name in ("md_dilate3", "md_erode3"):
+        f = getattr(lib, name)
+        f.argtypes = [vp, i, i, i, i, u8, vp, i, vp]
+        f.restype = i
     lib.md_dilate_batch.argtypes = [ctypes.POINTER(_Job), i]
     lib.md_dilate_batch.restype = i
     lib.md_set_stream.argtypes = [vp]
@@ -165,6 +169,43 @@ def dilate(img, mask, off, L: int, out=None):
 def erode(img, mask, off, L: int, out=None):
     """Exact erosion: min over the SE of img(x+y) - b(y), L-1 on empty windows."""
     return _run_single("md_erode", img, mask, off, L, out)
+
+
+def _run_volume(fname, vol, mask, off, L, out):
+    import torch
+
+    lib = load()
+    if not isinstance(vol, torch.Tensor) or not vol.is_cuda:
+        raise TypeError("volume must be a torch tensor on a HIP device")
+    if vol.dtype != torch.int32 or vol.dim() != 3:
+        raise TypeError("volume must be a 3-D torch.int32 tensor")
+    vol = vol.contiguous()
+    mask = np.ascontiguousarray(np.asarray(mask), dtype=np.uint8)
+    off = np.ascontiguousarray(np.asarray(off), dtype=np.int32)
+    if mask.ndim != 3 or mask.shape != off.shape or len(set(mask.shape)) != 1:
+        raise ValueError("mask and offsets must be k x k x k arrays of the same shape")
+    if out is None:
+        out = torch.empty_like(vol)
+    elif out.shape != vol.shape or out.dtype != torch.int32 or not out.is_contiguous():
+        raise ValueError("out must be a contiguous int32 tensor shaped like the volume")
+    with torch.cuda.device(vol.device):
+        _bind_stream(vol.device)
+        rc = getattr(lib, fname)(vol.data_ptr(), vol.shape[0], vol.shape[1], vol.shape[2], int(L),
+                                 mask.ctypes.data, off.ctypes.data, mask.shape[0], out.data_ptr())
+    _check(rc)
+    return out
+
+
+def dilate3(vol, mask, off, L: int, out=None):
+    """Exact volume dilation (md_dilate3): max over the k x k x k SE of
+    vol(x-y) + b(y), 0 on empty windows."""
+    return _run_volume("md_dilate3", vol, mask, off, L, out)
+
+
+def erode3(vol, mask, off, L: int, out=None):
+    """Exact volume erosion (md_erode3): min over the SE of vol(x+y) - b(y),
+    L-1 on empty windows."""
+    return _run_volume("md_erode3", vol, mask, off, L, out)
 
 
 # md_op codes of include/md.h

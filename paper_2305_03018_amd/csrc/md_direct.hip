@@ -28,28 +28,29 @@ __device__ __forceinline__ int straddle(int lo, int hi) {
     return (int)__builtin_amdgcn_alignbit((unsigned)hi, (unsigned)lo, 16u);
 }
 
-// Stages image rows [by0 - rad, by0 - rad + TH) x columns [bx0 - rad,
-// bx0 - rad + TC) into LDS (columns up to `pitch`, minus infinity outside the
-// image and past TC), complemented for erosion.  The 64 lanes of a wave cover
+// Stages rows [by0 - rad, by0 - rad + TH) x columns [bx0 - rad,
+// bx0 - rad + TC) of one H x W image (a volume slice) into LDS (columns up
+// to `pitch`, minus infinity outside the image and past TC), complemented for
+// erosion.  The 64 lanes of a wave cover
 // consecutive columns (4 x 64 per row, pitch <= 256 + 4: words past 256 are
 // never read), the waves take 4 consecutive rows each per pass.  The 16 loads
 // of a pass are unconditional (pixel 0 stands in outside the image and the
 // block) and issued together before any of them is used.  PACK: LDS word
 // (p, c) holds image rows 2p (low half) and 2p+1 (high half).  Returns
 // non-zero if an in-image value lies outside [0, L-1].
-template <bool PACK>
-__device__ __forceinline__ int dir_stage(const JobDev &J, int by0, int bx0, int rad, int TH, int TC, int pitch,
-                                         int32_t *tile) {
+template <bool PACK, int RB = 4>
+__device__ __forceinline__ int dir_stage(const JobDev &J, const int32_t *slice, int by0, int bx0, int rad, int TH,
+                                         int TC, int pitch, int32_t *tile) {
     const int lane = threadIdx.x & 63;
-    const auto img = gld(J.img);
+    const auto img = gld(slice);
     const int H = J.H, W = J.W, L = J.L, op = J.op;
     const int neg = PACK ? kNeg16 : kNeg;
     int badv = 0;
-    for (int a0 = (threadIdx.x >> 6) * 4; a0 < TH; a0 += kDirThreads / 16) {
-        int raw[4][4];
-        bool in[4][4];
+    for (int a0 = (threadIdx.x >> 6) * RB; a0 < TH; a0 += (kDirThreads / 64) * RB) {
+        int raw[RB][4];
+        bool in[RB][4];
 #pragma unroll
-        for (int h = 0; h < 4; ++h) {
+        for (int h = 0; h < RB; ++h) {
             const int gy = by0 - rad + a0 + h;
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
@@ -60,7 +61,7 @@ __device__ __forceinline__ int dir_stage(const JobDev &J, int by0, int bx0, int 
         }
         __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-        for (int h = 0; h < 4; ++h) {
+        for (int h = 0; h < RB; ++h) {
             const int a = a0 + h;
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
@@ -143,48 +144,87 @@ __device__ __forceinline__ void dir_row(int (&acc)[kDirRX], const int32_t *trow,
     }
 }
 
+// The 2-D window passes of one output slice z: for an image (nslab = 0) the
+// job's own SE arrays over slice 0; for a volume, each active SE slab s over
+// input slice z - dz_s (skipped when that slice lies outside the volume).
+// Returns false when pass s has no input slice.
+struct DirPass {
+    const int32_t *slice, *sek, *sek16, *rows, *steps;
+    int nsteps;
+};
+
+template <bool VOL>
+__device__ __forceinline__ bool dir_pass(const JobDev &J, int z, int s, DirPass &p) {
+    const size_t plane = (size_t)J.H * J.W;
+    if (!VOL) {
+        p.slice = J.img;
+        p.sek = J.sek;
+        p.sek16 = J.sek16;
+        p.rows = J.sek_rows;
+        p.steps = J.sek_steps;
+        p.nsteps = J.dir_nsteps;
+        return true;
+    }
+    const SlabDev &S = J.slabs[s];
+    const int zi = z - S.dz;
+    if ((unsigned)zi >= (unsigned)J.D) return false;
+    p.slice = J.img + (size_t)zi * plane;
+    p.sek = S.sek;
+    p.sek16 = S.sek16;
+    p.rows = S.sek_rows;
+    p.steps = S.sek_steps;
+    p.nsteps = S.dir_nsteps;
+    return true;
+}
+
 // LDS of one 32-bit block: the image words (pitch kDirBW + kpad), each SE
 // row's [first, last] active column, then (SEL) the SE offsets in correlation
-// order (k rows of kpad words).
-template <bool SEL>
-__device__ __forceinline__ void direct32_block(const JobDev &J, int by0, int bx0, int32_t *tile,
+// order (k rows of kpad words).  Output slice z of the job.
+template <bool SEL, bool VOL>
+__device__ __forceinline__ void direct32_block(const JobDev &J, int z, int by0, int bx0, int32_t *tile,
                                                unsigned int *range_err) {
     const int k = J.k, rad = (k - 1) >> 1, kpad = J.kpad;
     const int TWD = kDirBW + kpad;
     const int TH = kDirBH + k - 1;
     int32_t *rowL = tile + TH * TWD;
     int32_t *seL = rowL + ((2 * k + 3) & ~3);        // 16-byte aligned for the b128 reads
-    if (SEL)
-        for (int q = threadIdx.x; q < k * kpad; q += kDirThreads) seL[q] = gld(J.sek)[q];
-    for (int q = threadIdx.x; q < 2 * k; q += kDirThreads) rowL[q] = gld(J.sek_rows)[q];
-    const int bad = dir_stage<false>(J, by0, bx0, rad, TH, kDirBW + k - 1, TWD, tile);
-    if (bad && range_err) atomicOr(range_err, 1u);
-    __syncthreads();
     const int trow0 = threadIdx.x / (kDirBW / kDirRX);
     const int lx0 = (threadIdx.x % (kDirBW / kDirRX)) * kDirRX;
     int acc[kDirRX];
 #pragma unroll
     for (int t = 0; t < kDirRX; ++t) acc[t] = kNeg;
-    const int32_t *sebase = SEL ? seL : J.sek;
-    for (int i = 0; i < k; ++i) {
-        const int jlo = rowL[2 * i], jhi = rowL[2 * i + 1];
-        if (jlo > jhi) continue;
-        dir_row<SEL>(acc, tile + (trow0 + i) * TWD + lx0, sebase + i * kpad, jlo & ~(kDirRX - 1), jhi);
+    const int npass = VOL ? J.nslab : 1;
+    for (int s = 0; s < npass; ++s) {
+        DirPass ps;
+        if (!dir_pass<VOL>(J, z, s, ps)) continue;
+        if (SEL)
+            for (int q = threadIdx.x; q < k * kpad; q += kDirThreads) seL[q] = gld(ps.sek)[q];
+        for (int q = threadIdx.x; q < 2 * k; q += kDirThreads) rowL[q] = gld(ps.rows)[q];
+        const int bad = dir_stage<false>(J, ps.slice, by0, bx0, rad, TH, kDirBW + k - 1, TWD, tile);
+        if (bad && range_err) atomicOr(range_err, 1u);
+        __syncthreads();
+        const int32_t *sebase = SEL ? seL : ps.sek;
+        for (int i = 0; i < k; ++i) {
+            const int jlo = rowL[2 * i], jhi = rowL[2 * i + 1];
+            if (jlo > jhi) continue;
+            dir_row<SEL>(acc, tile + (trow0 + i) * TWD + lx0, sebase + i * kpad, jlo & ~(kDirRX - 1), jhi);
+        }
+        __syncthreads();   // the LDS block is restaged by the next pass or item
     }
     const int gy = by0 + trow0, L = J.L, W = J.W;
+    int32_t *out = J.out + (size_t)z * J.H * W;
     if (gy < J.H) {
 #pragma unroll
         for (int t = 0; t < kDirRX; ++t) {
             const int gx = bx0 + lx0 + t;
             if (gx >= W) continue;
             const int d = acc[t] < 0 ? 0 : acc[t];
-            gst(J.out)[(size_t)gy * W + gx] = J.op ? (L - 1 - d) : d;
+            gst(out)[(size_t)gy * W + gx] = J.op ? (L - 1 - d) : d;
         }
     }
-    __syncthreads();   // the LDS block is restaged by the next item
 }
 
-template <bool SEL>
+template <bool SEL, bool VOL>
 __global__ __launch_bounds__(kDirThreads) void k_direct32(const JobDev *__restrict__ jobs,
                                                           const Seg *__restrict__ segs, int nseg,
                                                           long long nitems, StatsDev *st) {
@@ -192,9 +232,10 @@ __global__ __launch_bounds__(kDirThreads) void k_direct32(const JobDev *__restri
     for (long long it = blockIdx.x; it < nitems; it += gridDim.x) {
         const Seg S = segs[find_seg(segs, nseg, it)];
         const JobDev &J = jobs[S.job];
-        const int local = (int)(it - S.item0);
-        const int byi = local / J.dir_bx, bxi = local - byi * J.dir_bx;
-        direct32_block<SEL>(J, byi * kDirBH, bxi * kDirBW, dyn_lds, &st->range_err);
+        const int local = (int)(it - S.item0), nb = J.dir_bx * J.dir_by;
+        const int z = local / nb, rem = local - z * nb;
+        const int byi = rem / J.dir_bx, bxi = rem - byi * J.dir_bx;
+        direct32_block<SEL, VOL>(J, z, byi * kDirBH, bxi * kDirBW, dyn_lds, &st->range_err);
     }
 }
 
@@ -353,15 +394,14 @@ __device__ __forceinline__ void d16_column(s16x2 (&acc)[kD16R][kDirRX], const in
 __host__ __device__ constexpr int d16_pitch(int kpad) { return kDirBW + kpad + 4; }
 __host__ __device__ constexpr int d16_rows(int k) { return (kD16BH + k - 1) / 2 + 1; }
 
-__device__ __forceinline__ void direct16_block(const JobDev &J, int by0, int bx0, int32_t *tile,
+// Output slice z of the job (0 for an image).
+template <bool VOL>
+__device__ __forceinline__ void direct16_block(const JobDev &J, int z, int by0, int bx0, int32_t *tile,
                                                unsigned int *range_err) {
     const int k = J.k, rad = (k - 1) >> 1, kpad = J.kpad;
     const int P = d16_pitch(kpad);
     const int TH = kD16BH + k - 1;                 // image rows the block reads (even: k is odd)
     const int TC = kDirBW + k - 1;                 // image columns the block reads
-    const int bad = dir_stage<true>(J, by0, bx0, rad, TH, TC, P, tile);
-    if (bad && range_err) atomicOr(range_err, 1u);
-    __syncthreads();
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, wx = wv & 1, wy = wv >> 1;
     const int cg = lane & 7, rg = lane >> 3;
     const int lx0 = wx * 64 + cg * kDirRX;         // first output column of the lane
@@ -374,27 +414,42 @@ __device__ __forceinline__ void direct16_block(const JobDev &J, int by0, int bx0
     for (int r = 0; r < kD16R; ++r)
 #pragma unroll
         for (int t = 0; t < kDirRX; ++t) acc[r][t] = __builtin_bit_cast(s16x2, neg);
-    if (live) {
-        // the SE's column steps: (first column, kind, first and last row pair);
-        // kind 0: 8 columns, 1: 4 columns, 2: 2 columns, 3: 2 columns at a
-        // first column = 2 mod 4
-        const auto steps = cst(J.sek_steps);
-        const int32_t *base = tile + q * P + lx0;
-        for (int i = 0; i < J.dir_nsteps; ++i) {
-            const int jb = steps[4 * i], kind = steps[4 * i + 1], s0 = steps[4 * i + 2], s1 = steps[4 * i + 3];
-            const int32_t *se = J.sek16 + jb;
-            switch (kind) {
-                case 0: d16_column<8, 0>(acc, base + jb, P, se, kpad, k, s0, s1); break;
-                case 1: d16_column<4, 0>(acc, base + jb, P, se, kpad, k, s0, s1); break;
-                case 2: d16_column<2, 0>(acc, base + jb, P, se, kpad, k, s0, s1); break;
-                default: d16_column<2, 2>(acc, base + jb - 2, P, se, kpad, k, s0, s1); break;
+    const int npass = VOL ? J.nslab : 1;
+    for (int s = 0; s < npass; ++s) {
+        DirPass ps;
+        if (!dir_pass<VOL>(J, z, s, ps)) continue;
+        // A volume restages while the accumulators are live: fewer loads in
+        // flight, and the block origin is made opaque per pass so that the
+        // staging addresses are recomputed rather than kept live across the
+        // window.
+        int oy = by0, ox = bx0;
+        if (VOL) asm volatile("" : "+s"(oy), "+s"(ox));
+        const int bad = dir_stage<true, VOL ? 2 : 4>(J, ps.slice, oy, ox, rad, TH, TC, P, tile);
+        if (bad && range_err) atomicOr(range_err, 1u);
+        __syncthreads();
+        if (live) {
+            // the SE's column steps: (first column, kind, first and last row
+            // pair); kind 0: 8 columns, 1: 4 columns, 2: 2 columns, 3: 2
+            // columns at a first column = 2 mod 4
+            const auto steps = cst(ps.steps);
+            const int32_t *base = tile + q * P + lx0;
+            for (int i = 0; i < ps.nsteps; ++i) {
+                const int jb = steps[4 * i], kind = steps[4 * i + 1], s0 = steps[4 * i + 2], s1 = steps[4 * i + 3];
+                const int32_t *se = ps.sek16 + jb;
+                switch (kind) {
+                    case 0: d16_column<8, 0>(acc, base + jb, P, se, kpad, k, s0, s1); break;
+                    case 1: d16_column<4, 0>(acc, base + jb, P, se, kpad, k, s0, s1); break;
+                    case 2: d16_column<2, 0>(acc, base + jb, P, se, kpad, k, s0, s1); break;
+                    default: d16_column<2, 2>(acc, base + jb - 2, P, se, kpad, k, s0, s1); break;
+                }
             }
         }
+        // every wave has finished reading the image block before it is
+        // restaged or reused for the results
+        __syncthreads();
     }
     // results (clamped at 0: a negative maximum is an empty window) go to LDS
-    // as 16-bit values, one row of 8 per b128 write, once every wave has
-    // finished reading the image block
-    __syncthreads();
+    // as 16-bit values, one row of 8 per b128 write
     if (live) {
         uint16_t *ob = (uint16_t *)tile;
 #pragma unroll
@@ -419,19 +474,21 @@ __device__ __forceinline__ void direct16_block(const JobDev &J, int by0, int bx0
     {
         const uint16_t *ob = (const uint16_t *)tile;
         const int L = J.L, W = J.W, op = J.op;
+        int32_t *out = J.out + (size_t)z * J.H * W;
         const int cx = threadIdx.x & (kDirBW - 1), gx = bx0 + cx;
         if (gx < W) {
             for (int y = threadIdx.x / kDirBW; y < kD16BH; y += kDirThreads / kDirBW) {
                 const int gy = by0 + y;
                 if (gy >= J.H) break;
                 const int d = ob[y * kDirBW + cx];
-                gst(J.out)[(size_t)gy * W + gx] = op ? (L - 1 - d) : d;
+                gst(out)[(size_t)gy * W + gx] = op ? (L - 1 - d) : d;
             }
         }
     }
     __syncthreads();   // the LDS block is restaged by the next item
 }
 
+template <bool VOL>
 __global__ __launch_bounds__(kDirThreads) void k_direct16(const JobDev *__restrict__ jobs,
                                                           const Seg *__restrict__ segs, int nseg,
                                                           long long nitems, StatsDev *st) {
@@ -439,9 +496,10 @@ __global__ __launch_bounds__(kDirThreads) void k_direct16(const JobDev *__restri
     for (long long it = blockIdx.x; it < nitems; it += gridDim.x) {
         const Seg S = segs[find_seg(segs, nseg, it)];
         const JobDev &J = jobs[S.job];
-        const int local = (int)(it - S.item0);
-        const int byi = local / J.dir_bx, bxi = local - byi * J.dir_bx;
-        direct16_block(J, byi * kD16BH, bxi * kDirBW, dyn_lds, &st->range_err);
+        const int local = (int)(it - S.item0), nb = J.dir_bx * J.dir_by;
+        const int z = local / nb, rem = local - z * nb;
+        const int byi = rem / J.dir_bx, bxi = rem - byi * J.dir_bx;
+        direct16_block<VOL>(J, z, byi * kD16BH, bxi * kDirBW, dyn_lds, &st->range_err);
     }
 }
 
@@ -457,11 +515,17 @@ size_t direct_lds_bytes(int k, int kpad, int pack, int sel) {
 }
 
 hipError_t launch_direct(int pack, int sel, const JobDev *jobs, const Seg *segs, int nseg, long long nitems,
-                         int grid, size_t lds_bytes, StatsDev *st, hipStream_t s) {
+                         int grid, size_t lds_bytes, StatsDev *st, hipStream_t s, bool vol) {
     if (nitems <= 0) return hipSuccess;
-    if (pack) k_direct16<<<grid, kDirThreads, lds_bytes, s>>>(jobs, segs, nseg, nitems, st);
-    else if (sel) k_direct32<true><<<grid, kDirThreads, lds_bytes, s>>>(jobs, segs, nseg, nitems, st);
-    else k_direct32<false><<<grid, kDirThreads, lds_bytes, s>>>(jobs, segs, nseg, nitems, st);
+    if (vol) {
+        if (pack) k_direct16<true><<<grid, kDirThreads, lds_bytes, s>>>(jobs, segs, nseg, nitems, st);
+        else if (sel) k_direct32<true, true><<<grid, kDirThreads, lds_bytes, s>>>(jobs, segs, nseg, nitems, st);
+        else k_direct32<false, true><<<grid, kDirThreads, lds_bytes, s>>>(jobs, segs, nseg, nitems, st);
+    } else {
+        if (pack) k_direct16<false><<<grid, kDirThreads, lds_bytes, s>>>(jobs, segs, nseg, nitems, st);
+        else if (sel) k_direct32<true, false><<<grid, kDirThreads, lds_bytes, s>>>(jobs, segs, nseg, nitems, st);
+        else k_direct32<false, false><<<grid, kDirThreads, lds_bytes, s>>>(jobs, segs, nseg, nitems, st);
+    }
     return hipGetLastError();
 }
 

@@ -56,6 +56,16 @@ enum : int { kPathFFT = 1, kPathDirect = 2 };
 enum : int { kPrecFP32 = 0, kPrecFP64 = 1, kPrecNTT = 2 };
 enum : int { kFbNone = 0, kFbFFT64 = 1 };
 
+// One SE slab of a volume job on the direct path: the 2-D window of SE slab
+// a (correlation-order arrays as in JobDev) applied to input slice
+// z - dz for output slice z, dz = a - r.
+struct SlabDev {
+    const int32_t *sek, *sek16, *sek_rows, *sek_steps;
+    int dir_nsteps;
+    int dz;
+    int pad[2];
+};
+
 // One job as the kernels see it.  Complex arrays are float2 in the FP32 form
 // and double2 in the FP64 form (the `dbl` flag of the job's plan).
 struct JobDev {
@@ -95,6 +105,12 @@ struct JobDev {
     const uint32_t *ntt_dec_s;   // Shoup companions of dec
     int ntt_dtop;                // largest possible degree: (L-1) + max offset
     int dir_bx, dir_by;          // direct-path blocks per row / column
+    // volumes (three image axes, z slowest): D slices of H x W; D = 1 and
+    // nslab = 0 for images.  Direct path: the window runs once per active SE
+    // slab (slabs[nslab]).  Transform path: cubic nt^3 tiles, tiles_z deep.
+    int D, tiles_z;
+    const SlabDev *slabs;
+    int nslab;
 };
 
 // A contiguous run of work items of one job.  FFT segments cover
@@ -138,8 +154,9 @@ int dec_pitch(int nr);
 hipError_t launch_decode(int var, int dbl, const JobDev *jobs, const Seg *segs, int nseg,
                          long long nitems, int grid, float band, unsigned int *tile_flags,
                          int2 *fb_list, StatsDev *st, hipStream_t s);
+// vol: volume jobs (a window pass per active SE slab, JobDev::slabs)
 hipError_t launch_direct(int pack, int sel, const JobDev *jobs, const Seg *segs, int nseg, long long nitems,
-                         int grid, size_t lds_bytes, StatsDev *st, hipStream_t s);
+                         int grid, size_t lds_bytes, StatsDev *st, hipStream_t s, bool vol = false);
 hipError_t launch_fallback(int nt64, const JobDev *jobs, const int2 *fb_list, const StatsDev *st,
                            double2 *slots, size_t slot_elems, int grid, const double2 *tw64, double2 *slabs,
                            hipStream_t s);
@@ -151,6 +168,19 @@ hipError_t launch_ntt(int nt, const JobDev *jobs, const Seg *segs, int nseg, lon
                       const uint32_t *tw, const uint32_t *tws, StatsDev *st, hipStream_t s);
 hipError_t launch_ntt_decode(const JobDev *jobs, const Seg *segs, int nseg, long long nitems, int grid,
                              hipStream_t s);
+// volumes on the exact transform path (md_ntt.hip): cubic tiles of nt^3
+// points, nt in {8, 16, 32}
+int ntt3_block_threads(int nt);
+hipError_t launch_ntt3(int nt, const JobDev *jobs, const Seg *segs, int nseg, long long nitems, int grid,
+                       const uint32_t *tw, const uint32_t *tws, StatsDev *st, hipStream_t s);
+hipError_t launch_ntt3_decode(const JobDev *jobs, const Seg *segs, int nseg, long long nitems, int grid,
+                              hipStream_t s);
+// spectrum of a k x k x k SE umbra mod p at spatial length nt and range
+// length n, scaled by nt^-3: spec / spec_s [n][nt][nt][nt]; work holds
+// n k^2 nt + n k nt^2 words
+hipError_t launch_ntt3_se_spectrum(const uint8_t *mask_d, const int32_t *off_d, int k, int nt, int n,
+                                   const uint32_t *rpow, const uint32_t *tw, uint32_t scale, uint32_t *work,
+                                   uint32_t *spec, uint32_t *spec_s, hipStream_t s);
 hipError_t launch_ntt_se_spectrum(const uint8_t *mask_d, const int32_t *off_d, int k, int nt, int n,
                                   const uint32_t *rpow, const uint32_t *tw, uint32_t scale, uint32_t *work,
                                   uint32_t *spec, uint32_t *spec_s, hipStream_t s);

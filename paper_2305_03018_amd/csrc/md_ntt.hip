@@ -356,7 +356,333 @@ __global__ void k_ntt_se_cols(const uint32_t *__restrict__ G, int k, int nt, con
     }
 }
 
+// ---- volumes: cubic tiles of N^3 points (Sec. 3 with N = 3 image axes: the
+// umbra is 4-dimensional; the range axis is handled by the table as above,
+// the three image axes by transforms of length N) ----
+//
+// LDS layout of one tile: point (z, y, x) at (z N + y)(N + 1) + x.  A pass
+// along x takes lines (z, y) with stride N + 1 between lanes, along y and z
+// it takes lines whose consecutive lanes differ in x: all three are free of
+// bank conflicts.
+template <int N>
+struct Vol {
+    static constexpr int P = N + 1;           // y pitch
+    static constexpr int PZ = N * (N + 1);    // z pitch
+    static constexpr int WORDS = N * PZ;
+    __device__ static constexpr int at(int z, int y, int x) { return z * PZ + y * P + x; }
+    // first element of line l (l < N^2) and element stride along AXIS 0 (x),
+    // 1 (y), 2 (z)
+    template <int AXIS>
+    __device__ static int line(int l) {
+        if (AXIS == 0) return l * P;                              // l = z N + y
+        if (AXIS == 1) return (l / N) * PZ + (l & (N - 1));       // l = z N + x
+        return (l / N) * P + (l & (N - 1));                       // l = y N + x
+    }
+    template <int AXIS>
+    static constexpr int es() { return AXIS == 0 ? 1 : AXIS == 1 ? P : PZ; }
+};
+
+// One fused decimation-in-time pass (radix-2 stages with half-sizes H0 ...
+// 2^(Q-1) H0) along AXIS over all N^2 lines of the tile.  The butterfly group
+// index is the same for every lane of a wave (N^2 >= 64 lines), so twiddles
+// are wave-uniform loads.
+template <int N, int Q, int H0, int AXIS, int BS, bool INV>
+__device__ __forceinline__ void vpass_dit(uint32_t *lds, const NTw &tw) {
+    constexpr int RAD = 1 << Q, LINES = N * N, UNITS = LINES * (N / RAD), ES = Vol<N>::template es<AXIS>();
+    for (int u = threadIdx.x; u < UNITS; u += BS) {
+        const int l = u & (LINES - 1);
+        const int gi = __builtin_amdgcn_readfirstlane(u / LINES);
+        const int o = gi % H0;
+        const int base = (gi / H0) * (RAD * H0) + o;
+        uint32_t *p = lds + Vol<N>::template line<AXIS>(l) + base * ES;
+        uint32_t x[RAD];
+#pragma unroll
+        for (int t = 0; t < RAD; ++t) x[t] = p[t * H0 * ES];
+#pragma unroll
+        for (int s = 0; s < Q; ++s) {
+            const int hu = 1 << s;
+#pragma unroll
+            for (int t = 0; t < RAD; ++t) {
+                if (t & hu) continue;
+                const int j = o + (t & (hu - 1)) * H0;
+                const bool one = H0 == 1 && (t & (hu - 1)) == 0;
+                const uint32_t b = one ? x[t + hu] : tw.mul<INV>(x[t + hu], j * (kNttTw / (2 * (H0 << s))));
+                const uint32_t a = x[t];
+                x[t] = addm(a, b);
+                x[t + hu] = subm(a, b);
+            }
+        }
+#pragma unroll
+        for (int t = 0; t < RAD; ++t) p[t * H0 * ES] = x[t];
+    }
+}
+
+// One fused decimation-in-frequency pass: half-sizes 2^(Q-1) HMIN ... HMIN.
+template <int N, int Q, int HMIN, int AXIS, int BS, bool INV>
+__device__ __forceinline__ void vpass_dif(uint32_t *lds, const NTw &tw) {
+    constexpr int RAD = 1 << Q, LINES = N * N, UNITS = LINES * (N / RAD), ES = Vol<N>::template es<AXIS>();
+    for (int u = threadIdx.x; u < UNITS; u += BS) {
+        const int l = u & (LINES - 1);
+        const int gi = __builtin_amdgcn_readfirstlane(u / LINES);
+        const int o = gi % HMIN;
+        const int base = (gi / HMIN) * (RAD * HMIN) + o;
+        uint32_t *p = lds + Vol<N>::template line<AXIS>(l) + base * ES;
+        uint32_t x[RAD];
+#pragma unroll
+        for (int t = 0; t < RAD; ++t) x[t] = p[t * HMIN * ES];
+#pragma unroll
+        for (int s = 0; s < Q; ++s) {
+            const int hu = RAD >> (s + 1);
+#pragma unroll
+            for (int t = 0; t < RAD; ++t) {
+                if (t & hu) continue;
+                const int j = o + (t & (hu - 1)) * HMIN;
+                const bool one = HMIN == 1 && (t & (hu - 1)) == 0;
+                const uint32_t a = x[t], b = x[t + hu];
+                x[t] = addm(a, b);
+                const uint32_t d = subm(a, b);
+                x[t + hu] = one ? d : tw.mul<INV>(d, j * (kNttTw / (2 * hu * HMIN)));
+            }
+        }
+#pragma unroll
+        for (int t = 0; t < RAD; ++t) p[t * HMIN * ES] = x[t];
+    }
+}
+
+template <int N, int AXIS, int BS, bool INV, int PASS = 0>
+__device__ __forceinline__ void vdit_axis(uint32_t *lds, const NTw &tw) {
+    constexpr int lg = nlog2(N);
+    if constexpr (PASS < nnpass(lg)) {
+        vpass_dit<N, npassq(lg, PASS), (1 << nstages_before(lg, PASS)), AXIS, BS, INV>(lds, tw);
+        __syncthreads();
+        vdit_axis<N, AXIS, BS, INV, PASS + 1>(lds, tw);
+    }
+}
+
+template <int N, int AXIS, int BS, bool INV, int PASS = 0>
+__device__ __forceinline__ void vdif_axis(uint32_t *lds, const NTw &tw) {
+    constexpr int lg = nlog2(N);
+    if constexpr (PASS < nnpass(lg)) {
+        constexpr int Q = npassq(lg, PASS), HMIN = N >> (nstages_before(lg, PASS) + Q);
+        vpass_dif<N, Q, HMIN, AXIS, BS, INV>(lds, tw);
+        __syncthreads();
+        vdif_axis<N, AXIS, BS, INV, PASS + 1>(lds, tw);
+    }
+}
+
+// One (tile, bin) of Step 2 modulo p for a volume: input point (zz, yy, xx)
+// holds f(o - r + (zz, yy, xx)) (minus-infinity = the zero column outside the
+// volume), the SE umbra sits at [0, k)^3, and circular output index i >= k-1
+// along each axis is the linear result for voxel o + i - (k-1).
+template <int N, int BS>
+__device__ __forceinline__ void ntt3_tile_bin(uint32_t *lds, const JobDev &J, int oz0, int oy0, int ox0,
+                                              const uint32_t *__restrict__ enc_m,
+                                              const uint32_t *__restrict__ spec_m,
+                                              const uint32_t *__restrict__ spec_s_m, uint32_t *__restrict__ ydst,
+                                              const NTw &tw, unsigned int *range_err) {
+    constexpr int LG = nlog2(N), NN = N * N, PER = N * N * N / BS, CH = PER < 8 ? PER : 8;
+    static_assert(PER * BS == N * N * N, "block size must divide the tile");
+    const int k = J.k, r = (k - 1) >> 1, T = N - k + 1;
+    const int iz0 = oz0 - r, iy0 = oy0 - r, ix0 = ox0 - r;
+    const int D = J.D, H = J.H, W = J.W, L = J.L, op = J.op;
+    const auto im = gld(J.img);
+    int badv = 0;
+    for (int c0 = 0; c0 < PER; c0 += CH) {
+        int val[CH];
+        bool in[CH];
+#pragma unroll
+        for (int e = 0; e < CH; ++e) {
+            const int q = (c0 + e) * BS + threadIdx.x;
+            const int gz = iz0 + q / NN, gy = iy0 + ((q >> LG) & (N - 1)), gx = ix0 + (q & (N - 1));
+            in[e] = (unsigned)gz < (unsigned)D && (unsigned)gy < (unsigned)H && (unsigned)gx < (unsigned)W;
+            val[e] = im[in[e] ? ((size_t)gz * H + gy) * W + gx : 0];
+        }
+        __builtin_amdgcn_sched_barrier(0);
+        uint32_t v[CH];
+#pragma unroll
+        for (int e = 0; e < CH; ++e) {
+            badv |= (int)(in[e] && (unsigned)val[e] >= (unsigned)L);
+            int w = min(max(val[e], 0), L - 1);
+            w = op ? L - 1 - w : w;
+            v[e] = gld(enc_m)[in[e] ? w : 0];
+        }
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int e = 0; e < CH; ++e) {
+            const int q = (c0 + e) * BS + threadIdx.x;
+            lds[Vol<N>::at(nbrev<LG>(q / NN), nbrev<LG>((q >> LG) & (N - 1)), nbrev<LG>(q & (N - 1)))] =
+                in[e] ? v[e] : 0u;
+        }
+    }
+    if (badv && range_err) atomicOr(range_err, 1u);
+    __syncthreads();
+    vdit_axis<N, 0, BS, false>(lds, tw);
+    vdit_axis<N, 1, BS, false>(lds, tw);
+    vdit_axis<N, 2, BS, false>(lds, tw);
+    for (int c0 = 0; c0 < PER; c0 += CH) {
+        uint32_t sv[CH], ss[CH];
+#pragma unroll
+        for (int e = 0; e < CH; ++e) {
+            const int q = (c0 + e) * BS + threadIdx.x;
+            sv[e] = gld(spec_m)[q];
+            ss[e] = gld(spec_s_m)[q];
+        }
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int e = 0; e < CH; ++e) {
+            const int q = (c0 + e) * BS + threadIdx.x;
+            uint32_t *x = lds + Vol<N>::at(q / NN, (q >> LG) & (N - 1), q & (N - 1));
+            *x = mulw(*x, sv[e], ss[e]);
+        }
+    }
+    __syncthreads();
+    vdif_axis<N, 2, BS, true>(lds, tw);
+    vdif_axis<N, 1, BS, true>(lds, tw);
+    vdif_axis<N, 0, BS, true>(lds, tw);
+    const int TT = T * T;
+    for (int q = threadIdx.x; q < TT * T; q += BS) {
+        const int a = q / TT, rem = q - a * TT, b = rem / T, c = rem - b * T;
+        gst(ydst)[q] = lds[Vol<N>::at(nbrev<LG>(a + k - 1), nbrev<LG>(b + k - 1), nbrev<LG>(c + k - 1))];
+    }
+    __syncthreads();
+}
+
+template <int N, int BS>
+__global__ __launch_bounds__(BS) void k_ntt3(const JobDev *__restrict__ jobs, const Seg *__restrict__ segs, int nseg,
+                                             long long nitems, const uint32_t *__restrict__ tw,
+                                             const uint32_t *__restrict__ tws, StatsDev *st) {
+    __shared__ uint32_t lds[Vol<N>::WORDS];
+    NTw t;
+    t.w = tw;
+    t.ws = tws;
+    for (long long it = blockIdx.x; it < nitems; it += gridDim.x) {
+        const Seg S = segs[find_seg(segs, nseg, it)];
+        const JobDev &J = jobs[S.job];
+        const long long local = it - S.item0;
+        const int m = (int)(local / S.ntiles), tl = (int)(local % S.ntiles);
+        const int tile = S.tile0 + tl, txy = J.tiles_x * J.tiles_y;
+        const int tz = tile / txy, rem = tile - tz * txy, ty = rem / J.tiles_x, tx = rem - ty * J.tiles_x;
+        const size_t TTT = (size_t)J.T * J.T * J.T, NNN = (size_t)N * N * N;
+        uint32_t *ydst = (uint32_t *)S.y + ((size_t)tl * J.bins + m) * TTT;
+        ntt3_tile_bin<N, BS>(lds, J, tz * J.T, ty * J.T, tx * J.T, (const uint32_t *)J.enc + (size_t)m * J.L,
+                             (const uint32_t *)J.se_spec + m * NNN, J.ntt_spec_s + m * NNN, ydst, t,
+                             m == 0 ? &st->range_err : nullptr);
+    }
+}
+
+// Step 3 modulo p for a volume tile: the T^3 voxels of each tile, decoded as
+// on images.
+__global__ __launch_bounds__(kDecThreads) void k_ntt3_decode(const JobDev *__restrict__ jobs,
+                                                             const Seg *__restrict__ segs, int nseg,
+                                                             long long nitems) {
+    for (long long it = blockIdx.x; it < nitems; it += gridDim.x) {
+        const Seg S = segs[find_seg(segs, nseg, it)];
+        const JobDev &J = jobs[S.job];
+        const int local = (int)(it - S.item0);
+        const int tl = local / S.pblocks, pb = local - tl * S.pblocks;
+        const int tile = S.tile0 + tl, txy = J.tiles_x * J.tiles_y;
+        const int tz = tile / txy, rem = tile - tz * txy, ty = rem / J.tiles_x, tx = rem - ty * J.tiles_x;
+        const int T = J.T, TT = T * T;
+        const size_t TTT = (size_t)TT * T;
+        const uint32_t *X = (const uint32_t *)S.y + (size_t)tl * J.bins * TTT;
+#pragma unroll 1
+        for (int q = 0; q < kDecPixPerThread; ++q) {
+            const int p = (pb * kDecPixPerThread + q) * kDecThreads + threadIdx.x;
+            const int lz = p / TT, r2 = p - lz * TT, ly = r2 / T, lx = r2 - ly * T;
+            const int gz = tz * T + lz, gy = ty * T + ly, gx = tx * T + lx;
+            const bool valid = p < (int)TTT && gz < J.D && gy < J.H && gx < J.W;
+            const int top = ntt_top(X, TTT, p, valid, (const uint32_t *)J.dec, J.ntt_dec_s, J.dec_pitch, J.nr,
+                                    J.ntt_dtop);
+            if (valid) {
+                const int d = top < 0 ? 0 : top;
+                gst(J.out)[((size_t)gz * J.H + gy) * J.W + gx] = J.op ? (J.L - 1 - d) : d;
+            }
+        }
+    }
+}
+
+// Spectrum of a k x k x k SE umbra mod p, separable: along x for every SE row
+// (a, i), then along y, then along z.
+__global__ void k_ntt3_se_rows(const uint8_t *__restrict__ mask, const int32_t *__restrict__ off, int k, int nt,
+                               int n, const uint32_t *__restrict__ rpow, const uint32_t *__restrict__ tw,
+                               uint32_t *G) {
+    const int kk = k * k, m = blockIdx.x / kk, row = blockIdx.x % kk;   // row = a k + i
+    const int step = kNttTw / nt;
+    for (int v = threadIdx.x; v < nt; v += blockDim.x) {
+        uint64_t acc = 0;
+        for (int j = 0; j < k; ++j) {
+            const size_t c = (size_t)row * k + j;
+            if (!mask[c]) continue;
+            const uint64_t a = rpow[((long long)off[c] * m) % n];
+            acc = (acc + a * tw[((v * j) % nt) * step]) % kP;
+        }
+        G[((size_t)m * kk + row) * nt + v] = (uint32_t)acc;
+    }
+}
+
+// Y[o][u][e] = scale * sum_{i < len} X[o][i][e] w_nt^(u i), o < outer, u < nt,
+// e < inner (one block per (o, u)); with `spec_s` set, also the Shoup
+// companions of Y.
+__global__ void k_ntt3_se_axis(const uint32_t *__restrict__ X, int len, int inner, int nt,
+                               const uint32_t *__restrict__ tw, uint32_t scale, uint32_t *Y, uint32_t *Ys) {
+    const int o = blockIdx.x / nt, u = blockIdx.x % nt;
+    const int step = kNttTw / nt;
+    for (int e = threadIdx.x; e < inner; e += blockDim.x) {
+        uint64_t acc = 0;
+        for (int i = 0; i < len; ++i)
+            acc = (acc + (uint64_t)X[((size_t)o * len + i) * inner + e] * tw[((u * i) % nt) * step]) % kP;
+        const uint32_t y = (uint32_t)(acc * scale % kP);
+        const size_t dst = ((size_t)o * nt + u) * inner + e;
+        Y[dst] = y;
+        if (Ys) Ys[dst] = (uint32_t)(((uint64_t)y << 32) / kP);
+    }
+}
+
 }  // namespace
+
+int ntt3_block_threads(int nt) {
+    switch (nt) {
+        case 8: return 128;
+        case 16: return 256;
+        case 32: return 1024;
+        default: return 0;
+    }
+}
+
+hipError_t launch_ntt3(int nt, const JobDev *jobs, const Seg *segs, int nseg, long long nitems, int grid,
+                       const uint32_t *tw, const uint32_t *tws, StatsDev *st, hipStream_t s) {
+    if (nitems <= 0) return hipSuccess;
+    switch (nt) {
+        case 8: k_ntt3<8, 128><<<grid, 128, 0, s>>>(jobs, segs, nseg, nitems, tw, tws, st); break;
+        case 16: k_ntt3<16, 256><<<grid, 256, 0, s>>>(jobs, segs, nseg, nitems, tw, tws, st); break;
+        case 32: k_ntt3<32, 1024><<<grid, 1024, 0, s>>>(jobs, segs, nseg, nitems, tw, tws, st); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_ntt3_decode(const JobDev *jobs, const Seg *segs, int nseg, long long nitems, int grid,
+                              hipStream_t s) {
+    if (nitems <= 0) return hipSuccess;
+    k_ntt3_decode<<<grid, kDecThreads, 0, s>>>(jobs, segs, nseg, nitems);
+    return hipGetLastError();
+}
+
+hipError_t launch_ntt3_se_spectrum(const uint8_t *mask_d, const int32_t *off_d, int k, int nt, int n,
+                                   const uint32_t *rpow, const uint32_t *tw, uint32_t scale, uint32_t *work,
+                                   uint32_t *spec, uint32_t *spec_s, hipStream_t s) {
+    const int threads = nt < 256 ? nt : 256;
+    uint32_t *g1 = work;                                  // [n][k][k][nt]
+    uint32_t *g2 = work + (size_t)n * k * k * nt;         // [n][k][nt][nt]
+    k_ntt3_se_rows<<<n * k * k, threads, 0, s>>>(mask_d, off_d, k, nt, n, rpow, tw, g1);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    k_ntt3_se_axis<<<n * k * nt, threads, 0, s>>>(g1, k, nt, nt, tw, 1u, g2, nullptr);   // along y
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    k_ntt3_se_axis<<<n * nt, 256, 0, s>>>(g2, k, nt * nt, nt, tw, scale, spec, spec_s);   // along z, scaled
+    return hipGetLastError();
+}
 
 int ntt_block_threads(int nt) {
     switch (nt) {

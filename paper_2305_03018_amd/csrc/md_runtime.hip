@@ -216,6 +216,7 @@ struct Ctx {
     std::unordered_map<std::string, std::unique_ptr<Exec>> execs;
     DevBuf se_work, se_in;
     DevBuf morph_a, morph_b;      // intermediates of md_morph
+    DevBuf vjob, vseg, vslabs, vy;  // volume path: job, segments, slab table, transform buffer
     // profiling
     struct Pending {
         std::string name;
@@ -816,6 +817,7 @@ int build_exec(const md_job *jobs, int n, const std::vector<SEData> &ses, Exec &
         MD_TRY(plan_job(j, ses[i], p));
         JobDev &d = ex.jobs_h[i];
         memset(&d, 0, sizeof d);
+        d.D = 1;
         d.img = j.img;
         d.out = j.out;
         d.H = j.H;
@@ -1498,6 +1500,330 @@ int morph(int op, const int32_t *img, int H, int W, int L, const uint8_t *mask, 
     return MD_OK;
 }
 
+// ---------------------------------------------------------------------------
+// volumes (three image axes, Sec. 2.1 / Sec. 3 with N = 3)
+// ---------------------------------------------------------------------------
+constexpr int kVolMaxK = 31;
+
+// Effective volume SE: the SE for dilation, its reflection through the
+// centre for erosion (duality, Sec. 2.1); k^3 cells, (a, i, j) row-major.
+struct VolSE {
+    int k = 0;
+    std::vector<uint8_t> mask;
+    std::vector<int32_t> off;
+    int maxoff = 0;
+    long long ncells = 0;
+    std::string key;
+};
+
+void make_vol_se(const uint8_t *mask, const int32_t *off, int k, int op, VolSE &se) {
+    const size_t n = (size_t)k * k * k;
+    se.k = k;
+    se.mask.assign(n, 0);
+    se.off.assign(n, 0);
+    se.maxoff = 0;
+    se.ncells = 0;
+    for (size_t c = 0; c < n; ++c) {
+        const size_t src = op ? n - 1 - c : c;   // reflection through the centre
+        if (!mask[src]) continue;
+        se.mask[c] = 1;
+        se.off[c] = off[src];
+        se.maxoff = std::max(se.maxoff, (int)off[src]);
+        ++se.ncells;
+    }
+    se.key = "vol";
+    se.key.append((const char *)&k, sizeof k);
+    se.key.append((const char *)se.mask.data(), n);
+    se.key.append((const char *)se.off.data(), n * sizeof(int32_t));
+}
+
+// One slab of the effective SE as a 2-D SE (already in effective form).
+void vol_slab(const VolSE &se, int a, SEData &sd) {
+    const size_t kk = (size_t)se.k * se.k;
+    make_se(se.mask.data() + a * kk, se.off.data() + a * kk, se.k, 0, sd);
+}
+
+// Exact-path SE spectrum of a volume SE at cubic length nt and range length n,
+// scaled by nt^-3, cached with the image spectra.
+int get_vspectrum(const VolSE &se, int nt, int n, const NttRange *rt, NttSpec **out) {
+    std::string key = se.key;
+    key.append((const char *)&nt, sizeof nt);
+    key.append((const char *)&n, sizeof n);
+    auto it = g.nspectra.find(key);
+    if (it != g.nspectra.end()) {
+        *out = it->second.get();
+        return MD_OK;
+    }
+    auto sp = std::make_unique<NttSpec>();
+    const int k = se.k;
+    const size_t nspec = (size_t)n * nt * nt * nt, kkk = (size_t)k * k * k;
+    MD_TRY(sp->spec.ensure(nspec * 4));
+    MD_TRY(sp->spec_s.ensure(nspec * 4));
+    MD_TRY(g.se_work.ensure(((size_t)n * k * k * nt + (size_t)n * k * nt * nt) * 4));
+    MD_TRY(g.se_in.ensure(kkk * (sizeof(int32_t) + 1) + 64));
+    MD_HIP(hipStreamSynchronize(g.stream));   // se_in may still be read by an earlier build
+    int32_t *off_d = (int32_t *)g.se_in.p;
+    uint8_t *mask_d = (uint8_t *)((char *)g.se_in.p + kkk * sizeof(int32_t));
+    MD_HIP(hipMemcpy(off_d, se.off.data(), kkk * sizeof(int32_t), hipMemcpyHostToDevice));
+    MD_HIP(hipMemcpy(mask_d, se.mask.data(), kkk, hipMemcpyHostToDevice));
+    const uint32_t scale = pinv(pmul(pmul((uint32_t)nt, (uint32_t)nt), (uint32_t)nt));
+    MD_HIP(launch_ntt3_se_spectrum(mask_d, off_d, k, nt, n, (const uint32_t *)rt->rpow.p, g.ntw, scale,
+                                   (uint32_t *)g.se_work.p, (uint32_t *)sp->spec.p, (uint32_t *)sp->spec_s.p,
+                                   g.stream));
+    MD_HIP(hipStreamSynchronize(g.stream));
+    *out = sp.get();
+    g.nspectra[key] = std::move(sp);
+    return MD_OK;
+}
+
+// Modular products of one cubic (tile, bin) item: one per butterfly of the
+// forward and inverse transforms along the three axes and one per point.
+double ntt3_item_products(int nt) {
+    const double n3 = (double)nt * nt * nt;
+    return n3 * std::log2(n3) + n3;
+}
+
+// Cost of one cubic item, scaled from the measured image item at length 16
+// by the modular products (both are LDS-resident transforms of the same
+// passes).
+double ntt3_item_cost(int nt) {
+    const double per = g.cost.fft_item[2][4] / (256.0 * 8.0 + 256.0);
+    return per * ntt3_item_products(nt);
+}
+
+struct VolPlan {
+    int path = kPathDirect;
+    int pack = 1, sel = 0;
+    size_t lds = 0;
+    int nt = 0, T = 0, n = 0, tiles_x = 0, tiles_y = 0, tiles_z = 0;
+    double cost_dir = INFINITY, cost_ntt = INFINITY;
+    std::vector<SEData> slabs;   // active slabs (direct)
+    std::vector<int> slab_a;
+};
+
+int vol_plan(int D, int H, int W, int L, const VolSE &se, VolPlan &p) {
+    const int k = se.k, r = (k - 1) / 2;
+    const double vox = (double)D * H * W;
+    // direct window: one pass per active slab
+    p.pack = (long long)(L - 1) + se.maxoff <= 16383 ? 1 : 0;
+    double cells = 0;
+    for (int a = 0; a < k; ++a) {
+        bool any = false;
+        for (size_t c = (size_t)a * k * k; c < (size_t)(a + 1) * k * k; ++c) any |= se.mask[c] != 0;
+        if (!any) continue;
+        p.slabs.emplace_back();
+        vol_slab(se, a, p.slabs.back());
+        p.slab_a.push_back(a);
+        cells += p.slabs.back().dir_cells[p.pack ? 0 : 1];
+    }
+    const int kpad = (k + kDirRX - 1) / kDirRX * kDirRX;
+    p.sel = !p.pack && direct_lds_bytes(k, kpad, 0, 1) <= kLdsBytes ? 1 : 0;
+    p.lds = direct_lds_bytes(k, kpad, p.pack, p.sel);
+    p.cost_dir = vox * ((double)p.slabs.size() * dir_staged(k, p.pack) * g.cost.dir_stage +
+                        cells * g.cost.dir_cell[p.pack ? 0 : 1]);
+    // exact transform: range length n >= L + max offset, cubic tiles 8 / 16 / 32
+    long long nmin = (long long)(L - 1) + se.maxoff + 1;
+    int n = ntt_length(nmin);
+    if (g.opt.nr > 0) {
+        if (g.opt.nr < nmin) return fail(MD_ERR_ARG, "forced range length %d < (L-1)+max offset+1 = %lld", g.opt.nr, nmin);
+        if (ntt_length(g.opt.nr) != g.opt.nr)
+            return fail(MD_ERR_ARG, "range length %d is not 2^a or 7*2^a up to %d", g.opt.nr, kNttMaxNr);
+        n = g.opt.nr;
+    }
+    if (n > 0 && n <= kNttMaxNr) {
+        for (int nt = 8; nt <= 32; nt *= 2) {
+            if (g.opt.tile > 0 && g.opt.tile != nt) continue;
+            const int T = nt - k + 1;
+            if (T < 1) continue;
+            const double tiles = (double)((D + T - 1) / T) * ((H + T - 1) / T) * ((W + T - 1) / T);
+            const double c = tiles * n * ntt3_item_cost(nt) + tiles * T * T * T * n * g.cost.dec_unit[2];
+            if (c < p.cost_ntt) {
+                p.cost_ntt = c;
+                p.nt = nt;
+                p.T = T;
+                p.n = n;
+            }
+        }
+    }
+    const bool ntt_ok = p.nt > 0;
+    switch (g.opt.path) {
+        case kPathFFT:
+            if (!ntt_ok)
+                return fail(MD_ERR_UNSUPPORTED,
+                            g.opt.tile > 0 ? "no volume transform plan with tile %d for k=%d, L+max offset=%lld"
+                                           : "no volume transform plan (tile %d) for k=%d, L+max offset=%lld",
+                            g.opt.tile, k, nmin);
+            p.path = kPathFFT;
+            break;
+        case kPathDirect: p.path = kPathDirect; break;
+        default: p.path = ntt_ok && p.cost_ntt < p.cost_dir ? kPathFFT : kPathDirect; break;
+    }
+    if (p.path == kPathFFT) {
+        p.tiles_z = (D + p.T - 1) / p.T;
+        p.tiles_y = (H + p.T - 1) / p.T;
+        p.tiles_x = (W + p.T - 1) / p.T;
+    } else if (p.lds > kLdsBytes) {
+        return fail(MD_ERR_UNSUPPORTED, "direct window for k=%d exceeds the LDS", k);
+    }
+    (void)r;
+    return MD_OK;
+}
+
+int vol_run(int op, const int32_t *vol, int D, int H, int W, int L, const uint8_t *mask, const int32_t *off, int k,
+            int32_t *out) {
+    MD_TRY(init());
+    if (!vol || !out) return fail(MD_ERR_ARG, "null volume or output pointer");
+    if ((const void *)vol == (const void *)out) return fail(MD_ERR_ARG, "output must not alias the input");
+    if (!mask || !off) return fail(MD_ERR_ARG, "null SE array");
+    if (D < 1 || H < 1 || W < 1) return fail(MD_ERR_ARG, "volume shape %dx%dx%d", D, H, W);
+    if ((long long)D * H * W > 0x7fffffffLL) return fail(MD_ERR_ARG, "volume has more than 2^31-1 voxels");
+    if (L < 2 || L > (1 << 24)) return fail(MD_ERR_ARG, "L=%d outside [2, 2^24]", L);
+    if (k < 1 || k > kVolMaxK || (k % 2) == 0) return fail(MD_ERR_ARG, "k=%d must be odd in [1,%d]", k, kVolMaxK);
+    for (int q = 0; q < k * k * k; ++q)
+        if (mask[q] && (off[q] < 0 || off[q] > (1 << 24)))
+            return fail(MD_ERR_RANGE, "SE offset %d at cell %d outside [0, 2^24]", off[q], q);
+    VolSE se;
+    make_vol_se(mask, off, k, op, se);
+    VolPlan p;
+    MD_TRY(vol_plan(D, H, W, L, se, p));
+    const bool prof = g.opt.profile != 0;
+    const double vox = (double)D * H * W;
+    JobDev d;
+    memset(&d, 0, sizeof d);
+    d.img = vol;
+    d.out = out;
+    d.D = D;
+    d.H = H;
+    d.W = W;
+    d.L = L;
+    d.k = k;
+    d.op = op;
+    d.path = p.path;
+    // the device tables are rewritten below: earlier work on the stream may
+    // still read them
+    MD_HIP(hipStreamSynchronize(g.stream));
+    MD_HIP(launch_zero(g.st_d, sizeof(StatsDev), g.stream));
+    long long tiles = 0;
+    if (p.path == kPathDirect) {
+        std::vector<SlabDev> sl(p.slabs.size());
+        for (size_t i = 0; i < p.slabs.size(); ++i) {
+            DirSE *ds = nullptr;
+            MD_TRY(get_dirse(p.slabs[i], &ds));
+            SlabDev &e = sl[i];
+            memset(&e, 0, sizeof e);
+            e.sek = (const int32_t *)ds->sek.p;
+            e.sek16 = (const int32_t *)ds->sek16.p;
+            e.sek_rows = (const int32_t *)ds->rows.p;
+            e.sek_steps = (const int32_t *)ds->steps.p;
+            e.dir_nsteps = ds->nsteps;
+            e.dz = p.slab_a[i] - (k - 1) / 2;
+            d.kpad = ds->kpad;
+        }
+        if (sl.empty()) d.kpad = (k + kDirRX - 1) / kDirRX * kDirRX;
+        MD_TRY(g.vslabs.ensure(std::max<size_t>(1, sl.size()) * sizeof(SlabDev)));
+        if (!sl.empty()) MD_HIP(hipMemcpy(g.vslabs.p, sl.data(), sl.size() * sizeof(SlabDev), hipMemcpyHostToDevice));
+        d.slabs = (const SlabDev *)g.vslabs.p;
+        d.nslab = (int)sl.size();
+        d.dir_pack = p.pack;
+        d.dir_bx = (W + kDirBW - 1) / kDirBW;
+        d.dir_by = (H + direct_block_rows(p.pack) - 1) / direct_block_rows(p.pack);
+        Seg sg{};
+        sg.job = 0;
+        const long long nitems = (long long)D * d.dir_by * d.dir_bx;
+        MD_TRY(g.vjob.ensure(sizeof(JobDev)));
+        MD_TRY(g.vseg.ensure(sizeof(Seg)));
+        MD_HIP(hipMemcpy(g.vjob.p, &d, sizeof(JobDev), hipMemcpyHostToDevice));
+        MD_HIP(hipMemcpy(g.vseg.p, &sg, sizeof(Seg), hipMemcpyHostToDevice));
+        double units = 0;
+        for (auto &sd : p.slabs) units += sd.dir_cells[p.pack ? 0 : 1];
+        ProfScope ps(prof, g.stream, p.pack ? "direct3_16" : "direct3_32", vox * 8.0, vox * se.ncells * 2.0,
+                     vox * units);
+        MD_HIP(launch_direct(p.pack, p.sel, (const JobDev *)g.vjob.p, (const Seg *)g.vseg.p, 1, nitems,
+                             occupancy_grid(nitems, p.lds, kDirThreads), p.lds, g.st_d, g.stream, true));
+        ps.done();
+    } else {
+        NttRange *nrt = nullptr;
+        MD_TRY(get_nrange(p.n, L, &nrt));
+        NttSpec *nsp = nullptr;
+        MD_TRY(get_vspectrum(se, p.nt, p.n, nrt, &nsp));
+        d.nt = p.nt;
+        d.T = p.T;
+        d.nr = p.n;
+        d.bins = p.n;
+        d.tiles_x = p.tiles_x;
+        d.tiles_y = p.tiles_y;
+        d.tiles_z = p.tiles_z;
+        d.dbl = kPrecNTT;
+        d.se_spec = nsp->spec.p;
+        d.ntt_spec_s = (const uint32_t *)nsp->spec_s.p;
+        d.enc = nrt->enc.p;
+        d.dec = nrt->dec.p;
+        d.ntt_dec_s = (const uint32_t *)nrt->dec_s.p;
+        d.dec_pitch = nrt->dp;
+        d.ntt_dtop = (L - 1) + se.maxoff;
+        tiles = (long long)p.tiles_x * p.tiles_y * p.tiles_z;
+        const size_t TTT = (size_t)p.T * p.T * p.T, per_tile = (size_t)p.n * TTT * sizeof(uint32_t);
+        const size_t cap = (size_t)(g.opt.ws_mb * 1024.0 * 1024.0);
+        const long long chunk = std::max<long long>(1, std::min<long long>(tiles, (long long)(cap / per_tile)));
+        const int pblocks = (int)((TTT + kDecThreads * kDecPixPerThread - 1) / (kDecThreads * kDecPixPerThread));
+        std::vector<Seg> segs;
+        for (long long t0 = 0; t0 < tiles; t0 += chunk) {
+            Seg sg{};
+            sg.job = 0;
+            sg.tile0 = (int)t0;
+            sg.ntiles = (int)std::min(chunk, tiles - t0);
+            sg.pblocks = pblocks;
+            segs.push_back(sg);
+        }
+        MD_TRY(g.vy.ensure((size_t)chunk * per_tile));
+        for (auto &sg : segs) sg.y = g.vy.p;
+        MD_TRY(g.vjob.ensure(sizeof(JobDev)));
+        MD_TRY(g.vseg.ensure(segs.size() * sizeof(Seg)));
+        MD_HIP(hipMemcpy(g.vjob.p, &d, sizeof(JobDev), hipMemcpyHostToDevice));
+        MD_HIP(hipMemcpy(g.vseg.p, segs.data(), segs.size() * sizeof(Seg), hipMemcpyHostToDevice));
+        const int threads = ntt3_block_threads(p.nt);
+        const size_t lds = (size_t)p.nt * p.nt * (p.nt + 1) * sizeof(uint32_t);
+        for (size_t c = 0; c < segs.size(); ++c) {
+            const Seg *sd = (const Seg *)g.vseg.p + c;
+            const long long nt_ = segs[c].ntiles, items = nt_ * p.n;
+            const double n3 = (double)p.nt * p.nt * p.nt;
+            {
+                ProfScope ps(prof, g.stream, "ntt3_n" + std::to_string(p.nt),
+                             (double)items * TTT * 4.0 + (double)nt_ * n3 * 4.0,
+                             (double)items * ntt3_item_products(p.nt), (double)items);
+                MD_HIP(launch_ntt3(p.nt, (const JobDev *)g.vjob.p, sd, 1, items, occupancy_grid(items, lds, threads),
+                                   g.ntw, g.ntws, g.st_d, g.stream));
+                ps.done();
+            }
+            {
+                const double v = (double)nt_ * TTT;
+                const long long ditems = nt_ * pblocks;
+                ProfScope ps(prof, g.stream, "decode_ntt3", v * p.n * 4.0 + v * 4.0, v * 8.0 * p.n, v * p.n);
+                MD_HIP(launch_ntt3_decode((const JobDev *)g.vjob.p, sd, 1, ditems,
+                                          occupancy_grid(ditems, 0, kDecThreads), g.stream));
+                ps.done();
+            }
+        }
+    }
+    if (g.opt.sync) {
+        MD_HIP(hipStreamSynchronize(g.stream));
+        resolve_profile();
+        MD_HIP(hipMemcpy(g.st_h, g.st_d, sizeof(StatsDev), hipMemcpyDeviceToHost));
+        md_stats &st = g.last;
+        memset(&st, 0, sizeof st);
+        st.tiles = tiles;
+        st.direct_jobs = p.path == kPathDirect;
+        st.fft_jobs = p.path == kPathFFT;
+        st.path = p.path;
+        st.n_t = p.path == kPathFFT ? p.nt : 0;
+        st.n_r = p.path == kPathFFT ? p.n : 0;
+        st.precision = p.path == kPathFFT ? kPrecNTT : g.opt.precision;
+        if (g.st_h->range_err) return fail(MD_ERR_RANGE, "a volume value lies outside [0, L-1]");
+    }
+    g_err.clear();
+    return MD_OK;
+}
+
 }  // namespace
 }  // namespace md
 
@@ -1518,6 +1844,16 @@ int md_erode(const int32_t *img, int H, int W, int L, const uint8_t *se_mask, co
 }
 
 int md_dilate_batch(const md_job *jobs, int n) { return run(jobs, n, true); }
+
+int md_dilate3(const int32_t *vol, int D, int H, int W, int L, const uint8_t *se_mask, const int32_t *se_offsets,
+               int k, int32_t *out) {
+    return vol_run(0, vol, D, H, W, L, se_mask, se_offsets, k, out);
+}
+
+int md_erode3(const int32_t *vol, int D, int H, int W, int L, const uint8_t *se_mask, const int32_t *se_offsets,
+              int k, int32_t *out) {
+    return vol_run(1, vol, D, H, W, L, se_mask, se_offsets, k, out);
+}
 
 int md_morph(int op, const int32_t *img, int H, int W, int L, const uint8_t *se_mask, const int32_t *se_offsets,
              int k, int32_t *out) {
@@ -1545,8 +1881,8 @@ int md_set_option(int key, double v) {
             o.path = (int)v;
             break;
         case MD_OPT_TILE:
-            if (v != 0 && !(v >= 16 && v <= kMaxN && v == floor(v) && ((int)v & ((int)v - 1)) == 0))
-                return fail(MD_ERR_ARG, "tile must be 0 or a power of two in [16, %d]", kMaxN);
+            if (v != 0 && !(v >= 8 && v <= kMaxN && v == floor(v) && ((int)v & ((int)v - 1)) == 0))
+                return fail(MD_ERR_ARG, "tile must be 0 or a power of two in [8, %d]", kMaxN);
             o.tile = (int)v;
             break;
         case MD_OPT_NR:
@@ -1651,6 +1987,10 @@ int md_release(void) {
     g.se_in.release();
     g.morph_a.release();
     g.morph_b.release();
+    g.vjob.release();
+    g.vseg.release();
+    g.vslabs.release();
+    g.vy.release();
     if (g.tw64) (void)hipFree(g.tw64);
     if (g.tw32) (void)hipFree(g.tw32);
     if (g.ntw) (void)hipFree(g.ntw);
