@@ -8,8 +8,9 @@ FP32 transforms with split twiddles and exact FP64 recompute of ambiguous
 tiles, HIP-graph replay).  Inputs are resident in HBM before timing starts.
 
 Also measured on the same batch: the plain FP64 FFT path (every job forced
-through FP64 transforms), the FP32 FFT path forced for every job, and the
-direct window for every job.  A profiled pass (HIP events around every
+through FP64 transforms), the FP32 FFT path forced for every job, the exact
+mod-p transform path, and the direct window for every job; and the volume
+path (three image axes) on a 128 x 256 x 256 volume.  A profiled pass (HIP events around every
 launch) gives the dominant kernel's average duration for the roofline
 figure; the CPU oracle is timed on a bounded prefix of the batch.
 
@@ -77,9 +78,17 @@ def timed_steps(md, torch, stream, args_list, outs, steps, warmup, **opts):
 def kernel_of(stage):
     """HIP kernel that a profiled stage launches."""
     if stage == "direct16":
-        return "k_direct16"
+        return "k_direct16<false>"
     if stage == "direct32":
-        return "k_direct<false>"
+        return "k_direct32<sel, false>"
+    if stage == "direct3_16":
+        return "k_direct16<true>"
+    if stage == "direct3_32":
+        return "k_direct32<sel, true>"
+    if stage == "decode_ntt3":
+        return "k_ntt3_decode"
+    if stage.startswith("ntt3"):
+        return f"k_ntt3<{stage.split('_n')[1]}>"
     if stage.startswith("fft"):
         prec, n = ("float" if stage.startswith("fft32") else "double"), int(stage.split("_n")[1])
         big = n > (128 if prec == "float" else 64)
@@ -102,7 +111,7 @@ def measured_traffic(kernel, workload):
     taken."""
     import hashlib
 
-    path = os.path.join(ROOT, "profiles", f"{kernel}_{workload}_traffic.txt")
+    path = os.path.join(ROOT, "profiles", f"{kernel.split('<')[0]}_{workload}_traffic.txt")
     if not os.path.exists(path):
         return None
     rec = {}
@@ -128,7 +137,7 @@ def roofline_for(stage, prof, workload):
             "stage": stage, "avg_launch_ms": per_launch_ms,
             "alg_bytes_per_launch": rec["alg_bytes"] / rec["launches"]}
     if stage.startswith("direct"):
-        peak = INT16X2_ALU_TOPS if stage == "direct16" else INT32_ALU_TOPS
+        peak = INT16X2_ALU_TOPS if stage.endswith("16") else INT32_ALU_TOPS
         return {"bound": "alu", "peak": peak, "unit": "TOP/s", "frac": achieved / peak, **base}
     if stage.startswith(("ntt", "decode_ntt")):
         # modular products (Shoup): one 32-bit high multiply (4 issue slots at
@@ -139,6 +148,52 @@ def roofline_for(stage, prof, workload):
     fp64 = stage.startswith(("fft64", "decode64", "recompute64"))
     peak = FP64_VECTOR_TFLOPS if fp64 else FP32_VECTOR_TFLOPS
     return {"bound": "alu", "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak, **base}
+
+
+def volume_leg(md, torch, dev, stream, steps):
+    """The volume path on a 128 x 256 x 256 blurred volume (L = 16, 7 x 7 x 7
+    ball SE, offsets in [0, 3]): auto, direct window and exact transform, each
+    timed over `steps` calls with per-stage figures from a profiled pass and
+    sampled voxels checked against the oracle."""
+    import oracle
+    from paper_2305_03018_amd import synthetic
+
+    job = synthetic.blurred_volume(0)
+    vol = torch.from_numpy(job.vol).to(dev)
+    out = torch.empty_like(vol)
+    nvox = int(job.vol.size)
+    rng = np.random.default_rng(9)
+    zs, ys, xs = (rng.integers(0, n, 2048) for n in job.vol.shape)
+    want = oracle.at3(job.vol, job.mask, job.off, job.L, 0, zs, ys, xs)
+    res = {"workload": job.name, "voxels": nvox}
+    for name, opts in (("auto", {}), ("direct", dict(path=2)), ("ntt", dict(path=1))):
+        with md.options(sync=0, **opts):
+            md.dilate3(vol, job.mask, job.off, job.L, out=out)
+            torch.cuda.synchronize()
+            t0 = torch.cuda.Event(enable_timing=True)
+            t1 = torch.cuda.Event(enable_timing=True)
+            t0.record(stream)
+            for _ in range(steps):
+                md.dilate3(vol, job.mask, job.off, job.L, out=out)
+            t1.record(stream)
+            torch.cuda.synchronize()
+        ms = t0.elapsed_time(t1) / steps
+        md.profile_reset()
+        with md.options(profile=1, sync=1, **opts):
+            for _ in range(2):
+                md.dilate3(vol, job.mask, job.off, job.L, out=out)
+            st = md.get_stats()
+        sp = md.profile_get()
+        md.profile_reset()
+        got = out[zs, ys, xs].cpu().numpy()
+        if not np.array_equal(got, want):
+            raise SystemExit(f"bench: volume parity failure ({name})")
+        res[name] = {"ms": ms, "mvoxels_s": nvox / (ms * 1e-3) / 1e6, "path": "direct" if st["path"] == 2 else "ntt",
+                     "n_t": st["n_t"], "n_r": st["n_r"],
+                     "stages": {k: {q: v for q, v in roofline_for(k, sp, "volume").items() if q != "traffic"}
+                                for k in sp if sp[k]["alg_ops"] > 0}}
+        log(f"bench: volume {name} {ms:.3f} ms ({res[name]['mvoxels_s']:.0f} Mvoxel/s)")
+    return res
 
 
 def cpu_baseline(jobs, budget_s):
@@ -232,6 +287,7 @@ def main():
                     st: {k: v for k, v in roofline_for(st, sp, args.workload).items() if k != "traffic"}
                     for st in sp if sp[st]["alg_ops"] > 0}
                 log(f"bench: {name} {m:.3f} ms/step")
+            cmp["volume"] = volume_leg(md, torch, dev, stream, max(3, args.steps // 4))
         # profiled pass for the roofline (events around every launch, no graph)
         md.profile_reset()
         with md.options(profile=1, graph=0, sync=1, precision=0, path=0):

@@ -217,6 +217,7 @@ struct Ctx {
     DevBuf se_work, se_in;
     DevBuf morph_a, morph_b;      // intermediates of md_morph
     DevBuf vjob, vseg, vslabs, vy;  // volume path: job, segments, slab table, transform buffer
+    std::string vtab;               // host image of what vjob / vseg / vslabs hold
     // profiling
     struct Pending {
         std::string name;
@@ -1699,13 +1700,17 @@ int vol_run(int op, const int32_t *vol, int D, int H, int W, int L, const uint8_
     d.k = k;
     d.op = op;
     d.path = p.path;
-    // the device tables are rewritten below: earlier work on the stream may
-    // still read them
-    MD_HIP(hipStreamSynchronize(g.stream));
-    MD_HIP(launch_zero(g.st_d, sizeof(StatsDev), g.stream));
+    // device tables: job, segments, slabs; uploaded only when they differ
+    // from what the buffers hold (a rewrite first waits for earlier work on
+    // the stream, which may still read them)
     long long tiles = 0;
+    std::vector<SlabDev> sl;
+    std::vector<Seg> segs;
+    long long dir_items = 0, chunk = 0;
+    size_t TTT = 0, per_tile = 0;
+    int pblocks = 0;
     if (p.path == kPathDirect) {
-        std::vector<SlabDev> sl(p.slabs.size());
+        sl.resize(p.slabs.size());
         for (size_t i = 0; i < p.slabs.size(); ++i) {
             DirSE *ds = nullptr;
             MD_TRY(get_dirse(p.slabs[i], &ds));
@@ -1717,30 +1722,19 @@ int vol_run(int op, const int32_t *vol, int D, int H, int W, int L, const uint8_
             e.sek_steps = (const int32_t *)ds->steps.p;
             e.dir_nsteps = ds->nsteps;
             e.dz = p.slab_a[i] - (k - 1) / 2;
-            d.kpad = ds->kpad;
         }
-        if (sl.empty()) d.kpad = (k + kDirRX - 1) / kDirRX * kDirRX;
-        MD_TRY(g.vslabs.ensure(std::max<size_t>(1, sl.size()) * sizeof(SlabDev)));
-        if (!sl.empty()) MD_HIP(hipMemcpy(g.vslabs.p, sl.data(), sl.size() * sizeof(SlabDev), hipMemcpyHostToDevice));
+        d.kpad = (k + kDirRX - 1) / kDirRX * kDirRX;
+        if (g.vslabs.bytes < std::max<size_t>(1, sl.size()) * sizeof(SlabDev)) {
+            MD_HIP(hipStreamSynchronize(g.stream));   // the table may still be in use
+            MD_TRY(g.vslabs.ensure(std::max<size_t>(1, sl.size()) * sizeof(SlabDev)));
+        }
         d.slabs = (const SlabDev *)g.vslabs.p;
         d.nslab = (int)sl.size();
         d.dir_pack = p.pack;
         d.dir_bx = (W + kDirBW - 1) / kDirBW;
         d.dir_by = (H + direct_block_rows(p.pack) - 1) / direct_block_rows(p.pack);
-        Seg sg{};
-        sg.job = 0;
-        const long long nitems = (long long)D * d.dir_by * d.dir_bx;
-        MD_TRY(g.vjob.ensure(sizeof(JobDev)));
-        MD_TRY(g.vseg.ensure(sizeof(Seg)));
-        MD_HIP(hipMemcpy(g.vjob.p, &d, sizeof(JobDev), hipMemcpyHostToDevice));
-        MD_HIP(hipMemcpy(g.vseg.p, &sg, sizeof(Seg), hipMemcpyHostToDevice));
-        double units = 0;
-        for (auto &sd : p.slabs) units += sd.dir_cells[p.pack ? 0 : 1];
-        ProfScope ps(prof, g.stream, p.pack ? "direct3_16" : "direct3_32", vox * 8.0, vox * se.ncells * 2.0,
-                     vox * units);
-        MD_HIP(launch_direct(p.pack, p.sel, (const JobDev *)g.vjob.p, (const Seg *)g.vseg.p, 1, nitems,
-                             occupancy_grid(nitems, p.lds, kDirThreads), p.lds, g.st_d, g.stream, true));
-        ps.done();
+        segs.push_back(Seg{});
+        dir_items = (long long)D * d.dir_by * d.dir_bx;
     } else {
         NttRange *nrt = nullptr;
         MD_TRY(get_nrange(p.n, L, &nrt));
@@ -1762,25 +1756,46 @@ int vol_run(int op, const int32_t *vol, int D, int H, int W, int L, const uint8_
         d.dec_pitch = nrt->dp;
         d.ntt_dtop = (L - 1) + se.maxoff;
         tiles = (long long)p.tiles_x * p.tiles_y * p.tiles_z;
-        const size_t TTT = (size_t)p.T * p.T * p.T, per_tile = (size_t)p.n * TTT * sizeof(uint32_t);
+        TTT = (size_t)p.T * p.T * p.T;
+        per_tile = (size_t)p.n * TTT * sizeof(uint32_t);
         const size_t cap = (size_t)(g.opt.ws_mb * 1024.0 * 1024.0);
-        const long long chunk = std::max<long long>(1, std::min<long long>(tiles, (long long)(cap / per_tile)));
-        const int pblocks = (int)((TTT + kDecThreads * kDecPixPerThread - 1) / (kDecThreads * kDecPixPerThread));
-        std::vector<Seg> segs;
+        chunk = std::max<long long>(1, std::min<long long>(tiles, (long long)(cap / per_tile)));
+        pblocks = (int)((TTT + kDecThreads * kDecPixPerThread - 1) / (kDecThreads * kDecPixPerThread));
         for (long long t0 = 0; t0 < tiles; t0 += chunk) {
             Seg sg{};
-            sg.job = 0;
             sg.tile0 = (int)t0;
             sg.ntiles = (int)std::min(chunk, tiles - t0);
             sg.pblocks = pblocks;
             segs.push_back(sg);
         }
-        MD_TRY(g.vy.ensure((size_t)chunk * per_tile));
+        if (g.vy.bytes < (size_t)chunk * per_tile) {
+            MD_HIP(hipStreamSynchronize(g.stream));   // the buffer may still be in use
+            MD_TRY(g.vy.ensure((size_t)chunk * per_tile));
+        }
         for (auto &sg : segs) sg.y = g.vy.p;
+    }
+    std::string tab((const char *)&d, sizeof d);
+    tab.append((const char *)segs.data(), segs.size() * sizeof(Seg));
+    tab.append((const char *)sl.data(), sl.size() * sizeof(SlabDev));
+    if (tab != g.vtab || g.vjob.bytes < sizeof(JobDev) || g.vseg.bytes < segs.size() * sizeof(Seg)) {
+        MD_HIP(hipStreamSynchronize(g.stream));
         MD_TRY(g.vjob.ensure(sizeof(JobDev)));
         MD_TRY(g.vseg.ensure(segs.size() * sizeof(Seg)));
         MD_HIP(hipMemcpy(g.vjob.p, &d, sizeof(JobDev), hipMemcpyHostToDevice));
         MD_HIP(hipMemcpy(g.vseg.p, segs.data(), segs.size() * sizeof(Seg), hipMemcpyHostToDevice));
+        if (!sl.empty()) MD_HIP(hipMemcpy(g.vslabs.p, sl.data(), sl.size() * sizeof(SlabDev), hipMemcpyHostToDevice));
+        g.vtab = tab;
+    }
+    MD_HIP(launch_zero(g.st_d, sizeof(StatsDev), g.stream));
+    if (p.path == kPathDirect) {
+        double units = 0;
+        for (auto &sd : p.slabs) units += sd.dir_cells[p.pack ? 0 : 1];
+        ProfScope ps(prof, g.stream, p.pack ? "direct3_16" : "direct3_32", vox * 8.0, vox * se.ncells * 2.0,
+                     vox * units);
+        MD_HIP(launch_direct(p.pack, p.sel, (const JobDev *)g.vjob.p, (const Seg *)g.vseg.p, 1, dir_items,
+                             occupancy_grid(dir_items, p.lds, kDirThreads), p.lds, g.st_d, g.stream, true));
+        ps.done();
+    } else {
         const int threads = ntt3_block_threads(p.nt);
         const size_t lds = (size_t)p.nt * p.nt * (p.nt + 1) * sizeof(uint32_t);
         for (size_t c = 0; c < segs.size(); ++c) {
@@ -1991,6 +2006,7 @@ int md_release(void) {
     g.vseg.release();
     g.vslabs.release();
     g.vy.release();
+    g.vtab.clear();
     if (g.tw64) (void)hipFree(g.tw64);
     if (g.tw32) (void)hipFree(g.tw32);
     if (g.ntw) (void)hipFree(g.ntw);
