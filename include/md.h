@@ -95,9 +95,14 @@ typedef enum {
     MD_OPT_PROFILE = 8,    /* 1: bracket every kernel launch of a non-graph call
                               with HIP events and accumulate per-stage times
                               (read with md_profile_get); default 0              */
-    MD_OPT_AUTOTUNE = 9    /* 1 (default): the first auto-path call on a device
+    MD_OPT_AUTOTUNE = 9,   /* 1 (default): the first auto-path call on a device
                               measures the kernels' rates and feeds them to the
                               cost model; 0 keeps the built-in estimates         */
+    MD_OPT_STREAM_ROWS = 10,/* md_dilate_host / md_erode_host: 0 (default) picks
+                              the band height from MD_OPT_STREAM_MB, else the
+                              output rows per band                               */
+    MD_OPT_STREAM_MB = 11  /* device memory for the band buffers of the host-
+                              streamed calls, MiB (default 2048)                 */
 } md_option;
 
 /* Dilation of one image (see the conventions above). */
@@ -142,6 +147,31 @@ typedef enum {
 
 int md_morph(int op, const int32_t *img, int H, int W, int L, const uint8_t *se_mask,
              const int32_t *se_offsets, int k, int32_t *out);
+
+/* Images in HOST memory, possibly larger than the GPU's memory: the
+ * partitioned convolution that the paper's conclusion proposes for very large
+ * images (n_i >= 10^9).  The image is cut into bands of output rows; each
+ * band is uploaded with r = (k-1)/2 halo rows on each side (fewer at the
+ * image border), dilated or eroded on the device as an image of its own by
+ * the same planner and kernels as md_dilate, and its interior rows are copied
+ * back.  A window of an interior row never leaves its band, so the result is
+ * exactly that of md_dilate / md_erode on the whole image.
+ *   - `img` and `out` are H x W int32 row-major HOST arrays (H may exceed
+ *     2^31; W >= 1; a band holds at most 2^31-1 pixels).  They must not
+ *     overlap.  Pinned memory (hipHostMalloc) lets the copies run
+ *     asynchronously; pageable memory works too.
+ *   - SE arrays, L, k and every option as for md_dilate; MD_OPT_SYNC does not
+ *     apply: the call returns when `out` is complete.
+ *   - Device memory: two input and two output band buffers within
+ *     MD_OPT_STREAM_MB (plus the transform workspace of one band), whatever
+ *     the image size.  Uploads, compute and downloads of consecutive bands
+ *     overlap on three HIP streams of default priority.
+ *   - MD_ERR_RANGE if any pixel lies outside [0, L-1] (then `out` is
+ *     unspecified); other errors as for md_dilate. */
+int md_dilate_host(const int32_t *img, long long H, int W, int L, const uint8_t *se_mask,
+                   const int32_t *se_offsets, int k, int32_t *out);
+int md_erode_host(const int32_t *img, long long H, int W, int L, const uint8_t *se_mask,
+                  const int32_t *se_offsets, int k, int32_t *out);
 
 /* Volumes: dilation and erosion of a three-axis image.  Sec. 2.1 defines
  * both for N-dimensional images and Sec. 3 turns the N-dimensional dilation

@@ -23,6 +23,8 @@ from ._binding import (  # noqa: F401
     OPT_PATH,
     OPT_PRECISION,
     OPT_PROFILE,
+    OPT_STREAM_MB,
+    OPT_STREAM_ROWS,
     OPT_SYNC,
     OPT_TILE,
     OPT_WORKSPACE_MB,
@@ -30,8 +32,10 @@ from ._binding import (  # noqa: F401
     dilate,
     dilate3,
     dilate_batch,
+    dilate_host,
     erode,
     erode3,
+    erode_host,
     exported_symbols,
     get_option,
     get_stats,

@@ -14,10 +14,11 @@ _HEADER = os.path.join(os.path.dirname(_PKG), "include", "md.h")
 _lib = None
 
 (OPT_PRECISION, OPT_BAND, OPT_PATH, OPT_TILE, OPT_NR, OPT_SYNC, OPT_GRAPH, OPT_WORKSPACE_MB,
- OPT_PROFILE, OPT_AUTOTUNE) = range(10)
+ OPT_PROFILE, OPT_AUTOTUNE, OPT_STREAM_ROWS, OPT_STREAM_MB) = range(12)
 _OPT_NAMES = {"precision": OPT_PRECISION, "band": OPT_BAND, "path": OPT_PATH, "tile": OPT_TILE,
               "nr": OPT_NR, "sync": OPT_SYNC, "graph": OPT_GRAPH, "workspace_mb": OPT_WORKSPACE_MB,
-              "profile": OPT_PROFILE, "autotune": OPT_AUTOTUNE}
+              "profile": OPT_PROFILE, "autotune": OPT_AUTOTUNE, "stream_rows": OPT_STREAM_ROWS,
+              "stream_mb": OPT_STREAM_MB}
 _STATUS = {0: "MD_OK", -1: "MD_ERR_ARG", -2: "MD_ERR_RANGE", -3: "MD_ERR_NOMEM",
            -4: "MD_ERR_DEVICE", -5: "MD_ERR_UNSUPPORTED"}
 
@@ -63,6 +64,10 @@ def load():
     for name in ("md_dilate", "md_erode"):
         f = getattr(lib, name)
         f.argtypes = [vp, i, i, i, u8, vp, i, vp]
+        f.restype = i
+    for name in ("md_dilate_host", "md_erode_host"):
+        f = getattr(lib, name)
+        f.argtypes = [vp, ctypes.c_longlong, i, i, u8, vp, i, vp]
         f.restype = i
     for name in ("md_dilate3", "md_erode3"):
         f = getattr(lib, name)
@@ -169,6 +174,45 @@ def dilate(img, mask, off, L: int, out=None):
 def erode(img, mask, off, L: int, out=None):
     """Exact erosion: min over the SE of img(x+y) - b(y), L-1 on empty windows."""
     return _run_single("md_erode", img, mask, off, L, out)
+
+
+def _run_host(fname, img, mask, off, L, out):
+    """img / out: C-contiguous int32 numpy arrays or CPU torch tensors (pinned
+    or not) of shape (H, W)."""
+    import torch
+
+    lib = load()
+
+    def ptr_of(a, what):
+        if isinstance(a, torch.Tensor):
+            if a.is_cuda or a.dtype != torch.int32 or a.dim() != 2 or not a.is_contiguous():
+                raise TypeError(f"{what} must be a contiguous 2-D int32 host tensor")
+            return a.data_ptr(), tuple(a.shape)
+        if not isinstance(a, np.ndarray) or a.dtype != np.int32 or a.ndim != 2 or not a.flags.c_contiguous:
+            raise TypeError(f"{what} must be a C-contiguous 2-D int32 numpy array")
+        return a.ctypes.data, a.shape
+
+    ip, shape = ptr_of(img, "image")
+    if out is None:
+        out = np.empty(shape, np.int32)
+    op_, oshape = ptr_of(out, "out")
+    if oshape != shape:
+        raise ValueError("out must have the image's shape")
+    mask, off = _se_arrays(mask, off)
+    rc = getattr(lib, fname)(ip, shape[0], shape[1], int(L), mask.ctypes.data, off.ctypes.data, mask.shape[0], op_)
+    _check(rc)
+    return out
+
+
+def dilate_host(img, mask, off, L: int, out=None):
+    """Exact dilation of an image in host memory, streamed through the GPU in
+    bands of rows (md_dilate_host)."""
+    return _run_host("md_dilate_host", img, mask, off, L, out)
+
+
+def erode_host(img, mask, off, L: int, out=None):
+    """Exact erosion of an image in host memory (md_erode_host)."""
+    return _run_host("md_erode_host", img, mask, off, L, out)
 
 
 def _run_volume(fname, vol, mask, off, L, out):

@@ -855,6 +855,10 @@ __global__ void k_zero(uint32_t *p, size_t n) {
         p[i] = 0u;
 }
 
+__global__ void k_or_flag(uint32_t *dst, const uint32_t *src) {
+    if (threadIdx.x == 0) dst[0] |= src[0];
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -928,6 +932,11 @@ hipError_t launch_zero(void *p, size_t bytes, hipStream_t s) {
     if (n == 0) return hipSuccess;
     const int grid = (int)std::min<size_t>((n + 255) / 256, 2048);
     k_zero<<<grid, 256, 0, s>>>((uint32_t *)p, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_or_flag(uint32_t *dst, const uint32_t *src, hipStream_t s) {
+    k_or_flag<<<1, 64, 0, s>>>(dst, src);
     return hipGetLastError();
 }
 

@@ -141,6 +141,8 @@ hipError_t launch_se_spectrum(const uint8_t *mask_d, const int32_t *off_d, int k
                               const double2 *tw64, double2 *work, double2 *spec64, float2 *spec32,
                               hipStream_t s);
 hipError_t launch_zero(void *p, size_t bytes, hipStream_t s);
+// *dst |= *src (one word)
+hipError_t launch_or_flag(uint32_t *dst, const uint32_t *src, hipStream_t s);
 // out[i] = in[i] + c  /  out[i] = x[i] - y[i], i < n (int32; out may alias)
 hipError_t launch_add_const(int32_t *out, const int32_t *in, int32_t c, size_t n, hipStream_t s);
 hipError_t launch_sub(int32_t *out, const int32_t *x, const int32_t *y, size_t n, hipStream_t s);

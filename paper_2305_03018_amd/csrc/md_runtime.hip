@@ -61,6 +61,8 @@ struct Options {
     double ws_mb = 8192.0;
     int profile = 0;
     int autotune = 1;
+    int stream_rows = 0;
+    double stream_mb = 2048.0;
 };
 
 // Device buffer that only grows.
@@ -218,6 +220,11 @@ struct Ctx {
     DevBuf morph_a, morph_b;      // intermediates of md_morph
     DevBuf vjob, vseg, vslabs, vy;  // volume path: job, segments, slab table, transform buffer
     std::string vtab;               // host image of what vjob / vseg / vslabs hold
+    // host-streamed images: upload / download streams, two band buffers per
+    // direction, their events, and an accumulated range-error flag
+    hipStream_t s_up = nullptr, s_down = nullptr;
+    hipEvent_t ev_up[2] = {nullptr, nullptr}, ev_comp[2] = {nullptr, nullptr}, ev_down[2] = {nullptr, nullptr};
+    DevBuf hs_in[2], hs_out[2], hs_flag;
     // profiling
     struct Pending {
         std::string name;
@@ -1502,6 +1509,123 @@ int morph(int op, const int32_t *img, int H, int W, int L, const uint8_t *mask, 
 }
 
 // ---------------------------------------------------------------------------
+// host-streamed images (partitioned convolution over bands of rows)
+// ---------------------------------------------------------------------------
+int stream_run(int op, const int32_t *img, long long H, int W, int L, const uint8_t *mask, const int32_t *off, int k,
+               int32_t *out) {
+    MD_TRY(init());
+    if (!img || !out) return fail(MD_ERR_ARG, "null image or output pointer");
+    if (!mask || !off) return fail(MD_ERR_ARG, "null SE array");
+    if (H < 1 || W < 1) return fail(MD_ERR_ARG, "image shape %lldx%d", H, W);
+    if (k < 1 || k > kMaxN - 1 || (k % 2) == 0) return fail(MD_ERR_ARG, "k=%d must be odd in [1,%d]", k, kMaxN - 1);
+    const size_t bytes_all = (size_t)H * W * sizeof(int32_t);
+    if ((const char *)img < (const char *)out + bytes_all && (const char *)out < (const char *)img + bytes_all)
+        return fail(MD_ERR_ARG, "output must not overlap the input");
+    const int r = (k - 1) / 2;
+    // output rows per band: forced, or the most that four buffers of
+    // (rows + 2r) x W words fit into the budget; a band image stays below 2^31
+    // pixels
+    long long R = g.opt.stream_rows;
+    if (R <= 0) {
+        const double budget = g.opt.stream_mb * 1024.0 * 1024.0;
+        R = (long long)(budget / (4.0 * sizeof(int32_t) * W)) - 2 * r;
+    }
+    R = std::min<long long>(R, 0x7fffffffLL / W - 2 * r);
+    if (R < 1) return fail(MD_ERR_ARG, "a band of %d columns with %d halo rows does not fit (MD_OPT_STREAM_MB)", W, 2 * r);
+    R = std::min<long long>(R, H);
+    const long long nb = (H + R - 1) / R;
+    const size_t band_bytes = (size_t)(std::min<long long>(H, R + 2 * r)) * W * sizeof(int32_t);
+    if (!g.s_up) {
+        MD_HIP(hipStreamCreateWithFlags(&g.s_up, hipStreamNonBlocking));
+        MD_HIP(hipStreamCreateWithFlags(&g.s_down, hipStreamNonBlocking));
+        for (int i = 0; i < 2; ++i) {
+            MD_HIP(hipEventCreateWithFlags(&g.ev_up[i], hipEventDisableTiming));
+            MD_HIP(hipEventCreateWithFlags(&g.ev_comp[i], hipEventDisableTiming));
+            MD_HIP(hipEventCreateWithFlags(&g.ev_down[i], hipEventDisableTiming));
+        }
+    }
+    // calibration (first auto-path call) before any band is in flight
+    if (g.opt.path == 0 && g.opt.autotune && !g.tuned && !g.tuning) MD_TRY(autotune());
+    MD_HIP(hipStreamSynchronize(g.stream));   // the band buffers may still be in use
+    for (int i = 0; i < 2; ++i) {
+        MD_TRY(g.hs_in[i].ensure(band_bytes));
+        MD_TRY(g.hs_out[i].ensure(band_bytes));
+    }
+    MD_TRY(g.hs_flag.ensure(sizeof(uint32_t)));
+    MD_HIP(launch_zero(g.hs_flag.p, sizeof(uint32_t), g.stream));
+    // bands run with MD_OPT_SYNC = 0 so that their work overlaps; every call
+    // below is stream-ordered on the library stream
+    const Options saved = g.opt;
+    g.opt.sync = 0;
+    auto band = [&](long long b, long long &y0, long long &y1, long long &a0, long long &a1) {
+        y0 = b * R;
+        y1 = std::min(H, y0 + R);
+        a0 = std::max(0LL, y0 - r);
+        a1 = std::min(H, y1 + r);
+    };
+    auto download = [&](long long b) -> int {
+        long long y0, y1, a0, a1;
+        band(b, y0, y1, a0, a1);
+        const int i = (int)(b & 1);
+        MD_HIP(hipStreamWaitEvent(g.s_down, g.ev_comp[i], 0));
+        MD_HIP(hipMemcpyAsync(out + (size_t)y0 * W, (const int32_t *)g.hs_out[i].p + (size_t)(y0 - a0) * W,
+                              (size_t)(y1 - y0) * W * sizeof(int32_t), hipMemcpyDeviceToHost, g.s_down));
+        MD_HIP(hipEventRecord(g.ev_down[i], g.s_down));
+        return MD_OK;
+    };
+    int rc = MD_OK;
+    for (long long b = 0; b < nb && rc == MD_OK; ++b) {
+        long long y0, y1, a0, a1;
+        band(b, y0, y1, a0, a1);
+        const int i = (int)(b & 1);
+        int32_t *din = (int32_t *)g.hs_in[i].p, *dout = (int32_t *)g.hs_out[i].p;
+        // buffer i was last read by the compute of band b-2 and written back by
+        // its download
+        if (b >= 2) {
+            if (hipStreamWaitEvent(g.s_up, g.ev_comp[i], 0) != hipSuccess ||
+                hipStreamWaitEvent(g.stream, g.ev_down[i], 0) != hipSuccess) {
+                rc = fail(MD_ERR_DEVICE, "stream wait failed");
+                break;
+            }
+        }
+        if (hipMemcpyAsync(din, img + (size_t)a0 * W, (size_t)(a1 - a0) * W * sizeof(int32_t), hipMemcpyHostToDevice,
+                           g.s_up) != hipSuccess ||
+            hipEventRecord(g.ev_up[i], g.s_up) != hipSuccess || hipStreamWaitEvent(g.stream, g.ev_up[i], 0) != hipSuccess) {
+            rc = fail(MD_ERR_DEVICE, "band upload failed");
+            break;
+        }
+        rc = single(op, din, (int)(a1 - a0), W, L, mask, off, k, dout);
+        if (rc != MD_OK) break;
+        if (launch_or_flag((uint32_t *)g.hs_flag.p, &g.st_d->range_err, g.stream) != hipSuccess ||
+            hipEventRecord(g.ev_comp[i], g.stream) != hipSuccess) {
+            rc = fail(MD_ERR_DEVICE, "band completion record failed");
+            break;
+        }
+        // the previous band goes back while this one computes
+        if (b >= 1) rc = download(b - 1);
+    }
+    if (rc == MD_OK) rc = download(nb - 1);
+    const std::string err = g_err;
+    // drain everything before returning (also after an error: no copy may
+    // still target the caller's arrays)
+    const hipError_t e1 = hipStreamSynchronize(g.s_up), e2 = hipStreamSynchronize(g.stream),
+                     e3 = hipStreamSynchronize(g.s_down);
+    g.opt = saved;
+    if (rc != MD_OK) {
+        g_err = err;
+        return rc;
+    }
+    MD_HIP(e1);
+    MD_HIP(e2);
+    MD_HIP(e3);
+    uint32_t flag = 0;
+    MD_HIP(hipMemcpy(&flag, g.hs_flag.p, sizeof flag, hipMemcpyDeviceToHost));
+    if (flag) return fail(MD_ERR_RANGE, "an image value lies outside [0, L-1]");
+    g_err.clear();
+    return MD_OK;
+}
+
+// ---------------------------------------------------------------------------
 // volumes (three image axes, Sec. 2.1 / Sec. 3 with N = 3)
 // ---------------------------------------------------------------------------
 constexpr int kVolMaxK = 31;
@@ -1860,6 +1984,16 @@ int md_erode(const int32_t *img, int H, int W, int L, const uint8_t *se_mask, co
 
 int md_dilate_batch(const md_job *jobs, int n) { return run(jobs, n, true); }
 
+int md_dilate_host(const int32_t *img, long long H, int W, int L, const uint8_t *se_mask, const int32_t *se_offsets,
+                   int k, int32_t *out) {
+    return stream_run(0, img, H, W, L, se_mask, se_offsets, k, out);
+}
+
+int md_erode_host(const int32_t *img, long long H, int W, int L, const uint8_t *se_mask, const int32_t *se_offsets,
+                  int k, int32_t *out) {
+    return stream_run(1, img, H, W, L, se_mask, se_offsets, k, out);
+}
+
 int md_dilate3(const int32_t *vol, int D, int H, int W, int L, const uint8_t *se_mask, const int32_t *se_offsets,
                int k, int32_t *out) {
     return vol_run(0, vol, D, H, W, L, se_mask, se_offsets, k, out);
@@ -1912,6 +2046,14 @@ int md_set_option(int key, double v) {
             break;
         case MD_OPT_PROFILE: o.profile = v != 0; break;
         case MD_OPT_AUTOTUNE: o.autotune = v != 0; break;
+        case MD_OPT_STREAM_ROWS:
+            if (!(v >= 0 && v <= 0x7fffffff) || v != floor(v)) return fail(MD_ERR_ARG, "band rows must be an integer >= 0");
+            o.stream_rows = (int)v;
+            break;
+        case MD_OPT_STREAM_MB:
+            if (!(v >= 1)) return fail(MD_ERR_ARG, "band buffer budget must be >= 1 MiB");
+            o.stream_mb = v;
+            break;
         default: return fail(MD_ERR_ARG, "unknown option %d", key);
     }
     g_err.clear();
@@ -1931,6 +2073,8 @@ double md_get_option(int key) {
         case MD_OPT_WORKSPACE_MB: return o.ws_mb;
         case MD_OPT_PROFILE: return o.profile;
         case MD_OPT_AUTOTUNE: return o.autotune;
+        case MD_OPT_STREAM_ROWS: return o.stream_rows;
+        case MD_OPT_STREAM_MB: return o.stream_mb;
         default: return NAN;
     }
 }
@@ -2007,6 +2151,16 @@ int md_release(void) {
     g.vslabs.release();
     g.vy.release();
     g.vtab.clear();
+    for (int i = 0; i < 2; ++i) {
+        g.hs_in[i].release();
+        g.hs_out[i].release();
+        for (hipEvent_t *e : {&g.ev_up[i], &g.ev_comp[i], &g.ev_down[i]})
+            if (*e) (void)hipEventDestroy(*e), *e = nullptr;
+    }
+    g.hs_flag.release();
+    if (g.s_up) (void)hipStreamDestroy(g.s_up);
+    if (g.s_down) (void)hipStreamDestroy(g.s_down);
+    g.s_up = g.s_down = nullptr;
     if (g.tw64) (void)hipFree(g.tw64);
     if (g.tw32) (void)hipFree(g.tw32);
     if (g.ntw) (void)hipFree(g.ntw);
