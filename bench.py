@@ -9,8 +9,10 @@ tiles, HIP-graph replay).  Inputs are resident in HBM before timing starts.
 
 Also measured on the same batch: the plain FP64 FFT path (every job forced
 through FP64 transforms), the FP32 FFT path forced for every job, the exact
-mod-p transform path, and the direct window for every job; and the volume
-path (three image axes) on a 128 x 256 x 256 volume.  A profiled pass (HIP events around every
+mod-p transform path, and the direct window for every job; the volume
+path (three image axes) on a 128 x 256 x 256 volume; and a 16384^2 image in
+pinned host memory streamed through the GPU in bands (PCIe included; a
+context figure, never the headline value).  A profiled pass (HIP events around every
 launch) gives the dominant kernel's average duration for the roofline
 figure; the CPU oracle is timed on a bounded prefix of the batch.
 
@@ -196,6 +198,53 @@ def volume_leg(md, torch, dev, stream, steps):
     return res
 
 
+def host_stream_leg(md, torch, dev, steps):
+    """A 16384 x 16384 image (1 GiB, L = 16 uniform, 15 x 15 disk SE with
+    offsets in [0, 7]) in pinned host memory, streamed through the GPU in
+    bands within a 256 MiB band budget (md_dilate_host): wall time per call
+    including the PCIe transfers, against the same dilation with the image
+    already resident in HBM; sampled pixels checked against the oracle."""
+    import oracle
+    from paper_2305_03018_amd import synthetic
+
+    side = 16384
+    rng = np.random.default_rng(11)
+    host = torch.empty((side, side), dtype=torch.int32, pin_memory=True)
+    host.copy_(torch.from_numpy(rng.integers(0, 16, (side, side), dtype=np.int32)))
+    out = torch.empty_like(host, pin_memory=True)
+    mask = synthetic.disk_mask(15)
+    off = rng.integers(0, 8, (15, 15)).astype(np.int32) * mask
+    res = {"workload": f"uniform_{side}x{side}_L16_disk15", "pixels": side * side, "band_budget_mb": 256}
+    with md.options(stream_rows=0, stream_mb=256):
+        md.dilate_host(host, mask, off, 16, out=out)
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            md.dilate_host(host, mask, off, 16, out=out)
+        dt = (time.perf_counter() - t0) / steps
+    ys, xs = rng.integers(0, side, 2048), rng.integers(0, side, 2048)
+    want = oracle.at(host.numpy(), mask, off, 16, 0, ys, xs)
+    if not np.array_equal(out.numpy()[ys, xs], want):
+        raise SystemExit("bench: host-streamed parity failure")
+    res["ms"] = dt * 1e3
+    res["mpx_s_pcie_inclusive"] = side * side / dt / 1e6
+    res["pcie_gb_s"] = 2 * side * side * 4 / dt / 1e9
+    dimg = host.to(dev)
+    dout = torch.empty_like(dimg)
+    md.dilate(dimg, mask, off, 16, out=dout)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        md.dilate(dimg, mask, off, 16, out=dout)
+    torch.cuda.synchronize()
+    dt2 = (time.perf_counter() - t0) / steps
+    res["resident_ms"] = dt2 * 1e3
+    res["resident_mpx_s"] = side * side / dt2 / 1e6
+    log(f"bench: host-streamed {res['ms']:.1f} ms ({res['mpx_s_pcie_inclusive']:.0f} Mpx/s incl. PCIe), "
+        f"resident {res['resident_ms']:.1f} ms")
+    del host, out, dimg, dout
+    return res
+
+
 def cpu_baseline(jobs, budget_s):
     import oracle
 
@@ -288,6 +337,7 @@ def main():
                     for st in sp if sp[st]["alg_ops"] > 0}
                 log(f"bench: {name} {m:.3f} ms/step")
             cmp["volume"] = volume_leg(md, torch, dev, stream, max(3, args.steps // 4))
+            cmp["host_stream"] = host_stream_leg(md, torch, dev, 3)
         # profiled pass for the roofline (events around every launch, no graph)
         md.profile_reset()
         with md.options(profile=1, graph=0, sync=1, precision=0, path=0):
