@@ -41,6 +41,11 @@ INT32_ALU_TOPS = CUS * LANES_PER_CU * CLOCK_GHZ / 1000.0   # one 32-bit integer 
 INT16X2_ALU_TOPS = 2 * INT32_ALU_TOPS                       # packed 16-bit: two ops per lane per clock
 
 
+# the forced-path comparison legs on the batch
+LEG_OPTS = {"fft64": dict(precision=1, path=1), "fft32": dict(precision=0, path=1),
+            "ntt": dict(precision=2, path=1), "direct": dict(precision=0, path=2)}
+
+
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
@@ -271,6 +276,9 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=12.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-compare", action="store_true")
+    ap.add_argument("--leg", choices=["fft64", "fft32", "ntt", "direct"],
+                    help="run only this forced path on the batch (warm-up, --steps timed steps, one profiled "
+                         "step) and print its own JSON line; for hardware-counter runs of its kernels")
     ap.add_argument("--copy-probe", action="store_true",
                     help="first run one plain device copy of 256 MiB (a known-size reference for HBM byte counters)")
     args = ap.parse_args()
@@ -299,6 +307,24 @@ def main():
     arglist = [(im, j.mask, j.off, j.L, j.op) for im, j in zip(imgs, jobs)]
     stream = torch.cuda.Stream()
     res = {}
+    if args.leg:
+        opts = LEG_OPTS[args.leg]
+        with torch.cuda.stream(stream):
+            # one auto-path call first: it calibrates the cost model (or loads
+            # the tune file), so the forced path plans as in the full run
+            with md.options(precision=0, path=0):
+                md.dilate_batch(arglist, outs=outs)
+            m = timed_steps(md, torch, stream, arglist, outs, args.steps, args.warmup, **opts)
+            md.profile_reset()
+            with md.options(profile=1, graph=0, sync=1, **opts):
+                md.dilate_batch(arglist, outs=outs)
+            sp = md.profile_get()
+            md.profile_reset()
+        print(json.dumps({"leg": args.leg, "workload": args.workload, "ms_per_step": m,
+                          "stages": {st: roofline_for(st, sp, args.workload) for st in sp if sp[st]["alg_ops"] > 0}}),
+              flush=True)
+        md.release()
+        return
     with torch.cuda.stream(stream):
         # headline: autotuned batch, FP32 + exact recompute, graph replay
         ms = timed_steps(md, torch, stream, arglist, outs, args.steps, args.warmup, precision=0, path=0)
@@ -321,8 +347,7 @@ def main():
                 raise SystemExit(f"bench: parity failure on job {q} ({j.name})")
         cmp = {}
         if not args.no_compare:
-            for name, opts in (("fft64", dict(precision=1, path=1)), ("fft32", dict(precision=0, path=1)),
-                               ("ntt", dict(precision=2, path=1)), ("direct", dict(precision=0, path=2))):
+            for name, opts in LEG_OPTS.items():
                 m = timed_steps(md, torch, stream, arglist, outs, max(3, args.steps // 4), 1, **opts)
                 cmp[name] = {"ms_per_step": m, "mpx_s": total_px / (m * 1e-3) / 1e6}
                 # per-stage figures of this path (events around every launch)
