@@ -250,6 +250,29 @@ def host_stream_leg(md, torch, dev, steps):
     return res
 
 
+def spectrum_error(md, torch, dev):
+    """Transform-domain values of one tile of the 512 x 512 blurred image
+    (15 x 15 disk, n_t = 128, n_r = 24) just before the inverse range
+    transform, FP32 and FP64, against the DFT of the exact per-pixel
+    coefficient vectors from the oracle."""
+    import oracle
+    from paper_2305_03018_amd import synthetic
+
+    job = synthetic.blurred_512(0)
+    img = torch.from_numpy(job.img).to(dev)
+    nt, nr, ty, tx = 128, 24, 1, 2
+    T = nt - job.k + 1
+    ys, xs = np.divmod(np.arange(T * T), T)
+    counts = oracle.counts_at(job.img, job.mask, job.off, ty * T + ys, tx * T + xs, nr)
+    ref = oracle.range_spectrum_ref(counts, nr).T
+    out = {"config": f"{job.name}, tile ({ty},{tx}) of {T}x{T}, n_t={nt}, n_r={nr}"}
+    for prec, name in ((0, "fp32"), (1, "fp64")):
+        got = md.debug_tile_values(img, job.mask, job.off, job.L, nt, nr, prec, ty, tx)
+        out[f"{name}_rel_l2"] = float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
+        out[f"{name}_max_abs"] = float(np.abs(got - ref).max())
+    return out
+
+
 def cpu_baseline(jobs, budget_s):
     import oracle
 
@@ -326,6 +349,14 @@ def main():
         md.release()
         return
     with torch.cuda.stream(stream):
+        # cold call: calibration first (one small auto-path call), then the
+        # batch's first call builds its plans, SE spectra and graph
+        with md.options(sync=1, precision=0, path=0):
+            md.dilate_batch(arglist[:1], outs=outs[:1])
+            t0 = time.perf_counter()
+            md.dilate_batch(arglist, outs=outs)
+            res["cold_ms"] = (time.perf_counter() - t0) * 1e3
+        log(f"bench: cold batch call {res['cold_ms']:.1f} ms")
         # headline: autotuned batch, FP32 + exact recompute, graph replay
         ms = timed_steps(md, torch, stream, arglist, outs, args.steps, args.warmup, precision=0, path=0)
         res["headline_ms"] = ms
@@ -395,15 +426,23 @@ def main():
                                         "fft_jobs", "direct_jobs")},
         "compare": cmp,
         "stage_ms_per_step": {k: v["ms"] / args.steps for k, v in prof.items()},
+        "cold_ms": res["cold_ms"],
         "cost_model": md.cost_model(),
     }
     if cmp:
         line["speedup_vs_fp64_fft"] = cmp["fft64"]["ms_per_step"] / res["headline_ms"]
         line["fp32_fft_vs_fp64_fft"] = cmp["fft64"]["ms_per_step"] / cmp["fft32"]["ms_per_step"]
         line["exact_ntt_vs_fp64_fft"] = cmp["fft64"]["ms_per_step"] / cmp["ntt"]["ms_per_step"]
+        line["spectrum_error"] = spectrum_error(md, torch, dev)
     if not args.no_cpu:
+        import oracle
+
         log("bench: timing the CPU oracle")
         line["cpu_baseline"] = cpu_baseline(jobs, args.cpu_budget)
+        threads = oracle.num_threads()
+        oracle.set_threads(1)
+        line["cpu_1core"] = cpu_baseline(jobs, args.cpu_budget / 3)
+        oracle.set_threads(threads)
     print(json.dumps(line), flush=True)
     md.release()
 
