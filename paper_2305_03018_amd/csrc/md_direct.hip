@@ -251,6 +251,9 @@ __global__ __launch_bounds__(kDirThreads) void k_direct32(const JobDev *__restri
 // scalar loads.  Per column step, only the SE row pairs with an active cell
 // in those columns are visited (sek_cols), so disk-shaped SEs skip their
 // empty corners.
+// R: packed output row pairs per lane (2 for images; 1 for volumes, whose
+// window passes keep fewer registers live so that 4 blocks fit per CU); a
+// block covers 32 R rows.
 constexpr int kD16R = 2;
 constexpr int kD16BH = 32 * kD16R;
 
@@ -304,16 +307,16 @@ __device__ __forceinline__ void d16_se(int (&b)[NS], const int32_t *p) {
 // arithmetic is the first use of the registers that the previous call's
 // issue() filled, so their wait comes before the loads that issue() starts,
 // and those loads stay in flight over the rest of the pair.
-template <int NS, int O, bool ODD, typename F>
-__device__ __forceinline__ void d16_pair(s16x2 (&acc)[kD16R][kDirRX], const int (&win)[kD16R + 1][D16<NS, O>::NW],
+template <int R, int NS, int O, bool ODD, typename F>
+__device__ __forceinline__ void d16_pair(s16x2 (&acc)[R][kDirRX], const int (&win)[R + 1][D16<NS, O>::NW],
                                          const int (&be)[NS], const int (&bo)[NS], F &&issue) {
     constexpr int NU = NS + kDirRX - 1;
     s16x2 b[NS];
 #pragma unroll
     for (int sj = 0; sj < NS; ++sj) b[sj] = __builtin_bit_cast(s16x2, be[sj]);
 #pragma unroll
-    for (int r = 0; r < kD16R; ++r) {
-        if (r == 1) {
+    for (int r = 0; r < R; ++r) {
+        if (r == (R > 1 ? 1 : 0)) {
             __builtin_amdgcn_sched_barrier(0);
             issue();
             __builtin_amdgcn_sched_barrier(0);
@@ -327,7 +330,7 @@ __device__ __forceinline__ void d16_pair(s16x2 (&acc)[kD16R][kDirRX], const int 
 #pragma unroll
         for (int sj = 0; sj < NS; ++sj) b[sj] = __builtin_bit_cast(s16x2, bo[sj]);
 #pragma unroll
-        for (int r = 0; r < kD16R; ++r) {
+        for (int r = 0; r < R; ++r) {
             s16x2 in[NU];
 #pragma unroll
             for (int t = 0; t < NU; ++t)
@@ -344,13 +347,13 @@ __device__ __forceinline__ void d16_pair(s16x2 (&acc)[kD16R][kDirRX], const int 
 // scalar loads share a counter) comes after its arithmetic.  The fetches
 // reach one word row past the staged block and SE row k at most, which the
 // LDS allocation and the SE array's extra row cover.
-template <int NS, int O>
-__device__ __forceinline__ void d16_column(s16x2 (&acc)[kD16R][kDirRX], const int32_t *trow, int P,
+template <int R, int NS, int O>
+__device__ __forceinline__ void d16_column(s16x2 (&acc)[R][kDirRX], const int32_t *trow, int P,
                                            const int32_t *se, int kpad, int k, int s0, int s1) {
     constexpr int NW = D16<NS, O>::NW;
-    int win[kD16R + 1][NW];
+    int win[R + 1][NW];
 #pragma unroll
-    for (int r = 0; r <= kD16R; ++r) d16_load<NW>(win[r], trow + (s0 + r) * P);
+    for (int r = 0; r <= R; ++r) d16_load<NW>(win[r], trow + (s0 + r) * P);
     const int sfull = min(s1, (k - 3) >> 1);   // pairs with both rows inside the SE
     int be[NS], bo[NS];
     d16_se<NS>(be, se + 2 * s0 * kpad);
@@ -359,17 +362,17 @@ __device__ __forceinline__ void d16_column(s16x2 (&acc)[kD16R][kDirRX], const in
     // one pair: offsets in (ce, co), those of the next pair fetched into (ne, no)
     auto step = [&](const int (&ce)[NS], const int (&co)[NS], int (&ne)[NS], int (&no)[NS]) {
         int nxt[NW];
-        d16_pair<NS, O, true>(acc, win, ce, co, [&] {
-            d16_load<NW>(nxt, trow + (s + kD16R + 1) * P);
+        d16_pair<R, NS, O, true>(acc, win, ce, co, [&] {
+            d16_load<NW>(nxt, trow + (s + R + 1) * P);
             d16_se<NS>(ne, se + (2 * s + 2) * kpad);
             d16_se<NS>(no, se + (2 * s + 3) * kpad);
         });
 #pragma unroll
-        for (int r = 0; r < kD16R; ++r)
+        for (int r = 0; r < R; ++r)
 #pragma unroll
             for (int t = 0; t < NW; ++t) win[r][t] = win[r + 1][t];
 #pragma unroll
-        for (int t = 0; t < NW; ++t) win[kD16R][t] = nxt[t];
+        for (int t = 0; t < NW; ++t) win[R][t] = nxt[t];
         ++s;
     };
     // two pairs per trip, the offset registers alternating between them
@@ -386,32 +389,33 @@ __device__ __forceinline__ void d16_column(s16x2 (&acc)[kD16R][kDirRX], const in
             bo[sj] = bo2[sj];
         }
     }
-    if (s <= s1) d16_pair<NS, O, false>(acc, win, be, bo, [] {});   // s = (k-1)/2: SE row k-1 alone
+    if (s <= s1) d16_pair<R, NS, O, false>(acc, win, be, bo, [] {});   // s = (k-1)/2: SE row k-1 alone
 }
 
 // LDS words of one packed block: word rows of image rows 2p, 2p+1 (low,
 // high half), one spare word row for the prefetch, pitch P = kDirBW + kpad + 4.
 __host__ __device__ constexpr int d16_pitch(int kpad) { return kDirBW + kpad + 4; }
-__host__ __device__ constexpr int d16_rows(int k) { return (kD16BH + k - 1) / 2 + 1; }
+__host__ __device__ constexpr int d16_rows(int k, int R) { return (32 * R + k - 1) / 2 + 1; }
 
 // Output slice z of the job (0 for an image).
 template <bool VOL>
 __device__ __forceinline__ void direct16_block(const JobDev &J, int z, int by0, int bx0, int32_t *tile,
                                                unsigned int *range_err) {
+    constexpr int R = VOL ? 1 : kD16R, BH = 32 * R;
     const int k = J.k, rad = (k - 1) >> 1, kpad = J.kpad;
     const int P = d16_pitch(kpad);
-    const int TH = kD16BH + k - 1;                 // image rows the block reads (even: k is odd)
+    const int TH = BH + k - 1;                     // image rows the block reads (even: k is odd)
     const int TC = kDirBW + k - 1;                 // image columns the block reads
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, wx = wv & 1, wy = wv >> 1;
     const int cg = lane & 7, rg = lane >> 3;
     const int lx0 = wx * 64 + cg * kDirRX;         // first output column of the lane
-    const int q = wy * 8 * kD16R + rg * kD16R;     // LDS word row = first output row / 2
+    const int q = wy * 8 * R + rg * R;             // LDS word row = first output row / 2
     // a wave whose outputs all lie outside the image skips the window
-    const bool live = bx0 + wx * 64 < J.W && by0 + wy * 16 * kD16R < J.H;
-    s16x2 acc[kD16R][kDirRX];
+    const bool live = bx0 + wx * 64 < J.W && by0 + wy * 16 * R < J.H;
+    s16x2 acc[R][kDirRX];
     const int neg = (int)(((unsigned)kNeg16 & 0xffffu) * 0x10001u);
 #pragma unroll
-    for (int r = 0; r < kD16R; ++r)
+    for (int r = 0; r < R; ++r)
 #pragma unroll
         for (int t = 0; t < kDirRX; ++t) acc[r][t] = __builtin_bit_cast(s16x2, neg);
     const int npass = VOL ? J.nslab : 1;
@@ -437,10 +441,10 @@ __device__ __forceinline__ void direct16_block(const JobDev &J, int z, int by0, 
                 const int jb = steps[4 * i], kind = steps[4 * i + 1], s0 = steps[4 * i + 2], s1 = steps[4 * i + 3];
                 const int32_t *se = ps.sek16 + jb;
                 switch (kind) {
-                    case 0: d16_column<8, 0>(acc, base + jb, P, se, kpad, k, s0, s1); break;
-                    case 1: d16_column<4, 0>(acc, base + jb, P, se, kpad, k, s0, s1); break;
-                    case 2: d16_column<2, 0>(acc, base + jb, P, se, kpad, k, s0, s1); break;
-                    default: d16_column<2, 2>(acc, base + jb - 2, P, se, kpad, k, s0, s1); break;
+                    case 0: d16_column<R, 8, 0>(acc, base + jb, P, se, kpad, k, s0, s1); break;
+                    case 1: d16_column<R, 4, 0>(acc, base + jb, P, se, kpad, k, s0, s1); break;
+                    case 2: d16_column<R, 2, 0>(acc, base + jb, P, se, kpad, k, s0, s1); break;
+                    default: d16_column<R, 2, 2>(acc, base + jb - 2, P, se, kpad, k, s0, s1); break;
                 }
             }
         }
@@ -453,7 +457,7 @@ __device__ __forceinline__ void direct16_block(const JobDev &J, int z, int by0, 
     if (live) {
         uint16_t *ob = (uint16_t *)tile;
 #pragma unroll
-        for (int r = 0; r < kD16R; ++r) {
+        for (int r = 0; r < R; ++r) {
             s16x2 c[kDirRX];
 #pragma unroll
             for (int t = 0; t < kDirRX; ++t) c[t] = __builtin_elementwise_max(acc[r][t], (s16x2){0, 0});
@@ -477,7 +481,7 @@ __device__ __forceinline__ void direct16_block(const JobDev &J, int z, int by0, 
         int32_t *out = J.out + (size_t)z * J.H * W;
         const int cx = threadIdx.x & (kDirBW - 1), gx = bx0 + cx;
         if (gx < W) {
-            for (int y = threadIdx.x / kDirBW; y < kD16BH; y += kDirThreads / kDirBW) {
+            for (int y = threadIdx.x / kDirBW; y < BH; y += kDirThreads / kDirBW) {
                 const int gy = by0 + y;
                 if (gy >= J.H) break;
                 const int d = ob[y * kDirBW + cx];
@@ -488,8 +492,10 @@ __device__ __forceinline__ void direct16_block(const JobDev &J, int z, int by0, 
     __syncthreads();   // the LDS block is restaged by the next item
 }
 
+// The volume form asks for 4 waves per SIMD: its window loops fit, and the few
+// values spilled to scratch are read and written outside them.
 template <bool VOL>
-__global__ __launch_bounds__(kDirThreads) void k_direct16(const JobDev *__restrict__ jobs,
+__global__ __launch_bounds__(kDirThreads) __attribute__((amdgpu_waves_per_eu(VOL ? 4 : 1))) void k_direct16(const JobDev *__restrict__ jobs,
                                                           const Seg *__restrict__ segs, int nseg,
                                                           long long nitems, StatsDev *st) {
     extern __shared__ int32_t dyn_lds[];
@@ -499,16 +505,16 @@ __global__ __launch_bounds__(kDirThreads) void k_direct16(const JobDev *__restri
         const int local = (int)(it - S.item0), nb = J.dir_bx * J.dir_by;
         const int z = local / nb, rem = local - z * nb;
         const int byi = rem / J.dir_bx, bxi = rem - byi * J.dir_bx;
-        direct16_block<VOL>(J, z, byi * kD16BH, bxi * kDirBW, dyn_lds, &st->range_err);
+        direct16_block<VOL>(J, z, byi * (VOL ? 32 : kD16BH), bxi * kDirBW, dyn_lds, &st->range_err);
     }
 }
 
 }  // namespace
 
-int direct_block_rows(int pack) { return pack ? kD16BH : kDirBH; }
+int direct_block_rows(int pack, bool vol) { return pack ? (vol ? 32 : kD16BH) : kDirBH; }
 
-size_t direct_lds_bytes(int k, int kpad, int pack, int sel) {
-    if (pack) return (size_t)d16_rows(k) * d16_pitch(kpad) * sizeof(int32_t);
+size_t direct_lds_bytes(int k, int kpad, int pack, int sel, bool vol) {
+    if (pack) return (size_t)d16_rows(k, vol ? 1 : kD16R) * d16_pitch(kpad) * sizeof(int32_t);
     const int rows = kDirBH + k - 1;
     return ((size_t)rows * (kDirBW + kpad) + (sel ? (size_t)k * kpad : 0) + (size_t)((2 * k + 3) & ~3) + 16) *
            sizeof(int32_t);

@@ -162,7 +162,8 @@ hipError_t launch_direct(int pack, int sel, const JobDev *jobs, const Seg *segs,
 hipError_t launch_fallback(int nt64, const JobDev *jobs, const int2 *fb_list, const StatsDev *st,
                            double2 *slots, size_t slot_elems, int grid, const double2 *tw64, double2 *slabs,
                            hipStream_t s);
-size_t direct_lds_bytes(int k, int kpad, int pack, int sel);
+// vol: the volume form of the packed kernel (32-row blocks)
+size_t direct_lds_bytes(int k, int kpad, int pack, int sel, bool vol = false);
 // exact transform path (md_ntt.hip)
 int ntt_block_threads(int nt);
 size_t ntt_lds_bytes(int nt);
@@ -187,7 +188,7 @@ hipError_t launch_ntt_se_spectrum(const uint8_t *mask_d, const int32_t *off_d, i
                                   const uint32_t *rpow, const uint32_t *tw, uint32_t scale, uint32_t *work,
                                   uint32_t *spec, uint32_t *spec_s, hipStream_t s);
 constexpr size_t kLdsBytes = 160 * 1024;
-int direct_block_rows(int pack);
+int direct_block_rows(int pack, bool vol = false);
 int fft_block_threads(int nt, int dbl);
 size_t fft_lds_bytes(int nt, int dbl);
 

@@ -361,19 +361,26 @@ struct SEData {
     double dir_cells[2] = {0, 0};   // cells the direct window steps through per output pixel (packed, 32-bit)
 };
 
-// SE cells per output pixel that the direct window steps through: in its
-// correlation order (row i, column j <-> SE cell (k-1-i, k-1-j)), each row's
-// active span from its first column rounded down to 8, in 8-column steps;
-// the packed form takes SE rows in pairs over the union of their spans, with
-// a 4-column final step where it suffices.
 // Column steps of the packed direct window for one SE, in its correlation
-// order (row i, column j <-> SE cell (k-1-i, k-1-j)).  Each 2-column group
-// g (columns 2g, 2g+1) has the range of SE row pairs (2s, 2s+1) with an
-// active cell there; runs of groups with the same range become steps of 8, 4
-// and 2 columns (8- and 4-column steps start at a multiple of 4, so a run
-// that starts at 2 mod 4 opens with a 2-column step).  Each step is
-// {first column, kind, first pair, last pair}, kind 0/1/2 = 8/4/2 columns,
-// 3 = 2 columns at 2 mod 4.
+// order (row i, column j <-> SE cell (k-1-i, k-1-j)).  Each 2-column group g
+// (columns 2g, 2g+1) has the range of SE row pairs (2s, 2s+1) with an active
+// cell there.  A step of 8, 4 or 2 columns runs over the union of its groups'
+// ranges (8- and 4-column steps start at a multiple of 4); the steps are
+// chosen by dynamic programming over the groups to minimise the issue cost of
+// the window, kDirPairCost per row pair and step width (instructions of one
+// pair in the kernel's unrolled loops), so neighbouring groups with nearly
+// equal ranges share a wider step even where that covers a few masked cells.
+// Each step is {first column, kind, first pair, last pair}, kind 0/1/2 =
+// 8/4/2 columns, 3 = 2 columns at 2 mod 4.
+constexpr double kDirPairCost[3] = {580.5, 311.5, 177.5};   // 8, 4, 2 columns
+
+// row pairs a step over pairs s0..s1 runs (the last, even SE row of an odd k
+// alone counts as one)
+int dir_pairs(int k, int s0, int s1) {
+    const int last = (k - 1) / 2, sfull = (k - 3) / 2;
+    return std::max(0, std::min(s1, sfull) - s0 + 1) + (s1 == last && 2 * last + 1 == k ? 1 : 0);
+}
+
 std::vector<int32_t> dir_steps(const SEData &se) {
     const int k = se.k, kpad = (k + kDirRX - 1) / kDirRX * kDirRX, ng = kpad / 2;
     std::vector<int> lo(ng, k), hi(ng, -1);
@@ -383,56 +390,65 @@ std::vector<int32_t> dir_steps(const SEData &se) {
                 lo[j / 2] = std::min(lo[j / 2], i / 2);
                 hi[j / 2] = std::max(hi[j / 2], i / 2);
             }
+    // best[g]: least cost covering groups [0, g); from[g]: the step that ends
+    // there (width in groups, 0 = an empty group skipped)
+    std::vector<double> best(ng + 1, INFINITY);
+    std::vector<int> from(ng + 1, -1);
+    best[0] = 0;
+    for (int g = 0; g < ng; ++g) {
+        if (!(best[g] < INFINITY)) continue;
+        if (lo[g] > hi[g] && best[g] < best[g + 1]) {
+            best[g + 1] = best[g];
+            from[g + 1] = 0;
+        }
+        for (int w : {1, 2, 4}) {   // groups per step: 2, 4, 8 columns
+            if (g + w > ng || (w > 1 && (2 * g) % 4 != 0)) continue;
+            int s0 = k, s1 = -1;
+            for (int q = g; q < g + w; ++q) {
+                s0 = std::min(s0, lo[q]);
+                s1 = std::max(s1, hi[q]);
+            }
+            if (s0 > s1) continue;
+            const double c = best[g] + kDirPairCost[w == 4 ? 0 : w == 2 ? 1 : 2] * dir_pairs(k, s0, s1);
+            if (c < best[g + w]) {
+                best[g + w] = c;
+                from[g + w] = w;
+            }
+        }
+    }
     std::vector<int32_t> st;
-    auto emit = [&](int jb, int kind, int s0, int s1) {
-        st.push_back(jb);
-        st.push_back(kind);
-        st.push_back(s0);
-        st.push_back(s1);
-    };
-    for (int g = 0; g < ng;) {
-        if (lo[g] > hi[g]) {
-            ++g;
+    for (int g = ng; g > 0;) {
+        const int w = from[g];
+        if (w <= 0) {
+            --g;
             continue;
         }
-        int n = 1;
-        while (g + n < ng && lo[g + n] == lo[g] && hi[g + n] == hi[g]) ++n;
-        const int s0 = lo[g], s1 = hi[g];
-        int c = 2 * g;                       // first column of the run
-        const int end = 2 * (g + n);
-        if (c % 4 == 2) {
-            emit(c, 3, s0, s1);
-            c += 2;
+        const int g0 = g - w;
+        int s0 = k, s1 = -1;
+        for (int q = g0; q < g; ++q) {
+            s0 = std::min(s0, lo[q]);
+            s1 = std::max(s1, hi[q]);
         }
-        while (end - c >= 8) {
-            emit(c, 0, s0, s1);
-            c += 8;
-        }
-        if (end - c >= 4) {
-            emit(c, 1, s0, s1);
-            c += 4;
-        }
-        if (end - c >= 2) {
-            emit(c, 2, s0, s1);
-            c += 2;
-        }
-        g += n;
+        const int c = 2 * g0, kind = w == 4 ? 0 : w == 2 ? 1 : (c % 4 == 2 ? 3 : 2);
+        st.insert(st.begin(), {c, kind, s0, s1});
+        g = g0;
     }
     return st;
 }
 
-// SE cells per output pixel that the direct window steps through.  Packed
-// form: over the column steps of dir_steps, NS columns x (both rows of each
-// full pair + the last row of an odd SE alone).  32-bit form: each row's
-// active span from its first column rounded down to 8, in 8-column steps.
+// Work of the direct window per output pixel.  Packed form: in 8-column-step
+// equivalents -- each step's row pairs weighted by their issue cost relative
+// to an 8-column pair of 16 cells -- so that one calibrated per-cell cost
+// prices every step width.  32-bit form: each row's active span from its
+// first column rounded down to 8, in 8-column steps.
 void dir_work(SEData &se) {
-    const int k = se.k, last = (k - 1) / 2, sfull_max = (k - 3) / 2;
+    const int k = se.k;
     const std::vector<int32_t> st = dir_steps(se);
     double e16 = 0;
     for (size_t i = 0; i < st.size(); i += 4) {
-        const int ns = st[i + 1] == 0 ? 8 : st[i + 1] == 1 ? 4 : 2, s0 = st[i + 2], s1 = st[i + 3];
-        const int nfull = std::max(0, std::min(s1, sfull_max) - s0 + 1);
-        e16 += (double)ns * (2 * nfull + (s1 == last && 2 * last + 1 == k ? 1 : 0));
+        const int kind = st[i + 1];
+        const double w = kDirPairCost[kind == 0 ? 0 : kind == 1 ? 1 : 2] / kDirPairCost[0];
+        e16 += 16.0 * w * dir_pairs(k, st[i + 2], st[i + 3]);
     }
     std::vector<int> lo(k, k), hi(k, -1);
     for (int i = 0; i < k; ++i)
@@ -1742,9 +1758,11 @@ int vol_plan(int D, int H, int W, int L, const VolSE &se, VolPlan &p) {
         cells += p.slabs.back().dir_cells[p.pack ? 0 : 1];
     }
     const int kpad = (k + kDirRX - 1) / kDirRX * kDirRX;
-    p.sel = !p.pack && direct_lds_bytes(k, kpad, 0, 1) <= kLdsBytes ? 1 : 0;
-    p.lds = direct_lds_bytes(k, kpad, p.pack, p.sel);
-    p.cost_dir = vox * ((double)p.slabs.size() * dir_staged(k, p.pack) * g.cost.dir_stage +
+    p.sel = !p.pack && direct_lds_bytes(k, kpad, 0, 1, true) <= kLdsBytes ? 1 : 0;
+    p.lds = direct_lds_bytes(k, kpad, p.pack, p.sel, true);
+    const int bh = direct_block_rows(p.pack, true);
+    const double staged = (double)(bh + k - 1) * (kDirBW + kpad) / ((double)bh * kDirBW);
+    p.cost_dir = vox * ((double)p.slabs.size() * staged * g.cost.dir_stage +
                         cells * g.cost.dir_cell[p.pack ? 0 : 1]);
     // exact transform: range length n >= L + max offset, cubic tiles 8 / 16 / 32
     long long nmin = (long long)(L - 1) + se.maxoff + 1;
@@ -1856,7 +1874,7 @@ int vol_run(int op, const int32_t *vol, int D, int H, int W, int L, const uint8_
         d.nslab = (int)sl.size();
         d.dir_pack = p.pack;
         d.dir_bx = (W + kDirBW - 1) / kDirBW;
-        d.dir_by = (H + direct_block_rows(p.pack) - 1) / direct_block_rows(p.pack);
+        d.dir_by = (H + direct_block_rows(p.pack, true) - 1) / direct_block_rows(p.pack, true);
         segs.push_back(Seg{});
         dir_items = (long long)D * d.dir_by * d.dir_bx;
     } else {
