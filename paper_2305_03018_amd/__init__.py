@@ -9,6 +9,7 @@ without a built ``libmd.so`` raises.
 """
 from ._binding import (  # noqa: F401
     BLACKHAT,
+    Batch,
     CLOSE,
     DILATE,
     ERODE,

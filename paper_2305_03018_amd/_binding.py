@@ -302,31 +302,48 @@ def blackhat(img, mask, off, L: int, out=None):
     return morph(BLACKHAT, img, mask, off, L, out)
 
 
+class Batch:
+    """A batch for md_dilate_batch, marshalled once: jobs is a sequence of
+    (img, mask, off, L, op) with op 0 = dilation, 1 = erosion and images
+    int32 device tensors; outs (optional) the output tensors.  run() makes
+    the call and returns the outputs; a loop that runs the same jobs on the
+    same buffers pays the marshalling once.  The object keeps the tensors and
+    SE arrays alive; SE arrays changed in place are seen by the library (it
+    compares their contents with the previous call's)."""
+
+    def __init__(self, jobs, outs=None):
+        import torch
+
+        self.lib = load()
+        self.n = len(jobs)
+        self.arr = (_Job * self.n)()
+        self.keep = []
+        self.outs = []
+        self.dev = None
+        for q, (img, mask, off, L, op) in enumerate(jobs):
+            img = _device_image(img)
+            self.dev = img.device if self.dev is None else self.dev
+            mask, off = _se_arrays(mask, off)
+            out = torch.empty_like(img) if outs is None else outs[q]
+            self.keep.append((img, mask, off))
+            self.outs.append(out)
+            self.arr[q] = _Job(img.data_ptr(), img.shape[0], img.shape[1], int(L), mask.ctypes.data,
+                               off.ctypes.data, mask.shape[0], out.data_ptr(), int(op))
+
+    def run(self):
+        import torch
+
+        with torch.cuda.device(self.dev):
+            _bind_stream(self.dev)
+            rc = self.lib.md_dilate_batch(self.arr, self.n)
+        _check(rc)
+        return self.outs
+
+
 def dilate_batch(jobs, outs=None):
     """jobs: sequence of (img, mask, off, L, op) with op 0 = dilation, 1 =
     erosion; images are int32 device tensors.  Returns the output tensors."""
-    import torch
-
-    lib = load()
-    n = len(jobs)
-    arr = (_Job * n)()
-    keep = []
-    res = []
-    dev = None
-    for q, (img, mask, off, L, op) in enumerate(jobs):
-        img = _device_image(img)
-        dev = img.device if dev is None else dev
-        mask, off = _se_arrays(mask, off)
-        out = torch.empty_like(img) if outs is None else outs[q]
-        keep.append((img, mask, off))
-        res.append(out)
-        arr[q] = _Job(img.data_ptr(), img.shape[0], img.shape[1], int(L), mask.ctypes.data,
-                      off.ctypes.data, mask.shape[0], out.data_ptr(), int(op))
-    with torch.cuda.device(dev):
-        _bind_stream(dev)
-        rc = lib.md_dilate_batch(arr, n)
-    _check(rc)
-    return res
+    return Batch(jobs, outs).run()
 
 
 def set_option(key, value: float):

@@ -216,6 +216,12 @@ struct Ctx {
     uint32_t *ntw = nullptr, *ntws = nullptr;   // w_kNttTw^j and Shoup companions
     std::unordered_map<std::string, std::unique_ptr<DirSE>> dirse;
     std::unordered_map<std::string, std::unique_ptr<Exec>> execs;
+    // repeat-call fast path: the previous batch call's job array, the bytes
+    // of its SE arrays, the options it ran with and its executor
+    std::vector<md_job> last_jobs;
+    std::string last_se;
+    Options last_opt;
+    Exec *last_exec = nullptr;
     DevBuf se_work, se_in;
     DevBuf morph_a, morph_b;      // intermediates of md_morph
     DevBuf vjob, vseg, vslabs, vy;  // volume path: job, segments, slab table, transform buffer
@@ -1380,7 +1386,7 @@ int autotune() {
     g.opt = saved;
     g.prof = saved_prof;
     g.last = saved_stats;
-    g.execs.clear();
+    g.execs.clear(), g.last_exec = nullptr;
     g.tuning = false;
     g.tuned = rc == MD_OK;
     g.cost_measured = rc == MD_OK;
@@ -1388,27 +1394,79 @@ int autotune() {
     return rc;
 }
 
+// Bytes of a batch's SE arrays as the caller passed them (masks, then
+// offsets, job by job): the repeat-call fast path compares them with the
+// previous call's.
+std::string se_bytes(const md_job *jobs, int n) {
+    size_t total = 0;
+    for (int i = 0; i < n; ++i) total += (size_t)jobs[i].k * jobs[i].k * (1 + sizeof(int32_t));
+    std::string b;
+    b.reserve(total);
+    for (int i = 0; i < n; ++i) {
+        const size_t kk = (size_t)jobs[i].k * jobs[i].k;
+        b.append((const char *)jobs[i].se_mask, kk);
+        b.append((const char *)jobs[i].se_offsets, kk * sizeof(int32_t));
+    }
+    return b;
+}
+
+bool same_options(const Options &a, const Options &b) {
+    return a.precision == b.precision && a.band == b.band && a.path == b.path && a.tile == b.tile && a.nr == b.nr &&
+           a.ws_mb == b.ws_mb;
+}
+
+bool same_se_bytes(const md_job *jobs, int n, const std::string &prev) {
+    size_t off = 0;
+    for (int i = 0; i < n; ++i) {
+        const size_t kk = (size_t)jobs[i].k * jobs[i].k;
+        if (off + kk * (1 + sizeof(int32_t)) > prev.size()) return false;
+        if (memcmp(prev.data() + off, jobs[i].se_mask, kk) != 0) return false;
+        off += kk;
+        if (memcmp(prev.data() + off, jobs[i].se_offsets, kk * sizeof(int32_t)) != 0) return false;
+        off += kk * sizeof(int32_t);
+    }
+    return off == prev.size();
+}
+
 int run(const md_job *jobs, int n, bool use_graph) {
     MD_TRY(init());
     if (g.opt.path == 0 && g.opt.autotune && !g.tuned && !g.tuning) MD_TRY(autotune());
     if (n < 1 || !jobs) return fail(MD_ERR_ARG, "empty batch");
-    std::vector<SEData> ses(n);
-    for (int i = 0; i < n; ++i) {
-        MD_TRY(check_job(jobs[i]));
-        make_se(jobs[i].se_mask, jobs[i].se_offsets, jobs[i].k, jobs[i].op, ses[i]);
-    }
-    const std::string sig = signature(jobs, n, ses);
-    auto it = g.execs.find(sig);
+    // A call identical to the previous one (job array, SE contents, options)
+    // runs its executor again without re-validating, re-planning or hashing
+    // the batch signature; everything was checked when that executor was
+    // built and the inputs have not changed since.
     Exec *ex = nullptr;
-    if (it == g.execs.end()) {
+    if (g.last_exec && (int)g.last_jobs.size() == n && same_options(g.opt, g.last_opt) &&
+        memcmp(g.last_jobs.data(), jobs, sizeof(md_job) * n) == 0 && same_se_bytes(jobs, n, g.last_se))
+        ex = g.last_exec;
+    const bool repeat = ex != nullptr;
+    std::vector<SEData> ses;
+    if (!ex) {
+        ses.resize(n);
+        for (int i = 0; i < n; ++i) {
+            MD_TRY(check_job(jobs[i]));
+            make_se(jobs[i].se_mask, jobs[i].se_offsets, jobs[i].k, jobs[i].op, ses[i]);
+        }
+    }
+    const std::string sig = ex ? std::string() : signature(jobs, n, ses);
+    auto it = ex ? g.execs.end() : g.execs.find(sig);
+    if (ex) {
+    } else if (it == g.execs.end()) {
         auto e = std::make_unique<Exec>();
         const int rc = build_exec(jobs, n, ses, *e);
         if (rc != MD_OK) return rc;
         ex = e.get();
-        if (g.execs.size() > 64) g.execs.clear();
+        if (g.execs.size() > 64) g.execs.clear(), g.last_exec = nullptr;
         g.execs[sig] = std::move(e);
     } else {
         ex = it->second.get();
+    }
+    if (!repeat) {
+        g.last_jobs.assign(jobs, jobs + n);
+        g.last_se = se_bytes(jobs, n);
+        g.last_opt = g.opt;
+        g.last_exec = ex;
     }
     // refresh image / output pointers in the device job table if they moved
     bool changed = false;
@@ -2156,7 +2214,7 @@ int md_cost_model(double *dst, int n, int *measured) {
 int md_release(void) {
     if (!g.inited) return MD_OK;
     (void)hipDeviceSynchronize();
-    g.execs.clear();
+    g.execs.clear(), g.last_exec = nullptr;
     g.spectra.clear();
     g.dirse.clear();
     g.ranges.clear();
