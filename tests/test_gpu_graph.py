@@ -62,3 +62,50 @@ def test_graph_replays(dev, mode):
                 want = oracle.run_job(j)
                 got = o.cpu().numpy()
                 assert np.array_equal(got, want), f"{mode} replay {rep} job {q} ({j.name}): {int((got != want).sum())} differ"
+
+
+def test_repeat_calls_see_in_place_changes(dev):
+    """The library reuses the previous call's executor only when the job
+    array, the SE bytes and the planning options are all unchanged: an SE
+    array edited in place, an offset changed under a masked cell, new image
+    contents and a changed precision must each give the new exact result."""
+    import torch
+
+    rng = np.random.default_rng(72)
+    jobs = batch_jobs(rng)
+    imgs = [torch.from_numpy(j.img).to(dev) for j in jobs]
+    batch = md.Batch([(im, j.mask, j.off, j.L, j.op) for im, j in zip(imgs, jobs)])
+
+    def check(tag):
+        outs = batch.run()
+        torch.cuda.synchronize()
+        for q, (j, o) in enumerate(zip(jobs, outs)):
+            want = oracle.run_job(j)
+            got = o.cpu().numpy()
+            assert np.array_equal(got, want), f"{tag}: job {q} ({j.name}) {int((got != want).sum())} differ"
+
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        check("first call")
+        check("identical repeat")
+        # the Batch holds the same numpy arrays the jobs hold: edit in place
+        j = jobs[1]
+        j.off[j.mask != 0] = (j.off[j.mask != 0] + 1) % (j.L // 4 + 1)
+        check("offsets edited in place")
+        j = jobs[3]
+        cells = np.argwhere(j.mask == 0)
+        if len(cells):
+            j.off[tuple(cells[0])] = 7          # under a masked cell: no effect on the result
+            check("offset under a masked cell")
+        j = jobs[0]
+        j.mask[:] = 0
+        j.mask[j.k // 2, 0] = 1
+        j.off[:] = 0
+        check("mask edited in place")
+        for j, im in zip(jobs, imgs):
+            j.img = rng.integers(0, j.L, j.img.shape).astype(np.int32)
+            im.copy_(torch.from_numpy(j.img))
+        check("new image contents")
+        with md.options(precision=1):
+            check("precision changed")
+        check("precision restored")
