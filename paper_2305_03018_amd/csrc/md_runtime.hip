@@ -226,6 +226,10 @@ struct Ctx {
     DevBuf morph_a, morph_b;      // intermediates of md_morph
     DevBuf vjob, vseg, vslabs, vy;  // volume path: job, segments, slab table, transform buffer
     std::string vtab;               // host image of what vjob / vseg / vslabs hold
+    // side stream of a batch: the direct-window launches run on it beside the
+    // transform path's launches (fork / join events on the library stream)
+    hipStream_t s_side = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     // host-streamed images: upload / download streams, two band buffers per
     // direction, their events, and an accumulated range-error flag
     hipStream_t s_up = nullptr, s_down = nullptr;
@@ -318,6 +322,9 @@ int init() {
         MD_HIP(hipMemcpy(g.ntws, ws.data(), sizeof(uint32_t) * kNttTw, hipMemcpyHostToDevice));
     }
     MD_HIP(launch_zero(g.st_d, sizeof(StatsDev), nullptr));
+    MD_HIP(hipStreamCreateWithFlags(&g.s_side, hipStreamNonBlocking));
+    MD_HIP(hipEventCreateWithFlags(&g.ev_fork, hipEventDisableTiming));
+    MD_HIP(hipEventCreateWithFlags(&g.ev_join, hipEventDisableTiming));
     MD_HIP(hipDeviceSynchronize());
     g.device = dev;
     g.inited = true;
@@ -1165,13 +1172,30 @@ int enqueue(Exec &ex, hipStream_t s, bool skip_decode = false, bool capturing = 
     const bool prof = g.opt.profile && !capturing;
     MD_HIP(launch_zero(g.st_d, sizeof(StatsDev), s));
     if (ex.nflags > 0) MD_HIP(launch_zero(ex.flags.p, ex.nflags * sizeof(unsigned int), s));
+    // With both paths in the batch, the direct-window launches go to a side
+    // stream, so the transform path's launches take the CUs that the direct
+    // grid's last blocks leave idle; the library stream joins the side stream
+    // before the recompute.  Profiled calls keep one stream, so that each
+    // stage's event time is its own.
+    bool any_direct = false, any_fft = false;
+    for (auto &gr : ex.direct) any_direct |= gr.nitems > 0;
+    for (auto &wv : ex.waves)
+        for (auto &gr : wv.fft) any_fft |= gr.nitems > 0;
+    const bool fork = any_direct && any_fft && !skip_decode && !prof;
+    hipStream_t sd = s;
+    if (fork) {
+        MD_HIP(hipEventRecord(g.ev_fork, s));
+        MD_HIP(hipStreamWaitEvent(g.s_side, g.ev_fork, 0));
+        sd = g.s_side;
+    }
     for (auto &gr : ex.direct) {
         if (gr.nitems <= 0) continue;
-        ProfScope ps(prof, s, gr.pack ? "direct16" : "direct32", gr.alg_bytes, gr.alg_ops, gr.units);
+        ProfScope ps(prof, sd, gr.pack ? "direct16" : "direct32", gr.alg_bytes, gr.alg_ops, gr.units);
         MD_HIP(launch_direct(gr.pack, gr.sel, ex.jobs_d, gr.segs_d, (int)gr.segs.size(), gr.nitems, gr.grid, gr.lds,
-                             g.st_d, s));
+                             g.st_d, sd));
         ps.done();
     }
+    if (fork) MD_HIP(hipEventRecord(g.ev_join, sd));
     const float band = (float)g.opt.band;
     for (auto &wv : ex.waves) {
         for (auto &gr : wv.fft) {
@@ -1202,6 +1226,7 @@ int enqueue(Exec &ex, hipStream_t s, bool skip_decode = false, bool capturing = 
             ps.done();
         }
     }
+    if (fork) MD_HIP(hipStreamWaitEvent(s, g.ev_join, 0));
     if (skip_decode) return MD_OK;
     for (int nt64 : ex.fb_classes) {
         ProfScope ps(prof, s, "recompute64_n" + std::to_string(nt64), 0, 0, 0);
@@ -2234,6 +2259,11 @@ int md_release(void) {
             if (*e) (void)hipEventDestroy(*e), *e = nullptr;
     }
     g.hs_flag.release();
+    if (g.ev_fork) (void)hipEventDestroy(g.ev_fork);
+    if (g.ev_join) (void)hipEventDestroy(g.ev_join);
+    if (g.s_side) (void)hipStreamDestroy(g.s_side);
+    g.ev_fork = g.ev_join = nullptr;
+    g.s_side = nullptr;
     if (g.s_up) (void)hipStreamDestroy(g.s_up);
     if (g.s_down) (void)hipStreamDestroy(g.s_down);
     g.s_up = g.s_down = nullptr;
