@@ -1264,9 +1264,10 @@ int run(const md_job *jobs, int n, bool use_graph);
 // Autotuner: time each kernel family on calibration images on this device
 // and replace the cost model's built-in estimates with the measured rates.
 int autotune_body() {
-    // calibration images: 1024^2 for the direct window and the LDS-resident
-    // lengths, 2048^2 for 256 (FP32) / 128-256 (FP64), 4096^2 for 512 and 1024
-    // (enough (tile, bin) items to load the whole GPU); grey values in [0, 16)
+    // calibration images: 1024^2 for the LDS-resident lengths, 2048^2 for 256
+    // (FP32) / 128-256 (FP64), 4096^2 for 512 and 1024 and for the direct
+    // window (enough (tile, bin) items or blocks to load the whole GPU); grey
+    // values in [0, 16)
     const int HS = 4096;
     DevBuf img, out;
     MD_TRY(img.ensure((size_t)HS * HS * 4));
@@ -1299,9 +1300,11 @@ int autotune_body() {
         return MD_OK;
     };
     // direct window: staging and per-cell costs from a small and a large SE
-    // (16-bit packed form), then the 32-bit per-cell cost (L = 32768)
+    // (16-bit packed form), then the 32-bit per-cell cost (L = 32768), on the
+    // 4096^2 image: 2048 blocks, so the GPU is as full as in a large batch
+    // (a smaller image leaves CUs idle and inflates the per-pixel costs)
     {
-        const int side = 1024;
+        const int side = HS;
         const double px = (double)side * side;
         SEData s3, s41, s15;
         double t3 = 0, t41 = 0, t15 = 0;
