@@ -43,7 +43,9 @@ INT16X2_ALU_TOPS = 2 * INT32_ALU_TOPS                       # packed 16-bit: two
 
 # the forced-path comparison legs on the batch
 LEG_OPTS = {"fft64": dict(precision=1, path=1), "fft32": dict(precision=0, path=1),
-            "ntt": dict(precision=2, path=1), "direct": dict(precision=0, path=2)}
+            "ntt": dict(precision=2, path=1), "direct": dict(precision=0, path=2),
+            # band 0: every tile of the FP32 path is recomputed exactly in FP64
+            "fft32_recompute_all": dict(precision=0, path=1, band=0.0)}
 
 
 def log(msg):
@@ -142,9 +144,11 @@ def measured_traffic(kernel, workload):
                      float(rec["write_kib"]) * float(rec["write_scale"]))
 
 
-def roofline_for(stage, prof, workload):
+def roofline_for(stage, prof, workload, launch_ms=None):
+    """Roofline figures of one profiled stage; `launch_ms` (if given) replaces
+    the profiled calls' mean launch time."""
     rec = prof[stage]
-    per_launch_ms = rec["ms"] / rec["launches"]
+    per_launch_ms = rec["ms"] / rec["launches"] if launch_ms is None else launch_ms
     ops = rec["alg_ops"] / rec["launches"]
     achieved = ops / (per_launch_ms * 1e-3) / 1e12
     kernel = kernel_of(stage)
@@ -307,7 +311,7 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=12.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-compare", action="store_true")
-    ap.add_argument("--leg", choices=["fft64", "fft32", "ntt", "direct"],
+    ap.add_argument("--leg", choices=["fft64", "fft32", "ntt", "direct", "fft32_recompute_all"],
                     help="run only this forced path on the batch (warm-up, --steps timed steps, one profiled "
                          "step) and print its own JSON line; for hardware-counter runs of its kernels")
     ap.add_argument("--copy-probe", action="store_true",
@@ -402,6 +406,17 @@ def main():
                 cmp[name]["stages"] = {
                     st: {k: v for k, v in roofline_for(st, sp, args.workload).items() if k != "traffic"}
                     for st in sp if sp[st]["alg_ops"] > 0}
+                rec = {st: v for st, v in sp.items() if st.startswith("recompute")}
+                if rec and name == "fft32_recompute_all":
+                    # the recompute's work is known only on the device (its tile
+                    # list): time per recomputed tile
+                    with md.options(sync=1, graph=0, **opts):
+                        md.dilate_batch(arglist, outs=outs)
+                        tiles = md.get_stats()["fallback_tiles"]
+                    ms_rec = sum(v["ms"] for v in rec.values()) / 2
+                    cmp[name]["recompute"] = {"tiles": tiles, "ms_per_step": ms_rec,
+                                              "us_per_tile": ms_rec * 1e3 / max(1, tiles),
+                                              "stages_ms_per_step": {st: v["ms"] / 2 for st, v in rec.items()}}
                 log(f"bench: {name} {m:.3f} ms/step")
             cmp["volume"] = volume_leg(md, torch, dev, stream, max(3, args.steps // 4))
             cmp["host_stream"] = host_stream_leg(md, torch, dev, 3)
@@ -414,7 +429,14 @@ def main():
         md.profile_reset()
         log(f"bench: profile {json.dumps(prof)}")
     dominant = max(prof, key=lambda k: prof[k]["ms"])
-    roof = roofline_for(dominant, prof, args.workload)
+    # the dominant kernel's launch time in the timed region: the HIP-event
+    # step time there times the stage's share of the profiled step (the
+    # profiled calls run synchronised, one at a time, outside that region)
+    share = prof[dominant]["ms"] / sum(v["ms"] for v in prof.values())
+    timed_launch_ms = res["headline_ms"] * share
+    roof = roofline_for(dominant, prof, args.workload, launch_ms=timed_launch_ms)
+    roof["share_of_step"] = share
+    roof["profiled_launch_ms"] = prof[dominant]["ms"] / prof[dominant]["launches"]
     value = total_px / (res["headline_ms"] * 1e-3) / 1e6
     line = {
         "metric": "exact dilated Mpixels/s, batched FP32+fallback vs FP64 FFT path, 1 MI355X",
