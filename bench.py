@@ -9,7 +9,9 @@ tiles, HIP-graph replay).  Inputs are resident in HBM before timing starts.
 
 Also measured on the same batch: the plain FP64 FFT path (every job forced
 through FP64 transforms), the FP32 FFT path forced for every job, the exact
-mod-p transform path, and the direct window for every job; the volume
+mod-p transform path, and the direct window for every job; a 2048^2 image
+with 4 grey levels and a 127 x 127 disk, where the transform path beats the
+window; the volume
 path (three image axes) on a 128 x 256 x 256 volume; and a 16384^2 image in
 pinned host memory streamed through the GPU in bands (PCIe included; a
 context figure, never the headline value).  A profiled pass (HIP events around every
@@ -262,6 +264,47 @@ def host_stream_leg(md, torch, dev, steps):
     return res
 
 
+def large_se_leg(md, torch, dev, stream, steps):
+    """The transform path's niche: a 2048 x 2048 image with L = 4 grey levels
+    (uniform) and a 127 x 127 disk SE (offsets in [0, 1]), where the
+    transform's work per pixel, independent of the SE's 12 649 cells, is below
+    the window's.  Auto, the direct window and the FP32 transform path, each
+    over `steps` calls; sampled pixels checked against the oracle."""
+    import oracle
+    from paper_2305_03018_amd import synthetic
+
+    rng = np.random.default_rng(13)
+    side, L, k = 2048, 4, 127
+    img_np = rng.integers(0, L, (side, side)).astype(np.int32)
+    mask = synthetic.disk_mask(k)
+    off = (rng.integers(0, 2, (k, k)) * mask).astype(np.int32)
+    img = torch.from_numpy(img_np).to(dev)
+    out = torch.empty_like(img)
+    ys, xs = rng.integers(0, side, 1024), rng.integers(0, side, 1024)
+    want = oracle.at(img_np, mask, off, L, 0, ys, xs)
+    res = {"workload": f"uniform_{side}x{side}_L{L}_disk{k}"}
+    for name, opts in (("auto", {}), ("direct", dict(path=2)), ("fft32", dict(precision=0, path=1))):
+        batch = md.Batch([(img, mask, off, L, 0)], [out])
+        with md.options(**opts):
+            batch.run()
+            st = md.get_stats()
+            with md.options(sync=0):
+                t0 = torch.cuda.Event(enable_timing=True)
+                t1 = torch.cuda.Event(enable_timing=True)
+                t0.record(stream)
+                for _ in range(steps):
+                    batch.run()
+                t1.record(stream)
+                torch.cuda.synchronize()
+        if not np.array_equal(out.cpu().numpy()[ys, xs], want):
+            raise SystemExit(f"bench: large-SE parity failure ({name})")
+        ms = t0.elapsed_time(t1) / steps
+        res[name] = {"ms": ms, "mpx_s": side * side / (ms * 1e-3) / 1e6,
+                     "path": "direct" if st["path"] == 2 else "fft", "n_t": st["n_t"], "n_r": st["n_r"]}
+        log(f"bench: large SE {name} {ms:.3f} ms ({res[name]['path']})")
+    return res
+
+
 def spectrum_error(md, torch, dev):
     """Transform-domain values of one tile of the 512 x 512 blurred image
     (15 x 15 disk, n_t = 128, n_r = 24) just before the inverse range
@@ -419,6 +462,7 @@ def main():
                                               "stages_ms_per_step": {st: v["ms"] / 2 for st, v in rec.items()}}
                 log(f"bench: {name} {m:.3f} ms/step")
             cmp["volume"] = volume_leg(md, torch, dev, stream, max(3, args.steps // 4))
+            cmp["large_se"] = large_se_leg(md, torch, dev, stream, 3)
             cmp["host_stream"] = host_stream_leg(md, torch, dev, 3)
         # profiled pass for the roofline (events around every launch, no graph)
         md.profile_reset()
