@@ -98,9 +98,9 @@ typedef enum {
     MD_OPT_AUTOTUNE = 9,   /* 1 (default): the first auto-path call on a device
                               measures the kernels' rates and feeds them to the
                               cost model; 0 keeps the built-in estimates         */
-    MD_OPT_STREAM_ROWS = 10,/* md_dilate_host / md_erode_host: 0 (default) picks
-                              the band height from MD_OPT_STREAM_MB, else the
-                              output rows per band                               */
+    MD_OPT_STREAM_ROWS = 10,/* host-streamed calls: 0 (default) picks the band
+                              height from MD_OPT_STREAM_MB, else the output
+                              rows (volumes: slices) per band                    */
     MD_OPT_STREAM_MB = 11  /* device memory for the band buffers of the host-
                               streamed calls, MiB (default 2048)                 */
 } md_option;
@@ -204,6 +204,19 @@ int md_dilate3(const int32_t *vol, int D, int H, int W, int L, const uint8_t *se
                const int32_t *se_offsets, int k, int32_t *out);
 int md_erode3(const int32_t *vol, int D, int H, int W, int L, const uint8_t *se_mask,
               const int32_t *se_offsets, int k, int32_t *out);
+
+/* Volumes in HOST memory, streamed through the GPU in bands of output
+ * slices with r = (k-1)/2 halo slices on each side, each band computed by
+ * md_dilate3 / md_erode3 as a volume of its own (the partitioned convolution
+ * of md_dilate_host along z).  `vol` / `out`: D x H x W int32 host arrays (D
+ * may exceed 2^31 / (H W); a band holds at most 2^31-1 voxels).  Band height:
+ * MD_OPT_STREAM_ROWS slices if set, else the most that four band buffers fit
+ * into MD_OPT_STREAM_MB.  SE arrays, L, k, options and errors as for
+ * md_dilate3; the call returns when `out` is complete. */
+int md_dilate3_host(const int32_t *vol, long long D, int H, int W, int L, const uint8_t *se_mask,
+                    const int32_t *se_offsets, int k, int32_t *out);
+int md_erode3_host(const int32_t *vol, long long D, int H, int W, int L, const uint8_t *se_mask,
+                   const int32_t *se_offsets, int k, int32_t *out);
 
 /* One job of a batch.  Pointer and ownership rules as for md_dilate. */
 typedef struct {

@@ -32,10 +32,12 @@ from ._binding import (  # noqa: F401
     debug_tile_values,
     dilate,
     dilate3,
+    dilate3_host,
     dilate_batch,
     dilate_host,
     erode,
     erode3,
+    erode3_host,
     erode_host,
     exported_symbols,
     get_option,

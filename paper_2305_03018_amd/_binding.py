@@ -69,6 +69,10 @@ def load():
         f = getattr(lib, name)
         f.argtypes = [vp, ctypes.c_longlong, i, i, u8, vp, i, vp]
         f.restype = i
+    for name in ("md_dilate3_host", "md_erode3_host"):
+        f = getattr(lib, name)
+        f.argtypes = [vp, ctypes.c_longlong, i, i, i, u8, vp, i, vp]
+        f.restype = i
     for name in ("md_dilate3", "md_erode3"):
         f = getattr(lib, name)
         f.argtypes = [vp, i, i, i, i, u8, vp, i, vp]
@@ -213,6 +217,49 @@ def dilate_host(img, mask, off, L: int, out=None):
 def erode_host(img, mask, off, L: int, out=None):
     """Exact erosion of an image in host memory (md_erode_host)."""
     return _run_host("md_erode_host", img, mask, off, L, out)
+
+
+def _run_volume_host(fname, vol, mask, off, L, out):
+    """vol / out: C-contiguous int32 numpy arrays or CPU torch tensors of
+    shape (D, H, W)."""
+    import torch
+
+    lib = load()
+
+    def ptr_of(a, what):
+        if isinstance(a, torch.Tensor):
+            if a.is_cuda or a.dtype != torch.int32 or a.dim() != 3 or not a.is_contiguous():
+                raise TypeError(f"{what} must be a contiguous 3-D int32 host tensor")
+            return a.data_ptr(), tuple(a.shape)
+        if not isinstance(a, np.ndarray) or a.dtype != np.int32 or a.ndim != 3 or not a.flags.c_contiguous:
+            raise TypeError(f"{what} must be a C-contiguous 3-D int32 numpy array")
+        return a.ctypes.data, a.shape
+
+    vp_, shape = ptr_of(vol, "volume")
+    if out is None:
+        out = np.empty(shape, np.int32)
+    op_, oshape = ptr_of(out, "out")
+    if oshape != shape:
+        raise ValueError("out must have the volume's shape")
+    mask = np.ascontiguousarray(np.asarray(mask), dtype=np.uint8)
+    off = np.ascontiguousarray(np.asarray(off), dtype=np.int32)
+    if mask.ndim != 3 or mask.shape != off.shape or len(set(mask.shape)) != 1:
+        raise ValueError("mask and offsets must be k x k x k arrays of the same shape")
+    rc = getattr(lib, fname)(vp_, shape[0], shape[1], shape[2], int(L), mask.ctypes.data, off.ctypes.data,
+                             mask.shape[0], op_)
+    _check(rc)
+    return out
+
+
+def dilate3_host(vol, mask, off, L: int, out=None):
+    """Exact volume dilation of a volume in host memory, streamed through the
+    GPU in bands of slices (md_dilate3_host)."""
+    return _run_volume_host("md_dilate3_host", vol, mask, off, L, out)
+
+
+def erode3_host(vol, mask, off, L: int, out=None):
+    """Exact volume erosion from host memory (md_erode3_host)."""
+    return _run_volume_host("md_erode3_host", vol, mask, off, L, out)
 
 
 def _run_volume(fname, vol, mask, off, L, out):

@@ -1183,10 +1183,27 @@ int enqueue(Exec &ex, hipStream_t s, bool skip_decode = false, bool capturing = 
         for (auto &gr : wv.fft) any_fft |= gr.nitems > 0;
     const bool fork = any_direct && any_fft && !skip_decode && !prof;
     hipStream_t sd = s;
+    // joins the side stream back into the library stream exactly once, also
+    // on an early error return (a capture with an unjoined stream is invalid)
+    struct Join {
+        bool pending = false;
+        hipStream_t side = nullptr, main = nullptr;
+        hipError_t run() {
+            if (!pending) return hipSuccess;
+            pending = false;
+            hipError_t e = hipEventRecord(g.ev_join, side);
+            if (e == hipSuccess) e = hipStreamWaitEvent(main, g.ev_join, 0);
+            return e;
+        }
+        ~Join() { (void)run(); }
+    } join;
     if (fork) {
         MD_HIP(hipEventRecord(g.ev_fork, s));
         MD_HIP(hipStreamWaitEvent(g.s_side, g.ev_fork, 0));
         sd = g.s_side;
+        join.pending = true;
+        join.side = sd;
+        join.main = s;
     }
     for (auto &gr : ex.direct) {
         if (gr.nitems <= 0) continue;
@@ -1195,7 +1212,6 @@ int enqueue(Exec &ex, hipStream_t s, bool skip_decode = false, bool capturing = 
                              g.st_d, sd));
         ps.done();
     }
-    if (fork) MD_HIP(hipEventRecord(g.ev_join, sd));
     const float band = (float)g.opt.band;
     for (auto &wv : ex.waves) {
         for (auto &gr : wv.fft) {
@@ -1226,7 +1242,7 @@ int enqueue(Exec &ex, hipStream_t s, bool skip_decode = false, bool capturing = 
             ps.done();
         }
     }
-    if (fork) MD_HIP(hipStreamWaitEvent(s, g.ev_join, 0));
+    MD_HIP(join.run());
     if (skip_decode) return MD_OK;
     for (int nt64 : ex.fb_classes) {
         ProfScope ps(prof, s, "recompute64_n" + std::to_string(nt64), 0, 0, 0);
@@ -1613,6 +1629,17 @@ int morph(int op, const int32_t *img, int H, int W, int L, const uint8_t *mask, 
 // ---------------------------------------------------------------------------
 // host-streamed images (partitioned convolution over bands of rows)
 // ---------------------------------------------------------------------------
+constexpr int kVolMaxK = 31;   // volume SE side
+
+// Bands of H "rows" of `W` words each (image rows, or volume slices of
+// H x W voxels), r = (k-1)/2 halo rows on each side; `compute(din, rows,
+// dout)` enqueues one band's dilation / erosion on the library stream.
+template <typename F>
+int stream_bands(const int32_t *img, long long H, size_t W, int k, int32_t *out, F &&compute);
+
+int vol_run(int op, const int32_t *vol, int D, int H, int W, int L, const uint8_t *mask, const int32_t *off, int k,
+            int32_t *out);
+
 int stream_run(int op, const int32_t *img, long long H, int W, int L, const uint8_t *mask, const int32_t *off, int k,
                int32_t *out) {
     MD_TRY(init());
@@ -1620,6 +1647,26 @@ int stream_run(int op, const int32_t *img, long long H, int W, int L, const uint
     if (!mask || !off) return fail(MD_ERR_ARG, "null SE array");
     if (H < 1 || W < 1) return fail(MD_ERR_ARG, "image shape %lldx%d", H, W);
     if (k < 1 || k > kMaxN - 1 || (k % 2) == 0) return fail(MD_ERR_ARG, "k=%d must be odd in [1,%d]", k, kMaxN - 1);
+    return stream_bands(img, H, (size_t)W, k, out, [&](const int32_t *din, long long rows, int32_t *dout) {
+        return single(op, din, (int)rows, W, L, mask, off, k, dout);
+    });
+}
+
+// The same over bands of volume slices.
+int stream_run3(int op, const int32_t *vol, long long D, int H, int W, int L, const uint8_t *mask, const int32_t *off,
+                int k, int32_t *out) {
+    MD_TRY(init());
+    if (!vol || !out) return fail(MD_ERR_ARG, "null volume or output pointer");
+    if (!mask || !off) return fail(MD_ERR_ARG, "null SE array");
+    if (D < 1 || H < 1 || W < 1) return fail(MD_ERR_ARG, "volume shape %lldx%dx%d", D, H, W);
+    if (k < 1 || k > kVolMaxK || (k % 2) == 0) return fail(MD_ERR_ARG, "k=%d must be odd in [1,%d]", k, kVolMaxK);
+    return stream_bands(vol, D, (size_t)H * W, k, out, [&](const int32_t *din, long long slices, int32_t *dout) {
+        return vol_run(op, din, (int)slices, H, W, L, mask, off, k, dout);
+    });
+}
+
+template <typename F>
+int stream_bands(const int32_t *img, long long H, size_t W, int k, int32_t *out, F &&compute) {
     const size_t bytes_all = (size_t)H * W * sizeof(int32_t);
     if ((const char *)img < (const char *)out + bytes_all && (const char *)out < (const char *)img + bytes_all)
         return fail(MD_ERR_ARG, "output must not overlap the input");
@@ -1632,8 +1679,9 @@ int stream_run(int op, const int32_t *img, long long H, int W, int L, const uint
         const double budget = g.opt.stream_mb * 1024.0 * 1024.0;
         R = (long long)(budget / (4.0 * sizeof(int32_t) * W)) - 2 * r;
     }
-    R = std::min<long long>(R, 0x7fffffffLL / W - 2 * r);
-    if (R < 1) return fail(MD_ERR_ARG, "a band of %d columns with %d halo rows does not fit (MD_OPT_STREAM_MB)", W, 2 * r);
+    R = std::min<long long>(R, (long long)(0x7fffffffLL / W) - 2 * r);
+    if (R < 1)
+        return fail(MD_ERR_ARG, "a band of %zu words per row with %d halo rows does not fit (MD_OPT_STREAM_MB)", W, 2 * r);
     R = std::min<long long>(R, H);
     const long long nb = (H + R - 1) / R;
     const size_t band_bytes = (size_t)(std::min<long long>(H, R + 2 * r)) * W * sizeof(int32_t);
@@ -1696,7 +1744,7 @@ int stream_run(int op, const int32_t *img, long long H, int W, int L, const uint
             rc = fail(MD_ERR_DEVICE, "band upload failed");
             break;
         }
-        rc = single(op, din, (int)(a1 - a0), W, L, mask, off, k, dout);
+        rc = compute(din, a1 - a0, dout);
         if (rc != MD_OK) break;
         if (launch_or_flag((uint32_t *)g.hs_flag.p, &g.st_d->range_err, g.stream) != hipSuccess ||
             hipEventRecord(g.ev_comp[i], g.stream) != hipSuccess) {
@@ -1730,8 +1778,6 @@ int stream_run(int op, const int32_t *img, long long H, int W, int L, const uint
 // ---------------------------------------------------------------------------
 // volumes (three image axes, Sec. 2.1 / Sec. 3 with N = 3)
 // ---------------------------------------------------------------------------
-constexpr int kVolMaxK = 31;
-
 // Effective volume SE: the SE for dilation, its reflection through the
 // centre for erosion (duality, Sec. 2.1); k^3 cells, (a, i, j) row-major.
 struct VolSE {
@@ -2096,6 +2142,16 @@ int md_dilate_host(const int32_t *img, long long H, int W, int L, const uint8_t 
 int md_erode_host(const int32_t *img, long long H, int W, int L, const uint8_t *se_mask, const int32_t *se_offsets,
                   int k, int32_t *out) {
     return stream_run(1, img, H, W, L, se_mask, se_offsets, k, out);
+}
+
+int md_dilate3_host(const int32_t *vol, long long D, int H, int W, int L, const uint8_t *se_mask,
+                    const int32_t *se_offsets, int k, int32_t *out) {
+    return stream_run3(0, vol, D, H, W, L, se_mask, se_offsets, k, out);
+}
+
+int md_erode3_host(const int32_t *vol, long long D, int H, int W, int L, const uint8_t *se_mask,
+                   const int32_t *se_offsets, int k, int32_t *out) {
+    return stream_run3(1, vol, D, H, W, L, se_mask, se_offsets, k, out);
 }
 
 int md_dilate3(const int32_t *vol, int D, int H, int W, int L, const uint8_t *se_mask, const int32_t *se_offsets,

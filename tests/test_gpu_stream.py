@@ -104,3 +104,31 @@ def test_range_error_and_arguments(dev):
     with md.options(stream_rows=30):
         got = md.dilate_host(job.img, job.mask, job.off, job.L)
     assert np.array_equal(got, oracle.dilate(job.img, job.mask, job.off))
+
+
+@pytest.mark.parametrize("case", [(23, 40, 50, 16, 5, 0.7, 3, 4), (17, 33, 70, 8, 7, 0.5, 2, 1), (9, 20, 30, 32, 3, 1.0, 8, 2)],
+                         ids=lambda c: "x".join(map(str, c)))
+def test_volume_bands(dev, case):
+    """md_dilate3_host / md_erode3_host: bands of slices with their halo,
+    on the direct window and on the exact transform path."""
+    D, H, W, L, k, p, max_off, slices = case
+    rng = np.random.default_rng(abs(hash(case)) % (2 ** 32))
+    job = synthetic.random_vol_job(rng, D, H, W, L, k, p=p, max_off=max_off)
+    for op in (0, 1):
+        want = oracle.dilate3(job.vol, job.mask, job.off) if op == 0 else oracle.erode3(job.vol, job.mask, job.off, L)
+        for name, opts in {"auto": {}, "direct": dict(path=2), "ntt16": dict(path=1, tile=16)}.items():
+            print(f"  case {case} op={op} {name}", flush=True)
+            with md.options(stream_rows=slices, **opts):
+                got = (md.dilate3_host if op == 0 else md.erode3_host)(job.vol, job.mask, job.off, L)
+            bad = got != want
+            assert not bad.any(), f"{case} op={op} {name}: {int(bad.sum())} differ"
+
+
+def test_volume_bands_range_error(dev):
+    rng = np.random.default_rng(65)
+    job = synthetic.random_vol_job(rng, 12, 10, 12, 16, 3, p=1.0, max_off=2)
+    bad = job.vol.copy()
+    bad[9, 5, 5] = 99
+    with md.options(stream_rows=2), pytest.raises(md.MDError) as e:
+        md.dilate3_host(bad, job.mask, job.off, job.L)
+    assert e.value.code == -2
