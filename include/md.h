@@ -205,6 +205,14 @@ int md_dilate3(const int32_t *vol, int D, int H, int W, int L, const uint8_t *se
 int md_erode3(const int32_t *vol, int D, int H, int W, int L, const uint8_t *se_mask,
               const int32_t *se_offsets, int k, int32_t *out);
 
+/* Compositions on volumes: md_morph's operations (MD_OPEN ... MD_BLACKHAT,
+ * with the same empty-window values) over three axes, each step by
+ * md_dilate3 / md_erode3.  Arguments, layout and errors as for md_dilate3;
+ * two D x H x W int32 device intermediates are owned by the library (freed
+ * by md_release). */
+int md_morph3(int op, const int32_t *vol, int D, int H, int W, int L, const uint8_t *se_mask,
+              const int32_t *se_offsets, int k, int32_t *out);
+
 /* Volumes in HOST memory, streamed through the GPU in bands of output
  * slices with r = (k-1)/2 halo slices on each side, each band computed by
  * md_dilate3 / md_erode3 as a volume of its own (the partitioned convolution

@@ -277,6 +277,29 @@ def at3(vol, mask, off, L: int, op: int, zs, ys, xs) -> np.ndarray:
     return out
 
 
+def opening3(vol, mask, off, L: int) -> np.ndarray:
+    """Volume opening: the erosion lies in [-m, L-1], so an empty dilation
+    window gives -m (as for images)."""
+    m = max_offset(mask, off)
+    return dilate3_e(erode3_e(vol, mask, off, L - 1), mask, off, -m)
+
+
+def closing3(vol, mask, off, L: int) -> np.ndarray:
+    m = max_offset(mask, off)
+    return erode3_e(dilate3_e(vol, mask, off, 0), mask, off, L - 1 + m)
+
+
+MORPH3 = {0: lambda f, m, o, L: dilate3(f, m, o), 1: erode3, 2: opening3, 3: closing3,
+          4: lambda f, m, o, L: dilate3(f, m, o) - erode3(f, m, o, L),
+          5: lambda f, m, o, L: np.asarray(f, np.int32) - opening3(f, m, o, L),
+          6: lambda f, m, o, L: closing3(f, m, o, L) - np.asarray(f, np.int32)}
+
+
+def morph3(op: int, vol, mask, off, L: int) -> np.ndarray:
+    """Volume operation `op`, numbered as for morph."""
+    return MORPH3[op](vol, mask, off, L)
+
+
 def run_job(job) -> np.ndarray:
     """Oracle result for a ``synthetic.Job``."""
     if job.op == 0:

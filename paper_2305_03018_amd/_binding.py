@@ -99,6 +99,8 @@ def load():
     lib.md_profile_reset.restype = i
     lib.md_morph.argtypes = [i, vp, i, i, i, u8, vp, i, vp]
     lib.md_morph.restype = i
+    lib.md_morph3.argtypes = [i, vp, i, i, i, i, u8, vp, i, vp]
+    lib.md_morph3.restype = i
     lib.md_cost_model.argtypes = [ctypes.POINTER(ctypes.c_double), i, ctypes.POINTER(ctypes.c_int)]
     lib.md_cost_model.restype = i
     _lib = lib
@@ -283,6 +285,29 @@ def _run_volume(fname, vol, mask, off, L, out):
         _bind_stream(vol.device)
         rc = getattr(lib, fname)(vol.data_ptr(), vol.shape[0], vol.shape[1], vol.shape[2], int(L),
                                  mask.ctypes.data, off.ctypes.data, mask.shape[0], out.data_ptr())
+    _check(rc)
+    return out
+
+
+def morph3(op: int, vol, mask, off, L: int, out=None):
+    """md_morph3: a volume composition (op as for morph: 0 dilation ... 6
+    black top-hat) over three axes."""
+    import torch
+
+    lib = load()
+    if not isinstance(vol, torch.Tensor) or not vol.is_cuda or vol.dtype != torch.int32 or vol.dim() != 3:
+        raise TypeError("volume must be a 3-D torch.int32 tensor on a HIP device")
+    vol = vol.contiguous()
+    mask = np.ascontiguousarray(np.asarray(mask), dtype=np.uint8)
+    off = np.ascontiguousarray(np.asarray(off), dtype=np.int32)
+    if mask.ndim != 3 or mask.shape != off.shape or len(set(mask.shape)) != 1:
+        raise ValueError("mask and offsets must be k x k x k arrays of the same shape")
+    if out is None:
+        out = torch.empty_like(vol)
+    with torch.cuda.device(vol.device):
+        _bind_stream(vol.device)
+        rc = lib.md_morph3(int(op), vol.data_ptr(), vol.shape[0], vol.shape[1], vol.shape[2], int(L),
+                           mask.ctypes.data, off.ctypes.data, mask.shape[0], out.data_ptr())
     _check(rc)
     return out
 

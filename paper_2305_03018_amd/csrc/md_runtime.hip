@@ -1569,25 +1569,56 @@ int single(int op, const int32_t *img, int H, int W, int L, const uint8_t *mask,
     return run(&j, 1, false);
 }
 
-// (f erosion b) dilation b into dst (tmp: H x W scratch): the erosion lies in
-// [-m, L-1]; shifted by m it is an image of range L+m, whose dilation (0 on
-// an empty window) shifted back gives -m there.
-int opening_into(const int32_t *img, int H, int W, int L, const uint8_t *mask, const int32_t *off, int k, int m,
-                 int32_t *tmp, int32_t *dst) {
-    const size_t n = (size_t)H * W;
-    MD_TRY(single(1, img, H, W, L, mask, off, k, tmp));
-    if (m) MD_HIP(launch_add_const(tmp, tmp, m, n, g.stream));
-    MD_TRY(single(0, tmp, H, W, L + m, mask, off, k, dst));
-    if (m) MD_HIP(launch_add_const(dst, dst, -m, n, g.stream));
+// Compositions of n-element images (or volumes): apply(o, src, Lr, dst)
+// enqueues the dilation (o = 0) or erosion (o = 1) of src, values in
+// [0, Lr-1], into dst.  m is the largest offset of an active SE cell.
+//   opening: the erosion lies in [-m, L-1]; shifted by m it is an image of
+//     range L+m, whose dilation (0 on an empty window) shifted back gives -m
+//     there;
+//   closing: the dilation lies in [0, L-1+m], an image of range L+m, whose
+//     erosion gives L-1+m on an empty window.
+template <typename A>
+int compose(int op, const int32_t *img, size_t n, int L, int m, int32_t *out, A &&apply) {
+    MD_TRY(g.morph_a.ensure(n * sizeof(int32_t)));
+    MD_TRY(g.morph_b.ensure(n * sizeof(int32_t)));
+    int32_t *a = (int32_t *)g.morph_a.p, *b = (int32_t *)g.morph_b.p;
+    auto opening_into = [&](int32_t *tmp, int32_t *dst) -> int {
+        MD_TRY(apply(1, img, L, tmp));
+        if (m) MD_HIP(launch_add_const(tmp, tmp, m, n, g.stream));
+        MD_TRY(apply(0, tmp, L + m, dst));
+        if (m) MD_HIP(launch_add_const(dst, dst, -m, n, g.stream));
+        return MD_OK;
+    };
+    auto closing_into = [&](int32_t *tmp, int32_t *dst) -> int {
+        MD_TRY(apply(0, img, L, tmp));
+        return apply(1, tmp, L + m, dst);
+    };
+    switch (op) {
+        case MD_OPEN: MD_TRY(opening_into(a, out)); break;
+        case MD_CLOSE: MD_TRY(closing_into(a, out)); break;
+        case MD_GRADIENT:
+            MD_TRY(apply(0, img, L, a));
+            MD_TRY(apply(1, img, L, b));
+            MD_HIP(launch_sub(out, a, b, n, g.stream));
+            break;
+        case MD_TOPHAT:
+            MD_TRY(opening_into(a, b));
+            MD_HIP(launch_sub(out, img, b, n, g.stream));
+            break;
+        default:   // MD_BLACKHAT
+            MD_TRY(closing_into(a, b));
+            MD_HIP(launch_sub(out, b, img, n, g.stream));
+            break;
+    }
+    if (g.opt.sync) MD_HIP(hipStreamSynchronize(g.stream));
     return MD_OK;
 }
 
-// (f dilation b) erosion b into dst: the dilation lies in [0, L-1+m], an image
-// of range L+m, whose erosion gives L-1+m on an empty window.
-int closing_into(const int32_t *img, int H, int W, int L, const uint8_t *mask, const int32_t *off, int k, int m,
-                 int32_t *tmp, int32_t *dst) {
-    MD_TRY(single(0, img, H, W, L, mask, off, k, tmp));
-    return single(1, tmp, H, W, L + m, mask, off, k, dst);
+int max_active_offset(const uint8_t *mask, const int32_t *off, size_t cells) {
+    int m = 0;
+    for (size_t q = 0; q < cells; ++q)
+        if (mask[q]) m = std::max(m, (int)off[q]);
+    return m;
 }
 
 int morph(int op, const int32_t *img, int H, int W, int L, const uint8_t *mask, const int32_t *off, int k,
@@ -1597,33 +1628,31 @@ int morph(int op, const int32_t *img, int H, int W, int L, const uint8_t *mask, 
     md_job j{img, H, W, L, mask, off, k, out, 0};
     MD_TRY(check_job(j));
     MD_TRY(init());
-    int m = 0;
-    for (int q = 0; q < k * k; ++q)
-        if (mask[q]) m = std::max(m, (int)off[q]);
+    const int m = max_active_offset(mask, off, (size_t)k * k);
     if ((long long)L + m > (1 << 24)) return fail(MD_ERR_RANGE, "L + max offset = %lld exceeds 2^24", (long long)L + m);
-    const size_t n = (size_t)H * W;
-    MD_TRY(g.morph_a.ensure(n * sizeof(int32_t)));
-    MD_TRY(g.morph_b.ensure(n * sizeof(int32_t)));
-    int32_t *a = (int32_t *)g.morph_a.p, *b = (int32_t *)g.morph_b.p;
-    switch (op) {
-        case MD_OPEN: return opening_into(img, H, W, L, mask, off, k, m, a, out);
-        case MD_CLOSE: return closing_into(img, H, W, L, mask, off, k, m, a, out);
-        case MD_GRADIENT:
-            MD_TRY(single(0, img, H, W, L, mask, off, k, a));
-            MD_TRY(single(1, img, H, W, L, mask, off, k, b));
-            MD_HIP(launch_sub(out, a, b, n, g.stream));
-            break;
-        case MD_TOPHAT:
-            MD_TRY(opening_into(img, H, W, L, mask, off, k, m, a, b));
-            MD_HIP(launch_sub(out, img, b, n, g.stream));
-            break;
-        default:   // MD_BLACKHAT
-            MD_TRY(closing_into(img, H, W, L, mask, off, k, m, a, b));
-            MD_HIP(launch_sub(out, b, img, n, g.stream));
-            break;
-    }
-    if (g.opt.sync) MD_HIP(hipStreamSynchronize(g.stream));
-    return MD_OK;
+    return compose(op, img, (size_t)H * W, L, m, out, [&](int o, const int32_t *src, int Lr, int32_t *dst) {
+        return single(o, src, H, W, Lr, mask, off, k, dst);
+    });
+}
+
+int vol_run(int op, const int32_t *vol, int D, int H, int W, int L, const uint8_t *mask, const int32_t *off, int k,
+            int32_t *out);
+
+int morph3(int op, const int32_t *vol, int D, int H, int W, int L, const uint8_t *mask, const int32_t *off, int k,
+           int32_t *out) {
+    if (op == MD_DILATE || op == MD_ERODE) return vol_run(op, vol, D, H, W, L, mask, off, k, out);
+    if (op < MD_OPEN || op > MD_BLACKHAT) return fail(MD_ERR_ARG, "unknown morphological operation %d", op);
+    if (!vol || !out || (const void *)vol == (const void *)out) return fail(MD_ERR_ARG, "null or aliased volume");
+    if (!mask || !off) return fail(MD_ERR_ARG, "null SE array");
+    if (D < 1 || H < 1 || W < 1 || (long long)D * H * W > 0x7fffffffLL)
+        return fail(MD_ERR_ARG, "volume shape %dx%dx%d", D, H, W);
+    if (k < 1 || k > 31 || (k % 2) == 0) return fail(MD_ERR_ARG, "k=%d must be odd in [1,31]", k);
+    MD_TRY(init());
+    const int m = max_active_offset(mask, off, (size_t)k * k * k);
+    if ((long long)L + m > (1 << 24)) return fail(MD_ERR_RANGE, "L + max offset = %lld exceeds 2^24", (long long)L + m);
+    return compose(op, vol, (size_t)D * H * W, L, m, out, [&](int o, const int32_t *src, int Lr, int32_t *dst) {
+        return vol_run(o, src, D, H, W, Lr, mask, off, k, dst);
+    });
 }
 
 // ---------------------------------------------------------------------------
@@ -1636,9 +1665,6 @@ constexpr int kVolMaxK = 31;   // volume SE side
 // dout)` enqueues one band's dilation / erosion on the library stream.
 template <typename F>
 int stream_bands(const int32_t *img, long long H, size_t W, int k, int32_t *out, F &&compute);
-
-int vol_run(int op, const int32_t *vol, int D, int H, int W, int L, const uint8_t *mask, const int32_t *off, int k,
-            int32_t *out);
 
 int stream_run(int op, const int32_t *img, long long H, int W, int L, const uint8_t *mask, const int32_t *off, int k,
                int32_t *out) {
@@ -2142,6 +2168,11 @@ int md_dilate_host(const int32_t *img, long long H, int W, int L, const uint8_t 
 int md_erode_host(const int32_t *img, long long H, int W, int L, const uint8_t *se_mask, const int32_t *se_offsets,
                   int k, int32_t *out) {
     return stream_run(1, img, H, W, L, se_mask, se_offsets, k, out);
+}
+
+int md_morph3(int op, const int32_t *vol, int D, int H, int W, int L, const uint8_t *se_mask,
+              const int32_t *se_offsets, int k, int32_t *out) {
+    return morph3(op, vol, D, H, W, L, se_mask, se_offsets, k, out);
 }
 
 int md_dilate3_host(const int32_t *vol, long long D, int H, int W, int L, const uint8_t *se_mask,

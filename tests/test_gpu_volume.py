@@ -162,3 +162,24 @@ def test_full_size_sampled(dev):
                 fn = md.dilate3 if op == 0 else md.erode3
                 got = fn(vol, job.mask, job.off, job.L)[zs, ys, xs].cpu().numpy()
             assert np.array_equal(got, want), f"op={op} {name}: {int((got != want).sum())} samples differ"
+
+
+@pytest.mark.parametrize("case", [(11, 37, 45, 16, 5, 0.6, 3), (6, 20, 130, 8, 7, 1.0, 2)],
+                         ids=lambda c: "x".join(map(str, c)))
+def test_volume_compositions(dev, case):
+    """md_morph3 (opening, closing, Beucher gradient, top-hats on volumes)
+    against the oracle's volume compositions on both volume paths."""
+    import torch
+
+    D, H, W, L, k, p, max_off = case
+    rng = np.random.default_rng(abs(hash(case)) % (2 ** 32))
+    job = synthetic.random_vol_job(rng, D, H, W, L, k, p=p, max_off=max_off)
+    vol = torch.from_numpy(job.vol).to(dev)
+    for op in range(2, 7):
+        want = oracle.morph3(op, job.vol, job.mask, job.off, L)
+        for name, opts in {"direct": dict(path=2), "ntt16": dict(path=1, tile=16)}.items():
+            print(f"  case {case} op={op} {name}", flush=True)
+            with md.options(**opts):
+                got = md.morph3(op, vol, job.mask, job.off, L).cpu().numpy()
+            bad = got != want
+            assert not bad.any(), f"{case} op={op} {name}: {int(bad.sum())} differ"

@@ -164,3 +164,48 @@ def test_volume_recipes():
     b = synthetic.ball_mask3(7)
     assert b.sum() == sum(1 for a in range(7) for i in range(7) for j in range(7)
                           if (a - 3) ** 2 + (i - 3) ** 2 + (j - 3) ** 2 <= 9)
+
+
+def test_volume_compositions_reduce_to_2d():
+    """On a one-slice volume with an SE in its centre slab, every volume
+    composition equals the (pinned) image composition of the slice."""
+    rng = np.random.default_rng(40)
+    k, L = 5, 16
+    job = synthetic.random_vol_job(rng, 1, 23, 19, L, k, p=0.6, max_off=4)
+    slab_m, slab_o = job.mask[k // 2].copy(), job.off[k // 2].copy()
+    m3 = np.zeros_like(job.mask)
+    m3[k // 2] = slab_m
+    o3 = np.zeros_like(job.off)
+    o3[k // 2] = slab_o
+    for op in range(7):
+        assert np.array_equal(oracle.morph3(op, job.vol, m3, o3, L)[0], oracle.morph(op, job.vol[0], slab_m, slab_o, L)), op
+
+
+def test_volume_compositions_algebra():
+    rng = np.random.default_rng(41)
+    L = 16
+    for p in (0.5, 1.0):
+        job = synthetic.random_vol_job(rng, 7, 9, 10, L, 3, p=p, max_off=3)
+        f, mk, of = job.vol, job.mask, job.off
+        o = oracle.opening3(f, mk, of, L)
+        c = oracle.closing3(f, mk, of, L)
+        assert (o <= f).all() and (c >= f).all()
+        m = oracle.max_offset(mk, of)
+        # idempotence: the second pass runs on the first result's range
+        assert np.array_equal(oracle.dilate3_e(oracle.erode3_e(o, mk, of, L - 1), mk, of, -m), o)
+        assert np.array_equal(oracle.erode3_e(oracle.dilate3_e(c, mk, of, -m), mk, of, L - 1 + m), c)
+        # complement duality with the reflected SE
+        cd = oracle.closing3(L - 1 - f, reflect3(mk), reflect3(of), L)
+        assert np.array_equal(o, L - 1 - cd)
+
+
+def test_volume_flat_opening_vs_scipy_interior():
+    rng = np.random.default_rng(42)
+    vol = rng.integers(0, 32, (12, 14, 15)).astype(np.int32)
+    k = 3
+    mask = synthetic.cube_mask3(k)
+    off = np.zeros((k, k, k), np.int32)
+    r = 2 * (k // 2)    # two SE radii: untouched by the border in both steps
+    inner = (slice(r, -r),) * 3
+    assert np.array_equal(oracle.opening3(vol, mask, off, 32)[inner], ndi.grey_opening(vol, size=k)[inner])
+    assert np.array_equal(oracle.closing3(vol, mask, off, 32)[inner], ndi.grey_closing(vol, size=k)[inner])
