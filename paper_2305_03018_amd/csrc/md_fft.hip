@@ -388,9 +388,9 @@ __device__ __forceinline__ void fft_tile_bin(typename Cx<R>::T *lds, const int32
 }
 
 // Lines of length N held in LDS at a time by the large-tile transform
-// (64 KiB of complex values, so two blocks fit a CU).
+// (32 KiB of complex values, so up to four blocks fit a CU).
 template <typename R, int N>
-constexpr int big_lines() { return (sizeof(R) == 4 ? 8192 : 4096) / N; }
+constexpr int big_lines() { return (sizeof(R) == 4 ? 4096 : 4096) / N; }
 
 // One (tile, bin) of Step 2 for spatial lengths whose N x N array does not
 // fit the LDS.  Same overlap-save geometry and bit-reversal bookkeeping as
@@ -412,7 +412,10 @@ __device__ __forceinline__ void fft_big_tile_bin(typename Cx<R>::T *lds, typenam
     using C = typename Cx<R>::T;
     constexpr int LB = big_lines<R, N>();
     constexpr int P = N + 1, LG = ilog2c(N), LLB = ilog2c(LB);
-    constexpr int CH = LB * N / BS < 16 ? LB * N / BS : 16;
+    // 4 loads in flight per batch: more would cost the registers that let a
+    // third block share the CU
+    constexpr int CHM = sizeof(R) == 4 ? 4 : 16;
+    constexpr int CH = LB * N / BS < CHM ? LB * N / BS : CHM;
     const int r = (k - 1) >> 1, T = N - k + 1;
     const int iy0 = oy0 - r, ix0 = ox0 - r;
     int bad = 0;
@@ -877,7 +880,7 @@ int fft_block_threads(int nt, int dbl) {
 
 size_t fft_lds_bytes(int nt, int dbl) {
     const size_t esz = dbl ? sizeof(double2) : sizeof(float2);
-    if (nt > (dbl ? kMaxLdsN64 : kMaxLdsN32)) return (size_t)((dbl ? 4096 : 8192) / nt) * (nt + 1) * esz;
+    if (nt > (dbl ? kMaxLdsN64 : kMaxLdsN32)) return (size_t)(4096 / nt) * (nt + 1) * esz;
     return (size_t)nt * (nt + 1) * esz;
 }
 

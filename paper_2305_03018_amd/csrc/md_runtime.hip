@@ -486,8 +486,14 @@ double dir_staged(int k, int pack) {
     return (double)(bh + k - 1) * (kDirBW + kpad) / ((double)bh * kDirBW);
 }
 
-double dir_cost(const md_job &j, const SEData &se, int pack) {
-    const double px = (double)j.H * j.W;
+// The per-unit costs are measured with the GPU full, several blocks sharing
+// each CU.  A job that runs alone (`lone`) and has fewer blocks than CUs
+// leaves CUs idle: it is priced as one block per CU (a block alone on a CU
+// runs about as many times faster as the blocks it would otherwise share the
+// CU with, so one round of resident blocks would overprice it).
+double dir_cost(const md_job &j, const SEData &se, int pack, bool lone = false) {
+    double px = (double)j.H * j.W;
+    if (lone) px = std::max(px, (double)g.cu * direct_block_rows(pack) * kDirBW);
     return px * (dir_staged(j.k, pack) * g.cost.dir_stage + se.dir_cells[pack ? 0 : 1] * g.cost.dir_cell[pack ? 0 : 1]);
 }
 
@@ -707,7 +713,17 @@ int check_job(const md_job &j) {
     return MD_OK;
 }
 
-double fft_cost(const md_job &j, int nt, int nr, int dbl) {
+// Floor of a lone transform launch: one item per CU for the LDS-resident
+// kernels (bound by the ALU and the LDS, so an item alone on a CU runs
+// correspondingly faster); two per CU for the large tiles, whose slab passes
+// through global memory are latency-bound (measured: an item alone is only
+// about 2.5x faster than four sharing a CU).
+double lone_items(int nt, int dbl) {
+    const bool big = dbl != kPrecNTT && nt > (dbl == kPrecFP64 ? kMaxLdsN64 : kMaxLdsN32);
+    return (big ? 2.0 : 1.0) * g.cu;
+}
+
+double fft_cost(const md_job &j, int nt, int nr, int dbl, bool lone = false) {
     const int T = nt - j.k + 1;
     if (T < 1) return INFINITY;
     const long long tiles = (long long)((j.H + T - 1) / T) * ((j.W + T - 1) / T);
@@ -715,16 +731,20 @@ double fft_cost(const md_job &j, int nt, int nr, int dbl) {
         if (nt > kNttMaxN) return INFINITY;
         const double item = g.cost.fft_item[2][ilog2i(nt)];
         if (item <= 0) return INFINITY;
-        return tiles * (double)nr * item + (double)tiles * T * T * nr * g.cost.dec_unit[2];
+        double items = (double)tiles * nr;
+        if (lone) items = std::max(items, lone_items(nt, dbl));
+        return items * item + (double)tiles * T * T * nr * g.cost.dec_unit[2];
     }
     const int bins = nr / 2 + 1;
     const double item = g.cost.fft_item[dbl][ilog2i(nt)];
     if (item <= 0) return INFINITY;
     const double pb = dec_padded_bins(bins, dbl);
-    return tiles * (double)bins * item + (double)tiles * T * T * pb * pb * g.cost.dec_unit[dbl];
+    double items = (double)tiles * bins;
+    if (lone) items = std::max(items, lone_items(nt, dbl));
+    return items * item + (double)tiles * T * T * pb * pb * g.cost.dec_unit[dbl];
 }
 
-int plan_job(const md_job &j, const SEData &se, Plan &p) {
+int plan_job(const md_job &j, const SEData &se, Plan &p, bool lone) {
     const long long nr_min = (long long)(j.L - 1) + se.maxoff + 1;
     int nr = (int)std::min<long long>(nr_min, 1 << 30);
     if (g.opt.nr > 0) {
@@ -750,14 +770,14 @@ int plan_job(const md_job &j, const SEData &se, Plan &p) {
     p.bins = dbl == kPrecNTT ? nr : nr / 2 + 1;
     const bool pack16 = (long long)(j.L - 1) + se.maxoff <= 16383;
     const bool dir_ok = j.k <= kMaxDirectK;
-    p.cost_dir = dir_ok ? dir_cost(j, se, pack16 ? 1 : 0) : INFINITY;
+    p.cost_dir = dir_ok ? dir_cost(j, se, pack16 ? 1 : 0, lone) : INFINITY;
     // transform plan: best spatial length by the cost model
     double best = INFINITY;
     int best_nt = 0;
     const bool fft_ok = nr_min <= 4096 && se.ncells > 0 && ntt_ok;
     for (int nt = 16; fft_ok && nt <= kMaxN; nt *= 2) {
         if (g.opt.tile > 0 && nt != g.opt.tile) continue;
-        const double cst = fft_cost(j, nt, nr, dbl);
+        const double cst = fft_cost(j, nt, nr, dbl, lone);
         if (cst < best) {
             best = cst;
             best_nt = nt;
@@ -851,7 +871,7 @@ int build_exec(const md_job *jobs, int n, const std::vector<SEData> &ses, Exec &
     for (int i = 0; i < n; ++i) {
         const md_job &j = jobs[i];
         Plan &p = ex.plans[i];
-        MD_TRY(plan_job(j, ses[i], p));
+        MD_TRY(plan_job(j, ses[i], p, n == 1));
         JobDev &d = ex.jobs_h[i];
         memset(&d, 0, sizeof d);
         d.D = 1;
@@ -1085,6 +1105,9 @@ int build_exec(const md_job *jobs, int n, const std::vector<SEData> &ses, Exec &
             }
             place(gr, fft_block_threads(gr.nt, gr.dbl), fft_lds_bytes(gr.nt, gr.dbl));
             if (gr.nt > (gr.dbl ? kMaxLdsN64 : kMaxLdsN32)) {
+                // 1024-point tiles keep 3 blocks per CU resident (registers):
+                // no slab for a fourth that would only wait
+                if (gr.nt >= 1024) gr.grid = (int)std::min<long long>(gr.grid, 3LL * g.cu);
                 auto b = std::make_unique<DevBuf>();
                 MD_TRY(b->ensure((size_t)gr.grid * gr.nt * gr.nt * (gr.dbl ? sizeof(double2) : sizeof(float2))));
                 gr.slabs = b->p;
