@@ -41,6 +41,9 @@ FP64_VECTOR_TFLOPS = 78.6
 CUS, CLOCK_GHZ, LANES_PER_CU = 256, 2.4, 64
 INT32_ALU_TOPS = CUS * LANES_PER_CU * CLOCK_GHZ / 1000.0   # one 32-bit integer op per lane per clock
 INT16X2_ALU_TOPS = 2 * INT32_ALU_TOPS                       # packed 16-bit: two ops per lane per clock
+# packed f16 window: two packed adds and one packed three-way max take two SE
+# cells of two pixels (8 add/max ops) in three issue slots
+F16X2_ADDMAX_TOPS = INT32_ALU_TOPS * 8.0 / 3.0
 
 
 # the forced-path comparison legs on the batch
@@ -94,14 +97,29 @@ def timed_steps(md, torch, stream, args_list, outs, steps, warmup, host=None, **
     return t0.elapsed_time(t1) / steps
 
 
+def stage_dtype(stage):
+    """Arithmetic type a profiled stage computes in."""
+    if stage in ("direct16", "direct3_16"):
+        return "f16"          # integers of magnitude <= 2048, exact in f16
+    if stage in ("direct16i", "direct3_16i"):
+        return "i16"
+    if stage.startswith("direct"):
+        return "i32"
+    if stage.startswith(("ntt", "decode_ntt")):
+        return "u32"          # residues mod 7 * 2^20 + 1
+    if stage.startswith(("fft64", "decode64", "recompute64")):
+        return "f64"
+    return "f32"
+
+
 def kernel_of(stage):
     """HIP kernel that a profiled stage launches."""
-    if stage == "direct16":
-        return "k_direct16<false>"
+    if stage in ("direct16", "direct16i"):
+        return f"k_direct16<false, {'true' if stage == 'direct16' else 'false'}>"
     if stage == "direct32":
         return "k_direct32<sel, false>"
-    if stage == "direct3_16":
-        return "k_direct16<true>"
+    if stage in ("direct3_16", "direct3_16i"):
+        return f"k_direct16<true, {'true' if stage == 'direct3_16' else 'false'}>"
     if stage == "direct3_32":
         return "k_direct32<sel, true>"
     if stage == "decode_ntt3":
@@ -158,7 +176,8 @@ def roofline_for(stage, prof, workload, launch_ms=None):
             "stage": stage, "avg_launch_ms": per_launch_ms,
             "alg_bytes_per_launch": rec["alg_bytes"] / rec["launches"]}
     if stage.startswith("direct"):
-        peak = INT16X2_ALU_TOPS if stage.endswith("16") else INT32_ALU_TOPS
+        peak = (F16X2_ADDMAX_TOPS if stage in ("direct16", "direct3_16") else
+                INT16X2_ALU_TOPS if stage in ("direct16i", "direct3_16i") else INT32_ALU_TOPS)
         return {"bound": "alu", "peak": peak, "unit": "TOP/s", "frac": achieved / peak, **base}
     if stage.startswith(("ntt", "decode_ntt")):
         # modular products (Shoup): one 32-bit high multiply (4 issue slots at
@@ -493,7 +512,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32+i32",
+        "dtype": "+".join(sorted({stage_dtype(k) for k in prof})),
         "data": "synthetic",
         "config": {"workload": args.workload, "jobs": len(jobs), "pixels": total_px,
                    "precision": "fp32 split twiddles + exact fp64 recompute", "path": "autotuned fft/direct",

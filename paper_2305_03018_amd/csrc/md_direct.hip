@@ -14,13 +14,30 @@ namespace {
 // acc = max(acc, in + b).  Erosion runs on the complement L-1-f with the
 // unreflected SE and complements the result (Sec. 2.1).
 //
-// Two element formats: two 16-bit lanes per 32-bit word holding vertically
-// adjacent image rows, so one packed add and one packed max advance two
-// outputs (k_direct16, used when every reachable sum fits: values and offsets
-// <= 16383 with minus infinity = -16384, so sums stay within [-32768,
-// 16383]), and plain int32 (k_direct32) for wider tonal ranges.
+// Element formats:
+//  * packed f16 (k_direct16<.., true>): two half-precision lanes per 32-bit
+//    word holding vertically adjacent image rows, used when every reachable
+//    sum is an integer of magnitude <= 2048 ((L-1) + max offset <= 2048),
+//    which f16 holds exactly; minus infinity is the f16 infinity, so no sum
+//    can wrap.  Two SE columns advance two outputs in three instructions:
+//    two packed adds and one packed three-way maximum;
+//  * packed int16 (k_direct16<.., false>): the same layout for values and
+//    offsets <= 16383 with minus infinity = -16384, so sums stay within
+//    [-32768, 16383]; one packed add and one packed max per SE column;
+//  * plain int32 (k_direct32) for wider tonal ranges.
 typedef short s16x2 __attribute__((ext_vector_type(2)));
+typedef _Float16 f16x2 __attribute__((ext_vector_type(2)));
 constexpr int kNeg16 = -16384;
+constexpr unsigned kNegF16 = 0xFC00u;   // f16 minus infinity
+
+template <bool F16> struct D16E {
+    using V = s16x2;
+    static constexpr unsigned kNegWord = ((unsigned)kNeg16 & 0xffffu) * 0x10001u;
+};
+template <> struct D16E<true> {
+    using V = f16x2;
+    static constexpr unsigned kNegWord = kNegF16 * 0x10001u;
+};
 
 // high 16 bits of lo-word, low 16 bits of hi-word: the packed pair of image
 // rows (2p+1, 2p+2) from word rows p and p+1
@@ -35,15 +52,17 @@ __device__ __forceinline__ int straddle(int lo, int hi) {
 // consecutive columns (4 x 64 per row, pitch <= 256 + 4: words past 256 are
 // never read), the waves take 4 consecutive rows each per pass.  The 16 loads
 // of a pass are unconditional (pixel 0 stands in outside the image and the
-// block) and issued together before any of them is used.  PACK: LDS word
-// (p, c) holds image rows 2p (low half) and 2p+1 (high half).  Returns
-// non-zero if an in-image value lies outside [0, L-1].
-template <bool PACK, int RB = 4>
+// block) and issued together before any of them is used.  FMT 0: int32
+// words; 1 (int16) and 2 (f16): LDS word (p, c) holds image rows 2p (low
+// half) and 2p+1 (high half).  Returns non-zero if an in-image value lies
+// outside [0, L-1].
+template <int FMT, int RB = 4>
 __device__ __forceinline__ int dir_stage(const JobDev &J, const int32_t *slice, int by0, int bx0, int rad, int TH,
                                          int TC, int pitch, int32_t *tile) {
     const int lane = threadIdx.x & 63;
     const auto img = gld(slice);
     const int H = J.H, W = J.W, L = J.L, op = J.op;
+    constexpr bool PACK = FMT != 0;
     const int neg = PACK ? kNeg16 : kNeg;
     int badv = 0;
     for (int a0 = (threadIdx.x >> 6) * RB; a0 < TH; a0 += (kDirThreads / 64) * RB) {
@@ -72,7 +91,9 @@ __device__ __forceinline__ int dir_stage(const JobDev &J, const int32_t *slice, 
                 v = op ? L - 1 - v : v;
                 v = in[h][u] ? v : neg;
                 if (a < TH && c < pitch) {
-                    if (PACK) ((short *)tile)[2 * ((a >> 1) * pitch + c) + (a & 1)] = (short)v;
+                    short hw = (short)v;
+                    if (FMT == 2) hw = in[h][u] ? __builtin_bit_cast(short, (_Float16)v) : (short)kNegF16;
+                    if (PACK) ((short *)tile)[2 * ((a >> 1) * pitch + c) + (a & 1)] = hw;
                     else tile[a * pitch + c] = v;
                 }
             }
@@ -200,7 +221,7 @@ __device__ __forceinline__ void direct32_block(const JobDev &J, int z, int by0, 
         if (SEL)
             for (int q = threadIdx.x; q < k * kpad; q += kDirThreads) seL[q] = gld(ps.sek)[q];
         for (int q = threadIdx.x; q < 2 * k; q += kDirThreads) rowL[q] = gld(ps.rows)[q];
-        const int bad = dir_stage<false>(J, ps.slice, by0, bx0, rad, TH, kDirBW + k - 1, TWD, tile);
+        const int bad = dir_stage<0>(J, ps.slice, by0, bx0, rad, TH, kDirBW + k - 1, TWD, tile);
         if (bad && range_err) atomicOr(range_err, 1u);
         __syncthreads();
         const int32_t *sebase = SEL ? seL : ps.sek;
@@ -279,16 +300,39 @@ __device__ __forceinline__ void d16_load(int (&w)[NW], const int32_t *p) {
 
 // acc = max(acc, in[t + sj] + b[sj]) over the NS SE columns of one SE row;
 // all sums of a column before their maxima (a packed op that reads the result
-// of the instruction right before it costs a wait state)
-template <int NS>
-__device__ __forceinline__ void d16_row(s16x2 (&acc)[kDirRX], const s16x2 *in, const s16x2 (&b)[NS]) {
+// of the instruction right before it costs a wait state).  In f16 two
+// columns share one three-way maximum.
+template <int NS, bool F16>
+__device__ __forceinline__ void d16_row(typename D16E<F16>::V (&acc)[kDirRX], const typename D16E<F16>::V *in,
+                                        const typename D16E<F16>::V (&b)[NS]) {
+    using V = typename D16E<F16>::V;
+    if constexpr (F16) {
+        static_assert(NS % 2 == 0, "f16 steps pair their SE columns");
 #pragma unroll
-    for (int sj = 0; sj < NS; ++sj) {
-        s16x2 sum[kDirRX];
+        for (int sj = 0; sj < NS; sj += 2) {
+            V s0[kDirRX], s1[kDirRX];
 #pragma unroll
-        for (int t = 0; t < kDirRX; ++t) sum[t] = in[t + sj] + b[sj];
+            for (int t = 0; t < kDirRX; ++t) s0[t] = in[t + sj] + b[sj];
 #pragma unroll
-        for (int t = 0; t < kDirRX; ++t) acc[t] = __builtin_elementwise_max(acc[t], sum[t]);
+            for (int t = 0; t < kDirRX; ++t) s1[t] = in[t + sj + 1] + b[sj + 1];
+#pragma unroll
+            for (int t = 0; t < kDirRX; ++t) {
+                acc[t] = __builtin_elementwise_maximum(acc[t], __builtin_elementwise_maximum(s0[t], s1[t]));
+                // the accumulator is opaque past this point, so the selector
+                // cannot regroup maxima across column pairs or SE rows (which
+                // turns one three-way maximum per two sums into three per four)
+                asm("" : "+v"(acc[t]));
+            }
+        }
+    } else {
+#pragma unroll
+        for (int sj = 0; sj < NS; ++sj) {
+            V sum[kDirRX];
+#pragma unroll
+            for (int t = 0; t < kDirRX; ++t) sum[t] = in[t + sj] + b[sj];
+#pragma unroll
+            for (int t = 0; t < kDirRX; ++t) acc[t] = __builtin_elementwise_max(acc[t], sum[t]);
+        }
     }
 }
 
@@ -307,13 +351,15 @@ __device__ __forceinline__ void d16_se(int (&b)[NS], const int32_t *p) {
 // arithmetic is the first use of the registers that the previous call's
 // issue() filled, so their wait comes before the loads that issue() starts,
 // and those loads stay in flight over the rest of the pair.
-template <int R, int NS, int O, bool ODD, typename F>
-__device__ __forceinline__ void d16_pair(s16x2 (&acc)[R][kDirRX], const int (&win)[R + 1][D16<NS, O>::NW],
-                                         const int (&be)[NS], const int (&bo)[NS], F &&issue) {
+template <int R, int NS, int O, bool ODD, bool F16, typename F>
+__device__ __forceinline__ void d16_pair(typename D16E<F16>::V (&acc)[R][kDirRX],
+                                         const int (&win)[R + 1][D16<NS, O>::NW], const int (&be)[NS],
+                                         const int (&bo)[NS], F &&issue) {
+    using V = typename D16E<F16>::V;
     constexpr int NU = NS + kDirRX - 1;
-    s16x2 b[NS];
+    V b[NS];
 #pragma unroll
-    for (int sj = 0; sj < NS; ++sj) b[sj] = __builtin_bit_cast(s16x2, be[sj]);
+    for (int sj = 0; sj < NS; ++sj) b[sj] = __builtin_bit_cast(V, be[sj]);
 #pragma unroll
     for (int r = 0; r < R; ++r) {
         if (r == (R > 1 ? 1 : 0)) {
@@ -321,21 +367,20 @@ __device__ __forceinline__ void d16_pair(s16x2 (&acc)[R][kDirRX], const int (&wi
             issue();
             __builtin_amdgcn_sched_barrier(0);
         }
-        s16x2 in[NU];
+        V in[NU];
 #pragma unroll
-        for (int t = 0; t < NU; ++t) in[t] = __builtin_bit_cast(s16x2, win[r][O + t]);
-        d16_row<NS>(acc[r], in, b);
+        for (int t = 0; t < NU; ++t) in[t] = __builtin_bit_cast(V, win[r][O + t]);
+        d16_row<NS, F16>(acc[r], in, b);
     }
     if constexpr (ODD) {
 #pragma unroll
-        for (int sj = 0; sj < NS; ++sj) b[sj] = __builtin_bit_cast(s16x2, bo[sj]);
+        for (int sj = 0; sj < NS; ++sj) b[sj] = __builtin_bit_cast(V, bo[sj]);
 #pragma unroll
         for (int r = 0; r < R; ++r) {
-            s16x2 in[NU];
+            V in[NU];
 #pragma unroll
-            for (int t = 0; t < NU; ++t)
-                in[t] = __builtin_bit_cast(s16x2, straddle(win[r][O + t], win[r + 1][O + t]));
-            d16_row<NS>(acc[r], in, b);
+            for (int t = 0; t < NU; ++t) in[t] = __builtin_bit_cast(V, straddle(win[r][O + t], win[r + 1][O + t]));
+            d16_row<NS, F16>(acc[r], in, b);
         }
     }
 }
@@ -347,8 +392,8 @@ __device__ __forceinline__ void d16_pair(s16x2 (&acc)[R][kDirRX], const int (&wi
 // scalar loads share a counter) comes after its arithmetic.  The fetches
 // reach one word row past the staged block and SE row k at most, which the
 // LDS allocation and the SE array's extra row cover.
-template <int R, int NS, int O>
-__device__ __forceinline__ void d16_column(s16x2 (&acc)[R][kDirRX], const int32_t *trow, int P,
+template <int R, int NS, int O, bool F16>
+__device__ __forceinline__ void d16_column(typename D16E<F16>::V (&acc)[R][kDirRX], const int32_t *trow, int P,
                                            const int32_t *se, int kpad, int k, int s0, int s1) {
     constexpr int NW = D16<NS, O>::NW;
     int win[R + 1][NW];
@@ -362,7 +407,7 @@ __device__ __forceinline__ void d16_column(s16x2 (&acc)[R][kDirRX], const int32_
     // one pair: offsets in (ce, co), those of the next pair fetched into (ne, no)
     auto step = [&](const int (&ce)[NS], const int (&co)[NS], int (&ne)[NS], int (&no)[NS]) {
         int nxt[NW];
-        d16_pair<R, NS, O, true>(acc, win, ce, co, [&] {
+        d16_pair<R, NS, O, true, F16>(acc, win, ce, co, [&] {
             d16_load<NW>(nxt, trow + (s + R + 1) * P);
             d16_se<NS>(ne, se + (2 * s + 2) * kpad);
             d16_se<NS>(no, se + (2 * s + 3) * kpad);
@@ -389,7 +434,7 @@ __device__ __forceinline__ void d16_column(s16x2 (&acc)[R][kDirRX], const int32_
             bo[sj] = bo2[sj];
         }
     }
-    if (s <= s1) d16_pair<R, NS, O, false>(acc, win, be, bo, [] {});   // s = (k-1)/2: SE row k-1 alone
+    if (s <= s1) d16_pair<R, NS, O, false, F16>(acc, win, be, bo, [] {});   // s = (k-1)/2: SE row k-1 alone
 }
 
 // LDS words of one packed block: word rows of image rows 2p, 2p+1 (low,
@@ -398,7 +443,7 @@ __host__ __device__ constexpr int d16_pitch(int kpad) { return kDirBW + kpad + 4
 __host__ __device__ constexpr int d16_rows(int k, int R) { return (32 * R + k - 1) / 2 + 1; }
 
 // Output slice z of the job (0 for an image).
-template <bool VOL>
+template <bool VOL, bool F16>
 __device__ __forceinline__ void direct16_block(const JobDev &J, int z, int by0, int bx0, int32_t *tile,
                                                unsigned int *range_err) {
     constexpr int R = VOL ? 1 : kD16R, BH = 32 * R;
@@ -412,12 +457,12 @@ __device__ __forceinline__ void direct16_block(const JobDev &J, int z, int by0, 
     const int q = wy * 8 * R + rg * R;             // LDS word row = first output row / 2
     // a wave whose outputs all lie outside the image skips the window
     const bool live = bx0 + wx * 64 < J.W && by0 + wy * 16 * R < J.H;
-    s16x2 acc[R][kDirRX];
-    const int neg = (int)(((unsigned)kNeg16 & 0xffffu) * 0x10001u);
+    using V = typename D16E<F16>::V;
+    V acc[R][kDirRX];
 #pragma unroll
     for (int r = 0; r < R; ++r)
 #pragma unroll
-        for (int t = 0; t < kDirRX; ++t) acc[r][t] = __builtin_bit_cast(s16x2, neg);
+        for (int t = 0; t < kDirRX; ++t) acc[r][t] = __builtin_bit_cast(V, D16E<F16>::kNegWord);
     const int npass = VOL ? J.nslab : 1;
     for (int s = 0; s < npass; ++s) {
         DirPass ps;
@@ -428,7 +473,7 @@ __device__ __forceinline__ void direct16_block(const JobDev &J, int z, int by0, 
         // window.
         int oy = by0, ox = bx0;
         if (VOL) asm volatile("" : "+s"(oy), "+s"(ox));
-        const int bad = dir_stage<true, VOL ? 2 : 4>(J, ps.slice, oy, ox, rad, TH, TC, P, tile);
+        const int bad = dir_stage<F16 ? 2 : 1, VOL ? 2 : 4>(J, ps.slice, oy, ox, rad, TH, TC, P, tile);
         if (bad && range_err) atomicOr(range_err, 1u);
         __syncthreads();
         if (live) {
@@ -441,10 +486,10 @@ __device__ __forceinline__ void direct16_block(const JobDev &J, int z, int by0, 
                 const int jb = steps[4 * i], kind = steps[4 * i + 1], s0 = steps[4 * i + 2], s1 = steps[4 * i + 3];
                 const int32_t *se = ps.sek16 + jb;
                 switch (kind) {
-                    case 0: d16_column<R, 8, 0>(acc, base + jb, P, se, kpad, k, s0, s1); break;
-                    case 1: d16_column<R, 4, 0>(acc, base + jb, P, se, kpad, k, s0, s1); break;
-                    case 2: d16_column<R, 2, 0>(acc, base + jb, P, se, kpad, k, s0, s1); break;
-                    default: d16_column<R, 2, 2>(acc, base + jb - 2, P, se, kpad, k, s0, s1); break;
+                    case 0: d16_column<R, 8, 0, F16>(acc, base + jb, P, se, kpad, k, s0, s1); break;
+                    case 1: d16_column<R, 4, 0, F16>(acc, base + jb, P, se, kpad, k, s0, s1); break;
+                    case 2: d16_column<R, 2, 0, F16>(acc, base + jb, P, se, kpad, k, s0, s1); break;
+                    default: d16_column<R, 2, 2, F16>(acc, base + jb - 2, P, se, kpad, k, s0, s1); break;
                 }
             }
         }
@@ -458,9 +503,12 @@ __device__ __forceinline__ void direct16_block(const JobDev &J, int z, int by0, 
         uint16_t *ob = (uint16_t *)tile;
 #pragma unroll
         for (int r = 0; r < R; ++r) {
-            s16x2 c[kDirRX];
+            V c[kDirRX];
 #pragma unroll
-            for (int t = 0; t < kDirRX; ++t) c[t] = __builtin_elementwise_max(acc[r][t], (s16x2){0, 0});
+            for (int t = 0; t < kDirRX; ++t) {
+                if constexpr (F16) c[t] = __builtin_elementwise_maximum(acc[r][t], (V){0, 0});
+                else c[t] = __builtin_elementwise_max(acc[r][t], (V){0, 0});
+            }
 #pragma unroll
             for (int hh = 0; hh < 2; ++hh) {
                 int4 w;
@@ -484,7 +532,8 @@ __device__ __forceinline__ void direct16_block(const JobDev &J, int z, int by0, 
             for (int y = threadIdx.x / kDirBW; y < BH; y += kDirThreads / kDirBW) {
                 const int gy = by0 + y;
                 if (gy >= J.H) break;
-                const int d = ob[y * kDirBW + cx];
+                const uint16_t h = ob[y * kDirBW + cx];
+                const int d = F16 ? (int)(float)__builtin_bit_cast(_Float16, h) : (int)h;
                 gst(out)[(size_t)gy * W + gx] = op ? (L - 1 - d) : d;
             }
         }
@@ -494,7 +543,7 @@ __device__ __forceinline__ void direct16_block(const JobDev &J, int z, int by0, 
 
 // The volume form asks for 4 waves per SIMD: its window loops fit, and the few
 // values spilled to scratch are read and written outside them.
-template <bool VOL>
+template <bool VOL, bool F16>
 __global__ __launch_bounds__(kDirThreads) __attribute__((amdgpu_waves_per_eu(VOL ? 4 : 1))) void k_direct16(const JobDev *__restrict__ jobs,
                                                           const Seg *__restrict__ segs, int nseg,
                                                           long long nitems, StatsDev *st) {
@@ -505,7 +554,7 @@ __global__ __launch_bounds__(kDirThreads) __attribute__((amdgpu_waves_per_eu(VOL
         const int local = (int)(it - S.item0), nb = J.dir_bx * J.dir_by;
         const int z = local / nb, rem = local - z * nb;
         const int byi = rem / J.dir_bx, bxi = rem - byi * J.dir_bx;
-        direct16_block<VOL>(J, z, byi * (VOL ? 32 : kD16BH), bxi * kDirBW, dyn_lds, &st->range_err);
+        direct16_block<VOL, F16>(J, z, byi * (VOL ? 32 : kD16BH), bxi * kDirBW, dyn_lds, &st->range_err);
     }
 }
 
@@ -524,11 +573,13 @@ hipError_t launch_direct(int pack, int sel, const JobDev *jobs, const Seg *segs,
                          int grid, size_t lds_bytes, StatsDev *st, hipStream_t s, bool vol) {
     if (nitems <= 0) return hipSuccess;
     if (vol) {
-        if (pack) k_direct16<true><<<grid, kDirThreads, lds_bytes, s>>>(jobs, segs, nseg, nitems, st);
+        if (pack == 2) k_direct16<true, true><<<grid, kDirThreads, lds_bytes, s>>>(jobs, segs, nseg, nitems, st);
+        else if (pack) k_direct16<true, false><<<grid, kDirThreads, lds_bytes, s>>>(jobs, segs, nseg, nitems, st);
         else if (sel) k_direct32<true, true><<<grid, kDirThreads, lds_bytes, s>>>(jobs, segs, nseg, nitems, st);
         else k_direct32<false, true><<<grid, kDirThreads, lds_bytes, s>>>(jobs, segs, nseg, nitems, st);
     } else {
-        if (pack) k_direct16<false><<<grid, kDirThreads, lds_bytes, s>>>(jobs, segs, nseg, nitems, st);
+        if (pack == 2) k_direct16<false, true><<<grid, kDirThreads, lds_bytes, s>>>(jobs, segs, nseg, nitems, st);
+        else if (pack) k_direct16<false, false><<<grid, kDirThreads, lds_bytes, s>>>(jobs, segs, nseg, nitems, st);
         else if (sel) k_direct32<true, false><<<grid, kDirThreads, lds_bytes, s>>>(jobs, segs, nseg, nitems, st);
         else k_direct32<false, false><<<grid, kDirThreads, lds_bytes, s>>>(jobs, segs, nseg, nitems, st);
     }

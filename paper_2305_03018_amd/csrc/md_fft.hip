@@ -303,13 +303,32 @@ __device__ __forceinline__ void batched(int n, LoadF load, UseF use) {
     }
 }
 
+// Order of the LDS walk in the encode and in the output of a tile.  Walking
+// the LDS in order keeps a wavefront's LDS accesses on consecutive words
+// and moves the bit reversal to the global side (scattered within one
+// row); walking the image in order keeps the global accesses contiguous and
+// puts the bit reversal on the LDS index, where lanes collide on banks.
+//  * Encode: LDS order while a wavefront's 64 scattered pixel loads stay
+//    within 512 bytes of the row (N <= 128); beyond that they touch up to
+//    16 cache lines per load and the image order is faster.
+//  * Output: LDS order in FP64 only.  FP64 elements span four banks, so the
+//    conflicts cost more than the scatter; FP32 transforms are bound by
+//    vector ALU issue, and the idle lanes and scattered stores of an
+//    LDS-order output cost more than the conflicts they remove.
+template <typename R, int N> constexpr bool kEncLdsOrder = N <= 128;
+template <typename R> constexpr bool kOutLdsOrder = sizeof(R) == 8;
+
 // Step 1 for `rows` x N input pixels starting at image pixel (gy0, gx0):
 // out-of-image pixels are the zero polynomial, in-image grey values
 // (complemented for erosion) become their range-DFT column enc_m[v].
-// Calls put(l, j, value) for row l < rows, column j < N.  The pixel loads of
-// CH elements go out together, then their table gathers; returns non-zero if
-// an in-image value lies outside [0, L-1].
-template <typename R, int N, int BS, int CH, typename PutF>
+// Calls put(l, c, value) for row l < rows and column c < N.  With XR the
+// column c is the LDS column and holds image column gx0 + brev(c) (the
+// forward transform wants bit-reversed input; reversing on the global side
+// keeps a wavefront's LDS stores on consecutive words, where a bit-reversed
+// LDS index puts 16 lanes on two banks); without XR, c is the image column.
+// The pixel loads of CH elements go out together, then their table gathers;
+// returns non-zero if an in-image value lies outside [0, L-1].
+template <typename R, int N, int BS, int CH, bool XR, typename PutF>
 __device__ __forceinline__ int encode_rows(int rows, const int32_t *__restrict__ img, int H, int W, int L, int op,
                                            int gy0, int gx0, const typename Cx<R>::T *__restrict__ enc_m, PutF put) {
     using C = typename Cx<R>::T;
@@ -323,7 +342,7 @@ __device__ __forceinline__ int encode_rows(int rows, const int32_t *__restrict__
 #pragma unroll
         for (int e = 0; e < CH; ++e) {
             const int q = q0 + e * BS;
-            const int gy = gy0 + (q >> LG), gx = gx0 + (q & (N - 1));
+            const int gy = gy0 + (q >> LG), gx = gx0 + (XR ? brev<LG>(q & (N - 1)) : (q & (N - 1)));
             in[e] = q < n && (unsigned)gy < (unsigned)H && (unsigned)gx < (unsigned)W;
             val[e] = im[in[e] ? (size_t)gy * W + gx : 0];
         }
@@ -364,8 +383,9 @@ __device__ __forceinline__ void fft_tile_bin(typename Cx<R>::T *lds, const int32
     constexpr int CH = N * N / BS < 16 ? N * N / BS : 16;
     const int r = (k - 1) >> 1, T = N - k + 1;
     const int iy0 = oy0 - r, ix0 = ox0 - r;
-    const int bad = encode_rows<R, N, BS, CH>(N, img, H, W, L, op, iy0, ix0, enc_m, [&](int i, int j, C v) {
-        lds[brev<LG>(i) * P + brev<LG>(j)] = v;
+    const int bad = encode_rows<R, N, BS, CH, kEncLdsOrder<R, N>>(N, img, H, W, L, op, iy0, ix0, enc_m,
+                                                                [&](int i, int c, C v) {
+        lds[brev<LG>(i) * P + (kEncLdsOrder<R, N> ? c : brev<LG>(c))] = v;
     });
     if (bad && range_err) atomicOr(range_err, 1u);
     __syncthreads();
@@ -380,9 +400,18 @@ __device__ __forceinline__ void fft_tile_bin(typename Cx<R>::T *lds, const int32
     __syncthreads();
     dif_axis<R, N, 1, BS, true>(lds, tw);
     dif_axis<R, N, 0, BS, true>(lds, tw);
-    for (int q = threadIdx.x; q < T * T; q += BS) {
-        const int i = q / T + (k - 1), j = q % T + (k - 1);
-        stg(ydst, q, lds[brev<LG>(i) * P + brev<LG>(j)]);
+    if constexpr (kOutLdsOrder<R>) {
+        // LDS column b holds output column brev(b): walk the LDS rows in
+        // order and scatter within the output row
+        for (int q = threadIdx.x; q < T * N; q += BS) {
+            const int i = (q >> LG) + (k - 1), b = q & (N - 1), j = brev<LG>(b);
+            if (j >= k - 1) stg(ydst, (size_t)(i - (k - 1)) * T + (j - (k - 1)), lds[brev<LG>(i) * P + b]);
+        }
+    } else {
+        for (int q = threadIdx.x; q < T * T; q += BS) {
+            const int i = q / T + (k - 1), j = q % T + (k - 1);
+            stg(ydst, q, lds[brev<LG>(i) * P + brev<LG>(j)]);
+        }
     }
     __syncthreads();
 }
@@ -421,8 +450,9 @@ __device__ __forceinline__ void fft_big_tile_bin(typename Cx<R>::T *lds, typenam
     int bad = 0;
     // 1. rows
     for (int rb = 0; rb < N; rb += LB) {
-        bad |= encode_rows<R, N, BS, CH>(LB, img, H, W, L, op, iy0 + rb, ix0, enc_m,
-                                         [&](int l, int j, C v) { lds[l * P + brev<LG>(j)] = v; });
+        bad |= encode_rows<R, N, BS, CH, kEncLdsOrder<R, N>>(LB, img, H, W, L, op, iy0 + rb, ix0, enc_m, [&](int l, int c, C v) {
+            lds[l * P + (kEncLdsOrder<R, N> ? c : brev<LG>(c))] = v;
+        });
         __syncthreads();
         dit_axis<R, N, 0, BS, false, LB>(lds, tw);
         for (int q = threadIdx.x; q < LB * N; q += BS) {
@@ -460,10 +490,18 @@ __device__ __forceinline__ void fft_big_tile_bin(typename Cx<R>::T *lds, typenam
             [&](int q, C v) { lds[(q >> LG) * P + (q & (N - 1))] = v; });
         __syncthreads();
         dif_axis<R, N, 0, BS, true, LB>(lds, tw);
-        for (int q = threadIdx.x; q < LB * T; q += BS) {
-            const int l = q / T, xo = q - l * T;
-            const int y = brev<LG>(rb + l);
-            if (y >= k - 1) stg(ydst, (size_t)(y - (k - 1)) * T + xo, lds[l * P + brev<LG>(xo + k - 1)]);
+        if constexpr (kOutLdsOrder<R>) {
+            for (int q = threadIdx.x; q < LB * N; q += BS) {
+                const int l = q >> LG, b = q & (N - 1);
+                const int y = brev<LG>(rb + l), x = brev<LG>(b);
+                if (y >= k - 1 && x >= k - 1) stg(ydst, (size_t)(y - (k - 1)) * T + (x - (k - 1)), lds[l * P + b]);
+            }
+        } else {
+            for (int q = threadIdx.x; q < LB * T; q += BS) {
+                const int l = q / T, xo = q - l * T;
+                const int y = brev<LG>(rb + l);
+                if (y >= k - 1) stg(ydst, (size_t)(y - (k - 1)) * T + xo, lds[l * P + brev<LG>(xo + k - 1)]);
+            }
         }
         __syncthreads();
     }

@@ -91,14 +91,15 @@ struct JobDev {
     const double2 *dec64;        // [dp][dp]
     // direct max-plus path
     const int32_t *sek;          // [k][kpad] offsets in correlation order, kNeg where masked
-    const int32_t *sek16;        // same, as two equal 16-bit lanes per word, -16384 where masked
+    const int32_t *sek16;        // same, as two equal 16-bit lanes per word: int16 (-16384 where
+                                 // masked) or f16 (minus infinity where masked), per dir_pack
     const int32_t *sek_rows;     // [k][2] first and last active column of each row (first > last: none)
     const int32_t *sek_steps;    // packed form: [dir_nsteps][4] column steps (first column, kind, first
                                  // and last SE row pair (2s, 2s+1)); kind 0/1/2: 8/4/2 columns, 3: 2
                                  // columns starting at a column = 2 mod 4
     int dir_nsteps;
     int kpad;
-    int dir_pack;                // 1: 16-bit packed form (all sums fit in int16)
+    int dir_pack;                // element form of the window, direct_form()
     // exact transform path (dbl == kPrecNTT): se_spec / enc / dec hold uint32
     // residues mod kNttP, nr == bins == n, dec_pitch = n rounded up to 8
     const uint32_t *ntt_spec_s;  // Shoup companions of se_spec
@@ -156,7 +157,8 @@ int dec_pitch(int nr);
 hipError_t launch_decode(int var, int dbl, const JobDev *jobs, const Seg *segs, int nseg,
                          long long nitems, int grid, float band, unsigned int *tile_flags,
                          int2 *fb_list, StatsDev *st, hipStream_t s);
-// vol: volume jobs (a window pass per active SE slab, JobDev::slabs)
+// vol: volume jobs (a window pass per active SE slab, JobDev::slabs);
+// pack: direct_form()
 hipError_t launch_direct(int pack, int sel, const JobDev *jobs, const Seg *segs, int nseg, long long nitems,
                          int grid, size_t lds_bytes, StatsDev *st, hipStream_t s, bool vol = false);
 hipError_t launch_fallback(int nt64, const JobDev *jobs, const int2 *fb_list, const StatsDev *st,
@@ -164,6 +166,11 @@ hipError_t launch_fallback(int nt64, const JobDev *jobs, const int2 *fb_list, co
                            hipStream_t s);
 // vol: the volume form of the packed kernel (32-row blocks)
 size_t direct_lds_bytes(int k, int kpad, int pack, int sel, bool vol = false);
+// Element form of the direct window for the largest reachable sum
+// top = (L-1) + max offset: 2 = packed f16 pairs (every sum an integer of
+// magnitude <= 2048, exact in f16), 1 = packed int16 pairs (<= 16383),
+// 0 = int32.  Both packed forms share block shape and LDS footprint.
+constexpr int direct_form(long long top) { return top <= 2048 ? 2 : top <= 16383 ? 1 : 0; }
 // exact transform path (md_ntt.hip)
 int ntt_block_threads(int nt);
 size_t ntt_lds_bytes(int nt);

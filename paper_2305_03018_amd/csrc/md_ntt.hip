@@ -155,7 +155,9 @@ __device__ __forceinline__ void ndif_axis(uint32_t *lds, const NTw &tw) {
 // path: input index j holds f(o0 - r + j), the SE umbra sits at [0, k), and
 // circular output index i >= k-1 is the linear result for pixel o0+i-(k-1).
 // Loads of a thread's CH pixels (and then their table gathers) are issued
-// together before any is used.
+// together before any is used.  LDS column b holds image column brev(b), so
+// a wavefront's LDS stores and loads stay on consecutive words; the bit
+// reversal is paid on the global side, within one tile row.
 template <int N, int BS>
 __device__ __forceinline__ void ntt_tile_bin(uint32_t *lds, const int32_t *__restrict__ img, int H, int W, int L,
                                              int op, int k, int oy0, int ox0, const uint32_t *__restrict__ enc_m,
@@ -174,7 +176,7 @@ __device__ __forceinline__ void ntt_tile_bin(uint32_t *lds, const int32_t *__res
 #pragma unroll
         for (int e = 0; e < CH; ++e) {
             const int q = (c0 + e) * BS + threadIdx.x;
-            const int gy = iy0 + (q >> LG), gx = ix0 + (q & (N - 1));
+            const int gy = iy0 + (q >> LG), gx = ix0 + nbrev<LG>(q & (N - 1));
             in[e] = (unsigned)gy < (unsigned)H && (unsigned)gx < (unsigned)W;
             val[e] = im[in[e] ? (size_t)gy * W + gx : 0];
         }
@@ -191,7 +193,7 @@ __device__ __forceinline__ void ntt_tile_bin(uint32_t *lds, const int32_t *__res
 #pragma unroll
         for (int e = 0; e < CH; ++e) {
             const int q = (c0 + e) * BS + threadIdx.x;
-            lds[nbrev<LG>(q >> LG) * P + nbrev<LG>(q & (N - 1))] = in[e] ? v[e] : 0u;
+            lds[nbrev<LG>(q >> LG) * P + (q & (N - 1))] = in[e] ? v[e] : 0u;
         }
     }
     if (badv && range_err) atomicOr(range_err, 1u);
@@ -217,9 +219,9 @@ __device__ __forceinline__ void ntt_tile_bin(uint32_t *lds, const int32_t *__res
     __syncthreads();
     ndif_axis<N, 1, BS, true>(lds, tw);
     ndif_axis<N, 0, BS, true>(lds, tw);
-    for (int q = threadIdx.x; q < T * T; q += BS) {
-        const int i = q / T + (k - 1), j = q % T + (k - 1);
-        gst(ydst)[q] = lds[nbrev<LG>(i) * P + nbrev<LG>(j)];
+    for (int q = threadIdx.x; q < T * N; q += BS) {
+        const int i = (q >> LG) + (k - 1), b = q & (N - 1), j = nbrev<LG>(b);
+        if (j >= k - 1) gst(ydst)[(size_t)(i - (k - 1)) * T + (j - (k - 1))] = lds[nbrev<LG>(i) * P + b];
     }
     __syncthreads();
 }

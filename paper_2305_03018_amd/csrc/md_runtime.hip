@@ -106,7 +106,7 @@ struct NttSpec {
 };
 
 struct DirSE {
-    DevBuf sek, sek16, rows, steps;
+    DevBuf sek, sek16, sekh, rows, steps;
     int kpad = 0, nsteps = 0;
 };
 
@@ -381,11 +381,14 @@ struct SEData {
 // ranges (8- and 4-column steps start at a multiple of 4); the steps are
 // chosen by dynamic programming over the groups to minimise the issue cost of
 // the window, kDirPairCost per row pair and step width (instructions of one
-// pair in the kernel's unrolled loops), so neighbouring groups with nearly
+// pair in the f16 kernel's unrolled loops), so neighbouring groups with nearly
 // equal ranges share a wider step even where that covers a few masked cells.
 // Each step is {first column, kind, first pair, last pair}, kind 0/1/2 =
-// 8/4/2 columns, 3 = 2 columns at 2 mod 4.
-constexpr double kDirPairCost[3] = {580.5, 311.5, 177.5};   // 8, 4, 2 columns
+// 8/4/2 columns, 3 = 2 columns at 2 mod 4.  The int16 form (one max per SE
+// column rather than half a three-way max) issues 580.5 / 311.5 / 177.5 and
+// takes the same steps.
+constexpr double kDirPairCost[3] = {461.0, 250.0, 146.0};   // 8, 4, 2 columns
+constexpr double kDirPairCostI16 = 580.5;                    // 8 columns, int16 form
 
 // row pairs a step over pairs s0..s1 runs (the last, even SE row of an odd k
 // alone counts as one)
@@ -491,10 +494,22 @@ double dir_staged(int k, int pack) {
 // leaves CUs idle: it is priced as one block per CU (a block alone on a CU
 // runs about as many times faster as the blocks it would otherwise share the
 // CU with, so one round of resident blocks would overprice it).
+// Per-cell cost of a direct_form(): the packed f16 form is the calibrated
+// one; the int16 form issues one max per SE column where f16 issues half a
+// three-way max, kDirPairCostI16 / kDirPairCost more per 8-column pair.
+double dir_cell_cost(int form) {
+    return form == 2 ? g.cost.dir_cell[0] : form == 1 ? g.cost.dir_cell[0] * (kDirPairCostI16 / kDirPairCost[0])
+                                                      : g.cost.dir_cell[1];
+}
+
+double dir_block_cost(int k, const SEData &se, int form) {
+    return dir_staged(k, form) * g.cost.dir_stage + se.dir_cells[form ? 0 : 1] * dir_cell_cost(form);
+}
+
 double dir_cost(const md_job &j, const SEData &se, int pack, bool lone = false) {
     double px = (double)j.H * j.W;
     if (lone) px = std::max(px, (double)g.cu * direct_block_rows(pack) * kDirBW);
-    return px * (dir_staged(j.k, pack) * g.cost.dir_stage + se.dir_cells[pack ? 0 : 1] * g.cost.dir_cell[pack ? 0 : 1]);
+    return px * dir_block_cost(j.k, se, pack);
 }
 
 // Kept bins rounded up as the decode variant for that count accumulates them.
@@ -647,9 +662,19 @@ int get_nspectrum(const SEData &se, int nt, int n, const NttRange *rt, NttSpec *
     return MD_OK;
 }
 
+// IEEE half-precision bits of an integer 0 <= v <= 2048 (exact: at most 11
+// significant bits).
+uint32_t f16_bits(int v) {
+    if (v <= 0) return 0;
+    int e = 0;
+    while ((v >> (e + 1)) != 0) ++e;                       // 2^e <= v < 2^(e+1)
+    const uint32_t frac = e <= 10 ? ((uint32_t)v << (10 - e)) & 0x3ffu : ((uint32_t)v >> (e - 10)) & 0x3ffu;
+    return (uint32_t)(e + 15) << 10 | frac;
+}
+
 // Correlation-order offsets for the direct window (the effective SE
-// reflected), as int32 and as packed 16-bit pairs, plus each row's span of
-// active cells.
+// reflected), as int32 and as packed 16-bit pairs (int16 and f16), plus each
+// row's span of active cells.
 int get_dirse(const SEData &se, DirSE **out) {
     auto it = g.dirse.find(se.key);
     if (it != g.dirse.end()) {
@@ -664,7 +689,9 @@ int get_dirse(const SEData &se, DirSE **out) {
     // whole row past the SE (SE row k, all minus infinity) ahead of use
     std::vector<int32_t> h((size_t)k * d->kpad + 16, kNeg), h16((size_t)(k + 1) * d->kpad + 16), rows((size_t)2 * k);
     const uint32_t neg16 = 0xC000C000u;   // -16384 in both lanes
+    const uint32_t negh = 0xFC00FC00u;    // f16 minus infinity in both lanes
     for (size_t q = 0; q < h16.size(); ++q) h16[q] = (int32_t)neg16;
+    std::vector<int32_t> hh(h16.size(), (int32_t)negh);
     for (int i = 0; i < k; ++i) {
         int lo = k, hi = -1;
         for (int j = 0; j < k; ++j) {
@@ -673,6 +700,8 @@ int get_dirse(const SEData &se, DirSE **out) {
             const int32_t b = se.off[src];
             h[(size_t)i * d->kpad + j] = b;
             h16[(size_t)i * d->kpad + j] = (int32_t)(((uint32_t)b & 0xffffu) * 0x10001u);
+            // offsets above 2048 never reach the f16 form (direct_form)
+            if (b <= 2048) hh[(size_t)i * d->kpad + j] = (int32_t)(f16_bits(b) * 0x10001u);
             lo = std::min(lo, j);
             hi = std::max(hi, j);
         }
@@ -683,12 +712,14 @@ int get_dirse(const SEData &se, DirSE **out) {
     d->nsteps = (int)steps.size() / 4;
     MD_TRY(d->sek.ensure(h.size() * sizeof(int32_t)));
     MD_TRY(d->sek16.ensure(h16.size() * sizeof(int32_t)));
+    MD_TRY(d->sekh.ensure(hh.size() * sizeof(int32_t)));
     MD_TRY(d->rows.ensure(rows.size() * sizeof(int32_t)));
     MD_TRY(d->steps.ensure(std::max<size_t>(1, steps.size()) * sizeof(int32_t)));
     if (!steps.empty())
         MD_HIP(hipMemcpy(d->steps.p, steps.data(), steps.size() * sizeof(int32_t), hipMemcpyHostToDevice));
     MD_HIP(hipMemcpy(d->sek.p, h.data(), h.size() * sizeof(int32_t), hipMemcpyHostToDevice));
     MD_HIP(hipMemcpy(d->sek16.p, h16.data(), h16.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+    MD_HIP(hipMemcpy(d->sekh.p, hh.data(), hh.size() * sizeof(int32_t), hipMemcpyHostToDevice));
     MD_HIP(hipMemcpy(d->rows.p, rows.data(), rows.size() * sizeof(int32_t), hipMemcpyHostToDevice));
     *out = d.get();
     g.dirse[se.key] = std::move(d);
@@ -768,9 +799,9 @@ int plan_job(const md_job &j, const SEData &se, Plan &p, bool lone) {
     p.dbl = dbl;
     p.nr = nr;
     p.bins = dbl == kPrecNTT ? nr : nr / 2 + 1;
-    const bool pack16 = (long long)(j.L - 1) + se.maxoff <= 16383;
+    const int form = direct_form((long long)(j.L - 1) + se.maxoff);
     const bool dir_ok = j.k <= kMaxDirectK;
-    p.cost_dir = dir_ok ? dir_cost(j, se, pack16 ? 1 : 0, lone) : INFINITY;
+    p.cost_dir = dir_ok ? dir_cost(j, se, form, lone) : INFINITY;
     // transform plan: best spatial length by the cost model
     double best = INFINITY;
     int best_nt = 0;
@@ -887,12 +918,12 @@ int build_exec(const md_job *jobs, int n, const std::vector<SEData> &ses, Exec &
             DirSE *ds = nullptr;
             MD_TRY(get_dirse(ses[i], &ds));
             d.sek = (const int32_t *)ds->sek.p;
-            d.sek16 = (const int32_t *)ds->sek16.p;
+            d.dir_pack = direct_form((long long)(j.L - 1) + ses[i].maxoff);
+            d.sek16 = (const int32_t *)(d.dir_pack == 2 ? ds->sekh.p : ds->sek16.p);
             d.sek_rows = (const int32_t *)ds->rows.p;
             d.sek_steps = (const int32_t *)ds->steps.p;
             d.dir_nsteps = ds->nsteps;
             d.kpad = ds->kpad;
-            d.dir_pack = (long long)(j.L - 1) + ses[i].maxoff <= 16383 ? 1 : 0;
             d.dir_bx = (j.W + kDirBW - 1) / kDirBW;
             d.dir_by = (j.H + direct_block_rows(d.dir_pack) - 1) / direct_block_rows(d.dir_pack);
             // the packed form reads the SE through scalar loads; the 32-bit form
@@ -969,10 +1000,7 @@ int build_exec(const md_job *jobs, int n, const std::vector<SEData> &ses, Exec &
     std::vector<int> dir_order;
     for (int i = 0; i < n; ++i)
         if (ex.plans[i].path == kPathDirect) dir_order.push_back(i);
-    auto block_cost = [&](int i) {
-        const int pk = ex.jobs_h[i].dir_pack;
-        return dir_staged(jobs[i].k, pk) * g.cost.dir_stage + ses[i].dir_cells[pk ? 0 : 1] * g.cost.dir_cell[pk ? 0 : 1];
-    };
+    auto block_cost = [&](int i) { return dir_block_cost(jobs[i].k, ses[i], ex.jobs_h[i].dir_pack); };
     std::stable_sort(dir_order.begin(), dir_order.end(), [&](int a, int b) { return block_cost(a) > block_cost(b); });
     for (int i : dir_order) {
         const int pack = ex.jobs_h[i].dir_pack, sel = dir_sel[i];
@@ -1230,7 +1258,8 @@ int enqueue(Exec &ex, hipStream_t s, bool skip_decode = false, bool capturing = 
     }
     for (auto &gr : ex.direct) {
         if (gr.nitems <= 0) continue;
-        ProfScope ps(prof, sd, gr.pack ? "direct16" : "direct32", gr.alg_bytes, gr.alg_ops, gr.units);
+        ProfScope ps(prof, sd, gr.pack == 2 ? "direct16" : gr.pack ? "direct16i" : "direct32", gr.alg_bytes,
+                     gr.alg_ops, gr.units);
         MD_HIP(launch_direct(gr.pack, gr.sel, ex.jobs_d, gr.segs_d, (int)gr.segs.size(), gr.nitems, gr.grid, gr.lds,
                              g.st_d, sd));
         ps.done();
@@ -1927,7 +1956,7 @@ int vol_plan(int D, int H, int W, int L, const VolSE &se, VolPlan &p) {
     const int k = se.k, r = (k - 1) / 2;
     const double vox = (double)D * H * W;
     // direct window: one pass per active slab
-    p.pack = (long long)(L - 1) + se.maxoff <= 16383 ? 1 : 0;
+    p.pack = direct_form((long long)(L - 1) + se.maxoff);
     double cells = 0;
     for (int a = 0; a < k; ++a) {
         bool any = false;
@@ -1943,8 +1972,7 @@ int vol_plan(int D, int H, int W, int L, const VolSE &se, VolPlan &p) {
     p.lds = direct_lds_bytes(k, kpad, p.pack, p.sel, true);
     const int bh = direct_block_rows(p.pack, true);
     const double staged = (double)(bh + k - 1) * (kDirBW + kpad) / ((double)bh * kDirBW);
-    p.cost_dir = vox * ((double)p.slabs.size() * staged * g.cost.dir_stage +
-                        cells * g.cost.dir_cell[p.pack ? 0 : 1]);
+    p.cost_dir = vox * ((double)p.slabs.size() * staged * g.cost.dir_stage + cells * dir_cell_cost(p.pack));
     // exact transform: range length n >= L + max offset, cubic tiles 8 / 16 / 32
     long long nmin = (long long)(L - 1) + se.maxoff + 1;
     int n = ntt_length(nmin);
@@ -2040,7 +2068,7 @@ int vol_run(int op, const int32_t *vol, int D, int H, int W, int L, const uint8_
             SlabDev &e = sl[i];
             memset(&e, 0, sizeof e);
             e.sek = (const int32_t *)ds->sek.p;
-            e.sek16 = (const int32_t *)ds->sek16.p;
+            e.sek16 = (const int32_t *)(p.pack == 2 ? ds->sekh.p : ds->sek16.p);
             e.sek_rows = (const int32_t *)ds->rows.p;
             e.sek_steps = (const int32_t *)ds->steps.p;
             e.dir_nsteps = ds->nsteps;
@@ -2113,7 +2141,7 @@ int vol_run(int op, const int32_t *vol, int D, int H, int W, int L, const uint8_
     if (p.path == kPathDirect) {
         double units = 0;
         for (auto &sd : p.slabs) units += sd.dir_cells[p.pack ? 0 : 1];
-        ProfScope ps(prof, g.stream, p.pack ? "direct3_16" : "direct3_32", vox * 8.0, vox * se.ncells * 2.0,
+        ProfScope ps(prof, g.stream, p.pack == 2 ? "direct3_16" : p.pack ? "direct3_16i" : "direct3_32", vox * 8.0, vox * se.ncells * 2.0,
                      vox * units);
         MD_HIP(launch_direct(p.pack, p.sel, (const JobDev *)g.vjob.p, (const Seg *)g.vseg.p, 1, dir_items,
                              occupancy_grid(dir_items, p.lds, kDirThreads), p.lds, g.st_d, g.stream, true));

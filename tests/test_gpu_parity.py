@@ -205,6 +205,59 @@ def test_direct_32bit_form(dev):
         assert_parity(job, dev, want=want)
 
 
+def _with_top(job, max_off):
+    """Sets the first active SE cell's offset to max_off, so that the largest
+    reachable sum is exactly (L-1) + max_off."""
+    i, j = np.argwhere(job.mask)[0]
+    job.off[i, j] = max_off
+    return job
+
+
+def _direct_stage(job, dev):
+    md.profile_reset()
+    with md.options(profile=1, graph=0):
+        run_job(job, dev, **DIRECT)
+    return [s for s in md.profile_get() if s.startswith("direct")]
+
+
+def test_direct_packed_forms(dev):
+    """The packed direct window computes in f16 while every reachable sum
+    (L-1) + max offset is at most 2048 (integers that f16 holds exactly), in
+    int16 up to 16383, and in int32 beyond.  Cases at and just past each
+    boundary, with masked cells, erosion and empty windows, match the oracle
+    exactly and run the form their range selects."""
+    rng = np.random.default_rng(31)
+    cases = [
+        # H, W, L, k, p, max_off, op, stage
+        (70, 150, 2049, 3, 1.0, 0, 0, "direct16"),       # top 2048: f16, sums reach it
+        (70, 150, 2049, 5, 0.6, 0, 1, "direct16"),
+        (90, 140, 2000, 7, 0.7, 47, 0, "direct16"),      # top 2046
+        (90, 140, 2000, 9, 0.7, 49, 1, "direct16"),      # top 2048
+        (90, 140, 2000, 7, 0.7, 50, 0, "direct16i"),     # top 2049: int16
+        (90, 140, 2000, 41, 0.3, 50, 1, "direct16i"),
+        (65, 257, 16000, 15, 0.5, 384, 0, "direct16i"),  # top 16383
+        (65, 257, 16000, 15, 0.5, 384, 1, "direct16i"),
+        (65, 257, 16000, 15, 0.5, 385, 0, "direct32"),   # top 16384: int32
+    ]
+    for H, W, L, k, p, max_off, op, stage in cases:
+        job = _with_top(synthetic.random_job(rng, H, W, L, k, p=p, max_off=max_off, op=op), max_off)
+        want = oracle.run_job(job)
+        assert_parity(job, dev, want=want, **DIRECT)
+        assert _direct_stage(job, dev) == [stage], (job.name, stage)
+    # one SE cell far from the origin: windows near the borders are empty
+    # (dilation 0, erosion L-1)
+    for L, max_off, stage in ((2049, 0, "direct16"), (3000, 77, "direct16i")):
+        for op in (0, 1):
+            img = rng.integers(0, L, (50, 300)).astype(np.int32)
+            mask = np.zeros((41, 41), np.uint8)
+            off = np.zeros((41, 41), np.int32)
+            mask[0, 40] = 1
+            off[0, 40] = max_off
+            job = synthetic.Job(img, L, mask, off, op, f"corner41_L{L}")
+            assert_parity(job, dev, **DIRECT)
+            assert _direct_stage(job, dev) == [stage]
+
+
 def test_large_se_fft_only(dev):
     """SEs beyond the direct window's limit (k > 127) go through the FFT path
     with spatial tiles larger than the LDS (256 to 1024 points per side)."""

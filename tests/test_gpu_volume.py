@@ -89,6 +89,18 @@ def test_wide_range_uses_32bit_window(dev):
         md.dilate3(__import__("torch").from_numpy(job.vol).to(dev), job.mask, job.off, job.L)
 
 
+def test_packed_forms(dev):
+    """The packed window's f16 form up to a reachable sum of 2048 and its
+    int16 form just past it, on volumes (one window pass per SE slab)."""
+    rng = np.random.default_rng(53)
+    for D, H, W, L, k, p, max_off in ((7, 20, 70, 2049, 3, 0.7, 0), (6, 25, 90, 1900, 5, 0.6, 148),
+                                      (7, 20, 70, 2000, 5, 0.6, 49), (5, 30, 75, 2000, 7, 0.4, 60)):
+        job = synthetic.random_vol_job(rng, D, H, W, L, k, p=p, max_off=max_off)
+        a, i, j = np.argwhere(job.mask)[0]
+        job.off[a, i, j] = max_off
+        check(job, dev, modes={"auto": {}, "direct": dict(path=2)})
+
+
 def test_degenerate_volumes(dev):
     rng = np.random.default_rng(52)
     # one slice, one voxel, k = 1
