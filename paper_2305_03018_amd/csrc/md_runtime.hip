@@ -151,11 +151,16 @@ struct Exec {
     std::vector<Wave> waves;
     DevBuf segbuf, ybuf, flags, list, slots;
     long long nflags = 0;
-    std::vector<int> fb_classes;
-    size_t slot_elems = 0;
+    // exact recompute, one launch per FP64 length: the per-block slot of the
+    // largest job of that length and the launch's block count
+    struct FbClass {
+        int nt64 = 0;
+        size_t slot_elems = 0;
+        int grid = 0;
+    };
+    std::vector<FbClass> fb_classes;
     std::vector<std::unique_ptr<DevBuf>> slabbufs;   // per-block slabs of large-tile groups
     DevBuf fb_slabs;
-    int fb_grid = 0;
     long long fft_tiles = 0;
     int n_direct = 0, n_fft = 0;
     hipGraph_t graph = nullptr;
@@ -502,8 +507,20 @@ double dir_cell_cost(int form) {
                                                       : g.cost.dir_cell[1];
 }
 
+// The per-cell cost is calibrated with 4 packed blocks per CU.  An SE whose
+// LDS footprint leaves fewer blocks per CU has fewer waves to hide latency
+// with: measured on 2048^2 images, k = 95 (2 blocks per CU) runs 3% and
+// k = 127 (1 block per CU) 10% above the calibrated figure.
+double dir_occupancy(int k, int form) {
+    if (!form) return 1.0;
+    const int kpad = (k + kDirRX - 1) / kDirRX * kDirRX;
+    const size_t per_cu = kLdsBytes / direct_lds_bytes(k, kpad, form, 0);
+    return per_cu >= 3 ? 1.0 : per_cu == 2 ? 1.03 : 1.10;
+}
+
 double dir_block_cost(int k, const SEData &se, int form) {
-    return dir_staged(k, form) * g.cost.dir_stage + se.dir_cells[form ? 0 : 1] * dir_cell_cost(form);
+    return dir_staged(k, form) * g.cost.dir_stage +
+           se.dir_cells[form ? 0 : 1] * dir_cell_cost(form) * dir_occupancy(k, form);
 }
 
 double dir_cost(const md_job &j, const SEData &se, int pack, bool lone = false) {
@@ -990,9 +1007,14 @@ int build_exec(const md_job *jobs, int n, const std::vector<SEData> &ses, Exec &
             d.se_spec64 = (const double2 *)sp64->s64.p;
             d.enc64 = (const double2 *)rt->enc64.p;
             d.dec64 = (const double2 *)rt->dec64.p;
-            ex.slot_elems = std::max(ex.slot_elems, (size_t)p.bins * p.T64 * p.T64);
-            if (std::find(ex.fb_classes.begin(), ex.fb_classes.end(), p.nt64) == ex.fb_classes.end())
-                ex.fb_classes.push_back(p.nt64);
+            auto fc = std::find_if(ex.fb_classes.begin(), ex.fb_classes.end(),
+                                   [&](const Exec::FbClass &c) { return c.nt64 == p.nt64; });
+            if (fc == ex.fb_classes.end()) {
+                ex.fb_classes.emplace_back();
+                fc = ex.fb_classes.end() - 1;
+                fc->nt64 = p.nt64;
+            }
+            fc->slot_elems = std::max(fc->slot_elems, (size_t)p.bins * p.T64 * p.T64);
         }
     }
     // direct groups: one segment per direct job, in decreasing cost per
@@ -1150,15 +1172,21 @@ int build_exec(const md_job *jobs, int n, const std::vector<SEData> &ses, Exec &
     MD_TRY(ex.flags.ensure(std::max<long long>(1, flag_total) * sizeof(unsigned int)));
     MD_TRY(ex.list.ensure(std::max<long long>(1, flag_total) * sizeof(int2)));
     if (!ex.fb_classes.empty()) {
-        int big64 = 0;
-        for (int nt64 : ex.fb_classes)
-            if (nt64 > kMaxLdsN64) big64 = std::max(big64, nt64);
-        // recompute blocks: bounded so slots and slabs stay under ~1 GiB
-        const double per_block = (double)ex.slot_elems * sizeof(double2) + (double)big64 * big64 * sizeof(double2);
-        const int cap = (int)std::max(1.0, std::min((double)std::min(g.cu, 128), (1 << 30) / per_block));
-        ex.fb_grid = (int)std::max<long long>(1, std::min<long long>(flag_total, cap));
-        MD_TRY(ex.slots.ensure((size_t)ex.fb_grid * ex.slot_elems * sizeof(double2)));
-        if (big64) MD_TRY(ex.fb_slabs.ensure((size_t)ex.fb_grid * big64 * big64 * sizeof(double2)));
+        // recompute blocks per length: two per CU (the kernel's LDS holds two),
+        // bounded so that that launch's slots and slabs stay under ~2 GiB.  Each
+        // length sizes its own grid, so a long tile's large slots do not starve
+        // the launches of shorter ones; the buffers fit the largest launch.
+        size_t slot_bytes = 0, slab_bytes = 0;
+        for (auto &c : ex.fb_classes) {
+            const double slab = c.nt64 > kMaxLdsN64 ? (double)c.nt64 * c.nt64 * sizeof(double2) : 0.0;
+            const double per_block = (double)c.slot_elems * sizeof(double2) + slab;
+            const int cap = (int)std::max(1.0, std::min(2.0 * g.cu, (double)(2ll << 30) / per_block));
+            c.grid = (int)std::max<long long>(1, std::min<long long>(flag_total, cap));
+            slot_bytes = std::max(slot_bytes, (size_t)c.grid * c.slot_elems * sizeof(double2));
+            if (slab > 0) slab_bytes = std::max(slab_bytes, (size_t)c.grid * c.nt64 * c.nt64 * sizeof(double2));
+        }
+        MD_TRY(ex.slots.ensure(slot_bytes));
+        if (slab_bytes) MD_TRY(ex.fb_slabs.ensure(slab_bytes));
     }
     // job table
     MD_HIP(hipMalloc(&ex.jobs_d, sizeof(JobDev) * n));
@@ -1296,10 +1324,10 @@ int enqueue(Exec &ex, hipStream_t s, bool skip_decode = false, bool capturing = 
     }
     MD_HIP(join.run());
     if (skip_decode) return MD_OK;
-    for (int nt64 : ex.fb_classes) {
-        ProfScope ps(prof, s, "recompute64_n" + std::to_string(nt64), 0, 0, 0);
-        MD_HIP(launch_fallback(nt64, ex.jobs_d, (const int2 *)ex.list.p, g.st_d, (double2 *)ex.slots.p,
-                               ex.slot_elems, ex.fb_grid, g.tw64, (double2 *)ex.fb_slabs.p, s));
+    for (const auto &c : ex.fb_classes) {
+        ProfScope ps(prof, s, "recompute64_n" + std::to_string(c.nt64), 0, 0, 0);
+        MD_HIP(launch_fallback(c.nt64, ex.jobs_d, (const int2 *)ex.list.p, g.st_d, (double2 *)ex.slots.p,
+                               c.slot_elems, c.grid, g.tw64, (double2 *)ex.fb_slabs.p, s));
         ps.done();
     }
     return MD_OK;
