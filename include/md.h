@@ -294,9 +294,10 @@ int md_profile_reset(void);
 
 /* Cost-model constants in use, in ns per work unit, into the host array
  * `dst` of capacity `n` (at least 24):
- *   [0] direct window, 16-bit packed form, per output pixel per SE cell
+ *   [0] direct window, packed f16 form, per output pixel per SE cell
  *       stepped through, counted in 8-column-step equivalents (a narrower
- *       step's cells weighted by its higher issue cost per cell)
+ *       step's cells weighted by its higher issue cost per cell); the packed
+ *       int16 form is priced at this times its issue-count ratio 580.5/461
  *   [1] the same, 32-bit form
  *   [2] direct window, per staged image word (block plus halo)
  *   [3] decode FP32, per pixel per (padded kept bins)^2

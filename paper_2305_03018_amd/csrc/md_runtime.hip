@@ -1444,7 +1444,9 @@ int autotune_body() {
 }
 
 // Persisted cost model: MD_TUNE_FILE names a text file of "key value" lines,
-// valid for the device whose name and compute-unit count it records.
+// valid for the device whose name and compute-unit count it records.  A file
+// that lacks any key (one written for other kernel forms) is ignored and the
+// model is measured again.
 std::string device_key() {
     hipDeviceProp_t prop;
     if (hipGetDeviceProperties(&prop, g.device) != hipSuccess) return "unknown";
@@ -1464,7 +1466,7 @@ bool load_tune_file() {
     if (fscanf(f, "device %255s", dev) == 1 && device_key() == dev) dev_ok = true;
     while (dev_ok && fscanf(f, "%127s %lf", key, &v) == 2) {
         const std::string k(key);
-        if (k == "direct16_cell") c.dir_cell[0] = v, ++got;
+        if (k == "direct_f16_cell") c.dir_cell[0] = v, ++got;
         else if (k == "direct32_cell") c.dir_cell[1] = v, ++got;
         else if (k == "direct_stage") c.dir_stage = v, ++got;
         else if (k == "decode32") c.dec_unit[0] = v, ++got;
@@ -1486,7 +1488,7 @@ void save_tune_file() {
     FILE *f = fopen(path, "w");
     if (!f) return;
     fprintf(f, "device %s\n", device_key().c_str());
-    fprintf(f, "direct16_cell %.9g\ndirect32_cell %.9g\ndirect_stage %.9g\ndecode32 %.9g\ndecode64 %.9g\n",
+    fprintf(f, "direct_f16_cell %.9g\ndirect32_cell %.9g\ndirect_stage %.9g\ndecode32 %.9g\ndecode64 %.9g\n",
             g.cost.dir_cell[0], g.cost.dir_cell[1], g.cost.dir_stage, g.cost.dec_unit[0], g.cost.dec_unit[1]);
     for (int nt = 16; nt <= kMaxN; nt *= 2) fprintf(f, "fft32_n%d %.9g\n", nt, g.cost.fft_item[0][ilog2i(nt)]);
     for (int nt = 16; nt <= kMaxN; nt *= 2) fprintf(f, "fft64_n%d %.9g\n", nt, g.cost.fft_item[1][ilog2i(nt)]);
