@@ -324,6 +324,54 @@ def large_se_leg(md, torch, dev, stream, steps):
     return res
 
 
+def paper_shapes_leg(md, torch, dev, stream, steps):
+    """The paper's own workload shapes (Sec. 4.1: i.i.d. uniform image and SE
+    values over the tonal range, square SEs; Sec. 4.2: 5 x 5 SE, 2- to 5-bit
+    images of side FFT size - 4), run through the auto path: a cold call
+    (plan, SE tables), then `steps` timed calls, with sampled pixels checked
+    against the oracle.  Odd SE sides stand in for the paper's even ones (the
+    SE origin is its centre cell)."""
+    import oracle
+    from paper_2305_03018_amd import synthetic
+
+    rng = np.random.default_rng(17)
+    cases = ([("se_size", 512, bits, k) for bits in (4, 8) for k in (33, 65, 129, 255)] +
+             [("image_size", n, 4, (n // 10) | 1) for n in (512, 1024, 2048, 4096)] +
+             [("image_size", n, 8, (n // 10) | 1) for n in (512, 1024, 2048)] +
+             [("fpga", n - 4, 5, 5) for n in (128, 512, 1024)])
+    res = []
+    for exp, side, bits, k in cases:
+        L = 1 << bits
+        img_np = rng.integers(0, L, (side, side)).astype(np.int32)
+        mask = synthetic.square_mask(k)
+        off = rng.integers(0, L, (k, k)).astype(np.int32)
+        img = torch.from_numpy(img_np).to(dev)
+        out = torch.empty_like(img)
+        batch = md.Batch([(img, mask, off, L, 0)], [out])
+        c0 = time.perf_counter()
+        batch.run()
+        cold = (time.perf_counter() - c0) * 1e3
+        st = md.get_stats()
+        with md.options(sync=0):
+            t0 = torch.cuda.Event(enable_timing=True)
+            t1 = torch.cuda.Event(enable_timing=True)
+            t0.record(stream)
+            for _ in range(steps):
+                batch.run()
+            t1.record(stream)
+            torch.cuda.synchronize()
+        ys, xs = rng.integers(0, side, 256), rng.integers(0, side, 256)
+        if not np.array_equal(out.cpu().numpy()[ys, xs], oracle.at(img_np, mask, off, L, 0, ys, xs)):
+            raise SystemExit(f"bench: paper-shape parity failure ({exp} {side} {bits}-bit k={k})")
+        ms = t0.elapsed_time(t1) / steps
+        res.append({"experiment": exp, "side": side, "bits": bits, "k": k, "ms": ms, "cold_ms": cold,
+                    "mpx_s": side * side / (ms * 1e-3) / 1e6, "path": "direct" if st["path"] == 2 else "fft",
+                    "n_t": st["n_t"], "n_r": st["n_r"]})
+        log(f"bench: paper shape {exp} {side}^2 {bits}-bit k={k}: {ms:.3f} ms ({res[-1]['path']})")
+        del batch, img, out
+    return res
+
+
 def spectrum_error(md, torch, dev):
     """Transform-domain values of one tile of the 512 x 512 blurred image
     (15 x 15 disk, n_t = 128, n_r = 24) just before the inverse range
@@ -483,6 +531,7 @@ def main():
             cmp["volume"] = volume_leg(md, torch, dev, stream, max(3, args.steps // 4))
             cmp["large_se"] = large_se_leg(md, torch, dev, stream, 3)
             cmp["host_stream"] = host_stream_leg(md, torch, dev, 3)
+            cmp["paper_shapes"] = paper_shapes_leg(md, torch, dev, stream, 3)
         # profiled pass for the roofline (events around every launch, no graph)
         md.profile_reset()
         with md.options(profile=1, graph=0, sync=1, precision=0, path=0):
