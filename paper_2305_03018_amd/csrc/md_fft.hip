@@ -704,6 +704,159 @@ __global__ __launch_bounds__(kDecThreads) void k_decode(const JobDev *__restrict
     if (threadIdx.x == 0 && rm > 0.f) atomicMax(&st->max_res_bits, __float_as_uint(rm));
 }
 
+// Range-axis FFT decode: Step 3 for a power-of-two range length nr = 2M.
+// A pixel's coefficient vector is the real inverse DFT of its Hermitian
+// spectrum, of which the bins X_0 .. X_M are kept:
+//   c_d = scale * sum_{m < nr} X_m w^(d m),  w = exp(2 pi i / nr),  X_{nr-m} = conj(X_m).
+// Its even and odd samples are one complex inverse DFT of length M:
+//   Z_k = (X_k + conj(X_{M-k})) + i w^k (X_k - conj(X_{M-k})),  k < M,
+//   z_n = sum_{k<M} Z_k exp(2 pi i k n / M),  c_{2n} = scale Re z_n,  c_{2n+1} = scale Im z_n,
+// about 2.5 nr log2(nr) flops per pixel where the dense decode takes
+// nr (nr/2 + 1) products.  A work item is P = 4096 / M pixels of one tile:
+//   1. each pixel's packed Z goes to one LDS row in bit-reversed order;
+//   2. radix-2 decimation-in-time stages, two per LDS round trip (a single
+//      first stage when log2 M is odd);
+//   3. every degree is rounded; the 64 lanes of a wave hold consecutive
+//      degrees of one pixel, so the wave takes its top non-zero degree with
+//      shuffles and one LDS atomic max per pixel; residuals and tile flags as
+//      in the dense decode.
+// Every job of one launch has the same range length, so the M twiddles are
+// staged in LDS once per block.
+template <typename R, int LM>
+__global__ __launch_bounds__(kDecThreads) void k_decode_fft(const JobDev *__restrict__ jobs,
+                                                            const Seg *__restrict__ segs, int nseg,
+                                                            long long nitems, float band,
+                                                            unsigned int *tile_flags, int2 *fb_list,
+                                                            StatsDev *st) {
+    using C = typename Cx<R>::T;
+    constexpr int M = 1 << LM, LP = 12 - LM, P = 1 << LP, PITCH = M + 1;
+    static_assert(M >= 64 && LP >= 0, "a wave scans 64 consecutive degrees of one pixel");
+    __shared__ C zs[P * PITCH];
+    __shared__ C tws[M];
+    __shared__ int s_top[P];
+    __shared__ float s_red[kDecThreads / 64];
+    float run_max = 0.f;
+    if (blockIdx.x < nitems) {
+        const C *tw = (const C *)jobs[segs[find_seg(segs, nseg, blockIdx.x)].job].rtw;
+        for (int m = threadIdx.x; m < M; m += kDecThreads) tws[m] = ldg(tw, m);
+    }
+    __syncthreads();
+    for (long long it = blockIdx.x; it < nitems; it += gridDim.x) {
+        const Seg S = segs[find_seg(segs, nseg, it)];
+        const JobDev &J = jobs[S.job];
+        const int local = (int)(it - S.item0);
+        const int tl = local / S.pblocks, pb = local - tl * S.pblocks;
+        const int tile = S.tile0 + tl;
+        const int T = J.T, TT = T * T;
+        const int ty = tile / J.tiles_x, tx = tile - ty * J.tiles_x;
+        const C *X = (const C *)S.y + (size_t)tl * J.bins * TT;
+        const int p0 = pb * P;
+        auto pixel_valid = [&](int p) {
+            const int q = p0 + p, ly = q / T, lx = q - ly * T;
+            return q < TT && ty * T + ly < J.H && tx * T + lx < J.W;
+        };
+        // 1. packed spectra (zero outside the image), bit-reversed per row;
+        // the loads of CH points per thread go out before any is used (the
+        // bins of one pixel lie T*T apart, so each load is its own burst)
+        constexpr int CH = 4, NPT = P * M / kDecThreads;
+        static_assert(NPT % CH == 0, "whole batches per thread");
+        const bool pv = pixel_valid(threadIdx.x & (P - 1));   // the same pixel in every batch
+        for (int u0 = threadIdx.x; u0 < P * M; u0 += CH * kDecThreads) {
+            C a[CH], b[CH];
+#pragma unroll
+            for (int e = 0; e < CH; ++e) {
+                const int u = u0 + e * kDecThreads, p = u & (P - 1), k = u >> LP;
+                a[e] = b[e] = czero<C>();
+                if (pv) {
+                    a[e] = ldg(X, (size_t)k * TT + p0 + p);
+                    b[e] = ldg(X, (size_t)(M - k) * TT + p0 + p);
+                }
+            }
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int e = 0; e < CH; ++e) {
+                const int u = u0 + e * kDecThreads, p = u & (P - 1), k = u >> LP;
+                const C w = tws[k];
+                const R ex = a[e].x + b[e].x, ey = a[e].y - b[e].y;   // a + conj(b)
+                const R ox = a[e].x - b[e].x, oy = a[e].y + b[e].y;   // a - conj(b)
+                const R wx = w.x * ox - w.y * oy, wy = w.x * oy + w.y * ox;
+                C zv;
+                zv.x = ex - wy;   // e + i (w^k o)
+                zv.y = ey + wx;
+                zs[p * PITCH + brev<LM>(k)] = zv;
+            }
+        }
+        if (threadIdx.x < P) s_top[threadIdx.x] = -1;
+        __syncthreads();
+        // 2. inverse DFT of length M
+        int h = 1;
+        if constexpr (LM & 1) {
+            for (int u = threadIdx.x; u < P * (M / 2); u += kDecThreads) {
+                C *L = zs + (u >> (LM - 1)) * PITCH + 2 * (u & (M / 2 - 1));
+                const C x0 = L[0], x1 = L[1];
+                L[0] = cadd(x0, x1);
+                L[1] = csub(x0, x1);
+            }
+            __syncthreads();
+            h = 2;
+        }
+        for (; h < M; h *= 4) {   // stages of half-size h and 2h over blocks of 4h points
+            for (int u = threadIdx.x; u < P * (M / 4); u += kDecThreads) {
+                const int r = u & (M / 4 - 1), t = r & (h - 1);
+                C *L = zs + (u >> (LM - 2)) * PITCH + (r - t) * 4 + t;
+                const C x0 = L[0], x1 = L[h], x2 = L[2 * h], x3 = L[3 * h];
+                const C w1 = tws[t * (M / h)];         // exp(2 pi i t / 2h)
+                const C w2 = tws[t * (M / (2 * h))];   // exp(2 pi i t / 4h)
+                const C y1 = cmul(w1, x1), y3 = cmul(w1, x3);
+                const C a0 = cadd(x0, y1), a1 = csub(x0, y1), a2 = cadd(x2, y3), a3 = csub(x2, y3);
+                const C y2 = cmul(w2, a2), y4 = cmul(w2, a3);
+                C iy4;   // exp(2 pi i (t + h) / 4h) = i w2
+                iy4.x = -y4.y;
+                iy4.y = y4.x;
+                L[0] = cadd(a0, y2);
+                L[2 * h] = csub(a0, y2);
+                L[h] = cadd(a1, iy4);
+                L[3 * h] = csub(a1, iy4);
+            }
+            __syncthreads();
+        }
+        // 3. round every degree
+        const R scale = (R)J.scale;
+        bool hit = false;
+        for (int u = threadIdx.x; u < P * M; u += kDecThreads) {
+            const int p = u >> LM, n = u & (M - 1);
+            const C v = zs[p * PITCH + n];
+            int top = -1;
+            R res = 0;
+            band_update<R>(v.x * scale, 2 * n, top, res);
+            band_update<R>(v.y * scale, 2 * n + 1, top, res);
+#pragma unroll
+            for (int o = 32; o > 0; o >>= 1) top = max(top, __shfl_xor(top, o, 64));
+            if ((threadIdx.x & 63) == 0 && top >= 0) atomicMax(&s_top[p], top);
+            run_max = fmaxf(run_max, (float)res);
+            hit |= (float)res >= band;
+        }
+        __syncthreads();
+        if (threadIdx.x < P && pixel_valid(threadIdx.x)) {
+            const int q = p0 + threadIdx.x, ly = q / T, lx = q - ly * T;
+            const int d = s_top[threadIdx.x] < 0 ? 0 : s_top[threadIdx.x];
+            gst(J.out)[(size_t)(ty * T + ly) * J.W + (tx * T + lx)] = J.op ? (J.L - 1 - d) : d;
+        }
+        // a wave whose degrees hit the band flags the tile (rare)
+        if (__any(hit) && (threadIdx.x & 63) == 0 && atomicCAS(&tile_flags[J.flag0 + tile], 0u, 1u) == 0u) {
+            if (J.fb_mode == kFbNone) {
+                atomicAdd(&st->pad, 1u);
+            } else {
+                const unsigned idx = atomicAdd(&st->fb_count, 1u);
+                fb_list[idx] = make_int2(S.job, tile);
+            }
+        }
+        __syncthreads();   // the rows and tops are rewritten by the next item
+    }
+    const float rm = block_max(run_max, s_red);
+    if (threadIdx.x == 0 && rm > 0.f) atomicMax(&st->max_res_bits, __float_as_uint(rm));
+}
+
 // Exact recompute of the tiles listed by the decode: FP64 transforms on
 // nt64-sized sub-tiles (LDS-resident up to 64, through this block's slab
 // beyond), each decoded from this block's slot.
@@ -796,12 +949,17 @@ __global__ void k_twiddles(double2 *tw64, TwF *tw32) {
 // DFT from the kept half of the bins (unscaled); degrees above nr/2 follow by
 // symmetry in the decode.
 __global__ void k_range_tables(int nr, int L, int bins, int dp, float2 *enc32, double2 *enc64, float2 *dec32,
-                               double2 *dec64) {
-    const long long ne = (long long)bins * L, nd = (long long)dp * dp;
-    for (long long q = blockIdx.x * (long long)blockDim.x + threadIdx.x; q < ne + nd;
+                               double2 *dec64, float2 *rtw32, double2 *rtw64) {
+    const long long ne = (long long)bins * L, nd = (long long)dp * dp, nw = nr / 2;
+    for (long long q = blockIdx.x * (long long)blockDim.x + threadIdx.x; q < ne + nd + nw;
          q += (long long)gridDim.x * blockDim.x) {
         double s, c;
-        if (q < ne) {
+        if (q >= ne + nd) {
+            const long long m = q - ne - nd;
+            sincospi(2.0 * (double)m / nr, &s, &c);
+            rtw64[m] = make_double2(c, s);
+            rtw32[m] = make_float2((float)c, (float)s);
+        } else if (q < ne) {
             const long long m = q / L, v = q % L;
             const long long ph = (v * m) % nr;
             sincospi(-2.0 * (double)ph / nr, &s, &c);
@@ -942,11 +1100,11 @@ hipError_t launch_twiddles(double2 *tw64, TwF *tw32, hipStream_t s) {
 }
 
 hipError_t launch_range_tables(int nr, int L, float2 *enc32, double2 *enc64, float2 *dec32, double2 *dec64,
-                               hipStream_t s) {
+                               float2 *rtw32, double2 *rtw64, hipStream_t s) {
     const int bins = nr / 2 + 1, dp = dec_pitch(nr);
-    const long long n = (long long)bins * L + (long long)dp * dp;
+    const long long n = (long long)bins * L + (long long)dp * dp + nr / 2;
     const int grid = (int)std::min<long long>((n + 255) / 256, 4096);
-    k_range_tables<<<grid, 256, 0, s>>>(nr, L, bins, dp, enc32, enc64, dec32, dec64);
+    k_range_tables<<<grid, 256, 0, s>>>(nr, L, bins, dp, enc32, enc64, dec32, dec64, rtw32, rtw64);
     return hipGetLastError();
 }
 
@@ -1020,6 +1178,27 @@ hipError_t launch_decode(int var, int dbl, const JobDev *jobs, const Seg *segs, 
                          int grid, float band, unsigned int *tile_flags, int2 *fb_list, StatsDev *st,
                          hipStream_t s) {
     if (nitems <= 0) return hipSuccess;
+    if (var >= kDecFftVar) {
+#define MD_DFFT(R, LM) \
+    k_decode_fft<R, LM><<<grid, kDecThreads, 0, s>>>(jobs, segs, nseg, nitems, band, tile_flags, fb_list, st); break
+        switch ((dbl ? 100 : 0) + var - kDecFftVar) {
+            case 6: MD_DFFT(float, 6);
+            case 7: MD_DFFT(float, 7);
+            case 8: MD_DFFT(float, 8);
+            case 9: MD_DFFT(float, 9);
+            case 10: MD_DFFT(float, 10);
+            case 11: MD_DFFT(float, 11);
+            case 106: MD_DFFT(double, 6);
+            case 107: MD_DFFT(double, 7);
+            case 108: MD_DFFT(double, 8);
+            case 109: MD_DFFT(double, 9);
+            case 110: MD_DFFT(double, 10);
+            case 111: MD_DFFT(double, 11);
+            default: return hipErrorInvalidValue;
+        }
+#undef MD_DFFT
+        return hipGetLastError();
+    }
 #define MD_DEC(R, V) \
     k_decode<R, V><<<grid, kDecThreads, 0, s>>>(jobs, segs, nseg, nitems, band, tile_flags, fb_list, st); break
     if (!dbl) {

@@ -81,6 +81,7 @@ struct JobDev {
     const void *enc;             // [bins][L]  exp(-2 pi i (v m mod nr) / nr)
     const void *dec;             // [dp][dp] w_m exp(+2 pi i d m / nr) for m, d < bins, zero beyond
     int dec_pitch;               // dp: bins rounded up to a multiple of 32
+    const void *rtw;             // [nr/2] exp(+2 pi i m / nr): twiddles of the range-axis FFT decode
     long long flag0;             // first entry of this job in the tile-flag array
     // exact recompute of ambiguous tiles
     int fb_mode;                 // kFbNone / kFbFFT64
@@ -136,8 +137,9 @@ struct StatsDev {
 // launchers (md_fft.hip, md_direct.hip); all enqueue on `s` and return the launch status
 // ---------------------------------------------------------------------------
 hipError_t launch_twiddles(double2 *tw64, TwF *tw32, hipStream_t s);
+// rtw32 / rtw64: nr/2 entries exp(+2 pi i m / nr)
 hipError_t launch_range_tables(int nr, int L, float2 *enc32, double2 *enc64, float2 *dec32,
-                               double2 *dec64, hipStream_t s);
+                               double2 *dec64, float2 *rtw32, double2 *rtw64, hipStream_t s);
 hipError_t launch_se_spectrum(const uint8_t *mask_d, const int32_t *off_d, int k, int nt, int nr,
                               const double2 *tw64, double2 *work, double2 *spec64, float2 *spec32,
                               hipStream_t s);
@@ -153,6 +155,13 @@ hipError_t launch_fft(int nt, int dbl, const JobDev *jobs, const Seg *segs, int 
 // decode kernel variant for a job's kept-bin count, and the zero-padded pitch
 // (both dimensions) of the [bin][degree] decode table for a range length
 int decode_group_variant(int bins, int dbl);
+// Range-axis FFT decode: used for power-of-two range lengths nr in
+// [kDecFftMinNr, kDecFftMaxNr]; its decode variant is kDecFftVar + log2(nr/2)
+// and one work item covers decode_fft_pixels(nr) pixels of a tile.
+constexpr int kDecFftVar = 16;
+constexpr int kDecFftMinNr = 128, kDecFftMaxNr = 4096;
+constexpr bool decode_uses_fft(int nr) { return nr >= kDecFftMinNr && nr <= kDecFftMaxNr && (nr & (nr - 1)) == 0; }
+constexpr int decode_fft_pixels(int nr) { return 8192 / nr; }
 int dec_pitch(int nr);
 hipError_t launch_decode(int var, int dbl, const JobDev *jobs, const Seg *segs, int nseg,
                          long long nitems, int grid, float band, unsigned int *tile_flags,

@@ -87,7 +87,7 @@ struct DevBuf {
 };
 
 struct RangeTables {
-    DevBuf enc32, enc64, dec32, dec64;
+    DevBuf enc32, enc64, dec32, dec64, rtw32, rtw64;
 };
 
 struct SESpec {
@@ -116,6 +116,7 @@ struct Plan {
     int dbl = 0;
     int nt = 0, T = 0, nr = 0, bins = 0, tiles_x = 0, tiles_y = 0;
     int fb_mode = kFbNone, nt64 = 0, T64 = 0;
+    bool dec_fft = false;          // range-axis FFT decode (decode_uses_fft(nr))
     double cost_fft = 0, cost_dir = 0;
 };
 
@@ -360,8 +361,10 @@ int get_range(int nr, int L, RangeTables **out) {
     MD_TRY(rt->enc64.ensure(ne * sizeof(double2)));
     MD_TRY(rt->dec32.ensure(nd * sizeof(float2)));
     MD_TRY(rt->dec64.ensure(nd * sizeof(double2)));
+    MD_TRY(rt->rtw32.ensure((size_t)(nr / 2 + 1) * sizeof(float2)));
+    MD_TRY(rt->rtw64.ensure((size_t)(nr / 2 + 1) * sizeof(double2)));
     MD_HIP(launch_range_tables(nr, L, (float2 *)rt->enc32.p, (double2 *)rt->enc64.p, (float2 *)rt->dec32.p,
-                               (double2 *)rt->dec64.p, g.stream));
+                               (double2 *)rt->dec64.p, (float2 *)rt->rtw32.p, (double2 *)rt->rtw64.p, g.stream));
     *out = rt.get();
     g.ranges[key] = std::move(rt);
     return MD_OK;
@@ -530,6 +533,19 @@ double dir_cost(const md_job &j, const SEData &se, int pack, bool lone = false) 
 }
 
 // Kept bins rounded up as the decode variant for that count accumulates them.
+double dec_padded_bins(int bins, int dbl);
+
+// Decode work per pixel in the dense decode's units (padded bins squared).
+// The range-axis FFT decode is priced at kDecFftRatio of those units per
+// nr log2 nr (measured on 2048^2 images, FP32 and FP64: 1.46 at nr = 128,
+// 1.24 at 256, 1.20 at 512, 1.13 at 1024).
+constexpr double kDecFftRatio = 1.3;
+double dec_units(int nr, int dbl) {
+    if (decode_uses_fft(nr)) return kDecFftRatio * nr * std::log2((double)nr);
+    const double pb = dec_padded_bins(nr / 2 + 1, dbl);
+    return pb * pb;
+}
+
 double dec_padded_bins(int bins, int dbl) {
     switch (decode_group_variant(bins, dbl)) {
         case 0: return 8;
@@ -786,10 +802,9 @@ double fft_cost(const md_job &j, int nt, int nr, int dbl, bool lone = false) {
     const int bins = nr / 2 + 1;
     const double item = g.cost.fft_item[dbl][ilog2i(nt)];
     if (item <= 0) return INFINITY;
-    const double pb = dec_padded_bins(bins, dbl);
     double items = (double)tiles * bins;
     if (lone) items = std::max(items, lone_items(nt, dbl));
-    return items * item + (double)tiles * T * T * pb * pb * g.cost.dec_unit[dbl];
+    return items * item + (double)tiles * T * T * dec_units(nr, dbl) * g.cost.dec_unit[dbl];
 }
 
 int plan_job(const md_job &j, const SEData &se, Plan &p, bool lone) {
@@ -814,23 +829,38 @@ int plan_job(const md_job &j, const SEData &se, Plan &p, bool lone) {
     }
     p = Plan();
     p.dbl = dbl;
-    p.nr = nr;
-    p.bins = dbl == kPrecNTT ? nr : nr / 2 + 1;
     const int form = direct_form((long long)(j.L - 1) + se.maxoff);
     const bool dir_ok = j.k <= kMaxDirectK;
     p.cost_dir = dir_ok ? dir_cost(j, se, form, lone) : INFINITY;
-    // transform plan: best spatial length by the cost model
-    double best = INFINITY;
-    int best_nt = 0;
-    const bool fft_ok = nr_min <= 4096 && se.ncells > 0 && ntt_ok;
-    for (int nt = 16; fft_ok && nt <= kMaxN; nt *= 2) {
-        if (g.opt.tile > 0 && nt != g.opt.tile) continue;
-        const double cst = fft_cost(j, nt, nr, dbl, lone);
-        if (cst < best) {
-            best = cst;
-            best_nt = nt;
-        }
+    // transform plan: best spatial length and, on the FP paths, range length
+    // by the cost model: the smallest range length (dense decode) or, past
+    // 256, the next power of two (range-axis FFT decode, at the price of more
+    // kept bins).  Up to 256 the dense decode of the smallest length is
+    // measured to cost no more than the FFT decode plus the extra bins (the
+    // calibrated dense unit, taken at about 12 bins, overprices 64 and more
+    // by 1.5-1.8x, so the model is not trusted there).
+    int nrs[2] = {nr, 0};
+    if (dbl != kPrecNTT && g.opt.nr <= 0 && nr > 256) {
+        int nr2 = 1;
+        while (nr2 < nr) nr2 <<= 1;
+        if (nr2 != nr && decode_uses_fft(nr2)) nrs[1] = nr2;
     }
+    double best = INFINITY;
+    int best_nt = 0, best_nr = nr;
+    const bool fft_ok = nr_min <= 4096 && se.ncells > 0 && ntt_ok;
+    for (int c = 0; c < 2 && nrs[c] > 0; ++c)
+        for (int nt = 16; fft_ok && nt <= kMaxN; nt *= 2) {
+            if (g.opt.tile > 0 && nt != g.opt.tile) continue;
+            const double cst = fft_cost(j, nt, nrs[c], dbl, lone);
+            if (cst < best) {
+                best = cst;
+                best_nt = nt;
+                best_nr = nrs[c];
+            }
+        }
+    p.nr = best_nr;
+    p.bins = dbl == kPrecNTT ? p.nr : p.nr / 2 + 1;
+    p.dec_fft = dbl != kPrecNTT && decode_uses_fft(p.nr);
     p.cost_fft = best;
     if (g.opt.path == kPathFFT) {
         if (!fft_ok)
@@ -994,6 +1024,7 @@ int build_exec(const md_job *jobs, int n, const std::vector<SEData> &ses, Exec &
         d.enc = p.dbl ? rt->enc64.p : rt->enc32.p;
         d.dec = p.dbl ? rt->dec64.p : rt->dec32.p;
         d.dec_pitch = dec_pitch(p.nr);
+        d.rtw = p.dbl ? rt->rtw64.p : rt->rtw32.p;
         d.flag0 = flag_total;
         flag_total += (long long)p.tiles_x * p.tiles_y;
         ex.fft_tiles += (long long)p.tiles_x * p.tiles_y;
@@ -1093,7 +1124,8 @@ int build_exec(const md_job *jobs, int n, const std::vector<SEData> &ses, Exec &
             s.job = i;
             s.tile0 = tile0;
             s.ntiles = nt_;
-            s.pblocks = (p.T * p.T + kDecThreads * kDecPixPerThread - 1) / (kDecThreads * kDecPixPerThread);
+            const int dpix = p.dec_fft ? decode_fft_pixels(p.nr) : kDecThreads * kDecPixPerThread;
+            s.pblocks = (p.T * p.T + dpix - 1) / dpix;
             s.y = (char *)ex.ybuf.p + off;
             off += per_tile * nt_;
             const bool ntt = p.dbl == kPrecNTT;
@@ -1108,7 +1140,8 @@ int build_exec(const md_job *jobs, int n, const std::vector<SEData> &ses, Exec &
             // exact: modular products (one per butterfly and per point)
             gf->alg_ops += ntt ? items * (N2 * log2(N2) + N2) : items * (2.0 * 5.0 * N2 * log2(N2) + 6.0 * N2);
             gf->units += items;
-            Group *gd = find_group(wv.dec, 0, p.dbl, ntt ? 0 : decode_group_variant(p.bins, p.dbl));
+            const int dvar = ntt ? 0 : p.dec_fft ? kDecFftVar + ilog2i(p.nr / 2) : decode_group_variant(p.bins, p.dbl);
+            Group *gd = find_group(wv.dec, 0, p.dbl, dvar);
             s.item0 = gd->nitems;
             gd->segs.push_back(s);
             gd->nitems += (long long)nt_ * s.pblocks;
@@ -1123,10 +1156,15 @@ int build_exec(const md_job *jobs, int n, const std::vector<SEData> &ses, Exec &
                 // one block of 8 degrees per pixel, over all n bins
                 gd->alg_ops += inside * p.nr * 8.0;
                 gd->units += (double)nt_ * TT * p.nr;
+            } else if (p.dec_fft) {
+                // packing (10 flops per point of the half-length transform)
+                // and a complex inverse FFT of length nr/2
+                const double h = p.nr / 2.0;
+                gd->alg_ops += inside * (5.0 * h * std::log2(h) + 10.0 * h);
+                gd->units += (double)nt_ * TT * dec_units(p.nr, p.dbl);
             } else {
                 gd->alg_ops += inside * p.nr * p.bins * 4.0;
-                const double pb = dec_padded_bins(p.bins, p.dbl);
-                gd->units += (double)nt_ * TT * pb * pb;
+                gd->units += (double)nt_ * TT * dec_units(p.nr, p.dbl);
             }
         }
         ex.waves.push_back(std::move(wv));
@@ -1164,7 +1202,13 @@ int build_exec(const md_job *jobs, int n, const std::vector<SEData> &ses, Exec &
                 ex.slabbufs.push_back(std::move(b));
             }
         }
-        for (auto &gr : wv.dec) place(gr, kDecThreads, 0);
+        for (auto &gr : wv.dec) {
+            // the range-axis FFT decode holds 4096 complex values and its M
+            // twiddles in LDS
+            const size_t elem = gr.dbl == kPrecFP64 ? sizeof(double2) : sizeof(float2);
+            const size_t lds = gr.big >= kDecFftVar ? (4096 + ((size_t)1 << (gr.big - kDecFftVar))) * elem : 0;
+            place(gr, kDecThreads, lds);
+        }
     }
     if (!all.empty()) MD_HIP(hipMemcpy(ex.segbuf.p, all.data(), all.size() * sizeof(Seg), hipMemcpyHostToDevice));
     // recompute resources

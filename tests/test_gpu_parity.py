@@ -258,6 +258,47 @@ def test_direct_packed_forms(dev):
             assert _direct_stage(job, dev) == [stage]
 
 
+def test_range_fft_decode(dev):
+    """Power-of-two range lengths from 128 to 4096 decode by a range-axis
+    FFT (even and odd coefficients from one complex inverse transform of
+    half length) instead of the dense inverse DFT.  Forced lengths in both
+    precisions, erosion, several tiles with ragged edges, and the exact
+    recompute of every tile (band 0), all bit-exact."""
+    rng = np.random.default_rng(41)
+    cases = [
+        # H, W, L, k, p, max_off, op, nr
+        (150, 203, 100, 7, 0.7, 27, 0, 128),
+        (97, 181, 200, 9, 0.6, 50, 1, 256),
+        (130, 140, 256, 15, 0.5, 255, 0, 512),
+        (70, 260, 900, 5, 0.8, 100, 1, 1024),
+        (40, 90, 1800, 3, 1.0, 200, 0, 2048),
+        (60, 70, 4000, 3, 1.0, 90, 0, 4096),
+    ]
+    for H, W, L, k, p, max_off, op, nr in cases:
+        job = _with_top(synthetic.random_job(rng, H, W, L, k, p=p, max_off=max_off, op=op), max_off)
+        want = oracle.run_job(job)
+        for opts in (FFT32, FFT64):
+            st = assert_parity(job, dev, want=want, nr=nr, **opts)
+            assert st["n_r"] == nr and st["max_residual"] < 0.25, st
+        assert_parity(job, dev, want=want, nr=nr, band=0.0, **FFT32)
+
+
+def test_planner_picks_fft_decode(dev):
+    """An 8-bit range (n_r >= 287) on the transform path: the planner prices
+    the smallest range length with the dense decode against the next power of
+    two with the FFT decode; either way the result is exact."""
+    rng = np.random.default_rng(43)
+    img = rng.integers(0, 256, (300, 280)).astype(np.int32)
+    mask = synthetic.disk_mask(31)
+    off = (rng.integers(0, 32, (31, 31)) * mask).astype(np.int32)
+    for op in (0, 1):
+        job = synthetic.Job(img, 256, mask, off, op, "octave_like_300x280_L256_disk31")
+        want = oracle.run_job(job)
+        for opts in (FFT32, FFT64):
+            st = assert_parity(job, dev, want=want, **opts)
+            assert st["n_r"] in (int((mask * off).max()) + 256, 512), st
+
+
 def test_large_se_fft_only(dev):
     """SEs beyond the direct window's limit (k > 127) go through the FFT path
     with spatial tiles larger than the LDS (256 to 1024 points per side)."""
