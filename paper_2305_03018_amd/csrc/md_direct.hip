@@ -63,7 +63,6 @@ __device__ __forceinline__ int dir_stage(const JobDev &J, const int32_t *slice, 
     const auto img = gld(slice);
     const int H = J.H, W = J.W, L = J.L, op = J.op;
     constexpr bool PACK = FMT != 0;
-    const int neg = PACK ? kNeg16 : kNeg;
     int badv = 0;
     for (int a0 = (threadIdx.x >> 6) * RB; a0 < TH; a0 += (kDirThreads / 64) * RB) {
         int raw[RB][4];
@@ -79,22 +78,51 @@ __device__ __forceinline__ int dir_stage(const JobDev &J, const int32_t *slice, 
             }
         }
         __builtin_amdgcn_sched_barrier(0);
+        // grey value of staged pixel (h, u): clamped, complemented for
+        // erosion; the caller's minus infinity outside the image
+        auto value = [&](int h, int u) {
+            int v = raw[h][u];
+            badv |= (int)(in[h][u] && (unsigned)v >= (unsigned)L);
+            v = min(max(v, 0), L - 1);
+            return op ? L - 1 - v : v;
+        };
+        if constexpr (PACK) {
+            // rows a, a+1 (a even) are the two halves of one LDS word: one
+            // conversion of the pair and one 32-bit store.  TH is even, so
+            // the pair is wholly inside the block or wholly outside.
+            static_assert(RB % 2 == 0, "row pairs");
 #pragma unroll
-        for (int h = 0; h < RB; ++h) {
-            const int a = a0 + h;
+            for (int h = 0; h < RB; h += 2) {
+                const int a = a0 + h;
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                const int c = lane + 64 * u;
-                int v = raw[h][u];
-                badv |= (int)(in[h][u] && (unsigned)v >= (unsigned)L);
-                v = min(max(v, 0), L - 1);
-                v = op ? L - 1 - v : v;
-                v = in[h][u] ? v : neg;
-                if (a < TH && c < pitch) {
-                    short hw = (short)v;
-                    if (FMT == 2) hw = in[h][u] ? __builtin_bit_cast(short, (_Float16)v) : (short)kNegF16;
-                    if (PACK) ((short *)tile)[2 * ((a >> 1) * pitch + c) + (a & 1)] = hw;
-                    else tile[a * pitch + c] = v;
+                for (int u = 0; u < 4; ++u) {
+                    const int c = lane + 64 * u;
+                    const int v0 = value(h, u), v1 = value(h + 1, u);
+                    if (a < TH && c < pitch) {
+                        unsigned w;
+                        if constexpr (FMT == 2) {
+                            // integers of magnitude <= 2048: exact under any rounding
+                            const float f0 = in[h][u] ? (float)v0 : -__builtin_inff();
+                            const float f1 = in[h + 1][u] ? (float)v1 : -__builtin_inff();
+                            w = __builtin_bit_cast(unsigned, __builtin_amdgcn_cvt_pkrtz(f0, f1));
+                        } else {
+                            const unsigned lo = (unsigned)(in[h][u] ? v0 : kNeg16) & 0xffffu;
+                            const unsigned hi = (unsigned)(in[h + 1][u] ? v1 : kNeg16) & 0xffffu;
+                            w = lo | hi << 16;
+                        }
+                        tile[(a >> 1) * pitch + c] = (int32_t)w;
+                    }
+                }
+            }
+        } else {
+#pragma unroll
+            for (int h = 0; h < RB; ++h) {
+                const int a = a0 + h;
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const int c = lane + 64 * u;
+                    const int v = value(h, u);
+                    if (a < TH && c < pitch) tile[a * pitch + c] = in[h][u] ? v : kNeg;
                 }
             }
         }
