@@ -376,7 +376,7 @@ __device__ __forceinline__ void fft_tile_bin(typename Cx<R>::T *lds, const int32
                                              int W, int L, int op, int k, int oy0, int ox0,
                                              const typename Cx<R>::T *__restrict__ enc_m,
                                              const typename Cx<R>::T *__restrict__ spec_m,
-                                             typename Cx<R>::T *__restrict__ ydst,
+                                             typename Cx<R>::T *__restrict__ ydst, int ybs,
                                              const typename TwSel<R>::T &tw, unsigned int *range_err) {
     using C = typename Cx<R>::T;
     constexpr int P = N + 1, LG = ilog2c(N);
@@ -405,12 +405,12 @@ __device__ __forceinline__ void fft_tile_bin(typename Cx<R>::T *lds, const int32
         // order and scatter within the output row
         for (int q = threadIdx.x; q < T * N; q += BS) {
             const int i = (q >> LG) + (k - 1), b = q & (N - 1), j = brev<LG>(b);
-            if (j >= k - 1) stg(ydst, (size_t)(i - (k - 1)) * T + (j - (k - 1)), lds[brev<LG>(i) * P + b]);
+            if (j >= k - 1) stg(ydst, ypix((size_t)(i - (k - 1)) * T + (j - (k - 1)), ybs), lds[brev<LG>(i) * P + b]);
         }
     } else {
         for (int q = threadIdx.x; q < T * T; q += BS) {
             const int i = q / T + (k - 1), j = q % T + (k - 1);
-            stg(ydst, q, lds[brev<LG>(i) * P + brev<LG>(j)]);
+            stg(ydst, ypix(q, ybs), lds[brev<LG>(i) * P + brev<LG>(j)]);
         }
     }
     __syncthreads();
@@ -436,7 +436,7 @@ __device__ __forceinline__ void fft_big_tile_bin(typename Cx<R>::T *lds, typenam
                                                  const int32_t *__restrict__ img, int H, int W, int L, int op,
                                                  int k, int oy0, int ox0, const typename Cx<R>::T *__restrict__ enc_m,
                                                  const typename Cx<R>::T *__restrict__ spec_m,
-                                                 typename Cx<R>::T *__restrict__ ydst,
+                                                 typename Cx<R>::T *__restrict__ ydst, int ybs,
                                                  const typename TwSel<R>::T &tw, unsigned int *range_err) {
     using C = typename Cx<R>::T;
     constexpr int LB = big_lines<R, N>();
@@ -494,13 +494,14 @@ __device__ __forceinline__ void fft_big_tile_bin(typename Cx<R>::T *lds, typenam
             for (int q = threadIdx.x; q < LB * N; q += BS) {
                 const int l = q >> LG, b = q & (N - 1);
                 const int y = brev<LG>(rb + l), x = brev<LG>(b);
-                if (y >= k - 1 && x >= k - 1) stg(ydst, (size_t)(y - (k - 1)) * T + (x - (k - 1)), lds[l * P + b]);
+                if (y >= k - 1 && x >= k - 1)
+                    stg(ydst, ypix((size_t)(y - (k - 1)) * T + (x - (k - 1)), ybs), lds[l * P + b]);
             }
         } else {
             for (int q = threadIdx.x; q < LB * T; q += BS) {
                 const int l = q / T, xo = q - l * T;
                 const int y = brev<LG>(rb + l);
-                if (y >= k - 1) stg(ydst, (size_t)(y - (k - 1)) * T + xo, lds[l * P + brev<LG>(xo + k - 1)]);
+                if (y >= k - 1) stg(ydst, ypix((size_t)(y - (k - 1)) * T + xo, ybs), lds[l * P + brev<LG>(xo + k - 1)]);
             }
         }
         __syncthreads();
@@ -523,11 +524,10 @@ __global__ __launch_bounds__(BS) void k_fft(const JobDev *__restrict__ jobs, con
         const int m = (int)(local / S.ntiles), tl = (int)(local % S.ntiles);
         const int tile = S.tile0 + tl;
         const int ty = tile / J.tiles_x, tx = tile - ty * J.tiles_x;
-        const size_t TT = (size_t)J.T * J.T;
-        C *ydst = (C *)S.y + ((size_t)tl * J.bins + m) * TT;
+        C *ydst = (C *)S.y + (size_t)tl * ytile_elems(J.bins, J.T, J.ybs) + ybin_offset(m, J.T, J.ybs);
         fft_tile_bin<R, N, BS>(lds, J.img, J.H, J.W, J.L, J.op, J.k, ty * J.T, tx * J.T,
                                (const C *)J.enc + (size_t)m * J.L, (const C *)J.se_spec + (size_t)m * N * N,
-                               ydst, tw, m == 0 ? &st->range_err : nullptr);
+                               ydst, J.ybs, tw, m == 0 ? &st->range_err : nullptr);
     }
 }
 
@@ -554,11 +554,10 @@ __global__ __launch_bounds__(BS) void k_fft_big(const JobDev *__restrict__ jobs,
         const int m = (int)(local / S.ntiles), tl = (int)(local % S.ntiles);
         const int tile = S.tile0 + tl;
         const int ty = tile / J.tiles_x, tx = tile - ty * J.tiles_x;
-        const size_t TT = (size_t)J.T * J.T;
-        C *ydst = (C *)S.y + ((size_t)tl * J.bins + m) * TT;
+        C *ydst = (C *)S.y + (size_t)tl * ytile_elems(J.bins, J.T, J.ybs) + ybin_offset(m, J.T, J.ybs);
         fft_big_tile_bin<R, N, BS>(lds, slab, J.img, J.H, J.W, J.L, J.op, J.k, ty * J.T, tx * J.T,
                                    (const C *)J.enc + (size_t)m * J.L, (const C *)J.se_spec + (size_t)m * N * N, ydst,
-                                   tw, m == 0 ? &st->range_err : nullptr);
+                                   J.ybs, tw, m == 0 ? &st->range_err : nullptr);
     }
 }
 
@@ -575,7 +574,7 @@ __global__ __launch_bounds__(BS) void k_fft_big(const JobDev *__restrict__ jobs,
 // With bins <= MB and nr/2 < DC one pass covers the pixel and its bin values
 // are loaded once.
 template <typename R, int MB, int DC>
-__device__ __forceinline__ void decode_px(const typename Cx<R>::T *X, size_t mstride, int p, bool valid,
+__device__ __forceinline__ void decode_px(const typename Cx<R>::T *X, size_t mstride, size_t p, bool valid,
                                           const typename Cx<R>::T *dec, int dp, int nr, int bins, R scale, int &top,
                                           R &res) {
     using C = typename Cx<R>::T;
@@ -625,7 +624,7 @@ __host__ __device__ constexpr int decode_variant(int bins, int dbl) {
 }
 
 template <typename R, int V>
-__device__ __forceinline__ void decode_var(const typename Cx<R>::T *X, size_t mstride, int p, bool valid,
+__device__ __forceinline__ void decode_var(const typename Cx<R>::T *X, size_t mstride, size_t p, bool valid,
                                            const typename Cx<R>::T *dec, int dp, int nr, int bins, R scale, int &top,
                                            R &res) {
     if constexpr (V == kDec8) decode_px<R, 8, 8>(X, mstride, p, valid, dec, dp, nr, bins, scale, top, res);
@@ -671,7 +670,8 @@ __global__ __launch_bounds__(kDecThreads) void k_decode(const JobDev *__restrict
         const int T = J.T;
         const int ty = tile / J.tiles_x, tx = tile - ty * J.tiles_x;
         const size_t TT = (size_t)T * T;
-        const C *X = (const C *)S.y + (size_t)tl * J.bins * TT;
+        const C *X = (const C *)S.y + (size_t)tl * ytile_elems(J.bins, T, J.ybs);
+        const size_t mstride = J.ybs ? 16 : TT;   // between bins of one pixel
         bool hit = false;
         // kDecPixPerThread pixels per thread per item amortise the item setup
 #pragma unroll 1
@@ -682,7 +682,8 @@ __global__ __launch_bounds__(kDecThreads) void k_decode(const JobDev *__restrict
             const bool valid = p < (int)TT && gy < J.H && gx < J.W;
             int top;
             R res;
-            decode_var<R, V>(X, TT, p, valid, (const C *)J.dec, J.dec_pitch, J.nr, J.bins, (R)J.scale, top, res);
+            decode_var<R, V>(X, mstride, ypix(p, J.ybs), valid, (const C *)J.dec, J.dec_pitch, J.nr, J.bins,
+                             (R)J.scale, top, res);
             if (valid) {
                 const int d = top < 0 ? 0 : top;
                 gst(J.out)[(size_t)gy * J.W + gx] = J.op ? (J.L - 1 - d) : d;
@@ -749,41 +750,49 @@ __global__ __launch_bounds__(kDecThreads) void k_decode_fft(const JobDev *__rest
         const int tile = S.tile0 + tl;
         const int T = J.T, TT = T * T;
         const int ty = tile / J.tiles_x, tx = tile - ty * J.tiles_x;
-        const C *X = (const C *)S.y + (size_t)tl * J.bins * TT;
+        const C *X = (const C *)S.y + (size_t)tl * ytile_elems(J.bins, T, J.ybs);
         const int p0 = pb * P;
         auto pixel_valid = [&](int p) {
             const int q = p0 + p, ly = q / T, lx = q - ly * T;
             return q < TT && ty * T + ly < J.H && tx * T + lx < J.W;
         };
-        // 1. packed spectra (zero outside the image), bit-reversed per row;
-        // the loads of CH points per thread go out before any is used (the
-        // bins of one pixel lie T*T apart, so each load is its own burst)
-        constexpr int CH = 4, NPT = P * M / kDecThreads;
-        static_assert(NPT % CH == 0, "whole batches per thread");
+        // 1. packed spectra (zero outside the image), bit-reversed per row.
+        // One thread takes the bin pair (X_j, X_{M-j}), j <= M/2, and writes
+        // both Z_j and Z_{M-j} (Z_0 alone for j = 0, whose partner is X_M;
+        // Z_{M/2} once); the loads of CH pairs go out before any is used
+        // (the bins of one pixel lie T*T apart, so each load is its own
+        // burst).
+        constexpr int CH = 4, NJ = M / 2 + 1;
         const bool pv = pixel_valid(threadIdx.x & (P - 1));   // the same pixel in every batch
-        for (int u0 = threadIdx.x; u0 < P * M; u0 += CH * kDecThreads) {
+        for (int u0 = threadIdx.x; u0 < P * NJ; u0 += CH * kDecThreads) {
             C a[CH], b[CH];
 #pragma unroll
             for (int e = 0; e < CH; ++e) {
-                const int u = u0 + e * kDecThreads, p = u & (P - 1), k = u >> LP;
+                const int u = u0 + e * kDecThreads, p = u & (P - 1), j = u >> LP;
                 a[e] = b[e] = czero<C>();
-                if (pv) {
-                    a[e] = ldg(X, (size_t)k * TT + p0 + p);
-                    b[e] = ldg(X, (size_t)(M - k) * TT + p0 + p);
+                if (pv && j < NJ) {
+                    const size_t q = ypix(p0 + p, J.ybs);
+                    a[e] = ldg(X, ybin_offset(j, T, J.ybs) + q);
+                    b[e] = ldg(X, ybin_offset(M - j, T, J.ybs) + q);
                 }
             }
             __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
             for (int e = 0; e < CH; ++e) {
-                const int u = u0 + e * kDecThreads, p = u & (P - 1), k = u >> LP;
-                const C w = tws[k];
-                const R ex = a[e].x + b[e].x, ey = a[e].y - b[e].y;   // a + conj(b)
-                const R ox = a[e].x - b[e].x, oy = a[e].y + b[e].y;   // a - conj(b)
-                const R wx = w.x * ox - w.y * oy, wy = w.x * oy + w.y * ox;
-                C zv;
-                zv.x = ex - wy;   // e + i (w^k o)
-                zv.y = ey + wx;
-                zs[p * PITCH + brev<LM>(k)] = zv;
+                const int u = u0 + e * kDecThreads, p = u & (P - 1), j = u >> LP;
+                if (j >= NJ) continue;
+                // Z_k from (x, y) = (X_k, X_{M-k}): (x + conj y) + i w^k (x - conj y)
+                auto pack = [&](C x, C y, int kk) {
+                    const C w = tws[kk];
+                    const R ox = x.x - y.x, oy = x.y + y.y;
+                    const R wx = w.x * ox - w.y * oy, wy = w.x * oy + w.y * ox;
+                    C zv;
+                    zv.x = x.x + y.x - wy;
+                    zv.y = x.y - y.y + wx;
+                    zs[p * PITCH + brev<LM>(kk)] = zv;
+                };
+                pack(a[e], b[e], j);
+                if (j > 0 && j < M / 2) pack(b[e], a[e], M - j);
             }
         }
         if (threadIdx.x < P) s_top[threadIdx.x] = -1;
@@ -820,21 +829,28 @@ __global__ __launch_bounds__(kDecThreads) void k_decode_fft(const JobDev *__rest
             }
             __syncthreads();
         }
-        // 3. round every degree
+        // 3. round every degree: G = kDecThreads / P threads per pixel, each
+        // taking every G-th point (consecutive lanes read consecutive words)
+        // and keeping its top degree in a register; one shuffle reduction
+        // per pixel, then one LDS maximum per pixel (per wave when a pixel
+        // spans several waves)
+        constexpr int G = kDecThreads / P, GW = G < 64 ? G : 64;
         const R scale = (R)J.scale;
         bool hit = false;
-        for (int u = threadIdx.x; u < P * M; u += kDecThreads) {
-            const int p = u >> LM, n = u & (M - 1);
-            const C v = zs[p * PITCH + n];
+        {
+            const int p = threadIdx.x / G, t = threadIdx.x & (G - 1);
             int top = -1;
             R res = 0;
-            band_update<R>(v.x * scale, 2 * n, top, res);
-            band_update<R>(v.y * scale, 2 * n + 1, top, res);
+            for (int n = t; n < M; n += G) {
+                const C v = zs[p * PITCH + n];
+                band_update<R>(v.x * scale, 2 * n, top, res);
+                band_update<R>(v.y * scale, 2 * n + 1, top, res);
+            }
 #pragma unroll
-            for (int o = 32; o > 0; o >>= 1) top = max(top, __shfl_xor(top, o, 64));
-            if ((threadIdx.x & 63) == 0 && top >= 0) atomicMax(&s_top[p], top);
+            for (int o = GW / 2; o > 0; o >>= 1) top = max(top, __shfl_xor(top, o, 64));
+            if ((t & (GW - 1)) == 0 && top >= 0) atomicMax(&s_top[p], top);
             run_max = fmaxf(run_max, (float)res);
-            hit |= (float)res >= band;
+            hit = (float)res >= band;
         }
         __syncthreads();
         if (threadIdx.x < P && pixel_valid(threadIdx.x)) {
@@ -889,12 +905,12 @@ __global__ __launch_bounds__(kDecThreads) void k_fallback(const JobDev *__restri
                     if constexpr (BIG)
                         fft_big_tile_bin<double, N, kDecThreads>(lds, slab, J.img, J.H, J.W, J.L, J.op, J.k, oy0 + sy,
                                                                  ox0 + sx, J.enc64 + (size_t)m * J.L,
-                                                                 J.se_spec64 + (size_t)m * N * N, slot + m * TT, tw,
-                                                                 nullptr);
+                                                                 J.se_spec64 + (size_t)m * N * N, slot + m * TT, 0,
+                                                                 tw, nullptr);
                     else
                         fft_tile_bin<double, N, kDecThreads>(lds, J.img, J.H, J.W, J.L, J.op, J.k, oy0 + sy, ox0 + sx,
                                                              J.enc64 + (size_t)m * J.L, J.se_spec64 + (size_t)m * N * N,
-                                                             slot + m * TT, tw, nullptr);
+                                                             slot + m * TT, 0, tw, nullptr);
                 }
                 const int sh = min(T64, oh - sy), sw = min(T64, ow - sx);
                 for (int p0 = 0; p0 < (int)TT; p0 += kDecThreads) {

@@ -82,6 +82,8 @@ struct JobDev {
     const void *dec;             // [dp][dp] w_m exp(+2 pi i d m / nr) for m, d < bins, zero beyond
     int dec_pitch;               // dp: bins rounded up to a multiple of 32
     const void *rtw;             // [nr/2] exp(+2 pi i m / nr): twiddles of the range-axis FFT decode
+    int ybs;                     // transform-domain layout of a tile: 0 = [bins][T*T]; else blocks of
+                                 // 16 pixels, [ceil(T*T/16)][bins][16], and ybs = bins * 16
     long long flag0;             // first entry of this job in the tile-flag array
     // exact recompute of ambiguous tiles
     int fb_mode;                 // kFbNone / kFbFFT64
@@ -125,6 +127,15 @@ struct Seg {
     int pblocks;                 // decode: ceil(T*T / (kDecThreads * kDecPixPerThread))
     void *y;                     // transform-domain buffer [ntiles][bins][T*T]
 };
+
+// Transform-domain elements of one tile, and the position of (bin m, pixel q)
+// in it, for either layout (JobDev::ybs).
+__host__ __device__ inline size_t ytile_elems(int bins, int T, int ybs) {
+    const size_t TT = (size_t)T * T;
+    return ybs ? (TT + 15) / 16 * (size_t)ybs : (size_t)bins * TT;
+}
+__host__ __device__ inline size_t ybin_offset(int m, int T, int ybs) { return ybs ? (size_t)m * 16 : (size_t)m * T * T; }
+__host__ __device__ inline size_t ypix(size_t q, int ybs) { return ybs ? (q >> 4) * (size_t)ybs + (q & 15) : q; }
 
 struct StatsDev {
     unsigned int max_res_bits;   // float bits of the largest rounding residual

@@ -535,6 +535,11 @@ double dir_cost(const md_job &j, const SEData &se, int pack, bool lone = false) 
 // Kept bins rounded up as the decode variant for that count accumulates them.
 double dec_padded_bins(int bins, int dbl);
 
+// Transform-domain layout of a plan's tiles (JobDev::ybs): blocks of 16
+// pixels with their bins contiguous for the range-axis FFT decode, which
+// reads all bins of a few pixels; bin-major otherwise.
+int plan_ybs(const Plan &p) { return p.dec_fft ? p.bins * 16 : 0; }
+
 // Decode work per pixel in the dense decode's units (padded bins squared).
 // The range-axis FFT decode is priced at kDecFftRatio of those units per
 // nr log2 nr (measured on 2048^2 images, FP32 and FP64: 1.46 at nr = 128,
@@ -1025,6 +1030,7 @@ int build_exec(const md_job *jobs, int n, const std::vector<SEData> &ses, Exec &
         d.dec = p.dbl ? rt->dec64.p : rt->dec32.p;
         d.dec_pitch = dec_pitch(p.nr);
         d.rtw = p.dbl ? rt->rtw64.p : rt->rtw32.p;
+        d.ybs = plan_ybs(p);
         d.flag0 = flag_total;
         flag_total += (long long)p.tiles_x * p.tiles_y;
         ex.fft_tiles += (long long)p.tiles_x * p.tiles_y;
@@ -1090,7 +1096,7 @@ int build_exec(const md_job *jobs, int n, const std::vector<SEData> &ses, Exec &
     for (int i = 0; i < n; ++i) {
         const Plan &p = ex.plans[i];
         if (p.path != kPathFFT) continue;
-        const size_t per_tile = (size_t)p.bins * p.T * p.T * elem_bytes(p.dbl);
+        const size_t per_tile = ytile_elems(p.bins, p.T, plan_ybs(p)) * elem_bytes(p.dbl);
         const int ntiles = p.tiles_x * p.tiles_y;
         int t = 0;
         while (t < ntiles) {
@@ -1119,7 +1125,7 @@ int build_exec(const md_job *jobs, int n, const std::vector<SEData> &ses, Exec &
         for (auto &ch : wave_chunks[w]) {
             const int i = ch.first, tile0 = ch.second.first, nt_ = ch.second.second;
             const Plan &p = ex.plans[i];
-            const size_t per_tile = (size_t)p.bins * p.T * p.T * elem_bytes(p.dbl);
+            const size_t per_tile = ytile_elems(p.bins, p.T, plan_ybs(p)) * elem_bytes(p.dbl);
             Seg s{};
             s.job = i;
             s.tile0 = tile0;
@@ -2532,11 +2538,17 @@ int md_debug_tile_values(const int32_t *img, int H, int W, int L, const uint8_t 
         const int tile = ty * p.tiles_x + tx;
         const Seg &s = ex.waves[0].fft[0].segs[0];
         const size_t TT = (size_t)p.T * p.T, n = (size_t)p.bins * TT;
+        const int ybs = plan_ybs(p);
+        const size_t nt_elems = ytile_elems(p.bins, p.T, ybs);
         const double sc = 1.0 / ((double)p.nt * p.nt);
         const size_t esz = elem_bytes(p.dbl);
-        std::vector<char> h(n * esz);
-        const char *src = (const char *)s.y + (size_t)(tile - s.tile0) * n * esz;
-        if (hipMemcpy(h.data(), src, n * esz, hipMemcpyDeviceToHost) != hipSuccess) { rc = fail(MD_ERR_DEVICE, "copy failed"); break; }
+        std::vector<char> hb(nt_elems * esz), h(n * esz);
+        const char *src = (const char *)s.y + (size_t)(tile - s.tile0) * nt_elems * esz;
+        if (hipMemcpy(hb.data(), src, nt_elems * esz, hipMemcpyDeviceToHost) != hipSuccess) { rc = fail(MD_ERR_DEVICE, "copy failed"); break; }
+        for (int m = 0; m < p.bins; ++m)   // bin-major, whatever the device layout
+            for (size_t q = 0; q < TT; ++q)
+                memcpy(h.data() + ((size_t)m * TT + q) * esz, hb.data() + (ybin_offset(m, p.T, ybs) + ypix(q, ybs)) * esz,
+                       esz);
         for (size_t q = 0; q < n; ++q) {
             if (p.dbl == kPrecNTT) {   // residues mod p, already scaled by n_t^-2
                 dst[2 * q] = ((const uint32_t *)h.data())[q];

@@ -367,12 +367,16 @@ def test_errors(dev):
 # ----------------------------------------------------------------------------
 # transform-domain values against the FP64 reference
 # ----------------------------------------------------------------------------
-def test_spectrum_error_report(dev):
+@pytest.mark.parametrize("nr", [24, 128])
+def test_spectrum_error_report(dev, nr):
+    """Transform-domain values of one tile against the DFT of the oracle's
+    exact coefficients; at a power-of-two range length the tile is stored in
+    blocks of 16 pixels (the FFT decode's layout) and read back bin-major."""
     import torch
 
     job = synthetic.blurred_512(0)
     img = torch.from_numpy(job.img).to(dev)
-    nt, nr = 64, 24
+    nt = 64
     T = nt - job.k + 1
     ty, tx = 2, 3
     ys, xs = np.divmod(np.arange(T * T), T)
