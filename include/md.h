@@ -86,7 +86,11 @@ typedef enum {
                               a power of two in [8, 1024] (images use 16 and
                               up, volumes 8, 16 or 32)                           */
     MD_OPT_NR = 4,         /* 0: auto, else the range-axis DFT length; must be at
-                              least (L-1) + max offset + 1                       */
+                              least (L-1) + max offset + 1.  FP paths decode a
+                              power-of-two length from 128 to 4096 by an FFT
+                              along the range axis, any other by a dense DFT;
+                              auto weighs the smallest length against the next
+                              power of two once the smallest passes 256         */
     MD_OPT_SYNC = 5,       /* 1 (default): wait for completion in every call    */
     MD_OPT_GRAPH = 6,      /* 1 (default): md_dilate_batch captures its launches
                               in a HIP graph per batch signature and replays it  */
@@ -277,8 +281,12 @@ int md_release(void);
  * the library's stream, synchronised calls only).  `alg_bytes` / `alg_ops`
  * are the algorithmic DRAM bytes and arithmetic operations the stage has to
  * perform for the work it was given (the figures a roofline is drawn with),
- * summed over its launches.  Stage names: "fft32_nN", "fft64_nN",
- * "decode32", "decode64", "direct", "recompute64_nN", "recompute_direct". */
+ * summed over its launches.  Stage names: transforms "fft32_nN",
+ * "fft64_nN", "ntt_nN" (images) and "ntt3_nN" (volumes); decodes
+ * "decode32", "decode64", "decode_ntt", "decode_ntt3"; exact recompute
+ * "recompute64_nN"; direct window "direct16" (packed f16), "direct16i"
+ * (packed int16), "direct32", and for volumes "direct3_16", "direct3_16i",
+ * "direct3_32". */
 typedef struct {
     char name[32];
     double ms;                /* summed event time                        */
