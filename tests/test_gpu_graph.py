@@ -4,7 +4,8 @@ the replays and new image contents and output buffers each time; every
 replay is checked against the oracle.  Covers the direct window, the FP32
 transform path, the exact recompute (band 0 sends every tile through it, so
 the device-built recompute list and its counters are reset and rebuilt
-inside the graph at every replay) and the exact mod-p path."""
+inside the graph at every replay), the exact mod-p path and the range-axis
+FFT decode in both precisions."""
 import numpy as np
 import pytest
 
@@ -31,14 +32,23 @@ def batch_jobs(rng):
             for i, (H, W, L, k) in enumerate(shapes)]
 
 
-@pytest.mark.parametrize("mode", ["auto", "fft32", "recompute_all", "ntt", "direct"])
+def fft_decode_jobs(rng):
+    """Range lengths 128 and 512 (forced below): the range-axis FFT decode and
+    its pixel-block layout of the transform-domain tiles."""
+    return [synthetic.random_job(rng, 150, 170, 100, 7, p=0.7, max_off=27, op=0),
+            synthetic.random_job(rng, 90, 260, 256, 15, p=0.5, max_off=255, op=1)]
+
+
+@pytest.mark.parametrize("mode", ["auto", "fft32", "recompute_all", "ntt", "direct", "fft_decode32",
+                                  "fft_decode64"])
 def test_graph_replays(dev, mode):
     import torch
 
     opts = {"auto": {}, "fft32": dict(precision=0, path=1), "recompute_all": dict(precision=0, path=1, band=0.0),
-            "ntt": dict(precision=2, path=1), "direct": dict(path=2)}[mode]
+            "ntt": dict(precision=2, path=1), "direct": dict(path=2),
+            "fft_decode32": dict(precision=0, path=1, nr=512), "fft_decode64": dict(precision=1, path=1, nr=512)}[mode]
     rng = np.random.default_rng(71)
-    jobs = batch_jobs(rng)
+    jobs = fft_decode_jobs(rng) if mode.startswith("fft_decode") else batch_jobs(rng)
     imgs = [torch.from_numpy(j.img).to(dev) for j in jobs]
     side = torch.randn(512, 512, device=dev)
     stream = torch.cuda.Stream()   # graphs are captured on a non-default stream only
