@@ -497,3 +497,31 @@ def test_uneven_batch_256(dev, mode):
         md.dilate_batch([(im, j.mask, j.off, j.L, j.op) for im, j in zip(imgs, jobs)], outs=outs2)
         for a, b in zip(outs, outs2):
             assert torch.equal(a, b)
+
+
+@pytest.mark.parametrize("mode", ["auto", "fft32", "direct"])
+def test_many_tiny_jobs(dev, mode):
+    """1500 jobs of 1x1 to 40x40 pixels in one batch call: segment tables
+    and their binary search over many short segments, a graph with many
+    segments, k from 1 to 9, L from 2 to 300, both operations, masks that
+    can be empty; every job exact."""
+    import torch
+
+    rng = np.random.default_rng(77)
+    jobs = []
+    for i in range(1500):
+        H, W = (int(v) for v in rng.integers(1, 41, 2))
+        L = int(rng.choice([2, 5, 16, 64, 300]))
+        k = int(rng.integers(0, 5)) * 2 + 1
+        jobs.append(synthetic.random_job(rng, H, W, L, k, p=float(rng.choice([0.0, 0.4, 1.0])),
+                                         max_off=int(rng.integers(0, 8)), op=i % 2))
+    if mode == "fft32":   # the transform path needs at least one SE cell
+        jobs = [j for j in jobs if j.mask.any()]
+    opts = {"auto": {}, "fft32": FFT32, "direct": DIRECT}[mode]
+    imgs = [torch.from_numpy(j.img).to(dev) for j in jobs]
+    _say(f"  {len(jobs)} tiny jobs mode={mode}")
+    with md.options(**opts):
+        outs = md.dilate_batch([(im, j.mask, j.off, j.L, j.op) for im, j in zip(imgs, jobs)])
+    for q, (j, o) in enumerate(zip(jobs, outs)):
+        got, want = o.cpu().numpy(), oracle.run_job(j)
+        assert np.array_equal(got, want), f"{mode} job {q} ({j.name}, op {j.op}): {int((got != want).sum())} differ"
