@@ -134,6 +134,8 @@ def kernel_of(stage):
         return "k_ntt_decode"
     if stage.startswith("ntt"):
         return f"k_ntt<{stage.split('_n')[1]}>"
+    if stage in ("decode32_fft", "decode64_fft"):
+        return f"k_decode_fft<{'float' if stage == 'decode32_fft' else 'double'}>"
     if stage.startswith("decode"):
         return f"k_decode<{'float' if stage == 'decode32' else 'double'}>"
     if stage.startswith("recompute64"):

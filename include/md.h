@@ -283,7 +283,8 @@ int md_release(void);
  * perform for the work it was given (the figures a roofline is drawn with),
  * summed over its launches.  Stage names: transforms "fft32_nN",
  * "fft64_nN", "ntt_nN" (images) and "ntt3_nN" (volumes); decodes
- * "decode32", "decode64", "decode_ntt", "decode_ntt3"; exact recompute
+ * "decode32", "decode64" (dense), "decode32_fft", "decode64_fft" (range-axis
+ * FFT), "decode_ntt", "decode_ntt3"; exact recompute
  * "recompute64_nN"; direct window "direct16" (packed f16), "direct16i"
  * (packed int16), "direct32", and for volumes "direct3_16", "direct3_16i",
  * "direct3_32". */

@@ -1366,7 +1366,9 @@ int enqueue(Exec &ex, hipStream_t s, bool skip_decode = false, bool capturing = 
                 ps.done();
                 continue;
             }
-            ProfScope ps(prof, s, gr.dbl ? "decode64" : "decode32", gr.alg_bytes, gr.alg_ops, gr.units);
+            const bool dfft = gr.big >= kDecFftVar;   // the range-axis FFT decode
+            ProfScope ps(prof, s, gr.dbl ? (dfft ? "decode64_fft" : "decode64") : (dfft ? "decode32_fft" : "decode32"),
+                         gr.alg_bytes, gr.alg_ops, gr.units);
             MD_HIP(launch_decode(gr.big, gr.dbl, ex.jobs_d, gr.segs_d, (int)gr.segs.size(), gr.nitems, gr.grid,
                                  band, (unsigned int *)ex.flags.p, (int2 *)ex.list.p, g.st_d, s));
             ps.done();
