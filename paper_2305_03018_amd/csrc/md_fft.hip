@@ -713,14 +713,16 @@ __global__ __launch_bounds__(kDecThreads) void k_decode(const JobDev *__restrict
 //   Z_k = (X_k + conj(X_{M-k})) + i w^k (X_k - conj(X_{M-k})),  k < M,
 //   z_n = sum_{k<M} Z_k exp(2 pi i k n / M),  c_{2n} = scale Re z_n,  c_{2n+1} = scale Im z_n,
 // about 2.5 nr log2(nr) flops per pixel where the dense decode takes
-// nr (nr/2 + 1) products.  A work item is P = 4096 / M pixels of one tile:
+// nr (nr/2 + 1) products.  A work item is P = 4096 / M pixels of one tile,
+// whose transform-domain values are stored in blocks of 16 pixels with the
+// bins contiguous (JobDev::ybs):
 //   1. each pixel's packed Z goes to one LDS row in bit-reversed order;
 //   2. radix-2 decimation-in-time stages, two per LDS round trip (a single
 //      first stage when log2 M is odd);
-//   3. every degree is rounded; the 64 lanes of a wave hold consecutive
-//      degrees of one pixel, so the wave takes its top non-zero degree with
-//      shuffles and one LDS atomic max per pixel; residuals and tile flags as
-//      in the dense decode.
+//   3. every degree is rounded by G = 256 / P threads per pixel, each keeping
+//      its top non-zero degree in a register, then one shuffle reduction and
+//      one LDS atomic max per pixel; residuals and tile flags as in the dense
+//      decode.
 // Every job of one launch has the same range length, so the M twiddles are
 // staged in LDS once per block.
 template <typename R, int LM>
@@ -731,7 +733,7 @@ __global__ __launch_bounds__(kDecThreads) void k_decode_fft(const JobDev *__rest
                                                             StatsDev *st) {
     using C = typename Cx<R>::T;
     constexpr int M = 1 << LM, LP = 12 - LM, P = 1 << LP, PITCH = M + 1;
-    static_assert(M >= 64 && LP >= 0, "a wave scans 64 consecutive degrees of one pixel");
+    static_assert(M >= 16 && LP >= 0, "P = 4096 / M pixels must divide the block");
     __shared__ C zs[P * PITCH];
     __shared__ C tws[M];
     __shared__ int s_top[P];
@@ -759,9 +761,7 @@ __global__ __launch_bounds__(kDecThreads) void k_decode_fft(const JobDev *__rest
         // 1. packed spectra (zero outside the image), bit-reversed per row.
         // One thread takes the bin pair (X_j, X_{M-j}), j <= M/2, and writes
         // both Z_j and Z_{M-j} (Z_0 alone for j = 0, whose partner is X_M;
-        // Z_{M/2} once); the loads of CH pairs go out before any is used
-        // (the bins of one pixel lie T*T apart, so each load is its own
-        // burst).
+        // Z_{M/2} once); the loads of CH pairs go out before any is used.
         constexpr int CH = 4, NJ = M / 2 + 1;
         const bool pv = pixel_valid(threadIdx.x & (P - 1));   // the same pixel in every batch
         for (int u0 = threadIdx.x; u0 < P * NJ; u0 += CH * kDecThreads) {
