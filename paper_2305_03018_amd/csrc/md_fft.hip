@@ -705,6 +705,60 @@ __global__ __launch_bounds__(kDecThreads) void k_decode(const JobDev *__restrict
     if (threadIdx.x == 0 && rm > 0.f) atomicMax(&st->max_res_bits, __float_as_uint(rm));
 }
 
+// cos(2 pi q / 16) for q in [0, 8]
+__host__ __device__ constexpr double cos16(int q) {
+    return q == 0 ? 1.0
+         : q == 1 ? 0.92387953251128675613
+         : q == 2 ? 0.70710678118654752440
+         : q == 3 ? 0.38268343236508977173
+         : q == 4 ? 0.0
+                  : -cos16(8 - q);
+}
+__host__ __device__ constexpr double sin16(int q) { return cos16(q <= 4 ? 4 - q : q - 4); }
+
+// DFT of N <= 16 points held in registers, positive exponent,
+// y_s = sum_r v_r exp(2 pi i r s / N), natural order in and out: radix-2
+// decimation in time after a bit reversal that full unrolling turns into
+// register renaming.
+template <typename R, int N, typename C>
+__device__ __forceinline__ void reg_dft(C (&v)[N]) {
+    constexpr int LN = N == 2 ? 1 : N == 4 ? 2 : N == 8 ? 3 : 4;
+    static_assert((1 << LN) == N, "N must be 2, 4, 8 or 16");
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+        const int j = brevc(i, LN);
+        if (i < j) {
+            const C t = v[i];
+            v[i] = v[j];
+            v[j] = t;
+        }
+    }
+#pragma unroll
+    for (int h = 1; h < N; h *= 2) {
+#pragma unroll
+        for (int i0 = 0; i0 < N; i0 += 2 * h) {
+#pragma unroll
+            for (int t = 0; t < h; ++t) {
+                const int q = t * (8 / h);   // exp(2 pi i t / 2h) = exp(2 pi i q / 16)
+                const C x0 = v[i0 + t], x1 = v[i0 + t + h];
+                C y;
+                if (q == 0) {
+                    y = x1;
+                } else if (q == 4) {
+                    y.x = -x1.y;
+                    y.y = x1.x;
+                } else {
+                    const R c = (R)cos16(q), s = (R)sin16(q);
+                    y.x = c * x1.x - s * x1.y;
+                    y.y = c * x1.y + s * x1.x;
+                }
+                v[i0 + t] = cadd(x0, y);
+                v[i0 + t + h] = csub(x0, y);
+            }
+        }
+    }
+}
+
 // Range-axis FFT decode: Step 3 for a power-of-two range length nr = 2M.
 // A pixel's coefficient vector is the real inverse DFT of its Hermitian
 // spectrum, of which the bins X_0 .. X_M are kept:
@@ -715,14 +769,21 @@ __global__ __launch_bounds__(kDecThreads) void k_decode(const JobDev *__restrict
 // about 2.5 nr log2(nr) flops per pixel where the dense decode takes
 // nr (nr/2 + 1) products.  A work item is P = 4096 / M pixels of one tile,
 // whose transform-domain values are stored in blocks of 16 pixels with the
-// bins contiguous (JobDev::ybs):
-//   1. each pixel's packed Z goes to one LDS row in bit-reversed order;
-//   2. radix-2 decimation-in-time stages, two per LDS round trip (a single
-//      first stage when log2 M is odd);
-//   3. every degree is rounded by G = 256 / P threads per pixel, each keeping
-//      its top non-zero degree in a register, then one shuffle reduction and
-//      one LDS atomic max per pixel; residuals and tile flags as in the dense
-//      decode.
+// bins contiguous (JobDev::ybs).  Thread (p, g), p < P, g < G = M / 16,
+// holds 16 points of pixel p through Stockham autosort passes: each pass of
+// radix Q takes butterflies j, reads the points j + r M / Q (r < Q), turns
+// them by exp(2 pi i r k / (S Q)) with k = j mod S (S: the length already
+// transformed), takes a Q-point DFT in registers and leaves point s at
+// (j - k) Q + k + s S.
+//   1. a radix-16 pass straight from the bins: thread g loads X_k and
+//      X_{M-k} for k = g + r G, packs Z_k and needs no turn (S = 1);
+//   2. one more pass when M <= 256 (radix G), two when M > 256 (radix 16,
+//      then M / 256), through LDS rows of P points, one row of padding
+//      after every 16 so that the strided writes of the first pass fall in
+//      distinct banks;
+//   3. the last pass leaves each thread's 16 points z_n in registers: it
+//      rounds them, keeps its top non-zero degree, and the threads of a
+//      pixel combine theirs by shuffles and one LDS maximum per wave.
 // Every job of one launch has the same range length, so the M twiddles are
 // staged in LDS once per block.
 template <typename R, int LM>
@@ -732,12 +793,23 @@ __global__ __launch_bounds__(kDecThreads) void k_decode_fft(const JobDev *__rest
                                                             unsigned int *tile_flags, int2 *fb_list,
                                                             StatsDev *st) {
     using C = typename Cx<R>::T;
-    constexpr int M = 1 << LM, LP = 12 - LM, P = 1 << LP, PITCH = M + 1;
-    static_assert(M >= 16 && LP >= 0, "P = 4096 / M pixels must divide the block");
-    __shared__ C zs[P * PITCH];
+    constexpr int M = 1 << LM, LP = 12 - LM, P = 1 << LP, G = M / 16;
+    constexpr int Q2 = M >= 256 ? 16 : G, Q3 = M > 256 ? M / 256 : 1;
+    static_assert(LM >= 6 && LM <= 11 && G * P == kDecThreads, "P = 4096 / M pixels of G threads each");
+    __shared__ C zs[(M + M / 16) * P];
     __shared__ C tws[M];
     __shared__ int s_top[P];
     __shared__ float s_red[kDecThreads / 64];
+    const int p = threadIdx.x & (P - 1), g = threadIdx.x >> LP;
+    auto at = [&](int n) -> C & { return zs[(n + (n >> 4)) * P + p]; };
+    auto turn = [&](C x, int m) {   // x exp(2 pi i m / nr), m < nr
+        C w = tws[m & (M - 1)];
+        if (m >= M) {
+            w.x = -w.x;
+            w.y = -w.y;
+        }
+        return cmul(x, w);
+    };
     float run_max = 0.f;
     if (blockIdx.x < nitems) {
         const C *tw = (const C *)jobs[segs[find_seg(segs, nseg, blockIdx.x)].job].rtw;
@@ -754,104 +826,95 @@ __global__ __launch_bounds__(kDecThreads) void k_decode_fft(const JobDev *__rest
         const int ty = tile / J.tiles_x, tx = tile - ty * J.tiles_x;
         const C *X = (const C *)S.y + (size_t)tl * ytile_elems(J.bins, T, J.ybs);
         const int p0 = pb * P;
-        auto pixel_valid = [&](int p) {
-            const int q = p0 + p, ly = q / T, lx = q - ly * T;
+        auto pixel_valid = [&](int pp) {
+            const int q = p0 + pp, ly = q / T, lx = q - ly * T;
             return q < TT && ty * T + ly < J.H && tx * T + lx < J.W;
         };
-        // 1. packed spectra (zero outside the image), bit-reversed per row.
-        // One thread takes the bin pair (X_j, X_{M-j}), j <= M/2, and writes
-        // both Z_j and Z_{M-j} (Z_0 alone for j = 0, whose partner is X_M;
-        // Z_{M/2} once); the loads of CH pairs go out before any is used.
-        constexpr int CH = 4, NJ = M / 2 + 1;
-        const bool pv = pixel_valid(threadIdx.x & (P - 1));   // the same pixel in every batch
-        for (int u0 = threadIdx.x; u0 < P * NJ; u0 += CH * kDecThreads) {
-            C a[CH], b[CH];
+        // 1. radix-16 pass from the bins (zero outside the image)
+        C v[16];
+        {
+            // X_k at xa[16 r G], X_{M-k} at xb[16 (15 - r) G] (M - k = G - g + (15 - r) G)
+            C a[16], b[16];
+            const bool pv = pixel_valid(p);
+            const C *xa = X + ypix(p0 + p, J.ybs) + 16 * g, *xb = xa + 16 * (G - 2 * g);
 #pragma unroll
-            for (int e = 0; e < CH; ++e) {
-                const int u = u0 + e * kDecThreads, p = u & (P - 1), j = u >> LP;
-                a[e] = b[e] = czero<C>();
-                if (pv && j < NJ) {
-                    const size_t q = ypix(p0 + p, J.ybs);
-                    a[e] = ldg(X, ybin_offset(j, T, J.ybs) + q);
-                    b[e] = ldg(X, ybin_offset(M - j, T, J.ybs) + q);
+            for (int r = 0; r < 16; ++r) {
+                a[r] = b[r] = czero<C>();
+                if (pv) {
+                    a[r] = ldg(xa, 16 * r * G);
+                    b[r] = ldg(xb, 16 * (15 - r) * G);
                 }
             }
-            __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-            for (int e = 0; e < CH; ++e) {
-                const int u = u0 + e * kDecThreads, p = u & (P - 1), j = u >> LP;
-                if (j >= NJ) continue;
+            for (int r = 0; r < 16; ++r) {
                 // Z_k from (x, y) = (X_k, X_{M-k}): (x + conj y) + i w^k (x - conj y)
-                auto pack = [&](C x, C y, int kk) {
-                    const C w = tws[kk];
-                    const R ox = x.x - y.x, oy = x.y + y.y;
-                    const R wx = w.x * ox - w.y * oy, wy = w.x * oy + w.y * ox;
-                    C zv;
-                    zv.x = x.x + y.x - wy;
-                    zv.y = x.y - y.y + wx;
-                    zs[p * PITCH + brev<LM>(kk)] = zv;
-                };
-                pack(a[e], b[e], j);
-                if (j > 0 && j < M / 2) pack(b[e], a[e], M - j);
+                const C x = a[r], y = b[r], w = tws[g + r * G];
+                const R ox = x.x - y.x, oy = x.y + y.y;
+                const R wx = w.x * ox - w.y * oy, wy = w.x * oy + w.y * ox;
+                v[r].x = x.x + y.x - wy;
+                v[r].y = x.y - y.y + wx;
             }
         }
+        reg_dft<R, 16>(v);
+#pragma unroll
+        for (int s = 0; s < 16; ++s) at(16 * g + s) = v[s];
         if (threadIdx.x < P) s_top[threadIdx.x] = -1;
         __syncthreads();
-        // 2. inverse DFT of length M
-        int h = 1;
-        if constexpr (LM & 1) {
-            for (int u = threadIdx.x; u < P * (M / 2); u += kDecThreads) {
-                C *L = zs + (u >> (LM - 1)) * PITCH + 2 * (u & (M / 2 - 1));
-                const C x0 = L[0], x1 = L[1];
-                L[0] = cadd(x0, x1);
-                L[1] = csub(x0, x1);
-            }
-            __syncthreads();
-            h = 2;
-        }
-        for (; h < M; h *= 4) {   // stages of half-size h and 2h over blocks of 4h points
-            for (int u = threadIdx.x; u < P * (M / 4); u += kDecThreads) {
-                const int r = u & (M / 4 - 1), t = r & (h - 1);
-                C *L = zs + (u >> (LM - 2)) * PITCH + (r - t) * 4 + t;
-                const C x0 = L[0], x1 = L[h], x2 = L[2 * h], x3 = L[3 * h];
-                const C w1 = tws[t * (M / h)];         // exp(2 pi i t / 2h)
-                const C w2 = tws[t * (M / (2 * h))];   // exp(2 pi i t / 4h)
-                const C y1 = cmul(w1, x1), y3 = cmul(w1, x3);
-                const C a0 = cadd(x0, y1), a1 = csub(x0, y1), a2 = cadd(x2, y3), a3 = csub(x2, y3);
-                const C y2 = cmul(w2, a2), y4 = cmul(w2, a3);
-                C iy4;   // exp(2 pi i (t + h) / 4h) = i w2
-                iy4.x = -y4.y;
-                iy4.y = y4.x;
-                L[0] = cadd(a0, y2);
-                L[2 * h] = csub(a0, y2);
-                L[h] = cadd(a1, iy4);
-                L[3 * h] = csub(a1, iy4);
-            }
-            __syncthreads();
-        }
-        // 3. round every degree: G = kDecThreads / P threads per pixel, each
-        // taking every G-th point (consecutive lanes read consecutive words)
-        // and keeping its top degree in a register; one shuffle reduction
-        // per pixel, then one LDS maximum per pixel (per wave when a pixel
-        // spans several waves)
-        constexpr int G = kDecThreads / P, GW = G < 64 ? G : 64;
-        const R scale = (R)J.scale;
-        bool hit = false;
-        {
-            const int p = threadIdx.x / G, t = threadIdx.x & (G - 1);
-            int top = -1;
-            R res = 0;
-            for (int n = t; n < M; n += G) {
-                const C v = zs[p * PITCH + n];
-                band_update<R>(v.x * scale, 2 * n, top, res);
-                band_update<R>(v.y * scale, 2 * n + 1, top, res);
-            }
+        // 2. the remaining passes; n(b, s) names the point left in u[b][s]
+        constexpr int B2 = 16 / Q2;
+        C u[B2][Q2];
 #pragma unroll
-            for (int o = GW / 2; o > 0; o >>= 1) top = max(top, __shfl_xor(top, o, 64));
-            if ((t & (GW - 1)) == 0 && top >= 0) atomicMax(&s_top[p], top);
-            run_max = fmaxf(run_max, (float)res);
-            hit = (float)res >= band;
+        for (int b = 0; b < B2; ++b) {
+            const int j = g + b * G, k = j & 15;
+#pragma unroll
+            for (int r = 0; r < Q2; ++r) {
+                const C x = at(j + r * (M / Q2));
+                u[b][r] = r == 0 ? x : turn(x, r * k * (2 * M / (16 * Q2)));
+            }
+            reg_dft<R, Q2>(u[b]);
         }
+        constexpr int B3 = 16 / Q3;
+        C w3[B3][Q3];
+        if constexpr (Q3 > 1) {
+            __syncthreads();   // every read of the first rows is done
+#pragma unroll
+            for (int s = 0; s < 16; ++s) at(256 * (g >> 4) + (g & 15) + 16 * s) = u[0][s];
+            __syncthreads();
+#pragma unroll
+            for (int b = 0; b < B3; ++b) {
+                const int j = g + b * G;
+#pragma unroll
+                for (int r = 0; r < Q3; ++r) {
+                    const C x = at(j + 256 * r);
+                    w3[b][r] = r == 0 ? x : turn(x, 2 * r * j);
+                }
+                reg_dft<R, Q3>(w3[b]);
+            }
+        }
+        // 3. round every degree held in registers
+        const R scale = (R)J.scale;
+        int top = -1;
+        R res = 0;
+        auto scan = [&](C z, int n) {
+            band_update<R>(z.x * scale, 2 * n, top, res);
+            band_update<R>(z.y * scale, 2 * n + 1, top, res);
+        };
+        if constexpr (Q3 == 1) {
+#pragma unroll
+            for (int b = 0; b < B2; ++b)
+#pragma unroll
+                for (int s = 0; s < Q2; ++s) scan(u[b][s], g + b * G + 16 * s);
+        } else {
+#pragma unroll
+            for (int b = 0; b < B3; ++b)
+#pragma unroll
+                for (int s = 0; s < Q3; ++s) scan(w3[b][s], g + b * G + 256 * s);
+        }
+#pragma unroll
+        for (int o = 32; o >= P; o >>= 1) top = max(top, __shfl_xor(top, o, 64));
+        if ((threadIdx.x & 63) < P && top >= 0) atomicMax(&s_top[p], top);
+        run_max = fmaxf(run_max, (float)res);
+        const bool hit = (float)res >= band;
         __syncthreads();
         if (threadIdx.x < P && pixel_valid(threadIdx.x)) {
             const int q = p0 + threadIdx.x, ly = q / T, lx = q - ly * T;
