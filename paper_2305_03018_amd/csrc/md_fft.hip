@@ -705,6 +705,20 @@ __global__ __launch_bounds__(kDecThreads) void k_decode(const JobDev *__restrict
     if (threadIdx.x == 0 && rm > 0.f) atomicMax(&st->max_res_bits, __float_as_uint(rm));
 }
 
+// Third word of a raw buffer resource on gfx9-class chips (32-bit data
+// format, no swizzle).
+constexpr int kBufWord3 = 0x00020000;
+
+// 8- or 16-byte load through a buffer resource at voff + soff bytes (soff
+// uniform across the wave)
+template <typename C>
+__device__ __forceinline__ C buf_load(__amdgpu_buffer_rsrc_t rs, unsigned voff, unsigned soff) {
+    if constexpr (sizeof(C) == 8)
+        return __builtin_bit_cast(C, __builtin_amdgcn_raw_buffer_load_b64(rs, voff, soff, 0));
+    else
+        return __builtin_bit_cast(C, __builtin_amdgcn_raw_buffer_load_b128(rs, voff, soff, 0));
+}
+
 // cos(2 pi q / 16) for q in [0, 8]
 __host__ __device__ constexpr double cos16(int q) {
     return q == 0 ? 1.0
@@ -795,13 +809,20 @@ __global__ __launch_bounds__(kDecThreads) void k_decode_fft(const JobDev *__rest
     using C = typename Cx<R>::T;
     constexpr int M = 1 << LM, LP = 12 - LM, P = 1 << LP, G = M / 16;
     constexpr int Q2 = M >= 256 ? 16 : G, Q3 = M > 256 ? M / 256 : 1;
+    constexpr int B2 = 16 / Q2, B3 = 16 / Q3;
     static_assert(LM >= 6 && LM <= 11 && G * P == kDecThreads, "P = 4096 / M pixels of G threads each");
     __shared__ C zs[(M + M / 16) * P];
-    __shared__ C tws[M];
+    __shared__ C tws[M];         // exp(2 pi i m / nr), m < M
+    __shared__ C tw2[M <= 256 ? M : 1];   // exp(2 pi i m / M) for the second pass when M <= 256
     __shared__ int s_top[P];
     __shared__ float s_red[kDecThreads / 64];
     const int p = threadIdx.x & (P - 1), g = threadIdx.x >> LP;
-    auto at = [&](int n) -> C & { return zs[(n + (n >> 4)) * P + p]; };
+    // LDS rows: point n of pixel p at (n + n / 16) P + p; the bases below
+    // leave compile-time steps
+    const int base1 = 17 * g * P + p;                              // n = 16 g + s
+    const int base2 = (M <= 256 ? g : g + (g >> 4)) * P + p;       // n = g + r M / Q2 (+ b G)
+    const int wbase2 = (272 * (g >> 4) + (g & 15)) * P + p;        // n = 256 (g / 16) + g % 16 + 16 s
+    constexpr int rstep2 = (M <= 256 ? 17 : (M / Q2) * 17 / 16) * P, bstep = (M <= 256 ? G : G * 17 / 16) * P;
     auto turn = [&](C x, int m) {   // x exp(2 pi i m / nr), m < nr
         C w = tws[m & (M - 1)];
         if (m >= M) {
@@ -814,6 +835,15 @@ __global__ __launch_bounds__(kDecThreads) void k_decode_fft(const JobDev *__rest
     if (blockIdx.x < nitems) {
         const C *tw = (const C *)jobs[segs[find_seg(segs, nseg, blockIdx.x)].job].rtw;
         for (int m = threadIdx.x; m < M; m += kDecThreads) tws[m] = ldg(tw, m);
+        if constexpr (M <= 256)
+            for (int m = threadIdx.x; m < M; m += kDecThreads) {
+                C w = ldg(tw, (2 * m) & (M - 1));
+                if (2 * m >= M) {
+                    w.x = -w.x;
+                    w.y = -w.y;
+                }
+                tw2[m] = w;
+            }
     }
     __syncthreads();
     for (long long it = blockIdx.x; it < nitems; it += gridDim.x) {
@@ -830,20 +860,27 @@ __global__ __launch_bounds__(kDecThreads) void k_decode_fft(const JobDev *__rest
             const int q = p0 + pp, ly = q / T, lx = q - ly * T;
             return q < TT && ty * T + ly < J.H && tx * T + lx < J.W;
         };
-        // 1. radix-16 pass from the bins (zero outside the image)
+        // 1. radix-16 pass from the bins
+        const bool pv = pixel_valid(p);
         C v[16];
         {
-            // X_k at xa[16 r G], X_{M-k} at xb[16 (15 - r) G] (M - k = G - g + (15 - r) G)
+            // X_k and X_{M-k} (M - k = G - g + (15 - r) G) through a buffer
+            // resource over the item's 16-pixel blocks: one address register
+            // per operand, the bin steps as uniform offsets.  A pixel outside
+            // the image reads the bins of the item's first pixel (always
+            // stored) and its results are dropped.
             C a[16], b[16];
-            const bool pv = pixel_valid(p);
-            const C *xa = X + ypix(p0 + p, J.ybs) + 16 * g, *xb = xa + 16 * (G - 2 * g);
+            const int pl = pv ? p : 0;
+            const int e0 = p0 & 15, blk = (e0 + pl) >> 4, pin = (p0 + pl) & 15;
+            const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+                (void *)(X + (size_t)(p0 >> 4) * J.ybs), (short)0,
+                (int)((unsigned)((e0 + P + 15) >> 4) * J.ybs * sizeof(C)), kBufWord3);
+            const unsigned va = (unsigned)(blk * J.ybs + pin + 16 * g) * sizeof(C);
+            const unsigned vb = (unsigned)(blk * J.ybs + pin + 16 * (G - g)) * sizeof(C);
 #pragma unroll
             for (int r = 0; r < 16; ++r) {
-                a[r] = b[r] = czero<C>();
-                if (pv) {
-                    a[r] = ldg(xa, 16 * r * G);
-                    b[r] = ldg(xb, 16 * (15 - r) * G);
-                }
+                a[r] = buf_load<C>(rs, va, 16 * r * G * sizeof(C));
+                b[r] = buf_load<C>(rs, vb, 16 * (15 - r) * G * sizeof(C));
             }
 #pragma unroll
             for (int r = 0; r < 16; ++r) {
@@ -857,58 +894,65 @@ __global__ __launch_bounds__(kDecThreads) void k_decode_fft(const JobDev *__rest
         }
         reg_dft<R, 16>(v);
 #pragma unroll
-        for (int s = 0; s < 16; ++s) at(16 * g + s) = v[s];
+        for (int s = 0; s < 16; ++s) zs[base1 + s * P] = v[s];
         if (threadIdx.x < P) s_top[threadIdx.x] = -1;
         __syncthreads();
-        // 2. the remaining passes; n(b, s) names the point left in u[b][s]
-        constexpr int B2 = 16 / Q2;
+        // 2. the remaining passes
         C u[B2][Q2];
 #pragma unroll
         for (int b = 0; b < B2; ++b) {
-            const int j = g + b * G, k = j & 15;
+            const int k = (g + b * G) & 15;
 #pragma unroll
             for (int r = 0; r < Q2; ++r) {
-                const C x = at(j + r * (M / Q2));
-                u[b][r] = r == 0 ? x : turn(x, r * k * (2 * M / (16 * Q2)));
+                const C x = zs[base2 + b * bstep + r * rstep2];
+                // exp(2 pi i r k / (16 Q2))
+                u[b][r] = r == 0 ? x : M <= 256 ? cmul(x, tw2[r * k]) : turn(x, r * k * (M / 128));
             }
             reg_dft<R, Q2>(u[b]);
         }
-        constexpr int B3 = 16 / Q3;
         C w3[B3][Q3];
         if constexpr (Q3 > 1) {
             __syncthreads();   // every read of the first rows is done
 #pragma unroll
-            for (int s = 0; s < 16; ++s) at(256 * (g >> 4) + (g & 15) + 16 * s) = u[0][s];
+            for (int s = 0; s < 16; ++s) zs[wbase2 + 17 * s * P] = u[0][s];
             __syncthreads();
 #pragma unroll
             for (int b = 0; b < B3; ++b) {
                 const int j = g + b * G;
 #pragma unroll
                 for (int r = 0; r < Q3; ++r) {
-                    const C x = at(j + 256 * r);
-                    w3[b][r] = r == 0 ? x : turn(x, 2 * r * j);
+                    const C x = zs[base2 + b * bstep + 272 * r * P];
+                    w3[b][r] = r == 0 ? x : turn(x, 2 * r * j);   // exp(2 pi i r j / M)
                 }
                 reg_dft<R, Q3>(w3[b]);
             }
         }
-        // 3. round every degree held in registers
+        // 3. round every degree held in registers, in increasing degree
+        // order (point n = g + b G + NS s), keeping the index of the last
+        // non-zero one
+        constexpr int NB = Q3 > 1 ? B3 : B2, NSP = Q3 > 1 ? Q3 : Q2, NS = Q3 > 1 ? 256 : 16;
         const R scale = (R)J.scale;
-        int top = -1;
+        int topi = -1;
         R res = 0;
-        auto scan = [&](C z, int n) {
-            band_update<R>(z.x * scale, 2 * n, top, res);
-            band_update<R>(z.y * scale, 2 * n + 1, top, res);
-        };
-        if constexpr (Q3 == 1) {
 #pragma unroll
-            for (int b = 0; b < B2; ++b)
+        for (int s = 0; s < NSP; ++s)
 #pragma unroll
-                for (int s = 0; s < Q2; ++s) scan(u[b][s], g + b * G + 16 * s);
-        } else {
-#pragma unroll
-            for (int b = 0; b < B3; ++b)
-#pragma unroll
-                for (int s = 0; s < Q3; ++s) scan(w3[b][s], g + b * G + 256 * s);
+            for (int b = 0; b < NB; ++b) {
+                const C z = Q3 > 1 ? w3[b][s] : u[b][s];
+                const int i = 2 * (s * NB + b);
+                const R cx = z.x * scale, cy = z.y * scale, rx = rint(cx), ry = rint(cy);
+                res = fmax(res, fmax(fabs(cx - rx), fabs(cy - ry)));
+                if (rx != R(0)) topi = i;
+                if (ry != R(0)) topi = i + 1;
+            }
+        if (!pv) {
+            topi = -1;
+            res = 0;
+        }
+        int top = -1;
+        if (topi >= 0) {
+            const int q = topi >> 1, s = q / NB, b = q - s * NB;
+            top = 2 * (g + b * G + NS * s) + (topi & 1);
         }
 #pragma unroll
         for (int o = 32; o >= P; o >>= 1) top = max(top, __shfl_xor(top, o, 64));

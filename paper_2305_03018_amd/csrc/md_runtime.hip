@@ -1210,9 +1210,10 @@ int build_exec(const md_job *jobs, int n, const std::vector<SEData> &ses, Exec &
         }
         for (auto &gr : wv.dec) {
             // the range-axis FFT decode holds 4096 complex values, one row
-            // of padding per 16 rows and its M twiddles in LDS
+            // of padding per 16 rows and its M twiddles in LDS (2 M when M <= 256)
             const size_t elem = gr.dbl == kPrecFP64 ? sizeof(double2) : sizeof(float2);
-            const size_t lds = gr.big >= kDecFftVar ? (4352 + ((size_t)1 << (gr.big - kDecFftVar))) * elem : 0;
+            const size_t dm = gr.big >= kDecFftVar ? (size_t)1 << (gr.big - kDecFftVar) : 0;
+            const size_t lds = dm ? (4352 + (dm <= 256 ? 2 * dm : dm)) * elem : 0;
             place(gr, kDecThreads, lds);
         }
     }
