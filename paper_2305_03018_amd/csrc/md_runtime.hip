@@ -541,12 +541,13 @@ double dec_padded_bins(int bins, int dbl);
 int plan_ybs(const Plan &p) { return p.dec_fft ? p.bins * 16 : 0; }
 
 // Decode work per pixel in the dense decode's units (padded bins squared).
-// The range-axis FFT decode is priced at kDecFftRatio of those units per
-// nr log2 nr (measured on 2048^2 images, FP32 and FP64: 1.46 at nr = 128,
-// 1.24 at 256, 1.20 at 512, 1.13 at 1024).
-constexpr double kDecFftRatio = 1.3;
+// The range-axis FFT decode is priced at kDecFftRatio[precision] of those
+// units per nr log2 nr (time per nr log2 nr over the dense decode's time per
+// unit at nr - 1, on 2048^2 images: FP32 1.37 at nr = 128, 1.08 at 256,
+// 0.73 at 512, 0.85 at 1024; FP64 0.88, 0.55, 0.49, 0.46).
+constexpr double kDecFftRatio[2] = {0.8, 0.5};
 double dec_units(int nr, int dbl) {
-    if (decode_uses_fft(nr)) return kDecFftRatio * nr * std::log2((double)nr);
+    if (decode_uses_fft(nr)) return kDecFftRatio[dbl ? 1 : 0] * nr * std::log2((double)nr);
     const double pb = dec_padded_bins(nr / 2 + 1, dbl);
     return pb * pb;
 }
