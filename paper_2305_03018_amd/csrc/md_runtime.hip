@@ -840,13 +840,14 @@ int plan_job(const md_job &j, const SEData &se, Plan &p, bool lone) {
     p.cost_dir = dir_ok ? dir_cost(j, se, form, lone) : INFINITY;
     // transform plan: best spatial length and, on the FP paths, range length
     // by the cost model: the smallest range length (dense decode) or, past
-    // 256, the next power of two (range-axis FFT decode, at the price of more
-    // kept bins).  Up to 256 the dense decode of the smallest length is
-    // measured to cost no more than the FFT decode plus the extra bins (the
-    // calibrated dense unit, taken at about 12 bins, overprices 64 and more
-    // by 1.5-1.8x, so the model is not trusted there).
+    // 128, the next power of two (range-axis FFT decode, at the price of more
+    // kept bins).  Up to 128 the extra bins cost more than the decode saves
+    // (the calibrated dense unit, taken at about 12 bins, overprices 64 and
+    // more, so the model is not trusted there); on 2048^2 images the power of
+    // two wins from about 150 on (FP32 12.9 against 6.5 ms at 230, FP64 42.1
+    // against 17.6 ms).
     int nrs[2] = {nr, 0};
-    if (dbl != kPrecNTT && g.opt.nr <= 0 && nr > 256) {
+    if (dbl != kPrecNTT && g.opt.nr <= 0 && nr > 128) {
         int nr2 = 1;
         while (nr2 < nr) nr2 <<= 1;
         if (nr2 != nr && decode_uses_fft(nr2)) nrs[1] = nr2;

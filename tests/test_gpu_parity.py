@@ -284,9 +284,10 @@ def test_range_fft_decode(dev):
 
 
 def test_planner_picks_fft_decode(dev):
-    """An 8-bit range (n_r >= 287) on the transform path: the planner prices
-    the smallest range length with the dense decode against the next power of
-    two with the FFT decode; either way the result is exact."""
+    """An 8-bit range (n_r >= 287), and one of 230, on the transform path:
+    the planner prices the smallest range length with the dense decode
+    against the next power of two with the FFT decode; either way the result
+    is exact."""
     rng = np.random.default_rng(43)
     img = rng.integers(0, 256, (300, 280)).astype(np.int32)
     mask = synthetic.disk_mask(31)
@@ -297,6 +298,15 @@ def test_planner_picks_fft_decode(dev):
         for opts in (FFT32, FFT64):
             st = assert_parity(job, dev, want=want, **opts)
             assert st["n_r"] in (int((mask * off).max()) + 256, 512), st
+    # a range length between 128 and 256: the smallest length or 256
+    img = rng.integers(0, 115, (260, 230)).astype(np.int32)
+    off = (rng.integers(0, 116, (31, 31)) * mask).astype(np.int32)
+    off[15, 15] = 115
+    job = synthetic.Job(img, 115, mask, off, 0, "mid_range_260x230_L115_disk31")
+    want = oracle.run_job(job)
+    for opts in (FFT32, FFT64):
+        st = assert_parity(job, dev, want=want, **opts)
+        assert st["n_r"] in (230, 256), st
 
 
 def test_large_se_fft_only(dev):
