@@ -773,58 +773,109 @@ __device__ __forceinline__ void reg_dft(C (&v)[N]) {
     }
 }
 
-// Range-axis FFT decode: Step 3 for a power-of-two range length nr = 2M.
-// A pixel's coefficient vector is the real inverse DFT of its Hermitian
-// spectrum, of which the bins X_0 .. X_M are kept:
+// cos(2 pi m / 24) and sin(2 pi m / 24) for any m >= 0
+__host__ __device__ constexpr double cos24q(int m) {   // m in [0, 6]: 0 .. 90 degrees
+    return m == 0 ? 1.0
+         : m == 1 ? 0.96592582628906828675
+         : m == 2 ? 0.86602540378443864676
+         : m == 3 ? 0.70710678118654752440
+         : m == 4 ? 0.5
+         : m == 5 ? 0.25881904510252076235
+                  : 0.0;
+}
+__host__ __device__ constexpr double cos24(int m) {
+    return (m % 24) <= 6 ? cos24q(m % 24) : (m % 24) <= 12 ? -cos24q(12 - m % 24) : -cos24(m % 24 - 12);
+}
+__host__ __device__ constexpr double sin24(int m) { return cos24(m % 24 + 18); }
+
+// DFT of 24 points in registers, positive exponent, natural order: for
+// r = 3 r2 + r1 and s = s1 + 8 s2, three 8-point DFTs over r2, turns
+// exp(2 pi i r1 s1 / 24), then eight 3-point DFTs over r1.
+template <typename R, typename C>
+__device__ __forceinline__ void reg_dft24(C (&v)[24]) {
+    C a[3][8];
+#pragma unroll
+    for (int r1 = 0; r1 < 3; ++r1) {
+#pragma unroll
+        for (int r2 = 0; r2 < 8; ++r2) a[r1][r2] = v[3 * r2 + r1];
+        reg_dft<R, 8>(a[r1]);
+#pragma unroll
+        for (int s1 = 1; s1 < 8; ++s1)
+            if (r1 > 0) {
+                const R c = (R)cos24(r1 * s1), sn = (R)sin24(r1 * s1);
+                const C x = a[r1][s1];
+                a[r1][s1].x = c * x.x - sn * x.y;
+                a[r1][s1].y = c * x.y + sn * x.x;
+            }
+    }
+    const R h = (R)0.86602540378443864676;   // sin(2 pi / 3)
+#pragma unroll
+    for (int s1 = 0; s1 < 8; ++s1) {
+        const C a0 = a[0][s1], t = cadd(a[1][s1], a[2][s1]), u = csub(a[1][s1], a[2][s1]);
+        C w;
+        w.x = a0.x - (R)0.5 * t.x;
+        w.y = a0.y - (R)0.5 * t.y;
+        C iu;   // i sin(2 pi / 3) (a1 - a2)
+        iu.x = -h * u.y;
+        iu.y = h * u.x;
+        v[s1] = cadd(a0, t);
+        v[s1 + 8] = cadd(w, iu);
+        v[s1 + 16] = csub(w, iu);
+    }
+}
+
+// Range-axis FFT decode: Step 3 for a range length nr = 2M with M = 2^a
+// (64 to 2048) or, in FP32, M = 3 2^a (96 to 768).  A pixel's coefficient
+// vector is the real inverse DFT of its Hermitian spectrum, of which the
+// bins X_0 .. X_M are kept:
 //   c_d = scale * sum_{m < nr} X_m w^(d m),  w = exp(2 pi i / nr),  X_{nr-m} = conj(X_m).
 // Its even and odd samples are one complex inverse DFT of length M:
 //   Z_k = (X_k + conj(X_{M-k})) + i w^k (X_k - conj(X_{M-k})),  k < M,
 //   z_n = sum_{k<M} Z_k exp(2 pi i k n / M),  c_{2n} = scale Re z_n,  c_{2n+1} = scale Im z_n,
 // about 2.5 nr log2(nr) flops per pixel where the dense decode takes
-// nr (nr/2 + 1) products.  A work item is P = 4096 / M pixels of one tile,
-// whose transform-domain values are stored in blocks of 16 pixels with the
-// bins contiguous (JobDev::ybs).  Thread (p, g), p < P, g < G = M / 16,
-// holds 16 points of pixel p through Stockham autosort passes: each pass of
-// radix Q takes butterflies j, reads the points j + r M / Q (r < Q), turns
-// them by exp(2 pi i r k / (S Q)) with k = j mod S (S: the length already
-// transformed), takes a Q-point DFT in registers and leaves point s at
-// (j - k) Q + k + s S.
-//   1. a radix-16 pass straight from the bins: thread g loads X_k and
-//      X_{M-k} for k = g + r G, packs Z_k and needs no turn (S = 1);
-//   2. one more pass when M <= 256 (radix G), two when M > 256 (radix 16,
-//      then M / 256), through LDS rows of P points, one row of padding
-//      after every 16 so that the strided writes of the first pass fall in
-//      distinct banks;
-//   3. the last pass leaves each thread's 16 points z_n in registers: it
-//      rounds them, keeps its top non-zero degree, and the threads of a
-//      pixel combine theirs by shuffles and one LDS maximum per wave.
+// nr (nr/2 + 1) products.  Thread (p, g), p < P, g < G = M / E, holds E
+// points of pixel p (E = 16 for M = 2^a, 24 for M = 3 2^a) through Stockham
+// autosort passes: each pass of radix Q takes butterflies j, reads the points
+// j + r M / Q (r < Q), turns them by exp(2 pi i r k / (S Q)) with k = j mod S
+// (S: the length already transformed), takes a Q-point DFT in registers and
+// leaves point s at (j - k) Q + k + s S.  A work item is the P = 256 E / M
+// pixels of one tile whose transform-domain values are stored in blocks of
+// 16 pixels with the bins contiguous (JobDev::ybs, the only layout these
+// jobs use).
+//   1. a radix-E pass straight from the bins: thread g loads X_k and X_{M-k}
+//      for k = g + r G, packs Z_k and needs no turn (S = 1);
+//   2. one or two more passes (M = 2^a: radix G up to 256, else radix 16
+//      then M / 256; M = 3 2^a: radix min(G, 8), then G / 8), through LDS
+//      rows of P points with one row of padding after every E, so that the
+//      strided writes of the first pass fall in distinct banks;
+//   3. the last pass leaves each thread's points z_n in registers in
+//      increasing n: it rounds them, keeps the index of its last non-zero
+//      degree, and the threads of a pixel combine theirs by shuffles and one
+//      LDS maximum per wave.
 // Every job of one launch has the same range length, so the M twiddles are
 // staged in LDS once per block.
-template <typename R, int LM>
+template <typename R, int M>
 __global__ __launch_bounds__(kDecThreads) void k_decode_fft(const JobDev *__restrict__ jobs,
                                                             const Seg *__restrict__ segs, int nseg,
                                                             long long nitems, float band,
                                                             unsigned int *tile_flags, int2 *fb_list,
                                                             StatsDev *st) {
     using C = typename Cx<R>::T;
-    constexpr int M = 1 << LM, LP = 12 - LM, P = 1 << LP, G = M / 16;
-    constexpr int Q2 = M >= 256 ? 16 : G, Q3 = M > 256 ? M / 256 : 1;
-    constexpr int B2 = 16 / Q2, B3 = 16 / Q3;
-    static_assert(LM >= 6 && LM <= 11 && G * P == kDecThreads, "P = 4096 / M pixels of G threads each");
-    __shared__ C zs[(M + M / 16) * P];
-    __shared__ C tws[M];         // exp(2 pi i m / nr), m < M
-    __shared__ C tw2[M <= 256 ? M : 1];   // exp(2 pi i m / M) for the second pass when M <= 256
+    constexpr bool POW2 = (M & (M - 1)) == 0;
+    constexpr int E = POW2 ? 16 : 24, Q1 = E, G = M / E, P = kDecThreads / G;
+    constexpr int Q2 = POW2 ? (M >= 256 ? 16 : G) : (G < 8 ? G : 8), Q3 = M / (Q1 * Q2);
+    constexpr int B2 = E / Q2, B3 = E / Q3, W = Q1 + 1;
+    static_assert(G * P == kDecThreads && (P & (P - 1)) == 0 && Q1 * Q2 * Q3 == M && E % Q2 == 0 &&
+                      E % Q3 == 0 && (POW2 || sizeof(R) == 4),
+                  "pass plan");
+    __shared__ C zs[(M + M / Q1) * P];   // point n of pixel p at (n + n / E) P + p
+    __shared__ C tws[M];                 // exp(2 pi i m / nr), m < M
+    __shared__ C tw2[Q3 == 1 ? M : 1];   // exp(2 pi i m / M) for a last second pass
     __shared__ int s_top[P];
     __shared__ float s_red[kDecThreads / 64];
-    const int p = threadIdx.x & (P - 1), g = threadIdx.x >> LP;
-    // LDS rows: point n of pixel p at (n + n / 16) P + p; the bases below
-    // leave compile-time steps
-    const int base1 = 17 * g * P + p;                              // n = 16 g + s
-    const int base2 = (M <= 256 ? g : g + (g >> 4)) * P + p;       // n = g + r M / Q2 (+ b G)
-    const int wbase2 = (272 * (g >> 4) + (g & 15)) * P + p;        // n = 256 (g / 16) + g % 16 + 16 s
-    constexpr int rstep2 = (M <= 256 ? 17 : (M / Q2) * 17 / 16) * P, bstep = (M <= 256 ? G : G * 17 / 16) * P;
+    const int p = threadIdx.x & (P - 1), g = threadIdx.x / P;
     auto turn = [&](C x, int m) {   // x exp(2 pi i m / nr), m < nr
-        C w = tws[m & (M - 1)];
+        C w = tws[m % M];
         if (m >= M) {
             w.x = -w.x;
             w.y = -w.y;
@@ -835,9 +886,9 @@ __global__ __launch_bounds__(kDecThreads) void k_decode_fft(const JobDev *__rest
     if (blockIdx.x < nitems) {
         const C *tw = (const C *)jobs[segs[find_seg(segs, nseg, blockIdx.x)].job].rtw;
         for (int m = threadIdx.x; m < M; m += kDecThreads) tws[m] = ldg(tw, m);
-        if constexpr (M <= 256)
+        if constexpr (Q3 == 1)
             for (int m = threadIdx.x; m < M; m += kDecThreads) {
-                C w = ldg(tw, (2 * m) & (M - 1));
+                C w = ldg(tw, (2 * m) % M);
                 if (2 * m >= M) {
                     w.x = -w.x;
                     w.y = -w.y;
@@ -860,16 +911,16 @@ __global__ __launch_bounds__(kDecThreads) void k_decode_fft(const JobDev *__rest
             const int q = p0 + pp, ly = q / T, lx = q - ly * T;
             return q < TT && ty * T + ly < J.H && tx * T + lx < J.W;
         };
-        // 1. radix-16 pass from the bins
+        // 1. radix-E pass from the bins
         const bool pv = pixel_valid(p);
-        C v[16];
+        C v[E];
         {
-            // X_k and X_{M-k} (M - k = G - g + (15 - r) G) through a buffer
+            // X_k and X_{M-k} (M - k = G - g + (E - 1 - r) G) through a buffer
             // resource over the item's 16-pixel blocks: one address register
             // per operand, the bin steps as uniform offsets.  A pixel outside
             // the image reads the bins of the item's first pixel (always
             // stored) and its results are dropped.
-            C a[16], b[16];
+            C a[E], b[E];
             const int pl = pv ? p : 0;
             const int e0 = p0 & 15, blk = (e0 + pl) >> 4, pin = (p0 + pl) & 15;
             const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
@@ -878,12 +929,12 @@ __global__ __launch_bounds__(kDecThreads) void k_decode_fft(const JobDev *__rest
             const unsigned va = (unsigned)(blk * J.ybs + pin + 16 * g) * sizeof(C);
             const unsigned vb = (unsigned)(blk * J.ybs + pin + 16 * (G - g)) * sizeof(C);
 #pragma unroll
-            for (int r = 0; r < 16; ++r) {
+            for (int r = 0; r < E; ++r) {
                 a[r] = buf_load<C>(rs, va, 16 * r * G * sizeof(C));
-                b[r] = buf_load<C>(rs, vb, 16 * (15 - r) * G * sizeof(C));
+                b[r] = buf_load<C>(rs, vb, 16 * (E - 1 - r) * G * sizeof(C));
             }
 #pragma unroll
-            for (int r = 0; r < 16; ++r) {
+            for (int r = 0; r < E; ++r) {
                 // Z_k from (x, y) = (X_k, X_{M-k}): (x + conj y) + i w^k (x - conj y)
                 const C x = a[r], y = b[r], w = tws[g + r * G];
                 const R ox = x.x - y.x, oy = x.y + y.y;
@@ -892,21 +943,22 @@ __global__ __launch_bounds__(kDecThreads) void k_decode_fft(const JobDev *__rest
                 v[r].y = x.y - y.y + wx;
             }
         }
-        reg_dft<R, 16>(v);
+        if constexpr (POW2) reg_dft<R, 16>(v);
+        else reg_dft24<R>(v);
+        const int base1 = W * g * P + p;   // rows E g + s
 #pragma unroll
-        for (int s = 0; s < 16; ++s) zs[base1 + s * P] = v[s];
+        for (int s = 0; s < E; ++s) zs[base1 + s * P] = v[s];
         if (threadIdx.x < P) s_top[threadIdx.x] = -1;
         __syncthreads();
-        // 2. the remaining passes
+        // 2. the remaining passes (S = E, then E Q2)
         C u[B2][Q2];
 #pragma unroll
         for (int b = 0; b < B2; ++b) {
-            const int k = (g + b * G) & 15;
+            const int j = g + b * G, k = j % Q1, rb = (j + j / Q1) * P + p;   // rows j + r E Q3
 #pragma unroll
             for (int r = 0; r < Q2; ++r) {
-                const C x = zs[base2 + b * bstep + r * rstep2];
-                // exp(2 pi i r k / (16 Q2))
-                u[b][r] = r == 0 ? x : M <= 256 ? cmul(x, tw2[r * k]) : turn(x, r * k * (M / 128));
+                const C x = zs[rb + r * Q3 * W * P];
+                u[b][r] = r == 0 ? x : Q3 == 1 ? cmul(x, tw2[r * k]) : turn(x, r * k * (2 * M / (Q1 * Q2)));
             }
             reg_dft<R, Q2>(u[b]);
         }
@@ -914,14 +966,18 @@ __global__ __launch_bounds__(kDecThreads) void k_decode_fft(const JobDev *__rest
         if constexpr (Q3 > 1) {
             __syncthreads();   // every read of the first rows is done
 #pragma unroll
-            for (int s = 0; s < 16; ++s) zs[wbase2 + 17 * s * P] = u[0][s];
+            for (int b = 0; b < B2; ++b) {
+                const int j = g + b * G, k = j % Q1, wb = ((j - k) / Q1 * Q2 * W + k) * P + p;
+#pragma unroll
+                for (int s = 0; s < Q2; ++s) zs[wb + s * W * P] = u[b][s];   // rows (j - k) Q2 + k + s E
+            }
             __syncthreads();
 #pragma unroll
             for (int b = 0; b < B3; ++b) {
-                const int j = g + b * G;
+                const int j = g + b * G, rb = (j + j / Q1) * P + p;   // rows j + r E Q2
 #pragma unroll
                 for (int r = 0; r < Q3; ++r) {
-                    const C x = zs[base2 + b * bstep + 272 * r * P];
+                    const C x = zs[rb + r * Q2 * W * P];
                     w3[b][r] = r == 0 ? x : turn(x, 2 * r * j);   // exp(2 pi i r j / M)
                 }
                 reg_dft<R, Q3>(w3[b]);
@@ -930,7 +986,7 @@ __global__ __launch_bounds__(kDecThreads) void k_decode_fft(const JobDev *__rest
         // 3. round every degree held in registers, in increasing degree
         // order (point n = g + b G + NS s), keeping the index of the last
         // non-zero one
-        constexpr int NB = Q3 > 1 ? B3 : B2, NSP = Q3 > 1 ? Q3 : Q2, NS = Q3 > 1 ? 256 : 16;
+        constexpr int NB = Q3 > 1 ? B3 : B2, NSP = Q3 > 1 ? Q3 : Q2, NS = Q3 > 1 ? Q1 * Q2 : Q1;
         const R scale = (R)J.scale;
         int topi = -1;
         R res = 0;
@@ -1302,21 +1358,25 @@ hipError_t launch_decode(int var, int dbl, const JobDev *jobs, const Seg *segs, 
                          hipStream_t s) {
     if (nitems <= 0) return hipSuccess;
     if (var >= kDecFftVar) {
-#define MD_DFFT(R, LM) \
-    k_decode_fft<R, LM><<<grid, kDecThreads, 0, s>>>(jobs, segs, nseg, nitems, band, tile_flags, fb_list, st); break
-        switch ((dbl ? 100 : 0) + var - kDecFftVar) {
-            case 6: MD_DFFT(float, 6);
-            case 7: MD_DFFT(float, 7);
-            case 8: MD_DFFT(float, 8);
-            case 9: MD_DFFT(float, 9);
-            case 10: MD_DFFT(float, 10);
-            case 11: MD_DFFT(float, 11);
-            case 106: MD_DFFT(double, 6);
-            case 107: MD_DFFT(double, 7);
-            case 108: MD_DFFT(double, 8);
-            case 109: MD_DFFT(double, 9);
-            case 110: MD_DFFT(double, 10);
-            case 111: MD_DFFT(double, 11);
+#define MD_DFFT(R, M) \
+    k_decode_fft<R, M><<<grid, kDecThreads, 0, s>>>(jobs, segs, nseg, nitems, band, tile_flags, fb_list, st); break
+        switch ((dbl ? 100000 : 0) + decode_fft_m(var)) {
+            case 64: MD_DFFT(float, 64);
+            case 128: MD_DFFT(float, 128);
+            case 256: MD_DFFT(float, 256);
+            case 512: MD_DFFT(float, 512);
+            case 1024: MD_DFFT(float, 1024);
+            case 2048: MD_DFFT(float, 2048);
+            case 96: MD_DFFT(float, 96);
+            case 192: MD_DFFT(float, 192);
+            case 384: MD_DFFT(float, 384);
+            case 768: MD_DFFT(float, 768);
+            case 100064: MD_DFFT(double, 64);
+            case 100128: MD_DFFT(double, 128);
+            case 100256: MD_DFFT(double, 256);
+            case 100512: MD_DFFT(double, 512);
+            case 101024: MD_DFFT(double, 1024);
+            case 102048: MD_DFFT(double, 2048);
             default: return hipErrorInvalidValue;
         }
 #undef MD_DFFT

@@ -116,7 +116,7 @@ struct Plan {
     int dbl = 0;
     int nt = 0, T = 0, nr = 0, bins = 0, tiles_x = 0, tiles_y = 0;
     int fb_mode = kFbNone, nt64 = 0, T64 = 0;
-    bool dec_fft = false;          // range-axis FFT decode (decode_uses_fft(nr))
+    bool dec_fft = false;          // range-axis FFT decode (decode_uses_fft(nr, dbl))
     double cost_fft = 0, cost_dir = 0;
 };
 
@@ -547,7 +547,7 @@ int plan_ybs(const Plan &p) { return p.dec_fft ? p.bins * 16 : 0; }
 // 0.73 at 512, 0.85 at 1024; FP64 0.88, 0.55, 0.49, 0.46).
 constexpr double kDecFftRatio[2] = {0.8, 0.5};
 double dec_units(int nr, int dbl) {
-    if (decode_uses_fft(nr)) return kDecFftRatio[dbl ? 1 : 0] * nr * std::log2((double)nr);
+    if (decode_uses_fft(nr, dbl)) return kDecFftRatio[dbl ? 1 : 0] * nr * std::log2((double)nr);
     const double pb = dec_padded_bins(nr / 2 + 1, dbl);
     return pb * pb;
 }
@@ -846,17 +846,22 @@ int plan_job(const md_job &j, const SEData &se, Plan &p, bool lone) {
     // more, so the model is not trusted there); on 2048^2 images the power of
     // two wins from about 150 on (FP32 12.9 against 6.5 ms at 230, FP64 42.1
     // against 17.6 ms).
-    int nrs[2] = {nr, 0};
+    // In FP32 the next length 3 2^a is offered too (fewer bins than the power
+    // of two, same decode).
+    int nrs[3] = {nr, 0, 0};
     if (dbl != kPrecNTT && g.opt.nr <= 0 && nr > 128) {
         int nr2 = 1;
         while (nr2 < nr) nr2 <<= 1;
-        if (nr2 != nr && decode_uses_fft(nr2)) nrs[1] = nr2;
+        if (nr2 != nr && decode_uses_fft(nr2, dbl)) nrs[1] = nr2;
+        int nr3 = 6;
+        while (nr3 < nr) nr3 <<= 1;
+        if (nr3 != nr && nr3 < nr2 && decode_uses_fft(nr3, dbl)) nrs[2] = nr3;
     }
     double best = INFINITY;
     int best_nt = 0, best_nr = nr;
     const bool fft_ok = nr_min <= 4096 && se.ncells > 0 && ntt_ok;
-    for (int c = 0; c < 2 && nrs[c] > 0; ++c)
-        for (int nt = 16; fft_ok && nt <= kMaxN; nt *= 2) {
+    for (int c = 0; c < 3; ++c)
+        for (int nt = 16; fft_ok && nrs[c] > 0 && nt <= kMaxN; nt *= 2) {
             if (g.opt.tile > 0 && nt != g.opt.tile) continue;
             const double cst = fft_cost(j, nt, nrs[c], dbl, lone);
             if (cst < best) {
@@ -867,7 +872,7 @@ int plan_job(const md_job &j, const SEData &se, Plan &p, bool lone) {
         }
     p.nr = best_nr;
     p.bins = dbl == kPrecNTT ? p.nr : p.nr / 2 + 1;
-    p.dec_fft = dbl != kPrecNTT && decode_uses_fft(p.nr);
+    p.dec_fft = dbl != kPrecNTT && decode_uses_fft(p.nr, dbl);
     p.cost_fft = best;
     if (g.opt.path == kPathFFT) {
         if (!fft_ok)
@@ -1148,7 +1153,7 @@ int build_exec(const md_job *jobs, int n, const std::vector<SEData> &ses, Exec &
             // exact: modular products (one per butterfly and per point)
             gf->alg_ops += ntt ? items * (N2 * log2(N2) + N2) : items * (2.0 * 5.0 * N2 * log2(N2) + 6.0 * N2);
             gf->units += items;
-            const int dvar = ntt ? 0 : p.dec_fft ? kDecFftVar + ilog2i(p.nr / 2) : decode_group_variant(p.bins, p.dbl);
+            const int dvar = ntt ? 0 : p.dec_fft ? decode_fft_var(p.nr) : decode_group_variant(p.bins, p.dbl);
             Group *gd = find_group(wv.dec, 0, p.dbl, dvar);
             s.item0 = gd->nitems;
             gd->segs.push_back(s);
@@ -1211,11 +1216,13 @@ int build_exec(const md_job *jobs, int n, const std::vector<SEData> &ses, Exec &
             }
         }
         for (auto &gr : wv.dec) {
-            // the range-axis FFT decode holds 4096 complex values, one row
-            // of padding per 16 rows and its M twiddles in LDS (2 M when M <= 256)
+            // the range-axis FFT decode holds 4096 (M = 2^a) or 6144 (M = 3 2^a)
+            // complex values, one row of padding per 16 or 24 rows, and its M
+            // twiddles in LDS (2 M when the second pass is the last)
             const size_t elem = gr.dbl == kPrecFP64 ? sizeof(double2) : sizeof(float2);
-            const size_t dm = gr.big >= kDecFftVar ? (size_t)1 << (gr.big - kDecFftVar) : 0;
-            const size_t lds = dm ? (4352 + (dm <= 256 ? 2 * dm : dm)) * elem : 0;
+            const size_t dm = gr.big >= kDecFftVar ? (size_t)decode_fft_m(gr.big) : 0;
+            const bool p2 = (dm & (dm - 1)) == 0;
+            const size_t lds = dm ? ((p2 ? 4352 : 6400) + ((p2 ? dm <= 256 : dm <= 192) ? 2 * dm : dm)) * elem : 0;
             place(gr, kDecThreads, lds);
         }
     }
