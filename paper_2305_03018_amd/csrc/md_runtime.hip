@@ -544,10 +544,12 @@ int plan_ybs(const Plan &p) { return p.dec_fft ? p.bins * 16 : 0; }
 // The range-axis FFT decode is priced at kDecFftRatio[precision] of those
 // units per nr log2 nr (time per nr log2 nr over the dense decode's time per
 // unit at nr - 1, on 2048^2 images: FP32 1.37 at nr = 128, 1.08 at 256,
-// 0.73 at 512, 0.85 at 1024; FP64 0.88, 0.55, 0.49, 0.46).
+// 0.73 at 512, 0.85 at 1024; FP64 0.88, 0.55, 0.49, 0.46).  The FP32
+// lengths 3 2^a take 1.4 times that (1.19 at 192, 1.14 at 384, 1.0 at 768).
 constexpr double kDecFftRatio[2] = {0.8, 0.5};
 double dec_units(int nr, int dbl) {
-    if (decode_uses_fft(nr, dbl)) return kDecFftRatio[dbl ? 1 : 0] * nr * std::log2((double)nr);
+    if (decode_uses_fft(nr, dbl))
+        return kDecFftRatio[dbl ? 1 : 0] * (is_pow2c(nr) ? 1.0 : 1.4) * nr * std::log2((double)nr);
     const double pb = dec_padded_bins(nr / 2 + 1, dbl);
     return pb * pb;
 }
