@@ -882,6 +882,12 @@ __global__ __launch_bounds__(kDecThreads) void k_decode_fft(const JobDev *__rest
         }
         return cmul(x, w);
     };
+    // LDS offset of row j + j / E, j = g + b G; for M = 2^a, G / 16 is whole
+    // or zero, so b only adds a compile-time step
+    auto row_base = [&](int b) {
+        const int j = g + b * G;
+        return POW2 ? (g + g / Q1) * P + p + b * (G + G / Q1) * P : (j + j / Q1) * P + p;
+    };
     float run_max = 0.f;
     if (blockIdx.x < nitems) {
         const C *tw = (const C *)jobs[segs[find_seg(segs, nseg, blockIdx.x)].job].rtw;
@@ -954,7 +960,7 @@ __global__ __launch_bounds__(kDecThreads) void k_decode_fft(const JobDev *__rest
         C u[B2][Q2];
 #pragma unroll
         for (int b = 0; b < B2; ++b) {
-            const int j = g + b * G, k = j % Q1, rb = (j + j / Q1) * P + p;   // rows j + r E Q3
+            const int j = g + b * G, k = j % Q1, rb = row_base(b);   // rows j + r E Q3
 #pragma unroll
             for (int r = 0; r < Q2; ++r) {
                 const C x = zs[rb + r * Q3 * W * P];
@@ -974,7 +980,7 @@ __global__ __launch_bounds__(kDecThreads) void k_decode_fft(const JobDev *__rest
             __syncthreads();
 #pragma unroll
             for (int b = 0; b < B3; ++b) {
-                const int j = g + b * G, rb = (j + j / Q1) * P + p;   // rows j + r E Q2
+                const int j = g + b * G, rb = row_base(b);   // rows j + r E Q2
 #pragma unroll
                 for (int r = 0; r < Q3; ++r) {
                     const C x = zs[rb + r * Q2 * W * P];
