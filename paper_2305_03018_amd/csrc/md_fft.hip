@@ -824,8 +824,69 @@ __device__ __forceinline__ void reg_dft24(C (&v)[24]) {
     }
 }
 
+// cos(2 pi m / 20) and sin(2 pi m / 20) for any m >= 0
+__host__ __device__ constexpr double cos20q(int m) {   // m in [0, 5]: 0 .. 90 degrees
+    return m == 0 ? 1.0
+         : m == 1 ? 0.95105651629515357212
+         : m == 2 ? 0.80901699437494742410
+         : m == 3 ? 0.58778525229247312917
+         : m == 4 ? 0.30901699437494742410
+                  : 0.0;
+}
+__host__ __device__ constexpr double cos20(int m) {
+    return (m % 20) <= 5 ? cos20q(m % 20) : (m % 20) <= 10 ? -cos20q(10 - m % 20) : -cos20(m % 20 - 10);
+}
+__host__ __device__ constexpr double sin20(int m) { return cos20(m % 20 + 15); }
+
+// DFT of 20 points in registers, positive exponent, natural order: for
+// r = 5 r2 + r1 and s = s1 + 4 s2, five 4-point DFTs over r2, turns
+// exp(2 pi i r1 s1 / 20), then four 5-point DFTs over r1 (sums and
+// differences of the conjugate pairs r1 = 1, 4 and 2, 3).
+template <typename R, typename C>
+__device__ __forceinline__ void reg_dft20(C (&v)[20]) {
+    C a[5][4];
+#pragma unroll
+    for (int r1 = 0; r1 < 5; ++r1) {
+#pragma unroll
+        for (int r2 = 0; r2 < 4; ++r2) a[r1][r2] = v[5 * r2 + r1];
+        reg_dft<R, 4>(a[r1]);
+#pragma unroll
+        for (int s1 = 1; s1 < 4; ++s1)
+            if (r1 > 0) {
+                const R c = (R)cos20(r1 * s1), sn = (R)sin20(r1 * s1);
+                const C x = a[r1][s1];
+                a[r1][s1].x = c * x.x - sn * x.y;
+                a[r1][s1].y = c * x.y + sn * x.x;
+            }
+    }
+    const R c1 = (R)cos20(4), c2 = (R)cos20(8), s1 = (R)sin20(4), s2 = (R)sin20(8);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const C a0 = a[0][q], t1 = cadd(a[1][q], a[4][q]), t2 = cadd(a[2][q], a[3][q]);
+        const C d1 = csub(a[1][q], a[4][q]), d2 = csub(a[2][q], a[3][q]);
+        C b1, b2, e1, e2;
+        b1.x = a0.x + c1 * t1.x + c2 * t2.x;
+        b1.y = a0.y + c1 * t1.y + c2 * t2.y;
+        b2.x = a0.x + c2 * t1.x + c1 * t2.x;
+        b2.y = a0.y + c2 * t1.y + c1 * t2.y;
+        e1.x = s1 * d1.x + s2 * d2.x;   // e1 = s1 d1 + s2 d2, e2 = s2 d1 - s1 d2
+        e1.y = s1 * d1.y + s2 * d2.y;
+        e2.x = s2 * d1.x - s1 * d2.x;
+        e2.y = s2 * d1.y - s1 * d2.y;
+        v[q] = cadd(a0, cadd(t1, t2));
+        v[q + 4].x = b1.x - e1.y;   // b1 + i e1
+        v[q + 4].y = b1.y + e1.x;
+        v[q + 16].x = b1.x + e1.y;   // b1 - i e1
+        v[q + 16].y = b1.y - e1.x;
+        v[q + 8].x = b2.x - e2.y;   // b2 + i e2
+        v[q + 8].y = b2.y + e2.x;
+        v[q + 12].x = b2.x + e2.y;   // b2 - i e2
+        v[q + 12].y = b2.y - e2.x;
+    }
+}
+
 // Range-axis FFT decode: Step 3 for a range length nr = 2M with M = 2^a
-// (64 to 2048) or, in FP32, M = 3 2^a (96 to 768).  A pixel's coefficient
+// (64 to 2048) or, in FP32, M = 3 2^a (96 to 768) or 5 2^a (80 to 320).  A pixel's coefficient
 // vector is the real inverse DFT of its Hermitian spectrum, of which the
 // bins X_0 .. X_M are kept:
 //   c_d = scale * sum_{m < nr} X_m w^(d m),  w = exp(2 pi i / nr),  X_{nr-m} = conj(X_m).
@@ -834,7 +895,7 @@ __device__ __forceinline__ void reg_dft24(C (&v)[24]) {
 //   z_n = sum_{k<M} Z_k exp(2 pi i k n / M),  c_{2n} = scale Re z_n,  c_{2n+1} = scale Im z_n,
 // about 2.5 nr log2(nr) flops per pixel where the dense decode takes
 // nr (nr/2 + 1) products.  Thread (p, g), p < P, g < G = M / E, holds E
-// points of pixel p (E = 16 for M = 2^a, 24 for M = 3 2^a) through Stockham
+// points of pixel p (E = 16 for M = 2^a, 24 for M = 3 2^a, 20 for M = 5 2^a) through Stockham
 // autosort passes: each pass of radix Q takes butterflies j, reads the points
 // j + r M / Q (r < Q), turns them by exp(2 pi i r k / (S Q)) with k = j mod S
 // (S: the length already transformed), takes a Q-point DFT in registers and
@@ -845,7 +906,8 @@ __device__ __forceinline__ void reg_dft24(C (&v)[24]) {
 //   1. a radix-E pass straight from the bins: thread g loads X_k and X_{M-k}
 //      for k = g + r G, packs Z_k and needs no turn (S = 1);
 //   2. one or two more passes (M = 2^a: radix G up to 256, else radix 16
-//      then M / 256; M = 3 2^a: radix min(G, 8), then G / 8), through LDS
+//      then M / 256; M = 3 2^a: radix min(G, 8), then G / 8; M = 5 2^a:
+//      radix 4, then G / 4), through LDS
 //      rows of P points with one row of padding after every E, so that the
 //      strided writes of the first pass fall in distinct banks;
 //   3. the last pass leaves each thread's points z_n in registers in
@@ -862,8 +924,8 @@ __global__ __launch_bounds__(kDecThreads) void k_decode_fft(const JobDev *__rest
                                                             StatsDev *st) {
     using C = typename Cx<R>::T;
     constexpr bool POW2 = (M & (M - 1)) == 0;
-    constexpr int E = POW2 ? 16 : 24, Q1 = E, G = M / E, P = kDecThreads / G;
-    constexpr int Q2 = POW2 ? (M >= 256 ? 16 : G) : (G < 8 ? G : 8), Q3 = M / (Q1 * Q2);
+    constexpr int E = POW2 ? 16 : M % 3 == 0 ? 24 : 20, Q1 = E, G = M / E, P = kDecThreads / G;
+    constexpr int Q2 = POW2 ? (M >= 256 ? 16 : G) : E == 24 ? (G < 8 ? G : 8) : 4, Q3 = M / (Q1 * Q2);
     constexpr int B2 = E / Q2, B3 = E / Q3, W = Q1 + 1;
     static_assert(G * P == kDecThreads && (P & (P - 1)) == 0 && Q1 * Q2 * Q3 == M && E % Q2 == 0 &&
                       E % Q3 == 0 && (POW2 || sizeof(R) == 4),
@@ -950,7 +1012,8 @@ __global__ __launch_bounds__(kDecThreads) void k_decode_fft(const JobDev *__rest
             }
         }
         if constexpr (POW2) reg_dft<R, 16>(v);
-        else reg_dft24<R>(v);
+        else if constexpr (E == 24) reg_dft24<R>(v);
+        else reg_dft20<R>(v);
         const int base1 = W * g * P + p;   // rows E g + s
 #pragma unroll
         for (int s = 0; s < E; ++s) zs[base1 + s * P] = v[s];
@@ -1377,6 +1440,9 @@ hipError_t launch_decode(int var, int dbl, const JobDev *jobs, const Seg *segs, 
             case 192: MD_DFFT(float, 192);
             case 384: MD_DFFT(float, 384);
             case 768: MD_DFFT(float, 768);
+            case 80: MD_DFFT(float, 80);
+            case 160: MD_DFFT(float, 160);
+            case 320: MD_DFFT(float, 320);
             case 100064: MD_DFFT(double, 64);
             case 100128: MD_DFFT(double, 128);
             case 100256: MD_DFFT(double, 256);

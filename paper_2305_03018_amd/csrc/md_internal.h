@@ -167,24 +167,31 @@ hipError_t launch_fft(int nt, int dbl, const JobDev *jobs, const Seg *segs, int 
 // (both dimensions) of the [bin][degree] decode table for a range length
 int decode_group_variant(int bins, int dbl);
 // Range-axis FFT decode: for nr = 2M with M = 2^a (nr 128..4096, both
-// precisions) or M = 3 2^a (nr 192..1536, FP32).  Its decode variant is
-// kDecFftVar + log2 M for the first, kDecFftVar + 16 + log2(M / 3) for the
-// second, and one work item covers decode_fft_pixels(nr) pixels of a tile.
+// precisions), M = 3 2^a (nr 192..1536, FP32) or M = 5 2^a (nr 160..640,
+// FP32).  Its decode variant is kDecFftVar + log2 M, kDecFftVar + 16 +
+// log2(M / 3) or kDecFftVar + 32 + log2(M / 5), and one work item covers
+// decode_fft_pixels(nr) pixels of a tile (256 E / M for E points per thread:
+// 16, 24 or 20).
 constexpr int kDecFftVar = 16;
 constexpr int kDecFftMinNr = 128, kDecFftMaxNr = 4096;
 constexpr bool is_pow2c(int x) { return x > 0 && (x & (x - 1)) == 0; }
 constexpr int ilog2c(int x) { return x <= 1 ? 0 : 1 + ilog2c(x / 2); }
 constexpr bool decode_uses_fft(int nr, int dbl) {
     return (nr >= kDecFftMinNr && nr <= kDecFftMaxNr && is_pow2c(nr)) ||
-           (dbl == 0 && nr >= 192 && nr <= 1536 && nr % 3 == 0 && is_pow2c(nr / 3));
+           (dbl == 0 && nr >= 192 && nr <= 1536 && nr % 3 == 0 && is_pow2c(nr / 3)) ||
+           (dbl == 0 && nr >= 160 && nr <= 640 && nr % 5 == 0 && is_pow2c(nr / 5));
 }
 constexpr int decode_fft_var(int nr) {
-    return is_pow2c(nr) ? kDecFftVar + ilog2c(nr / 2) : kDecFftVar + 16 + ilog2c(nr / 6);
+    return is_pow2c(nr) ? kDecFftVar + ilog2c(nr / 2)
+         : nr % 3 == 0  ? kDecFftVar + 16 + ilog2c(nr / 6)
+                        : kDecFftVar + 32 + ilog2c(nr / 10);
 }
 constexpr int decode_fft_m(int var) {
-    return var - kDecFftVar < 16 ? 1 << (var - kDecFftVar) : 3 << (var - kDecFftVar - 16);
+    return var - kDecFftVar < 16   ? 1 << (var - kDecFftVar)
+         : var - kDecFftVar < 32 ? 3 << (var - kDecFftVar - 16)
+                                 : 5 << (var - kDecFftVar - 32);
 }
-constexpr int decode_fft_pixels(int nr) { return is_pow2c(nr) ? 8192 / nr : 12288 / nr; }
+constexpr int decode_fft_pixels(int nr) { return is_pow2c(nr) ? 8192 / nr : nr % 3 == 0 ? 12288 / nr : 10240 / nr; }
 int dec_pitch(int nr);
 hipError_t launch_decode(int var, int dbl, const JobDev *jobs, const Seg *segs, int nseg,
                          long long nitems, int grid, float band, unsigned int *tile_flags,

@@ -545,11 +545,13 @@ int plan_ybs(const Plan &p) { return p.dec_fft ? p.bins * 16 : 0; }
 // units per nr log2 nr (time per nr log2 nr over the dense decode's time per
 // unit at nr - 1, on 2048^2 images: FP32 1.37 at nr = 128, 1.08 at 256,
 // 0.73 at 512, 0.85 at 1024; FP64 0.88, 0.55, 0.49, 0.46).  The FP32
-// lengths 3 2^a take 1.4 times that (1.19 at 192, 1.14 at 384, 1.0 at 768).
+// lengths 3 2^a take 1.4 times that (1.19 at 192, 1.14 at 384, 1.0 at 768),
+// the lengths 5 2^a 1.3 times (1.38 at 160, 1.05 at 320, 0.78 at 640).
 constexpr double kDecFftRatio[2] = {0.8, 0.5};
 double dec_units(int nr, int dbl) {
     if (decode_uses_fft(nr, dbl))
-        return kDecFftRatio[dbl ? 1 : 0] * (is_pow2c(nr) ? 1.0 : 1.4) * nr * std::log2((double)nr);
+        return kDecFftRatio[dbl ? 1 : 0] * (is_pow2c(nr) ? 1.0 : nr % 3 == 0 ? 1.4 : 1.3) * nr *
+               std::log2((double)nr);
     const double pb = dec_padded_bins(nr / 2 + 1, dbl);
     return pb * pb;
 }
@@ -848,9 +850,9 @@ int plan_job(const md_job &j, const SEData &se, Plan &p, bool lone) {
     // more, so the model is not trusted there); on 2048^2 images the power of
     // two wins from about 150 on (FP32 12.9 against 6.5 ms at 230, FP64 42.1
     // against 17.6 ms).
-    // In FP32 the next length 3 2^a is offered too (fewer bins than the power
-    // of two, same decode).
-    int nrs[3] = {nr, 0, 0};
+    // In FP32 the next lengths 3 2^a and 5 2^a are offered too when shorter
+    // (fewer bins than the power of two, the same decode).
+    int nrs[4] = {nr, 0, 0, 0};
     if (dbl != kPrecNTT && g.opt.nr <= 0 && nr > 128) {
         int nr2 = 1;
         while (nr2 < nr) nr2 <<= 1;
@@ -858,11 +860,14 @@ int plan_job(const md_job &j, const SEData &se, Plan &p, bool lone) {
         int nr3 = 6;
         while (nr3 < nr) nr3 <<= 1;
         if (nr3 != nr && nr3 < nr2 && decode_uses_fft(nr3, dbl)) nrs[2] = nr3;
+        int nr5 = 10;
+        while (nr5 < nr) nr5 <<= 1;
+        if (nr5 != nr && nr5 < nr2 && nr5 < nr3 && decode_uses_fft(nr5, dbl)) nrs[3] = nr5;
     }
     double best = INFINITY;
     int best_nt = 0, best_nr = nr;
     const bool fft_ok = nr_min <= 4096 && se.ncells > 0 && ntt_ok;
-    for (int c = 0; c < 3; ++c)
+    for (int c = 0; c < 4; ++c)
         for (int nt = 16; fft_ok && nrs[c] > 0 && nt <= kMaxN; nt *= 2) {
             if (g.opt.tile > 0 && nt != g.opt.tile) continue;
             const double cst = fft_cost(j, nt, nrs[c], dbl, lone);
@@ -1218,13 +1223,15 @@ int build_exec(const md_job *jobs, int n, const std::vector<SEData> &ses, Exec &
             }
         }
         for (auto &gr : wv.dec) {
-            // the range-axis FFT decode holds 4096 (M = 2^a) or 6144 (M = 3 2^a)
-            // complex values, one row of padding per 16 or 24 rows, and its M
-            // twiddles in LDS (2 M when the second pass is the last)
+            // the range-axis FFT decode holds 256 E complex values (E = 16, 24
+            // or 20 points per thread), one row of padding per E rows, and its
+            // M twiddles in LDS (2 M when the second pass is the last)
             const size_t elem = gr.dbl == kPrecFP64 ? sizeof(double2) : sizeof(float2);
             const size_t dm = gr.big >= kDecFftVar ? (size_t)decode_fft_m(gr.big) : 0;
-            const bool p2 = (dm & (dm - 1)) == 0;
-            const size_t lds = dm ? ((p2 ? 4352 : 6400) + ((p2 ? dm <= 256 : dm <= 192) ? 2 * dm : dm)) * elem : 0;
+            const bool p2 = (dm & (dm - 1)) == 0, m3 = dm % 3 == 0;
+            const size_t pts = p2 ? 4352 : m3 ? 6400 : 5376;
+            const bool last2 = p2 ? dm <= 256 : m3 ? dm <= 192 : dm <= 80;
+            const size_t lds = dm ? (pts + (last2 ? 2 * dm : dm)) * elem : 0;
             place(gr, kDecThreads, lds);
         }
     }

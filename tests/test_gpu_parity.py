@@ -260,7 +260,7 @@ def test_direct_packed_forms(dev):
 
 def test_range_fft_decode(dev):
     """Power-of-two range lengths from 128 to 4096, and in FP32 the lengths
-    3 2^a from 192 to 1536, decode by a range-axis FFT (even and odd
+    3 2^a from 192 to 1536 and 5 2^a from 160 to 640, decode by a range-axis FFT (even and odd
     coefficients from one complex inverse transform of half length) instead
     of the dense inverse DFT.  Forced lengths in both
     precisions, erosion, several tiles with ragged edges, and the exact
@@ -274,11 +274,16 @@ def test_range_fft_decode(dev):
         (70, 260, 900, 5, 0.8, 100, 1, 1024),
         (40, 90, 1800, 3, 1.0, 200, 0, 2048),
         (60, 70, 4000, 3, 1.0, 90, 0, 4096),
-        # 3 2^a lengths (the FP32 FFT decode; FP64 decodes them densely)
+        # 3 2^a lengths (the FP32 FFT decode; FP64 decodes them, and the 5 2^a
+        # lengths below, densely)
         (120, 170, 150, 9, 0.6, 40, 0, 192),
         (100, 150, 300, 11, 0.7, 80, 1, 384),
         (64, 200, 600, 5, 0.9, 160, 0, 768),
         (50, 80, 1200, 3, 1.0, 300, 1, 1536),
+        # 5 2^a lengths (FP32 FFT decode)
+        (110, 160, 120, 7, 0.6, 35, 1, 160),
+        (90, 140, 250, 9, 0.7, 60, 0, 320),
+        (60, 150, 500, 5, 0.9, 130, 1, 640),
     ]
     for H, W, L, k, p, max_off, op, nr in cases:
         job = _with_top(synthetic.random_job(rng, H, W, L, k, p=p, max_off=max_off, op=op), max_off)
@@ -303,7 +308,7 @@ def test_planner_picks_fft_decode(dev):
         want = oracle.run_job(job)
         for opts in (FFT32, FFT64):
             st = assert_parity(job, dev, want=want, **opts)
-            assert st["n_r"] in (int((mask * off).max()) + 256, 384, 512), st
+            assert st["n_r"] in (int((mask * off).max()) + 256, 320, 384, 512), st
     # a range length between 128 and 256: the smallest length or 256
     img = rng.integers(0, 115, (260, 230)).astype(np.int32)
     off = (rng.integers(0, 116, (31, 31)) * mask).astype(np.int32)
