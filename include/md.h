@@ -88,10 +88,11 @@ typedef enum {
     MD_OPT_NR = 4,         /* 0: auto, else the range-axis DFT length; must be at
                               least (L-1) + max offset + 1.  FP paths decode a
                               length 2^a from 128 to 4096 (and FP32 a length
-                              3 2^a from 192 to 1536) by an FFT along the range
-                              axis, any other by a dense DFT; auto weighs the
-                              smallest length against the next such lengths
-                              once the smallest passes 128                      */
+                              3 2^a from 192 to 1536 or 5 2^a from 160 to 640)
+                              by an FFT along the range axis, any other by a
+                              dense DFT; auto weighs the smallest length
+                              against the next such lengths once the smallest
+                              passes 128                                        */
     MD_OPT_SYNC = 5,       /* 1 (default): wait for completion in every call    */
     MD_OPT_GRAPH = 6,      /* 1 (default): md_dilate_batch captures its launches
                               in a HIP graph per batch signature and replays it  */
