@@ -886,30 +886,30 @@ __device__ __forceinline__ void reg_dft20(C (&v)[20]) {
 }
 
 // Range-axis FFT decode: Step 3 for a range length nr = 2M with M = 2^a
-// (64 to 2048) or, in FP32, M = 3 2^a (96 to 768) or 5 2^a (80 to 320).  A pixel's coefficient
-// vector is the real inverse DFT of its Hermitian spectrum, of which the
-// bins X_0 .. X_M are kept:
+// (64 to 2048) or, in FP32, M = 3 2^a (96 to 768) or 5 2^a (80 to 320).
+// A pixel's coefficient vector is the real inverse DFT of its Hermitian
+// spectrum, of which the bins X_0 .. X_M are kept:
 //   c_d = scale * sum_{m < nr} X_m w^(d m),  w = exp(2 pi i / nr),  X_{nr-m} = conj(X_m).
 // Its even and odd samples are one complex inverse DFT of length M:
 //   Z_k = (X_k + conj(X_{M-k})) + i w^k (X_k - conj(X_{M-k})),  k < M,
 //   z_n = sum_{k<M} Z_k exp(2 pi i k n / M),  c_{2n} = scale Re z_n,  c_{2n+1} = scale Im z_n,
 // about 2.5 nr log2(nr) flops per pixel where the dense decode takes
 // nr (nr/2 + 1) products.  Thread (p, g), p < P, g < G = M / E, holds E
-// points of pixel p (E = 16 for M = 2^a, 24 for M = 3 2^a, 20 for M = 5 2^a) through Stockham
-// autosort passes: each pass of radix Q takes butterflies j, reads the points
-// j + r M / Q (r < Q), turns them by exp(2 pi i r k / (S Q)) with k = j mod S
-// (S: the length already transformed), takes a Q-point DFT in registers and
-// leaves point s at (j - k) Q + k + s S.  A work item is the P = 256 E / M
-// pixels of one tile whose transform-domain values are stored in blocks of
-// 16 pixels with the bins contiguous (JobDev::ybs, the only layout these
-// jobs use).
+// points of pixel p (E = 16 for M = 2^a, 24 for M = 3 2^a, 20 for
+// M = 5 2^a) through Stockham autosort passes: each pass of radix Q takes
+// butterflies j, reads the points j + r M / Q (r < Q), turns them by
+// exp(2 pi i r k / (S Q)) with k = j mod S (S: the length already
+// transformed), takes a Q-point DFT in registers and leaves point s at
+// (j - k) Q + k + s S.  A work item is the P = 256 E / M pixels of one tile
+// whose transform-domain values are stored in blocks of 16 pixels with the
+// bins contiguous (JobDev::ybs, the only layout these jobs use).
 //   1. a radix-E pass straight from the bins: thread g loads X_k and X_{M-k}
 //      for k = g + r G, packs Z_k and needs no turn (S = 1);
 //   2. one or two more passes (M = 2^a: radix G up to 256, else radix 16
 //      then M / 256; M = 3 2^a: radix min(G, 8), then G / 8; M = 5 2^a:
-//      radix 4, then G / 4), through LDS
-//      rows of P points with one row of padding after every E, so that the
-//      strided writes of the first pass fall in distinct banks;
+//      radix 4, then G / 4), through LDS rows of P points with one row of
+//      padding after every E, so that the strided writes of the first pass
+//      fall in distinct banks;
 //   3. the last pass leaves each thread's points z_n in registers in
 //      increasing n: it rounds them, keeps the index of its last non-zero
 //      degree, and the threads of a pixel combine theirs by shuffles and one
