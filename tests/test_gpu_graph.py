@@ -32,23 +32,27 @@ def batch_jobs(rng):
             for i, (H, W, L, k) in enumerate(shapes)]
 
 
-def fft_decode_jobs(rng):
-    """Range lengths 128 and 512 (forced below): the range-axis FFT decode and
-    its pixel-block layout of the transform-domain tiles."""
+def fft_decode_jobs(rng, nr):
+    """Jobs for a forced range length nr (512, or the FP32 lengths 320 and
+    384): the range-axis FFT decode and its pixel-block layout of the
+    transform-domain tiles."""
+    L2, off2 = (256, 255) if nr >= 512 else (200, 100)
     return [synthetic.random_job(rng, 150, 170, 100, 7, p=0.7, max_off=27, op=0),
-            synthetic.random_job(rng, 90, 260, 256, 15, p=0.5, max_off=255, op=1)]
+            synthetic.random_job(rng, 90, 260, L2, 15, p=0.5, max_off=off2, op=1)]
 
 
 @pytest.mark.parametrize("mode", ["auto", "fft32", "recompute_all", "ntt", "direct", "fft_decode32",
-                                  "fft_decode64"])
+                                  "fft_decode64", "fft_decode32_n320", "fft_decode32_n384"])
 def test_graph_replays(dev, mode):
     import torch
 
     opts = {"auto": {}, "fft32": dict(precision=0, path=1), "recompute_all": dict(precision=0, path=1, band=0.0),
             "ntt": dict(precision=2, path=1), "direct": dict(path=2),
-            "fft_decode32": dict(precision=0, path=1, nr=512), "fft_decode64": dict(precision=1, path=1, nr=512)}[mode]
+            "fft_decode32": dict(precision=0, path=1, nr=512), "fft_decode64": dict(precision=1, path=1, nr=512),
+            "fft_decode32_n320": dict(precision=0, path=1, nr=320),
+            "fft_decode32_n384": dict(precision=0, path=1, nr=384)}[mode]
     rng = np.random.default_rng(71)
-    jobs = fft_decode_jobs(rng) if mode.startswith("fft_decode") else batch_jobs(rng)
+    jobs = fft_decode_jobs(rng, opts["nr"]) if mode.startswith("fft_decode") else batch_jobs(rng)
     imgs = [torch.from_numpy(j.img).to(dev) for j in jobs]
     side = torch.randn(512, 512, device=dev)
     stream = torch.cuda.Stream()   # graphs are captured on a non-default stream only
