@@ -3,20 +3,24 @@
 Workload (default): the uneven batch -- 256 seeded synthetic images with
 sides uniform in [128, 1024], L in {8, 16, 32, 64}, odd SE sides 3..41 with
 disk / square / Bernoulli(0.6) masks and offsets in [0, L/4] -- run as one
-md_dilate_batch call per step (planner + autotuned FFT/direct crossover,
-FP32 transforms with split twiddles and exact FP64 recompute of ambiguous
-tiles, HIP-graph replay).  Inputs are resident in HBM before timing starts.
+md_dilate_batch call per step.  Inputs are resident in HBM before timing
+starts.
 
-Also measured on the same batch: the plain FP64 FFT path (every job forced
-through FP64 transforms), the FP32 FFT path forced for every job, the exact
-mod-p transform path, and the direct window for every job; a 2048^2 image
+Headline (`value`): every job through the transform path (the paper's
+Steps 1-3: one-hot umbra encode, FFT convolution, top-degree decode) with
+FP32 transforms and split twiddles, the exact tiers behind them (FP64
+recompute of tiles that fail the decode's checks, then the integer window),
+HIP-graph replay.  Beside it in the same line: the plain FP64 transform path
+on the same batch and the ratio; the autotuned batch (which picks the
+classical window for every job of this batch) as a named extra; the exact
+mod-p path, the window forced, the recompute of every tile; a 2048^2 image
 with 4 grey levels and a 127 x 127 disk, where the transform path beats the
-window; the volume
-path (three image axes) on a 128 x 256 x 256 volume; and a 16384^2 image in
-pinned host memory streamed through the GPU in bands (PCIe included; a
-context figure, never the headline value).  A profiled pass (HIP events around every
-launch) gives the dominant kernel's average duration for the roofline
-figure; the CPU oracle is timed on a bounded prefix of the batch.
+window; the volume path; and a 16384^2 image streamed from host memory
+(PCIe included; a context figure).  Every output of the headline and of
+the FP64 leg is compared with the CPU oracle, all pixels of all 256 jobs;
+the oracle's run over the batch is the CPU baseline.  A profiled pass (HIP
+events on the library stream around every launch) gives the dominant
+kernel's average launch duration for the roofline figure.
 
 Prints one JSON line on stdout; progress goes to stderr.
 """
@@ -39,6 +43,7 @@ HBM_PEAK_GBS = 8000.0
 FP32_VECTOR_TFLOPS = 157.3
 FP64_VECTOR_TFLOPS = 78.6
 CUS, CLOCK_GHZ, LANES_PER_CU = 256, 2.4, 64
+FP32_NONPACKED_TFLOPS = CUS * LANES_PER_CU * 2 * CLOCK_GHZ / 1000.0   # one FMA per lane per clock
 INT32_ALU_TOPS = CUS * LANES_PER_CU * CLOCK_GHZ / 1000.0   # one 32-bit integer op per lane per clock
 INT16X2_ALU_TOPS = 2 * INT32_ALU_TOPS                       # packed 16-bit: two ops per lane per clock
 # packed f16 window: two packed adds and one packed three-way max take two SE
@@ -150,7 +155,10 @@ def measured_traffic(kernel, workload):
     taken."""
     import hashlib
 
-    path = os.path.join(ROOT, "profiles", f"{kernel.split('<')[0]}_{workload}_traffic.txt")
+    inst = kernel.replace("<", "_").replace(">", "").replace(", ", "_")
+    path = os.path.join(ROOT, "profiles", f"{inst}_{workload}_traffic.txt")
+    if not os.path.exists(path):
+        path = os.path.join(ROOT, "profiles", f"{kernel.split('<')[0]}_{workload}_traffic.txt")
     if not os.path.exists(path):
         return None
     rec = {}
@@ -188,8 +196,25 @@ def roofline_for(stage, prof, workload, launch_ms=None):
         peak = INT32_ALU_TOPS / 9.0
         return {"bound": "alu", "peak": peak, "unit": "T modmul/s", "frac": achieved / peak, **base}
     fp64 = stage.startswith(("fft64", "decode64", "recompute64"))
-    peak = FP64_VECTOR_TFLOPS if fp64 else FP32_VECTOR_TFLOPS
-    return {"bound": "alu", "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak, **base}
+    if fp64:
+        return {"bound": "alu", "peak": FP64_VECTOR_TFLOPS, "unit": "TFLOP/s",
+                "frac": achieved / FP64_VECTOR_TFLOPS, **base}
+    # FP32: the kernels are built without packed FP32 instructions, so the
+    # vector ALU's FMA rate is 256 CUs x 64 lanes x 2 flops x 2.4 GHz; the
+    # published 157.3 counts packed FP32
+    out = {"bound": "alu", "peak": FP32_NONPACKED_TFLOPS, "unit": "TFLOP/s",
+           "frac": achieved / FP32_NONPACKED_TFLOPS, "peak_published_fp32": FP32_VECTOR_TFLOPS,
+           "frac_published_fp32": achieved / FP32_VECTOR_TFLOPS, **base}
+    if stage.startswith("fft32"):
+        # the transform-domain volume a two-pass (unfused) design would move:
+        # nt^2 complex FP32 values per (tile, bin) item, V = (nt/T)^2 bins per
+        # output pixel; the fused kernel keeps it in LDS
+        n = int(stage.split("_n")[1])
+        vol = rec["units"] / rec["launches"] * n * n * 8.0
+        gbs = vol / (per_launch_ms * 1e-3) / 1e9
+        out["volume_view"] = {"bytes_per_launch": vol, "achieved_GBs": gbs, "peak_GBs": HBM_PEAK_GBS,
+                              "frac": gbs / HBM_PEAK_GBS}
+    return out
 
 
 def volume_leg(md, torch, dev, stream, steps):
@@ -414,16 +439,44 @@ def cpu_baseline(jobs, budget_s):
             "sample": f"first {n} of {len(jobs)} jobs ({px} px), {dt:.1f} s, direct max over the SE (C, OpenMP)"}
 
 
+def parity_full(jobs, outs, wants, what):
+    """Every pixel of every job against the oracle."""
+    for q, (j, o, w) in enumerate(zip(jobs, outs, wants)):
+        got = o.cpu().numpy()
+        if not np.array_equal(got, w):
+            raise SystemExit(f"bench: parity failure ({what}) on job {q} ({j.name}): "
+                             f"{int((got != w).sum())} pixels differ")
+
+
+def leg_stats(md, batch, **opts):
+    """One synchronised call of a forced leg and its statistics."""
+    with md.options(sync=1, **opts):
+        batch.run()
+        return md.get_stats()
+
+
+def profiled(md, batch, calls, **opts):
+    """Per-stage event times of `calls` synchronised calls without a graph."""
+    md.profile_reset()
+    with md.options(profile=1, graph=0, sync=1, **opts):
+        for _ in range(calls):
+            batch.run()
+    sp = md.profile_get()
+    md.profile_reset()
+    return sp
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="uneven_batch")
-    ap.add_argument("--cpu-budget", type=float, default=12.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-compare", action="store_true")
-    ap.add_argument("--leg", choices=["fft64", "fft32", "ntt", "direct", "fft32_recompute_all"],
+    ap.add_argument("--paper-shapes", action="store_true",
+                    help="also run the paper's own timing shapes through the auto path (context only)")
+    ap.add_argument("--leg", choices=sorted(LEG_OPTS),
                     help="run only this forced path on the batch (warm-up, --steps timed steps, one profiled "
                          "step) and print its own JSON line; for hardware-counter runs of its kernels")
     ap.add_argument("--copy-probe", action="store_true",
@@ -453,7 +506,6 @@ def main():
     outs = [torch.empty_like(t) for t in imgs]
     arglist = [(im, j.mask, j.off, j.L, j.op) for im, j in zip(imgs, jobs)]
     stream = torch.cuda.Stream()
-    res = {}
     if args.leg:
         opts = LEG_OPTS[args.leg]
         with torch.cuda.stream(stream):
@@ -462,96 +514,79 @@ def main():
             with md.options(precision=0, path=0):
                 md.dilate_batch(arglist, outs=outs)
             m = timed_steps(md, torch, stream, arglist, outs, args.steps, args.warmup, **opts)
-            md.profile_reset()
-            with md.options(profile=1, graph=0, sync=1, **opts):
-                md.dilate_batch(arglist, outs=outs)
-            sp = md.profile_get()
-            md.profile_reset()
+            sp = profiled(md, md.Batch(arglist, outs), 1, **opts)
         print(json.dumps({"leg": args.leg, "workload": args.workload, "ms_per_step": m,
                           "stages": {st: roofline_for(st, sp, args.workload) for st in sp if sp[st]["alg_ops"] > 0}}),
               flush=True)
         md.release()
         return
+    import oracle
+
+    # the oracle over the whole batch: parity reference for every leg, and
+    # the CPU baseline (its wall time on all host threads)
+    log("bench: oracle over the batch")
+    t0 = time.perf_counter()
+    wants = [oracle.run_job(j) for j in jobs]
+    cpu_s = time.perf_counter() - t0
+    head = LEG_OPTS["fft32"]
+    res = {}
     with torch.cuda.stream(stream):
-        # cold call: calibration first (one small auto-path call), then the
-        # batch's first call builds its plans, SE spectra and graph
+        # calibration first (one small auto-path call), then the headline
+        # leg's first call builds its plans, SE spectra and graph
         with md.options(sync=1, precision=0, path=0):
             md.dilate_batch(arglist[:1], outs=outs[:1])
+        with md.options(sync=1, **head):
             t0 = time.perf_counter()
             md.dilate_batch(arglist, outs=outs)
             res["cold_ms"] = (time.perf_counter() - t0) * 1e3
-        log(f"bench: cold batch call {res['cold_ms']:.1f} ms")
-        # headline: autotuned batch, FP32 + exact recompute, graph replay
+        log(f"bench: cold call of the FP32 transform leg {res['cold_ms']:.1f} ms")
+        batch = md.Batch(arglist, outs)
+        # headline: FP32 transforms + exact tiers, graph replay
         host = {}
-        ms = timed_steps(md, torch, stream, arglist, outs, args.steps, args.warmup, host=host, precision=0, path=0)
-        res["headline_ms"] = ms
-        res["host_ms"] = host["ms"]
-        log(f"bench: host time per call {host['ms']:.3f} ms")
-        with md.options(sync=1, precision=0, path=0):
-            md.dilate_batch(arglist, outs=outs)
-            stats = md.get_stats()
-        log(f"bench: headline {ms:.3f} ms/step, stats {stats}")
-        # spot parity against the oracle on a few jobs (sampled pixels)
-        import oracle
-
-        rng = np.random.default_rng(7)
-        for q in range(0, len(jobs), max(1, len(jobs) // 8)):
-            j = jobs[q]
-            H, W = j.img.shape
-            ys, xs = rng.integers(0, H, 512), rng.integers(0, W, 512)
-            want = oracle.at(j.img, j.mask, j.off, j.L, j.op, ys, xs)
-            got = outs[q].cpu().numpy()[ys, xs]
-            if not np.array_equal(got, want):
-                raise SystemExit(f"bench: parity failure on job {q} ({j.name})")
+        ms = timed_steps(md, torch, stream, arglist, outs, args.steps, args.warmup, host=host, **head)
+        stats = leg_stats(md, batch, **head)
+        parity_full(jobs, outs, wants, "fp32 transform leg")
+        log(f"bench: FP32 transform leg {ms:.3f} ms/step, host {host['ms']:.3f} ms per call, stats {stats}")
+        # the plain FP64 transform path on the same batch
+        ms64 = timed_steps(md, torch, stream, arglist, outs, max(3, args.steps // 2), 1, **LEG_OPTS["fft64"])
+        stats64 = leg_stats(md, batch, **LEG_OPTS["fft64"])
+        parity_full(jobs, outs, wants, "fp64 transform leg")
+        log(f"bench: FP64 transform leg {ms64:.3f} ms/step, stats {stats64}")
+        # per-stage event times of the headline leg (the roofline's launch
+        # durations) and of the FP64 leg
+        prof = profiled(md, batch, max(2, args.steps // 4), **head)
+        prof64 = profiled(md, batch, 2, **LEG_OPTS["fft64"])
+        log(f"bench: profile {json.dumps(prof)}")
         cmp = {}
         if not args.no_compare:
-            for name, opts in LEG_OPTS.items():
+            for name, opts in (("autotuned", dict(precision=0, path=0)), ("direct", LEG_OPTS["direct"]),
+                               ("ntt", LEG_OPTS["ntt"]), ("fft32_recompute_all", LEG_OPTS["fft32_recompute_all"])):
                 m = timed_steps(md, torch, stream, arglist, outs, max(3, args.steps // 4), 1, **opts)
-                cmp[name] = {"ms_per_step": m, "mpx_s": total_px / (m * 1e-3) / 1e6}
-                # per-stage figures of this path (events around every launch)
-                md.profile_reset()
-                with md.options(profile=1, graph=0, sync=1, **opts):
-                    for _ in range(2):
-                        md.dilate_batch(arglist, outs=outs)
-                sp = md.profile_get()
-                md.profile_reset()
-                cmp[name]["stages"] = {
-                    st: {k: v for k, v in roofline_for(st, sp, args.workload).items() if k != "traffic"}
-                    for st in sp if sp[st]["alg_ops"] > 0}
-                rec = {st: v for st, v in sp.items() if st.startswith("recompute")}
-                if rec and name == "fft32_recompute_all":
-                    # the recompute's work is known only on the device (its tile
-                    # list): time per recomputed tile
-                    with md.options(sync=1, graph=0, **opts):
-                        md.dilate_batch(arglist, outs=outs)
-                        tiles = md.get_stats()["fallback_tiles"]
+                st = leg_stats(md, batch, **opts)
+                parity_full(jobs, outs, wants, name)
+                sp = profiled(md, batch, 2, **opts)
+                cmp[name] = {"ms_per_step": m, "mpx_s": total_px / (m * 1e-3) / 1e6,
+                             "stats": {k: st[k] for k in ("fft_jobs", "direct_jobs", "tiles", "fallback_tiles",
+                                                          "window_tiles", "max_residual")},
+                             "stages": {q: {k: v for k, v in roofline_for(q, sp, args.workload).items()
+                                            if k != "traffic"} for q in sp if sp[q]["alg_ops"] > 0}}
+                if name == "fft32_recompute_all":
+                    rec = {q: v for q, v in sp.items() if q.startswith("recompute")}
                     ms_rec = sum(v["ms"] for v in rec.values()) / 2
-                    cmp[name]["recompute"] = {"tiles": tiles, "ms_per_step": ms_rec,
-                                              "us_per_tile": ms_rec * 1e3 / max(1, tiles),
-                                              "stages_ms_per_step": {st: v["ms"] / 2 for st, v in rec.items()}}
+                    cmp[name]["recompute"] = {"tiles": st["fallback_tiles"], "ms_per_step": ms_rec,
+                                              "us_per_tile": ms_rec * 1e3 / max(1, st["fallback_tiles"])}
                 log(f"bench: {name} {m:.3f} ms/step")
             cmp["volume"] = volume_leg(md, torch, dev, stream, max(3, args.steps // 4))
             cmp["large_se"] = large_se_leg(md, torch, dev, stream, 3)
             cmp["host_stream"] = host_stream_leg(md, torch, dev, 3)
-            cmp["paper_shapes"] = paper_shapes_leg(md, torch, dev, stream, 3)
-        # profiled pass for the roofline (events around every launch, no graph)
-        md.profile_reset()
-        with md.options(profile=1, graph=0, sync=1, precision=0, path=0):
-            for _ in range(args.steps):
-                md.dilate_batch(arglist, outs=outs)
-        prof = md.profile_get()
-        md.profile_reset()
-        log(f"bench: profile {json.dumps(prof)}")
-    dominant = max(prof, key=lambda k: prof[k]["ms"])
-    # the dominant kernel's launch time in the timed region: the HIP-event
-    # step time there times the stage's share of the profiled step (the
-    # profiled calls run synchronised, one at a time, outside that region)
-    share = prof[dominant]["ms"] / sum(v["ms"] for v in prof.values())
-    timed_launch_ms = res["headline_ms"] * share
-    roof = roofline_for(dominant, prof, args.workload, launch_ms=timed_launch_ms)
-    roof["share_of_step"] = share
-    roof["profiled_launch_ms"] = prof[dominant]["ms"] / prof[dominant]["launches"]
-    value = total_px / (res["headline_ms"] * 1e-3) / 1e6
+            if args.paper_shapes:
+                cmp["paper_shapes"] = paper_shapes_leg(md, torch, dev, stream, 3)
+        spec_err = spectrum_error(md, torch, dev)
+    fft_stages = [k for k in prof if k.startswith("fft32")]
+    dominant = max(fft_stages or list(prof), key=lambda k: prof[k]["ms"])
+    roof = roofline_for(dominant, prof, args.workload)
+    roof["share_of_step"] = prof[dominant]["ms"] / sum(v["ms"] for v in prof.values())
+    value = total_px / (ms * 1e-3) / 1e6
     line = {
         "metric": "exact dilated Mpixels/s, batched FP32+fallback vs FP64 FFT path, 1 MI355X",
         "value": value,
@@ -559,37 +594,44 @@ def main():
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": res["headline_ms"],
+        "ms_per_step": ms,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "+".join(sorted({stage_dtype(k) for k in prof})),
+        "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": args.workload, "jobs": len(jobs), "pixels": total_px,
-                   "precision": "fp32 split twiddles + exact fp64 recompute", "path": "autotuned fft/direct",
+                   "path": "transform (umbra FFT convolution) for every job",
+                   "precision": "fp32 split twiddles; exact tiers: fp64 recompute, then integer window",
                    "launch": "hipGraph replay of stage-wise persistent kernels"},
+        "fp64_fft": {"ms_per_step": ms64, "mpx_s": total_px / (ms64 * 1e-3) / 1e6,
+                     "stages": {k: {q: v for q, v in roofline_for(k, prof64, args.workload).items() if q != "traffic"}
+                                for k in prof64 if prof64[k]["alg_ops"] > 0}},
+        "speedup_vs_fp64_fft": ms64 / ms,
         "roofline": roof,
-        "stats": {k: stats[k] for k in ("max_residual", "tiles", "fallback_tiles", "unresolved_tiles",
-                                        "fft_jobs", "direct_jobs")},
-        "compare": cmp,
-        "stage_ms_per_step": {k: v["ms"] / args.steps for k, v in prof.items()},
+        "stats": {"max_residual": stats["max_residual"], "tiles": stats["tiles"],
+                  "fallback_tiles": stats["fallback_tiles"], "window_tiles": stats["window_tiles"],
+                  "fallback_fraction": stats["fallback_tiles"] / max(1, stats["tiles"]),
+                  "fft_jobs": stats["fft_jobs"], "direct_jobs": stats["direct_jobs"],
+                  "fp64_max_residual": stats64["max_residual"], "spectrum_error": spec_err,
+                  "parity": "all pixels of all jobs equal the oracle (fp32 and fp64 legs"
+                            + (", and every compare leg)" if cmp else ")")},
+        "stage_ms_per_step": {k: v["ms"] / max(2, args.steps // 4) for k, v in prof.items()},
         "cold_ms": res["cold_ms"],
-        "host_ms_per_call": res["host_ms"],
+        "host_ms_per_call": host["ms"],
+        "compare": cmp,
         "cost_model": md.cost_model(),
     }
-    if cmp:
-        line["speedup_vs_fp64_fft"] = cmp["fft64"]["ms_per_step"] / res["headline_ms"]
-        line["fp32_fft_vs_fp64_fft"] = cmp["fft64"]["ms_per_step"] / cmp["fft32"]["ms_per_step"]
-        line["exact_ntt_vs_fp64_fft"] = cmp["fft64"]["ms_per_step"] / cmp["ntt"]["ms_per_step"]
-        line["spectrum_error"] = spectrum_error(md, torch, dev)
+    if "autotuned" in cmp:
+        line["autotuned_mpx_s"] = cmp["autotuned"]["mpx_s"]
     if not args.no_cpu:
-        import oracle
-
-        log("bench: timing the CPU oracle")
-        line["cpu_baseline"] = cpu_baseline(jobs, args.cpu_budget)
         threads = oracle.num_threads()
+        line["cpu_baseline"] = {"value": total_px / cpu_s / 1e6, "unit": "Mpixels/s", "cores": threads,
+                                "kind": "oracle",
+                                "sample": f"all {len(jobs)} jobs ({total_px} px), {cpu_s:.1f} s: the direct max "
+                                          f"over the SE (C, OpenMP, {threads} threads)"}
         oracle.set_threads(1)
-        line["cpu_1core"] = cpu_baseline(jobs, args.cpu_budget / 3)
+        line["cpu_1core"] = cpu_baseline(jobs, 4.0)
         oracle.set_threads(threads)
     print(json.dumps(line), flush=True)
     md.release()

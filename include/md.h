@@ -36,7 +36,18 @@
  *                 erosion(f, b) = (L-1) - dilation((L-1) - f, reflected b)
  *                 holds everywhere, the complement duality of Sec. 2.1).
  *                 Erosion values can be negative, down to -max(b).
- *   - Results are exact integers for every precision setting.
+ *   - Results are exact integers for every precision setting.  The
+ *     transform path checks every decoded pixel (Step 3 on rounded
+ *     coefficients c_d): a tile fails if any in-image pixel has a degree d
+ *     with |c_d - rint(c_d)| >= the band, or rint(c_d) < 0, or if the sum of
+ *     its rounded coefficients differs from the number of SE cells whose
+ *     window pixel lies in the image (the coefficients count exactly those
+ *     pairs, Sec. 3.1).  A failing tile goes to the next exact tier: an FP32
+ *     tile is recomputed with FP64 transforms (same checks, band 0.25); a
+ *     tile that fails in FP64 (first pass or recompute) is recomputed by the
+ *     integer window max of Eq. (6new).  FP32 is planned only where its
+ *     worst-case rounding error, nt sqrt(|B|) 3 log2(nt^2 nr) (u + beta)
+ *     with u = 2^-24, stays at most 0.25; other jobs take FP64.
  *   - Work is enqueued on the stream set by md_set_stream (default: the null
  *     stream).  With MD_OPT_SYNC = 1 (default) a call waits for its work and
  *     reports device-side errors and statistics; with 0 it returns after
@@ -77,9 +88,11 @@ typedef enum {
                               prime 7340033 (no rounding, no recompute): tiles
                               of 16..128 points, range lengths 2^a or 7*2^a up
                               to 1024, so (L-1) + max offset < 1024           */
-    MD_OPT_BAND = 1,       /* ambiguity band: a tile whose decoded coefficient c
-                              has |c - rint(c)| >= band is recomputed (default
-                              0.25; 0 forces every tile through the recompute)   */
+    MD_OPT_BAND = 1,       /* ambiguity band of the first transform pass: a tile
+                              whose decoded coefficient c has |c - rint(c)| >=
+                              band goes to the next exact tier (default 0.25; 0
+                              sends every tile there: FP32 tiles to the FP64
+                              recompute, FP64 tiles to the integer window)       */
     MD_OPT_PATH = 2,       /* 0: auto (cost model), 1: FFT convolution of umbras,
                               2: direct max-plus window (classical, Eq. (6new)) */
     MD_OPT_TILE = 3,       /* 0: auto, else the spatial FFT length per tile axis,
@@ -107,8 +120,14 @@ typedef enum {
     MD_OPT_STREAM_ROWS = 10,/* host-streamed calls: 0 (default) picks the band
                               height from MD_OPT_STREAM_MB, else the output
                               rows (volumes: slices) per band                    */
-    MD_OPT_STREAM_MB = 11  /* device memory for the band buffers of the host-
+    MD_OPT_STREAM_MB = 11, /* device memory for the band buffers of the host-
                               streamed calls, MiB (default 2048)                 */
+    MD_OPT_CACHE_MB = 12   /* bound on the device memory of the library's
+                              caches (range tables, SE spectra, window tables),
+                              MiB (default 16384): past it the least recently
+                              used entries that no cached batch plan references
+                              are freed; a single entry larger than the bound
+                              is still kept while in use                        */
 } md_option;
 
 /* Dilation of one image (see the conventions above). */
@@ -252,6 +271,63 @@ typedef struct {
  * `jobs` is a host array read during the call only. */
 int md_dilate_batch(const md_job *jobs, int n);
 
+/* Caller-owned workspace for the transform path, for callers that own all
+ * device scratch memory themselves.  `dev_ptr` is a DEVICE buffer of
+ * `bytes` bytes, 256-byte aligned, that holds what a batch needs beyond its
+ * inputs and outputs: the transform-domain buffer, the large-tile slabs, the
+ * tile flags and tier lists, the FP64 recompute's slots and slabs.  It stays
+ * the caller's: it must remain valid, and untouched by other work, while
+ * calls may use it -- until md_set_workspace is called again or md_release.
+ * Calls are ordered on the library stream, so successive calls share it.
+ * (NULL, 0) returns to library-owned workspace (the default).  Setting it
+ * waits for the device and drops cached batch plans.  A call whose plan needs
+ * more than `bytes` fails with MD_ERR_ARG before enqueueing anything.
+ * MD_ERR_ARG if only one of dev_ptr and bytes is 0 or the pointer is not
+ * 256-byte aligned.  The library still owns its caches, plans and tables. */
+int md_set_workspace(void *dev_ptr, size_t bytes);
+
+/* Workspace bytes that md_dilate_batch(jobs, n) needs under the current
+ * options (plans as that call would make them; the first auto-path call on a
+ * device runs the autotuner first).  0 for a batch with no transform job, and
+ * 0 on an invalid job (md_last_error then says why; it is empty otherwise).
+ * A single image is the batch of one job (op 0 or 1). */
+size_t md_workspace_size(const md_job *jobs, int n);
+
+/* Device memory the library holds beyond the caller's buffers: *cache_bytes
+ * for the cache of MD_OPT_CACHE_MB (range tables, SE spectra, window
+ * tables), *plan_bytes for the workspace owned by its *plans cached batch
+ * plans (each captured graph with its launch tables; at most 64, their
+ * workspace also kept within MD_OPT_CACHE_MB by dropping the least recently
+ * run ones).  Host pointers.  Excludes what the HIP runtime itself allocates
+ * (graphs, kernel arguments). */
+int md_memory_usage(size_t *cache_bytes, size_t *plan_bytes, int *plans);
+
+/* The plan md_dilate_batch would make for one job under the current options
+ * and cost model, computed on the host only: no device is touched and the
+ * autotuner does not run (before the first auto-path call on a device the
+ * cost model holds its built-in estimates).  batch = 0 plans the job as a
+ * single-image call, 1 as one job of a larger batch (a lone job is priced as
+ * if it filled the GPU's compute units).  Transform plans (path 1) use
+ * overlap-save tiles of n_t points per side with T = n_t - k + 1 outputs,
+ * tiles_x = ceil(W / T), tiles_y = ceil(H / T), and a range length
+ * n_r >= (L-1) + max offset + 1 with `bins` kept range bins.  Errors as for
+ * md_dilate_batch's host checks (MD_ERR_ARG, MD_ERR_RANGE,
+ * MD_ERR_UNSUPPORTED).  `job` and `out` are host pointers; job->img and
+ * job->out are only checked for being non-null and distinct. */
+typedef struct {
+    int path;            /* 1: transform (umbra convolution), 2: direct window       */
+    int precision;       /* transform plans: 0 FP32 + exact tiers, 1 FP64, 2 mod p    */
+    int n_t, T, n_r, bins, tiles_x, tiles_y;
+    int decode_fft;      /* 1: the range-axis FFT decode, 0: the dense inverse DFT    */
+    int n_t64;           /* FP32 plans: tile length of the FP64 recompute             */
+    double fp32_bound;   /* transform plans: the FP32 worst-case error bound of n_t,
+                            n_r and the SE (NaN for direct plans)                     */
+    double cost_fft_ns;  /* cost model's estimates, INFINITY where no plan exists     */
+    double cost_direct_ns;
+} md_plan_info;
+
+int md_plan(const md_job *job, int batch, md_plan_info *out);
+
 /* Stream for subsequent calls (a hipStream_t, or NULL for the null stream). */
 int md_set_stream(void *hip_stream);
 
@@ -262,13 +338,15 @@ double md_get_option(int key);  /* NaN for an unknown key */
 typedef struct {
     double max_residual;      /* max |c - rint(c)| over decoded coefficients (FFT path) */
     long long tiles;          /* FFT tiles processed                                     */
-    long long fallback_tiles; /* tiles recomputed by the exact fallback                  */
-    long long unresolved_tiles; /* tiles that hit the band with no recompute available
-                                 (FP64 mode); 0 in every measured run                   */
+    long long fallback_tiles; /* FP32 tiles recomputed with FP64 transforms               */
+    long long window_tiles;   /* tiles recomputed by the integer window (failed the
+                                 checks in FP64)                                       */
     long long direct_jobs;    /* jobs that took the direct path                          */
     long long fft_jobs;       /* jobs that took the FFT path                             */
     int path, n_t, n_r;       /* plan of the last job: path 1 FFT / 2 direct, lengths    */
-    int precision;            /* 0 FP32 + fallback, 1 FP64                               */
+    int precision;            /* of the last job: 0 FP32 + fallback, 1 FP64, 2 exact
+                                 mod p (a transform job planned FP64 because of the
+                                 FP32 error bound reports 1)                          */
 } md_stats;
 
 int md_get_stats(md_stats *stats);
@@ -296,6 +374,11 @@ typedef struct {
     long long launches;
     double alg_bytes;
     double alg_ops;           /* flops (FFT/decode) or int ops (direct)   */
+    double units;             /* work units the cost model prices the stage
+                                 by: (tile, bin) items for the transforms,
+                                 output pixels times SE cells stepped for
+                                 the direct window, pixels times decode units
+                                 for the decodes                          */
 } md_stage_time;
 
 /* Copies up to `max` stage records into `out` and the number available into
@@ -335,6 +418,25 @@ int md_cost_model(double *dst, int n, int *measured);
 int md_debug_tile_values(const int32_t *img, int H, int W, int L, const uint8_t *se_mask,
                          const int32_t *se_offsets, int k, int n_t, int n_r, int precision,
                          int ty, int tx, double *dst);
+
+/* Test hook for the exact tiers: from the next call on, perturb the listed
+ * transform tiles.  A tile is named by its flat index over the call's
+ * transform tiles: the tiles of its transform jobs in job order, each job's
+ * tiles row-major (ty * tiles_x + tx).  bits[i]: 1 adds 0.4 to every decoded
+ * coefficient of tile tiles[i] in the first transform pass, 2 does the same
+ * in the FP64 recompute; so a tile with bit 1 fails the band and is
+ * recomputed, and with bits 1|2 in FP32 (or 1 in FP64) reaches the integer
+ * window.  The result must stay exact.  Calls run without a graph while the
+ * list is set; indices beyond a call's tiles are ignored.  n = 0 clears the
+ * list.  Host arrays, read during the call. */
+int md_debug_perturb_tiles(const long long *tiles, const uint8_t *bits, int n);
+
+/* Test hook: the per-tile tier flags of the last batch or single call
+ * (bit 0: recomputed in FP64; bit 1: recomputed by the integer window), flat
+ * tile order as for md_debug_perturb_tiles.  Copies min(cap, count) words to
+ * the HOST array dst and the count into *n (0 when the last call had no
+ * transform tile).  Waits for the library stream. */
+int md_debug_tile_flags(uint32_t *dst, long long cap, long long *n);
 
 #ifdef __cplusplus
 }

@@ -14,11 +14,11 @@ _HEADER = os.path.join(os.path.dirname(_PKG), "include", "md.h")
 _lib = None
 
 (OPT_PRECISION, OPT_BAND, OPT_PATH, OPT_TILE, OPT_NR, OPT_SYNC, OPT_GRAPH, OPT_WORKSPACE_MB,
- OPT_PROFILE, OPT_AUTOTUNE, OPT_STREAM_ROWS, OPT_STREAM_MB) = range(12)
+ OPT_PROFILE, OPT_AUTOTUNE, OPT_STREAM_ROWS, OPT_STREAM_MB, OPT_CACHE_MB) = range(13)
 _OPT_NAMES = {"precision": OPT_PRECISION, "band": OPT_BAND, "path": OPT_PATH, "tile": OPT_TILE,
               "nr": OPT_NR, "sync": OPT_SYNC, "graph": OPT_GRAPH, "workspace_mb": OPT_WORKSPACE_MB,
               "profile": OPT_PROFILE, "autotune": OPT_AUTOTUNE, "stream_rows": OPT_STREAM_ROWS,
-              "stream_mb": OPT_STREAM_MB}
+              "stream_mb": OPT_STREAM_MB, "cache_mb": OPT_CACHE_MB}
 _STATUS = {0: "MD_OK", -1: "MD_ERR_ARG", -2: "MD_ERR_RANGE", -3: "MD_ERR_NOMEM",
            -4: "MD_ERR_DEVICE", -5: "MD_ERR_UNSUPPORTED"}
 
@@ -37,15 +37,22 @@ class _Job(ctypes.Structure):
 
 class _Stats(ctypes.Structure):
     _fields_ = [("max_residual", ctypes.c_double), ("tiles", ctypes.c_longlong),
-                ("fallback_tiles", ctypes.c_longlong), ("unresolved_tiles", ctypes.c_longlong),
+                ("fallback_tiles", ctypes.c_longlong), ("window_tiles", ctypes.c_longlong),
                 ("direct_jobs", ctypes.c_longlong), ("fft_jobs", ctypes.c_longlong),
                 ("path", ctypes.c_int), ("n_t", ctypes.c_int), ("n_r", ctypes.c_int),
                 ("precision", ctypes.c_int)]
 
 
+class _PlanInfo(ctypes.Structure):
+    _fields_ = [("path", ctypes.c_int), ("precision", ctypes.c_int), ("n_t", ctypes.c_int), ("T", ctypes.c_int),
+                ("n_r", ctypes.c_int), ("bins", ctypes.c_int), ("tiles_x", ctypes.c_int), ("tiles_y", ctypes.c_int),
+                ("decode_fft", ctypes.c_int), ("n_t64", ctypes.c_int), ("fp32_bound", ctypes.c_double),
+                ("cost_fft_ns", ctypes.c_double), ("cost_direct_ns", ctypes.c_double)]
+
+
 class _StageTime(ctypes.Structure):
     _fields_ = [("name", ctypes.c_char * 32), ("ms", ctypes.c_double), ("launches", ctypes.c_longlong),
-                ("alg_bytes", ctypes.c_double), ("alg_ops", ctypes.c_double)]
+                ("alg_bytes", ctypes.c_double), ("alg_ops", ctypes.c_double), ("units", ctypes.c_double)]
 
 
 def library_path() -> str:
@@ -103,6 +110,20 @@ def load():
     lib.md_morph3.restype = i
     lib.md_cost_model.argtypes = [ctypes.POINTER(ctypes.c_double), i, ctypes.POINTER(ctypes.c_int)]
     lib.md_cost_model.restype = i
+    lib.md_memory_usage.argtypes = [ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(ctypes.c_size_t),
+                                    ctypes.POINTER(ctypes.c_int)]
+    lib.md_memory_usage.restype = i
+    lib.md_plan.argtypes = [ctypes.POINTER(_Job), i, ctypes.POINTER(_PlanInfo)]
+    lib.md_plan.restype = i
+    lib.md_set_workspace.argtypes = [vp, ctypes.c_size_t]
+    lib.md_set_workspace.restype = i
+    lib.md_workspace_size.argtypes = [ctypes.POINTER(_Job), i]
+    lib.md_workspace_size.restype = ctypes.c_size_t
+    lib.md_debug_perturb_tiles.argtypes = [ctypes.POINTER(ctypes.c_longlong), ctypes.POINTER(ctypes.c_uint8), i]
+    lib.md_debug_perturb_tiles.restype = i
+    lib.md_debug_tile_flags.argtypes = [ctypes.POINTER(ctypes.c_uint32), ctypes.c_longlong,
+                                        ctypes.POINTER(ctypes.c_longlong)]
+    lib.md_debug_tile_flags.restype = i
     _lib = lib
     return lib
 
@@ -412,6 +433,78 @@ class Batch:
         return self.outs
 
 
+def set_workspace(buf=None):
+    """md_set_workspace: a caller-owned device buffer (a torch tensor on the
+    device, 256-byte aligned; the library carves its transform workspace from
+    it) or None for library-owned workspace.  Keep the tensor alive while it
+    is set."""
+    if buf is None:
+        _check(load().md_set_workspace(None, 0))
+    else:
+        _check(load().md_set_workspace(ctypes.c_void_p(buf.data_ptr()), buf.numel() * buf.element_size()))
+
+
+def workspace_size(jobs) -> int:
+    """md_workspace_size for jobs given as for dilate_batch (outputs are not
+    needed: a placeholder pointer is passed)."""
+    lib = load()
+    n = len(jobs)
+    arr = (_Job * n)()
+    keep = []
+    for q, (img, mask, off, L, op) in enumerate(jobs):
+        img = _device_image(img)
+        mask, off = _se_arrays(mask, off)
+        keep.append((img, mask, off))
+        arr[q] = _Job(img.data_ptr(), img.shape[0], img.shape[1], int(L), mask.ctypes.data, off.ctypes.data,
+                      mask.shape[0], img.data_ptr() + 4, int(op))
+    size = lib.md_workspace_size(arr, n)
+    err = lib.md_last_error().decode()
+    if err:
+        raise MDError(-1, err)
+    return int(size)
+
+
+def memory_usage() -> dict:
+    """md_memory_usage: bytes of the library's cache and of its cached batch
+    plans' workspace, and the number of cached plans."""
+    c, p, n = ctypes.c_size_t(0), ctypes.c_size_t(0), ctypes.c_int(0)
+    _check(load().md_memory_usage(ctypes.byref(c), ctypes.byref(p), ctypes.byref(n)))
+    return {"cache_bytes": c.value, "plan_bytes": p.value, "plans": n.value}
+
+
+def plan(shape, mask, off, L: int, op: int = 0, batch: bool = False) -> dict:
+    """md_plan: the host-side plan of one job of the given (H, W) shape (no
+    device involved; placeholder image pointers are passed)."""
+    mask, off = _se_arrays(mask, off)
+    H, W = shape
+    job = _Job(16, int(H), int(W), int(L), mask.ctypes.data, off.ctypes.data, mask.shape[0], 32, int(op))
+    info = _PlanInfo()
+    _check(load().md_plan(ctypes.byref(job), 1 if batch else 0, ctypes.byref(info)))
+    return {f: getattr(info, f) for f, _ in _PlanInfo._fields_}
+
+
+def debug_perturb_tiles(tiles, bits):
+    """md_debug_perturb_tiles: flat transform-tile indices and their bits (1:
+    first pass, 2: FP64 recompute); empty lists clear the hook."""
+    t = np.ascontiguousarray(np.asarray(tiles, dtype=np.int64))
+    b = np.ascontiguousarray(np.asarray(bits, dtype=np.uint8))
+    if t.shape != b.shape or t.ndim != 1:
+        raise ValueError("tiles and bits must be 1-D of the same length")
+    _check(load().md_debug_perturb_tiles(t.ctypes.data_as(ctypes.POINTER(ctypes.c_longlong)),
+                                         b.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)), t.shape[0]))
+
+
+def debug_tile_flags() -> np.ndarray:
+    """md_debug_tile_flags: per-tile tier bits of the last call (1: FP64
+    recompute, 2: integer window), flat tile order."""
+    lib = load()
+    n = ctypes.c_longlong(0)
+    _check(lib.md_debug_tile_flags(None, 0, ctypes.byref(n)))
+    out = np.zeros(max(1, n.value), np.uint32)
+    _check(lib.md_debug_tile_flags(out.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32)), n.value, ctypes.byref(n)))
+    return out[:n.value]
+
+
 def dilate_batch(jobs, outs=None):
     """jobs: sequence of (img, mask, off, L, op) with op 0 = dilation, 1 =
     erosion; images are int32 device tensors.  Returns the output tensors."""
@@ -464,7 +557,8 @@ def profile_get() -> dict:
     arr = (_StageTime * max(1, n.value))()
     _check(lib.md_profile_get(arr, n.value, ctypes.byref(n)))
     return {arr[q].name.decode(): {"ms": arr[q].ms, "launches": arr[q].launches,
-                                   "alg_bytes": arr[q].alg_bytes, "alg_ops": arr[q].alg_ops}
+                                   "alg_bytes": arr[q].alg_bytes, "alg_ops": arr[q].alg_ops,
+                                   "units": arr[q].units}
             for q in range(n.value)}
 
 

@@ -370,14 +370,15 @@ __device__ __forceinline__ int encode_rows(int rows, const int32_t *__restrict__
 // input index j holds f(o0 - r + j) and the SE umbra sits at [0, k) on both
 // axes, so circular output index i >= k-1 is the linear result for pixel
 // o0 + i - (k-1).  Out-of-image pixels are the zero polynomial (Sec. 3,
-// Step 1).  Writes the T x T valid values (unscaled) to ydst.
+// Step 1).  Writes the T x T valid values (unscaled) to ydst, with `bump`
+// added to their real parts (0 except under the perturbation test hook).
 template <typename R, int N, int BS>
 __device__ __forceinline__ void fft_tile_bin(typename Cx<R>::T *lds, const int32_t *__restrict__ img, int H,
                                              int W, int L, int op, int k, int oy0, int ox0,
                                              const typename Cx<R>::T *__restrict__ enc_m,
                                              const typename Cx<R>::T *__restrict__ spec_m,
                                              typename Cx<R>::T *__restrict__ ydst, int ybs,
-                                             const typename TwSel<R>::T &tw, unsigned int *range_err) {
+                                             const typename TwSel<R>::T &tw, unsigned int *range_err, R bump) {
     using C = typename Cx<R>::T;
     constexpr int P = N + 1, LG = ilog2c(N);
     constexpr int CH = N * N / BS < 16 ? N * N / BS : 16;
@@ -405,12 +406,18 @@ __device__ __forceinline__ void fft_tile_bin(typename Cx<R>::T *lds, const int32
         // order and scatter within the output row
         for (int q = threadIdx.x; q < T * N; q += BS) {
             const int i = (q >> LG) + (k - 1), b = q & (N - 1), j = brev<LG>(b);
-            if (j >= k - 1) stg(ydst, ypix((size_t)(i - (k - 1)) * T + (j - (k - 1)), ybs), lds[brev<LG>(i) * P + b]);
+            if (j >= k - 1) {
+                C v = lds[brev<LG>(i) * P + b];
+                v.x += bump;
+                stg(ydst, ypix((size_t)(i - (k - 1)) * T + (j - (k - 1)), ybs), v);
+            }
         }
     } else {
         for (int q = threadIdx.x; q < T * T; q += BS) {
             const int i = q / T + (k - 1), j = q % T + (k - 1);
-            stg(ydst, ypix(q, ybs), lds[brev<LG>(i) * P + brev<LG>(j)]);
+            C v = lds[brev<LG>(i) * P + brev<LG>(j)];
+            v.x += bump;
+            stg(ydst, ypix(q, ybs), v);
         }
     }
     __syncthreads();
@@ -437,7 +444,7 @@ __device__ __forceinline__ void fft_big_tile_bin(typename Cx<R>::T *lds, typenam
                                                  int k, int oy0, int ox0, const typename Cx<R>::T *__restrict__ enc_m,
                                                  const typename Cx<R>::T *__restrict__ spec_m,
                                                  typename Cx<R>::T *__restrict__ ydst, int ybs,
-                                                 const typename TwSel<R>::T &tw, unsigned int *range_err) {
+                                                 const typename TwSel<R>::T &tw, unsigned int *range_err, R bump) {
     using C = typename Cx<R>::T;
     constexpr int LB = big_lines<R, N>();
     constexpr int P = N + 1, LG = ilog2c(N), LLB = ilog2c(LB);
@@ -494,14 +501,21 @@ __device__ __forceinline__ void fft_big_tile_bin(typename Cx<R>::T *lds, typenam
             for (int q = threadIdx.x; q < LB * N; q += BS) {
                 const int l = q >> LG, b = q & (N - 1);
                 const int y = brev<LG>(rb + l), x = brev<LG>(b);
-                if (y >= k - 1 && x >= k - 1)
-                    stg(ydst, ypix((size_t)(y - (k - 1)) * T + (x - (k - 1)), ybs), lds[l * P + b]);
+                if (y >= k - 1 && x >= k - 1) {
+                    C v = lds[l * P + b];
+                    v.x += bump;
+                    stg(ydst, ypix((size_t)(y - (k - 1)) * T + (x - (k - 1)), ybs), v);
+                }
             }
         } else {
             for (int q = threadIdx.x; q < LB * T; q += BS) {
                 const int l = q / T, xo = q - l * T;
                 const int y = brev<LG>(rb + l);
-                if (y >= k - 1) stg(ydst, ypix((size_t)(y - (k - 1)) * T + xo, ybs), lds[l * P + brev<LG>(xo + k - 1)]);
+                if (y >= k - 1) {
+                    C v = lds[l * P + brev<LG>(xo + k - 1)];
+                    v.x += bump;
+                    stg(ydst, ypix((size_t)(y - (k - 1)) * T + xo, ybs), v);
+                }
             }
         }
         __syncthreads();
@@ -509,10 +523,21 @@ __device__ __forceinline__ void fft_big_tile_bin(typename Cx<R>::T *lds, typenam
 }
 
 
+// Under the perturbation test hook (perturb non-null), bin 0 of a tile whose
+// kPerturbFirst bit is set gets 0.4 nt^2 nr added to the real part of every
+// output: after the decode's 1 / (nt^2 nr) scale every coefficient of its
+// pixels moves by 0.4, so the band flags exactly those tiles.
+template <typename R>
+__device__ __forceinline__ R perturb_bump(const uint8_t *perturb, const JobDev &J, int tile, int m, uint8_t bit) {
+    if (!perturb || m != 0 || !(perturb[J.flag0 + tile] & bit)) return R(0);
+    return (R)(0.4 * (double)J.nt * J.nt * J.nr);
+}
+
 template <typename R, int N, int BS>
 __global__ __launch_bounds__(BS) void k_fft(const JobDev *__restrict__ jobs, const Seg *__restrict__ segs,
                                             int nseg, long long nitems, const TwF *__restrict__ tw32,
-                                            const double2 *__restrict__ tw64, StatsDev *st) {
+                                            const double2 *__restrict__ tw64, StatsDev *st,
+                                            const uint8_t *__restrict__ perturb) {
     using C = typename Cx<R>::T;
     __shared__ C lds[N * (N + 1)];
     typename TwSel<R>::T tw;
@@ -527,21 +552,54 @@ __global__ __launch_bounds__(BS) void k_fft(const JobDev *__restrict__ jobs, con
         C *ydst = (C *)S.y + (size_t)tl * ytile_elems(J.bins, J.T, J.ybs) + ybin_offset(m, J.T, J.ybs);
         fft_tile_bin<R, N, BS>(lds, J.img, J.H, J.W, J.L, J.op, J.k, ty * J.T, tx * J.T,
                                (const C *)J.enc + (size_t)m * J.L, (const C *)J.se_spec + (size_t)m * N * N,
-                               ydst, J.ybs, tw, m == 0 ? &st->range_err : nullptr);
+                               ydst, J.ybs, tw, m == 0 ? &st->range_err : nullptr,
+                               perturb_bump<R>(perturb, J, tile, m, kPerturbFirst));
     }
 }
 
+// Step 3 on one coefficient c_d: the top degree with rint(c_d) != 0, and
+// what the exactness checks need: the largest distance |c_d - rint(c_d)|, the
+// sum of the rounded coefficients and whether any rounds below zero.
 template <typename R>
-__device__ __forceinline__ void band_update(R c, int d, int &top, R &res) {
-    const R rc = rint(c);
-    res = fmax(res, fabs(c - rc));
-    if (rc != R(0)) top = max(top, d);
+struct PxDecode {
+    int top = -1;
+    R res = 0, sum = 0;
+    bool neg = false;
+    __device__ __forceinline__ void add(R c, int d) {
+        const R rc = rint(c);
+        res = fmax(res, fabs(c - rc));
+        sum += rc;
+        neg |= rc < R(0);
+        if (rc != R(0)) top = max(top, d);
+    }
+};
+
+// Number of SE cells y whose window pixel x - y lies in the image, for the
+// pixel (gy, gx): the count of active cells (a, c) of the effective mask with
+// a in [gy + r - H + 1, gy + r] and c in [gx + r - W + 1, gx + r], from the
+// mask's prefix counts.  Every such pair adds 1 to exactly one coefficient of
+// the pixel's product polynomial (Sec. 3.1), so the coefficients sum to it.
+__device__ __forceinline__ int window_cells(const JobDev &J, int gy, int gx) {
+    const int k = J.k, r = (k - 1) >> 1, kp = k + 1;
+    const int a0 = max(0, gy + r - J.H + 1), a1 = min(k - 1, gy + r);
+    const int c0 = max(0, gx + r - J.W + 1), c1 = min(k - 1, gx + r);
+    if (a0 > a1 || c0 > c1) return 0;
+    const auto P = gld(J.se_cnt);
+    return P[(a1 + 1) * kp + c1 + 1] - P[a0 * kp + c1 + 1] - P[(a1 + 1) * kp + c0] + P[a0 * kp + c0];
+}
+
+// Whether a decoded pixel fails the exactness checks (band: the residual
+// bound of the pass).
+template <typename R>
+__device__ __forceinline__ bool px_ambiguous(const PxDecode<R> &dd, float band, const JobDev &J, int gy, int gx) {
+    return (float)dd.res >= band || dd.neg || (int)dd.sum != window_cells(J, gy, gx);
 }
 
 template <typename R, int N, int BS>
 __global__ __launch_bounds__(BS) void k_fft_big(const JobDev *__restrict__ jobs, const Seg *__restrict__ segs,
                                                 int nseg, long long nitems, const TwF *__restrict__ tw32,
-                                                const double2 *__restrict__ tw64, void *slabs, StatsDev *st) {
+                                                const double2 *__restrict__ tw64, void *slabs, StatsDev *st,
+                                                const uint8_t *__restrict__ perturb) {
     using C = typename Cx<R>::T;
     __shared__ C lds[big_lines<R, N>() * (N + 1)];
     typename TwSel<R>::T tw;
@@ -557,7 +615,8 @@ __global__ __launch_bounds__(BS) void k_fft_big(const JobDev *__restrict__ jobs,
         C *ydst = (C *)S.y + (size_t)tl * ytile_elems(J.bins, J.T, J.ybs) + ybin_offset(m, J.T, J.ybs);
         fft_big_tile_bin<R, N, BS>(lds, slab, J.img, J.H, J.W, J.L, J.op, J.k, ty * J.T, tx * J.T,
                                    (const C *)J.enc + (size_t)m * J.L, (const C *)J.se_spec + (size_t)m * N * N, ydst,
-                                   J.ybs, tw, m == 0 ? &st->range_err : nullptr);
+                                   J.ybs, tw, m == 0 ? &st->range_err : nullptr,
+                                   perturb_bump<R>(perturb, J, tile, m, kPerturbFirst));
     }
 }
 
@@ -575,12 +634,11 @@ __global__ __launch_bounds__(BS) void k_fft_big(const JobDev *__restrict__ jobs,
 // are loaded once.
 template <typename R, int MB, int DC>
 __device__ __forceinline__ void decode_px(const typename Cx<R>::T *X, size_t mstride, size_t p, bool valid,
-                                          const typename Cx<R>::T *dec, int dp, int nr, int bins, R scale, int &top,
-                                          R &res) {
+                                          const typename Cx<R>::T *dec, int dp, int nr, int bins, R scale,
+                                          PxDecode<R> &out) {
     using C = typename Cx<R>::T;
     const int dh = nr >> 1;
-    top = -1;
-    res = 0;
+    out = PxDecode<R>();
     if (!__any(valid)) return;   // the whole wave lies outside the image
     for (int d0 = 0; d0 <= dh; d0 += DC) {
         R A[DC], B[DC];
@@ -608,8 +666,8 @@ __device__ __forceinline__ void decode_px(const typename Cx<R>::T *X, size_t mst
         for (int dd = 0; dd < DC; ++dd) {
             const int d = d0 + dd;
             if (d <= dh) {
-                band_update<R>((A[dd] - B[dd]) * scale, d, top, res);
-                if (d > 0 && 2 * d != nr) band_update<R>((A[dd] + B[dd]) * scale, nr - d, top, res);
+                out.add((A[dd] - B[dd]) * scale, d);
+                if (d > 0 && 2 * d != nr) out.add((A[dd] + B[dd]) * scale, nr - d);
             }
         }
     }
@@ -625,13 +683,23 @@ __host__ __device__ constexpr int decode_variant(int bins, int dbl) {
 
 template <typename R, int V>
 __device__ __forceinline__ void decode_var(const typename Cx<R>::T *X, size_t mstride, size_t p, bool valid,
-                                           const typename Cx<R>::T *dec, int dp, int nr, int bins, R scale, int &top,
-                                           R &res) {
-    if constexpr (V == kDec8) decode_px<R, 8, 8>(X, mstride, p, valid, dec, dp, nr, bins, scale, top, res);
-    else if constexpr (V == kDec12) decode_px<R, 12, 12>(X, mstride, p, valid, dec, dp, nr, bins, scale, top, res);
-    else if constexpr (V == kDec24) decode_px<R, 24, 24>(X, mstride, p, valid, dec, dp, nr, bins, scale, top, res);
-    else if constexpr (sizeof(R) == 4) decode_px<R, 16, 16>(X, mstride, p, valid, dec, dp, nr, bins, scale, top, res);
-    else decode_px<R, 8, 8>(X, mstride, p, valid, dec, dp, nr, bins, scale, top, res);
+                                           const typename Cx<R>::T *dec, int dp, int nr, int bins, R scale,
+                                           PxDecode<R> &out) {
+    if constexpr (V == kDec8) decode_px<R, 8, 8>(X, mstride, p, valid, dec, dp, nr, bins, scale, out);
+    else if constexpr (V == kDec12) decode_px<R, 12, 12>(X, mstride, p, valid, dec, dp, nr, bins, scale, out);
+    else if constexpr (V == kDec24) decode_px<R, 24, 24>(X, mstride, p, valid, dec, dp, nr, bins, scale, out);
+    else if constexpr (sizeof(R) == 4) decode_px<R, 16, 16>(X, mstride, p, valid, dec, dp, nr, bins, scale, out);
+    else decode_px<R, 8, 8>(X, mstride, p, valid, dec, dp, nr, bins, scale, out);
+}
+
+// Sends a flagged tile to the next exact tier, once: FP32 jobs to the FP64
+// recompute (fb_list), FP64 jobs to the exact window (win_list).
+__device__ __forceinline__ void flag_tile(const JobDev &J, int job, int tile, unsigned int *tile_flags, int2 *fb_list,
+                                          int2 *win_list, StatsDev *st) {
+    const unsigned bit = J.fb_mode == kFbFFT64 ? kFlagFp64 : kFlagWindow;
+    if (atomicOr(&tile_flags[J.flag0 + tile], bit) != 0u) return;
+    if (bit == kFlagFp64) fb_list[atomicAdd(&st->fb_count, 1u)] = make_int2(job, tile);
+    else win_list[atomicAdd(&st->win_count, 1u)] = make_int2(job, tile);
 }
 
 __device__ __forceinline__ float wave_max(float v) {
@@ -657,7 +725,7 @@ __global__ __launch_bounds__(kDecThreads) void k_decode(const JobDev *__restrict
                                                         const Seg *__restrict__ segs, int nseg,
                                                         long long nitems, float band,
                                                         unsigned int *tile_flags, int2 *fb_list,
-                                                        StatsDev *st) {
+                                                        int2 *win_list, StatsDev *st) {
     using C = typename Cx<R>::T;
     __shared__ float s_red[kDecThreads / 64];
     float run_max = 0.f;          // largest residual this thread has seen (stats)
@@ -680,26 +748,18 @@ __global__ __launch_bounds__(kDecThreads) void k_decode(const JobDev *__restrict
             const int ly = p / T, lx = p - ly * T;
             const int gy = ty * T + ly, gx = tx * T + lx;
             const bool valid = p < (int)TT && gy < J.H && gx < J.W;
-            int top;
-            R res;
+            PxDecode<R> dd;
             decode_var<R, V>(X, mstride, ypix(p, J.ybs), valid, (const C *)J.dec, J.dec_pitch, J.nr, J.bins,
-                             (R)J.scale, top, res);
+                             (R)J.scale, dd);
             if (valid) {
-                const int d = top < 0 ? 0 : top;
+                const int d = dd.top < 0 ? 0 : dd.top;
                 gst(J.out)[(size_t)gy * J.W + gx] = J.op ? (J.L - 1 - d) : d;
-            }
-            run_max = fmaxf(run_max, (float)res);
-            hit |= (float)res >= band;
-        }
-        // a wave whose pixels hit the band flags the tile (rare); no barrier
-        if (__any(hit) && (threadIdx.x & 63) == 0 && atomicCAS(&tile_flags[J.flag0 + tile], 0u, 1u) == 0u) {
-            if (J.fb_mode == kFbNone) {
-                atomicAdd(&st->pad, 1u);   // counted once per tile
-            } else {
-                const unsigned idx = atomicAdd(&st->fb_count, 1u);
-                fb_list[idx] = make_int2(S.job, tile);
+                run_max = fmaxf(run_max, (float)dd.res);
+                hit |= px_ambiguous(dd, band, J, gy, gx);
             }
         }
+        // a wave whose pixels fail a check flags the tile (rare); no barrier
+        if (__any(hit) && (threadIdx.x & 63) == 0) flag_tile(J, S.job, tile, tile_flags, fb_list, win_list, st);
     }
     const float rm = block_max(run_max, s_red);
     if (threadIdx.x == 0 && rm > 0.f) atomicMax(&st->max_res_bits, __float_as_uint(rm));
@@ -921,7 +981,7 @@ __global__ __launch_bounds__(kDecThreads) void k_decode_fft(const JobDev *__rest
                                                             const Seg *__restrict__ segs, int nseg,
                                                             long long nitems, float band,
                                                             unsigned int *tile_flags, int2 *fb_list,
-                                                            StatsDev *st) {
+                                                            int2 *win_list, StatsDev *st) {
     using C = typename Cx<R>::T;
     constexpr bool POW2 = (M & (M - 1)) == 0;
     constexpr int E = POW2 ? 16 : M % 3 == 0 ? 24 : 20, Q1 = E, G = M / E, P = kDecThreads / G;
@@ -933,7 +993,7 @@ __global__ __launch_bounds__(kDecThreads) void k_decode_fft(const JobDev *__rest
     __shared__ C zs[(M + M / Q1) * P];   // point n of pixel p at (n + n / E) P + p
     __shared__ C tws[M];                 // exp(2 pi i m / nr), m < M
     __shared__ C tw2[Q3 == 1 ? M : 1];   // exp(2 pi i m / M) for a last second pass
-    __shared__ int s_top[P];
+    __shared__ int s_top[P], s_sum[P];
     __shared__ float s_red[kDecThreads / 64];
     const int p = threadIdx.x & (P - 1), g = threadIdx.x / P;
     auto turn = [&](C x, int m) {   // x exp(2 pi i m / nr), m < nr
@@ -1017,7 +1077,10 @@ __global__ __launch_bounds__(kDecThreads) void k_decode_fft(const JobDev *__rest
         const int base1 = W * g * P + p;   // rows E g + s
 #pragma unroll
         for (int s = 0; s < E; ++s) zs[base1 + s * P] = v[s];
-        if (threadIdx.x < P) s_top[threadIdx.x] = -1;
+        if (threadIdx.x < P) {
+            s_top[threadIdx.x] = -1;
+            s_sum[threadIdx.x] = 0;
+        }
         __syncthreads();
         // 2. the remaining passes (S = E, then E Q2)
         C u[B2][Q2];
@@ -1056,9 +1119,12 @@ __global__ __launch_bounds__(kDecThreads) void k_decode_fft(const JobDev *__rest
         // order (point n = g + b G + NS s), keeping the index of the last
         // non-zero one
         constexpr int NB = Q3 > 1 ? B3 : B2, NSP = Q3 > 1 ? Q3 : Q2, NS = Q3 > 1 ? Q1 * Q2 : Q1;
+        // (with the exactness checks' inputs: residual, negative coefficients,
+        // and the sum of the rounded coefficients)
         const R scale = (R)J.scale;
         int topi = -1;
-        R res = 0;
+        R res = 0, rsum = 0;
+        bool neg = false;
 #pragma unroll
         for (int s = 0; s < NSP; ++s)
 #pragma unroll
@@ -1067,38 +1133,43 @@ __global__ __launch_bounds__(kDecThreads) void k_decode_fft(const JobDev *__rest
                 const int i = 2 * (s * NB + b);
                 const R cx = z.x * scale, cy = z.y * scale, rx = rint(cx), ry = rint(cy);
                 res = fmax(res, fmax(fabs(cx - rx), fabs(cy - ry)));
+                rsum += rx + ry;
+                neg |= (rx < R(0)) | (ry < R(0));
                 if (rx != R(0)) topi = i;
                 if (ry != R(0)) topi = i + 1;
             }
         if (!pv) {
             topi = -1;
             res = 0;
+            rsum = 0;
+            neg = false;
         }
-        int top = -1;
+        int top = -1, isum = (int)rsum;
         if (topi >= 0) {
             const int q = topi >> 1, s = q / NB, b = q - s * NB;
             top = 2 * (g + b * G + NS * s) + (topi & 1);
         }
 #pragma unroll
-        for (int o = 32; o >= P; o >>= 1) top = max(top, __shfl_xor(top, o, 64));
-        if ((threadIdx.x & 63) < P && top >= 0) atomicMax(&s_top[p], top);
+        for (int o = 32; o >= P; o >>= 1) {
+            top = max(top, __shfl_xor(top, o, 64));
+            isum += __shfl_xor(isum, o, 64);
+        }
+        if ((threadIdx.x & 63) < P) {
+            if (top >= 0) atomicMax(&s_top[p], top);
+            atomicAdd(&s_sum[p], isum);
+        }
         run_max = fmaxf(run_max, (float)res);
-        const bool hit = (float)res >= band;
+        bool hit = (float)res >= band || neg;
         __syncthreads();
         if (threadIdx.x < P && pixel_valid(threadIdx.x)) {
             const int q = p0 + threadIdx.x, ly = q / T, lx = q - ly * T;
+            const int gy = ty * T + ly, gx = tx * T + lx;
             const int d = s_top[threadIdx.x] < 0 ? 0 : s_top[threadIdx.x];
-            gst(J.out)[(size_t)(ty * T + ly) * J.W + (tx * T + lx)] = J.op ? (J.L - 1 - d) : d;
+            gst(J.out)[(size_t)gy * J.W + gx] = J.op ? (J.L - 1 - d) : d;
+            hit |= s_sum[threadIdx.x] != window_cells(J, gy, gx);
         }
-        // a wave whose degrees hit the band flags the tile (rare)
-        if (__any(hit) && (threadIdx.x & 63) == 0 && atomicCAS(&tile_flags[J.flag0 + tile], 0u, 1u) == 0u) {
-            if (J.fb_mode == kFbNone) {
-                atomicAdd(&st->pad, 1u);
-            } else {
-                const unsigned idx = atomicAdd(&st->fb_count, 1u);
-                fb_list[idx] = make_int2(S.job, tile);
-            }
-        }
+        // a wave whose pixels fail a check flags the tile (rare)
+        if (__any(hit) && (threadIdx.x & 63) == 0) flag_tile(J, S.job, tile, tile_flags, fb_list, win_list, st);
         __syncthreads();   // the rows and tops are rewritten by the next item
     }
     const float rm = block_max(run_max, s_red);
@@ -1107,13 +1178,16 @@ __global__ __launch_bounds__(kDecThreads) void k_decode_fft(const JobDev *__rest
 
 // Exact recompute of the tiles listed by the decode: FP64 transforms on
 // nt64-sized sub-tiles (LDS-resident up to 64, through this block's slab
-// beyond), each decoded from this block's slot.
+// beyond), each decoded from this block's slot.  The decode applies the
+// exactness checks with kExactBand; a tile that fails them here too goes on
+// to the exact window (win_list).
 template <int N>
 __global__ __launch_bounds__(kDecThreads) void k_fallback(const JobDev *__restrict__ jobs,
-                                                          const int2 *__restrict__ fb_list,
-                                                          const StatsDev *__restrict__ st, double2 *slots,
-                                                          size_t slot_elems, const double2 *__restrict__ tw64,
-                                                          double2 *slabs) {
+                                                          const int2 *__restrict__ fb_list, StatsDev *st,
+                                                          double2 *slots, size_t slot_elems,
+                                                          const double2 *__restrict__ tw64, double2 *slabs,
+                                                          unsigned int *tile_flags, int2 *win_list,
+                                                          const uint8_t *__restrict__ perturb) {
     constexpr bool BIG = N > kMaxLdsN64;
     __shared__ double2 lds[BIG ? big_lines<double, N>() * (N + 1) : N * (N + 1)];
     Tw64 tw;
@@ -1131,6 +1205,9 @@ __global__ __launch_bounds__(kDecThreads) void k_fallback(const JobDev *__restri
         const int oh = min(J.T, J.H - oy0), ow = min(J.T, J.W - ox0);
         const int T64 = J.T64;
         const size_t TT = (size_t)T64 * T64;
+        // the test hook's bump, in the units of this pass (nt64, not nt)
+        const double bump = perturb && (perturb[J.flag0 + tile] & kPerturbFp64) ? 0.4 * N * N * J.nr : 0.0;
+        bool hit = false;
         for (int sy = 0; sy < oh; sy += T64) {
             for (int sx = 0; sx < ow; sx += T64) {
                 for (int m = 0; m < J.bins; ++m) {
@@ -1138,40 +1215,83 @@ __global__ __launch_bounds__(kDecThreads) void k_fallback(const JobDev *__restri
                         fft_big_tile_bin<double, N, kDecThreads>(lds, slab, J.img, J.H, J.W, J.L, J.op, J.k, oy0 + sy,
                                                                  ox0 + sx, J.enc64 + (size_t)m * J.L,
                                                                  J.se_spec64 + (size_t)m * N * N, slot + m * TT, 0,
-                                                                 tw, nullptr);
+                                                                 tw, nullptr, m == 0 ? bump : 0.0);
                     else
                         fft_tile_bin<double, N, kDecThreads>(lds, J.img, J.H, J.W, J.L, J.op, J.k, oy0 + sy, ox0 + sx,
                                                              J.enc64 + (size_t)m * J.L, J.se_spec64 + (size_t)m * N * N,
-                                                             slot + m * TT, 0, tw, nullptr);
+                                                             slot + m * TT, 0, tw, nullptr, m == 0 ? bump : 0.0);
                 }
                 const int sh = min(T64, oh - sy), sw = min(T64, ow - sx);
                 for (int p0 = 0; p0 < (int)TT; p0 += kDecThreads) {
                     const int p = p0 + threadIdx.x;
                     const int ly = p / T64, lx = p - ly * T64;
                     const bool valid = p < (int)TT && ly < sh && lx < sw;
-                    int top;
-                    double res;
+                    PxDecode<double> dd;
                     switch (decode_variant(J.bins, 1)) {
                         case kDec8:
-                            decode_var<double, kDec8>(slot, TT, p, valid, J.dec64, J.dec_pitch, J.nr, J.bins,
-                                                      J.scale64, top, res);
+                            decode_var<double, kDec8>(slot, TT, p, valid, J.dec64, J.dec_pitch, J.nr, J.bins, J.scale64,
+                                                      dd);
                             break;
                         case kDec12:
                             decode_var<double, kDec12>(slot, TT, p, valid, J.dec64, J.dec_pitch, J.nr, J.bins,
-                                                       J.scale64, top, res);
+                                                       J.scale64, dd);
                             break;
                         default:
                             decode_var<double, kDecBlk>(slot, TT, p, valid, J.dec64, J.dec_pitch, J.nr, J.bins,
-                                                        J.scale64, top, res);
+                                                        J.scale64, dd);
                     }
                     if (valid) {
-                        const int d = top < 0 ? 0 : top;
-                        gst(J.out)[(size_t)(oy0 + sy + ly) * J.W + (ox0 + sx + lx)] = J.op ? (J.L - 1 - d) : d;
+                        const int gy = oy0 + sy + ly, gx = ox0 + sx + lx;
+                        const int d = dd.top < 0 ? 0 : dd.top;
+                        gst(J.out)[(size_t)gy * J.W + gx] = J.op ? (J.L - 1 - d) : d;
+                        hit |= px_ambiguous(dd, kExactBand, J, gy, gx);
                     }
                 }
                 __syncthreads();   // the slot is rewritten by the next sub-tile
             }
         }
+        if (__syncthreads_or(hit) && threadIdx.x == 0) {
+            atomicOr(&tile_flags[J.flag0 + tile], kFlagWindow);
+            win_list[atomicAdd(&st->win_count, 1u)] = e;
+        }
+    }
+}
+
+// The exact tier behind both transform passes: the classical window
+// max { f(x-y) + b(y) } (Eq. (6new)) in int32 over every pixel of the tiles
+// on win_list, for tiles whose FP64 coefficients still failed the checks.
+// The effective SE comes in correlation order (sek, row i / column j holds
+// the offset of cell (k-1-i, k-1-j), kNeg where masked), so the pixel (y, x)
+// takes the image pixel (y + i - r, x + j - r); erosion complements the
+// image values and the result (duality, Sec. 2.1).  A work item is one block
+// of kDecThreads pixels of a listed tile.
+__global__ __launch_bounds__(kDecThreads) void k_tile_window(const JobDev *__restrict__ jobs,
+                                                             const int2 *__restrict__ win_list,
+                                                             const StatsDev *__restrict__ st, int pblocks) {
+    const unsigned cnt = __builtin_amdgcn_readfirstlane(*(volatile const unsigned *)&st->win_count);
+    const long long items = (long long)cnt * pblocks;
+    for (long long it = blockIdx.x; it < items; it += gridDim.x) {
+        const int2 e = win_list[it / pblocks];
+        const JobDev &J = jobs[e.x];
+        const int T = J.T, q = (int)(it % pblocks) * kDecThreads + threadIdx.x;
+        const int ty = e.y / J.tiles_x, tx = e.y - ty * J.tiles_x;
+        const int gy = ty * T + q / T, gx = tx * T + q % T;
+        if (q >= T * T || gy >= J.H || gx >= J.W) continue;
+        const int k = J.k, r = (k - 1) >> 1;
+        const int i0 = max(0, r - gy), i1 = min(k, J.H - gy + r), j0 = max(0, r - gx), j1 = min(k, J.W - gx + r);
+        const auto im = gld(J.img);
+        int best = kNeg;
+        for (int i = i0; i < i1; ++i) {
+            const size_t row = (size_t)(gy + i - r) * J.W + (gx - r);
+            const int32_t *srow = J.sek + (size_t)i * J.kpad;
+            for (int j = j0; j < j1; ++j) {
+                int v = min(max(im[row + j], 0), J.L - 1);
+                v = J.op ? J.L - 1 - v : v;
+                best = max(best, v + srow[j]);
+            }
+        }
+        const int d = best < 0 ? 0 : best;
+        gst(J.out)[(size_t)gy * J.W + gx] = J.op ? (J.L - 1 - d) : d;
     }
 }
 
@@ -1388,12 +1508,14 @@ hipError_t launch_or_flag(uint32_t *dst, const uint32_t *src, hipStream_t s) {
 }
 
 hipError_t launch_fft(int nt, int dbl, const JobDev *jobs, const Seg *segs, int nseg, long long nitems,
-                      int grid, const TwF *tw32, const double2 *tw64, void *slabs, StatsDev *st, hipStream_t s) {
+                      int grid, const TwF *tw32, const double2 *tw64, void *slabs, StatsDev *st,
+                      const uint8_t *perturb, hipStream_t s) {
     if (nitems <= 0) return hipSuccess;
 #define MD_FFT_CASE(R, N, BS) \
-    k_fft<R, N, BS><<<grid, BS, 0, s>>>(jobs, segs, nseg, nitems, tw32, tw64, st); break;
+    k_fft<R, N, BS><<<grid, BS, 0, s>>>(jobs, segs, nseg, nitems, tw32, tw64, st, perturb); break;
 #define MD_FFT_BIG(R, N) \
-    k_fft_big<R, N, kBigThreads><<<grid, kBigThreads, 0, s>>>(jobs, segs, nseg, nitems, tw32, tw64, slabs, st); break;
+    k_fft_big<R, N, kBigThreads><<<grid, kBigThreads, 0, s>>>(jobs, segs, nseg, nitems, tw32, tw64, slabs, st, \
+                                                              perturb); break;
     if (!dbl) {
         switch (nt) {
             case 16: MD_FFT_CASE(float, 16, 64)
@@ -1423,12 +1545,13 @@ hipError_t launch_fft(int nt, int dbl, const JobDev *jobs, const Seg *segs, int 
 }
 
 hipError_t launch_decode(int var, int dbl, const JobDev *jobs, const Seg *segs, int nseg, long long nitems,
-                         int grid, float band, unsigned int *tile_flags, int2 *fb_list, StatsDev *st,
-                         hipStream_t s) {
+                         int grid, float band, unsigned int *tile_flags, int2 *fb_list, int2 *win_list,
+                         StatsDev *st, hipStream_t s) {
     if (nitems <= 0) return hipSuccess;
     if (var >= kDecFftVar) {
 #define MD_DFFT(R, M) \
-    k_decode_fft<R, M><<<grid, kDecThreads, 0, s>>>(jobs, segs, nseg, nitems, band, tile_flags, fb_list, st); break
+    k_decode_fft<R, M><<<grid, kDecThreads, 0, s>>>(jobs, segs, nseg, nitems, band, tile_flags, fb_list, win_list, \
+                                                     st); break
         switch ((dbl ? 100000 : 0) + decode_fft_m(var)) {
             case 64: MD_DFFT(float, 64);
             case 128: MD_DFFT(float, 128);
@@ -1455,7 +1578,8 @@ hipError_t launch_decode(int var, int dbl, const JobDev *jobs, const Seg *segs, 
         return hipGetLastError();
     }
 #define MD_DEC(R, V) \
-    k_decode<R, V><<<grid, kDecThreads, 0, s>>>(jobs, segs, nseg, nitems, band, tile_flags, fb_list, st); break
+    k_decode<R, V><<<grid, kDecThreads, 0, s>>>(jobs, segs, nseg, nitems, band, tile_flags, fb_list, win_list, st); \
+    break
     if (!dbl) {
         switch (var) {
             case kDec8: MD_DEC(float, kDec8);
@@ -1478,10 +1602,13 @@ int decode_group_variant(int bins, int dbl) { return decode_variant(bins, dbl); 
 
 int dec_pitch(int nr) { return ((nr / 2 + 1) + 31) / 32 * 32; }
 
-hipError_t launch_fallback(int nt64, const JobDev *jobs, const int2 *fb_list, const StatsDev *st,
-                           double2 *slots, size_t slot_elems, int grid, const double2 *tw64, double2 *slabs,
-                           hipStream_t s) {
-#define MD_FB(N) k_fallback<N><<<grid, kDecThreads, 0, s>>>(jobs, fb_list, st, slots, slot_elems, tw64, slabs); break;
+hipError_t launch_fallback(int nt64, const JobDev *jobs, const int2 *fb_list, StatsDev *st, double2 *slots,
+                           size_t slot_elems, int grid, const double2 *tw64, double2 *slabs,
+                           unsigned int *tile_flags, int2 *win_list, const uint8_t *perturb, hipStream_t s) {
+#define MD_FB(N)                                                                                             \
+    k_fallback<N><<<grid, kDecThreads, 0, s>>>(jobs, fb_list, st, slots, slot_elems, tw64, slabs, tile_flags, \
+                                                win_list, perturb);                                          \
+    break;
     switch (nt64) {
         case 16: MD_FB(16)
         case 32: MD_FB(32)
@@ -1493,6 +1620,13 @@ hipError_t launch_fallback(int nt64, const JobDev *jobs, const int2 *fb_list, co
         default: return hipErrorInvalidValue;
     }
 #undef MD_FB
+    return hipGetLastError();
+}
+
+hipError_t launch_tile_window(const JobDev *jobs, const int2 *win_list, const StatsDev *st, int pblocks, int grid,
+                              hipStream_t s) {
+    if (grid <= 0 || pblocks <= 0) return hipSuccess;
+    k_tile_window<<<grid, kDecThreads, 0, s>>>(jobs, win_list, st, pblocks);
     return hipGetLastError();
 }
 

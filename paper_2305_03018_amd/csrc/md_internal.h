@@ -103,6 +103,8 @@ struct JobDev {
     int dir_nsteps;
     int kpad;
     int dir_pack;                // element form of the window, direct_form()
+    const int32_t *se_cnt;       // [k+1][k+1] prefix counts of the effective SE mask: cnt[i][j] = active
+                                 // cells in rows < i, columns < j (transform jobs: the decode's count check)
     // exact transform path (dbl == kPrecNTT): se_spec / enc / dec hold uint32
     // residues mod kNttP, nr == bins == n, dec_pitch = n rounded up to 8
     const uint32_t *ntt_spec_s;  // Shoup companions of se_spec
@@ -140,9 +142,27 @@ __host__ __device__ inline size_t ypix(size_t q, int ybs) { return ybs ? (q >> 4
 struct StatsDev {
     unsigned int max_res_bits;   // float bits of the largest rounding residual
     unsigned int range_err;      // non-zero if an image value was outside [0, L-1]
-    unsigned int fb_count;       // ambiguous tiles appended to the recompute list
-    unsigned int pad;
+    unsigned int fb_count;       // FP32 tiles appended to the FP64 recompute list
+    unsigned int win_count;      // tiles appended to the exact window list (still ambiguous in FP64)
 };
+
+// Exactness checks of a decoded pixel (Step 3 on rounded coefficients).  A
+// tile is sent on to the next exact tier when, for any of its in-image
+// pixels and any degree d, |c_d - rint(c_d)| >= the band, or rint(c_d) < 0,
+// or sum_d rint(c_d) differs from the number of SE cells whose window pixel
+// lies in the image (the coefficients count those pairs).  The FP32 pass uses
+// MD_OPT_BAND; the FP64 passes of the tiers behind it use kExactBand, the
+// widest band within which rounding to the nearest integer is still sound
+// for errors below 0.75.
+constexpr float kExactBand = 0.25f;
+
+// Tile flags (one word per transform tile of a batch): bit 0 set when the
+// FP64 recompute took the tile, bit 1 when the exact window did.
+enum : unsigned { kFlagFp64 = 1u, kFlagWindow = 2u };
+
+// Test hook bits of the per-tile perturbation array: bit 0 perturbs the first
+// transform pass of the tile, bit 1 the FP64 recompute.
+enum : uint8_t { kPerturbFirst = 1, kPerturbFp64 = 2 };
 
 // ---------------------------------------------------------------------------
 // launchers (md_fft.hip, md_direct.hip); all enqueue on `s` and return the launch status
@@ -161,8 +181,10 @@ hipError_t launch_or_flag(uint32_t *dst, const uint32_t *src, hipStream_t s);
 hipError_t launch_add_const(int32_t *out, const int32_t *in, int32_t c, size_t n, hipStream_t s);
 hipError_t launch_sub(int32_t *out, const int32_t *x, const int32_t *y, size_t n, hipStream_t s);
 hipError_t launch_fill_hash(int32_t *p, size_t n, int L, unsigned int seed, hipStream_t s);
+// perturb: nullptr, or the test hook's per-tile bits (kPerturbFirst)
 hipError_t launch_fft(int nt, int dbl, const JobDev *jobs, const Seg *segs, int nseg, long long nitems,
-                      int grid, const TwF *tw32, const double2 *tw64, void *slabs, StatsDev *st, hipStream_t s);
+                      int grid, const TwF *tw32, const double2 *tw64, void *slabs, StatsDev *st,
+                      const uint8_t *perturb, hipStream_t s);
 // decode kernel variant for a job's kept-bin count, and the zero-padded pitch
 // (both dimensions) of the [bin][degree] decode table for a range length
 int decode_group_variant(int bins, int dbl);
@@ -193,16 +215,24 @@ constexpr int decode_fft_m(int var) {
 }
 constexpr int decode_fft_pixels(int nr) { return is_pow2c(nr) ? 8192 / nr : nr % 3 == 0 ? 12288 / nr : 10240 / nr; }
 int dec_pitch(int nr);
+// Flagged tiles of FP32 jobs go to fb_list (the FP64 recompute), those of
+// FP64 jobs to win_list (the exact window).
 hipError_t launch_decode(int var, int dbl, const JobDev *jobs, const Seg *segs, int nseg,
                          long long nitems, int grid, float band, unsigned int *tile_flags,
-                         int2 *fb_list, StatsDev *st, hipStream_t s);
+                         int2 *fb_list, int2 *win_list, StatsDev *st, hipStream_t s);
 // vol: volume jobs (a window pass per active SE slab, JobDev::slabs);
 // pack: direct_form()
 hipError_t launch_direct(int pack, int sel, const JobDev *jobs, const Seg *segs, int nseg, long long nitems,
                          int grid, size_t lds_bytes, StatsDev *st, hipStream_t s, bool vol = false);
-hipError_t launch_fallback(int nt64, const JobDev *jobs, const int2 *fb_list, const StatsDev *st,
-                           double2 *slots, size_t slot_elems, int grid, const double2 *tw64, double2 *slabs,
-                           hipStream_t s);
+// FP64 recompute of the tiles on fb_list whose recompute length is nt64; a
+// tile still ambiguous there is appended to win_list.
+hipError_t launch_fallback(int nt64, const JobDev *jobs, const int2 *fb_list, StatsDev *st, double2 *slots,
+                           size_t slot_elems, int grid, const double2 *tw64, double2 *slabs,
+                           unsigned int *tile_flags, int2 *win_list, const uint8_t *perturb, hipStream_t s);
+// Exact integer window (Eq. (6new)) over the tiles on win_list; each work
+// item is one block of kDecThreads pixels of a tile, pblocks items per tile.
+hipError_t launch_tile_window(const JobDev *jobs, const int2 *win_list, const StatsDev *st, int pblocks, int grid,
+                              hipStream_t s);
 // vol: the volume form of the packed kernel (32-row blocks)
 size_t direct_lds_bytes(int k, int kpad, int pack, int sel, bool vol = false);
 // Element form of the direct window for the largest reachable sum

@@ -63,6 +63,7 @@ struct Options {
     int autotune = 1;
     int stream_rows = 0;
     double stream_mb = 2048.0;
+    double cache_mb = 16384.0;
 };
 
 // Device buffer that only grows.
@@ -86,28 +87,58 @@ struct DevBuf {
     }
 };
 
-struct RangeTables {
-    DevBuf enc32, enc64, dec32, dec64, rtw32, rtw64;
+// Cached device objects: range tables, SE spectra (both transform
+// families) and the direct window's SE tables.  They live in one cache keyed
+// by their defining bytes and bounded in total size (MD_OPT_CACHE_MB):
+// inserting past the bound evicts the least recently used objects that no
+// cached executor references and that the current call has not touched.
+struct CacheObj {
+    virtual ~CacheObj() = default;
+    virtual size_t bytes() const = 0;
 };
 
-struct SESpec {
+struct RangeTables : CacheObj {
+    DevBuf enc32, enc64, dec32, dec64, rtw32, rtw64;
+    size_t bytes() const override {
+        return enc32.bytes + enc64.bytes + dec32.bytes + dec64.bytes + rtw32.bytes + rtw64.bytes;
+    }
+};
+
+struct SESpec : CacheObj {
     DevBuf s32, s64;
+    size_t bytes() const override { return s32.bytes + s64.bytes; }
 };
 
 // Exact transform path: range-axis tables for (n, L) and an SE spectrum per
 // (SE, nt, n), residues mod kNttP with Shoup companions.
-struct NttRange {
+struct NttRange : CacheObj {
     DevBuf enc, rpow, dec, dec_s;   // enc [n][L]; rpow [n] = w_n^e; dec [rows][dp] = n^-1 w_n^(-d m)
     int dp = 0;
+    size_t bytes() const override { return enc.bytes + rpow.bytes + dec.bytes + dec_s.bytes; }
 };
 
-struct NttSpec {
+struct NttSpec : CacheObj {
     DevBuf spec, spec_s;            // [n][nt][nt]
+    size_t bytes() const override { return spec.bytes + spec_s.bytes; }
 };
 
-struct DirSE {
-    DevBuf sek, sek16, sekh, rows, steps;
+// Per effective SE: the direct window's tables, and the 2-D prefix counts of
+// its mask (cnt[i][j] = active cells in rows < i and columns < j, pitch
+// k + 1) from which a decode derives how many window cells of a pixel lie in
+// the image.
+struct DirSE : CacheObj {
+    DevBuf sek, sek16, sekh, rows, steps, cnt;
     int kpad = 0, nsteps = 0;
+    size_t bytes() const override {
+        return sek.bytes + sek16.bytes + sekh.bytes + rows.bytes + steps.bytes + cnt.bytes;
+    }
+};
+
+struct CacheEntry {
+    std::unique_ptr<CacheObj> obj;
+    size_t bytes = 0;
+    unsigned long long stamp = 0;   // call that last used it
+    int refs = 0;                   // cached executors that hold its device pointers
 };
 
 // Per-job plan.
@@ -130,8 +161,10 @@ struct Group {
     Seg *segs_d = nullptr;
     int grid = 0;
     // algorithmic DRAM bytes / operations of the whole launch, and the work
-    // units the cost model prices it by
-    double alg_bytes = 0, alg_ops = 0, units = 0;
+    // units the cost model prices it by; transform and decode groups also
+    // count the in-image pixels they produce and (transforms) the complex
+    // transform-domain values they write
+    double alg_bytes = 0, alg_ops = 0, units = 0, pixels = 0, vol_elems = 0;
 };
 
 struct Wave {
@@ -142,6 +175,7 @@ struct Wave {
 struct Exec {
     std::vector<JobDev> jobs_h;
     std::vector<Plan> plans;
+    std::vector<CacheEntry *> pins;   // cache entries whose device pointers jobs_h holds
     JobDev *jobs_d = nullptr;
     JobDev *jobs_pin = nullptr;
     hipEvent_t copy_done = nullptr;
@@ -150,7 +184,17 @@ struct Exec {
     // allowed by the LDS footprint, capped at 4)
     std::vector<Group> direct;
     std::vector<Wave> waves;
-    DevBuf segbuf, ybuf, flags, list, slots;
+    DevBuf segbuf;
+    // workspace: the transform-domain buffer, the large-tile groups' slabs,
+    // the tile flags, the FP64-recompute and window lists, the recompute's
+    // slots and slabs; carved from the caller's buffer (md_set_workspace) or
+    // from ws_own
+    DevBuf ws_own;
+    size_t ws_need = 0;
+    void *ybuf = nullptr;
+    unsigned int *flags = nullptr;
+    int2 *list = nullptr, *wlist = nullptr;
+    double2 *slots = nullptr, *fb_slabs = nullptr;
     long long nflags = 0;
     // exact recompute, one launch per FP64 length: the per-block slot of the
     // largest job of that length and the launch's block count
@@ -160,10 +204,11 @@ struct Exec {
         int grid = 0;
     };
     std::vector<FbClass> fb_classes;
-    std::vector<std::unique_ptr<DevBuf>> slabbufs;   // per-block slabs of large-tile groups
-    DevBuf fb_slabs;
+    // exact window tier: pixel blocks per listed tile and the launch's blocks
+    int win_pblocks = 0, win_grid = 0;
     long long fft_tiles = 0;
     int n_direct = 0, n_fft = 0;
+    unsigned long long stamp = 0;   // call that last ran it
     hipGraph_t graph = nullptr;
     hipGraphExec_t gexec = nullptr;
     hipStream_t graph_stream = nullptr;
@@ -174,12 +219,8 @@ struct Exec {
         if (jobs_pin) (void)hipHostFree(jobs_pin);
         if (jobs_d) (void)hipFree(jobs_d);
         segbuf.release();
-        ybuf.release();
-        flags.release();
-        list.release();
-        slots.release();
-        fb_slabs.release();
-        for (auto &b : slabbufs) b->release();
+        ws_own.release();
+        for (CacheEntry *e : pins) --e->refs;
     }
 };
 
@@ -215,12 +256,21 @@ struct Ctx {
     StatsDev *st_h = nullptr;
     md_stats last{};
     CostModel cost;
-    std::map<std::pair<int, int>, std::unique_ptr<RangeTables>> ranges;
-    std::unordered_map<std::string, std::unique_ptr<SESpec>> spectra;
-    std::map<std::pair<int, int>, std::unique_ptr<NttRange>> nranges;
-    std::unordered_map<std::string, std::unique_ptr<NttSpec>> nspectra;
+    // cached device objects (see CacheObj), their total size, the number of
+    // the current call (an object it has touched is never evicted during it)
+    // and, while an executor is built, where the entries it uses are pinned
+    std::unordered_map<std::string, CacheEntry> cache;
+    size_t cache_bytes = 0;
+    unsigned long long call_id = 0;
+    std::vector<CacheEntry *> *pin_sink = nullptr;
+    // caller-owned workspace (md_set_workspace); null: each executor owns its own
+    void *ws_ptr = nullptr;
+    size_t ws_bytes = 0;
+    // perturbation test hook: (flat transform tile index, kPerturb* bits), and
+    // the per-tile byte array a call built from it
+    std::vector<std::pair<long long, uint8_t>> perturb;
+    DevBuf perturb_d;
     uint32_t *ntw = nullptr, *ntws = nullptr;   // w_kNttTw^j and Shoup companions
-    std::unordered_map<std::string, std::unique_ptr<DirSE>> dirse;
     std::unordered_map<std::string, std::unique_ptr<Exec>> execs;
     // repeat-call fast path: the previous batch call's job array, the bytes
     // of its SE arrays, the options it ran with and its executor
@@ -347,26 +397,91 @@ int init() {
 // ---------------------------------------------------------------------------
 // caches
 // ---------------------------------------------------------------------------
-int get_range(int nr, int L, RangeTables **out) {
-    auto key = std::make_pair(nr, L);
-    auto it = g.ranges.find(key);
-    if (it != g.ranges.end()) {
-        *out = it->second.get();
-        return MD_OK;
+// Key of a cached object: a tag for its kind, then its defining values.
+template <class... A> std::string cache_key(char tag, const A &...vals) {
+    std::string k(1, tag);
+    (k.append((const char *)&vals, sizeof vals), ...);
+    return k;
+}
+
+void cache_pin(CacheEntry &e) {
+    e.stamp = g.call_id;
+    if (g.pin_sink) {
+        ++e.refs;
+        g.pin_sink->push_back(&e);
     }
+}
+
+// The cached object under `key`, marked as used by the current call and
+// pinned to the executor being built; nullptr if absent.
+template <class T> T *cache_get(const std::string &key) {
+    auto it = g.cache.find(key);
+    if (it == g.cache.end()) return nullptr;
+    cache_pin(it->second);
+    return static_cast<T *>(it->second.obj.get());
+}
+
+// Makes room for `need` more bytes under MD_OPT_CACHE_MB: evicts, least
+// recently used first, objects that no cached executor pins and the current
+// call has not touched; if that is not enough, drops the cached executors
+// (they are rebuilt on their next call) and evicts again.  An object larger
+// than the bound still goes in.
+int cache_reserve(size_t need) {
+    const double cap = g.opt.cache_mb * 1024.0 * 1024.0;
+    if ((double)(g.cache_bytes + need) <= cap) return MD_OK;
+    MD_HIP(hipDeviceSynchronize());   // evicted objects may still be read by enqueued work
+    for (int pass = 0; pass < 2 && (double)(g.cache_bytes + need) > cap; ++pass) {
+        if (pass == 1) g.execs.clear(), g.last_exec = nullptr;
+        std::vector<std::pair<unsigned long long, std::string>> cand;
+        for (auto &kv : g.cache)
+            if (kv.second.refs == 0 && kv.second.stamp != g.call_id) cand.push_back({kv.second.stamp, kv.first});
+        std::sort(cand.begin(), cand.end());
+        for (auto &c : cand) {
+            if ((double)(g.cache_bytes + need) <= cap) break;
+            auto it = g.cache.find(c.second);
+            g.cache_bytes -= it->second.bytes;
+            g.cache.erase(it);
+        }
+    }
+    return MD_OK;
+}
+
+// Stores a newly built object and pins it as cache_get does.
+template <class T> T *cache_put(const std::string &key, std::unique_ptr<T> obj) {
+    T *p = obj.get();
+    CacheEntry &e = g.cache[key];
+    e.obj = std::move(obj);
+    e.bytes = p->bytes();
+    g.cache_bytes += e.bytes;
+    cache_pin(e);
+    return p;
+}
+
+// Brings an entry's recorded size up to date after buffers were added to it.
+void cache_resize(const std::string &key) {
+    auto it = g.cache.find(key);
+    if (it == g.cache.end()) return;
+    g.cache_bytes -= it->second.bytes;
+    it->second.bytes = it->second.obj->bytes();
+    g.cache_bytes += it->second.bytes;
+}
+
+int get_range(int nr, int L, RangeTables **out) {
+    const std::string key = cache_key('R', nr, L);
+    if ((*out = cache_get<RangeTables>(key))) return MD_OK;
     auto rt = std::make_unique<RangeTables>();
     const size_t bins = nr / 2 + 1;
     const size_t ne = bins * (size_t)L, nd = (size_t)dec_pitch(nr) * dec_pitch(nr);
+    MD_TRY(cache_reserve((ne + nd + bins) * (sizeof(float2) + sizeof(double2))));
     MD_TRY(rt->enc32.ensure(ne * sizeof(float2)));
     MD_TRY(rt->enc64.ensure(ne * sizeof(double2)));
     MD_TRY(rt->dec32.ensure(nd * sizeof(float2)));
     MD_TRY(rt->dec64.ensure(nd * sizeof(double2)));
-    MD_TRY(rt->rtw32.ensure((size_t)(nr / 2 + 1) * sizeof(float2)));
-    MD_TRY(rt->rtw64.ensure((size_t)(nr / 2 + 1) * sizeof(double2)));
+    MD_TRY(rt->rtw32.ensure(bins * sizeof(float2)));
+    MD_TRY(rt->rtw64.ensure(bins * sizeof(double2)));
     MD_HIP(launch_range_tables(nr, L, (float2 *)rt->enc32.p, (double2 *)rt->enc64.p, (float2 *)rt->dec32.p,
                                (double2 *)rt->dec64.p, (float2 *)rt->rtw32.p, (double2 *)rt->rtw64.p, g.stream));
-    *out = rt.get();
-    g.ranges[key] = std::move(rt);
+    *out = cache_put(key, std::move(rt));
     return MD_OK;
 }
 
@@ -592,26 +707,22 @@ void make_se(const uint8_t *mask, const int32_t *off, int k, int op, SEData &se)
 }
 
 int get_spectrum(const SEData &se, int nt, int nr, bool need32, bool need64, SESpec **out) {
-    std::string key = se.key;
+    std::string key = "S" + se.key;
     key.append((const char *)&nt, sizeof nt);
     key.append((const char *)&nr, sizeof nr);
-    auto it = g.spectra.find(key);
-    SESpec *sp = nullptr;
-    if (it != g.spectra.end()) {
-        sp = it->second.get();
-        if ((!need32 || sp->s32.p) && (!need64 || sp->s64.p)) {
-            *out = sp;
-            return MD_OK;
-        }
-    } else {
-        auto n = std::make_unique<SESpec>();
-        sp = n.get();
-        g.spectra[key] = std::move(n);
+    SESpec *sp = cache_get<SESpec>(key);
+    if (sp && (!need32 || sp->s32.p) && (!need64 || sp->s64.p)) {
+        *out = sp;
+        return MD_OK;
     }
     const int k = se.k, bins = nr / 2 + 1;
     const size_t nspec = (size_t)bins * nt * nt;
-    if (need32) MD_TRY(sp->s32.ensure(nspec * sizeof(float2)));
-    if (need64) MD_TRY(sp->s64.ensure(nspec * sizeof(double2)));
+    const bool add32 = need32 && !(sp && sp->s32.p), add64 = need64 && !(sp && sp->s64.p);
+    MD_TRY(cache_reserve(nspec * ((add32 ? sizeof(float2) : 0) + (add64 ? sizeof(double2) : 0))));
+    if (!sp) sp = cache_put(key, std::make_unique<SESpec>());
+    if (add32) MD_TRY(sp->s32.ensure(nspec * sizeof(float2)));
+    if (add64) MD_TRY(sp->s64.ensure(nspec * sizeof(double2)));
+    cache_resize(key);
     MD_TRY(g.se_work.ensure((size_t)bins * k * nt * sizeof(double2)));
     const size_t kk = (size_t)k * k;
     MD_TRY(g.se_in.ensure(kk * (sizeof(int32_t) + 1) + 64));
@@ -621,7 +732,7 @@ int get_spectrum(const SEData &se, int nt, int nr, bool need32, bool need64, SES
     MD_HIP(hipMemcpy(off_d, se.off.data(), kk * sizeof(int32_t), hipMemcpyHostToDevice));
     MD_HIP(hipMemcpy(mask_d, se.mask.data(), kk, hipMemcpyHostToDevice));
     MD_HIP(launch_se_spectrum(mask_d, off_d, k, nt, nr, g.tw64, (double2 *)g.se_work.p,
-                              need64 ? (double2 *)sp->s64.p : nullptr, need32 ? (float2 *)sp->s32.p : nullptr,
+                              sp->s64.p ? (double2 *)sp->s64.p : nullptr, sp->s32.p ? (float2 *)sp->s32.p : nullptr,
                               g.stream));
     MD_HIP(hipStreamSynchronize(g.stream));
     *out = sp;
@@ -632,12 +743,8 @@ int get_spectrum(const SEData &se, int nt, int nr, bool need32, bool need64, SES
 // enc[m][v] = w_n^(v m), rpow[e] = w_n^e, dec[m][d] = n^-1 w_n^(-d m) with
 // pitch dp = n rounded up to 8 and rows padded to a multiple of 16 (zeros).
 int get_nrange(int n, int L, NttRange **out) {
-    auto key = std::make_pair(n, L);
-    auto it = g.nranges.find(key);
-    if (it != g.nranges.end()) {
-        *out = it->second.get();
-        return MD_OK;
-    }
+    const std::string key = cache_key('N', n, L);
+    if ((*out = cache_get<NttRange>(key))) return MD_OK;
     auto rt = std::make_unique<NttRange>();
     const uint32_t wn = ppow(kNttG, (kNttP - 1) / n), ninv = pinv((uint32_t)n);
     std::vector<uint32_t> pw(n);
@@ -658,6 +765,7 @@ int get_nrange(int n, int L, NttRange **out) {
             dec[(size_t)m * rt->dp + d] = w;
             decs[(size_t)m * rt->dp + d] = shoup(w);
         }
+    MD_TRY(cache_reserve((enc.size() + pw.size() + dec.size() + decs.size()) * 4));
     MD_TRY(rt->enc.ensure(enc.size() * 4));
     MD_TRY(rt->rpow.ensure(pw.size() * 4));
     MD_TRY(rt->dec.ensure(dec.size() * 4));
@@ -666,25 +774,21 @@ int get_nrange(int n, int L, NttRange **out) {
     MD_HIP(hipMemcpy(rt->rpow.p, pw.data(), pw.size() * 4, hipMemcpyHostToDevice));
     MD_HIP(hipMemcpy(rt->dec.p, dec.data(), dec.size() * 4, hipMemcpyHostToDevice));
     MD_HIP(hipMemcpy(rt->dec_s.p, decs.data(), decs.size() * 4, hipMemcpyHostToDevice));
-    *out = rt.get();
-    g.nranges[key] = std::move(rt);
+    *out = cache_put(key, std::move(rt));
     return MD_OK;
 }
 
 // SE spectrum of the exact path at spatial length nt and range length n,
 // scaled by nt^-2.
 int get_nspectrum(const SEData &se, int nt, int n, const NttRange *rt, NttSpec **out) {
-    std::string key = se.key;
+    std::string key = "P" + se.key;
     key.append((const char *)&nt, sizeof nt);
     key.append((const char *)&n, sizeof n);
-    auto it = g.nspectra.find(key);
-    if (it != g.nspectra.end()) {
-        *out = it->second.get();
-        return MD_OK;
-    }
+    if ((*out = cache_get<NttSpec>(key))) return MD_OK;
     auto sp = std::make_unique<NttSpec>();
     const int k = se.k;
     const size_t nspec = (size_t)n * nt * nt;
+    MD_TRY(cache_reserve(nspec * 8));
     MD_TRY(sp->spec.ensure(nspec * 4));
     MD_TRY(sp->spec_s.ensure(nspec * 4));
     MD_TRY(g.se_work.ensure((size_t)n * k * nt * 4));
@@ -700,8 +804,7 @@ int get_nspectrum(const SEData &se, int nt, int n, const NttRange *rt, NttSpec *
                                   (uint32_t *)g.se_work.p, (uint32_t *)sp->spec.p, (uint32_t *)sp->spec_s.p,
                                   g.stream));
     MD_HIP(hipStreamSynchronize(g.stream));
-    *out = sp.get();
-    g.nspectra[key] = std::move(sp);
+    *out = cache_put(key, std::move(sp));
     return MD_OK;
 }
 
@@ -719,11 +822,8 @@ uint32_t f16_bits(int v) {
 // reflected), as int32 and as packed 16-bit pairs (int16 and f16), plus each
 // row's span of active cells.
 int get_dirse(const SEData &se, DirSE **out) {
-    auto it = g.dirse.find(se.key);
-    if (it != g.dirse.end()) {
-        *out = it->second.get();
-        return MD_OK;
-    }
+    const std::string key = "D" + se.key;
+    if ((*out = cache_get<DirSE>(key))) return MD_OK;
     auto d = std::make_unique<DirSE>();
     const int k = se.k;
     d->kpad = (k + kDirRX - 1) / kDirRX * kDirRX;
@@ -753,6 +853,14 @@ int get_dirse(const SEData &se, DirSE **out) {
     }
     const std::vector<int32_t> steps = dir_steps(se);
     d->nsteps = (int)steps.size() / 4;
+    // prefix counts of the mask
+    std::vector<int32_t> cnt((size_t)(k + 1) * (k + 1), 0);
+    for (int i = 0; i < k; ++i)
+        for (int j = 0; j < k; ++j)
+            cnt[(size_t)(i + 1) * (k + 1) + j + 1] = cnt[(size_t)i * (k + 1) + j + 1] +
+                                                     cnt[(size_t)(i + 1) * (k + 1) + j] -
+                                                     cnt[(size_t)i * (k + 1) + j] + (se.mask[(size_t)i * k + j] ? 1 : 0);
+    MD_TRY(cache_reserve((h.size() + h16.size() + hh.size() + rows.size() + steps.size() + cnt.size()) * 4));
     MD_TRY(d->sek.ensure(h.size() * sizeof(int32_t)));
     MD_TRY(d->sek16.ensure(h16.size() * sizeof(int32_t)));
     MD_TRY(d->sekh.ensure(hh.size() * sizeof(int32_t)));
@@ -764,8 +872,9 @@ int get_dirse(const SEData &se, DirSE **out) {
     MD_HIP(hipMemcpy(d->sek16.p, h16.data(), h16.size() * sizeof(int32_t), hipMemcpyHostToDevice));
     MD_HIP(hipMemcpy(d->sekh.p, hh.data(), hh.size() * sizeof(int32_t), hipMemcpyHostToDevice));
     MD_HIP(hipMemcpy(d->rows.p, rows.data(), rows.size() * sizeof(int32_t), hipMemcpyHostToDevice));
-    *out = d.get();
-    g.dirse[se.key] = std::move(d);
+    MD_TRY(d->cnt.ensure(cnt.size() * sizeof(int32_t)));
+    MD_HIP(hipMemcpy(d->cnt.p, cnt.data(), cnt.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+    *out = cache_put(key, std::move(d));
     return MD_OK;
 }
 
@@ -817,6 +926,21 @@ double fft_cost(const md_job &j, int nt, int nr, int dbl, bool lone = false) {
     return items * item + (double)tiles * T * T * dec_units(nr, dbl) * g.cost.dec_unit[dbl];
 }
 
+// Worst-case rounding error of a decoded coefficient from the FP32 pass of
+// one tile: |a|_2 |b|_2 3 log2(nt^2 nr) (u + beta) with u = 2^-24, the tile
+// umbra's 2-norm |a|_2 <= nt (one unit entry per pixel at each bin), the SE
+// umbra's |b|_2 = sqrt(|B|) (one per SE cell), the spatial stages' twiddle
+// error beta ~ 0 (split hi/lo twiddles) and the range stages' beta ~ u
+// (single-float twiddles in the decode), so the range stages count twice.
+// The band check is sound while the true error stays below 0.75 (a larger
+// one can round to a wrong integer unflagged); FP32 plans are kept where
+// this bound is at most kFp32BoundMax.
+double fp32_error_bound(int nt, int nr, long long ncells) {
+    return nt * std::sqrt((double)ncells) * 3.0 * (std::log2((double)nt * nt) + 2.0 * std::log2((double)nr)) *
+           std::ldexp(1.0, -24);
+}
+constexpr double kFp32BoundMax = 0.25;
+
 int plan_job(const md_job &j, const SEData &se, Plan &p, bool lone) {
     const long long nr_min = (long long)(j.L - 1) + se.maxoff + 1;
     int nr = (int)std::min<long long>(nr_min, 1 << 30);
@@ -825,7 +949,7 @@ int plan_job(const md_job &j, const SEData &se, Plan &p, bool lone) {
             return fail(MD_ERR_ARG, "forced range length %d < (L-1)+max offset+1 = %lld", g.opt.nr, nr_min);
         nr = g.opt.nr;
     }
-    const int dbl = g.opt.precision;   // kPrecFP32 / kPrecFP64 / kPrecNTT
+    int dbl = g.opt.precision;   // kPrecFP32 / kPrecFP64 / kPrecNTT
     bool ntt_ok = true;
     if (dbl == kPrecNTT) {
         // a range length that divides p - 1 (forced lengths must, too)
@@ -838,10 +962,10 @@ int plan_job(const md_job &j, const SEData &se, Plan &p, bool lone) {
         ntt_ok = nr > 0;
     }
     p = Plan();
-    p.dbl = dbl;
     const int form = direct_form((long long)(j.L - 1) + se.maxoff);
     const bool dir_ok = j.k <= kMaxDirectK;
     p.cost_dir = dir_ok ? dir_cost(j, se, form, lone) : INFINITY;
+    const bool fft_ok = nr_min <= 4096 && se.ncells > 0 && ntt_ok;
     // transform plan: best spatial length and, on the FP paths, range length
     // by the cost model: the smallest range length (dense decode) or, past
     // 128, the next power of two (range-axis FFT decode, at the price of more
@@ -851,32 +975,45 @@ int plan_job(const md_job &j, const SEData &se, Plan &p, bool lone) {
     // two wins from about 150 on (FP32 12.9 against 6.5 ms at 230, FP64 42.1
     // against 17.6 ms).
     // In FP32 the next lengths 3 2^a and 5 2^a are offered too when shorter
-    // (fewer bins than the power of two, the same decode).
-    int nrs[4] = {nr, 0, 0, 0};
-    if (dbl != kPrecNTT && g.opt.nr <= 0 && nr > 128) {
-        int nr2 = 1;
-        while (nr2 < nr) nr2 <<= 1;
-        if (nr2 != nr && decode_uses_fft(nr2, dbl)) nrs[1] = nr2;
-        int nr3 = 6;
-        while (nr3 < nr) nr3 <<= 1;
-        if (nr3 != nr && nr3 < nr2 && decode_uses_fft(nr3, dbl)) nrs[2] = nr3;
-        int nr5 = 10;
-        while (nr5 < nr) nr5 <<= 1;
-        if (nr5 != nr && nr5 < nr2 && nr5 < nr3 && decode_uses_fft(nr5, dbl)) nrs[3] = nr5;
-    }
+    // (fewer bins than the power of two, the same decode).  FP32 candidates
+    // whose error bound exceeds kFp32BoundMax are skipped; if none is left the
+    // job runs in FP64.
     double best = INFINITY;
     int best_nt = 0, best_nr = nr;
-    const bool fft_ok = nr_min <= 4096 && se.ncells > 0 && ntt_ok;
-    for (int c = 0; c < 4; ++c)
-        for (int nt = 16; fft_ok && nrs[c] > 0 && nt <= kMaxN; nt *= 2) {
-            if (g.opt.tile > 0 && nt != g.opt.tile) continue;
-            const double cst = fft_cost(j, nt, nrs[c], dbl, lone);
-            if (cst < best) {
-                best = cst;
-                best_nt = nt;
-                best_nr = nrs[c];
-            }
+    auto search = [&](int prec) {
+        int nrs[4] = {nr, 0, 0, 0};
+        if (prec != kPrecNTT && g.opt.nr <= 0 && nr > 128) {
+            int nr2 = 1;
+            while (nr2 < nr) nr2 <<= 1;
+            if (nr2 != nr && decode_uses_fft(nr2, prec)) nrs[1] = nr2;
+            int nr3 = 6;
+            while (nr3 < nr) nr3 <<= 1;
+            if (nr3 != nr && nr3 < nr2 && decode_uses_fft(nr3, prec)) nrs[2] = nr3;
+            int nr5 = 10;
+            while (nr5 < nr) nr5 <<= 1;
+            if (nr5 != nr && nr5 < nr2 && nr5 < nr3 && decode_uses_fft(nr5, prec)) nrs[3] = nr5;
         }
+        best = INFINITY;
+        best_nt = 0;
+        best_nr = nr;
+        for (int c = 0; c < 4; ++c)
+            for (int nt = 16; fft_ok && nrs[c] > 0 && nt <= kMaxN; nt *= 2) {
+                if (g.opt.tile > 0 && nt != g.opt.tile) continue;
+                if (prec == kPrecFP32 && fp32_error_bound(nt, nrs[c], se.ncells) > kFp32BoundMax) continue;
+                const double cst = fft_cost(j, nt, nrs[c], prec, lone);
+                if (cst < best) {
+                    best = cst;
+                    best_nt = nt;
+                    best_nr = nrs[c];
+                }
+            }
+    };
+    search(dbl);
+    if (dbl == kPrecFP32 && fft_ok && !best_nt) {
+        dbl = kPrecFP64;
+        search(dbl);
+    }
+    p.dbl = dbl;
     p.nr = best_nr;
     p.bins = dbl == kPrecNTT ? p.nr : p.nr / 2 + 1;
     p.dec_fft = dbl != kPrecNTT && decode_uses_fft(p.nr, dbl);
@@ -957,12 +1094,20 @@ std::string signature(const md_job *jobs, int n, const std::vector<SEData> &ses)
     return s;
 }
 
-int build_exec(const md_job *jobs, int n, const std::vector<SEData> &ses, Exec &ex) {
+// Builds a batch's executor: plans, device job and segment tables, launch
+// groups and the workspace layout.  With layout_only it stops once the
+// workspace size (ex.ws_need) is known, touching no device memory.
+int build_exec(const md_job *jobs, int n, const std::vector<SEData> &ses, Exec &ex, bool layout_only = false) {
+    struct PinScope {   // cache entries used from here on are pinned to ex
+        explicit PinScope(std::vector<CacheEntry *> *p) { g.pin_sink = p; }
+        ~PinScope() { g.pin_sink = nullptr; }
+    } pin_scope(layout_only ? nullptr : &ex.pins);
     ex.jobs_h.resize(n);
     ex.plans.resize(n);
     std::vector<size_t> dir_lds(n, 0);
     std::vector<int> dir_sel(n, 0);
     long long flag_total = 0;
+    int win_tmax = 0;
     const size_t cap_bytes = (size_t)std::max(1.0, g.opt.ws_mb) * 1024 * 1024;
     // per-job plans and device descriptors
     for (int i = 0; i < n; ++i) {
@@ -980,57 +1125,35 @@ int build_exec(const md_job *jobs, int n, const std::vector<SEData> &ses, Exec &
         d.k = j.k;
         d.op = j.op;
         d.path = p.path;
-        if (p.path == kPathDirect) {
-            DirSE *ds = nullptr;
+        d.kpad = (j.k + kDirRX - 1) / kDirRX * kDirRX;
+        DirSE *ds = nullptr;
+        // window tables: the direct path, and the exact window tier behind
+        // the FP transform passes
+        if (!layout_only && (p.path == kPathDirect || p.dbl != kPrecNTT)) {
             MD_TRY(get_dirse(ses[i], &ds));
             d.sek = (const int32_t *)ds->sek.p;
+            d.se_cnt = (const int32_t *)ds->cnt.p;
+        }
+        if (p.path == kPathDirect) {
             d.dir_pack = direct_form((long long)(j.L - 1) + ses[i].maxoff);
-            d.sek16 = (const int32_t *)(d.dir_pack == 2 ? ds->sekh.p : ds->sek16.p);
-            d.sek_rows = (const int32_t *)ds->rows.p;
-            d.sek_steps = (const int32_t *)ds->steps.p;
-            d.dir_nsteps = ds->nsteps;
-            d.kpad = ds->kpad;
+            if (ds) {
+                d.sek16 = (const int32_t *)(d.dir_pack == 2 ? ds->sekh.p : ds->sek16.p);
+                d.sek_rows = (const int32_t *)ds->rows.p;
+                d.sek_steps = (const int32_t *)ds->steps.p;
+                d.dir_nsteps = ds->nsteps;
+            }
             d.dir_bx = (j.W + kDirBW - 1) / kDirBW;
             d.dir_by = (j.H + direct_block_rows(d.dir_pack) - 1) / direct_block_rows(d.dir_pack);
             // the packed form reads the SE through scalar loads; the 32-bit form
             // stages it in LDS when it fits
-            const int sel = !d.dir_pack && direct_lds_bytes(j.k, ds->kpad, 0, 1) <= kLdsBytes ? 1 : 0;
+            const int sel = !d.dir_pack && direct_lds_bytes(j.k, d.kpad, 0, 1) <= kLdsBytes ? 1 : 0;
             dir_sel[i] = sel;
-            dir_lds[i] = direct_lds_bytes(j.k, ds->kpad, d.dir_pack, sel);
+            dir_lds[i] = direct_lds_bytes(j.k, d.kpad, d.dir_pack, sel);
             if (dir_lds[i] > kLdsBytes) return fail(MD_ERR_UNSUPPORTED, "direct window for k=%d exceeds the LDS", j.k);
-        }
-        if (p.path == kPathDirect) {
             ++ex.n_direct;
             continue;
         }
         ++ex.n_fft;
-        if (p.dbl == kPrecNTT) {
-            NttRange *nrt = nullptr;
-            MD_TRY(get_nrange(p.nr, j.L, &nrt));
-            NttSpec *nsp = nullptr;
-            MD_TRY(get_nspectrum(ses[i], p.nt, p.nr, nrt, &nsp));
-            d.nt = p.nt;
-            d.T = p.T;
-            d.nr = p.nr;
-            d.bins = p.bins;
-            d.tiles_x = p.tiles_x;
-            d.tiles_y = p.tiles_y;
-            d.dbl = kPrecNTT;
-            d.se_spec = nsp->spec.p;
-            d.ntt_spec_s = (const uint32_t *)nsp->spec_s.p;
-            d.enc = nrt->enc.p;
-            d.dec = nrt->dec.p;
-            d.ntt_dec_s = (const uint32_t *)nrt->dec_s.p;
-            d.dec_pitch = nrt->dp;
-            d.ntt_dtop = (j.L - 1) + ses[i].maxoff;
-            d.fb_mode = kFbNone;
-            ex.fft_tiles += (long long)p.tiles_x * p.tiles_y;
-            continue;
-        }
-        RangeTables *rt = nullptr;
-        MD_TRY(get_range(p.nr, j.L, &rt));
-        SESpec *sp = nullptr;
-        MD_TRY(get_spectrum(ses[i], p.nt, p.nr, !p.dbl, p.dbl != 0, &sp));
         d.nt = p.nt;
         d.T = p.T;
         d.nr = p.nr;
@@ -1038,26 +1161,53 @@ int build_exec(const md_job *jobs, int n, const std::vector<SEData> &ses, Exec &
         d.tiles_x = p.tiles_x;
         d.tiles_y = p.tiles_y;
         d.dbl = p.dbl;
+        if (p.dbl == kPrecNTT) {
+            if (!layout_only) {
+                NttRange *nrt = nullptr;
+                MD_TRY(get_nrange(p.nr, j.L, &nrt));
+                NttSpec *nsp = nullptr;
+                MD_TRY(get_nspectrum(ses[i], p.nt, p.nr, nrt, &nsp));
+                d.se_spec = nsp->spec.p;
+                d.ntt_spec_s = (const uint32_t *)nsp->spec_s.p;
+                d.enc = nrt->enc.p;
+                d.dec = nrt->dec.p;
+                d.ntt_dec_s = (const uint32_t *)nrt->dec_s.p;
+                d.dec_pitch = nrt->dp;
+            }
+            d.ntt_dtop = (j.L - 1) + ses[i].maxoff;
+            d.fb_mode = kFbNone;
+            ex.fft_tiles += (long long)p.tiles_x * p.tiles_y;
+            continue;
+        }
+        RangeTables *rt = nullptr;
+        if (!layout_only) {
+            MD_TRY(get_range(p.nr, j.L, &rt));
+            SESpec *sp = nullptr;
+            MD_TRY(get_spectrum(ses[i], p.nt, p.nr, !p.dbl, p.dbl != 0, &sp));
+            d.se_spec = p.dbl ? sp->s64.p : sp->s32.p;
+            d.enc = p.dbl ? rt->enc64.p : rt->enc32.p;
+            d.dec = p.dbl ? rt->dec64.p : rt->dec32.p;
+            d.rtw = p.dbl ? rt->rtw64.p : rt->rtw32.p;
+        }
         d.scale = 1.0 / ((double)p.nt * p.nt * p.nr);
-        d.se_spec = p.dbl ? sp->s64.p : sp->s32.p;
-        d.enc = p.dbl ? rt->enc64.p : rt->enc32.p;
-        d.dec = p.dbl ? rt->dec64.p : rt->dec32.p;
         d.dec_pitch = dec_pitch(p.nr);
-        d.rtw = p.dbl ? rt->rtw64.p : rt->rtw32.p;
         d.ybs = plan_ybs(p);
         d.flag0 = flag_total;
         flag_total += (long long)p.tiles_x * p.tiles_y;
         ex.fft_tiles += (long long)p.tiles_x * p.tiles_y;
+        win_tmax = std::max(win_tmax, p.T);
         d.fb_mode = p.fb_mode;
         if (p.fb_mode == kFbFFT64) {
-            SESpec *sp64 = nullptr;
-            MD_TRY(get_spectrum(ses[i], p.nt64, p.nr, false, true, &sp64));
+            if (!layout_only) {
+                SESpec *sp64 = nullptr;
+                MD_TRY(get_spectrum(ses[i], p.nt64, p.nr, false, true, &sp64));
+                d.se_spec64 = (const double2 *)sp64->s64.p;
+                d.enc64 = (const double2 *)rt->enc64.p;
+                d.dec64 = (const double2 *)rt->dec64.p;
+            }
             d.nt64 = p.nt64;
             d.T64 = p.T64;
             d.scale64 = 1.0 / ((double)p.nt64 * p.nt64 * p.nr);
-            d.se_spec64 = (const double2 *)sp64->s64.p;
-            d.enc64 = (const double2 *)rt->enc64.p;
-            d.dec64 = (const double2 *)rt->dec64.p;
             auto fc = std::find_if(ex.fb_classes.begin(), ex.fb_classes.end(),
                                    [&](const Exec::FbClass &c) { return c.nt64 == p.nt64; });
             if (fc == ex.fb_classes.end()) {
@@ -1131,7 +1281,6 @@ int build_exec(const md_job *jobs, int n, const std::vector<SEData> &ses, Exec &
     }
     size_t ymax = 0;
     for (size_t w = 0; w < wave_chunks.size(); ++w) ymax = std::max(ymax, wave_bytes[w]);
-    MD_TRY(ex.ybuf.ensure(ymax));
     for (size_t w = 0; w < wave_chunks.size(); ++w) {
         if (wave_chunks[w].empty()) continue;
         Wave wv;
@@ -1146,32 +1295,38 @@ int build_exec(const md_job *jobs, int n, const std::vector<SEData> &ses, Exec &
             s.ntiles = nt_;
             const int dpix = p.dec_fft ? decode_fft_pixels(p.nr) : kDecThreads * kDecPixPerThread;
             s.pblocks = (p.T * p.T + dpix - 1) / dpix;
-            s.y = (char *)ex.ybuf.p + off;
+            s.y = (void *)(uintptr_t)off;   // an offset into the transform-domain buffer until it is placed
             off += per_tile * nt_;
             const bool ntt = p.dbl == kPrecNTT;
             const double esz = (double)elem_bytes(p.dbl), N2 = (double)p.nt * p.nt, TT = (double)p.T * p.T;
             const double items = (double)nt_ * p.bins;
-            Group *gf = find_group(wv.fft, p.nt, p.dbl, 0);
-            s.item0 = gf->nitems;
-            gf->segs.push_back(s);
-            gf->nitems += (long long)nt_ * p.bins;
-            gf->alg_bytes += items * TT * esz + (double)nt_ * N2 * 4.0;
-            // FP: flops of the forward and inverse 2-D FFTs and the product;
-            // exact: modular products (one per butterfly and per point)
-            gf->alg_ops += ntt ? items * (N2 * log2(N2) + N2) : items * (2.0 * 5.0 * N2 * log2(N2) + 6.0 * N2);
-            gf->units += items;
-            const int dvar = ntt ? 0 : p.dec_fft ? decode_fft_var(p.nr) : decode_group_variant(p.bins, p.dbl);
-            Group *gd = find_group(wv.dec, 0, p.dbl, dvar);
-            s.item0 = gd->nitems;
-            gd->segs.push_back(s);
-            gd->nitems += (long long)nt_ * s.pblocks;
             // pixels of these tiles that lie inside the image
             double inside = 0;
             for (int t = tile0; t < tile0 + nt_; ++t) {
                 const int ty = t / p.tiles_x, tx = t % p.tiles_x;
                 inside += (double)std::min(p.T, jobs[i].H - ty * p.T) * std::min(p.T, jobs[i].W - tx * p.T);
             }
+            Group *gf = find_group(wv.fft, p.nt, p.dbl, 0);
+            s.item0 = gf->nitems;
+            gf->segs.push_back(s);
+            gf->nitems += (long long)nt_ * p.bins;
+            // HBM bytes the transform must move: the int32 tile in once per
+            // bin (the encode reads it from HBM or L2) and its valid outputs
+            // out; the SE spectrum is L2/MALL-resident
+            gf->alg_bytes += items * TT * esz + (double)nt_ * N2 * 4.0;
+            // FP: flops of the forward and inverse 2-D FFTs and the product;
+            // exact: modular products (one per butterfly and per point)
+            gf->alg_ops += ntt ? items * (N2 * log2(N2) + N2) : items * (2.0 * 5.0 * N2 * log2(N2) + 6.0 * N2);
+            gf->units += items;
+            gf->pixels += inside;
+            gf->vol_elems += items * TT;
+            const int dvar = ntt ? 0 : p.dec_fft ? decode_fft_var(p.nr) : decode_group_variant(p.bins, p.dbl);
+            Group *gd = find_group(wv.dec, 0, p.dbl, dvar);
+            s.item0 = gd->nitems;
+            gd->segs.push_back(s);
+            gd->nitems += (long long)nt_ * s.pblocks;
             gd->alg_bytes += inside * (p.bins * esz + 4.0);
+            gd->pixels += inside;
             if (ntt) {
                 // one block of 8 degrees per pixel, over all n bins
                 gd->alg_ops += inside * p.nr * 8.0;
@@ -1189,37 +1344,28 @@ int build_exec(const md_job *jobs, int n, const std::vector<SEData> &ses, Exec &
         }
         ex.waves.push_back(std::move(wv));
     }
-    // device copies of the segment tables
+    // segment tables (device copies below) and launch grids
     size_t nseg_total = 0;
     for (auto &gr : ex.direct) nseg_total += gr.segs.size();
     for (auto &wv : ex.waves) {
         for (auto &gr : wv.fft) nseg_total += gr.segs.size();
         for (auto &gr : wv.dec) nseg_total += gr.segs.size();
     }
-    MD_TRY(ex.segbuf.ensure(std::max<size_t>(1, nseg_total) * sizeof(Seg)));
-    std::vector<Seg> all;
-    all.reserve(nseg_total);
-    auto place = [&](Group &gr, int threads, size_t lds) {
-        gr.segs_d = (Seg *)ex.segbuf.p + all.size();
-        all.insert(all.end(), gr.segs.begin(), gr.segs.end());
-        gr.grid = occupancy_grid(gr.nitems, lds, threads);
-    };
-    for (auto &gr : ex.direct) place(gr, kDirThreads, gr.lds);
+    for (auto &gr : ex.direct) gr.grid = occupancy_grid(gr.nitems, gr.lds, kDirThreads);
+    std::vector<std::pair<Group *, size_t>> slab_groups;   // large-tile groups and their slab bytes
     for (auto &wv : ex.waves) {
         for (auto &gr : wv.fft) {
             if (gr.dbl == kPrecNTT) {
-                place(gr, ntt_block_threads(gr.nt), ntt_lds_bytes(gr.nt));
+                gr.grid = occupancy_grid(gr.nitems, ntt_lds_bytes(gr.nt), ntt_block_threads(gr.nt));
                 continue;
             }
-            place(gr, fft_block_threads(gr.nt, gr.dbl), fft_lds_bytes(gr.nt, gr.dbl));
+            gr.grid = occupancy_grid(gr.nitems, fft_lds_bytes(gr.nt, gr.dbl), fft_block_threads(gr.nt, gr.dbl));
             if (gr.nt > (gr.dbl ? kMaxLdsN64 : kMaxLdsN32)) {
                 // 1024-point tiles keep 3 blocks per CU resident (registers):
                 // no slab for a fourth that would only wait
                 if (gr.nt >= 1024) gr.grid = (int)std::min<long long>(gr.grid, 3LL * g.cu);
-                auto b = std::make_unique<DevBuf>();
-                MD_TRY(b->ensure((size_t)gr.grid * gr.nt * gr.nt * (gr.dbl ? sizeof(double2) : sizeof(float2))));
-                gr.slabs = b->p;
-                ex.slabbufs.push_back(std::move(b));
+                slab_groups.push_back(
+                    {&gr, (size_t)gr.grid * gr.nt * gr.nt * (gr.dbl ? sizeof(double2) : sizeof(float2))});
             }
         }
         for (auto &gr : wv.dec) {
@@ -1232,31 +1378,80 @@ int build_exec(const md_job *jobs, int n, const std::vector<SEData> &ses, Exec &
             const size_t pts = p2 ? 4352 : m3 ? 6400 : 5376;
             const bool last2 = p2 ? dm <= 256 : m3 ? dm <= 192 : dm <= 80;
             const size_t lds = dm ? (pts + (last2 ? 2 * dm : dm)) * elem : 0;
-            place(gr, kDecThreads, lds);
+            gr.grid = occupancy_grid(gr.nitems, lds, kDecThreads);
         }
     }
-    if (!all.empty()) MD_HIP(hipMemcpy(ex.segbuf.p, all.data(), all.size() * sizeof(Seg), hipMemcpyHostToDevice));
-    // recompute resources
+    // recompute tiers
     ex.nflags = flag_total;
-    MD_TRY(ex.flags.ensure(std::max<long long>(1, flag_total) * sizeof(unsigned int)));
-    MD_TRY(ex.list.ensure(std::max<long long>(1, flag_total) * sizeof(int2)));
+    size_t slot_bytes = 0, fb_slab_bytes = 0;
     if (!ex.fb_classes.empty()) {
         // recompute blocks per length: two per CU (the kernel's LDS holds two),
         // bounded so that that launch's slots and slabs stay under ~2 GiB.  Each
         // length sizes its own grid, so a long tile's large slots do not starve
         // the launches of shorter ones; the buffers fit the largest launch.
-        size_t slot_bytes = 0, slab_bytes = 0;
         for (auto &c : ex.fb_classes) {
             const double slab = c.nt64 > kMaxLdsN64 ? (double)c.nt64 * c.nt64 * sizeof(double2) : 0.0;
             const double per_block = (double)c.slot_elems * sizeof(double2) + slab;
             const int cap = (int)std::max(1.0, std::min(2.0 * g.cu, (double)(2ll << 30) / per_block));
             c.grid = (int)std::max<long long>(1, std::min<long long>(flag_total, cap));
             slot_bytes = std::max(slot_bytes, (size_t)c.grid * c.slot_elems * sizeof(double2));
-            if (slab > 0) slab_bytes = std::max(slab_bytes, (size_t)c.grid * c.nt64 * c.nt64 * sizeof(double2));
+            if (slab > 0) fb_slab_bytes = std::max(fb_slab_bytes, (size_t)c.grid * c.nt64 * c.nt64 * sizeof(double2));
         }
-        MD_TRY(ex.slots.ensure(slot_bytes));
-        if (slab_bytes) MD_TRY(ex.fb_slabs.ensure(slab_bytes));
     }
+    if (flag_total > 0) {
+        ex.win_pblocks = (win_tmax * win_tmax + kDecThreads - 1) / kDecThreads;
+        ex.win_grid = (int)std::max<long long>(1, std::min<long long>(flag_total * ex.win_pblocks, 8LL * g.cu));
+    }
+    // workspace layout, 256-byte aligned regions
+    size_t ws = 0;
+    auto region = [&](size_t bytes) {
+        const size_t at = ws;
+        ws += (bytes + 255) / 256 * 256;
+        return at;
+    };
+    const size_t o_y = region(ymax);
+    std::vector<size_t> o_slab;
+    for (auto &sg : slab_groups) o_slab.push_back(region(sg.second));
+    const size_t o_flags = region((size_t)flag_total * sizeof(unsigned int));
+    const size_t o_list = region((size_t)flag_total * sizeof(int2));
+    const size_t o_wlist = region((size_t)flag_total * sizeof(int2));
+    const size_t o_slots = region(slot_bytes);
+    const size_t o_fbslab = region(fb_slab_bytes);
+    ex.ws_need = ws;
+    if (layout_only) return MD_OK;
+    char *base = nullptr;
+    if (g.ws_ptr) {
+        if (ws > g.ws_bytes)
+            return fail(MD_ERR_ARG, "the workspace holds %zu bytes, this batch needs %zu (md_workspace_size)", g.ws_bytes,
+                        ws);
+        base = (char *)g.ws_ptr;
+    } else {
+        MD_TRY(ex.ws_own.ensure(ws));
+        base = (char *)ex.ws_own.p;
+    }
+    ex.ybuf = base + o_y;
+    for (size_t q = 0; q < slab_groups.size(); ++q) slab_groups[q].first->slabs = base + o_slab[q];
+    ex.flags = (unsigned int *)(base + o_flags);
+    ex.list = (int2 *)(base + o_list);
+    ex.wlist = (int2 *)(base + o_wlist);
+    ex.slots = (double2 *)(base + o_slots);
+    ex.fb_slabs = (double2 *)(base + o_fbslab);
+    // segment tables on the device, transform-domain offsets made pointers
+    MD_TRY(ex.segbuf.ensure(std::max<size_t>(1, nseg_total) * sizeof(Seg)));
+    std::vector<Seg> all;
+    all.reserve(nseg_total);
+    auto place = [&](Group &gr) {
+        for (auto &sg : gr.segs)
+            if (sg.y || ex.plans[sg.job].path == kPathFFT) sg.y = (char *)ex.ybuf + (uintptr_t)sg.y;
+        gr.segs_d = (Seg *)ex.segbuf.p + all.size();
+        all.insert(all.end(), gr.segs.begin(), gr.segs.end());
+    };
+    for (auto &gr : ex.direct) place(gr);
+    for (auto &wv : ex.waves) {
+        for (auto &gr : wv.fft) place(gr);
+        for (auto &gr : wv.dec) place(gr);
+    }
+    if (!all.empty()) MD_HIP(hipMemcpy(ex.segbuf.p, all.data(), all.size() * sizeof(Seg), hipMemcpyHostToDevice));
     // job table
     MD_HIP(hipMalloc(&ex.jobs_d, sizeof(JobDev) * n));
     MD_HIP(hipHostMalloc((void **)&ex.jobs_pin, sizeof(JobDev) * n, 0));
@@ -1315,11 +1510,13 @@ void resolve_profile() {
     g.pending.clear();
 }
 
-// Stream-ordered launches of one batch.
-int enqueue(Exec &ex, hipStream_t s, bool skip_decode = false, bool capturing = false) {
+// Stream-ordered launches of one batch.  perturb: the test hook's per-tile
+// bits (never set while capturing).
+int enqueue(Exec &ex, hipStream_t s, bool skip_decode = false, bool capturing = false,
+            const uint8_t *perturb = nullptr) {
     const bool prof = g.opt.profile && !capturing;
     MD_HIP(launch_zero(g.st_d, sizeof(StatsDev), s));
-    if (ex.nflags > 0) MD_HIP(launch_zero(ex.flags.p, ex.nflags * sizeof(unsigned int), s));
+    if (ex.nflags > 0) MD_HIP(launch_zero(ex.flags, ex.nflags * sizeof(unsigned int), s));
     // With both paths in the batch, the direct-window launches go to a side
     // stream, so the transform path's launches take the CUs that the direct
     // grid's last blocks leave idle; the library stream joins the side stream
@@ -1374,7 +1571,7 @@ int enqueue(Exec &ex, hipStream_t s, bool skip_decode = false, bool capturing = 
             ProfScope ps(prof, s, std::string(gr.dbl ? "fft64_n" : "fft32_n") + std::to_string(gr.nt), gr.alg_bytes,
                          gr.alg_ops, gr.units);
             MD_HIP(launch_fft(gr.nt, gr.dbl, ex.jobs_d, gr.segs_d, (int)gr.segs.size(), gr.nitems, gr.grid, g.tw32,
-                              g.tw64, gr.slabs, g.st_d, s));
+                              g.tw64, gr.slabs, g.st_d, perturb, s));
             ps.done();
         }
         if (skip_decode) continue;
@@ -1389,7 +1586,7 @@ int enqueue(Exec &ex, hipStream_t s, bool skip_decode = false, bool capturing = 
             ProfScope ps(prof, s, gr.dbl ? (dfft ? "decode64_fft" : "decode64") : (dfft ? "decode32_fft" : "decode32"),
                          gr.alg_bytes, gr.alg_ops, gr.units);
             MD_HIP(launch_decode(gr.big, gr.dbl, ex.jobs_d, gr.segs_d, (int)gr.segs.size(), gr.nitems, gr.grid,
-                                 band, (unsigned int *)ex.flags.p, (int2 *)ex.list.p, g.st_d, s));
+                                 band, ex.flags, ex.list, ex.wlist, g.st_d, s));
             ps.done();
         }
     }
@@ -1397,8 +1594,13 @@ int enqueue(Exec &ex, hipStream_t s, bool skip_decode = false, bool capturing = 
     if (skip_decode) return MD_OK;
     for (const auto &c : ex.fb_classes) {
         ProfScope ps(prof, s, "recompute64_n" + std::to_string(c.nt64), 0, 0, 0);
-        MD_HIP(launch_fallback(c.nt64, ex.jobs_d, (const int2 *)ex.list.p, g.st_d, (double2 *)ex.slots.p,
-                               c.slot_elems, c.grid, g.tw64, (double2 *)ex.fb_slabs.p, s));
+        MD_HIP(launch_fallback(c.nt64, ex.jobs_d, ex.list, g.st_d, ex.slots, c.slot_elems, c.grid, g.tw64,
+                               ex.fb_slabs, ex.flags, ex.wlist, perturb, s));
+        ps.done();
+    }
+    if (ex.win_grid > 0) {
+        ProfScope ps(prof, s, "window_exact", 0, 0, 0);
+        MD_HIP(launch_tile_window(ex.jobs_d, ex.wlist, g.st_d, ex.win_pblocks, ex.win_grid, s));
         ps.done();
     }
     return MD_OK;
@@ -1414,14 +1616,14 @@ int collect_stats(Exec &ex, int *range_err) {
     st.max_residual = res;
     st.tiles = ex.fft_tiles;
     st.fallback_tiles = g.st_h->fb_count;
-    st.unresolved_tiles = g.st_h->pad;
+    st.window_tiles = g.st_h->win_count;
     st.direct_jobs = ex.n_direct;
     st.fft_jobs = ex.n_fft;
     const Plan &p = ex.plans.back();
     st.path = p.path;
     st.n_t = p.nt;
     st.n_r = p.path == kPathFFT ? p.nr : 0;
-    st.precision = g.opt.precision;
+    st.precision = p.path == kPathFFT ? p.dbl : g.opt.precision;
     *range_err = g.st_h->range_err != 0;
     return MD_OK;
 }
@@ -1625,8 +1827,33 @@ bool same_se_bytes(const md_job *jobs, int n, const std::string &prev) {
     return off == prev.size();
 }
 
+// Room for a new cached executor whose own workspace takes `adding` bytes:
+// the cached executors are kept to at most kMaxExecs, and their workspace
+// together with the new one's within MD_OPT_CACHE_MB, by dropping the least
+// recently run ones (they are rebuilt on their next call).
+constexpr size_t kMaxExecs = 64;
+int trim_execs(size_t adding) {
+    const double cap = g.opt.cache_mb * 1024.0 * 1024.0;
+    auto total = [&] {
+        size_t t = adding;
+        for (auto &kv : g.execs) t += kv.second->ws_own.bytes;
+        return t;
+    };
+    if (g.execs.size() < kMaxExecs && (double)total() <= cap) return MD_OK;
+    MD_HIP(hipDeviceSynchronize());   // their graphs and buffers may still be in use
+    while (!g.execs.empty() && (g.execs.size() >= kMaxExecs || (double)total() > cap)) {
+        auto lru = g.execs.begin();
+        for (auto it = g.execs.begin(); it != g.execs.end(); ++it)
+            if (it->second->stamp < lru->second->stamp) lru = it;
+        if (lru->second.get() == g.last_exec) g.last_exec = nullptr;
+        g.execs.erase(lru);
+    }
+    return MD_OK;
+}
+
 int run(const md_job *jobs, int n, bool use_graph) {
     MD_TRY(init());
+    ++g.call_id;
     if (g.opt.path == 0 && g.opt.autotune && !g.tuned && !g.tuning) MD_TRY(autotune());
     if (n < 1 || !jobs) return fail(MD_ERR_ARG, "empty batch");
     // A call identical to the previous one (job array, SE contents, options)
@@ -1654,11 +1881,12 @@ int run(const md_job *jobs, int n, bool use_graph) {
         const int rc = build_exec(jobs, n, ses, *e);
         if (rc != MD_OK) return rc;
         ex = e.get();
-        if (g.execs.size() > 64) g.execs.clear(), g.last_exec = nullptr;
+        MD_TRY(trim_execs(e->ws_own.bytes));
         g.execs[sig] = std::move(e);
     } else {
         ex = it->second.get();
     }
+    ex->stamp = g.call_id;
     if (!repeat) {
         g.last_jobs.assign(jobs, jobs + n);
         g.last_se = se_bytes(jobs, n);
@@ -1681,7 +1909,18 @@ int run(const md_job *jobs, int n, bool use_graph) {
         MD_HIP(hipEventRecord(ex->copy_done, g.stream));
         ex->copy_pending = true;
     }
-    const bool graph = use_graph && g.opt.graph && g.stream != nullptr;
+    // the perturbation test hook: a per-tile byte array for this call, no graph
+    const uint8_t *perturb = nullptr;
+    if (!g.perturb.empty() && ex->nflags > 0) {
+        std::vector<uint8_t> bits((size_t)ex->nflags, 0);
+        for (auto &pt : g.perturb)
+            if (pt.first >= 0 && pt.first < ex->nflags) bits[(size_t)pt.first] |= pt.second;
+        MD_HIP(hipStreamSynchronize(g.stream));
+        MD_TRY(g.perturb_d.ensure(bits.size()));
+        MD_HIP(hipMemcpy(g.perturb_d.p, bits.data(), bits.size(), hipMemcpyHostToDevice));
+        perturb = (const uint8_t *)g.perturb_d.p;
+    }
+    const bool graph = use_graph && g.opt.graph && g.stream != nullptr && !perturb;
     if (graph) {
         if (!ex->gexec || ex->graph_stream != g.stream) {
             if (ex->gexec) (void)hipGraphExecDestroy(ex->gexec);
@@ -1703,7 +1942,7 @@ int run(const md_job *jobs, int n, bool use_graph) {
         }
         MD_HIP(hipGraphLaunch(ex->gexec, g.stream));
     } else {
-        MD_TRY(enqueue(*ex, g.stream));
+        MD_TRY(enqueue(*ex, g.stream, false, false, perturb));
     }
     if (g.opt.sync) {
         int range_err = 0;
@@ -1998,17 +2237,14 @@ void vol_slab(const VolSE &se, int a, SEData &sd) {
 // Exact-path SE spectrum of a volume SE at cubic length nt and range length n,
 // scaled by nt^-3, cached with the image spectra.
 int get_vspectrum(const VolSE &se, int nt, int n, const NttRange *rt, NttSpec **out) {
-    std::string key = se.key;
+    std::string key = "Q" + se.key;
     key.append((const char *)&nt, sizeof nt);
     key.append((const char *)&n, sizeof n);
-    auto it = g.nspectra.find(key);
-    if (it != g.nspectra.end()) {
-        *out = it->second.get();
-        return MD_OK;
-    }
+    if ((*out = cache_get<NttSpec>(key))) return MD_OK;
     auto sp = std::make_unique<NttSpec>();
     const int k = se.k;
     const size_t nspec = (size_t)n * nt * nt * nt, kkk = (size_t)k * k * k;
+    MD_TRY(cache_reserve(nspec * 8));
     MD_TRY(sp->spec.ensure(nspec * 4));
     MD_TRY(sp->spec_s.ensure(nspec * 4));
     MD_TRY(g.se_work.ensure(((size_t)n * k * k * nt + (size_t)n * k * nt * nt) * 4));
@@ -2023,8 +2259,7 @@ int get_vspectrum(const VolSE &se, int nt, int n, const NttRange *rt, NttSpec **
                                    (uint32_t *)g.se_work.p, (uint32_t *)sp->spec.p, (uint32_t *)sp->spec_s.p,
                                    g.stream));
     MD_HIP(hipStreamSynchronize(g.stream));
-    *out = sp.get();
-    g.nspectra[key] = std::move(sp);
+    *out = cache_put(key, std::move(sp));
     return MD_OK;
 }
 
@@ -2125,6 +2360,7 @@ int vol_plan(int D, int H, int W, int L, const VolSE &se, VolPlan &p) {
 int vol_run(int op, const int32_t *vol, int D, int H, int W, int L, const uint8_t *mask, const int32_t *off, int k,
             int32_t *out) {
     MD_TRY(init());
+    ++g.call_id;
     if (!vol || !out) return fail(MD_ERR_ARG, "null volume or output pointer");
     if ((const void *)vol == (const void *)out) return fail(MD_ERR_ARG, "output must not alias the input");
     if (!mask || !off) return fail(MD_ERR_ARG, "null SE array");
@@ -2352,6 +2588,101 @@ int md_morph(int op, const int32_t *img, int H, int W, int L, const uint8_t *se_
     return morph(op, img, H, W, L, se_mask, se_offsets, k, out);
 }
 
+int md_set_workspace(void *dev_ptr, size_t bytes) {
+    if ((dev_ptr == nullptr) != (bytes == 0)) return fail(MD_ERR_ARG, "workspace pointer and size must both be set or both be 0");
+    if (dev_ptr && ((uintptr_t)dev_ptr & 255u)) return fail(MD_ERR_ARG, "workspace must be 256-byte aligned");
+    if (g.inited) {
+        // executors hold pointers into the previous workspace, and their
+        // graphs may still run on it
+        MD_HIP(hipDeviceSynchronize());
+        g.execs.clear(), g.last_exec = nullptr;
+    }
+    g.ws_ptr = dev_ptr;
+    g.ws_bytes = bytes;
+    g_err.clear();
+    return MD_OK;
+}
+
+size_t md_workspace_size(const md_job *jobs, int n) {
+    g_err.clear();
+    if (n < 1 || !jobs) return fail(MD_ERR_ARG, "empty batch"), 0;
+    if (init() != MD_OK) return 0;
+    ++g.call_id;
+    if (g.opt.path == 0 && g.opt.autotune && !g.tuned && !g.tuning && autotune() != MD_OK) return 0;
+    std::vector<SEData> ses(n);
+    for (int i = 0; i < n; ++i) {
+        if (check_job(jobs[i]) != MD_OK) return 0;
+        make_se(jobs[i].se_mask, jobs[i].se_offsets, jobs[i].k, jobs[i].op, ses[i]);
+    }
+    Exec ex;
+    if (build_exec(jobs, n, ses, ex, true) != MD_OK) return 0;
+    return ex.ws_need;
+}
+
+int md_memory_usage(size_t *cache_bytes, size_t *plan_bytes, int *plans) {
+    if (!cache_bytes || !plan_bytes || !plans) return fail(MD_ERR_ARG, "null pointer");
+    *cache_bytes = g.cache_bytes;
+    size_t t = 0;
+    for (auto &kv : g.execs) t += kv.second->ws_own.bytes;
+    *plan_bytes = t;
+    *plans = (int)g.execs.size();
+    return MD_OK;
+}
+
+int md_plan(const md_job *job, int batch, md_plan_info *out) {
+    if (!job || !out) return fail(MD_ERR_ARG, "null pointer");
+    MD_TRY(check_job(*job));
+    SEData se;
+    make_se(job->se_mask, job->se_offsets, job->k, job->op, se);
+    Plan p;
+    MD_TRY(plan_job(*job, se, p, batch == 0));
+    memset(out, 0, sizeof *out);
+    out->path = p.path;
+    out->precision = p.dbl;
+    out->cost_fft_ns = p.cost_fft;
+    out->cost_direct_ns = p.cost_dir;
+    out->fp32_bound = NAN;
+    if (p.path == kPathFFT) {
+        out->n_t = p.nt;
+        out->T = p.T;
+        out->n_r = p.nr;
+        out->bins = p.bins;
+        out->tiles_x = p.tiles_x;
+        out->tiles_y = p.tiles_y;
+        out->decode_fft = p.dec_fft ? 1 : 0;
+        out->n_t64 = p.nt64;
+        out->fp32_bound = fp32_error_bound(p.nt, p.nr, se.ncells);
+    }
+    g_err.clear();
+    return MD_OK;
+}
+
+int md_debug_perturb_tiles(const long long *tiles, const uint8_t *bits, int n) {
+    if (n < 0 || (n > 0 && (!tiles || !bits))) return fail(MD_ERR_ARG, "null tile list");
+    g.perturb.clear();
+    for (int i = 0; i < n; ++i) {
+        if (tiles[i] < 0) return fail(MD_ERR_ARG, "negative tile index");
+        g.perturb.push_back({tiles[i], bits[i]});
+    }
+    g_err.clear();
+    return MD_OK;
+}
+
+int md_debug_tile_flags(uint32_t *dst, long long cap, long long *n) {
+    if (!n || (cap > 0 && !dst)) return fail(MD_ERR_ARG, "null pointer");
+    *n = 0;
+    if (!g.inited || !g.last_exec) return MD_OK;
+    Exec &ex = *g.last_exec;
+    *n = ex.nflags;
+    const long long c = std::min(cap, ex.nflags);
+    if (c > 0) {
+        MD_HIP(hipStreamSynchronize(g.stream));
+        MD_HIP(hipMemcpy(dst, ex.flags, (size_t)c * sizeof(uint32_t), hipMemcpyDeviceToHost));
+    }
+    g_err.clear();
+    return MD_OK;
+}
+
 int md_set_stream(void *hip_stream) {
     g.stream = (hipStream_t)hip_stream;
     return MD_OK;
@@ -2397,6 +2728,10 @@ int md_set_option(int key, double v) {
             if (!(v >= 1)) return fail(MD_ERR_ARG, "band buffer budget must be >= 1 MiB");
             o.stream_mb = v;
             break;
+        case MD_OPT_CACHE_MB:
+            if (!(v >= 1)) return fail(MD_ERR_ARG, "cache bound must be >= 1 MiB");
+            o.cache_mb = v;
+            break;
         default: return fail(MD_ERR_ARG, "unknown option %d", key);
     }
     g_err.clear();
@@ -2418,6 +2753,7 @@ double md_get_option(int key) {
         case MD_OPT_AUTOTUNE: return o.autotune;
         case MD_OPT_STREAM_ROWS: return o.stream_rows;
         case MD_OPT_STREAM_MB: return o.stream_mb;
+        case MD_OPT_CACHE_MB: return o.cache_mb;
         default: return NAN;
     }
 }
@@ -2446,6 +2782,7 @@ int md_profile_get(md_stage_time *out, int max, int *n) {
             t.launches = kv.second.launches;
             t.alg_bytes = kv.second.bytes;
             t.alg_ops = kv.second.ops;
+            t.units = kv.second.units;
         }
         ++q;
     }
@@ -2482,9 +2819,8 @@ int md_release(void) {
     if (!g.inited) return MD_OK;
     (void)hipDeviceSynchronize();
     g.execs.clear(), g.last_exec = nullptr;
-    g.spectra.clear();
-    g.dirse.clear();
-    g.ranges.clear();
+    g.cache.clear();
+    g.cache_bytes = 0;
     g.se_work.release();
     g.se_in.release();
     g.morph_a.release();
@@ -2514,8 +2850,6 @@ int md_release(void) {
     if (g.ntw) (void)hipFree(g.ntw);
     if (g.ntws) (void)hipFree(g.ntws);
     g.ntw = g.ntws = nullptr;
-    g.nranges.clear();
-    g.nspectra.clear();
     if (g.st_d) (void)hipFree(g.st_d);
     if (g.st_h) (void)hipHostFree(g.st_h);
     g.tw64 = nullptr;
@@ -2530,6 +2864,7 @@ int md_release(void) {
 int md_debug_tile_values(const int32_t *img, int H, int W, int L, const uint8_t *se_mask, const int32_t *se_offsets,
                          int k, int n_t, int n_r, int precision, int ty, int tx, double *dst) {
     MD_TRY(init());
+    ++g.call_id;
     if (!dst) return fail(MD_ERR_ARG, "null destination");
     const Options saved = g.opt;
     g.opt.path = kPathFFT;

@@ -21,13 +21,15 @@ def test_options_roundtrip_and_errors():
         assert md.get_option("tile") == 64
         assert md.get_option("nr") == 40
         assert md.get_option("precision") == 1
-    with md.options(precision=2):
+    with md.options(precision=2, cache_mb=512):
         assert md.get_option("precision") == 2
+        assert md.get_option("cache_mb") == 512
+    assert md.get_option("cache_mb") == 16384
     assert md.get_option("band") == pytest.approx(0.25)
     assert md.get_option("path") == 0
     assert math.isnan(md.get_option(99))
     for key, bad in (("band", 0.7), ("band", -1), ("path", 3), ("tile", 48), ("precision", 3),
-                     ("nr", 4097), ("nr", 2.5), ("workspace_mb", 0), (99, 1)):
+                     ("nr", 4097), ("nr", 2.5), ("workspace_mb", 0), ("cache_mb", 0.5), (99, 1)):
         with pytest.raises(md.MDError) as ei:
             md.set_option(key, bad)
         assert ei.value.code == -1
@@ -46,3 +48,15 @@ def test_cost_model_shape():
     assert sorted(cm["fft64_item"]) == [16, 32, 64, 128, 256, 512, 1024]
     assert all(v > 0 for v in cm["fft32_item"].values())
     assert cm["direct16_per_px_cell"] > 0 and cm["direct32_per_px_cell"] > 0 and cm["direct_per_staged_word"] > 0
+
+
+def test_workspace_argument_checks():
+    """md_set_workspace rejects a pointer without a size (and the reverse) and
+    unaligned pointers, without touching a device."""
+    import ctypes
+
+    lib = md.load()
+    assert lib.md_set_workspace(None, 4096) == -1
+    assert lib.md_set_workspace(ctypes.c_void_p(4096), 0) == -1
+    assert lib.md_set_workspace(ctypes.c_void_p(4096 + 8), 4096) == -1
+    assert lib.md_set_workspace(None, 0) == 0
