@@ -66,10 +66,15 @@ struct Options {
     double cache_mb = 16384.0;
 };
 
-// Device buffer that only grows.
+// Device buffer that only grows; freed when it is destroyed (a cache entry
+// or executor going away releases its device memory).
 struct DevBuf {
     void *p = nullptr;
     size_t bytes = 0;
+    DevBuf() = default;
+    DevBuf(const DevBuf &) = delete;
+    DevBuf &operator=(const DevBuf &) = delete;
+    ~DevBuf() { release(); }
     int ensure(size_t n) {
         if (n <= bytes) return MD_OK;
         if (p) (void)hipFree(p);
