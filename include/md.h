@@ -271,6 +271,28 @@ typedef struct {
  * `jobs` is a host array read during the call only. */
 int md_dilate_batch(const md_job *jobs, int n);
 
+/* Dilation for callers that cannot allocate device memory: code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc.  Same
+ * arguments, layout, result and host-side errors as md_dilate, computed by
+ * the direct max-plus window of Eq. (6new) (the exact integer path md_dilate
+ * takes for small SEs), with k <= 127 (MD_ERR_UNSUPPORTED beyond).
+ *   - Allocates nothing: no hipMalloc, hipFree or allocating library call.
+ *     Its device memory beyond `img` and `out` -- job and segment
+ *     descriptors, the range-error word and the SE tables of the window --
+ *     is a fixed 1 MiB array in the library's device code, which every GPU
+ *     the library runs on holds until the process ends.  An SE whose tables
+ *     would not fit it fails with MD_ERR_ARG (cannot happen for k <= 127).
+ *   - Every call on a GPU shares that GPU's array and rewrites it, so calls
+ *     that overlap on one GPU (several host threads, or streams without
+ *     ordering between them) race; serialise them.
+ *   - Runs on the stream of md_set_stream and always waits for its work
+ *     (MD_OPT_SYNC does not apply): the SE tables are uploaded from host
+ *     memory of the call.  Reports MD_ERR_RANGE for an image value outside
+ *     [0, L-1].  Options, caches, plans and md_set_workspace do not apply;
+ *     md_get_stats afterwards reports one direct-path job. */
+int md_dilate_noalloc(const int32_t *img, int H, int W, int L, const uint8_t *se_mask,
+                      const int32_t *se_offsets, int k, int32_t *out);
+
 /* Caller-owned workspace for the transform path, for callers that own all
  * device scratch memory themselves.  `dev_ptr` is a DEVICE buffer of
  * `bytes` bytes, 256-byte aligned, that holds what a batch needs beyond its

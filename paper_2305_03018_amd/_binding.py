@@ -68,7 +68,7 @@ def load():
         raise MDError(-4, f"{_LIB_PATH} is not built (run __graft_entry__.build())")
     lib = ctypes.CDLL(_LIB_PATH)
     vp, i, u8 = ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p
-    for name in ("md_dilate", "md_erode"):
+    for name in ("md_dilate", "md_erode", "md_dilate_noalloc"):
         f = getattr(lib, name)
         f.argtypes = [vp, i, i, i, u8, vp, i, vp]
         f.restype = i
@@ -196,6 +196,12 @@ def _run_single(fname, img, mask, off, L, out):
 def dilate(img, mask, off, L: int, out=None):
     """Exact dilation: max over the SE of img(x-y) + b(y), 0 on empty windows."""
     return _run_single("md_dilate", img, mask, off, L, out)
+
+
+def dilate_noalloc(img, mask, off, L: int, out=None):
+    """md_dilate_noalloc: the same dilation through the direct window with no
+    device allocation in the library (k <= 127)."""
+    return _run_single("md_dilate_noalloc", img, mask, off, L, out)
 
 
 def erode(img, mask, off, L: int, out=None):

@@ -823,62 +823,77 @@ uint32_t f16_bits(int v) {
     return (uint32_t)(e + 15) << 10 | frac;
 }
 
-// Correlation-order offsets for the direct window (the effective SE
-// reflected), as int32 and as packed 16-bit pairs (int16 and f16), plus each
-// row's span of active cells.
-int get_dirse(const SEData &se, DirSE **out) {
-    const std::string key = "D" + se.key;
-    if ((*out = cache_get<DirSE>(key))) return MD_OK;
-    auto d = std::make_unique<DirSE>();
+// Host images of the direct window's SE tables: correlation-order offsets
+// (the effective SE reflected) as int32 and as packed 16-bit pairs (int16
+// and f16), each row's span of active cells, the column steps of the packed
+// form, and the 2-D prefix counts of the mask.
+struct DirTables {
+    int kpad = 0;
+    std::vector<int32_t> h, h16, hh, rows, steps, cnt;
+};
+
+void dir_tables(const SEData &se, DirTables &t) {
     const int k = se.k;
-    d->kpad = (k + kDirRX - 1) / kDirRX * kDirRX;
+    t.kpad = (k + kDirRX - 1) / kDirRX * kDirRX;
     // 16 words of padding after the last row: the direct kernel prefetches
     // past the end of a row's active span; the packed form also reads one
     // whole row past the SE (SE row k, all minus infinity) ahead of use
-    std::vector<int32_t> h((size_t)k * d->kpad + 16, kNeg), h16((size_t)(k + 1) * d->kpad + 16), rows((size_t)2 * k);
+    t.h.assign((size_t)k * t.kpad + 16, kNeg);
     const uint32_t neg16 = 0xC000C000u;   // -16384 in both lanes
     const uint32_t negh = 0xFC00FC00u;    // f16 minus infinity in both lanes
-    for (size_t q = 0; q < h16.size(); ++q) h16[q] = (int32_t)neg16;
-    std::vector<int32_t> hh(h16.size(), (int32_t)negh);
+    t.h16.assign((size_t)(k + 1) * t.kpad + 16, (int32_t)neg16);
+    t.hh.assign(t.h16.size(), (int32_t)negh);
+    t.rows.assign((size_t)2 * k, 0);
     for (int i = 0; i < k; ++i) {
         int lo = k, hi = -1;
         for (int j = 0; j < k; ++j) {
             const size_t src = (size_t)(k - 1 - i) * k + (k - 1 - j);
             if (!se.mask[src]) continue;
             const int32_t b = se.off[src];
-            h[(size_t)i * d->kpad + j] = b;
-            h16[(size_t)i * d->kpad + j] = (int32_t)(((uint32_t)b & 0xffffu) * 0x10001u);
+            t.h[(size_t)i * t.kpad + j] = b;
+            t.h16[(size_t)i * t.kpad + j] = (int32_t)(((uint32_t)b & 0xffffu) * 0x10001u);
             // offsets above 2048 never reach the f16 form (direct_form)
-            if (b <= 2048) hh[(size_t)i * d->kpad + j] = (int32_t)(f16_bits(b) * 0x10001u);
+            if (b <= 2048) t.hh[(size_t)i * t.kpad + j] = (int32_t)(f16_bits(b) * 0x10001u);
             lo = std::min(lo, j);
             hi = std::max(hi, j);
         }
-        rows[2 * i] = lo;
-        rows[2 * i + 1] = hi;
+        t.rows[2 * i] = lo;
+        t.rows[2 * i + 1] = hi;
     }
-    const std::vector<int32_t> steps = dir_steps(se);
-    d->nsteps = (int)steps.size() / 4;
+    t.steps = dir_steps(se);
     // prefix counts of the mask
-    std::vector<int32_t> cnt((size_t)(k + 1) * (k + 1), 0);
+    t.cnt.assign((size_t)(k + 1) * (k + 1), 0);
     for (int i = 0; i < k; ++i)
         for (int j = 0; j < k; ++j)
-            cnt[(size_t)(i + 1) * (k + 1) + j + 1] = cnt[(size_t)i * (k + 1) + j + 1] +
-                                                     cnt[(size_t)(i + 1) * (k + 1) + j] -
-                                                     cnt[(size_t)i * (k + 1) + j] + (se.mask[(size_t)i * k + j] ? 1 : 0);
-    MD_TRY(cache_reserve((h.size() + h16.size() + hh.size() + rows.size() + steps.size() + cnt.size()) * 4));
-    MD_TRY(d->sek.ensure(h.size() * sizeof(int32_t)));
-    MD_TRY(d->sek16.ensure(h16.size() * sizeof(int32_t)));
-    MD_TRY(d->sekh.ensure(hh.size() * sizeof(int32_t)));
-    MD_TRY(d->rows.ensure(rows.size() * sizeof(int32_t)));
-    MD_TRY(d->steps.ensure(std::max<size_t>(1, steps.size()) * sizeof(int32_t)));
-    if (!steps.empty())
-        MD_HIP(hipMemcpy(d->steps.p, steps.data(), steps.size() * sizeof(int32_t), hipMemcpyHostToDevice));
-    MD_HIP(hipMemcpy(d->sek.p, h.data(), h.size() * sizeof(int32_t), hipMemcpyHostToDevice));
-    MD_HIP(hipMemcpy(d->sek16.p, h16.data(), h16.size() * sizeof(int32_t), hipMemcpyHostToDevice));
-    MD_HIP(hipMemcpy(d->sekh.p, hh.data(), hh.size() * sizeof(int32_t), hipMemcpyHostToDevice));
-    MD_HIP(hipMemcpy(d->rows.p, rows.data(), rows.size() * sizeof(int32_t), hipMemcpyHostToDevice));
-    MD_TRY(d->cnt.ensure(cnt.size() * sizeof(int32_t)));
-    MD_HIP(hipMemcpy(d->cnt.p, cnt.data(), cnt.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+            t.cnt[(size_t)(i + 1) * (k + 1) + j + 1] = t.cnt[(size_t)i * (k + 1) + j + 1] +
+                                                       t.cnt[(size_t)(i + 1) * (k + 1) + j] -
+                                                       t.cnt[(size_t)i * (k + 1) + j] +
+                                                       (se.mask[(size_t)i * k + j] ? 1 : 0);
+}
+
+// The direct window's SE tables on the device (cached per effective SE).
+int get_dirse(const SEData &se, DirSE **out) {
+    const std::string key = "D" + se.key;
+    if ((*out = cache_get<DirSE>(key))) return MD_OK;
+    auto d = std::make_unique<DirSE>();
+    DirTables t;
+    dir_tables(se, t);
+    d->kpad = t.kpad;
+    d->nsteps = (int)t.steps.size() / 4;
+    MD_TRY(cache_reserve((t.h.size() + t.h16.size() + t.hh.size() + t.rows.size() + t.steps.size() + t.cnt.size()) * 4));
+    MD_TRY(d->sek.ensure(t.h.size() * sizeof(int32_t)));
+    MD_TRY(d->sek16.ensure(t.h16.size() * sizeof(int32_t)));
+    MD_TRY(d->sekh.ensure(t.hh.size() * sizeof(int32_t)));
+    MD_TRY(d->rows.ensure(t.rows.size() * sizeof(int32_t)));
+    MD_TRY(d->steps.ensure(std::max<size_t>(1, t.steps.size()) * sizeof(int32_t)));
+    if (!t.steps.empty())
+        MD_HIP(hipMemcpy(d->steps.p, t.steps.data(), t.steps.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+    MD_HIP(hipMemcpy(d->sek.p, t.h.data(), t.h.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+    MD_HIP(hipMemcpy(d->sek16.p, t.h16.data(), t.h16.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+    MD_HIP(hipMemcpy(d->sekh.p, t.hh.data(), t.hh.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+    MD_HIP(hipMemcpy(d->rows.p, t.rows.data(), t.rows.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+    MD_TRY(d->cnt.ensure(t.cnt.size() * sizeof(int32_t)));
+    MD_HIP(hipMemcpy(d->cnt.p, t.cnt.data(), t.cnt.size() * sizeof(int32_t), hipMemcpyHostToDevice));
     *out = cache_put(key, std::move(d));
     return MD_OK;
 }
@@ -1958,6 +1973,122 @@ int run(const md_job *jobs, int n, bool use_graph) {
     return MD_OK;
 }
 
+// ---------------------------------------------------------------------------
+// allocation-free dilation (md_dilate_noalloc)
+// ---------------------------------------------------------------------------
+// Device memory of md_dilate_noalloc: the job and segment descriptors, the
+// statistics word and the SE tables of the direct window live in this array.
+// Each device holds its own copy until the process ends; host code reaches it
+// only through the address hipGetSymbolAddress returns on that device.
+constexpr size_t kNoAllocBytes = 1u << 20;
+constexpr int kNoAllocDevices = 64;
+static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+void *noalloc_base[kNoAllocDevices] = {};
+
+// This device's address of `scratch`, looked up once per device.
+int noalloc_scratch(int dev, unsigned char **out) {
+    if (dev < 0 || dev >= kNoAllocDevices)
+        return fail(MD_ERR_UNSUPPORTED, "md_dilate_noalloc supports devices 0..%d, not %d", kNoAllocDevices - 1, dev);
+    if (!noalloc_base[dev]) {
+        void *p = nullptr;
+        MD_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (!p) return fail(MD_ERR_DEVICE, "hipGetSymbolAddress returned a null address for the scratch array");
+        noalloc_base[dev] = p;
+    }
+    *out = (unsigned char *)noalloc_base[dev];
+    return MD_OK;
+}
+
+// Dilation by the direct max-plus window (Eq. (6new)) with every device
+// buffer beyond the image and output taken from `scratch`: no allocation,
+// no cache, no plan kept.  Synchronous: the tables are uploaded from host
+// memory that lives on this call's stack, so it waits for its work.
+int noalloc_dilate(const int32_t *img, int H, int W, int L, const uint8_t *mask, const int32_t *off, int k,
+                   int32_t *out) {
+    const md_job j{img, H, W, L, mask, off, k, out, 0};
+    MD_TRY(check_job(j));
+    if (k > kMaxDirectK)
+        return fail(MD_ERR_UNSUPPORTED, "md_dilate_noalloc runs the direct window, k <= %d (k=%d)", kMaxDirectK, k);
+    SEData se;
+    make_se(mask, off, k, 0, se);
+    DirTables t;
+    dir_tables(se, t);
+    const int pack = direct_form((long long)(L - 1) + se.maxoff);
+    const int sel = !pack && direct_lds_bytes(k, t.kpad, 0, 1) <= kLdsBytes ? 1 : 0;
+    const size_t lds = direct_lds_bytes(k, t.kpad, pack, sel);
+    if (lds > kLdsBytes) return fail(MD_ERR_UNSUPPORTED, "direct window for k=%d exceeds the LDS", k);
+    const std::vector<int32_t> &packed = pack == 2 ? t.hh : t.h16;
+    // scratch layout, 256-byte aligned regions
+    size_t at = 0;
+    auto region = [&](size_t bytes) {
+        const size_t o = at;
+        at += (bytes + 255) / 256 * 256;
+        return o;
+    };
+    const size_t o_job = region(sizeof(JobDev)), o_seg = region(sizeof(Seg)), o_st = region(sizeof(StatsDev));
+    const size_t o_sek = region(t.h.size() * 4), o_pk = region(packed.size() * 4), o_rows = region(t.rows.size() * 4);
+    const size_t o_steps = region(std::max<size_t>(1, t.steps.size()) * 4);
+    if (at > kNoAllocBytes)
+        return fail(MD_ERR_ARG, "md_dilate_noalloc needs %zu bytes of scratch for k=%d, the maximum is %zu", at, k,
+                    kNoAllocBytes);
+    int dev = 0;
+    MD_HIP(hipGetDevice(&dev));
+    unsigned char *base = nullptr;
+    MD_TRY(noalloc_scratch(dev, &base));
+    int cu = 0;
+    MD_HIP(hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, dev));
+    JobDev d;
+    memset(&d, 0, sizeof d);
+    d.img = img;
+    d.out = out;
+    d.H = H;
+    d.W = W;
+    d.L = L;
+    d.k = k;
+    d.op = 0;
+    d.path = kPathDirect;
+    d.D = 1;
+    d.kpad = t.kpad;
+    d.dir_pack = pack;
+    d.sek = (const int32_t *)(base + o_sek);
+    d.sek16 = (const int32_t *)(base + o_pk);
+    d.sek_rows = (const int32_t *)(base + o_rows);
+    d.sek_steps = (const int32_t *)(base + o_steps);
+    d.dir_nsteps = (int)t.steps.size() / 4;
+    d.dir_bx = (W + kDirBW - 1) / kDirBW;
+    d.dir_by = (H + direct_block_rows(pack) - 1) / direct_block_rows(pack);
+    Seg sg;
+    memset(&sg, 0, sizeof sg);
+    sg.job = 0;
+    const long long nitems = (long long)d.dir_bx * d.dir_by;
+    const int per_cu = std::max(1, std::min(2048 / kDirThreads, (int)(kLdsBytes / lds)));
+    const int grid = (int)std::max<long long>(1, std::min<long long>(nitems, (long long)std::max(cu, 1) * per_cu));
+    const hipStream_t s = g.stream;
+    StatsDev *st = (StatsDev *)(base + o_st);
+    MD_HIP(hipMemcpyAsync(base + o_job, &d, sizeof d, hipMemcpyHostToDevice, s));
+    MD_HIP(hipMemcpyAsync(base + o_seg, &sg, sizeof sg, hipMemcpyHostToDevice, s));
+    MD_HIP(hipMemcpyAsync(base + o_sek, t.h.data(), t.h.size() * 4, hipMemcpyHostToDevice, s));
+    MD_HIP(hipMemcpyAsync(base + o_pk, packed.data(), packed.size() * 4, hipMemcpyHostToDevice, s));
+    MD_HIP(hipMemcpyAsync(base + o_rows, t.rows.data(), t.rows.size() * 4, hipMemcpyHostToDevice, s));
+    if (!t.steps.empty())
+        MD_HIP(hipMemcpyAsync(base + o_steps, t.steps.data(), t.steps.size() * 4, hipMemcpyHostToDevice, s));
+    // the range-error word starts at zero on every call (a fill kernel, not a
+    // memset node)
+    MD_HIP(launch_zero(st, sizeof(StatsDev), s));
+    MD_HIP(launch_direct(pack, sel, (const JobDev *)(base + o_job), (const Seg *)(base + o_seg), 1, nitems, grid, lds,
+                         st, s));
+    StatsDev sh;
+    MD_HIP(hipMemcpyAsync(&sh, st, sizeof sh, hipMemcpyDeviceToHost, s));
+    MD_HIP(hipStreamSynchronize(s));
+    md_stats &ls = g.last;
+    ls = md_stats{};
+    ls.direct_jobs = 1;
+    ls.path = kPathDirect;
+    ls.precision = g.opt.precision;
+    if (sh.range_err) return fail(MD_ERR_RANGE, "image value outside [0, L-1] (L=%d)", L);
+    return MD_OK;
+}
+
 // One dilation (op 0) or erosion (op 1) of an image whose values lie in
 // [0, L-1], through the same planner and kernels as md_dilate.
 int single(int op, const int32_t *img, int H, int W, int L, const uint8_t *mask, const int32_t *off, int k,
@@ -2543,6 +2674,12 @@ int md_dilate(const int32_t *img, int H, int W, int L, const uint8_t *se_mask, c
               int32_t *out) {
     md_job j{img, H, W, L, se_mask, se_offsets, k, out, 0};
     return run(&j, 1, false);
+}
+
+int md_dilate_noalloc(const int32_t *img, int H, int W, int L, const uint8_t *se_mask, const int32_t *se_offsets,
+                      int k, int32_t *out) {
+    g_err.clear();
+    return noalloc_dilate(img, H, W, L, se_mask, se_offsets, k, out);
 }
 
 int md_erode(const int32_t *img, int H, int W, int L, const uint8_t *se_mask, const int32_t *se_offsets, int k,
