@@ -946,7 +946,7 @@ __device__ __forceinline__ void reg_dft20(C (&v)[20]) {
 }
 
 // Range-axis FFT decode: Step 3 for a range length nr = 2M with M = 2^a
-// (64 to 2048) or, in FP32, M = 3 2^a (96 to 768) or 5 2^a (80 to 320).
+// (32 to 2048) or, in FP32, M = 3 2^a (48 to 768) or 5 2^a (40 to 320).
 // A pixel's coefficient vector is the real inverse DFT of its Hermitian
 // spectrum, of which the bins X_0 .. X_M are kept:
 //   c_d = scale * sum_{m < nr} X_m w^(d m),  w = exp(2 pi i / nr),  X_{nr-m} = conj(X_m).
@@ -967,7 +967,7 @@ __device__ __forceinline__ void reg_dft20(C (&v)[20]) {
 //      for k = g + r G, packs Z_k and needs no turn (S = 1);
 //   2. one or two more passes (M = 2^a: radix G up to 256, else radix 16
 //      then M / 256; M = 3 2^a: radix min(G, 8), then G / 8; M = 5 2^a:
-//      radix 4, then G / 4), through LDS rows of P points with one row of
+//      radix min(G, 4), then G / 4), through LDS rows of P points with one row of
 //      padding after every E, so that the strided writes of the first pass
 //      fall in distinct banks;
 //   3. the last pass leaves each thread's points z_n in registers in
@@ -985,9 +985,9 @@ __global__ __launch_bounds__(kDecThreads) void k_decode_fft(const JobDev *__rest
     using C = typename Cx<R>::T;
     constexpr bool POW2 = (M & (M - 1)) == 0;
     constexpr int E = POW2 ? 16 : M % 3 == 0 ? 24 : 20, Q1 = E, G = M / E, P = kDecThreads / G;
-    constexpr int Q2 = POW2 ? (M >= 256 ? 16 : G) : E == 24 ? (G < 8 ? G : 8) : 4, Q3 = M / (Q1 * Q2);
+    constexpr int Q2 = POW2 ? (M >= 256 ? 16 : G) : E == 24 ? (G < 8 ? G : 8) : (G < 4 ? G : 4), Q3 = M / (Q1 * Q2);
     constexpr int B2 = E / Q2, B3 = E / Q3, W = Q1 + 1;
-    static_assert(G * P == kDecThreads && (P & (P - 1)) == 0 && Q1 * Q2 * Q3 == M && E % Q2 == 0 &&
+    static_assert(G >= 2 && G * P == kDecThreads && (P & (P - 1)) == 0 && Q1 * Q2 * Q3 == M && E % Q2 == 0 &&
                       E % Q3 == 0 && (POW2 || sizeof(R) == 4),
                   "pass plan");
     __shared__ C zs[(M + M / Q1) * P];   // point n of pixel p at (n + n / E) P + p
@@ -1553,19 +1553,23 @@ hipError_t launch_decode(int var, int dbl, const JobDev *jobs, const Seg *segs, 
     k_decode_fft<R, M><<<grid, kDecThreads, 0, s>>>(jobs, segs, nseg, nitems, band, tile_flags, fb_list, win_list, \
                                                      st); break
         switch ((dbl ? 100000 : 0) + decode_fft_m(var)) {
+            case 32: MD_DFFT(float, 32);
             case 64: MD_DFFT(float, 64);
             case 128: MD_DFFT(float, 128);
             case 256: MD_DFFT(float, 256);
             case 512: MD_DFFT(float, 512);
             case 1024: MD_DFFT(float, 1024);
             case 2048: MD_DFFT(float, 2048);
+            case 48: MD_DFFT(float, 48);
             case 96: MD_DFFT(float, 96);
             case 192: MD_DFFT(float, 192);
             case 384: MD_DFFT(float, 384);
             case 768: MD_DFFT(float, 768);
+            case 40: MD_DFFT(float, 40);
             case 80: MD_DFFT(float, 80);
             case 160: MD_DFFT(float, 160);
             case 320: MD_DFFT(float, 320);
+            case 100032: MD_DFFT(double, 32);
             case 100064: MD_DFFT(double, 64);
             case 100128: MD_DFFT(double, 128);
             case 100256: MD_DFFT(double, 256);

@@ -188,20 +188,20 @@ hipError_t launch_fft(int nt, int dbl, const JobDev *jobs, const Seg *segs, int 
 // decode kernel variant for a job's kept-bin count, and the zero-padded pitch
 // (both dimensions) of the [bin][degree] decode table for a range length
 int decode_group_variant(int bins, int dbl);
-// Range-axis FFT decode: for nr = 2M with M = 2^a (nr 128..4096, both
-// precisions), M = 3 2^a (nr 192..1536, FP32) or M = 5 2^a (nr 160..640,
+// Range-axis FFT decode: for nr = 2M with M = 2^a (nr 64..4096, both
+// precisions), M = 3 2^a (nr 96..1536, FP32) or M = 5 2^a (nr 80..640,
 // FP32).  Its decode variant is kDecFftVar + log2 M, kDecFftVar + 16 +
 // log2(M / 3) or kDecFftVar + 32 + log2(M / 5), and one work item covers
 // decode_fft_pixels(nr) pixels of a tile (256 E / M for E points per thread:
 // 16, 24 or 20).
 constexpr int kDecFftVar = 16;
-constexpr int kDecFftMinNr = 128, kDecFftMaxNr = 4096;
+constexpr int kDecFftMinNr = 64, kDecFftMaxNr = 4096;
 constexpr bool is_pow2c(int x) { return x > 0 && (x & (x - 1)) == 0; }
 constexpr int ilog2c(int x) { return x <= 1 ? 0 : 1 + ilog2c(x / 2); }
 constexpr bool decode_uses_fft(int nr, int dbl) {
     return (nr >= kDecFftMinNr && nr <= kDecFftMaxNr && is_pow2c(nr)) ||
-           (dbl == 0 && nr >= 192 && nr <= 1536 && nr % 3 == 0 && is_pow2c(nr / 3)) ||
-           (dbl == 0 && nr >= 160 && nr <= 640 && nr % 5 == 0 && is_pow2c(nr / 5));
+           (dbl == 0 && nr >= 96 && nr <= 1536 && nr % 3 == 0 && is_pow2c(nr / 3)) ||
+           (dbl == 0 && nr >= 80 && nr <= 640 && nr % 5 == 0 && is_pow2c(nr / 5));
 }
 constexpr int decode_fft_var(int nr) {
     return is_pow2c(nr) ? kDecFftVar + ilog2c(nr / 2)

@@ -259,8 +259,8 @@ def test_direct_packed_forms(dev):
 
 
 def test_range_fft_decode(dev):
-    """Power-of-two range lengths from 128 to 4096, and in FP32 the lengths
-    3 2^a from 192 to 1536 and 5 2^a from 160 to 640, decode by a range-axis FFT (even and odd
+    """Power-of-two range lengths from 64 to 4096, and in FP32 the lengths
+    3 2^a from 96 to 1536 and 5 2^a from 80 to 640, decode by a range-axis FFT (even and odd
     coefficients from one complex inverse transform of half length) instead
     of the dense inverse DFT.  Forced lengths in both
     precisions, erosion, several tiles with ragged edges, and the exact
@@ -268,6 +268,7 @@ def test_range_fft_decode(dev):
     rng = np.random.default_rng(41)
     cases = [
         # H, W, L, k, p, max_off, op, nr
+        (133, 171, 48, 9, 0.7, 12, 1, 64),
         (150, 203, 100, 7, 0.7, 27, 0, 128),
         (97, 181, 200, 9, 0.6, 50, 1, 256),
         (130, 140, 256, 15, 0.5, 255, 0, 512),
@@ -276,11 +277,14 @@ def test_range_fft_decode(dev):
         (60, 70, 4000, 3, 1.0, 90, 0, 4096),
         # 3 2^a lengths (the FP32 FFT decode; FP64 decodes them, and the 5 2^a
         # lengths below, densely)
+        (141, 99, 70, 11, 0.6, 20, 0, 96),
         (120, 170, 150, 9, 0.6, 40, 0, 192),
         (100, 150, 300, 11, 0.7, 80, 1, 384),
         (64, 200, 600, 5, 0.9, 160, 0, 768),
         (50, 80, 1200, 3, 1.0, 300, 1, 1536),
         # 5 2^a lengths (FP32 FFT decode)
+        (157, 203, 64, 21, 0.6, 16, 0, 80),
+        (88, 131, 50, 41, 0.8, 12, 1, 80),
         (110, 160, 120, 7, 0.6, 35, 1, 160),
         (90, 140, 250, 9, 0.7, 60, 0, 320),
         (60, 150, 500, 5, 0.9, 130, 1, 640),

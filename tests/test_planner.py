@@ -58,9 +58,9 @@ def test_range_length_holds_every_degree():
             assert p["n_r"] >= top + 1
             assert p["bins"] == p["n_r"] // 2 + 1
             n = p["n_r"]
-            fft_len = (n >= 128 and n & (n - 1) == 0) or (
-                p["precision"] == 0 and ((n % 3 == 0 and 192 <= n <= 1536 and (n // 3) & (n // 3 - 1) == 0) or
-                                         (n % 5 == 0 and 160 <= n <= 640 and (n // 5) & (n // 5 - 1) == 0)))
+            fft_len = (n >= 64 and n & (n - 1) == 0) or (
+                p["precision"] == 0 and ((n % 3 == 0 and 96 <= n <= 1536 and (n // 3) & (n // 3 - 1) == 0) or
+                                         (n % 5 == 0 and 80 <= n <= 640 and (n // 5) & (n // 5 - 1) == 0)))
             assert p["decode_fft"] == (1 if fft_len and n <= 4096 else 0), p
 
 
