@@ -134,7 +134,7 @@ def kernel_of(stage):
     if stage.startswith("fft"):
         prec, n = ("float" if stage.startswith("fft32") else "double"), int(stage.split("_n")[1])
         big = n > (128 if prec == "float" else 64)
-        return f"k_fft{'_big' if big else ''}<{prec}, {n}>"
+        return f"k_fft_big<{prec}, {n}>" if big else f"k_fft_reg<{prec}, {n}>"
     if stage == "decode_ntt":
         return "k_ntt_decode"
     if stage.startswith("ntt"):

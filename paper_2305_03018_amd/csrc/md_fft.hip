@@ -37,6 +37,8 @@
 #include <math.h>
 
 #include <algorithm>
+#include <type_traits>
+#include <utility>
 
 namespace md {
 namespace {
@@ -392,10 +394,11 @@ __device__ __forceinline__ void fft_tile_bin(typename Cx<R>::T *lds, const int32
     __syncthreads();
     dit_axis<R, N, 0, BS, false>(lds, tw);
     dit_axis<R, N, 1, BS, false>(lds, tw);
+    // the spectrum is stored [kx][ky]: q walks ky fastest, down an LDS column
     batched<BS, CH>(
         N * N, [&](int q) { return ldg(spec_m, q); },
         [&](int q, C sv) {
-            C *e = lds + (q >> LG) * P + (q & (N - 1));
+            C *e = lds + (q & (N - 1)) * P + (q >> LG);
             *e = cmul(*e, sv);
         });
     __syncthreads();
@@ -476,10 +479,11 @@ __device__ __forceinline__ void fft_big_tile_bin(typename Cx<R>::T *lds, typenam
             [&](int q, C v) { lds[(q & (LB - 1)) * P + (q >> LLB)] = v; });
         __syncthreads();
         dit_axis<R, N, 0, BS, false, LB>(lds, tw);
+        // the spectrum is stored [kx][ky]: q walks ky fastest
         batched<BS, CH>(
-            LB * N, [&](int q) { return ldg(spec_m, (size_t)(q >> LLB) * N + cb + (q & (LB - 1))); },
+            LB * N, [&](int q) { return ldg(spec_m, (size_t)(cb + (q >> LG)) * N + (q & (N - 1))); },
             [&](int q, C sv) {
-                C *e = lds + (q & (LB - 1)) * P + (q >> LLB);
+                C *e = lds + (q >> LG) * P + (q & (N - 1));
                 *e = cmul(*e, sv);
             });
         __syncthreads();
@@ -533,15 +537,383 @@ __device__ __forceinline__ R perturb_bump(const uint8_t *perturb, const JobDev &
     return (R)(0.4 * (double)J.nt * J.nt * J.nr);
 }
 
-template <typename R, int N, int BS>
-__global__ __launch_bounds__(BS) void k_fft(const JobDev *__restrict__ jobs, const Seg *__restrict__ segs,
-                                            int nseg, long long nitems, const TwF *__restrict__ tw32,
-                                            const double2 *__restrict__ tw64, StatsDev *st,
-                                            const uint8_t *__restrict__ perturb) {
+// ---------------------------------------------------------------------------
+// Spatial transform with register-resident lines (tiles of 16..128 points)
+// ---------------------------------------------------------------------------
+// One (tile, bin) work item per block of 4 N threads.  Every line of the
+// N x N tile (a column, or a row) is held by the G = 4 lanes 16 apart in a
+// wavefront, E = N / 4 points each: lane part g holds the points g + 4 e.  A
+// line transform of length N = E G (Cooley-Tukey over n = g + G e,
+// k = k1 + E k2) is
+//   * an E-point DFT of each lane's points in registers,
+//   * the turn w_N^(g k1) of its output k1 (a per-lane twiddle kept in
+//     registers for the whole kernel),
+//   * a 4-point DFT across the lanes of the line for every k1, as two
+//     radix-2 stages whose operands are exchanged by the permlane swaps
+//     (lanes 32 apart, then lanes 16 apart) with the turn -i between them.
+// Lane g then holds the outputs k = k1 + E k2 for k1 in its chunk
+// [g E/4, (g+1) E/4) and all four k2.  The inverse transform runs the same
+// steps mirrored with conjugate twiddles and ends with the lane holding the
+// points g + 4 e again.  The tile crosses the LDS twice:
+//   1. columns: each lane encodes its points straight from the image (Step 1;
+//      the lanes of a row of 16 walk 16 image columns), transforms along y and
+//      stores its outputs;
+//   2. rows: each lane loads its points of a row, transforms along x,
+//      multiplies by the SE spectrum (stored transposed, [kx][ky], so that
+//      lanes holding consecutive rows read consecutive words), transforms
+//      back along x and stores them where it loaded them;
+//   3. columns: each lane loads what it stored in 1, transforms back along
+//      y and writes its valid outputs (rows and columns >= k - 1, the
+//      overlap-save rule); waves whose 16 columns all lie left of the
+//      overlap skip this phase.
+// The LDS array has row pitch N + 1, so that the 16 lanes of a row of
+// lanes touch 16 distinct bank pairs in both orientations.
+
+// cos and sin of 2 pi j / n in double at compile time (Taylor series on an
+// argument reduced to [0, pi / 2])
+constexpr double kPiD = 3.14159265358979323846264338327950288;
+constexpr double taylor_cos(double x) {
+    double t = 1.0, s = 1.0;
+    for (int q = 1; q < 20; ++q) {
+        t *= -x * x / ((2.0 * q - 1.0) * (2.0 * q));
+        s += t;
+    }
+    return s;
+}
+constexpr double taylor_sin(double x) {
+    double t = x, s = x;
+    for (int q = 1; q < 20; ++q) {
+        t *= -x * x / ((2.0 * q) * (2.0 * q + 1.0));
+        s += t;
+    }
+    return s;
+}
+constexpr double cos2pi(int j, int n) {
+    j = ((j % n) + n) % n;
+    if (2 * j > n) j = n - j;                       // cos is even
+    const double x = 2.0 * kPiD * j / n;            // [0, pi]
+    return 2 * x > kPiD ? -taylor_cos(kPiD - x) : taylor_cos(x);
+}
+constexpr double sin2pi(int j, int n) {
+    j = ((j % n) + n) % n;
+    if (2 * j > n) return -sin2pi(n - j, n);        // sin is odd
+    const double x = 2.0 * kPiD * j / n;            // [0, pi]
+    return taylor_sin(2 * x > kPiD ? kPiD - x : x);
+}
+
+template <int V> using ic = std::integral_constant<int, V>;
+template <typename F, int... I>
+__device__ __forceinline__ void unroll_seq(F &&f, std::integer_sequence<int, I...>) {
+    (f(ic<I>{}), ...);
+}
+// f(ic<0>), ..., f(ic<N-1>) with compile-time indices
+template <int N, typename F>
+__device__ __forceinline__ void unroll_c(F &&f) {
+    unroll_seq(f, std::make_integer_sequence<int, N>{});
+}
+
+// x * exp(-+2 pi i J / NN) with a compile-time twiddle: free for multiples of
+// a quarter turn, the eighth turns (+-1 +-i) c take a sum and a scaling, the
+// others a full product.  In FP32 the constant is split into hi + lo floats
+// (the lo products first), as the table twiddles are.
+template <typename R, int J, int NN, bool INV, typename C>
+__device__ __forceinline__ C twc(C x) {
+    constexpr int j = ((J % NN) + NN) % NN;
+    if constexpr (j == 0) return x;
+    else if constexpr (4 * j == NN) {   // -i (forward), +i (inverse)
+        C r;
+        if (INV) { r.x = -x.y; r.y = x.x; } else { r.x = x.y; r.y = -x.x; }
+        return r;
+    } else if constexpr (2 * j == NN) {
+        C r;
+        r.x = -x.x;
+        r.y = -x.y;
+        return r;
+    } else if constexpr (4 * j == 3 * NN) {
+        C r;
+        if (INV) { r.x = x.y; r.y = -x.x; } else { r.x = -x.y; r.y = x.x; }
+        return r;
+    } else {
+        constexpr double wc = cos2pi(j, NN), ws0 = -sin2pi(j, NN);
+        constexpr double ws = INV ? -ws0 : ws0;
+        C r;
+        if constexpr (8 * j == NN || 8 * j == 3 * NN || 8 * j == 5 * NN || 8 * j == 7 * NN) {
+            // w = c (sx + i sy), sx, sy = +-1
+            constexpr double c = wc < 0 ? -wc : wc;
+            constexpr R sx = wc < 0 ? R(-1) : R(1), sy = ws < 0 ? R(-1) : R(1);
+            const R t1 = sx * x.x - sy * x.y, t2 = sx * x.y + sy * x.x;
+            if constexpr (sizeof(R) == 4) {
+                constexpr float ch = (float)c, cl = (float)(c - (double)ch);
+                r.x = fmaf(t1, ch, t1 * cl);
+                r.y = fmaf(t2, ch, t2 * cl);
+            } else {
+                r.x = t1 * c;
+                r.y = t2 * c;
+            }
+        } else if constexpr (sizeof(R) == 4) {
+            constexpr float hx = (float)wc, hy = (float)ws;
+            constexpr float lx = (float)(wc - (double)hx), ly = (float)(ws - (double)hy);
+            const float sxx = fmaf(x.x, lx, -x.y * ly), syy = fmaf(x.x, ly, x.y * lx);
+            r.x = fmaf(x.x, hx, fmaf(-x.y, hy, sxx));
+            r.y = fmaf(x.x, hy, fmaf(x.y, hx, syy));
+        } else {
+            r.x = fma(x.x, wc, -x.y * ws);
+            r.y = fma(x.x, ws, x.y * wc);
+        }
+        return r;
+    }
+}
+
+// In-register DFT of E points, natural order in and out:
+// y_s = sum_r v_r exp(-+2 pi i r s / E).  Radix-2 decimation in time after a
+// bit reversal that full unrolling turns into register renaming.
+template <typename R, int E, bool INV, typename C>
+__device__ __forceinline__ void reg_fft(C (&v)[E]) {
+    constexpr int LE = ilog2c(E);
+    unroll_c<E>([&](auto i) {
+        constexpr int I = decltype(i)::value, J = brevc(I, LE);
+        if constexpr (I < J) {
+            const C t = v[I];
+            v[I] = v[J];
+            v[J] = t;
+        }
+    });
+    unroll_c<LE>([&](auto st) {
+        constexpr int H = 1 << decltype(st)::value;
+        unroll_c<E / 2>([&](auto b) {
+            constexpr int B = decltype(b)::value, T = B % H, I = (B / H) * 2 * H + T;
+            const C y = twc<R, T, 2 * H, INV>(v[I + H]);
+            const C x = v[I];
+            v[I] = cadd(x, y);
+            v[I + H] = csub(x, y);
+        });
+    });
+}
+
+// Per-lane twiddle w_N^(g k1) kept in registers: FP32 as split hi + lo
+// floats, FP64 as one double pair.
+template <typename R> struct LaneTw;
+template <> struct LaneTw<float> {
+    float hx, hy, lx, ly;
+    __device__ __forceinline__ void load(const TwF *tw, int idx) {
+        const TwF w = tw[idx];
+        hx = w.hi.x; hy = w.hi.y; lx = w.lo.x; ly = w.lo.y;
+    }
+    template <bool INV>
+    __device__ __forceinline__ float2 mul(float2 a) const {
+        const float y_h = INV ? -hy : hy, y_l = INV ? -ly : ly;
+        const float sx = fmaf(a.x, lx, -a.y * y_l), sy = fmaf(a.x, y_l, a.y * lx);
+        float2 r;
+        r.x = fmaf(a.x, hx, fmaf(-a.y, y_h, sx));
+        r.y = fmaf(a.x, y_h, fmaf(a.y, hx, sy));
+        return r;
+    }
+};
+template <> struct LaneTw<double> {
+    double x, y;
+    __device__ __forceinline__ void load(const double2 *tw, int idx) {
+        const double2 w = tw[idx];
+        x = w.x; y = w.y;
+    }
+    template <bool INV>
+    __device__ __forceinline__ double2 mul(double2 a) const {
+        const double wy = INV ? -y : y;
+        double2 r;
+        r.x = fma(a.x, x, -a.y * wy);
+        r.y = fma(a.x, wy, a.y * x);
+        return r;
+    }
+};
+
+// The lane twiddles w_N^(g k1), k1 < E, of a line transform: held in
+// registers (RegTw), or read from a per-block LDS table of w_N^j, j < N
+// (LdsTw: for the largest FP32 tile, whose registers are taken by its 32
+// points per lane and the transform's constants).
+template <typename R, int E> struct RegTw {
+    LaneTw<R> w[E];
+    template <typename TWT>
+    __device__ __forceinline__ void init(const TWT *tw, int g, int stride) {
+        unroll_c<E>([&](auto q) {
+            constexpr int K1 = decltype(q)::value;
+            w[K1].load(tw, (g * K1 * stride) & (kTwN - 1));
+        });
+    }
+    template <bool INV, int K1, typename C>
+    __device__ __forceinline__ C mul(ic<K1>, C x) const { return w[K1].template mul<INV>(x); }
+};
+template <typename R, int N> struct LdsTw {
+    using TWT = typename std::conditional<sizeof(R) == 4, TwF, double2>::type;
+    const __attribute__((address_space(3))) TWT *t;   // LDS, N entries
+    int g;
+    int z = 0;   // an opaque zero per transform (see fresh())
+    // A new opaque zero added to the table index: the compiler can then
+    // neither hoist the table reads out of the item loop nor share them
+    // between the four transforms of an item, which would keep the whole
+    // table live in the registers this form exists to save.
+    __device__ __forceinline__ void fresh() {
+        int q;
+        asm volatile("v_mov_b32 %0, 0" : "=v"(q));
+        z = q;
+    }
+    template <bool INV, int K1, typename C>
+    __device__ __forceinline__ C mul(ic<K1>, C x) const {
+        const int i = ((g * K1) & (N - 1)) + z;
+        LaneTw<R> lw;
+        if constexpr (sizeof(R) == 4) {
+            typedef float f32x4 __attribute__((ext_vector_type(4)));
+            const f32x4 w = ((const __attribute__((address_space(3))) f32x4 *)t)[i];
+            lw.hx = w.x; lw.hy = w.y; lw.lx = w.z; lw.ly = w.w;
+        } else {
+            const f64x2 w = ((const __attribute__((address_space(3))) f64x2 *)t)[i];
+            lw.x = w.x; lw.y = w.y;
+        }
+        return lw.template mul<INV>(x);
+    }
+};
+template <typename T> __device__ __forceinline__ void tw_fresh(T &) {}
+template <typename R, int N> __device__ __forceinline__ void tw_fresh(LdsTw<R, N> &t) { t.fresh(); }
+
+// Exchange across lanes XOR apart (32 or 16) for a radix-2 stage: the lane
+// with the lower partner bit ends with (its a, the partner's a), the other
+// with (the partner's b, its b).
+template <int XOR>
+__device__ __forceinline__ void lane_swap32(uint32_t &a, uint32_t &b) {
+    if constexpr (XOR == 32) {
+        const auto r = __builtin_amdgcn_permlane32_swap(a, b, false, false);
+        a = r[0];
+        b = r[1];
+    } else {
+        const auto r = __builtin_amdgcn_permlane16_swap(a, b, false, false);
+        a = r[0];
+        b = r[1];
+    }
+}
+template <int XOR>
+__device__ __forceinline__ void lane_swap(float2 &a, float2 &b) {
+    uint32_t ax = __float_as_uint(a.x), ay = __float_as_uint(a.y), bx = __float_as_uint(b.x), by = __float_as_uint(b.y);
+    lane_swap32<XOR>(ax, bx);
+    lane_swap32<XOR>(ay, by);
+    a.x = __uint_as_float(ax); a.y = __uint_as_float(ay); b.x = __uint_as_float(bx); b.y = __uint_as_float(by);
+}
+template <int XOR>
+__device__ __forceinline__ void lane_swap(double2 &a, double2 &b) {
+    uint64_t A[2] = {(uint64_t)__double_as_longlong(a.x), (uint64_t)__double_as_longlong(a.y)};
+    uint64_t B[2] = {(uint64_t)__double_as_longlong(b.x), (uint64_t)__double_as_longlong(b.y)};
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+        uint32_t alo = (uint32_t)A[q], ahi = (uint32_t)(A[q] >> 32), blo = (uint32_t)B[q], bhi = (uint32_t)(B[q] >> 32);
+        lane_swap32<XOR>(alo, blo);
+        lane_swap32<XOR>(ahi, bhi);
+        A[q] = (uint64_t)ahi << 32 | alo;
+        B[q] = (uint64_t)bhi << 32 | blo;
+    }
+    a.x = __longlong_as_double((long long)A[0]); a.y = __longlong_as_double((long long)A[1]);
+    b.x = __longlong_as_double((long long)B[0]); b.y = __longlong_as_double((long long)B[1]);
+}
+
+// Line geometry of the register-resident transform: E points per lane, the
+// frequency held in register s by lane part g after a forward transform.
+template <int E>
+__device__ __forceinline__ constexpr int line_freq_c(int s) {
+    // s = j + (E/4) k2b + (E/2) k2a  ->  k = j + E (k2a + 2 k2b) (+ g E / 4)
+    return (s % (E / 4)) + E * ((s / (E / 2)) + 2 * ((s / (E / 4)) % 2));
+}
+
+// Forward transform of one line held as v[e] = x[g + 4 e] (g: the lane's
+// part, lanes 16 apart); afterwards v[s] = X[line_freq_c<E>(s) + g E / 4].
+template <typename R, int E, typename C, typename TWS>
+__device__ __forceinline__ void line_fwd(C (&v)[E], const TWS &ltw, bool g0) {
+    reg_fft<R, E, false>(v);
+    unroll_c<E - 1>([&](auto q) {
+        constexpr int K1 = decltype(q)::value + 1;
+        v[K1] = ltw.template mul<false>(ic<K1>{}, v[K1]);
+    });
+    // stage over lane-part bit 1 (lanes 32 apart)
+    unroll_c<E / 2>([&](auto q) {
+        constexpr int J = decltype(q)::value;
+        lane_swap<32>(v[J], v[J + E / 2]);
+        const C a = v[J], b = v[J + E / 2];
+        v[J] = cadd(a, b);
+        v[J + E / 2] = csub(a, b);
+    });
+    // turn -i of k2a = 1 on lane parts with bit 0 set
+    unroll_c<E / 2>([&](auto q) {
+        constexpr int S = decltype(q)::value + E / 2;
+        const C x = v[S];
+        v[S].x = g0 ? x.y : x.x;
+        v[S].y = g0 ? -x.x : x.y;
+    });
+    // stage over lane-part bit 0 (lanes 16 apart)
+    unroll_c<E / 2>([&](auto q) {
+        constexpr int Q = decltype(q)::value, J = Q % (E / 4) + (Q / (E / 4)) * (E / 2);
+        lane_swap<16>(v[J], v[J + E / 4]);
+        const C a = v[J], b = v[J + E / 4];
+        v[J] = cadd(a, b);
+        v[J + E / 4] = csub(a, b);
+    });
+}
+
+// Inverse (unnormalised) of line_fwd: takes v[s] = X[line_freq_c<E>(s) + g E / 4],
+// leaves v[e] = N x[g + 4 e] with x the inverse DFT of X.
+template <typename R, int E, typename C, typename TWS>
+__device__ __forceinline__ void line_inv(C (&v)[E], const TWS &ltw, bool g0) {
+    unroll_c<E / 2>([&](auto q) {
+        constexpr int Q = decltype(q)::value, J = Q % (E / 4) + (Q / (E / 4)) * (E / 2);
+        const C a = v[J], b = v[J + E / 4];
+        v[J] = cadd(a, b);
+        v[J + E / 4] = csub(a, b);
+        lane_swap<16>(v[J], v[J + E / 4]);
+    });
+    unroll_c<E / 2>([&](auto q) {
+        constexpr int S = decltype(q)::value + E / 2;
+        const C x = v[S];
+        v[S].x = g0 ? -x.y : x.x;
+        v[S].y = g0 ? x.x : x.y;
+    });
+    unroll_c<E / 2>([&](auto q) {
+        constexpr int J = decltype(q)::value;
+        const C a = v[J], b = v[J + E / 2];
+        v[J] = cadd(a, b);
+        v[J + E / 2] = csub(a, b);
+        lane_swap<32>(v[J], v[J + E / 2]);
+    });
+    unroll_c<E - 1>([&](auto q) {
+        constexpr int K1 = decltype(q)::value + 1;
+        v[K1] = ltw.template mul<true>(ic<K1>{}, v[K1]);
+    });
+    reg_fft<R, E, true>(v);
+}
+
+template <typename R, int N>
+__global__ __launch_bounds__(4 * N) void k_fft_reg(const JobDev *__restrict__ jobs, const Seg *__restrict__ segs,
+                                                   int nseg, long long nitems, const TwF *__restrict__ tw32,
+                                                   const double2 *__restrict__ tw64, StatsDev *st,
+                                                   const uint8_t *__restrict__ perturb) {
     using C = typename Cx<R>::T;
-    __shared__ C lds[N * (N + 1)];
-    typename TwSel<R>::T tw;
-    if constexpr (sizeof(R) == 4) tw.p = tw32; else tw.p = tw64;
+    constexpr int E = N / 4, P = N + 1;
+    static_assert(E >= 4 && (E & (E - 1)) == 0, "E = N / 4 must be a power of two >= 4");
+    using TWT = typename std::conditional<sizeof(R) == 4, TwF, double2>::type;
+    constexpr bool TW_LDS = sizeof(R) == 4 && N >= 128;
+    __shared__ C lds[N * P];
+    __shared__ TWT tws[TW_LDS ? N : 1];
+    const int lane = threadIdx.x & 63, g = lane >> 4;
+    const bool g0 = (g & 1) != 0;
+    const int line = (threadIdx.x >> 6) * 16 + (lane & 15);   // column (phases 1, 3) or row (phase 2)
+    const int lbase = (threadIdx.x >> 6) * 16;                 // first line of this wave
+    const TWT *twg;
+    if constexpr (sizeof(R) == 4) twg = tw32; else twg = tw64;
+    // w_N^(g k1), k1 < E
+    typename std::conditional<TW_LDS, LdsTw<R, N>, RegTw<R, E>>::type ltw;
+    if constexpr (TW_LDS) {
+        for (int j = threadIdx.x; j < N; j += 4 * N) tws[j] = twg[j * (kTwN / N)];
+        ltw.t = (const __attribute__((address_space(3))) TWT *)tws;
+        ltw.g = g;
+        __syncthreads();
+    } else {
+        ltw.init(twg, g, kTwN / N);
+    }
+    // LDS row of register s in phases 1 and 3: the frequency it holds
+    const int frow = g * (E / 4);
     for (long long it = blockIdx.x; it < nitems; it += gridDim.x) {
         const Seg S = segs[find_seg(segs, nseg, it)];
         const JobDev &J = jobs[S.job];
@@ -549,11 +921,94 @@ __global__ __launch_bounds__(BS) void k_fft(const JobDev *__restrict__ jobs, con
         const int m = (int)(local / S.ntiles), tl = (int)(local % S.ntiles);
         const int tile = S.tile0 + tl;
         const int ty = tile / J.tiles_x, tx = tile - ty * J.tiles_x;
+        const int k = J.k, r = (k - 1) >> 1, T = N - k + 1;
+        const int iy0 = ty * J.T - r, ix0 = tx * J.T - r;
+        const C *enc_m = (const C *)J.enc + (size_t)m * J.L;
+        const C *spec_m = (const C *)J.se_spec + (size_t)m * N * N;
         C *ydst = (C *)S.y + (size_t)tl * ytile_elems(J.bins, J.T, J.ybs) + ybin_offset(m, J.T, J.ybs);
-        fft_tile_bin<R, N, BS>(lds, J.img, J.H, J.W, J.L, J.op, J.k, ty * J.T, tx * J.T,
-                               (const C *)J.enc + (size_t)m * J.L, (const C *)J.se_spec + (size_t)m * N * N,
-                               ydst, J.ybs, tw, m == 0 ? &st->range_err : nullptr,
-                               perturb_bump<R>(perturb, J, tile, m, kPerturbFirst));
+        // 1. columns: encode (Step 1) and forward transform along y
+        C v[E];
+        {
+            const auto im = gld(J.img);
+            const int gx = ix0 + line, H = J.H, W = J.W, L = J.L, op = J.op;
+            const bool colin = (unsigned)gx < (unsigned)W;
+            int val[E];
+            bool in[E];
+            unroll_c<E>([&](auto q) {
+                constexpr int Q = decltype(q)::value;
+                const int gy = iy0 + g + 4 * Q;
+                in[Q] = colin && (unsigned)gy < (unsigned)H;
+                val[Q] = im[in[Q] ? (size_t)gy * W + gx : 0];
+            });
+            int bad = 0;
+            unroll_c<E>([&](auto q) {
+                constexpr int Q = decltype(q)::value;
+                bad |= (int)(in[Q] && (unsigned)val[Q] >= (unsigned)L);
+                int w = min(max(val[Q], 0), L - 1);
+                w = op ? L - 1 - w : w;
+                v[Q] = in[Q] ? ldg(enc_m, w) : czero<C>();
+            });
+            if (m == 0 && __any(bad) && lane == 0) atomicOr(&st->range_err, 1u);
+        }
+        tw_fresh(ltw);
+        line_fwd<R, E>(v, ltw, g0);
+        unroll_c<E>([&](auto q) {
+            constexpr int Q = decltype(q)::value;
+            lds[(frow + line_freq_c<E>(Q)) * P + line] = v[Q];
+        });
+        __syncthreads();
+        // 2. rows: forward along x, times the SE spectrum, inverse along x
+        unroll_c<E>([&](auto q) {
+            constexpr int Q = decltype(q)::value;
+            v[Q] = lds[line * P + g + 4 * Q];
+        });
+        tw_fresh(ltw);
+        line_fwd<R, E>(v, ltw, g0);
+        // spectrum loads in groups of up to 8 (register pressure)
+        constexpr int SG = E < 8 ? E : 8;
+        unroll_c<E / SG>([&](auto cg) {
+            constexpr int Q0 = SG * decltype(cg)::value;
+            C sv[SG];
+            unroll_c<SG>([&](auto q) {
+                constexpr int Q = Q0 + decltype(q)::value;
+                sv[Q - Q0] = ldg(spec_m, (size_t)(frow + line_freq_c<E>(Q)) * N + line);
+            });
+            unroll_c<SG>([&](auto q) {
+                constexpr int Q = Q0 + decltype(q)::value;
+                v[Q] = cmul(v[Q], sv[Q - Q0]);
+            });
+        });
+        tw_fresh(ltw);
+        line_inv<R, E>(v, ltw, g0);
+        unroll_c<E>([&](auto q) {
+            constexpr int Q = decltype(q)::value;
+            lds[line * P + g + 4 * Q] = v[Q];
+        });
+        __syncthreads();
+        // 3. columns: inverse along y and the valid outputs (rows and columns
+        // >= k - 1); waves whose columns all lie left of them skip it
+        if (lbase + 15 >= k - 1) {
+            unroll_c<E>([&](auto q) {
+                constexpr int Q = decltype(q)::value;
+                v[Q] = lds[(frow + line_freq_c<E>(Q)) * P + line];
+            });
+            tw_fresh(ltw);
+            line_inv<R, E>(v, ltw, g0);
+            const R bump = perturb_bump<R>(perturb, J, tile, m, kPerturbFirst);
+            const int oc = line - (k - 1);
+            if (oc >= 0) {
+                unroll_c<E>([&](auto q) {
+                    constexpr int Q = decltype(q)::value;
+                    const int orow = g + 4 * Q - (k - 1);
+                    if (orow >= 0) {
+                        C o = v[Q];
+                        o.x += bump;
+                        stg(ydst, ypix((size_t)orow * T + oc, J.ybs), o);
+                    }
+                });
+            }
+        }
+        __syncthreads();
     }
 }
 
@@ -1385,7 +1840,7 @@ __global__ void k_se_cols(const double2 *__restrict__ G, int k, int nt, const do
             ax += g.x * t.x - g.y * t.y;
             ay += g.x * t.y + g.y * t.x;
         }
-        const size_t o = ((size_t)m * nt + u) * nt + v;
+        const size_t o = ((size_t)m * nt + v) * nt + u;   // [m][kx][ky]
         if (spec64) spec64[o] = make_double2(ax, ay);
         if (spec32) spec32[o] = make_float2((float)ax, (float)ay);
     }
@@ -1433,11 +1888,9 @@ __global__ void k_or_flag(uint32_t *dst, const uint32_t *src) {
 // ---------------------------------------------------------------------------
 int fft_block_threads(int nt, int dbl) {
     if (nt > (dbl ? kMaxLdsN64 : kMaxLdsN32)) return nt <= kMaxN ? kBigThreads : 0;
+    // k_fft_reg: four lanes per line of the tile
     switch (nt) {
-        case 16: return 64;
-        case 32: return 128;
-        case 64: return 256;
-        case 128: return 1024;
+        case 16: case 32: case 64: case 128: return 4 * nt;
         default: return 0;
     }
 }
@@ -1511,17 +1964,17 @@ hipError_t launch_fft(int nt, int dbl, const JobDev *jobs, const Seg *segs, int 
                       int grid, const TwF *tw32, const double2 *tw64, void *slabs, StatsDev *st,
                       const uint8_t *perturb, hipStream_t s) {
     if (nitems <= 0) return hipSuccess;
-#define MD_FFT_CASE(R, N, BS) \
-    k_fft<R, N, BS><<<grid, BS, 0, s>>>(jobs, segs, nseg, nitems, tw32, tw64, st, perturb); break;
+#define MD_FFT_CASE(R, N) \
+    k_fft_reg<R, N><<<grid, 4 * N, 0, s>>>(jobs, segs, nseg, nitems, tw32, tw64, st, perturb); break;
 #define MD_FFT_BIG(R, N) \
     k_fft_big<R, N, kBigThreads><<<grid, kBigThreads, 0, s>>>(jobs, segs, nseg, nitems, tw32, tw64, slabs, st, \
                                                               perturb); break;
     if (!dbl) {
         switch (nt) {
-            case 16: MD_FFT_CASE(float, 16, 64)
-            case 32: MD_FFT_CASE(float, 32, 128)
-            case 64: MD_FFT_CASE(float, 64, 256)
-            case 128: MD_FFT_CASE(float, 128, 1024)
+            case 16: MD_FFT_CASE(float, 16)
+            case 32: MD_FFT_CASE(float, 32)
+            case 64: MD_FFT_CASE(float, 64)
+            case 128: MD_FFT_CASE(float, 128)
             case 256: MD_FFT_BIG(float, 256)
             case 512: MD_FFT_BIG(float, 512)
             case 1024: MD_FFT_BIG(float, 1024)
@@ -1529,9 +1982,9 @@ hipError_t launch_fft(int nt, int dbl, const JobDev *jobs, const Seg *segs, int 
         }
     } else {
         switch (nt) {
-            case 16: MD_FFT_CASE(double, 16, 64)
-            case 32: MD_FFT_CASE(double, 32, 128)
-            case 64: MD_FFT_CASE(double, 64, 256)
+            case 16: MD_FFT_CASE(double, 16)
+            case 32: MD_FFT_CASE(double, 32)
+            case 64: MD_FFT_CASE(double, 64)
             case 128: MD_FFT_BIG(double, 128)
             case 256: MD_FFT_BIG(double, 256)
             case 512: MD_FFT_BIG(double, 512)
