@@ -100,8 +100,9 @@ typedef enum {
                               up, volumes 8, 16 or 32)                           */
     MD_OPT_NR = 4,         /* 0: auto, else the range-axis DFT length; must be at
                               least (L-1) + max offset + 1.  FP paths decode a
-                              length 2^a from 64 to 4096 (and FP32 a length
-                              3 2^a from 96 to 1536 or 5 2^a from 80 to 640)
+                              length 2^a from 8 to 4096, 3 2^a from 12 to 48 or
+                              5 2^a from 10 to 40 (and FP32 also 3 2^a up to
+                              1536 and 5 2^a up to 640)
                               by an FFT along the range axis, any other by a
                               dense DFT; auto weighs the smallest length
                               against the next such lengths once the smallest

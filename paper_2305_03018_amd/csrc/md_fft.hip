@@ -1631,6 +1631,148 @@ __global__ __launch_bounds__(kDecThreads) void k_decode_fft(const JobDev *__rest
     if (threadIdx.x == 0 && rm > 0.f) atomicMax(&st->max_res_bits, __float_as_uint(rm));
 }
 
+// DFT with positive exponent of M = 2^a 3^b 5^c points in registers,
+// natural order in and out: y_s = sum_r v_r exp(+2 pi i r s / M).  Mixed
+// radix, decimation in time on the smallest factor, compile-time twiddles.
+template <typename R, int M, typename C>
+__device__ __forceinline__ void reg_idft(C (&v)[M]) {
+    if constexpr (M == 2) {
+        const C a = v[0], b = v[1];
+        v[0] = cadd(a, b);
+        v[1] = csub(a, b);
+    } else if constexpr (M == 3) {
+        const R h = (R)0.86602540378443864676;   // sin(2 pi / 3)
+        const C a0 = v[0], t = cadd(v[1], v[2]), u = csub(v[1], v[2]);
+        C w;
+        w.x = a0.x - (R)0.5 * t.x;
+        w.y = a0.y - (R)0.5 * t.y;
+        v[0] = cadd(a0, t);
+        v[1].x = w.x - h * u.y;   // w + i sin(2 pi / 3) (a1 - a2)
+        v[1].y = w.y + h * u.x;
+        v[2].x = w.x + h * u.y;
+        v[2].y = w.y - h * u.x;
+    } else if constexpr (M == 5) {
+        const R c1 = (R)cos2pi(1, 5), c2 = (R)cos2pi(2, 5), s1 = (R)sin2pi(1, 5), s2 = (R)sin2pi(2, 5);
+        const C a0 = v[0], t1 = cadd(v[1], v[4]), t2 = cadd(v[2], v[3]);
+        const C d1 = csub(v[1], v[4]), d2 = csub(v[2], v[3]);
+        C b1, b2, e1, e2;
+        b1.x = a0.x + c1 * t1.x + c2 * t2.x;
+        b1.y = a0.y + c1 * t1.y + c2 * t2.y;
+        b2.x = a0.x + c2 * t1.x + c1 * t2.x;
+        b2.y = a0.y + c2 * t1.y + c1 * t2.y;
+        e1.x = s1 * d1.x + s2 * d2.x;
+        e1.y = s1 * d1.y + s2 * d2.y;
+        e2.x = s2 * d1.x - s1 * d2.x;
+        e2.y = s2 * d1.y - s1 * d2.y;
+        v[0] = cadd(a0, cadd(t1, t2));
+        v[1].x = b1.x - e1.y;   // b1 + i e1
+        v[1].y = b1.y + e1.x;
+        v[4].x = b1.x + e1.y;   // b1 - i e1
+        v[4].y = b1.y - e1.x;
+        v[2].x = b2.x - e2.y;   // b2 + i e2
+        v[2].y = b2.y + e2.x;
+        v[3].x = b2.x + e2.y;   // b2 - i e2
+        v[3].y = b2.y - e2.x;
+    } else {
+        constexpr int P = M % 2 == 0 ? 2 : M % 3 == 0 ? 3 : 5, Q = M / P;
+        static_assert(P * Q == M && Q > 1, "M must factor into 2, 3 and 5");
+        C a[P][Q];
+        unroll_c<P>([&](auto r) {
+            constexpr int RR = decltype(r)::value;
+            unroll_c<Q>([&](auto j) {
+                constexpr int JJ = decltype(j)::value;
+                a[RR][JJ] = v[P * JJ + RR];
+            });
+            reg_idft<R, Q>(a[RR]);
+            unroll_c<Q>([&](auto s) {
+                constexpr int SS = decltype(s)::value;
+                a[RR][SS] = twc<R, RR * SS, M, true>(a[RR][SS]);
+            });
+        });
+        unroll_c<Q>([&](auto s) {
+            constexpr int SS = decltype(s)::value;
+            C b[P];
+            unroll_c<P>([&](auto r) { b[decltype(r)::value] = a[decltype(r)::value][SS]; });
+            reg_idft<R, P>(b);
+            unroll_c<P>([&](auto t) { v[SS + Q * decltype(t)::value] = b[decltype(t)::value]; });
+        });
+    }
+}
+
+// Range-axis FFT decode for short range lengths nr = 2M, M = 2^a < 32,
+// 3 2^a < 48 or 5 2^a < 40: one pixel per thread, all of it in registers.
+// The thread loads the pixel's bins X_0 .. X_M (16-pixel blocks, bins
+// contiguous), packs Z_k = (X_k + conj X_{M-k}) + i w^k (X_k - conj X_{M-k}),
+// w = exp(2 pi i / nr), takes the M-point inverse DFT z and reads
+// c_{2n} = scale Re z_n, c_{2n+1} = scale Im z_n (the even and odd samples of
+// the real inverse DFT of the Hermitian spectrum), then Step 3 and the
+// exactness checks as the other decodes.  kDecSmallPix pixels of a tile per
+// work item.
+template <typename R, int M>
+__global__ __launch_bounds__(kDecThreads) void k_decode_small(const JobDev *__restrict__ jobs,
+                                                              const Seg *__restrict__ segs, int nseg,
+                                                              long long nitems, float band,
+                                                              unsigned int *tile_flags, int2 *fb_list,
+                                                              int2 *win_list, StatsDev *st) {
+    using C = typename Cx<R>::T;
+    constexpr int PPT = kDecSmallPix / kDecThreads;   // pixels per thread per item
+    __shared__ float s_red[kDecThreads / 64];
+    float run_max = 0.f;
+    for (long long it = blockIdx.x; it < nitems; it += gridDim.x) {
+        const Seg S = segs[find_seg(segs, nseg, it)];
+        const JobDev &J = jobs[S.job];
+        const int local = (int)(it - S.item0);
+        const int tl = local / S.pblocks, pb = local - tl * S.pblocks;
+        const int tile = S.tile0 + tl;
+        const int T = J.T, TT = T * T;
+        const int ty = tile / J.tiles_x, tx = tile - ty * J.tiles_x;
+        const C *X = (const C *)S.y + (size_t)tl * ytile_elems(J.bins, T, J.ybs);
+        const R scale = (R)J.scale;
+        bool hit = false;
+#pragma unroll 1
+        for (int q = 0; q < PPT; ++q) {
+            const int p = (pb * PPT + q) * kDecThreads + threadIdx.x;
+            const int ly = p / T, lx = p - ly * T;
+            const int gy = ty * T + ly, gx = tx * T + lx;
+            const bool valid = p < TT && gy < J.H && gx < J.W;
+            if (!__any(valid)) continue;
+            const size_t b0 = ypix(valid ? p : 0, J.ybs);
+            C x[M + 1];
+            unroll_c<M + 1>([&](auto m) {
+                constexpr int MM = decltype(m)::value;
+                x[MM] = ldg(X, b0 + 16 * MM);
+            });
+            C z[M];
+            unroll_c<M>([&](auto kk) {
+                constexpr int K = decltype(kk)::value;
+                const C a = x[K], b = x[M - K];
+                C d;
+                d.x = a.x - b.x;
+                d.y = a.y + b.y;
+                const C t = twc<R, K, 2 * M, true>(d);   // w^k (x - conj y)
+                z[K].x = a.x + b.x - t.y;
+                z[K].y = a.y - b.y + t.x;
+            });
+            reg_idft<R, M>(z);
+            PxDecode<R> dd;
+            unroll_c<M>([&](auto n) {
+                constexpr int NN = decltype(n)::value;
+                dd.add(z[NN].x * scale, 2 * NN);
+                dd.add(z[NN].y * scale, 2 * NN + 1);
+            });
+            if (valid) {
+                const int d = dd.top < 0 ? 0 : dd.top;
+                gst(J.out)[(size_t)gy * J.W + gx] = J.op ? (J.L - 1 - d) : d;
+                run_max = fmaxf(run_max, (float)dd.res);
+                hit |= px_ambiguous(dd, band, J, gy, gx);
+            }
+        }
+        if (__any(hit) && (threadIdx.x & 63) == 0) flag_tile(J, S.job, tile, tile_flags, fb_list, win_list, st);
+    }
+    const float rm = block_max(run_max, s_red);
+    if (threadIdx.x == 0 && rm > 0.f) atomicMax(&st->max_res_bits, __float_as_uint(rm));
+}
+
 // Exact recompute of the tiles listed by the decode: FP64 transforms on
 // nt64-sized sub-tiles (LDS-resident up to 64, through this block's slab
 // beyond), each decoded from this block's slot.  The decode applies the
@@ -2005,7 +2147,36 @@ hipError_t launch_decode(int var, int dbl, const JobDev *jobs, const Seg *segs, 
 #define MD_DFFT(R, M) \
     k_decode_fft<R, M><<<grid, kDecThreads, 0, s>>>(jobs, segs, nseg, nitems, band, tile_flags, fb_list, win_list, \
                                                      st); break
-        switch ((dbl ? 100000 : 0) + decode_fft_m(var)) {
+        const int dm = decode_fft_m(var);
+        if (decode_small_m(dm)) {
+#define MD_DSMALL(R, M) \
+    k_decode_small<R, M><<<grid, kDecThreads, 0, s>>>(jobs, segs, nseg, nitems, band, tile_flags, fb_list, win_list, \
+                                                       st); break
+            switch ((dbl ? 100000 : 0) + dm) {
+                case 4: MD_DSMALL(float, 4);
+                case 5: MD_DSMALL(float, 5);
+                case 6: MD_DSMALL(float, 6);
+                case 8: MD_DSMALL(float, 8);
+                case 10: MD_DSMALL(float, 10);
+                case 12: MD_DSMALL(float, 12);
+                case 16: MD_DSMALL(float, 16);
+                case 20: MD_DSMALL(float, 20);
+                case 24: MD_DSMALL(float, 24);
+                case 100004: MD_DSMALL(double, 4);
+                case 100005: MD_DSMALL(double, 5);
+                case 100006: MD_DSMALL(double, 6);
+                case 100008: MD_DSMALL(double, 8);
+                case 100010: MD_DSMALL(double, 10);
+                case 100012: MD_DSMALL(double, 12);
+                case 100016: MD_DSMALL(double, 16);
+                case 100020: MD_DSMALL(double, 20);
+                case 100024: MD_DSMALL(double, 24);
+                default: return hipErrorInvalidValue;
+            }
+#undef MD_DSMALL
+            return hipGetLastError();
+        }
+        switch ((dbl ? 100000 : 0) + dm) {
             case 32: MD_DFFT(float, 32);
             case 64: MD_DFFT(float, 64);
             case 128: MD_DFFT(float, 128);

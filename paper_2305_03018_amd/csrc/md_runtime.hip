@@ -1391,13 +1391,14 @@ int build_exec(const md_job *jobs, int n, const std::vector<SEData> &ses, Exec &
         for (auto &gr : wv.dec) {
             // the range-axis FFT decode holds 256 E complex values (E = 16, 24
             // or 20 points per thread), one row of padding per E rows, and its
-            // M twiddles in LDS (2 M when the second pass is the last)
+            // M twiddles in LDS (2 M when the second pass is the last); the
+            // short-length form keeps everything in registers
             const size_t elem = gr.dbl == kPrecFP64 ? sizeof(double2) : sizeof(float2);
             const size_t dm = gr.big >= kDecFftVar ? (size_t)decode_fft_m(gr.big) : 0;
             const bool p2 = (dm & (dm - 1)) == 0, m3 = dm % 3 == 0;
             const size_t pts = p2 ? 4352 : m3 ? 6400 : 5376;
             const bool last2 = p2 ? dm <= 256 : m3 ? dm <= 192 : dm <= 80;
-            const size_t lds = dm ? (pts + (last2 ? 2 * dm : dm)) * elem : 0;
+            const size_t lds = dm && !decode_small_m((int)dm) ? (pts + (last2 ? 2 * dm : dm)) * elem : 0;
             gr.grid = occupancy_grid(gr.nitems, lds, kDecThreads);
         }
     }

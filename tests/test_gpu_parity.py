@@ -259,8 +259,9 @@ def test_direct_packed_forms(dev):
 
 
 def test_range_fft_decode(dev):
-    """Power-of-two range lengths from 64 to 4096, and in FP32 the lengths
-    3 2^a from 96 to 1536 and 5 2^a from 80 to 640, decode by a range-axis FFT (even and odd
+    """Power-of-two range lengths from 8 to 4096, 3 2^a from 12 to 48 and
+    5 2^a from 10 to 40, and in FP32 the lengths 3 2^a up to 1536 and 5 2^a
+    up to 640, decode by a range-axis FFT (even and odd
     coefficients from one complex inverse transform of half length) instead
     of the dense inverse DFT.  Forced lengths in both
     precisions, erosion, several tiles with ragged edges, and the exact
@@ -268,6 +269,16 @@ def test_range_fft_decode(dev):
     rng = np.random.default_rng(41)
     cases = [
         # H, W, L, k, p, max_off, op, nr
+        # short lengths: one pixel per thread in registers
+        (61, 77, 6, 5, 0.8, 2, 0, 8),
+        (90, 45, 8, 13, 0.6, 2, 1, 10),
+        (33, 140, 9, 7, 0.7, 3, 0, 12),
+        (100, 99, 12, 3, 1.0, 4, 1, 16),
+        (71, 129, 16, 21, 0.5, 4, 0, 20),
+        (130, 64, 18, 9, 0.6, 5, 1, 24),
+        (57, 88, 25, 11, 0.7, 7, 0, 32),
+        (120, 111, 32, 31, 0.6, 8, 1, 40),
+        (66, 95, 40, 15, 0.6, 8, 0, 48),
         (133, 171, 48, 9, 0.7, 12, 1, 64),
         (150, 203, 100, 7, 0.7, 27, 0, 128),
         (97, 181, 200, 9, 0.6, 50, 1, 256),

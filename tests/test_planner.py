@@ -58,9 +58,11 @@ def test_range_length_holds_every_degree():
             assert p["n_r"] >= top + 1
             assert p["bins"] == p["n_r"] // 2 + 1
             n = p["n_r"]
-            fft_len = (n >= 64 and n & (n - 1) == 0) or (
-                p["precision"] == 0 and ((n % 3 == 0 and 96 <= n <= 1536 and (n // 3) & (n // 3 - 1) == 0) or
-                                         (n % 5 == 0 and 80 <= n <= 640 and (n // 5) & (n // 5 - 1) == 0)))
+            pow2 = lambda x: x > 0 and x & (x - 1) == 0
+            fft_len = (n >= 8 and pow2(n)) or (n % 3 == 0 and 12 <= n <= 48 and pow2(n // 3)) or (
+                n % 5 == 0 and 10 <= n <= 40 and pow2(n // 5)) or (
+                p["precision"] == 0 and ((n % 3 == 0 and 96 <= n <= 1536 and pow2(n // 3)) or
+                                         (n % 5 == 0 and 80 <= n <= 640 and pow2(n // 5))))
             assert p["decode_fft"] == (1 if fft_len and n <= 4096 else 0), p
 
 
