@@ -1050,28 +1050,114 @@ __device__ __forceinline__ bool px_ambiguous(const PxDecode<R> &dd, float band, 
     return (float)dd.res >= band || dd.neg || (int)dd.sum != window_cells(J, gy, gx);
 }
 
-template <typename R, int N, int BS>
-__global__ __launch_bounds__(BS) void k_fft_big(const JobDev *__restrict__ jobs, const Seg *__restrict__ segs,
-                                                int nseg, long long nitems, const TwF *__restrict__ tw32,
-                                                const double2 *__restrict__ tw64, void *slabs, StatsDev *st,
-                                                const uint8_t *__restrict__ perturb) {
+// Large tiles (FP32 256..1024 points per side, FP64 128..1024) in three
+// grid-wide passes.  The N x N array of a (tile, bin) item does not fit the
+// LDS, so each pass takes batches of LB = big_lines() lines of one item
+// through the LDS, and the array lives in a per-item intermediate `mid` in
+// global memory between passes.  A launch handles a chunk of `cn` items
+// starting at `it0` (the chunk's intermediates are small enough to stay in
+// the L2 and Infinity Cache between the passes):
+//   PH 0: encode LB image rows (bit-reversed columns), forward DIT along x,
+//         store row i at intermediate row brev(i) (the columns then hold
+//         bit-reversed input for the DIT along y);
+//   PH 1: LB columns: forward DIT along y, times the SE spectrum
+//         ([kx][ky]), inverse DIF along y (row r' then holds output row
+//         brev(r')), stored back;
+//   PH 2: LB rows: inverse DIF along x and the T x T valid outputs.
+// Work units are (item, batch) pairs, item-major, so that consecutive blocks
+// share an item's image rows, intermediate and spectrum.
+template <typename R, int N, int PH>
+__global__ __launch_bounds__(kBigThreads) void k_fft_big(const JobDev *__restrict__ jobs, const Seg *__restrict__ segs,
+                                                         int nseg, long long it0, int cn, const TwF *__restrict__ tw32,
+                                                         const double2 *__restrict__ tw64, void *mid, StatsDev *st,
+                                                         const uint8_t *__restrict__ perturb) {
     using C = typename Cx<R>::T;
-    __shared__ C lds[big_lines<R, N>() * (N + 1)];
+    constexpr int BS = kBigThreads, LB = big_lines<R, N>(), NB = N / LB;
+    constexpr int P = N + 1, LG = ilog2c(N), LLB = ilog2c(LB);
+    constexpr int CHM = sizeof(R) == 4 ? 4 : 16;
+    constexpr int CH = LB * N / BS < CHM ? LB * N / BS : CHM;
+    __shared__ C lds[LB * P];
     typename TwSel<R>::T tw;
     if constexpr (sizeof(R) == 4) tw.p = tw32; else tw.p = tw64;
-    C *slab = (C *)slabs + (size_t)blockIdx.x * N * N;
-    for (long long it = blockIdx.x; it < nitems; it += gridDim.x) {
+    const long long units = (long long)cn * NB;
+    for (long long u = blockIdx.x; u < units; u += gridDim.x) {
+        const int i = (int)(u / NB), b = (int)(u - (long long)i * NB);
+        const long long it = it0 + i;
         const Seg S = segs[find_seg(segs, nseg, it)];
         const JobDev &J = jobs[S.job];
         const long long local = it - S.item0;
         const int m = (int)(local / S.ntiles), tl = (int)(local % S.ntiles);
         const int tile = S.tile0 + tl;
         const int ty = tile / J.tiles_x, tx = tile - ty * J.tiles_x;
-        C *ydst = (C *)S.y + (size_t)tl * ytile_elems(J.bins, J.T, J.ybs) + ybin_offset(m, J.T, J.ybs);
-        fft_big_tile_bin<R, N, BS>(lds, slab, J.img, J.H, J.W, J.L, J.op, J.k, ty * J.T, tx * J.T,
-                                   (const C *)J.enc + (size_t)m * J.L, (const C *)J.se_spec + (size_t)m * N * N, ydst,
-                                   J.ybs, tw, m == 0 ? &st->range_err : nullptr,
-                                   perturb_bump<R>(perturb, J, tile, m, kPerturbFirst));
+        const int k = J.k, r = (k - 1) >> 1, T = N - k + 1;
+        C *slab = (C *)mid + (size_t)i * N * N;
+        if constexpr (PH == 0) {
+            const int rb = b * LB;
+            const C *enc_m = (const C *)J.enc + (size_t)m * J.L;
+            const int bad = encode_rows<R, N, BS, CH, kEncLdsOrder<R, N>>(
+                LB, J.img, J.H, J.W, J.L, J.op, ty * J.T - r + rb, tx * J.T - r, enc_m,
+                [&](int l, int c, C v) { lds[l * P + (kEncLdsOrder<R, N> ? c : brev<LG>(c))] = v; });
+            if (m == 0 && bad) atomicOr(&st->range_err, 1u);
+            __syncthreads();
+            dit_axis<R, N, 0, BS, false, LB>(lds, tw);
+            for (int q = threadIdx.x; q < LB * N; q += BS) {
+                const int l = q >> LG, v = q & (N - 1);
+                stg(slab, (size_t)brev<LG>(rb + l) * N + v, lds[l * P + v]);
+            }
+        } else if constexpr (PH == 1) {
+            const int cb = b * LB;
+            const C *spec_m = (const C *)J.se_spec + (size_t)m * N * N;
+            batched<BS, CH>(
+                LB * N, [&](int q) { return ldg(slab, (size_t)(q >> LLB) * N + cb + (q & (LB - 1))); },
+                [&](int q, C v) { lds[(q & (LB - 1)) * P + (q >> LLB)] = v; });
+            __syncthreads();
+            dit_axis<R, N, 0, BS, false, LB>(lds, tw);
+            // the spectrum is stored [kx][ky]: q walks ky fastest
+            batched<BS, CH>(
+                LB * N, [&](int q) { return ldg(spec_m, (size_t)(cb + (q >> LG)) * N + (q & (N - 1))); },
+                [&](int q, C sv) {
+                    C *e = lds + (q >> LG) * P + (q & (N - 1));
+                    *e = cmul(*e, sv);
+                });
+            __syncthreads();
+            dif_axis<R, N, 0, BS, true, LB>(lds, tw);
+            for (int q = threadIdx.x; q < LB * N; q += BS) {
+                const int rr = q >> LLB, l = q & (LB - 1);
+                stg(slab, (size_t)rr * N + cb + l, lds[l * P + rr]);
+            }
+        } else {
+            // intermediate row rb + l is output row y = brev(rb + l)
+            const int rb = b * LB;
+            C *ydst = (C *)S.y + (size_t)tl * ytile_elems(J.bins, J.T, J.ybs) + ybin_offset(m, J.T, J.ybs);
+            const R bump = perturb_bump<R>(perturb, J, tile, m, kPerturbFirst);
+            batched<BS, CH>(
+                LB * N, [&](int q) { return ldg(slab, (size_t)(rb + (q >> LG)) * N + (q & (N - 1))); },
+                [&](int q, C v) { lds[(q >> LG) * P + (q & (N - 1))] = v; });
+            __syncthreads();
+            dif_axis<R, N, 0, BS, true, LB>(lds, tw);
+            if constexpr (kOutLdsOrder<R>) {
+                for (int q = threadIdx.x; q < LB * N; q += BS) {
+                    const int l = q >> LG, bb = q & (N - 1);
+                    const int y = brev<LG>(rb + l), x = brev<LG>(bb);
+                    if (y >= k - 1 && x >= k - 1) {
+                        C v = lds[l * P + bb];
+                        v.x += bump;
+                        stg(ydst, ypix((size_t)(y - (k - 1)) * T + (x - (k - 1)), J.ybs), v);
+                    }
+                }
+            } else {
+                for (int q = threadIdx.x; q < LB * T; q += BS) {
+                    const int l = q / T, xo = q - l * T;
+                    const int y = brev<LG>(rb + l);
+                    if (y >= k - 1) {
+                        C v = lds[l * P + brev<LG>(xo + k - 1)];
+                        v.x += bump;
+                        stg(ydst, ypix((size_t)(y - (k - 1)) * T + xo, J.ybs), v);
+                    }
+                }
+            }
+        }
+        __syncthreads();
     }
 }
 
@@ -2103,14 +2189,21 @@ hipError_t launch_or_flag(uint32_t *dst, const uint32_t *src, hipStream_t s) {
 }
 
 hipError_t launch_fft(int nt, int dbl, const JobDev *jobs, const Seg *segs, int nseg, long long nitems,
-                      int grid, const TwF *tw32, const double2 *tw64, void *slabs, StatsDev *st,
-                      const uint8_t *perturb, hipStream_t s) {
+                      int grid, const TwF *tw32, const double2 *tw64, void *slabs, long long big_chunk,
+                      StatsDev *st, const uint8_t *perturb, hipStream_t s) {
     if (nitems <= 0) return hipSuccess;
 #define MD_FFT_CASE(R, N) \
     k_fft_reg<R, N><<<grid, 4 * N, 0, s>>>(jobs, segs, nseg, nitems, tw32, tw64, st, perturb); break;
-#define MD_FFT_BIG(R, N) \
-    k_fft_big<R, N, kBigThreads><<<grid, kBigThreads, 0, s>>>(jobs, segs, nseg, nitems, tw32, tw64, slabs, st, \
-                                                              perturb); break;
+#define MD_FFT_BIG(R, N)                                                                                        \
+    for (long long c0 = 0; c0 < nitems; c0 += big_chunk) {                                                      \
+        const int cn = (int)std::min<long long>(big_chunk, nitems - c0);                                        \
+        k_fft_big<R, N, 0><<<grid, kBigThreads, 0, s>>>(jobs, segs, nseg, c0, cn, tw32, tw64, slabs, st, perturb); \
+        k_fft_big<R, N, 1><<<grid, kBigThreads, 0, s>>>(jobs, segs, nseg, c0, cn, tw32, tw64, slabs, st, perturb); \
+        k_fft_big<R, N, 2><<<grid, kBigThreads, 0, s>>>(jobs, segs, nseg, c0, cn, tw32, tw64, slabs, st, perturb); \
+        const hipError_t e_ = hipGetLastError();                                                                \
+        if (e_ != hipSuccess) return e_;                                                                        \
+    }                                                                                                           \
+    break;
     if (!dbl) {
         switch (nt) {
             case 16: MD_FFT_CASE(float, 16)

@@ -181,10 +181,22 @@ hipError_t launch_or_flag(uint32_t *dst, const uint32_t *src, hipStream_t s);
 hipError_t launch_add_const(int32_t *out, const int32_t *in, int32_t c, size_t n, hipStream_t s);
 hipError_t launch_sub(int32_t *out, const int32_t *x, const int32_t *y, size_t n, hipStream_t s);
 hipError_t launch_fill_hash(int32_t *p, size_t n, int L, unsigned int seed, hipStream_t s);
-// perturb: nullptr, or the test hook's per-tile bits (kPerturbFirst)
+// perturb: nullptr, or the test hook's per-tile bits (kPerturbFirst).
+// Large tiles (big_tile()) run three passes per chunk of big_chunk items;
+// `slabs` then holds big_chunk intermediates of nt x nt complex values and
+// `grid` is the blocks of each pass.
 hipError_t launch_fft(int nt, int dbl, const JobDev *jobs, const Seg *segs, int nseg, long long nitems,
-                      int grid, const TwF *tw32, const double2 *tw64, void *slabs, StatsDev *st,
-                      const uint8_t *perturb, hipStream_t s);
+                      int grid, const TwF *tw32, const double2 *tw64, void *slabs, long long big_chunk,
+                      StatsDev *st, const uint8_t *perturb, hipStream_t s);
+constexpr bool big_tile(int nt, int dbl) { return nt > (dbl ? kMaxLdsN64 : kMaxLdsN32); }
+// Items per chunk of a large-tile launch: intermediates of about 256 MiB
+// (the Infinity Cache), at least one item.
+inline long long big_chunk_items(int nt, int dbl, long long nitems) {
+    const long long per = (long long)nt * nt * (dbl ? 16 : 8);
+    long long c = (256ll << 20) / per;
+    if (c < 1) c = 1;
+    return c < nitems ? c : nitems;
+}
 // decode kernel variant for a job's kept-bin count, and the zero-padded pitch
 // (both dimensions) of the [bin][degree] decode table for a range length
 int decode_group_variant(int bins, int dbl);

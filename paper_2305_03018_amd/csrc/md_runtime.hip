@@ -160,7 +160,8 @@ struct Group {
     int nt = 0, dbl = 0, big = 0;   // big: decode variant (decode groups), blocks per CU (direct groups)
     int pack = 0, sel = 0;        // direct groups: element form, SE staged in LDS
     size_t lds = 0;               // dynamic LDS per block (direct groups)
-    void *slabs = nullptr;        // large-tile FFT groups: grid x nt x nt complex
+    void *slabs = nullptr;        // large-tile FFT groups: big_chunk x nt x nt complex intermediates
+    long long big_chunk = 0;      // large-tile FFT groups: items per chunk of three passes
     std::vector<Seg> segs;
     long long nitems = 0;
     Seg *segs_d = nullptr;
@@ -918,12 +919,12 @@ int check_job(const md_job &j) {
 
 // Floor of a lone transform launch: one item per CU for the LDS-resident
 // kernels (bound by the ALU and the LDS, so an item alone on a CU runs
-// correspondingly faster); two per CU for the large tiles, whose slab passes
-// through global memory are latency-bound (measured: an item alone is only
-// about 2.5x faster than four sharing a CU).
+// correspondingly faster).  A large-tile item spreads over its nt^2 / 4096
+// line batches in each of its three passes, so items enough for four blocks
+// per CU fill the GPU.
 double lone_items(int nt, int dbl) {
-    const bool big = dbl != kPrecNTT && nt > (dbl == kPrecFP64 ? kMaxLdsN64 : kMaxLdsN32);
-    return (big ? 2.0 : 1.0) * g.cu;
+    if (dbl != kPrecNTT && big_tile(nt, dbl)) return std::max(1.0, 4.0 * g.cu * 4096.0 / ((double)nt * nt));
+    return g.cu;
 }
 
 double fft_cost(const md_job &j, int nt, int nr, int dbl, bool lone = false) {
@@ -1379,13 +1380,16 @@ int build_exec(const md_job *jobs, int n, const std::vector<SEData> &ses, Exec &
                 gr.grid = occupancy_grid(gr.nitems, ntt_lds_bytes(gr.nt), ntt_block_threads(gr.nt));
                 continue;
             }
-            gr.grid = occupancy_grid(gr.nitems, fft_lds_bytes(gr.nt, gr.dbl), fft_block_threads(gr.nt, gr.dbl));
-            if (gr.nt > (gr.dbl ? kMaxLdsN64 : kMaxLdsN32)) {
-                // 1024-point tiles keep 3 blocks per CU resident (registers):
-                // no slab for a fourth that would only wait
-                if (gr.nt >= 1024) gr.grid = (int)std::min<long long>(gr.grid, 3LL * g.cu);
-                slab_groups.push_back(
-                    {&gr, (size_t)gr.grid * gr.nt * gr.nt * (gr.dbl ? sizeof(double2) : sizeof(float2))});
+            if (big_tile(gr.nt, gr.dbl)) {
+                // three passes per chunk of items, each over (item, line batch)
+                // units, through the chunk's intermediates
+                gr.big_chunk = big_chunk_items(gr.nt, gr.dbl, gr.nitems);
+                const long long units = gr.big_chunk * (gr.nt / (4096 / gr.nt));
+                gr.grid = occupancy_grid(units, fft_lds_bytes(gr.nt, gr.dbl), fft_block_threads(gr.nt, gr.dbl));
+                slab_groups.push_back({&gr, (size_t)gr.big_chunk * gr.nt * gr.nt *
+                                                (gr.dbl ? sizeof(double2) : sizeof(float2))});
+            } else {
+                gr.grid = occupancy_grid(gr.nitems, fft_lds_bytes(gr.nt, gr.dbl), fft_block_threads(gr.nt, gr.dbl));
             }
         }
         for (auto &gr : wv.dec) {
@@ -1592,7 +1596,7 @@ int enqueue(Exec &ex, hipStream_t s, bool skip_decode = false, bool capturing = 
             ProfScope ps(prof, s, std::string(gr.dbl ? "fft64_n" : "fft32_n") + std::to_string(gr.nt), gr.alg_bytes,
                          gr.alg_ops, gr.units);
             MD_HIP(launch_fft(gr.nt, gr.dbl, ex.jobs_d, gr.segs_d, (int)gr.segs.size(), gr.nitems, gr.grid, g.tw32,
-                              g.tw64, gr.slabs, g.st_d, perturb, s));
+                              g.tw64, gr.slabs, gr.big_chunk, g.st_d, perturb, s));
             ps.done();
         }
         if (skip_decode) continue;
