@@ -422,6 +422,33 @@ def spectrum_error(md, torch, dev):
     return out
 
 
+def dft16_leg(md, torch, dev, stream, lines=1 << 20, reps=32, runs=5):
+    """Batched 16-point DFTs (md_debug_dft16), `reps` in a row per line, by
+    the vector-ALU butterflies of the spatial transform, FP32 matrix-core
+    products and split-bf16 matrix-core products: mean event time per call
+    and the rate in 16-point DFTs per second and in algorithmic flops
+    (5 N log2 N = 320 per DFT)."""
+    rng = np.random.default_rng(23)
+    x = torch.from_numpy((rng.uniform(-1, 1, (lines, 16)) + 1j * rng.uniform(-1, 1, (lines, 16)))
+                         .astype(np.complex64)).to(dev)
+    out = torch.empty_like(x)
+    res = {"lines": lines, "reps": reps}
+    for v, name in ((0, "valu_butterflies"), (1, "mfma_fp32"), (2, "mfma_bf16x3")):
+        md.debug_dft16(v, x, reps=reps, out=out)
+        t0 = torch.cuda.Event(enable_timing=True)
+        t1 = torch.cuda.Event(enable_timing=True)
+        t0.record(stream)
+        for _ in range(runs):
+            md.debug_dft16(v, x, reps=reps, out=out)
+        t1.record(stream)
+        torch.cuda.synchronize()
+        ms = t0.elapsed_time(t1) / runs
+        dfts = lines * reps
+        res[name] = {"ms": ms, "gdft_s": dfts / (ms * 1e-3) / 1e9, "tflops_alg": dfts * 320.0 / (ms * 1e-3) / 1e12}
+        log(f"bench: dft16 {name} {ms:.3f} ms ({res[name]['tflops_alg']:.1f} TFLOP/s algorithmic)")
+    return res
+
+
 def cpu_baseline(jobs, budget_s):
     import oracle
 
@@ -479,6 +506,8 @@ def main():
     ap.add_argument("--leg", choices=sorted(LEG_OPTS),
                     help="run only this forced path on the batch (warm-up, --steps timed steps, one profiled "
                          "step) and print its own JSON line; for hardware-counter runs of its kernels")
+    ap.add_argument("--dft16", action="store_true",
+                    help="only the batched 16-point DFT comparison (vector ALU against matrix cores), one JSON line")
     ap.add_argument("--copy-probe", action="store_true",
                     help="first run one plain device copy of 256 MiB (a known-size reference for HBM byte counters)")
     args = ap.parse_args()
@@ -499,6 +528,12 @@ def main():
         torch.cuda.synchronize()
         log(f"bench: copy probe {src.numel() * 4} bytes read, {dst.numel() * 4} bytes written")
         del src, dst
+    if args.dft16:
+        stream = torch.cuda.Stream()
+        with torch.cuda.stream(stream):
+            print(json.dumps({"dft16": dft16_leg(md, torch, dev, stream)}), flush=True)
+        md.release()
+        return
     jobs = build_workload(args.workload)
     total_px = sum(j.img.size for j in jobs)
     log(f"bench: workload {args.workload}: {len(jobs)} jobs, {total_px / 1e6:.2f} Mpx")
@@ -579,6 +614,7 @@ def main():
             cmp["volume"] = volume_leg(md, torch, dev, stream, max(3, args.steps // 4))
             cmp["large_se"] = large_se_leg(md, torch, dev, stream, 3)
             cmp["host_stream"] = host_stream_leg(md, torch, dev, 3)
+            cmp["dft16"] = dft16_leg(md, torch, dev, stream)
             if args.paper_shapes:
                 cmp["paper_shapes"] = paper_shapes_leg(md, torch, dev, stream, 3)
         spec_err = spectrum_error(md, torch, dev)

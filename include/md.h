@@ -461,6 +461,20 @@ int md_debug_perturb_tiles(const long long *tiles, const uint8_t *bits, int n);
  * transform tile).  Waits for the library stream. */
 int md_debug_tile_flags(uint32_t *dst, long long cap, long long *n);
 
+/* Measurement hook for the choice between butterflies and matrix-core
+ * products in the transform's fixed-radix stages: applies `reps` forward
+ * 16-point DFTs, y_k = sum_n x_n exp(-2 pi i n k / 16), in a row to each of
+ * `lines` lines of 16 complex FP32 values (interleaved re, im; DEVICE
+ * arrays of 32 * lines floats, `in` and `out` may be equal), on the library
+ * stream, waiting for completion.  variant 0: the vector-ALU radix-2 DFT the
+ * spatial transform uses (split hi + lo FP32 constants); 1: FP32
+ * matrix-core products (v_mfma_f32_16x16x4_f32, the DFT matrix rounded to
+ * FP32); 2: split-bf16 matrix-core products (v_mfma_f32_16x16x32_bf16, both
+ * operands as bf16 hi + lo, three products, FP32 accumulation).
+ * MD_ERR_ARG unless lines is a positive multiple of 64, 1 <= reps <= 64 and
+ * variant is 0, 1 or 2. */
+int md_debug_dft16(int variant, const float *in, float *out, long long lines, int reps);
+
 #ifdef __cplusplus
 }
 #endif

@@ -124,6 +124,8 @@ def load():
     lib.md_debug_tile_flags.argtypes = [ctypes.POINTER(ctypes.c_uint32), ctypes.c_longlong,
                                         ctypes.POINTER(ctypes.c_longlong)]
     lib.md_debug_tile_flags.restype = i
+    lib.md_debug_dft16.argtypes = [i, vp, vp, ctypes.c_longlong, i]
+    lib.md_debug_dft16.restype = i
     _lib = lib
     return lib
 
@@ -498,6 +500,24 @@ def debug_perturb_tiles(tiles, bits):
         raise ValueError("tiles and bits must be 1-D of the same length")
     _check(load().md_debug_perturb_tiles(t.ctypes.data_as(ctypes.POINTER(ctypes.c_longlong)),
                                          b.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)), t.shape[0]))
+
+
+def debug_dft16(variant: int, x, reps: int = 1, out=None):
+    """md_debug_dft16 on a complex64 HIP tensor x of shape (lines, 16):
+    `reps` forward 16-point DFTs per line by the vector ALU (0), FP32
+    matrix cores (1) or split-bf16 matrix cores (2)."""
+    import torch
+
+    if not isinstance(x, torch.Tensor) or not x.is_cuda or x.dtype != torch.complex64 or x.dim() != 2 \
+            or x.shape[1] != 16:
+        raise TypeError("x must be a complex64 HIP tensor of shape (lines, 16)")
+    x = x.contiguous()
+    if out is None:
+        out = torch.empty_like(x)
+    with torch.cuda.device(x.device):
+        _bind_stream(x.device)
+        _check(load().md_debug_dft16(int(variant), x.data_ptr(), out.data_ptr(), x.shape[0], int(reps)))
+    return out
 
 
 def debug_tile_flags() -> np.ndarray:

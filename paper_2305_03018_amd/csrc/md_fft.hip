@@ -1859,6 +1859,147 @@ __global__ __launch_bounds__(kDecThreads) void k_decode_small(const JobDev *__re
     if (threadIdx.x == 0 && rm > 0.f) atomicMax(&st->max_res_bits, __float_as_uint(rm));
 }
 
+// ---------------------------------------------------------------------------
+// Measured comparison: batched 16-point DFTs on the vector ALU and on the
+// matrix cores
+// ---------------------------------------------------------------------------
+// The question is whether the fixed-radix DFT stages of the spatial
+// transform would run faster as dense products on the matrix cores than as
+// butterflies.  Three kernels apply `reps` forward 16-point DFTs in a row to
+// each of `lines` lines held in registers (one load and one store per line,
+// so that the arithmetic dominates):
+//   variant 0: the in-register radix-2 DFT of k_fft_reg (split hi + lo FP32
+//              constants), one line per lane;
+//   variant 1: FP32 products on v_mfma_f32_16x16x4_f32: a wavefront holds 64
+//              lines as four 16 x 16 (point x line) blocks, lane (j, q) with
+//              the points 4q + s (s < 4) of line j of each block; one DFT is
+//              Z = F X with F the 16 x 16 DFT matrix, as 4 K-steps of the real
+//              products Fr Xr - Fi Xi and Fi Xr + Fr Xi, and its output comes
+//              back in the same layout (row 4q + r of D in lane group q);
+//   variant 2: the same product on v_mfma_f32_16x16x32_bf16 with both
+//              operands split into bf16 hi + lo and three products
+//              (hi hi + hi lo + lo hi, FP32 accumulation): one K = 32 step per
+//              real output ([Fr | -Fi] and [Fi | Fr] against [Xr; Xi]).
+// The layouts are taken from the data placement of each kernel, so neither
+// pays for moving data between lanes; inside k_fft_reg an MFMA stage would
+// also need that movement.  Test and measurement hook only.
+typedef float f32x4m __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8m __attribute__((ext_vector_type(8)));
+
+__global__ __launch_bounds__(256) void k_dft16_valu(const float2 *__restrict__ in, float2 *__restrict__ out,
+                                                     long long lines, int reps) {
+    const long long line = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (line >= lines) return;
+    float2 v[16];
+    unroll_c<16>([&](auto e) { v[decltype(e)::value] = ldg(in, (size_t)line * 16 + decltype(e)::value); });
+    for (int r = 0; r < reps; ++r) reg_fft<float, 16, false>(v);
+    unroll_c<16>([&](auto e) { stg(out, (size_t)line * 16 + decltype(e)::value, v[decltype(e)::value]); });
+}
+
+// DFT matrix entry exp(-2 pi i a b / 16)
+__device__ __forceinline__ float dft16_re(int a, int b) { return (float)cospi(-2.0 * ((a * b) & 15) / 16.0); }
+__device__ __forceinline__ float dft16_im(int a, int b) { return (float)sinpi(-2.0 * ((a * b) & 15) / 16.0); }
+
+__global__ __launch_bounds__(256) void k_dft16_mfma32(const float2 *__restrict__ in, float2 *__restrict__ out,
+                                                       long long lines, int reps) {
+    const int lane = threadIdx.x & 63, j = lane & 15, q = lane >> 4;
+    const long long w0 = ((long long)blockIdx.x * blockDim.x + threadIdx.x - lane);   // first line of the wave
+    if (w0 >= lines) return;
+    // A operand of K-step s: lane (i = j, k = q) holds F[i][4k + s]
+    float are[4], aim[4], anim[4];
+    for (int s = 0; s < 4; ++s) {
+        are[s] = dft16_re(j, 4 * q + s);
+        aim[s] = dft16_im(j, 4 * q + s);
+        anim[s] = -aim[s];
+    }
+    f32x4m xr[4], xi[4];   // block b: points 4q + s of line w0 + 16 b + j
+    for (int b = 0; b < 4; ++b)
+        for (int s = 0; s < 4; ++s) {
+            const float2 x = ldg(in, (size_t)(w0 + 16 * b + j) * 16 + 4 * q + s);
+            xr[b][s] = x.x;
+            xi[b][s] = x.y;
+        }
+    for (int r = 0; r < reps; ++r) {
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+            f32x4m dr = {0, 0, 0, 0}, di = {0, 0, 0, 0};
+#pragma unroll
+            for (int s = 0; s < 4; ++s) {
+                dr = __builtin_amdgcn_mfma_f32_16x16x4f32(are[s], xr[b][s], dr, 0, 0, 0);
+                dr = __builtin_amdgcn_mfma_f32_16x16x4f32(anim[s], xi[b][s], dr, 0, 0, 0);
+                di = __builtin_amdgcn_mfma_f32_16x16x4f32(aim[s], xr[b][s], di, 0, 0, 0);
+                di = __builtin_amdgcn_mfma_f32_16x16x4f32(are[s], xi[b][s], di, 0, 0, 0);
+            }
+            xr[b] = dr;   // row 4q + s of the output in lane group q
+            xi[b] = di;
+        }
+    }
+    for (int b = 0; b < 4; ++b)
+        for (int s = 0; s < 4; ++s)
+            stg(out, (size_t)(w0 + 16 * b + j) * 16 + 4 * q + s, make_float2(xr[b][s], xi[b][s]));
+}
+
+__device__ __forceinline__ void bf16_split(float x, __bf16 &hi, __bf16 &lo) {
+    hi = (__bf16)x;
+    lo = (__bf16)(x - (float)hi);
+}
+
+__global__ __launch_bounds__(256) void k_dft16_mfma_bf16x3(const float2 *__restrict__ in, float2 *__restrict__ out,
+                                                            long long lines, int reps) {
+    const int lane = threadIdx.x & 63, j = lane & 15, q = lane >> 4;
+    const long long w0 = ((long long)blockIdx.x * blockDim.x + threadIdx.x - lane);
+    if (w0 >= lines) return;
+    // A operands: lane (i = j, k = q) holds K = 8q + t, t < 8: t < 4 the
+    // coefficient of Re x[4q + t], t >= 4 that of Im x[4q + t - 4]
+    bf16x8m arh, arl, aih, ail;   // rows of Re z: [Fr | -Fi]; of Im z: [Fi | Fr]
+    for (int t = 0; t < 8; ++t) {
+        const int e = 4 * q + (t & 3);
+        const float fr = dft16_re(j, e), fi = dft16_im(j, e);
+        __bf16 h, l;
+        bf16_split(t < 4 ? fr : -fi, h, l);
+        arh[t] = h;
+        arl[t] = l;
+        bf16_split(t < 4 ? fi : fr, h, l);
+        aih[t] = h;
+        ail[t] = l;
+    }
+    f32x4m xr[4], xi[4];
+    for (int b = 0; b < 4; ++b)
+        for (int s = 0; s < 4; ++s) {
+            const float2 x = ldg(in, (size_t)(w0 + 16 * b + j) * 16 + 4 * q + s);
+            xr[b][s] = x.x;
+            xi[b][s] = x.y;
+        }
+    for (int r = 0; r < reps; ++r) {
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+            bf16x8m bh, bl;
+#pragma unroll
+            for (int s = 0; s < 4; ++s) {
+                __bf16 h, l;
+                bf16_split(xr[b][s], h, l);
+                bh[s] = h;
+                bl[s] = l;
+                bf16_split(xi[b][s], h, l);
+                bh[s + 4] = h;
+                bl[s + 4] = l;
+            }
+            f32x4m dr = {0, 0, 0, 0}, di = {0, 0, 0, 0};
+            dr = __builtin_amdgcn_mfma_f32_16x16x32_bf16(arl, bh, dr, 0, 0, 0);
+            dr = __builtin_amdgcn_mfma_f32_16x16x32_bf16(arh, bl, dr, 0, 0, 0);
+            dr = __builtin_amdgcn_mfma_f32_16x16x32_bf16(arh, bh, dr, 0, 0, 0);
+            di = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ail, bh, di, 0, 0, 0);
+            di = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aih, bl, di, 0, 0, 0);
+            di = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aih, bh, di, 0, 0, 0);
+            xr[b] = dr;
+            xi[b] = di;
+        }
+    }
+    for (int b = 0; b < 4; ++b)
+        for (int s = 0; s < 4; ++s)
+            stg(out, (size_t)(w0 + 16 * b + j) * 16 + 4 * q + s, make_float2(xr[b][s], xi[b][s]));
+}
+
 // Exact recompute of the tiles listed by the decode: FP64 transforms on
 // nt64-sized sub-tiles (LDS-resident up to 64, through this block's slab
 // beyond), each decoded from this block's slot.  The decode applies the
@@ -2341,6 +2482,18 @@ hipError_t launch_fallback(int nt64, const JobDev *jobs, const int2 *fb_list, St
         default: return hipErrorInvalidValue;
     }
 #undef MD_FB
+    return hipGetLastError();
+}
+
+hipError_t launch_dft16(int variant, const float2 *in, float2 *out, long long lines, int reps, hipStream_t s) {
+    if (lines <= 0) return hipSuccess;
+    const int grid = (int)((lines + 255) / 256);
+    switch (variant) {
+        case 0: k_dft16_valu<<<grid, 256, 0, s>>>(in, out, lines, reps); break;
+        case 1: k_dft16_mfma32<<<grid, 256, 0, s>>>(in, out, lines, reps); break;
+        case 2: k_dft16_mfma_bf16x3<<<grid, 256, 0, s>>>(in, out, lines, reps); break;
+        default: return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 

@@ -256,6 +256,10 @@ hipError_t launch_fallback(int nt64, const JobDev *jobs, const int2 *fb_list, St
 // item is one block of kDecThreads pixels of a tile, pblocks items per tile.
 hipError_t launch_tile_window(const JobDev *jobs, const int2 *win_list, const StatsDev *st, int pblocks, int grid,
                               hipStream_t s);
+// Measurement hook: `reps` forward 16-point DFTs of `lines` lines (a multiple
+// of 64) of 16 complex FP32 values: variant 0 vector ALU, 1 FP32 matrix
+// cores, 2 split-bf16 matrix cores.
+hipError_t launch_dft16(int variant, const float2 *in, float2 *out, long long lines, int reps, hipStream_t s);
 // vol: the volume form of the packed kernel (32-row blocks)
 size_t direct_lds_bytes(int k, int kpad, int pack, int sel, bool vol = false);
 // Element form of the direct window for the largest reachable sum

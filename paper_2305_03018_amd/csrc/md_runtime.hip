@@ -2804,6 +2804,18 @@ int md_plan(const md_job *job, int batch, md_plan_info *out) {
     return MD_OK;
 }
 
+int md_debug_dft16(int variant, const float *in, float *out, long long lines, int reps) {
+    g_err.clear();
+    if (variant < 0 || variant > 2) return fail(MD_ERR_ARG, "variant %d must be 0, 1 or 2", variant);
+    if (lines <= 0 || lines % 64 != 0) return fail(MD_ERR_ARG, "lines=%lld must be a positive multiple of 64", lines);
+    if (reps < 1 || reps > 64) return fail(MD_ERR_ARG, "reps=%d outside [1, 64]", reps);
+    if (!in || !out) return fail(MD_ERR_ARG, "null pointer");
+    MD_TRY(init());
+    MD_HIP(launch_dft16(variant, (const float2 *)in, (float2 *)out, lines, reps, g.stream));
+    MD_HIP(hipStreamSynchronize(g.stream));
+    return MD_OK;
+}
+
 int md_debug_perturb_tiles(const long long *tiles, const uint8_t *bits, int n) {
     if (n < 0 || (n > 0 && (!tiles || !bits))) return fail(MD_ERR_ARG, "null tile list");
     g.perturb.clear();
