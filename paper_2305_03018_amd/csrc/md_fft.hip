@@ -884,8 +884,12 @@ __device__ __forceinline__ void line_inv(C (&v)[E], const TWS &ltw, bool g0) {
     reg_fft<R, E, true>(v);
 }
 
+// waves per SIMD asked of k_fft_reg: the LDS allows four 64-point FP32 blocks
+// (16 waves) per CU, and with the twiddle table in LDS they fit 128 VGPRs
+template <typename R, int N> constexpr int fft_reg_waves() { return sizeof(R) == 4 && N == 64 ? 4 : 1; }
+
 template <typename R, int N>
-__global__ __launch_bounds__(4 * N) void k_fft_reg(const JobDev *__restrict__ jobs, const Seg *__restrict__ segs,
+__global__ __launch_bounds__(4 * N) __attribute__((amdgpu_waves_per_eu(fft_reg_waves<R, N>()))) void k_fft_reg(const JobDev *__restrict__ jobs, const Seg *__restrict__ segs,
                                                    int nseg, long long nitems, const TwF *__restrict__ tw32,
                                                    const double2 *__restrict__ tw64, StatsDev *st,
                                                    const uint8_t *__restrict__ perturb) {
@@ -893,7 +897,7 @@ __global__ __launch_bounds__(4 * N) void k_fft_reg(const JobDev *__restrict__ jo
     constexpr int E = N / 4, P = N + 1;
     static_assert(E >= 4 && (E & (E - 1)) == 0, "E = N / 4 must be a power of two >= 4");
     using TWT = typename std::conditional<sizeof(R) == 4, TwF, double2>::type;
-    constexpr bool TW_LDS = sizeof(R) == 4 && N >= 128;
+    constexpr bool TW_LDS = sizeof(R) == 4 && N >= 64;
     __shared__ C lds[N * P];
     __shared__ TWT tws[TW_LDS ? N : 1];
     const int lane = threadIdx.x & 63, g = lane >> 4;
