@@ -1819,43 +1819,54 @@ __global__ __launch_bounds__(kDecThreads) void k_decode_small(const JobDev *__re
         const C *X = (const C *)S.y + (size_t)tl * ytile_elems(J.bins, T, J.ybs);
         const R scale = (R)J.scale;
         bool hit = false;
+        // the bins of PF pixels are loaded together (their loads in flight at
+        // once), as many as keep the loaded values within about 96 registers
+        constexpr int PF = (M + 1) * (int)sizeof(C) / 4 * PPT <= 96 ? PPT : 1;
 #pragma unroll 1
-        for (int q = 0; q < PPT; ++q) {
-            const int p = (pb * PPT + q) * kDecThreads + threadIdx.x;
-            const int ly = p / T, lx = p - ly * T;
-            const int gy = ty * T + ly, gx = tx * T + lx;
-            const bool valid = p < TT && gy < J.H && gx < J.W;
-            if (!__any(valid)) continue;
-            const size_t b0 = ypix(valid ? p : 0, J.ybs);
-            C x[M + 1];
-            unroll_c<M + 1>([&](auto m) {
-                constexpr int MM = decltype(m)::value;
-                x[MM] = ldg(X, b0 + 16 * MM);
+        for (int q0 = 0; q0 < PPT; q0 += PF) {
+            int gy[PF], gx[PF];
+            bool valid[PF];
+            C x[PF][M + 1];
+            unroll_c<PF>([&](auto qq) {
+                constexpr int Q = decltype(qq)::value;
+                const int p = (pb * PPT + q0 + Q) * kDecThreads + threadIdx.x;
+                const int ly = p / T, lx = p - ly * T;
+                gy[Q] = ty * T + ly;
+                gx[Q] = tx * T + lx;
+                valid[Q] = p < TT && gy[Q] < J.H && gx[Q] < J.W;
+                const size_t b0 = ypix(valid[Q] ? p : 0, J.ybs);
+                unroll_c<M + 1>([&](auto m) {
+                    constexpr int MM = decltype(m)::value;
+                    x[Q][MM] = ldg(X, b0 + 16 * MM);
+                });
             });
-            C z[M];
-            unroll_c<M>([&](auto kk) {
-                constexpr int K = decltype(kk)::value;
-                const C a = x[K], b = x[M - K];
-                C d;
-                d.x = a.x - b.x;
-                d.y = a.y + b.y;
-                const C t = twc<R, K, 2 * M, true>(d);   // w^k (x - conj y)
-                z[K].x = a.x + b.x - t.y;
-                z[K].y = a.y - b.y + t.x;
+            unroll_c<PF>([&](auto qq) {
+                constexpr int Q = decltype(qq)::value;
+                C z[M];
+                unroll_c<M>([&](auto kk) {
+                    constexpr int K = decltype(kk)::value;
+                    const C a = x[Q][K], b = x[Q][M - K];
+                    C d;
+                    d.x = a.x - b.x;
+                    d.y = a.y + b.y;
+                    const C t = twc<R, K, 2 * M, true>(d);   // w^k (x - conj y)
+                    z[K].x = a.x + b.x - t.y;
+                    z[K].y = a.y - b.y + t.x;
+                });
+                reg_idft<R, M>(z);
+                PxDecode<R> dd;
+                unroll_c<M>([&](auto n) {
+                    constexpr int NN = decltype(n)::value;
+                    dd.add(z[NN].x * scale, 2 * NN);
+                    dd.add(z[NN].y * scale, 2 * NN + 1);
+                });
+                if (valid[Q]) {
+                    const int d = dd.top < 0 ? 0 : dd.top;
+                    gst(J.out)[(size_t)gy[Q] * J.W + gx[Q]] = J.op ? (J.L - 1 - d) : d;
+                    run_max = fmaxf(run_max, (float)dd.res);
+                    hit |= px_ambiguous(dd, band, J, gy[Q], gx[Q]);
+                }
             });
-            reg_idft<R, M>(z);
-            PxDecode<R> dd;
-            unroll_c<M>([&](auto n) {
-                constexpr int NN = decltype(n)::value;
-                dd.add(z[NN].x * scale, 2 * NN);
-                dd.add(z[NN].y * scale, 2 * NN + 1);
-            });
-            if (valid) {
-                const int d = dd.top < 0 ? 0 : dd.top;
-                gst(J.out)[(size_t)gy * J.W + gx] = J.op ? (J.L - 1 - d) : d;
-                run_max = fmaxf(run_max, (float)dd.res);
-                hit |= px_ambiguous(dd, band, J, gy, gx);
-            }
         }
         if (__any(hit) && (threadIdx.x & 63) == 0) flag_tile(J, S.job, tile, tile_flags, fb_list, win_list, st);
     }
