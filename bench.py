@@ -73,6 +73,8 @@ def build_workload(name):
         return [synthetic.large_random_mask(0, True), synthetic.large_random_mask(0, False)]
     if name == "octave_noise_4096":
         return [synthetic.octave_noise_4096(0)]
+    if name == "large_disk_2048":
+        return [synthetic.large_disk_2048()]
     if name == "small_uniform":
         return [synthetic.small_uniform(0)]
     raise SystemExit(f"unknown workload {name}")
@@ -319,11 +321,9 @@ def large_se_leg(md, torch, dev, stream, steps):
     import oracle
     from paper_2305_03018_amd import synthetic
 
-    rng = np.random.default_rng(13)
-    side, L, k = 2048, 4, 127
-    img_np = rng.integers(0, L, (side, side)).astype(np.int32)
-    mask = synthetic.disk_mask(k)
-    off = (rng.integers(0, 2, (k, k)) * mask).astype(np.int32)
+    job = synthetic.large_disk_2048()
+    img_np, mask, off, L, k, side = job.img, job.mask, job.off, job.L, job.k, job.img.shape[0]
+    rng = np.random.default_rng(14)
     img = torch.from_numpy(img_np).to(dev)
     out = torch.empty_like(img)
     ys, xs = rng.integers(0, side, 1024), rng.integers(0, side, 1024)

@@ -884,6 +884,31 @@ __device__ __forceinline__ void line_inv(C (&v)[E], const TWS &ltw, bool g0) {
     reg_fft<R, E, true>(v);
 }
 
+// XCD-aware walk of a persistent launch's items.  Workgroups are dealt to the
+// eight XCDs in turn (workgroup b to XCD b mod 8), each XCD with its own L2.
+// Striding the items by the grid would put consecutive items -- the tiles of
+// one range bin, sharing its SE spectrum, and the bins of one tile, sharing
+// its image rows -- on all eight XCDs at once, so every L2 would fetch the
+// same data.  Instead each XCD walks its own contiguous eighth of the items
+// (grid a multiple of 8; otherwise the plain stride).
+struct XcdWalk {
+    long long it, end, step;
+    __device__ __forceinline__ XcdWalk(long long nitems) {
+        const int grid = gridDim.x;
+        if (grid % 8 == 0 && grid >= 8) {
+            const int x = blockIdx.x & 7;
+            const long long per = (nitems + 7) / 8;
+            it = x * per + (blockIdx.x >> 3);
+            end = min(nitems, (x + 1) * per);
+            step = grid >> 3;
+        } else {
+            it = blockIdx.x;
+            end = nitems;
+            step = grid;
+        }
+    }
+};
+
 // waves per SIMD asked of k_fft_reg: the LDS allows four 64-point FP32 blocks
 // (16 waves) per CU, and with the twiddle table in LDS they fit 128 VGPRs
 template <typename R, int N> constexpr int fft_reg_waves() { return sizeof(R) == 4 && N == 64 ? 4 : 1; }
@@ -918,7 +943,8 @@ __global__ __launch_bounds__(4 * N) __attribute__((amdgpu_waves_per_eu(fft_reg_w
     }
     // LDS row of register s in phases 1 and 3: the frequency it holds
     const int frow = g * (E / 4);
-    for (long long it = blockIdx.x; it < nitems; it += gridDim.x) {
+    XcdWalk walk(nitems);
+    for (long long it = walk.it; it < walk.end; it += walk.step) {
         const Seg S = segs[find_seg(segs, nseg, it)];
         const JobDev &J = jobs[S.job];
         const long long local = it - S.item0;

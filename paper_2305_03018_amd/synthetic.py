@@ -112,6 +112,18 @@ def large_random_mask(seed: int = 0, flat: bool = True) -> Job:
                "random_2048x2048_L32_bern63_" + ("flat" if flat else "nonflat"))
 
 
+def large_disk_2048(seed: int = 13) -> Job:
+    """2048x2048, L=4 i.i.d. uniform; 127x127 disk SE with offsets uniform in
+    [0, 1]: a large SE over few grey levels, where the transform's work per
+    pixel (independent of the SE's cells) is below the window's."""
+    rng = np.random.default_rng(seed)
+    side, L, k = 2048, 4, 127
+    img = rng.integers(0, L, (side, side)).astype(np.int32)
+    mask = disk_mask(k)
+    off = (rng.integers(0, 2, (k, k)) * mask).astype(np.int32)
+    return Job(img, L, mask, off, 0, f"uniform_{side}x{side}_L{L}_disk{k}")
+
+
 def uneven_batch(seed: int = 0, n: int = 256) -> list[Job]:
     """n images with sides uniform in [128,1024] (non-square), L drawn from
     {8,16,32,64}, uniform values; odd SE side in [3,41], disk / square /
