@@ -537,6 +537,32 @@ __device__ __forceinline__ R perturb_bump(const uint8_t *perturb, const JobDev &
     return (R)(0.4 * (double)J.nt * J.nt * J.nr);
 }
 
+// Third word of a raw buffer resource on gfx9-class chips (32-bit data
+// format, no swizzle).
+constexpr int kBufWord3 = 0x00020000;
+
+// 8- or 16-byte load through a buffer resource at voff + soff bytes (soff
+// uniform across the wave)
+template <typename C>
+__device__ __forceinline__ C buf_load(__amdgpu_buffer_rsrc_t rs, unsigned voff, unsigned soff) {
+    if constexpr (sizeof(C) == 8)
+        return __builtin_bit_cast(C, __builtin_amdgcn_raw_buffer_load_b64(rs, voff, soff, 0));
+    else
+        return __builtin_bit_cast(C, __builtin_amdgcn_raw_buffer_load_b128(rs, voff, soff, 0));
+}
+
+// 8- or 16-byte store through a buffer resource at voff + soff bytes; a
+// store whose offset lies at or past the resource's size is dropped
+template <typename C>
+__device__ __forceinline__ void buf_store(C v, __amdgpu_buffer_rsrc_t rs, unsigned voff, unsigned soff) {
+    if constexpr (sizeof(C) == 8)
+        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(__attribute__((ext_vector_type(2))) unsigned, v), rs,
+                                              voff, soff, 0);
+    else
+        __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(__attribute__((ext_vector_type(4))) unsigned, v), rs,
+                                               voff, soff, 0);
+}
+
 // ---------------------------------------------------------------------------
 // Spatial transform with register-resident lines (tiles of 16..128 points)
 // ---------------------------------------------------------------------------
@@ -943,42 +969,48 @@ __global__ __launch_bounds__(4 * N) __attribute__((amdgpu_waves_per_eu(fft_reg_w
     }
     // LDS row of register s in phases 1 and 3: the frequency it holds
     const int frow = g * (E / 4);
+    // byte offset of this lane's first spectrum value ([kx][ky], kx = frow + ...)
+    const unsigned spec_voff = (unsigned)(frow * N + line) * sizeof(C);
     XcdWalk walk(nitems);
     for (long long it = walk.it; it < walk.end; it += walk.step) {
         const Seg S = segs[find_seg(segs, nseg, it)];
         const JobDev &J = jobs[S.job];
-        const long long local = it - S.item0;
-        const int m = (int)(local / S.ntiles), tl = (int)(local % S.ntiles);
+        const int local = (int)(it - S.item0);   // a segment holds fewer than 2^31 items
+        const int m = local / S.ntiles, tl = local - m * S.ntiles;
         const int tile = S.tile0 + tl;
         const int ty = tile / J.tiles_x, tx = tile - ty * J.tiles_x;
         const int k = J.k, r = (k - 1) >> 1, T = N - k + 1;
         const int iy0 = ty * J.T - r, ix0 = tx * J.T - r;
-        const C *enc_m = (const C *)J.enc + (size_t)m * J.L;
-        const C *spec_m = (const C *)J.se_spec + (size_t)m * N * N;
-        C *ydst = (C *)S.y + (size_t)tl * ytile_elems(J.bins, J.T, J.ybs) + ybin_offset(m, J.T, J.ybs);
-        // 1. columns: encode (Step 1) and forward transform along y
+        // 1. columns: encode (Step 1) and forward transform along y.  The
+        // range-DFT column of grey value w is read through a buffer resource
+        // of the L table entries: an out-of-image pixel takes index L, past
+        // the table, and reads the zero polynomial.
         C v[E];
         {
-            const auto im = gld(J.img);
-            const int gx = ix0 + line, H = J.H, W = J.W, L = J.L, op = J.op;
+            const int W = J.W, H = J.H, L = J.L;
+            const int gx = ix0 + line, y0 = iy0 + g;
             const bool colin = (unsigned)gx < (unsigned)W;
+            const int32_t *col = J.img + ((ptrdiff_t)y0 * W + gx);   // pixel (y0, gx); read only in the image
+            const __amdgpu_buffer_rsrc_t ers =
+                __builtin_amdgcn_make_buffer_rsrc((void *)((const C *)J.enc + (size_t)m * L), (short)0,
+                                                  (int)(L * sizeof(C)), kBufWord3);
+            // erosion complements the values: w = (L - 1) - v
+            const int wmul = J.op ? -1 : 1, wadd = J.op ? L - 1 : 0;
             int val[E];
             bool in[E];
             unroll_c<E>([&](auto q) {
                 constexpr int Q = decltype(q)::value;
-                const int gy = iy0 + g + 4 * Q;
-                in[Q] = colin && (unsigned)gy < (unsigned)H;
-                val[Q] = im[in[Q] ? (size_t)gy * W + gx : 0];
+                in[Q] = colin && (unsigned)(y0 + 4 * Q) < (unsigned)H;
+                val[Q] = in[Q] ? gld(col)[(ptrdiff_t)(4 * Q) * W] : 0;
             });
-            int bad = 0;
+            unsigned top = 0;   // largest in-image value (as unsigned: negatives count as large)
             unroll_c<E>([&](auto q) {
                 constexpr int Q = decltype(q)::value;
-                bad |= (int)(in[Q] && (unsigned)val[Q] >= (unsigned)L);
-                int w = min(max(val[Q], 0), L - 1);
-                w = op ? L - 1 - w : w;
-                v[Q] = in[Q] ? ldg(enc_m, w) : czero<C>();
+                top = max(top, (unsigned)val[Q]);
+                const unsigned idx = in[Q] ? (unsigned)(wadd + wmul * val[Q]) : (unsigned)L;
+                v[Q] = buf_load<C>(ers, idx * (unsigned)sizeof(C), 0);
             });
-            if (m == 0 && __any(bad) && lane == 0) atomicOr(&st->range_err, 1u);
+            if (m == 0 && __any(top >= (unsigned)L) && lane == 0) atomicOr(&st->range_err, 1u);
         }
         tw_fresh(ltw);
         line_fwd<R, E>(v, ltw, g0);
@@ -994,20 +1026,27 @@ __global__ __launch_bounds__(4 * N) __attribute__((amdgpu_waves_per_eu(fft_reg_w
         });
         tw_fresh(ltw);
         line_fwd<R, E>(v, ltw, g0);
-        // spectrum loads in groups of up to 8 (register pressure)
-        constexpr int SG = E < 8 ? E : 8;
-        unroll_c<E / SG>([&](auto cg) {
-            constexpr int Q0 = SG * decltype(cg)::value;
-            C sv[SG];
-            unroll_c<SG>([&](auto q) {
-                constexpr int Q = Q0 + decltype(q)::value;
-                sv[Q - Q0] = ldg(spec_m, (size_t)(frow + line_freq_c<E>(Q)) * N + line);
+        {
+            // spectrum values through a buffer resource: one offset register
+            // per lane, the compile-time steps as uniform offsets; loads in
+            // groups of up to 8 (register pressure)
+            const __amdgpu_buffer_rsrc_t srs =
+                __builtin_amdgcn_make_buffer_rsrc((void *)((const C *)J.se_spec + (size_t)m * N * N), (short)0,
+                                                  (int)(N * N * sizeof(C)), kBufWord3);
+            constexpr int SG = E < 8 ? E : 8;
+            unroll_c<E / SG>([&](auto cg) {
+                constexpr int Q0 = SG * decltype(cg)::value;
+                C sv[SG];
+                unroll_c<SG>([&](auto q) {
+                    constexpr int Q = Q0 + decltype(q)::value;
+                    sv[Q - Q0] = buf_load<C>(srs, spec_voff, (unsigned)(line_freq_c<E>(Q) * N * sizeof(C)));
+                });
+                unroll_c<SG>([&](auto q) {
+                    constexpr int Q = Q0 + decltype(q)::value;
+                    v[Q] = cmul(v[Q], sv[Q - Q0]);
+                });
             });
-            unroll_c<SG>([&](auto q) {
-                constexpr int Q = Q0 + decltype(q)::value;
-                v[Q] = cmul(v[Q], sv[Q - Q0]);
-            });
-        });
+        }
         tw_fresh(ltw);
         line_inv<R, E>(v, ltw, g0);
         unroll_c<E>([&](auto q) {
@@ -1027,20 +1066,31 @@ __global__ __launch_bounds__(4 * N) __attribute__((amdgpu_waves_per_eu(fft_reg_w
             const R bump = perturb_bump<R>(perturb, J, tile, m, kPerturbFirst);
             const int oc = line - (k - 1);
             if (oc >= 0) {
+                // stores through a buffer resource over the tile's values; the
+                // pixel index of row g + 4 Q is q0 + 4 T Q, negative for the
+                // discarded rows, which then take an offset past the resource
+                // and are dropped.  The [bins][T*T] layout is the blocked one
+                // with 16-pixel blocks of pitch 16.
+                const size_t te = ytile_elems(J.bins, J.T, J.ybs);
+                const __amdgpu_buffer_rsrc_t ors = __builtin_amdgcn_make_buffer_rsrc(
+                    (void *)((C *)S.y + (size_t)tl * te), (short)0, (int)(te * sizeof(C)), kBufWord3);
+                const int ybs = J.ybs ? J.ybs : 16;
+                const int binoff = (int)ybin_offset(m, J.T, J.ybs);
+                const int q0 = (g - (k - 1)) * T + oc;
                 unroll_c<E>([&](auto q) {
                     constexpr int Q = decltype(q)::value;
-                    const int orow = g + 4 * Q - (k - 1);
-                    if (orow >= 0) {
-                        C o = v[Q];
-                        o.x += bump;
-                        stg(ydst, ypix((size_t)orow * T + oc, J.ybs), o);
-                    }
+                    const int qq = q0 + 4 * Q * T;
+                    const unsigned e = (unsigned)(binoff + (qq >> 4) * ybs + (qq & 15));
+                    C o = v[Q];
+                    o.x += bump;
+                    buf_store<C>(o, ors, qq >= 0 ? e * (unsigned)sizeof(C) : 0xfffffff0u, 0);
                 });
             }
         }
         __syncthreads();
     }
 }
+
 
 // Step 3 on one coefficient c_d: the top degree with rint(c_d) != 0, and
 // what the exactness checks need: the largest distance |c_d - rint(c_d)|, the
@@ -1334,20 +1384,6 @@ __global__ __launch_bounds__(kDecThreads) void k_decode(const JobDev *__restrict
     }
     const float rm = block_max(run_max, s_red);
     if (threadIdx.x == 0 && rm > 0.f) atomicMax(&st->max_res_bits, __float_as_uint(rm));
-}
-
-// Third word of a raw buffer resource on gfx9-class chips (32-bit data
-// format, no swizzle).
-constexpr int kBufWord3 = 0x00020000;
-
-// 8- or 16-byte load through a buffer resource at voff + soff bytes (soff
-// uniform across the wave)
-template <typename C>
-__device__ __forceinline__ C buf_load(__amdgpu_buffer_rsrc_t rs, unsigned voff, unsigned soff) {
-    if constexpr (sizeof(C) == 8)
-        return __builtin_bit_cast(C, __builtin_amdgcn_raw_buffer_load_b64(rs, voff, soff, 0));
-    else
-        return __builtin_bit_cast(C, __builtin_amdgcn_raw_buffer_load_b128(rs, voff, soff, 0));
 }
 
 // cos(2 pi q / 16) for q in [0, 8]
