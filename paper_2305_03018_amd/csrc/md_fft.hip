@@ -862,40 +862,46 @@ __device__ __forceinline__ void line_fwd(C (&v)[E], const TWS &ltw, bool g0) {
         v[J] = cadd(a, b);
         v[J + E / 2] = csub(a, b);
     });
-    // turn -i of k2a = 1 on lane parts with bit 0 set
-    unroll_c<E / 2>([&](auto q) {
-        constexpr int S = decltype(q)::value + E / 2;
-        const C x = v[S];
-        v[S].x = g0 ? x.y : x.x;
-        v[S].y = g0 ? -x.x : x.y;
-    });
-    // stage over lane-part bit 0 (lanes 16 apart)
+    // stage over lane-part bit 0 (lanes 16 apart), with the turn -i of the
+    // k2a = 1 values of the lane parts with bit 0 set: after the exchange the
+    // second operand of every pair is such a part's value, so the turn is a
+    // compile-time -i butterfly on the pairs of k2a = 1 in every lane
     unroll_c<E / 2>([&](auto q) {
         constexpr int Q = decltype(q)::value, J = Q % (E / 4) + (Q / (E / 4)) * (E / 2);
         lane_swap<16>(v[J], v[J + E / 4]);
-        const C a = v[J], b = v[J + E / 4];
+        const C a = v[J];
+        C b = v[J + E / 4];
+        if constexpr (J >= E / 2) {   // k2a = 1: b * (-i)
+            const R t = b.x;
+            b.x = b.y;
+            b.y = -t;
+        }
         v[J] = cadd(a, b);
         v[J + E / 4] = csub(a, b);
     });
+    (void)g0;
 }
 
 // Inverse (unnormalised) of line_fwd: takes v[s] = X[line_freq_c<E>(s) + g E / 4],
 // leaves v[e] = N x[g + 4 e] with x the inverse DFT of X.
 template <typename R, int E, typename C, typename TWS>
 __device__ __forceinline__ void line_inv(C (&v)[E], const TWS &ltw, bool g0) {
+    // mirror of the last stage of line_fwd: (p, q) -> (p + q, (p - q) * (+i)
+    // for the pairs of k2a = 1), then the exchange
     unroll_c<E / 2>([&](auto q) {
         constexpr int Q = decltype(q)::value, J = Q % (E / 4) + (Q / (E / 4)) * (E / 2);
         const C a = v[J], b = v[J + E / 4];
         v[J] = cadd(a, b);
-        v[J + E / 4] = csub(a, b);
+        C d = csub(a, b);
+        if constexpr (J >= E / 2) {   // k2a = 1: d * (+i)
+            const R t = d.x;
+            d.x = -d.y;
+            d.y = t;
+        }
+        v[J + E / 4] = d;
         lane_swap<16>(v[J], v[J + E / 4]);
     });
-    unroll_c<E / 2>([&](auto q) {
-        constexpr int S = decltype(q)::value + E / 2;
-        const C x = v[S];
-        v[S].x = g0 ? -x.y : x.x;
-        v[S].y = g0 ? x.x : x.y;
-    });
+    (void)g0;
     unroll_c<E / 2>([&](auto q) {
         constexpr int J = decltype(q)::value;
         const C a = v[J], b = v[J + E / 2];
@@ -1165,8 +1171,8 @@ __global__ __launch_bounds__(kBigThreads) void k_fft_big(const JobDev *__restric
         const long long it = it0 + i;
         const Seg S = segs[find_seg(segs, nseg, it)];
         const JobDev &J = jobs[S.job];
-        const long long local = it - S.item0;
-        const int m = (int)(local / S.ntiles), tl = (int)(local % S.ntiles);
+        const int local = (int)(it - S.item0);   // a segment holds fewer than 2^31 items
+        const int m = local / S.ntiles, tl = local - m * S.ntiles;
         const int tile = S.tile0 + tl;
         const int ty = tile / J.tiles_x, tx = tile - ty * J.tiles_x;
         const int k = J.k, r = (k - 1) >> 1, T = N - k + 1;
