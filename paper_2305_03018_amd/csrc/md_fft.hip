@@ -641,8 +641,9 @@ __device__ __forceinline__ void unroll_c(F &&f) {
 // x * exp(-+2 pi i J / NN) with a compile-time twiddle: free for multiples of
 // a quarter turn, the eighth turns (+-1 +-i) c take a sum and a scaling, the
 // others a full product.  In FP32 the constant is split into hi + lo floats
-// (the lo products first), as the table twiddles are.
-template <typename R, int J, int NN, bool INV, typename C>
+// (the lo products first), as the table twiddles are; SPLIT = false (the
+// range-axis decodes, whose sums are short) rounds it to one float.
+template <typename R, int J, int NN, bool INV, bool SPLIT = true, typename C>
 __device__ __forceinline__ C twc(C x) {
     constexpr int j = ((J % NN) + NN) % NN;
     if constexpr (j == 0) return x;
@@ -668,23 +669,23 @@ __device__ __forceinline__ C twc(C x) {
             constexpr double c = wc < 0 ? -wc : wc;
             constexpr R sx = wc < 0 ? R(-1) : R(1), sy = ws < 0 ? R(-1) : R(1);
             const R t1 = sx * x.x - sy * x.y, t2 = sx * x.y + sy * x.x;
-            if constexpr (sizeof(R) == 4) {
+            if constexpr (sizeof(R) == 4 && SPLIT) {
                 constexpr float ch = (float)c, cl = (float)(c - (double)ch);
                 r.x = fmaf(t1, ch, t1 * cl);
                 r.y = fmaf(t2, ch, t2 * cl);
             } else {
-                r.x = t1 * c;
-                r.y = t2 * c;
+                r.x = t1 * (R)c;
+                r.y = t2 * (R)c;
             }
-        } else if constexpr (sizeof(R) == 4) {
+        } else if constexpr (sizeof(R) == 4 && SPLIT) {
             constexpr float hx = (float)wc, hy = (float)ws;
             constexpr float lx = (float)(wc - (double)hx), ly = (float)(ws - (double)hy);
             const float sxx = fmaf(x.x, lx, -x.y * ly), syy = fmaf(x.x, ly, x.y * lx);
             r.x = fmaf(x.x, hx, fmaf(-x.y, hy, sxx));
             r.y = fmaf(x.x, hy, fmaf(x.y, hx, syy));
         } else {
-            r.x = fma(x.x, wc, -x.y * ws);
-            r.y = fma(x.x, ws, x.y * wc);
+            r.x = fma(x.x, (R)wc, -x.y * (R)ws);
+            r.y = fma(x.x, (R)ws, x.y * (R)wc);
         }
         return r;
     }
@@ -1844,7 +1845,7 @@ __device__ __forceinline__ void reg_idft(C (&v)[M]) {
             reg_idft<R, Q>(a[RR]);
             unroll_c<Q>([&](auto s) {
                 constexpr int SS = decltype(s)::value;
-                a[RR][SS] = twc<R, RR * SS, M, true>(a[RR][SS]);
+                a[RR][SS] = twc<R, RR * SS, M, true, false>(a[RR][SS]);
             });
         });
         unroll_c<Q>([&](auto s) {
@@ -1858,7 +1859,8 @@ __device__ __forceinline__ void reg_idft(C (&v)[M]) {
 }
 
 // Range-axis FFT decode for short range lengths nr = 2M, M = 2^a < 32,
-// 3 2^a < 48 or 5 2^a < 40: one pixel per thread, all of it in registers.
+// 3 2^a < 48 or 5 2^a < 40 (and M = 40 in FP32): one pixel per thread, all of
+// it in registers.
 // The thread loads the pixel's bins X_0 .. X_M (16-pixel blocks, bins
 // contiguous), packs Z_k = (X_k + conj X_{M-k}) + i w^k (X_k - conj X_{M-k}),
 // w = exp(2 pi i / nr), takes the M-point inverse DFT z and reads
@@ -1917,7 +1919,7 @@ __global__ __launch_bounds__(kDecThreads) void k_decode_small(const JobDev *__re
                     C d;
                     d.x = a.x - b.x;
                     d.y = a.y + b.y;
-                    const C t = twc<R, K, 2 * M, true>(d);   // w^k (x - conj y)
+                    const C t = twc<R, K, 2 * M, true, false>(d);   // w^k (x - conj y)
                     z[K].x = a.x + b.x - t.y;
                     z[K].y = a.y - b.y + t.x;
                 });
@@ -2465,7 +2467,7 @@ hipError_t launch_decode(int var, int dbl, const JobDev *jobs, const Seg *segs, 
     k_decode_fft<R, M><<<grid, kDecThreads, 0, s>>>(jobs, segs, nseg, nitems, band, tile_flags, fb_list, win_list, \
                                                      st); break
         const int dm = decode_fft_m(var);
-        if (decode_small_m(dm)) {
+        if (decode_small_m(dm, dbl)) {
 #define MD_DSMALL(R, M) \
     k_decode_small<R, M><<<grid, kDecThreads, 0, s>>>(jobs, segs, nseg, nitems, band, tile_flags, fb_list, win_list, \
                                                        st); break
@@ -2479,6 +2481,7 @@ hipError_t launch_decode(int var, int dbl, const JobDev *jobs, const Seg *segs, 
                 case 16: MD_DSMALL(float, 16);
                 case 20: MD_DSMALL(float, 20);
                 case 24: MD_DSMALL(float, 24);
+                case 40: MD_DSMALL(float, 40);
                 case 100004: MD_DSMALL(double, 4);
                 case 100005: MD_DSMALL(double, 5);
                 case 100006: MD_DSMALL(double, 6);

@@ -205,7 +205,7 @@ int decode_group_variant(int bins, int dbl);
 // and 80 on are decoded so in FP32 only (the FP64 decode of those is dense).
 // Its decode variant is kDecFftVar + log2 M, kDecFftVar + 16 + log2(M / 3)
 // or kDecFftVar + 32 + log2(M / 5).  Short lengths (decode_small_m: M < 32,
-// 48 or 40) run k_decode_small, one pixel per thread in registers, with
+// 48 or 40, and M = 40 in FP32) run k_decode_small, one pixel per thread in registers, with
 // kDecSmallPix pixels of a tile per work item; the others run k_decode_fft,
 // whose work item covers decode_fft_pixels(nr) pixels (256 E / M for E points
 // per thread: 16, 24 or 20).
@@ -214,12 +214,12 @@ constexpr int kDecFftMinNr = 8, kDecFftMaxNr = 4096;
 constexpr int kDecSmallPix = 512;
 constexpr bool is_pow2c(int x) { return x > 0 && (x & (x - 1)) == 0; }
 constexpr int ilog2c(int x) { return x <= 1 ? 0 : 1 + ilog2c(x / 2); }
-constexpr bool decode_small_m(int m) {
+constexpr bool decode_small_m(int m, int dbl) {
     return (is_pow2c(m) && m >= 4 && m < 32) || (m % 3 == 0 && is_pow2c(m / 3) && m >= 6 && m < 48) ||
-           (m % 5 == 0 && is_pow2c(m / 5) && m >= 5 && m < 40);
+           (m % 5 == 0 && is_pow2c(m / 5) && m >= 5 && m < (dbl ? 40 : 80));
 }
 constexpr bool decode_uses_fft(int nr, int dbl) {
-    return (nr % 2 == 0 && decode_small_m(nr / 2)) ||
+    return (nr % 2 == 0 && decode_small_m(nr / 2, dbl)) ||
            (nr >= kDecFftMinNr && nr <= kDecFftMaxNr && is_pow2c(nr)) ||
            (dbl == 0 && nr >= 96 && nr <= 1536 && nr % 3 == 0 && is_pow2c(nr / 3)) ||
            (dbl == 0 && nr >= 80 && nr <= 640 && nr % 5 == 0 && is_pow2c(nr / 5));
@@ -234,8 +234,8 @@ constexpr int decode_fft_m(int var) {
          : var - kDecFftVar < 32 ? 3 << (var - kDecFftVar - 16)
                                  : 5 << (var - kDecFftVar - 32);
 }
-constexpr int decode_fft_pixels(int nr) {
-    return decode_small_m(nr / 2) ? kDecSmallPix : is_pow2c(nr) ? 8192 / nr : nr % 3 == 0 ? 12288 / nr : 10240 / nr;
+constexpr int decode_fft_pixels(int nr, int dbl) {
+    return decode_small_m(nr / 2, dbl) ? kDecSmallPix : is_pow2c(nr) ? 8192 / nr : nr % 3 == 0 ? 12288 / nr : 10240 / nr;
 }
 int dec_pitch(int nr);
 // Flagged tiles of FP32 jobs go to fb_list (the FP64 recompute), those of

@@ -1314,7 +1314,7 @@ int build_exec(const md_job *jobs, int n, const std::vector<SEData> &ses, Exec &
             s.job = i;
             s.tile0 = tile0;
             s.ntiles = nt_;
-            const int dpix = p.dec_fft ? decode_fft_pixels(p.nr) : kDecThreads * kDecPixPerThread;
+            const int dpix = p.dec_fft ? decode_fft_pixels(p.nr, p.dbl) : kDecThreads * kDecPixPerThread;
             s.pblocks = (p.T * p.T + dpix - 1) / dpix;
             s.y = (void *)(uintptr_t)off;   // an offset into the transform-domain buffer until it is placed
             off += per_tile * nt_;
@@ -1402,7 +1402,7 @@ int build_exec(const md_job *jobs, int n, const std::vector<SEData> &ses, Exec &
             const bool p2 = (dm & (dm - 1)) == 0, m3 = dm % 3 == 0;
             const size_t pts = p2 ? 4352 : m3 ? 6400 : 5376;
             const bool last2 = p2 ? dm <= 256 : m3 ? dm <= 192 : dm <= 80;
-            const size_t lds = dm && !decode_small_m((int)dm) ? (pts + (last2 ? 2 * dm : dm)) * elem : 0;
+            const size_t lds = dm && !decode_small_m((int)dm, gr.dbl) ? (pts + (last2 ? 2 * dm : dm)) * elem : 0;
             gr.grid = occupancy_grid(gr.nitems, lds, kDecThreads);
         }
     }
