@@ -988,22 +988,21 @@ int plan_job(const md_job &j, const SEData &se, Plan &p, bool lone) {
     p.cost_dir = dir_ok ? dir_cost(j, se, form, lone) : INFINITY;
     const bool fft_ok = nr_min <= 4096 && se.ncells > 0 && ntt_ok;
     // transform plan: best spatial length and, on the FP paths, range length
-    // by the cost model: the smallest range length (dense decode) or, past
-    // 128, the next power of two (range-axis FFT decode, at the price of more
-    // kept bins).  Up to 128 the extra bins cost more than the decode saves
-    // (the calibrated dense unit, taken at about 12 bins, overprices 64 and
-    // more, so the model is not trusted there); on 2048^2 images the power of
+    // by the cost model: the smallest range length, or the next lengths with
+    // a range-axis FFT decode (2^a, 3 2^a, 5 2^a), at the price of more kept
+    // bins.  Past 128 they are offered always: on 2048^2 images the power of
     // two wins from about 150 on (FP32 12.9 against 6.5 ms at 230, FP64 42.1
-    // against 17.6 ms).
-    // In FP32 the next lengths 3 2^a and 5 2^a are offered too when shorter
-    // (fewer bins than the power of two, the same decode).  FP32 candidates
-    // whose error bound exceeds kFp32BoundMax are skipped; if none is left the
-    // job runs in FP64.
+    // against 17.6 ms).  Up to 128 they are offered only when the smallest
+    // length has no FFT decode (dense decode, 4 nr bins flops a pixel,
+    // against the short decode's one read of the bins): from one FFT-decoded
+    // length to a longer one the extra bins cost more than the decode saves.
+    // FP32 candidates whose error bound exceeds kFp32BoundMax are skipped; if
+    // none is left the job runs in FP64.
     double best = INFINITY;
     int best_nt = 0, best_nr = nr;
     auto search = [&](int prec) {
         int nrs[4] = {nr, 0, 0, 0};
-        if (prec != kPrecNTT && g.opt.nr <= 0 && nr > 128) {
+        if (prec != kPrecNTT && g.opt.nr <= 0 && (nr > 128 || !decode_uses_fft(nr, prec))) {
             int nr2 = 1;
             while (nr2 < nr) nr2 <<= 1;
             if (nr2 != nr && decode_uses_fft(nr2, prec)) nrs[1] = nr2;
@@ -1726,9 +1725,13 @@ int autotune_body() {
         for (int nt = 16; nt <= kMaxN; nt *= 2) {
             MD_TRY(measure(std::min(nt / 8 * 2 + 1, 33), 16, side_for(nt, prec), kPathFFT, prec, nt,
                            pre + std::to_string(nt), nullptr, &g.cost.fft_item[prec][ilog2i(nt)], nullptr));
-            if (nt == 64)
-                MD_TRY(measure(17, 16, 1024, kPathFFT, prec, nt, prec ? "decode64" : "decode32", nullptr,
-                               &g.cost.dec_unit[prec], nullptr));
+            if (nt == 64) {   // the dense decode, at the smallest range length (19)
+                g.opt.nr = 19;
+                const int rc = measure(17, 16, 1024, kPathFFT, prec, nt, prec ? "decode64" : "decode32", nullptr,
+                                       &g.cost.dec_unit[prec], nullptr);
+                g.opt.nr = 0;
+                MD_TRY(rc);
+            }
         }
     }
     // exact path: lengths 16..128 and its decode

@@ -153,3 +153,28 @@ def test_paths_and_errors():
     assert ei.value.code == -1
     with md.options(path=1, nr=19):
         assert md.plan((40, 40), m5, o5, 16)["n_r"] == 19
+
+
+def test_range_length_candidates():
+    """FP paths: the range length is the smallest one, (L-1) + max offset + 1,
+    or the next 2^a, 3 2^a or 5 2^a above it that has a range-axis FFT
+    decode; up to 128 a smallest length that has an FFT decode is kept."""
+    rng = np.random.default_rng(8)
+    pow2 = lambda x: x > 0 and x & (x - 1) == 0
+    for _ in range(120):
+        k = int(rng.integers(0, 8)) * 2 + 1
+        L = int(rng.choice([int(rng.integers(2, 140)), int(rng.integers(2, 1000))]))
+        mask, off = _se(rng, k, 0.7, int(rng.integers(0, max(1, L // 4))))
+        nr_min = (L - 1) + int(off[mask != 0].max()) + 1
+        for prec in (0, 1):
+            with md.options(path=1, precision=prec):
+                p = md.plan((400, 300), mask, off, L)
+            n = p["n_r"]
+            if n == nr_min:
+                continue
+            assert p["decode_fft"] == 1, (nr_min, p)
+            nxt = [min(c << a for a in range(13) if (c << a) >= nr_min) for c in (1, 3, 5)]
+            assert n in nxt and pow2(n // (3 if n % 3 == 0 else 5 if n % 5 == 0 else 1)), (nr_min, n)
+            if nr_min <= 128:
+                with md.options(path=1, precision=p["precision"], nr=nr_min):
+                    assert md.plan((400, 300), mask, off, L)["decode_fft"] == 0, (nr_min, n)
