@@ -942,6 +942,25 @@ struct XcdWalk {
     }
 };
 
+// Item order of k_fft_reg within a segment: groups of kTileGroup tiles, all
+// bins of a group before the next, bin-major inside the group (the last group
+// takes the remaining tiles).  The blocks of an XCD then share a few image
+// windows and a few bins' SE spectra at a time, both L2-resident, instead of
+// one spectrum and a new image window per item.
+constexpr int kTileGroup = 8;
+__device__ __forceinline__ void tile_group_item(int local, int ntiles, int bins, int &m, int &tl) {
+    const int full = ntiles - ntiles % kTileGroup;   // tiles in whole groups
+    if (local < full * bins) {
+        const int per = bins * kTileGroup, grp = local / per, q = local - grp * per;
+        m = q / kTileGroup;
+        tl = grp * kTileGroup + (q & (kTileGroup - 1));
+    } else {
+        const int rem = ntiles - full, q = local - full * bins;
+        m = q / rem;
+        tl = full + (q - m * rem);
+    }
+}
+
 // waves per SIMD asked of k_fft_reg: the LDS allows four 64-point FP32 blocks
 // (16 waves) per CU, and with the twiddle table in LDS they fit 128 VGPRs
 template <typename R, int N> constexpr int fft_reg_waves() { return sizeof(R) == 4 && N == 64 ? 4 : 1; }
@@ -983,7 +1002,8 @@ __global__ __launch_bounds__(4 * N) __attribute__((amdgpu_waves_per_eu(fft_reg_w
         const Seg S = segs[find_seg(segs, nseg, it)];
         const JobDev &J = jobs[S.job];
         const int local = (int)(it - S.item0);   // a segment holds fewer than 2^31 items
-        const int m = local / S.ntiles, tl = local - m * S.ntiles;
+        int m, tl;
+        tile_group_item(local, S.ntiles, J.bins, m, tl);
         const int tile = S.tile0 + tl;
         const int ty = tile / J.tiles_x, tx = tile - ty * J.tiles_x;
         const int k = J.k, r = (k - 1) >> 1, T = N - k + 1;
