@@ -1878,9 +1878,9 @@ __device__ __forceinline__ void reg_idft(C (&v)[M]) {
     }
 }
 
-// Range-axis FFT decode for short range lengths nr = 2M, M = 2^a < 32,
-// 3 2^a < 48 or 5 2^a < 40 (and M = 40 in FP32): one pixel per thread, all of
-// it in registers.
+// Range-axis FFT decode for short range lengths nr = 2M, M from 4 to 45 in
+// FP32 (to 24 in FP64) with no prime factor above 5, except 32: one pixel per
+// thread, all of it in registers.
 // The thread loads the pixel's bins X_0 .. X_M (16-pixel blocks, bins
 // contiguous), packs Z_k = (X_k + conj X_{M-k}) + i w^k (X_k - conj X_{M-k}),
 // w = exp(2 pi i / nr), takes the M-point inverse DFT z and reads
@@ -2502,6 +2502,14 @@ hipError_t launch_decode(int var, int dbl, const JobDev *jobs, const Seg *segs, 
                 case 20: MD_DSMALL(float, 20);
                 case 24: MD_DSMALL(float, 24);
                 case 40: MD_DSMALL(float, 40);
+                case 9: MD_DSMALL(float, 9);
+                case 15: MD_DSMALL(float, 15);
+                case 18: MD_DSMALL(float, 18);
+                case 25: MD_DSMALL(float, 25);
+                case 27: MD_DSMALL(float, 27);
+                case 30: MD_DSMALL(float, 30);
+                case 36: MD_DSMALL(float, 36);
+                case 45: MD_DSMALL(float, 45);
                 case 100004: MD_DSMALL(double, 4);
                 case 100005: MD_DSMALL(double, 5);
                 case 100006: MD_DSMALL(double, 6);
@@ -2511,6 +2519,9 @@ hipError_t launch_decode(int var, int dbl, const JobDev *jobs, const Seg *segs, 
                 case 100016: MD_DSMALL(double, 16);
                 case 100020: MD_DSMALL(double, 20);
                 case 100024: MD_DSMALL(double, 24);
+                case 100009: MD_DSMALL(double, 9);
+                case 100015: MD_DSMALL(double, 15);
+                case 100018: MD_DSMALL(double, 18);
                 default: return hipErrorInvalidValue;
             }
 #undef MD_DSMALL

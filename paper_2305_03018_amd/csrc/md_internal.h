@@ -203,37 +203,33 @@ int decode_group_variant(int bins, int dbl);
 // Range-axis FFT decode: for nr = 2M with M = 2^a (nr 8..4096), M = 3 2^a
 // (nr 12..1536) or M = 5 2^a (nr 10..640); lengths 3 2^a and 5 2^a from 96
 // and 80 on are decoded so in FP32 only (the FP64 decode of those is dense).
-// Its decode variant is kDecFftVar + log2 M, kDecFftVar + 16 + log2(M / 3)
-// or kDecFftVar + 32 + log2(M / 5).  Short lengths (decode_small_m: M < 32,
-// 48 or 40, and M = 40 in FP32) run k_decode_small, one pixel per thread in registers, with
-// kDecSmallPix pixels of a tile per work item; the others run k_decode_fft,
-// whose work item covers decode_fft_pixels(nr) pixels (256 E / M for E points
-// per thread: 16, 24 or 20).
+// Short lengths (decode_small_m: M from 4 to 45 in FP32, to 24 in FP64, with
+// no prime factor above 5, except 32) run k_decode_small, one pixel per
+// thread in registers, with kDecSmallPix pixels of a tile per work item; the
+// others run k_decode_fft, whose work item covers decode_fft_pixels(nr)
+// pixels (256 E / M for E points per thread: 16, 24 or 20).  The decode
+// variant of a range length is kDecFftVar + M.
 constexpr int kDecFftVar = 16;
 constexpr int kDecFftMinNr = 8, kDecFftMaxNr = 4096;
 constexpr int kDecSmallPix = 512;
 constexpr bool is_pow2c(int x) { return x > 0 && (x & (x - 1)) == 0; }
 constexpr int ilog2c(int x) { return x <= 1 ? 0 : 1 + ilog2c(x / 2); }
-constexpr bool decode_small_m(int m, int dbl) {
-    return (is_pow2c(m) && m >= 4 && m < 32) || (m % 3 == 0 && is_pow2c(m / 3) && m >= 6 && m < 48) ||
-           (m % 5 == 0 && is_pow2c(m / 5) && m >= 5 && m < (dbl ? 40 : 80));
+constexpr bool smooth235(int m) {
+    if (m < 1) return false;
+    while (m % 2 == 0) m /= 2;
+    while (m % 3 == 0) m /= 3;
+    while (m % 5 == 0) m /= 5;
+    return m == 1;
 }
+constexpr bool decode_small_m(int m, int dbl) { return m >= 4 && m != 32 && m <= (dbl ? 24 : 45) && smooth235(m); }
 constexpr bool decode_uses_fft(int nr, int dbl) {
     return (nr % 2 == 0 && decode_small_m(nr / 2, dbl)) ||
            (nr >= kDecFftMinNr && nr <= kDecFftMaxNr && is_pow2c(nr)) ||
            (dbl == 0 && nr >= 96 && nr <= 1536 && nr % 3 == 0 && is_pow2c(nr / 3)) ||
            (dbl == 0 && nr >= 80 && nr <= 640 && nr % 5 == 0 && is_pow2c(nr / 5));
 }
-constexpr int decode_fft_var(int nr) {
-    return is_pow2c(nr) ? kDecFftVar + ilog2c(nr / 2)
-         : nr % 3 == 0  ? kDecFftVar + 16 + ilog2c(nr / 6)
-                        : kDecFftVar + 32 + ilog2c(nr / 10);
-}
-constexpr int decode_fft_m(int var) {
-    return var - kDecFftVar < 16   ? 1 << (var - kDecFftVar)
-         : var - kDecFftVar < 32 ? 3 << (var - kDecFftVar - 16)
-                                 : 5 << (var - kDecFftVar - 32);
-}
+constexpr int decode_fft_var(int nr) { return kDecFftVar + nr / 2; }
+constexpr int decode_fft_m(int var) { return var - kDecFftVar; }
 constexpr int decode_fft_pixels(int nr, int dbl) {
     return decode_small_m(nr / 2, dbl) ? kDecSmallPix : is_pow2c(nr) ? 8192 / nr : nr % 3 == 0 ? 12288 / nr : 10240 / nr;
 }

@@ -989,8 +989,8 @@ int plan_job(const md_job &j, const SEData &se, Plan &p, bool lone) {
     const bool fft_ok = nr_min <= 4096 && se.ncells > 0 && ntt_ok;
     // transform plan: best spatial length and, on the FP paths, range length
     // by the cost model: the smallest range length, or the next lengths with
-    // a range-axis FFT decode (2^a, 3 2^a, 5 2^a), at the price of more kept
-    // bins.  Past 128 they are offered always: on 2048^2 images the power of
+    // a range-axis FFT decode (2^a, 3 2^a, 5 2^a, and the shortest length with
+    // any FFT decode), at the price of more kept bins.  Past 128 they are offered always: on 2048^2 images the power of
     // two wins from about 150 on (FP32 12.9 against 6.5 ms at 230, FP64 42.1
     // against 17.6 ms).  Up to 128 they are offered only when the smallest
     // length has no FFT decode (dense decode, 4 nr bins flops a pixel,
@@ -1001,7 +1001,7 @@ int plan_job(const md_job &j, const SEData &se, Plan &p, bool lone) {
     double best = INFINITY;
     int best_nt = 0, best_nr = nr;
     auto search = [&](int prec) {
-        int nrs[4] = {nr, 0, 0, 0};
+        int nrs[5] = {nr, 0, 0, 0, 0};
         if (prec != kPrecNTT && g.opt.nr <= 0 && (nr > 128 || !decode_uses_fft(nr, prec))) {
             int nr2 = 1;
             while (nr2 < nr) nr2 <<= 1;
@@ -1012,11 +1012,18 @@ int plan_job(const md_job &j, const SEData &se, Plan &p, bool lone) {
             int nr5 = 10;
             while (nr5 < nr) nr5 <<= 1;
             if (nr5 != nr && nr5 < nr2 && nr5 < nr3 && decode_uses_fft(nr5, prec)) nrs[3] = nr5;
+            // and the shortest length above nr with any FFT decode (the short
+            // decode's lengths 2M, M with no prime factor above 5)
+            for (int n = nr + 1; n < 2 * nr && n <= 4096; ++n)
+                if (decode_uses_fft(n, prec)) {
+                    if (n != nrs[1] && n != nrs[2] && n != nrs[3]) nrs[4] = n;
+                    break;
+                }
         }
         best = INFINITY;
         best_nt = 0;
         best_nr = nr;
-        for (int c = 0; c < 4; ++c)
+        for (int c = 0; c < 5; ++c)
             for (int nt = 16; fft_ok && nrs[c] > 0 && nt <= kMaxN; nt *= 2) {
                 if (g.opt.tile > 0 && nt != g.opt.tile) continue;
                 if (prec == kPrecFP32 && fp32_error_bound(nt, nrs[c], se.ncells) > kFp32BoundMax) continue;

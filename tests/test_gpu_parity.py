@@ -259,9 +259,10 @@ def test_direct_packed_forms(dev):
 
 
 def test_range_fft_decode(dev):
-    """Power-of-two range lengths from 8 to 4096, 3 2^a from 12 to 48 and
-    5 2^a from 10 to 40, and in FP32 the lengths 3 2^a up to 1536 and 5 2^a
-    up to 640, decode by a range-axis FFT (even and odd
+    """Power-of-two range lengths from 8 to 4096, the short lengths 2M (M
+    from 4 to 24 in FP64 and to 45 in FP32 with no prime factor above 5), and
+    in FP32 the lengths 3 2^a up to 1536 and 5 2^a up to 640, decode by a
+    range-axis FFT (even and odd
     coefficients from one complex inverse transform of half length) instead
     of the dense inverse DFT.  Forced lengths in both
     precisions, erosion, several tiles with ragged edges, and the exact
@@ -279,6 +280,15 @@ def test_range_fft_decode(dev):
         (57, 88, 25, 11, 0.7, 7, 0, 32),
         (120, 111, 32, 31, 0.6, 8, 1, 40),
         (66, 95, 40, 15, 0.6, 8, 0, 48),
+        # short lengths with factors 3 and 5 beyond one (M = 9 .. 45)
+        (77, 91, 12, 9, 0.7, 5, 1, 18),
+        (95, 60, 20, 7, 0.6, 8, 0, 30),
+        (64, 130, 28, 11, 0.8, 7, 1, 36),
+        (101, 83, 40, 5, 0.7, 9, 0, 50),
+        (58, 147, 44, 13, 0.6, 9, 1, 54),
+        (120, 75, 48, 9, 0.7, 11, 0, 60),
+        (93, 118, 60, 17, 0.6, 10, 1, 72),
+        (81, 139, 70, 7, 0.8, 18, 0, 90),
         (133, 171, 48, 9, 0.7, 12, 1, 64),
         (150, 203, 100, 7, 0.7, 27, 0, 128),
         (97, 181, 200, 9, 0.6, 50, 1, 256),

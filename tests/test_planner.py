@@ -59,11 +59,24 @@ def test_range_length_holds_every_degree():
             assert p["bins"] == p["n_r"] // 2 + 1
             n = p["n_r"]
             pow2 = lambda x: x > 0 and x & (x - 1) == 0
-            fft_len = (n >= 8 and pow2(n)) or (n % 3 == 0 and 12 <= n <= 48 and pow2(n // 3)) or (
-                n % 5 == 0 and 10 <= n <= 40 and pow2(n // 5)) or (
-                p["precision"] == 0 and ((n % 3 == 0 and 96 <= n <= 1536 and pow2(n // 3)) or
-                                         (n % 5 == 0 and 80 <= n <= 640 and pow2(n // 5))))
-            assert p["decode_fft"] == (1 if fft_len and n <= 4096 else 0), p
+            assert p["decode_fft"] == (1 if _fft_decodable(n, p["precision"]) else 0), p
+
+
+def _smooth(m):
+    for f in (2, 3, 5):
+        while m % f == 0:
+            m //= f
+    return m == 1
+
+
+def _fft_decodable(n, prec):
+    """Range lengths with a range-axis FFT decode: 2^a (8..4096); 3 2^a and
+    5 2^a up to 1536 and 640 in FP32; and the short decode's 2M with M from 4
+    to 45 (FP32) or 24 (FP64), no prime factor above 5, M != 32."""
+    pow2 = lambda x: x > 0 and x & (x - 1) == 0
+    small = n % 2 == 0 and 4 <= n // 2 <= (24 if prec else 45) and n // 2 != 32 and _smooth(n // 2)
+    return small or (8 <= n <= 4096 and pow2(n)) or (prec == 0 and (
+        (n % 3 == 0 and 96 <= n <= 1536 and pow2(n // 3)) or (n % 5 == 0 and 80 <= n <= 640 and pow2(n // 5))))
 
 
 def test_fp32_only_under_the_error_bound():
@@ -157,10 +170,10 @@ def test_paths_and_errors():
 
 def test_range_length_candidates():
     """FP paths: the range length is the smallest one, (L-1) + max offset + 1,
-    or the next 2^a, 3 2^a or 5 2^a above it that has a range-axis FFT
-    decode; up to 128 a smallest length that has an FFT decode is kept."""
+    or above it the next 2^a, 3 2^a or 5 2^a, or the shortest length, that
+    has a range-axis FFT decode; up to 128 a smallest length that has an FFT
+    decode is kept."""
     rng = np.random.default_rng(8)
-    pow2 = lambda x: x > 0 and x & (x - 1) == 0
     for _ in range(120):
         k = int(rng.integers(0, 8)) * 2 + 1
         L = int(rng.choice([int(rng.integers(2, 140)), int(rng.integers(2, 1000))]))
@@ -172,9 +185,11 @@ def test_range_length_candidates():
             n = p["n_r"]
             if n == nr_min:
                 continue
-            assert p["decode_fft"] == 1, (nr_min, p)
+            prec_p = p["precision"]
+            assert p["decode_fft"] == 1 and _fft_decodable(n, prec_p), (nr_min, p)
             nxt = [min(c << a for a in range(13) if (c << a) >= nr_min) for c in (1, 3, 5)]
-            assert n in nxt and pow2(n // (3 if n % 3 == 0 else 5 if n % 5 == 0 else 1)), (nr_min, n)
+            first = next(m for m in range(nr_min + 1, 2 * nr_min) if _fft_decodable(m, prec_p))
+            assert n in nxt or n == first, (nr_min, n)
             if nr_min <= 128:
                 with md.options(path=1, precision=p["precision"], nr=nr_min):
                     assert md.plan((400, 300), mask, off, L)["decode_fft"] == 0, (nr_min, n)
