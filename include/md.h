@@ -100,13 +100,14 @@ typedef enum {
                               up, volumes 8, 16 or 32)                           */
     MD_OPT_NR = 4,         /* 0: auto, else the range-axis DFT length; must be at
                               least (L-1) + max offset + 1.  FP paths decode a
-                              length 2^a from 8 to 4096, 3 2^a from 12 to 48 or
-                              5 2^a from 10 to 40 (and FP32 also 3 2^a up to
-                              1536 and 5 2^a up to 640)
-                              by an FFT along the range axis, any other by a
-                              dense DFT; auto weighs the smallest length
-                              against the next such lengths once the smallest
-                              passes 128                                        */
+                              length 2^a from 8 to 4096, a length 2M with M in
+                              [4, 24] (FP32: [4, 45]) having no prime factor
+                              above 5, and in FP32 also 3 2^a up to 1536 and
+                              5 2^a up to 640, by an FFT along the range axis,
+                              any other by a dense DFT; auto weighs the
+                              smallest length against the next such lengths
+                              when the smallest has no FFT decode or passes
+                              128                                               */
     MD_OPT_SYNC = 5,       /* 1 (default): wait for completion in every call    */
     MD_OPT_GRAPH = 6,      /* 1 (default): md_dilate_batch captures its launches
                               in a HIP graph per batch signature and replays it  */
