@@ -449,6 +449,30 @@ def dft16_leg(md, torch, dev, stream, lines=1 << 20, reps=32, runs=5):
     return res
 
 
+def stream_probe(torch, dev, gib=4, runs=10):
+    """Device-memory rate of torch's own streaming kernels: a copy (read
+    and write) and a full-tensor sum (read), timed with HIP events."""
+    n = gib << 28
+    x = torch.ones(n, dtype=torch.float32, device=dev)
+    y = torch.empty_like(x)
+    res = {}
+    for name, f, nbytes in (("copy", lambda: y.copy_(x), 2 * 4 * n), ("sum", lambda: x.sum(), 4 * n)):
+        f()
+        torch.cuda.synchronize()
+        t0 = torch.cuda.Event(enable_timing=True)
+        t1 = torch.cuda.Event(enable_timing=True)
+        t0.record()
+        for _ in range(runs):
+            f()
+        t1.record()
+        torch.cuda.synchronize()
+        ms = t0.elapsed_time(t1) / runs
+        res[name] = {"ms": ms, "bytes": nbytes, "TB_s": nbytes / (ms * 1e-3) / 1e12}
+        log(f"bench: stream probe {name} {gib} GiB: {ms:.3f} ms, {res[name]['TB_s']:.2f} TB/s")
+    del x, y
+    return res
+
+
 def cpu_baseline(jobs, budget_s):
     import oracle
 
@@ -508,6 +532,9 @@ def main():
                          "step) and print its own JSON line; for hardware-counter runs of its kernels")
     ap.add_argument("--dft16", action="store_true",
                     help="only the batched 16-point DFT comparison (vector ALU against matrix cores), one JSON line")
+    ap.add_argument("--stream-probe", action="store_true",
+                    help="only time torch's own streaming kernels (a 4 GiB device copy and a full-tensor sum) "
+                         "with HIP events: the rate this GPU reaches for plain streaming access, one JSON line")
     ap.add_argument("--copy-probe", action="store_true",
                     help="first run one plain device copy of 256 MiB (a known-size reference for HBM byte counters)")
     args = ap.parse_args()
@@ -521,6 +548,9 @@ def main():
     import paper_2305_03018_amd as md
 
     dev = torch.device("cuda:0")
+    if args.stream_probe:
+        print(json.dumps({"stream_probe": stream_probe(torch, dev)}), flush=True)
+        return
     if args.copy_probe:
         src = torch.arange(64 << 20, dtype=torch.int32, device=dev)
         dst = torch.empty_like(src)

@@ -427,9 +427,9 @@ __device__ __forceinline__ void fft_tile_bin(typename Cx<R>::T *lds, const int32
 }
 
 // Lines of length N held in LDS at a time by the large-tile transform
-// (32 KiB of complex values, so up to four blocks fit a CU).
+// (4096 points: in FP32 32 KiB, so up to four blocks fit a CU).
 template <typename R, int N>
-constexpr int big_lines() { return (sizeof(R) == 4 ? 4096 : 4096) / N; }
+constexpr int big_lines() { return big_lines_of(N, sizeof(R) == 8); }
 
 // One (tile, bin) of Step 2 for spatial lengths whose N x N array does not
 // fit the LDS.  Same overlap-save geometry and bit-reversal bookkeeping as
@@ -1171,8 +1171,9 @@ __device__ __forceinline__ bool px_ambiguous(const PxDecode<R> &dd, float band, 
 //         ([kx][ky]), inverse DIF along y (row r' then holds output row
 //         brev(r')), stored back;
 //   PH 2: LB rows: inverse DIF along x and the T x T valid outputs.
-// Work units are (item, batch) pairs, item-major, so that consecutive blocks
-// share an item's image rows, intermediate and spectrum.
+// Work units are (item, batch) pairs, item-major, walked per XCD (XcdWalk),
+// so that the blocks of one XCD share an item's image rows, intermediate
+// lines and spectrum in their L2.
 template <typename R, int N, int PH>
 __global__ __launch_bounds__(kBigThreads) void k_fft_big(const JobDev *__restrict__ jobs, const Seg *__restrict__ segs,
                                                          int nseg, long long it0, int cn, const TwF *__restrict__ tw32,
@@ -1187,7 +1188,8 @@ __global__ __launch_bounds__(kBigThreads) void k_fft_big(const JobDev *__restric
     typename TwSel<R>::T tw;
     if constexpr (sizeof(R) == 4) tw.p = tw32; else tw.p = tw64;
     const long long units = (long long)cn * NB;
-    for (long long u = blockIdx.x; u < units; u += gridDim.x) {
+    XcdWalk walk(units);
+    for (long long u = walk.it; u < walk.end; u += walk.step) {
         const int i = (int)(u / NB), b = (int)(u - (long long)i * NB);
         const long long it = it0 + i;
         const Seg S = segs[find_seg(segs, nseg, it)];
@@ -1321,19 +1323,49 @@ __device__ __forceinline__ void decode_px(const typename Cx<R>::T *X, size_t mst
     }
 }
 
-// Decode variants by kept-bin count: one register pass for bins <= 8, <= 12
-// and (FP32) <= 24; else blocks of 16 x 16 (FP32) or 8 x 8 (FP64).
-enum : int { kDec8 = 0, kDec12 = 1, kDec24 = 2, kDecBlk = 3 };
+// decode_px for at most MB bins and nr / 2 < MB degree pairs (one pass), with
+// the pixel's bins already loaded (zero past the kept ones)
+template <typename R, int MB>
+__device__ __forceinline__ void decode_px_regs(const typename Cx<R>::T (&x)[MB], const typename Cx<R>::T *dec,
+                                               int dp, int nr, R scale, PxDecode<R> &out) {
+    using C = typename Cx<R>::T;
+    const int dh = nr >> 1;
+    out = PxDecode<R>();
+    R A[MB], B[MB];
+#pragma unroll
+    for (int dd = 0; dd < MB; ++dd) A[dd] = B[dd] = 0;
+#pragma unroll
+    for (int mm = 0; mm < MB; ++mm) {
+#pragma unroll
+        for (int dd = 0; dd < MB; ++dd) {
+            const C w = ldc(dec, (size_t)mm * dp + dd);
+            A[dd] = fma(x[mm].x, w.x, A[dd]);
+            B[dd] = fma(x[mm].y, w.y, B[dd]);
+        }
+    }
+#pragma unroll
+    for (int d = 0; d < MB; ++d) {
+        if (d <= dh) {
+            out.add((A[d] - B[d]) * scale, d);
+            if (d > 0 && 2 * d != nr) out.add((A[d] + B[d]) * scale, nr - d);
+        }
+    }
+}
+
+// Decode variants by kept-bin count: one register pass for bins <= 4, <= 8,
+// <= 12 and (FP32) <= 24; else blocks of 16 x 16 (FP32) or 8 x 8 (FP64).
+enum : int { kDec8 = 0, kDec12 = 1, kDec24 = 2, kDecBlk = 3, kDec4 = 4 };
 
 __host__ __device__ constexpr int decode_variant(int bins, int dbl) {
-    return bins <= 8 ? kDec8 : bins <= 12 ? kDec12 : (bins <= 24 && !dbl) ? kDec24 : kDecBlk;
+    return bins <= 4 ? kDec4 : bins <= 8 ? kDec8 : bins <= 12 ? kDec12 : (bins <= 24 && !dbl) ? kDec24 : kDecBlk;
 }
 
 template <typename R, int V>
 __device__ __forceinline__ void decode_var(const typename Cx<R>::T *X, size_t mstride, size_t p, bool valid,
                                            const typename Cx<R>::T *dec, int dp, int nr, int bins, R scale,
                                            PxDecode<R> &out) {
-    if constexpr (V == kDec8) decode_px<R, 8, 8>(X, mstride, p, valid, dec, dp, nr, bins, scale, out);
+    if constexpr (V == kDec4) decode_px<R, 4, 4>(X, mstride, p, valid, dec, dp, nr, bins, scale, out);
+    else if constexpr (V == kDec8) decode_px<R, 8, 8>(X, mstride, p, valid, dec, dp, nr, bins, scale, out);
     else if constexpr (V == kDec12) decode_px<R, 12, 12>(X, mstride, p, valid, dec, dp, nr, bins, scale, out);
     else if constexpr (V == kDec24) decode_px<R, 24, 24>(X, mstride, p, valid, dec, dp, nr, bins, scale, out);
     else if constexpr (sizeof(R) == 4) decode_px<R, 16, 16>(X, mstride, p, valid, dec, dp, nr, bins, scale, out);
@@ -1389,6 +1421,39 @@ __global__ __launch_bounds__(kDecThreads) void k_decode(const JobDev *__restrict
         const C *X = (const C *)S.y + (size_t)tl * ytile_elems(J.bins, T, J.ybs);
         const size_t mstride = J.ybs ? 16 : TT;   // between bins of one pixel
         bool hit = false;
+        if constexpr (V == kDec4 || V == kDec8) {
+            // at most 4 or 8 bins: the bins of all kDecPixPerThread pixels
+            // are loaded together (their loads in flight at once)
+            constexpr int MB = V == kDec4 ? 4 : 8;
+            C xs[kDecPixPerThread][MB];
+            int gys[kDecPixPerThread], gxs[kDecPixPerThread];
+            bool vals[kDecPixPerThread];
+            unroll_c<kDecPixPerThread>([&](auto qq) {
+                constexpr int Q = decltype(qq)::value;
+                const int p = (pb * kDecPixPerThread + Q) * kDecThreads + threadIdx.x;
+                const int ly = p / T, lx = p - ly * T;
+                gys[Q] = ty * T + ly;
+                gxs[Q] = tx * T + lx;
+                vals[Q] = p < (int)TT && gys[Q] < J.H && gxs[Q] < J.W;
+                const size_t b0 = ypix(vals[Q] ? p : 0, J.ybs);
+                unroll_c<MB>([&](auto mq) {
+                    constexpr int MM = decltype(mq)::value;
+                    xs[Q][MM] = czero<C>();
+                    if (vals[Q] && MM < J.bins) xs[Q][MM] = ldg(X, (size_t)MM * mstride + b0);
+                });
+            });
+            unroll_c<kDecPixPerThread>([&](auto qq) {
+                constexpr int Q = decltype(qq)::value;
+                PxDecode<R> dd;
+                decode_px_regs<R, MB>(xs[Q], (const C *)J.dec, J.dec_pitch, J.nr, (R)J.scale, dd);
+                if (vals[Q]) {
+                    const int d = dd.top < 0 ? 0 : dd.top;
+                    gst(J.out)[(size_t)gys[Q] * J.W + gxs[Q]] = J.op ? (J.L - 1 - d) : d;
+                    run_max = fmaxf(run_max, (float)dd.res);
+                    hit |= px_ambiguous(dd, band, J, gys[Q], gxs[Q]);
+                }
+            });
+        } else {
         // kDecPixPerThread pixels per thread per item amortise the item setup
 #pragma unroll 1
         for (int q = 0; q < kDecPixPerThread; ++q) {
@@ -1405,6 +1470,7 @@ __global__ __launch_bounds__(kDecThreads) void k_decode(const JobDev *__restrict
                 run_max = fmaxf(run_max, (float)dd.res);
                 hit |= px_ambiguous(dd, band, J, gy, gx);
             }
+        }
         }
         // a wave whose pixels fail a check flags the tile (rare); no barrier
         if (__any(hit) && (threadIdx.x & 63) == 0) flag_tile(J, S.job, tile, tile_flags, fb_list, win_list, st);
@@ -2157,6 +2223,7 @@ __global__ __launch_bounds__(kDecThreads) void k_fallback(const JobDev *__restri
                     const bool valid = p < (int)TT && ly < sh && lx < sw;
                     PxDecode<double> dd;
                     switch (decode_variant(J.bins, 1)) {
+                        case kDec4:
                         case kDec8:
                             decode_var<double, kDec8>(slot, TT, p, valid, J.dec64, J.dec_pitch, J.nr, J.bins, J.scale64,
                                                       dd);
@@ -2371,7 +2438,7 @@ int fft_block_threads(int nt, int dbl) {
 
 size_t fft_lds_bytes(int nt, int dbl) {
     const size_t esz = dbl ? sizeof(double2) : sizeof(float2);
-    if (nt > (dbl ? kMaxLdsN64 : kMaxLdsN32)) return (size_t)(4096 / nt) * (nt + 1) * esz;
+    if (nt > (dbl ? kMaxLdsN64 : kMaxLdsN32)) return (size_t)big_lines_of(nt, dbl) * (nt + 1) * esz;
     return (size_t)nt * (nt + 1) * esz;
 }
 
@@ -2561,6 +2628,7 @@ hipError_t launch_decode(int var, int dbl, const JobDev *jobs, const Seg *segs, 
     break
     if (!dbl) {
         switch (var) {
+            case kDec4: MD_DEC(float, kDec4);
             case kDec8: MD_DEC(float, kDec8);
             case kDec12: MD_DEC(float, kDec12);
             case kDec24: MD_DEC(float, kDec24);
@@ -2568,6 +2636,7 @@ hipError_t launch_decode(int var, int dbl, const JobDev *jobs, const Seg *segs, 
         }
     } else {
         switch (var) {
+            case kDec4: MD_DEC(double, kDec4);
             case kDec8: MD_DEC(double, kDec8);
             case kDec12: MD_DEC(double, kDec12);
             default: MD_DEC(double, kDecBlk);

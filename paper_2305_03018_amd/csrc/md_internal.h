@@ -191,6 +191,10 @@ hipError_t launch_fft(int nt, int dbl, const JobDev *jobs, const Seg *segs, int 
 constexpr bool big_tile(int nt, int dbl) { return nt > (dbl ? kMaxLdsN64 : kMaxLdsN32); }
 // Items per chunk of a large-tile launch: intermediates of about 256 MiB
 // (the Infinity Cache), at least one item.
+// lines of one item that a large-tile pass takes through the LDS per block:
+// 4096 points, 32 KiB (FP32) or 64 KiB (FP64); twice that in FP32 measured
+// slower (fewer blocks per CU)
+constexpr int big_lines_of(int nt, int dbl) { return (void)dbl, 4096 / nt; }
 inline long long big_chunk_items(int nt, int dbl, long long nitems) {
     const long long per = (long long)nt * nt * (dbl ? 16 : 8);
     long long c = (256ll << 20) / per;

@@ -679,6 +679,7 @@ double dec_units(int nr, int dbl) {
 
 double dec_padded_bins(int bins, int dbl) {
     switch (decode_group_variant(bins, dbl)) {
+        case 4: return 4;
         case 0: return 8;
         case 1: return 12;
         case 2: return 24;
@@ -1337,10 +1338,10 @@ int build_exec(const md_job *jobs, int n, const std::vector<SEData> &ses, Exec &
             s.item0 = gf->nitems;
             gf->segs.push_back(s);
             gf->nitems += (long long)nt_ * p.bins;
-            // HBM bytes the transform must move: the int32 tile in once per
-            // bin (the encode reads it from HBM or L2) and its valid outputs
-            // out; the SE spectrum is L2/MALL-resident
-            gf->alg_bytes += items * TT * esz + (double)nt_ * N2 * 4.0;
+            // HBM bytes the transform must move: the valid outputs of every
+            // item out, and in the int32 tile once and the SE spectrum of
+            // each bin once (each then serves its other items from L2/MALL)
+            gf->alg_bytes += items * TT * esz + (double)nt_ * N2 * 4.0 + (double)p.bins * N2 * esz;
             // FP: flops of the forward and inverse 2-D FFTs and the product;
             // exact: modular products (one per butterfly and per point)
             gf->alg_ops += ntt ? items * (N2 * log2(N2) + N2) : items * (2.0 * 5.0 * N2 * log2(N2) + 6.0 * N2);
@@ -1390,7 +1391,7 @@ int build_exec(const md_job *jobs, int n, const std::vector<SEData> &ses, Exec &
                 // three passes per chunk of items, each over (item, line batch)
                 // units, through the chunk's intermediates
                 gr.big_chunk = big_chunk_items(gr.nt, gr.dbl, gr.nitems);
-                const long long units = gr.big_chunk * (gr.nt / (4096 / gr.nt));
+                const long long units = gr.big_chunk * (gr.nt / big_lines_of(gr.nt, gr.dbl));
                 gr.grid = occupancy_grid(units, fft_lds_bytes(gr.nt, gr.dbl), fft_block_threads(gr.nt, gr.dbl));
                 slab_groups.push_back({&gr, (size_t)gr.big_chunk * gr.nt * gr.nt *
                                                 (gr.dbl ? sizeof(double2) : sizeof(float2))});
