@@ -1480,14 +1480,12 @@ __global__ __launch_bounds__(kDecThreads) void k_decode(const JobDev *__restrict
 }
 
 // cos(2 pi q / 16) for q in [0, 8]
-__host__ __device__ constexpr double cos16(int q) {
-    return q == 0 ? 1.0
-         : q == 1 ? 0.92387953251128675613
-         : q == 2 ? 0.70710678118654752440
-         : q == 3 ? 0.38268343236508977173
-         : q == 4 ? 0.0
-                  : -cos16(8 - q);
+__host__ __device__ constexpr double cos16q(int q) {   // q in [0, 4]: 0 .. 90 degrees
+    return q == 0 ? 1.0 : q == 1 ? 0.92387953251128675613 : q == 2 ? 0.70710678118654752440
+         : q == 3 ? 0.38268343236508977173 : 0.0;
 }
+// (not recursive, so that every call inlines and folds to a constant)
+__host__ __device__ constexpr double cos16(int q) { return q <= 4 ? cos16q(q) : -cos16q(8 - q); }
 __host__ __device__ constexpr double sin16(int q) { return cos16(q <= 4 ? 4 - q : q - 4); }
 
 // DFT of N <= 16 points held in registers, positive exponent,
@@ -1543,8 +1541,9 @@ __host__ __device__ constexpr double cos24q(int m) {   // m in [0, 6]: 0 .. 90 d
          : m == 5 ? 0.25881904510252076235
                   : 0.0;
 }
-__host__ __device__ constexpr double cos24(int m) {
-    return (m % 24) <= 6 ? cos24q(m % 24) : (m % 24) <= 12 ? -cos24q(12 - m % 24) : -cos24(m % 24 - 12);
+__host__ __device__ constexpr double cos24(int m) {   // not recursive: inlines to a constant
+    return (m % 24) <= 6 ? cos24q(m % 24) : (m % 24) <= 12 ? -cos24q(12 - m % 24)
+         : (m % 24) <= 18 ? -cos24q(m % 24 - 12) : cos24q(24 - m % 24);
 }
 __host__ __device__ constexpr double sin24(int m) { return cos24(m % 24 + 18); }
 
@@ -1593,8 +1592,9 @@ __host__ __device__ constexpr double cos20q(int m) {   // m in [0, 5]: 0 .. 90 d
          : m == 4 ? 0.30901699437494742410
                   : 0.0;
 }
-__host__ __device__ constexpr double cos20(int m) {
-    return (m % 20) <= 5 ? cos20q(m % 20) : (m % 20) <= 10 ? -cos20q(10 - m % 20) : -cos20(m % 20 - 10);
+__host__ __device__ constexpr double cos20(int m) {   // not recursive: inlines to a constant
+    return (m % 20) <= 5 ? cos20q(m % 20) : (m % 20) <= 10 ? -cos20q(10 - m % 20)
+         : (m % 20) <= 15 ? -cos20q(m % 20 - 10) : cos20q(20 - m % 20);
 }
 __host__ __device__ constexpr double sin20(int m) { return cos20(m % 20 + 15); }
 
