@@ -943,10 +943,12 @@ struct XcdWalk {
 };
 
 // Item order of k_fft_reg within a segment: groups of kTileGroup tiles, all
-// bins of a group before the next, bin-major inside the group (the last group
-// takes the remaining tiles).  The blocks of an XCD then share a few image
-// windows and a few bins' SE spectra at a time, both L2-resident, instead of
-// one spectrum and a new image window per item.
+// bins of a group before the next, bin-major inside it (the last group takes
+// the remaining tiles).  The blocks of an XCD then share a few image windows
+// and a few bins' SE spectra at a time, both L2-resident, and a block's
+// consecutive items (kTileGroup divides the walk's stride) are bins of one
+// tile, which it keeps in its grey-value cache.  (A group as wide as the
+// stride, all bins of one tile per block, measured slower.)
 constexpr int kTileGroup = 8;
 __device__ __forceinline__ void tile_group_item(int local, int ntiles, int bins, int &m, int &tl) {
     const int full = ntiles - ntiles % kTileGroup;   // tiles in whole groups
@@ -977,6 +979,9 @@ __global__ __launch_bounds__(4 * N) __attribute__((amdgpu_waves_per_eu(fft_reg_w
     constexpr bool TW_LDS = sizeof(R) == 4 && N >= 64;
     __shared__ C lds[N * P];
     __shared__ TWT tws[TW_LDS ? N : 1];
+    // grey values of the block's current tile window, one byte each, for the
+    // next items of the same tile (a lane reads back only what it wrote)
+    __shared__ uint8_t vcache[N * N];
     const int lane = threadIdx.x & 63, g = lane >> 4;
     const bool g0 = (g & 1) != 0;
     const int line = (threadIdx.x >> 6) * 16 + (lane & 15);   // column (phases 1, 3) or row (phase 2)
@@ -997,6 +1002,8 @@ __global__ __launch_bounds__(4 * N) __attribute__((amdgpu_waves_per_eu(fft_reg_w
     const int frow = g * (E / 4);
     // byte offset of this lane's first spectrum value ([kx][ky], kx = frow + ...)
     const unsigned spec_voff = (unsigned)(frow * N + line) * sizeof(C);
+    long long cached = -1;    // (job, tile) whose grey values vcache holds
+    unsigned inmask = 0;      // in-image bits of this lane's points, for that tile
     XcdWalk walk(nitems);
     for (long long it = walk.it; it < walk.end; it += walk.step) {
         const Seg S = segs[find_seg(segs, nseg, it)];
@@ -1021,23 +1028,68 @@ __global__ __launch_bounds__(4 * N) __attribute__((amdgpu_waves_per_eu(fft_reg_w
             const __amdgpu_buffer_rsrc_t ers =
                 __builtin_amdgcn_make_buffer_rsrc((void *)((const C *)J.enc + (size_t)m * L), (short)0,
                                                   (int)(L * sizeof(C)), kBufWord3);
-            // erosion complements the values: w = (L - 1) - v
-            const int wmul = J.op ? -1 : 1, wadd = J.op ? L - 1 : 0;
+            // erosion complements the values: w = (L - 1) - v = (v ^ -1) + L
+            const unsigned wxor = J.op ? ~0u : 0u, wadd = J.op ? (unsigned)L : 0u;
             int val[E];
             bool in[E];
-            unroll_c<E>([&](auto q) {
-                constexpr int Q = decltype(q)::value;
-                in[Q] = colin && (unsigned)(y0 + 4 * Q) < (unsigned)H;
-                val[Q] = in[Q] ? gld(col)[(ptrdiff_t)(4 * Q) * W] : 0;
-            });
+            const long long npx = (long long)H * W;
+            const long long key = ((long long)S.job << 32) | (unsigned)(S.tile0 + tl);
+            if (key == cached) {
+                // the same tile as the block's previous item: its values
+                // (checked against L when loaded) from the cache
+                unroll_c<E>([&](auto q) {
+                    constexpr int Q = decltype(q)::value;
+                    in[Q] = (inmask >> Q) & 1u;
+                    val[Q] = vcache[(g + 4 * Q) * N + line];
+                });
+            } else if (npx < (1ll << 29) && W <= (1 << 22)) {
+                // the image through a buffer resource: the pixel (y0 + 4 Q, gx)
+                // at byte offset o0 + 16 W Q, in 32-bit unsigned arithmetic.
+                // An in-image pixel lies below 4 H W < 2^31; a row above the
+                // image wraps to [2^31, 2^32), a row below stays under 2^32,
+                // and a column outside the image starts at 2^31: all past the
+                // resource, so their loads return 0 and the offset test marks
+                // them out.
+                const __amdgpu_buffer_rsrc_t irs =
+                    __builtin_amdgcn_make_buffer_rsrc((void *)J.img, (short)0, (int)(npx * 4), kBufWord3);
+                const unsigned o0 = colin ? ((unsigned)y0 * (unsigned)W + (unsigned)gx) * 4u : 0x80000000u;
+                const unsigned step = 16u * (unsigned)W, lim = (unsigned)(npx * 4);
+                unroll_c<E>([&](auto q) {
+                    constexpr int Q = decltype(q)::value;
+                    const unsigned o = o0 + (unsigned)Q * step;
+                    in[Q] = o < lim;
+                    val[Q] = __builtin_amdgcn_raw_buffer_load_b32(irs, o, 0, 0);
+                });
+            } else {
+                unroll_c<E>([&](auto q) {
+                    constexpr int Q = decltype(q)::value;
+                    in[Q] = colin && (unsigned)(y0 + 4 * Q) < (unsigned)H;
+                    val[Q] = in[Q] ? gld(col)[(ptrdiff_t)(4 * Q) * W] : 0;
+                });
+            }
             unsigned top = 0;   // largest in-image value (as unsigned: negatives count as large)
             unroll_c<E>([&](auto q) {
                 constexpr int Q = decltype(q)::value;
                 top = max(top, (unsigned)val[Q]);
-                const unsigned idx = in[Q] ? (unsigned)(wadd + wmul * val[Q]) : (unsigned)L;
+                const unsigned idx = in[Q] ? (((unsigned)val[Q] ^ wxor) + wadd) : (unsigned)L;
                 v[Q] = buf_load<C>(ers, idx * (unsigned)sizeof(C), 0);
             });
-            if (m == 0 && __any(top >= (unsigned)L) && lane == 0) atomicOr(&st->range_err, 1u);
+            if (key != cached) {
+                if (__any(top >= (unsigned)L) && lane == 0) atomicOr(&st->range_err, 1u);
+                // values below L <= 256 fit a byte: keep them for this tile's
+                // next items
+                if (L <= 256) {
+                    inmask = 0;
+                    unroll_c<E>([&](auto q) {
+                        constexpr int Q = decltype(q)::value;
+                        vcache[(g + 4 * Q) * N + line] = (uint8_t)val[Q];
+                        inmask |= (unsigned)in[Q] << Q;
+                    });
+                    cached = key;
+                } else {
+                    cached = -1;
+                }
+            }
         }
         tw_fresh(ltw);
         line_fwd<R, E>(v, ltw, g0);
@@ -2439,7 +2491,9 @@ int fft_block_threads(int nt, int dbl) {
 size_t fft_lds_bytes(int nt, int dbl) {
     const size_t esz = dbl ? sizeof(double2) : sizeof(float2);
     if (nt > (dbl ? kMaxLdsN64 : kMaxLdsN32)) return (size_t)big_lines_of(nt, dbl) * (nt + 1) * esz;
-    return (size_t)nt * (nt + 1) * esz;
+    // k_fft_reg: the tile, the grey-value cache and (FP32 from 64 points) the
+    // lane-twiddle table
+    return (size_t)nt * (nt + 1) * esz + (size_t)nt * nt + (!dbl && nt >= 64 ? (size_t)nt * sizeof(TwF) : 16);
 }
 
 hipError_t launch_add_const(int32_t *out, const int32_t *in, int32_t c, size_t n, hipStream_t s) {
