@@ -942,20 +942,20 @@ struct XcdWalk {
     }
 };
 
-// Item order of k_fft_reg within a segment: groups of kTileGroup tiles, all
-// bins of a group before the next, bin-major inside it (the last group takes
-// the remaining tiles).  The blocks of an XCD then share a few image windows
-// and a few bins' SE spectra at a time, both L2-resident, and a block's
-// consecutive items (kTileGroup divides the walk's stride) are bins of one
-// tile, which it keeps in its grey-value cache.  (A group as wide as the
-// stride, all bins of one tile per block, measured slower.)
-constexpr int kTileGroup = 8;
-__device__ __forceinline__ void tile_group_item(int local, int ntiles, int bins, int &m, int &tl) {
-    const int full = ntiles - ntiles % kTileGroup;   // tiles in whole groups
+// Item order of k_fft_reg within a segment: groups of G tiles, all bins of a
+// group before the next, bin-major inside it (the last group takes the
+// remaining tiles).  With G a quarter of the walk's stride (the blocks of one
+// XCD), a block's consecutive items are every fourth bin of one tile, which
+// it keeps in its grey-value cache, and the XCD's blocks share G image
+// windows and four bins' SE spectra at a time in their L2.  (G equal to the
+// stride, every bin of a tile in one block, measured slower.)
+__device__ __forceinline__ int tile_group_width(long long step) { return step >= 32 ? (int)(step / 4) : 8; }
+__device__ __forceinline__ void tile_group_item(int local, int ntiles, int bins, int G, int &m, int &tl) {
+    const int full = ntiles - ntiles % G;   // tiles in whole groups
     if (local < full * bins) {
-        const int per = bins * kTileGroup, grp = local / per, q = local - grp * per;
-        m = q / kTileGroup;
-        tl = grp * kTileGroup + (q & (kTileGroup - 1));
+        const int per = bins * G, grp = local / per, q = local - grp * per;
+        m = q / G;
+        tl = grp * G + (q - m * G);
     } else {
         const int rem = ntiles - full, q = local - full * bins;
         m = q / rem;
@@ -1002,15 +1002,16 @@ __global__ __launch_bounds__(4 * N) __attribute__((amdgpu_waves_per_eu(fft_reg_w
     const int frow = g * (E / 4);
     // byte offset of this lane's first spectrum value ([kx][ky], kx = frow + ...)
     const unsigned spec_voff = (unsigned)(frow * N + line) * sizeof(C);
+    XcdWalk walk(nitems);
+    const int tgw = tile_group_width(walk.step);
     long long cached = -1;    // (job, tile) whose grey values vcache holds
     unsigned inmask = 0;      // in-image bits of this lane's points, for that tile
-    XcdWalk walk(nitems);
     for (long long it = walk.it; it < walk.end; it += walk.step) {
         const Seg S = segs[find_seg(segs, nseg, it)];
         const JobDev &J = jobs[S.job];
         const int local = (int)(it - S.item0);   // a segment holds fewer than 2^31 items
         int m, tl;
-        tile_group_item(local, S.ntiles, J.bins, m, tl);
+        tile_group_item(local, S.ntiles, J.bins, tgw, m, tl);
         const int tile = S.tile0 + tl;
         const int ty = tile / J.tiles_x, tx = tile - ty * J.tiles_x;
         const int k = J.k, r = (k - 1) >> 1, T = N - k + 1;
@@ -1149,7 +1150,9 @@ __global__ __launch_bounds__(4 * N) __attribute__((amdgpu_waves_per_eu(fft_reg_w
                 // pixel index of row g + 4 Q is q0 + 4 T Q, negative for the
                 // discarded rows, which then take an offset past the resource
                 // and are dropped.  The [bins][T*T] layout is the blocked one
-                // with 16-pixel blocks of pitch 16.
+                // with 16-pixel blocks of pitch 16.  (Jobs on the short-length
+                // decode in the bin-major layout, whose kept rows need no
+                // per-row offset, measured slower.)
                 const size_t te = ytile_elems(J.bins, J.T, J.ybs);
                 const __amdgpu_buffer_rsrc_t ors = __builtin_amdgcn_make_buffer_rsrc(
                     (void *)((C *)S.y + (size_t)tl * te), (short)0, (int)(te * sizeof(C)), kBufWord3);
@@ -2000,7 +2003,8 @@ __device__ __forceinline__ void reg_idft(C (&v)[M]) {
 // FP32 (to 24 in FP64) with no prime factor above 5, except 32: one pixel per
 // thread, all of it in registers.
 // The thread loads the pixel's bins X_0 .. X_M (16-pixel blocks, bins
-// contiguous), packs Z_k = (X_k + conj X_{M-k}) + i w^k (X_k - conj X_{M-k}),
+// contiguous), packs
+// Z_k = (X_k + conj X_{M-k}) + i w^k (X_k - conj X_{M-k}),
 // w = exp(2 pi i / nr), takes the M-point inverse DFT z and reads
 // c_{2n} = scale Re z_n, c_{2n+1} = scale Im z_n (the even and odd samples of
 // the real inverse DFT of the Hermitian spectrum), then Step 3 and the
