@@ -980,8 +980,10 @@ __global__ __launch_bounds__(4 * N) __attribute__((amdgpu_waves_per_eu(fft_reg_w
     __shared__ C lds[N * P];
     __shared__ TWT tws[TW_LDS ? N : 1];
     // grey values of the block's current tile window, one byte each, for the
-    // next items of the same tile (a lane reads back only what it wrote)
-    __shared__ uint8_t vcache[N * N];
+    // next items of the same tile (a lane reads back only what it wrote);
+    // rows padded by a word so that a wave's four rows use distinct banks
+    constexpr int VP = N + 4;
+    __shared__ uint8_t vcache[N * VP];
     const int lane = threadIdx.x & 63, g = lane >> 4;
     const bool g0 = (g & 1) != 0;
     const int line = (threadIdx.x >> 6) * 16 + (lane & 15);   // column (phases 1, 3) or row (phase 2)
@@ -1041,7 +1043,7 @@ __global__ __launch_bounds__(4 * N) __attribute__((amdgpu_waves_per_eu(fft_reg_w
                 unroll_c<E>([&](auto q) {
                     constexpr int Q = decltype(q)::value;
                     in[Q] = (inmask >> Q) & 1u;
-                    val[Q] = vcache[(g + 4 * Q) * N + line];
+                    val[Q] = vcache[(g + 4 * Q) * VP + line];
                 });
             } else if (npx < (1ll << 29) && W <= (1 << 22)) {
                 // the image through a buffer resource: the pixel (y0 + 4 Q, gx)
@@ -1083,7 +1085,7 @@ __global__ __launch_bounds__(4 * N) __attribute__((amdgpu_waves_per_eu(fft_reg_w
                     inmask = 0;
                     unroll_c<E>([&](auto q) {
                         constexpr int Q = decltype(q)::value;
-                        vcache[(g + 4 * Q) * N + line] = (uint8_t)val[Q];
+                        vcache[(g + 4 * Q) * VP + line] = (uint8_t)val[Q];
                         inmask |= (unsigned)in[Q] << Q;
                     });
                     cached = key;
@@ -2497,7 +2499,7 @@ size_t fft_lds_bytes(int nt, int dbl) {
     if (nt > (dbl ? kMaxLdsN64 : kMaxLdsN32)) return (size_t)big_lines_of(nt, dbl) * (nt + 1) * esz;
     // k_fft_reg: the tile, the grey-value cache and (FP32 from 64 points) the
     // lane-twiddle table
-    return (size_t)nt * (nt + 1) * esz + (size_t)nt * nt + (!dbl && nt >= 64 ? (size_t)nt * sizeof(TwF) : 16);
+    return (size_t)nt * (nt + 1) * esz + (size_t)nt * (nt + 4) + (!dbl && nt >= 64 ? (size_t)nt * sizeof(TwF) : 16);
 }
 
 hipError_t launch_add_const(int32_t *out, const int32_t *in, int32_t c, size_t n, hipStream_t s) {
