@@ -1976,7 +1976,12 @@ __device__ __forceinline__ void reg_idft(C (&v)[M]) {
         v[3].x = b2.x + e2.y;   // b2 - i e2
         v[3].y = b2.y - e2.x;
     } else {
-        constexpr int P = M % 2 == 0 ? 2 : M % 3 == 0 ? 3 : 5, Q = M / P;
+        // outer factor: for M = 2^a 3^b 5^c with b + c > 0, 8 or 4 where they
+        // divide M (fewer general turns than a radix-2 split: the turns by
+        // multiples of M / 8 are eighth turns); powers of two split by 2
+        constexpr bool POW2 = (M & (M - 1)) == 0;
+        constexpr int P = !POW2 && M % 8 == 0 ? 8 : !POW2 && M % 4 == 0 ? 4 : M % 2 == 0 ? 2 : M % 3 == 0 ? 3 : 5,
+                      Q = M / P;
         static_assert(P * Q == M && Q > 1, "M must factor into 2, 3 and 5");
         C a[P][Q];
         unroll_c<P>([&](auto r) {

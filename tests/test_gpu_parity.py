@@ -410,6 +410,32 @@ def test_errors(dev):
     assert_parity(job, dev)
 
 
+def test_wide_rows_and_value_cache_bounds(dev):
+    """Image rows wider than 2^22 pixels take the transform's plain image
+    loads instead of the 32-bit buffer offsets; grey ranges up to 256 keep a
+    tile's values in the per-block byte cache, wider ones reload them; a value
+    past the range (256 with L = 256, which the byte cache would wrap to 0)
+    is still reported."""
+    import torch
+
+    rng = np.random.default_rng(47)
+    wide = synthetic.random_job(rng, 3, (1 << 22) + 37, 16, 5, p=0.7, max_off=3)
+    want = oracle.run_job(wide)
+    for opts in (FFT32, FFT64):
+        _say(f"  wide rows {opts}")
+        assert_parity(wide, dev, want=want, **opts)
+    for L in (256, 257):
+        job = synthetic.random_job(rng, 150, 170, L, 9, p=0.6, max_off=6, op=L % 2)
+        assert_parity(job, dev, tile=32, **FFT32)
+    job = synthetic.random_job(rng, 100, 120, 256, 7, p=0.6, max_off=5)
+    bad = torch.from_numpy(job.img).to(dev)
+    bad[57, 33] = 256
+    for opts in (FFT32, FFT64):
+        with md.options(**opts), pytest.raises(md.MDError) as ei:
+            md.dilate(bad, job.mask, job.off, 256)
+        assert ei.value.code == -2
+
+
 # ----------------------------------------------------------------------------
 # transform-domain values against the FP64 reference
 # ----------------------------------------------------------------------------
