@@ -136,7 +136,8 @@ def kernel_of(stage):
     if stage.startswith("fft"):
         prec, n = ("float" if stage.startswith("fft32") else "double"), int(stage.split("_n")[1])
         big = n > (128 if prec == "float" else 64)
-        return f"k_fft_big<{prec}, {n}>" if big else f"k_fft_reg<{prec}, {n}>"
+        lanes = 8 if (prec == "float" and n == 128) else 4   # lanes per tile line
+        return f"k_fft_big<{prec}, {n}>" if big else f"k_fft_reg<{prec}, {n}, {lanes}>"
     if stage == "decode_ntt":
         return "k_ntt_decode"
     if stage.startswith("ntt"):

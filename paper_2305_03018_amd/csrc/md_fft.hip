@@ -917,6 +917,119 @@ __device__ __forceinline__ void line_inv(C (&v)[E], const TWS &ltw, bool g0) {
     reg_fft<R, E, true>(v);
 }
 
+// Eight lanes per line (lanes 8 apart, E = N / 8 points each): the same
+// Cooley-Tukey split with G = 8, its 8-point DFT across the lanes as three
+// radix-2 stages over the lane-part bits (lanes 32, 16 and 8 apart).  With
+// g = 4 g2 + 2 g1 + g0 and k2 = k2a + 2 k2b + 4 k2c,
+//   w_8^(g k2) = (-1)^(g2 k2a) w_4^(g1 k2a) (-1)^(g1 k2b) w_8^(g0 (k2a + 2 k2b)) (-1)^(g0 k2c),
+// so the turn before the second stage is -i (k2a = 1) and before the third
+// w_8^(k2a + 2 k2b), each on the operand that the exchange brings from the
+// part with that bit set, a compile-time turn per register.  Lane part g then
+// holds k1 in [g E/8, (g+1) E/8) for every k2: register
+// s = j + (E/8) k2c + (E/4) k2b + (E/2) k2a has k = j + g E/8 + E k2.
+template <int E>
+__device__ __forceinline__ constexpr int line_freq8_c(int s) {
+    return (s % (E / 8)) + E * ((s / (E / 2)) + 2 * ((s / (E / 4)) % 2) + 4 * ((s / (E / 8)) % 2));
+}
+
+// Exchange across lanes 8 apart (the same semantics as lane_swap<32/16>),
+// through a row rotation by 8 of the 16-lane DPP rows: each lane sends the
+// value its partner keeps and takes the partner's.
+__device__ __forceinline__ void lane_swap8_32(uint32_t &a, uint32_t &b, bool hi) {
+    const uint32_t t = hi ? a : b;
+    const uint32_t r = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)t, 0x128, 0xf, 0xf, false);   // row_ror:8
+    a = hi ? r : a;
+    b = hi ? b : r;
+}
+__device__ __forceinline__ void lane_swap8(float2 &a, float2 &b, bool hi) {
+    uint32_t ax = __float_as_uint(a.x), ay = __float_as_uint(a.y), bx = __float_as_uint(b.x), by = __float_as_uint(b.y);
+    lane_swap8_32(ax, bx, hi);
+    lane_swap8_32(ay, by, hi);
+    a.x = __uint_as_float(ax); a.y = __uint_as_float(ay); b.x = __uint_as_float(bx); b.y = __uint_as_float(by);
+}
+
+// Forward transform of one line held as v[e] = x[g + 8 e] (lane part g, lanes
+// 8 apart; hi: bit 0 of g); afterwards v[s] = X[line_freq8_c<E>(s) + g E / 8].
+template <typename R, int E, typename C, typename TWS>
+__device__ __forceinline__ void line_fwd8(C (&v)[E], const TWS &ltw, bool hi) {
+    reg_fft<R, E, false>(v);
+    unroll_c<E - 1>([&](auto q) {
+        constexpr int K1 = decltype(q)::value + 1;
+        v[K1] = ltw.template mul<false>(ic<K1>{}, v[K1]);
+    });
+    // lane-part bit 2 (lanes 32 apart): k2a
+    unroll_c<E / 2>([&](auto q) {
+        constexpr int J = decltype(q)::value;
+        lane_swap<32>(v[J], v[J + E / 2]);
+        const C a = v[J], b = v[J + E / 2];
+        v[J] = cadd(a, b);
+        v[J + E / 2] = csub(a, b);
+    });
+    // bit 1 (lanes 16 apart): k2b, after the turn -i of k2a = 1
+    unroll_c<E / 2>([&](auto q) {
+        constexpr int Q = decltype(q)::value, J = Q % (E / 4) + (Q / (E / 4)) * (E / 2);
+        lane_swap<16>(v[J], v[J + E / 4]);
+        const C a = v[J];
+        C b = v[J + E / 4];
+        if constexpr (J >= E / 2) {
+            const R t = b.x;
+            b.x = b.y;
+            b.y = -t;
+        }
+        v[J] = cadd(a, b);
+        v[J + E / 4] = csub(a, b);
+    });
+    // bit 0 (lanes 8 apart): k2c, after the turn w_8^(k2a + 2 k2b)
+    unroll_c<E / 2>([&](auto q) {
+        constexpr int Q = decltype(q)::value, J = Q % (E / 8) + (Q / (E / 8)) * (E / 4);
+        constexpr int TW = (J / (E / 2)) + 2 * ((J / (E / 4)) % 2);
+        lane_swap8(v[J], v[J + E / 8], hi);
+        const C a = v[J];
+        const C b = twc<R, TW, 8, false>(v[J + E / 8]);
+        v[J] = cadd(a, b);
+        v[J + E / 8] = csub(a, b);
+    });
+}
+
+// Inverse (unnormalised) of line_fwd8: takes v[s] = X[line_freq8_c<E>(s) + g E / 8],
+// leaves v[e] = N x[g + 8 e].
+template <typename R, int E, typename C, typename TWS>
+__device__ __forceinline__ void line_inv8(C (&v)[E], const TWS &ltw, bool hi) {
+    unroll_c<E / 2>([&](auto q) {
+        constexpr int Q = decltype(q)::value, J = Q % (E / 8) + (Q / (E / 8)) * (E / 4);
+        constexpr int TW = (J / (E / 2)) + 2 * ((J / (E / 4)) % 2);
+        const C a = v[J], b = v[J + E / 8];
+        v[J] = cadd(a, b);
+        v[J + E / 8] = twc<R, TW, 8, true>(csub(a, b));
+        lane_swap8(v[J], v[J + E / 8], hi);
+    });
+    unroll_c<E / 2>([&](auto q) {
+        constexpr int Q = decltype(q)::value, J = Q % (E / 4) + (Q / (E / 4)) * (E / 2);
+        const C a = v[J], b = v[J + E / 4];
+        v[J] = cadd(a, b);
+        C d = csub(a, b);
+        if constexpr (J >= E / 2) {   // * (+i)
+            const R t = d.x;
+            d.x = -d.y;
+            d.y = t;
+        }
+        v[J + E / 4] = d;
+        lane_swap<16>(v[J], v[J + E / 4]);
+    });
+    unroll_c<E / 2>([&](auto q) {
+        constexpr int J = decltype(q)::value;
+        const C a = v[J], b = v[J + E / 2];
+        v[J] = cadd(a, b);
+        v[J + E / 2] = csub(a, b);
+        lane_swap<32>(v[J], v[J + E / 2]);
+    });
+    unroll_c<E - 1>([&](auto q) {
+        constexpr int K1 = decltype(q)::value + 1;
+        v[K1] = ltw.template mul<true>(ic<K1>{}, v[K1]);
+    });
+    reg_fft<R, E, true>(v);
+}
+
 // XCD-aware walk of a persistent launch's items.  Workgroups are dealt to the
 // eight XCDs in turn (workgroup b to XCD b mod 8), each XCD with its own L2.
 // Striding the items by the grid would put consecutive items -- the tiles of
@@ -964,17 +1077,22 @@ __device__ __forceinline__ void tile_group_item(int local, int ntiles, int bins,
 }
 
 // waves per SIMD asked of k_fft_reg: the LDS allows four 64-point FP32 blocks
-// (16 waves) per CU, and with the twiddle table in LDS they fit 128 VGPRs
-template <typename R, int N> constexpr int fft_reg_waves() { return sizeof(R) == 4 && N == 64 ? 4 : 1; }
+// (16 waves) per CU, and with the twiddle table in LDS they fit 128 VGPRs; the
+// 128-point FP32 block of eight lanes per line is 16 waves, 4 per SIMD
+template <typename R, int N, int G> constexpr int fft_reg_waves() {
+    return sizeof(R) == 4 && (N == 64 || G == 8) ? 4 : 1;
+}
 
-template <typename R, int N>
-__global__ __launch_bounds__(4 * N) __attribute__((amdgpu_waves_per_eu(fft_reg_waves<R, N>()))) void k_fft_reg(const JobDev *__restrict__ jobs, const Seg *__restrict__ segs,
+// G lanes per line: 4 (lanes 16 apart), or 8 (lanes 8 apart, line_fwd8).
+template <typename R, int N, int G = 4>
+__global__ __launch_bounds__(G * N) __attribute__((amdgpu_waves_per_eu(fft_reg_waves<R, N, G>()))) void k_fft_reg(const JobDev *__restrict__ jobs, const Seg *__restrict__ segs,
                                                    int nseg, long long nitems, const TwF *__restrict__ tw32,
                                                    const double2 *__restrict__ tw64, StatsDev *st,
                                                    const uint8_t *__restrict__ perturb) {
     using C = typename Cx<R>::T;
-    constexpr int E = N / 4, P = N + 1;
-    static_assert(E >= 4 && (E & (E - 1)) == 0, "E = N / 4 must be a power of two >= 4");
+    static_assert(G == 4 || G == 8, "four or eight lanes per line");
+    constexpr int E = N / G, P = N + 1, LW = 64 / G;   // points per lane, lines per wave
+    static_assert(E >= 4 && (E & (E - 1)) == 0 && (G == 4 || E >= 8), "E = N / G must be a power of two");
     using TWT = typename std::conditional<sizeof(R) == 4, TwF, double2>::type;
     constexpr bool TW_LDS = sizeof(R) == 4 && N >= 64;
     __shared__ C lds[N * P];
@@ -984,16 +1102,21 @@ __global__ __launch_bounds__(4 * N) __attribute__((amdgpu_waves_per_eu(fft_reg_w
     // rows padded by a word so that a wave's four rows use distinct banks
     constexpr int VP = N + 4;
     __shared__ uint8_t vcache[N * VP];
-    const int lane = threadIdx.x & 63, g = lane >> 4;
+    const int lane = threadIdx.x & 63, g = lane / LW;
     const bool g0 = (g & 1) != 0;
-    const int line = (threadIdx.x >> 6) * 16 + (lane & 15);   // column (phases 1, 3) or row (phase 2)
-    const int lbase = (threadIdx.x >> 6) * 16;                 // first line of this wave
+    const int line = (threadIdx.x >> 6) * LW + (lane & (LW - 1));   // column (phases 1, 3) or row (phase 2)
+    const int lbase = (threadIdx.x >> 6) * LW;                       // first line of this wave
+    // the frequency of register s after a forward line transform (plus g E / G)
+    auto lfreq = [](auto q) constexpr {
+        constexpr int Qv = decltype(q)::value;
+        return G == 4 ? line_freq_c<E>(Qv) : line_freq8_c<E>(Qv);
+    };
     const TWT *twg;
     if constexpr (sizeof(R) == 4) twg = tw32; else twg = tw64;
     // w_N^(g k1), k1 < E
     typename std::conditional<TW_LDS, LdsTw<R, N>, RegTw<R, E>>::type ltw;
     if constexpr (TW_LDS) {
-        for (int j = threadIdx.x; j < N; j += 4 * N) tws[j] = twg[j * (kTwN / N)];
+        for (int j = threadIdx.x; j < N; j += G * N) tws[j] = twg[j * (kTwN / N)];
         ltw.t = (const __attribute__((address_space(3))) TWT *)tws;
         ltw.g = g;
         __syncthreads();
@@ -1001,7 +1124,7 @@ __global__ __launch_bounds__(4 * N) __attribute__((amdgpu_waves_per_eu(fft_reg_w
         ltw.init(twg, g, kTwN / N);
     }
     // LDS row of register s in phases 1 and 3: the frequency it holds
-    const int frow = g * (E / 4);
+    const int frow = g * (E / G);
     // byte offset of this lane's first spectrum value ([kx][ky], kx = frow + ...)
     const unsigned spec_voff = (unsigned)(frow * N + line) * sizeof(C);
     XcdWalk walk(nitems);
@@ -1043,11 +1166,11 @@ __global__ __launch_bounds__(4 * N) __attribute__((amdgpu_waves_per_eu(fft_reg_w
                 unroll_c<E>([&](auto q) {
                     constexpr int Q = decltype(q)::value;
                     in[Q] = (inmask >> Q) & 1u;
-                    val[Q] = vcache[(g + 4 * Q) * VP + line];
+                    val[Q] = vcache[(g + G * Q) * VP + line];
                 });
             } else if (npx < (1ll << 29) && W <= (1 << 22)) {
-                // the image through a buffer resource: the pixel (y0 + 4 Q, gx)
-                // at byte offset o0 + 16 W Q, in 32-bit unsigned arithmetic.
+                // the image through a buffer resource: the pixel (y0 + G Q, gx)
+                // at byte offset o0 + 4 G W Q, in 32-bit unsigned arithmetic.
                 // An in-image pixel lies below 4 H W < 2^31; a row above the
                 // image wraps to [2^31, 2^32), a row below stays under 2^32,
                 // and a column outside the image starts at 2^31: all past the
@@ -1056,7 +1179,7 @@ __global__ __launch_bounds__(4 * N) __attribute__((amdgpu_waves_per_eu(fft_reg_w
                 const __amdgpu_buffer_rsrc_t irs =
                     __builtin_amdgcn_make_buffer_rsrc((void *)J.img, (short)0, (int)(npx * 4), kBufWord3);
                 const unsigned o0 = colin ? ((unsigned)y0 * (unsigned)W + (unsigned)gx) * 4u : 0x80000000u;
-                const unsigned step = 16u * (unsigned)W, lim = (unsigned)(npx * 4);
+                const unsigned step = 4u * G * (unsigned)W, lim = (unsigned)(npx * 4);
                 unroll_c<E>([&](auto q) {
                     constexpr int Q = decltype(q)::value;
                     const unsigned o = o0 + (unsigned)Q * step;
@@ -1066,8 +1189,8 @@ __global__ __launch_bounds__(4 * N) __attribute__((amdgpu_waves_per_eu(fft_reg_w
             } else {
                 unroll_c<E>([&](auto q) {
                     constexpr int Q = decltype(q)::value;
-                    in[Q] = colin && (unsigned)(y0 + 4 * Q) < (unsigned)H;
-                    val[Q] = in[Q] ? gld(col)[(ptrdiff_t)(4 * Q) * W] : 0;
+                    in[Q] = colin && (unsigned)(y0 + G * Q) < (unsigned)H;
+                    val[Q] = in[Q] ? gld(col)[(ptrdiff_t)(G * Q) * W] : 0;
                 });
             }
             unsigned top = 0;   // largest in-image value (as unsigned: negatives count as large)
@@ -1085,7 +1208,7 @@ __global__ __launch_bounds__(4 * N) __attribute__((amdgpu_waves_per_eu(fft_reg_w
                     inmask = 0;
                     unroll_c<E>([&](auto q) {
                         constexpr int Q = decltype(q)::value;
-                        vcache[(g + 4 * Q) * VP + line] = (uint8_t)val[Q];
+                        vcache[(g + G * Q) * VP + line] = (uint8_t)val[Q];
                         inmask |= (unsigned)in[Q] << Q;
                     });
                     cached = key;
@@ -1095,19 +1218,19 @@ __global__ __launch_bounds__(4 * N) __attribute__((amdgpu_waves_per_eu(fft_reg_w
             }
         }
         tw_fresh(ltw);
-        line_fwd<R, E>(v, ltw, g0);
+        if constexpr (G == 4) line_fwd<R, E>(v, ltw, g0); else line_fwd8<R, E>(v, ltw, g0);
         unroll_c<E>([&](auto q) {
             constexpr int Q = decltype(q)::value;
-            lds[(frow + line_freq_c<E>(Q)) * P + line] = v[Q];
+            lds[(frow + lfreq(ic<Q>{})) * P + line] = v[Q];
         });
         __syncthreads();
         // 2. rows: forward along x, times the SE spectrum, inverse along x
         unroll_c<E>([&](auto q) {
             constexpr int Q = decltype(q)::value;
-            v[Q] = lds[line * P + g + 4 * Q];
+            v[Q] = lds[line * P + g + G * Q];
         });
         tw_fresh(ltw);
-        line_fwd<R, E>(v, ltw, g0);
+        if constexpr (G == 4) line_fwd<R, E>(v, ltw, g0); else line_fwd8<R, E>(v, ltw, g0);
         {
             // spectrum values through a buffer resource: one offset register
             // per lane, the compile-time steps as uniform offsets; loads in
@@ -1121,7 +1244,7 @@ __global__ __launch_bounds__(4 * N) __attribute__((amdgpu_waves_per_eu(fft_reg_w
                 C sv[SG];
                 unroll_c<SG>([&](auto q) {
                     constexpr int Q = Q0 + decltype(q)::value;
-                    sv[Q - Q0] = buf_load<C>(srs, spec_voff, (unsigned)(line_freq_c<E>(Q) * N * sizeof(C)));
+                    sv[Q - Q0] = buf_load<C>(srs, spec_voff, (unsigned)(lfreq(ic<Q>{}) * N * sizeof(C)));
                 });
                 unroll_c<SG>([&](auto q) {
                     constexpr int Q = Q0 + decltype(q)::value;
@@ -1130,26 +1253,26 @@ __global__ __launch_bounds__(4 * N) __attribute__((amdgpu_waves_per_eu(fft_reg_w
             });
         }
         tw_fresh(ltw);
-        line_inv<R, E>(v, ltw, g0);
+        if constexpr (G == 4) line_inv<R, E>(v, ltw, g0); else line_inv8<R, E>(v, ltw, g0);
         unroll_c<E>([&](auto q) {
             constexpr int Q = decltype(q)::value;
-            lds[line * P + g + 4 * Q] = v[Q];
+            lds[line * P + g + G * Q] = v[Q];
         });
         __syncthreads();
         // 3. columns: inverse along y and the valid outputs (rows and columns
         // >= k - 1); waves whose columns all lie left of them skip it
-        if (lbase + 15 >= k - 1) {
+        if (lbase + LW - 1 >= k - 1) {
             unroll_c<E>([&](auto q) {
                 constexpr int Q = decltype(q)::value;
-                v[Q] = lds[(frow + line_freq_c<E>(Q)) * P + line];
+                v[Q] = lds[(frow + lfreq(ic<Q>{})) * P + line];
             });
             tw_fresh(ltw);
-            line_inv<R, E>(v, ltw, g0);
+            if constexpr (G == 4) line_inv<R, E>(v, ltw, g0); else line_inv8<R, E>(v, ltw, g0);
             const R bump = perturb_bump<R>(perturb, J, tile, m, kPerturbFirst);
             const int oc = line - (k - 1);
             if (oc >= 0) {
                 // stores through a buffer resource over the tile's values; the
-                // pixel index of row g + 4 Q is q0 + 4 T Q, negative for the
+                // pixel index of row g + G Q is q0 + G T Q, negative for the
                 // discarded rows, which then take an offset past the resource
                 // and are dropped.  The [bins][T*T] layout is the blocked one
                 // with 16-pixel blocks of pitch 16.  (Jobs on the short-length
@@ -1163,7 +1286,7 @@ __global__ __launch_bounds__(4 * N) __attribute__((amdgpu_waves_per_eu(fft_reg_w
                 const int q0 = (g - (k - 1)) * T + oc;
                 unroll_c<E>([&](auto q) {
                     constexpr int Q = decltype(q)::value;
-                    const int qq = q0 + 4 * Q * T;
+                    const int qq = q0 + G * Q * T;
                     const unsigned e = (unsigned)(binoff + (qq >> 4) * ybs + (qq & 15));
                     C o = v[Q];
                     o.x += bump;
@@ -2492,9 +2615,9 @@ __global__ void k_or_flag(uint32_t *dst, const uint32_t *src) {
 // ---------------------------------------------------------------------------
 int fft_block_threads(int nt, int dbl) {
     if (nt > (dbl ? kMaxLdsN64 : kMaxLdsN32)) return nt <= kMaxN ? kBigThreads : 0;
-    // k_fft_reg: four lanes per line of the tile
+    // k_fft_reg: four or eight lanes per line of the tile
     switch (nt) {
-        case 16: case 32: case 64: case 128: return 4 * nt;
+        case 16: case 32: case 64: case 128: return fft_reg_lanes(nt, dbl) * nt;
         default: return 0;
     }
 }
@@ -2571,7 +2694,8 @@ hipError_t launch_fft(int nt, int dbl, const JobDev *jobs, const Seg *segs, int 
                       StatsDev *st, const uint8_t *perturb, hipStream_t s) {
     if (nitems <= 0) return hipSuccess;
 #define MD_FFT_CASE(R, N) \
-    k_fft_reg<R, N><<<grid, 4 * N, 0, s>>>(jobs, segs, nseg, nitems, tw32, tw64, st, perturb); break;
+    k_fft_reg<R, N, fft_reg_lanes(N, sizeof(R) == 8)><<<grid, fft_reg_lanes(N, sizeof(R) == 8) * N, 0, s>>>( \
+        jobs, segs, nseg, nitems, tw32, tw64, st, perturb); break;
 #define MD_FFT_BIG(R, N)                                                                                        \
     for (long long c0 = 0; c0 < nitems; c0 += big_chunk) {                                                      \
         const int cn = (int)std::min<long long>(big_chunk, nitems - c0);                                        \

@@ -191,6 +191,10 @@ hipError_t launch_fft(int nt, int dbl, const JobDev *jobs, const Seg *segs, int 
 constexpr bool big_tile(int nt, int dbl) { return nt > (dbl ? kMaxLdsN64 : kMaxLdsN32); }
 // Items per chunk of a large-tile launch: intermediates of about 256 MiB
 // (the Infinity Cache), at least one item.
+// lanes per tile line in k_fft_reg: eight for the 128-point FP32 tile (16
+// waves per block, 4 per SIMD, where four lanes of 32 points would leave 2),
+// four otherwise
+constexpr int fft_reg_lanes(int nt, int dbl) { return !dbl && nt == 128 ? 8 : 4; }
 // lines of one item that a large-tile pass takes through the LDS per block:
 // 4096 points, 32 KiB (FP32) or 64 KiB (FP64); twice that in FP32 measured
 // slower (fewer blocks per CU)

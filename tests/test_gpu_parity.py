@@ -448,18 +448,18 @@ def test_spectrum_error_report(dev, nr):
 
     job = synthetic.blurred_512(0)
     img = torch.from_numpy(job.img).to(dev)
-    nt = 64
-    T = nt - job.k + 1
-    ty, tx = 2, 3
-    ys, xs = np.divmod(np.arange(T * T), T)
-    counts = oracle.counts_at(job.img, job.mask, job.off, ty * T + ys, tx * T + xs, nr)
-    ref = oracle.range_spectrum_ref(counts, nr).T           # (bins, T*T)
-    for prec, tol in ((0, 2e-5), (1, 1e-12)):
-        got = md.debug_tile_values(img, job.mask, job.off, job.L, nt, nr, prec, ty, tx)
-        rel = np.linalg.norm(got - ref) / np.linalg.norm(ref)
-        mx = np.abs(got - ref).max()
-        _say(f"  precision={prec}: relative L2 {rel:.3e}, max abs {mx:.3e}")
-        assert rel < tol
+    for nt in (64, 128):   # four and (FP32) eight lanes per tile line
+        T = nt - job.k + 1
+        ty, tx = 2, 3
+        ys, xs = np.divmod(np.arange(T * T), T)
+        counts = oracle.counts_at(job.img, job.mask, job.off, ty * T + ys, tx * T + xs, nr)
+        ref = oracle.range_spectrum_ref(counts, nr).T           # (bins, T*T)
+        for prec, tol in ((0, 2e-5), (1, 1e-12)):
+            got = md.debug_tile_values(img, job.mask, job.off, job.L, nt, nr, prec, ty, tx)
+            rel = np.linalg.norm(got - ref) / np.linalg.norm(ref)
+            mx = np.abs(got - ref).max()
+            _say(f"  nt={nt} precision={prec}: relative L2 {rel:.3e}, max abs {mx:.3e}")
+            assert rel < tol
 
 
 def test_ntt_exact_counts(dev):
