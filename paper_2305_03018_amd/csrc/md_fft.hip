@@ -1091,7 +1091,11 @@ __global__ __launch_bounds__(G * N) __attribute__((amdgpu_waves_per_eu(fft_reg_w
                                                    const uint8_t *__restrict__ perturb) {
     using C = typename Cx<R>::T;
     static_assert(G == 4 || G == 8, "four or eight lanes per line");
-    constexpr int E = N / G, P = N + 1, LW = 64 / G;   // points per lane, lines per wave
+    // points per lane, lines per wave; LDS row pitch P (complex values): with
+    // eight lanes per line a 16-lane group spans 8 lines and 2 lane parts, and
+    // N + 4 puts both its row accesses (line P + g + 8 e) and its column
+    // accesses ((2 g + f) P + line) in 32 distinct banks
+    constexpr int E = N / G, P = G == 8 ? N + 4 : N + 1, LW = 64 / G;
     static_assert(E >= 4 && (E & (E - 1)) == 0 && (G == 4 || E >= 8), "E = N / G must be a power of two");
     using TWT = typename std::conditional<sizeof(R) == 4, TwF, double2>::type;
     constexpr bool TW_LDS = sizeof(R) == 4 && N >= 64;
@@ -2627,7 +2631,8 @@ size_t fft_lds_bytes(int nt, int dbl) {
     if (nt > (dbl ? kMaxLdsN64 : kMaxLdsN32)) return (size_t)big_lines_of(nt, dbl) * (nt + 1) * esz;
     // k_fft_reg: the tile, the grey-value cache and (FP32 from 64 points) the
     // lane-twiddle table
-    return (size_t)nt * (nt + 1) * esz + (size_t)nt * (nt + 4) + (!dbl && nt >= 64 ? (size_t)nt * sizeof(TwF) : 16);
+    const size_t pitch = fft_reg_lanes(nt, dbl) == 8 ? nt + 4 : nt + 1;
+    return (size_t)nt * pitch * esz + (size_t)nt * (nt + 4) + (!dbl && nt >= 64 ? (size_t)nt * sizeof(TwF) : 16);
 }
 
 hipError_t launch_add_const(int32_t *out, const int32_t *in, int32_t c, size_t n, hipStream_t s) {
