@@ -694,8 +694,45 @@ __device__ __forceinline__ C twc(C x) {
 // In-register DFT of E points, natural order in and out:
 // y_s = sum_r v_r exp(-+2 pi i r s / E).  Radix-2 decimation in time after a
 // bit reversal that full unrolling turns into register renaming.
+// 4-point DFT in place, exp(-+2 pi i / 4) = -+i as operand swaps
+template <bool INV, typename C>
+__device__ __forceinline__ void dft4(C &a, C &b, C &c, C &d) {
+    const C t0 = cadd(a, c), t1 = csub(a, c), t2 = cadd(b, d), u = csub(b, d);
+    C t3;   // (b - d) * (-i) forward, * (+i) inverse
+    if (INV) { t3.x = -u.y; t3.y = u.x; } else { t3.x = u.y; t3.y = -u.x; }
+    a = cadd(t0, t2);
+    c = csub(t0, t2);
+    b = cadd(t1, t3);
+    d = csub(t1, t3);
+}
+
 template <typename R, int E, bool INV, typename C>
 __device__ __forceinline__ void reg_fft(C (&v)[E]) {
+    if constexpr (E == 16) {
+        // 16 = 4 x 4: n = r + 4 m, k = s + 4 t; four 4-point DFTs over m,
+        // the turns w_16^(r s) (4 general, 4 eighth, 1 quarter: fewer than
+        // the radix-2 split's 8 general and 6 eighth), four over r
+        unroll_c<4>([&](auto rr) {
+            constexpr int Rr = decltype(rr)::value;
+            dft4<INV>(v[Rr], v[Rr + 4], v[Rr + 8], v[Rr + 12]);   // A[r][s] at v[r + 4 s]
+            unroll_c<3>([&](auto ss) {
+                constexpr int Ss = decltype(ss)::value + 1;
+                v[Rr + 4 * Ss] = twc<R, Rr * Ss, 16, INV>(v[Rr + 4 * Ss]);
+            });
+        });
+        C w[16];
+        unroll_c<4>([&](auto ss) {
+            constexpr int Ss = decltype(ss)::value;
+            C a = v[4 * Ss], b = v[4 * Ss + 1], c = v[4 * Ss + 2], d = v[4 * Ss + 3];
+            dft4<INV>(a, b, c, d);   // X[s + 4 t]
+            w[Ss] = a;
+            w[Ss + 4] = b;
+            w[Ss + 8] = c;
+            w[Ss + 12] = d;
+        });
+        unroll_c<16>([&](auto q) { v[decltype(q)::value] = w[decltype(q)::value]; });
+        return;
+    }
     constexpr int LE = ilog2c(E);
     unroll_c<E>([&](auto i) {
         constexpr int I = decltype(i)::value, J = brevc(I, LE);
