@@ -1385,13 +1385,20 @@ __device__ __forceinline__ bool px_ambiguous(const PxDecode<R> &dd, float band, 
 // global memory between passes.  A launch handles a chunk of `cn` items
 // starting at `it0` (the chunk's intermediates are small enough to stay in
 // the L2 and Infinity Cache between the passes):
-//   PH 0: encode LB image rows (bit-reversed columns), forward DIT along x,
-//         store row i at intermediate row brev(i) (the columns then hold
-//         bit-reversed input for the DIT along y);
-//   PH 1: LB columns: forward DIT along y, times the SE spectrum
-//         ([kx][ky]), inverse DIF along y (row r' then holds output row
-//         brev(r')), stored back;
-//   PH 2: LB rows: inverse DIF along x and the T x T valid outputs.
+//   PH 0: encode LB image rows in column order, forward DIF along x
+//         (column c then holds kx = brev(c)), store row i at intermediate
+//         row brev(i) (the columns then hold bit-reversed input for the DIT
+//         along y);
+//   PH 1: LB columns c: forward DIT along y, times the SE spectrum row
+//         kx = brev(c) ([kx][ky]), inverse DIF along y (row r' then holds
+//         output row brev(r')), stored back for the kept rows
+//         brev(r') >= k - 1 only;
+//   PH 2: LB kept output rows y = k - 1 + b LB + l (intermediate row
+//         brev(y)): inverse DIT along x (bit-reversed kx in, x in column
+//         order out) and the T x T valid outputs; the batches past the last
+//         kept row return at once.
+// Every LDS walk outside the butterflies is in column order: a bit-reversed
+// LDS index would put the lanes of a wavefront on a few banks.
 // Work units are (item, batch) pairs, item-major, walked per XCD (XcdWalk),
 // so that the blocks of one XCD share an item's image rows, intermediate
 // lines and spectrum in their L2.
@@ -1424,12 +1431,12 @@ __global__ __launch_bounds__(kBigThreads) void k_fft_big(const JobDev *__restric
         if constexpr (PH == 0) {
             const int rb = b * LB;
             const C *enc_m = (const C *)J.enc + (size_t)m * J.L;
-            const int bad = encode_rows<R, N, BS, CH, kEncLdsOrder<R, N>>(
+            const int bad = encode_rows<R, N, BS, CH, false>(
                 LB, J.img, J.H, J.W, J.L, J.op, ty * J.T - r + rb, tx * J.T - r, enc_m,
-                [&](int l, int c, C v) { lds[l * P + (kEncLdsOrder<R, N> ? c : brev<LG>(c))] = v; });
+                [&](int l, int c, C v) { lds[l * P + c] = v; });
             if (m == 0 && bad) atomicOr(&st->range_err, 1u);
             __syncthreads();
-            dit_axis<R, N, 0, BS, false, LB>(lds, tw);
+            dif_axis<R, N, 0, BS, false, LB>(lds, tw);
             for (int q = threadIdx.x; q < LB * N; q += BS) {
                 const int l = q >> LG, v = q & (N - 1);
                 stg(slab, (size_t)brev<LG>(rb + l) * N + v, lds[l * P + v]);
@@ -1444,7 +1451,7 @@ __global__ __launch_bounds__(kBigThreads) void k_fft_big(const JobDev *__restric
             dit_axis<R, N, 0, BS, false, LB>(lds, tw);
             // the spectrum is stored [kx][ky]: q walks ky fastest
             batched<BS, CH>(
-                LB * N, [&](int q) { return ldg(spec_m, (size_t)(cb + (q >> LG)) * N + (q & (N - 1))); },
+                LB * N, [&](int q) { return ldg(spec_m, (size_t)brev<LG>(cb + (q >> LG)) * N + (q & (N - 1))); },
                 [&](int q, C sv) {
                     C *e = lds + (q >> LG) * P + (q & (N - 1));
                     *e = cmul(*e, sv);
@@ -1453,37 +1460,31 @@ __global__ __launch_bounds__(kBigThreads) void k_fft_big(const JobDev *__restric
             dif_axis<R, N, 0, BS, true, LB>(lds, tw);
             for (int q = threadIdx.x; q < LB * N; q += BS) {
                 const int rr = q >> LLB, l = q & (LB - 1);
-                stg(slab, (size_t)rr * N + cb + l, lds[l * P + rr]);
+                if (brev<LG>(rr) >= k - 1) stg(slab, (size_t)rr * N + cb + l, lds[l * P + rr]);
             }
         } else {
-            // intermediate row rb + l is output row y = brev(rb + l)
-            const int rb = b * LB;
+            // line l is output row y0 + l, intermediate row brev(y0 + l); the
+            // lines of a last, partial batch past row N - 1 re-read row N - 1
+            // and are not stored
+            const int y0 = k - 1 + b * LB;
+            if (y0 >= N) continue;   // block-uniform: the whole block skips the unit
             C *ydst = (C *)S.y + (size_t)tl * ytile_elems(J.bins, J.T, J.ybs) + ybin_offset(m, J.T, J.ybs);
             const R bump = perturb_bump<R>(perturb, J, tile, m, kPerturbFirst);
             batched<BS, CH>(
-                LB * N, [&](int q) { return ldg(slab, (size_t)(rb + (q >> LG)) * N + (q & (N - 1))); },
+                LB * N,
+                [&](int q) {
+                    const int y = min(y0 + (q >> LG), N - 1);
+                    return ldg(slab, (size_t)brev<LG>(y) * N + (q & (N - 1)));
+                },
                 [&](int q, C v) { lds[(q >> LG) * P + (q & (N - 1))] = v; });
             __syncthreads();
-            dif_axis<R, N, 0, BS, true, LB>(lds, tw);
-            if constexpr (kOutLdsOrder<R>) {
-                for (int q = threadIdx.x; q < LB * N; q += BS) {
-                    const int l = q >> LG, bb = q & (N - 1);
-                    const int y = brev<LG>(rb + l), x = brev<LG>(bb);
-                    if (y >= k - 1 && x >= k - 1) {
-                        C v = lds[l * P + bb];
-                        v.x += bump;
-                        stg(ydst, ypix((size_t)(y - (k - 1)) * T + (x - (k - 1)), J.ybs), v);
-                    }
-                }
-            } else {
-                for (int q = threadIdx.x; q < LB * T; q += BS) {
-                    const int l = q / T, xo = q - l * T;
-                    const int y = brev<LG>(rb + l);
-                    if (y >= k - 1) {
-                        C v = lds[l * P + brev<LG>(xo + k - 1)];
-                        v.x += bump;
-                        stg(ydst, ypix((size_t)(y - (k - 1)) * T + xo, J.ybs), v);
-                    }
+            dit_axis<R, N, 0, BS, true, LB>(lds, tw);
+            for (int q = threadIdx.x; q < LB * T; q += BS) {
+                const int l = q / T, xo = q - l * T;
+                if (y0 + l < N) {
+                    C v = lds[l * P + xo + k - 1];
+                    v.x += bump;
+                    stg(ydst, ypix((size_t)(y0 + l - (k - 1)) * T + xo, J.ybs), v);
                 }
             }
         }
