@@ -1399,9 +1399,10 @@ __device__ __forceinline__ bool px_ambiguous(const PxDecode<R> &dd, float band, 
 //         kept row return at once.
 // Every LDS walk outside the butterflies is in column order: a bit-reversed
 // LDS index would put the lanes of a wavefront on a few banks.
-// Work units are (item, batch) pairs, item-major, walked per XCD (XcdWalk),
-// so that the blocks of one XCD share an item's image rows, intermediate
-// lines and spectrum in their L2.
+// Work units are (item, batch) pairs, walked per XCD (XcdWalk): item-major
+// in PH 0 and 2, so that the blocks of one XCD share an item's image rows
+// and intermediate lines in their L2; in PH 1 in pairs of batches, each
+// pair over every item (see there).
 template <typename R, int N, int PH>
 __global__ __launch_bounds__(kBigThreads) void k_fft_big(const JobDev *__restrict__ jobs, const Seg *__restrict__ segs,
                                                          int nseg, long long it0, int cn, const TwF *__restrict__ tw32,
@@ -1409,6 +1410,7 @@ __global__ __launch_bounds__(kBigThreads) void k_fft_big(const JobDev *__restric
                                                          const uint8_t *__restrict__ perturb) {
     using C = typename Cx<R>::T;
     constexpr int BS = kBigThreads, LB = big_lines<R, N>(), NB = N / LB;
+    static_assert(NB % 2 == 0, "the column pass walks batches in pairs");
     constexpr int P = N + 1, LG = ilog2c(N), LLB = ilog2c(LB);
     constexpr int CHM = sizeof(R) == 4 ? 4 : 16;
     constexpr int CH = LB * N / BS < CHM ? LB * N / BS : CHM;
@@ -1418,7 +1420,19 @@ __global__ __launch_bounds__(kBigThreads) void k_fft_big(const JobDev *__restric
     const long long units = (long long)cn * NB;
     XcdWalk walk(units);
     for (long long u = walk.it; u < walk.end; u += walk.step) {
-        const int i = (int)(u / NB), b = (int)(u - (long long)i * NB);
+        int i, b;
+        if constexpr (PH == 1) {
+            // pairs of column batches (whole 128-byte lines of the
+            // intermediate rows), every item of the chunk per pair: an XCD's
+            // blocks then share each pair's slice of the spectra in their L2
+            const long long pr = u / (2 * cn);
+            const int rem = (int)(u - pr * 2 * cn);
+            i = rem >> 1;
+            b = (int)pr * 2 + (rem & 1);
+        } else {
+            i = (int)(u / NB);
+            b = (int)(u - (long long)i * NB);
+        }
         const long long it = it0 + i;
         const Seg S = segs[find_seg(segs, nseg, it)];
         const JobDev &J = jobs[S.job];
