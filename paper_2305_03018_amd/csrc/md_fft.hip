@@ -1116,6 +1116,36 @@ __device__ __forceinline__ void tile_group_item(int local, int ntiles, int bins,
 // waves per SIMD asked of k_fft_reg: the LDS allows four 64-point FP32 blocks
 // (16 waves) per CU, and with the twiddle table in LDS they fit 128 VGPRs; the
 // 128-point FP32 block of eight lanes per line is 16 waves, 4 per SIMD
+// Number of SE cells y whose window pixel x - y lies in the image, for the
+// pixel (gy, gx): the count of active cells (a, c) of the effective mask with
+// a in [gy + r - H + 1, gy + r] and c in [gx + r - W + 1, gx + r], from the
+// mask's prefix counts.  Every such pair adds 1 to exactly one coefficient of
+// the pixel's product polynomial (Sec. 3.1), so the coefficients sum to it.
+__device__ __forceinline__ int window_cells(const JobDev &J, int gy, int gx) {
+    const int k = J.k, r = (k - 1) >> 1, kp = k + 1;
+    const int a0 = max(0, gy + r - J.H + 1), a1 = min(k - 1, gy + r);
+    const int c0 = max(0, gx + r - J.W + 1), c1 = min(k - 1, gx + r);
+    if (a0 > a1 || c0 > c1) return 0;
+    const auto P = gld(J.se_cnt);
+    return P[(a1 + 1) * kp + c1 + 1] - P[a0 * kp + c1 + 1] - P[(a1 + 1) * kp + c0] + P[a0 * kp + c0];
+}
+
+// Bin 0 of every (tile, bin) item has a closed form.  At m = 0 the
+// range-DFT column of every in-image grey value is 1 and that of every SE
+// cell is 1 (Step 1), so the bin-0 product at a pixel is the count of SE
+// cells whose window pixel lies in the image, window_cells, and the
+// unscaled inverse 2-D transform holds nt^2 times it: an integer times a
+// power of two, exact in either precision.  The transform kernels write
+// that plane instead of transforming the item (the FP64 recompute of a
+// flagged tile still transforms every bin).
+template <typename R>
+__device__ __forceinline__ typename Cx<R>::T dc_plane_value(const JobDev &J, int nt, int gy, int gx, R bump) {
+    typename Cx<R>::T o;
+    o.x = (R)((double)nt * nt) * (R)window_cells(J, gy, gx) + bump;
+    o.y = R(0);
+    return o;
+}
+
 template <typename R, int N, int G> constexpr int fft_reg_waves() {
     return sizeof(R) == 4 && (N == 64 || G == 8) ? 4 : 1;
 }
@@ -1182,6 +1212,17 @@ __global__ __launch_bounds__(G * N) __attribute__((amdgpu_waves_per_eu(fft_reg_w
         const int ty = tile / J.tiles_x, tx = tile - ty * J.tiles_x;
         const int k = J.k, r = (k - 1) >> 1, T = N - k + 1;
         const int iy0 = ty * J.T - r, ix0 = tx * J.T - r;
+        if (m == 0) {
+            // bin 0 in closed form (block-uniform; no LDS use, so the next
+            // item needs no barrier after it)
+            C *yt = (C *)S.y + (size_t)tl * ytile_elems(J.bins, J.T, J.ybs) + ybin_offset(0, J.T, J.ybs);
+            const R bump = perturb_bump<R>(perturb, J, tile, 0, kPerturbFirst);
+            for (int q = threadIdx.x; q < T * T; q += G * N) {
+                const int i = q / T, j = q - i * T;
+                stg(yt, ypix(q, J.ybs), dc_plane_value<R>(J, N, ty * J.T + i, tx * J.T + j, bump));
+            }
+            continue;
+        }
         // 1. columns: encode (Step 1) and forward transform along y.  The
         // range-DFT column of grey value w is read through a buffer resource
         // of the L table entries: an out-of-image pixel takes index L, past
@@ -1357,19 +1398,6 @@ struct PxDecode {
     }
 };
 
-// Number of SE cells y whose window pixel x - y lies in the image, for the
-// pixel (gy, gx): the count of active cells (a, c) of the effective mask with
-// a in [gy + r - H + 1, gy + r] and c in [gx + r - W + 1, gx + r], from the
-// mask's prefix counts.  Every such pair adds 1 to exactly one coefficient of
-// the pixel's product polynomial (Sec. 3.1), so the coefficients sum to it.
-__device__ __forceinline__ int window_cells(const JobDev &J, int gy, int gx) {
-    const int k = J.k, r = (k - 1) >> 1, kp = k + 1;
-    const int a0 = max(0, gy + r - J.H + 1), a1 = min(k - 1, gy + r);
-    const int c0 = max(0, gx + r - J.W + 1), c1 = min(k - 1, gx + r);
-    if (a0 > a1 || c0 > c1) return 0;
-    const auto P = gld(J.se_cnt);
-    return P[(a1 + 1) * kp + c1 + 1] - P[a0 * kp + c1 + 1] - P[(a1 + 1) * kp + c0] + P[a0 * kp + c0];
-}
 
 // Whether a decoded pixel fails the exactness checks (band: the residual
 // bound of the pass).
@@ -1442,6 +1470,24 @@ __global__ __launch_bounds__(kBigThreads) void k_fft_big(const JobDev *__restric
         const int ty = tile / J.tiles_x, tx = tile - ty * J.tiles_x;
         const int k = J.k, r = (k - 1) >> 1, T = N - k + 1;
         C *slab = (C *)mid + (size_t)i * N * N;
+        if (m == 0) {
+            // bin 0 in closed form, written by the row pass (block-uniform;
+            // no LDS use, so the next unit needs no barrier after it)
+            if constexpr (PH == 2) {
+                const int y0 = k - 1 + b * LB;
+                C *ydst = (C *)S.y + (size_t)tl * ytile_elems(J.bins, J.T, J.ybs) + ybin_offset(0, J.T, J.ybs);
+                const R bump = perturb_bump<R>(perturb, J, tile, 0, kPerturbFirst);
+                for (int q = threadIdx.x; q < LB * T; q += BS) {
+                    const int l = q / T, xo = q - l * T, y = y0 + l;
+                    if (y < N) {
+                        const int yo = y - (k - 1);
+                        stg(ydst, ypix((size_t)yo * T + xo, J.ybs),
+                            dc_plane_value<R>(J, N, ty * J.T + yo, tx * J.T + xo, bump));
+                    }
+                }
+            }
+            continue;
+        }
         if constexpr (PH == 0) {
             const int rb = b * LB;
             const C *enc_m = (const C *)J.enc + (size_t)m * J.L;

@@ -943,7 +943,8 @@ double fft_cost(const md_job &j, int nt, int nr, int dbl, bool lone = false) {
     const int bins = nr / 2 + 1;
     const double item = g.cost.fft_item[dbl][ilog2i(nt)];
     if (item <= 0) return INFINITY;
-    double items = (double)tiles * bins;
+    // bin 0 is written in closed form (its plane is priced with the decode)
+    double items = (double)tiles * (bins - 1);
     if (lone) items = std::max(items, lone_items(nt, dbl));
     return items * item + (double)tiles * T * T * dec_units(nr, dbl) * g.cost.dec_unit[dbl];
 }
@@ -1328,6 +1329,9 @@ int build_exec(const md_job *jobs, int n, const std::vector<SEData> &ses, Exec &
             const bool ntt = p.dbl == kPrecNTT;
             const double esz = (double)elem_bytes(p.dbl), N2 = (double)p.nt * p.nt, TT = (double)p.T * p.T;
             const double items = (double)nt_ * p.bins;
+            // items the transform kernels transform: bin 0 of the floating-
+            // point paths is written in closed form instead
+            const double fitems = ntt ? items : (double)nt_ * (p.bins - 1);
             // pixels of these tiles that lie inside the image
             double inside = 0;
             for (int t = tile0; t < tile0 + nt_; ++t) {
@@ -1340,12 +1344,14 @@ int build_exec(const md_job *jobs, int n, const std::vector<SEData> &ses, Exec &
             gf->nitems += (long long)nt_ * p.bins;
             // HBM bytes the transform must move: the valid outputs of every
             // item out, and in the int32 tile once and the SE spectrum of
-            // each bin once (each then serves its other items from L2/MALL)
-            gf->alg_bytes += items * TT * esz + (double)nt_ * N2 * 4.0 + (double)p.bins * N2 * esz;
+            // each transformed bin once (each then serves its other items
+            // from L2/MALL)
+            gf->alg_bytes += items * TT * esz + (fitems > 0 ? (double)nt_ * N2 * 4.0 : 0.0) +
+                             (fitems / nt_) * N2 * esz;
             // FP: flops of the forward and inverse 2-D FFTs and the product;
             // exact: modular products (one per butterfly and per point)
-            gf->alg_ops += ntt ? items * (N2 * log2(N2) + N2) : items * (2.0 * 5.0 * N2 * log2(N2) + 6.0 * N2);
-            gf->units += items;
+            gf->alg_ops += ntt ? items * (N2 * log2(N2) + N2) : fitems * (2.0 * 5.0 * N2 * log2(N2) + 6.0 * N2);
+            gf->units += fitems;
             gf->pixels += inside;
             gf->vol_elems += items * TT;
             const int dvar = ntt ? 0 : p.dec_fft ? decode_fft_var(p.nr) : decode_group_variant(p.bins, p.dbl);
