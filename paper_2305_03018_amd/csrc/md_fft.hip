@@ -1137,7 +1137,9 @@ __device__ __forceinline__ int window_cells(const JobDev &J, int gy, int gx) {
 // unscaled inverse 2-D transform holds nt^2 times it: an integer times a
 // power of two, exact in either precision.  The transform kernels write
 // that plane instead of transforming the item (the FP64 recompute of a
-// flagged tile still transforms every bin).
+// flagged tile still transforms every bin).  L >= 2, so n_r >= 2 and every
+// tile has a transformed bin whose encode checks the tile's values against
+// [0, L-1].
 template <typename R>
 __device__ __forceinline__ typename Cx<R>::T dc_plane_value(const JobDev &J, int nt, int gy, int gx, R bump) {
     typename Cx<R>::T o;
@@ -1494,7 +1496,7 @@ __global__ __launch_bounds__(kBigThreads) void k_fft_big(const JobDev *__restric
             const int bad = encode_rows<R, N, BS, CH, false>(
                 LB, J.img, J.H, J.W, J.L, J.op, ty * J.T - r + rb, tx * J.T - r, enc_m,
                 [&](int l, int c, C v) { lds[l * P + c] = v; });
-            if (m == 0 && bad) atomicOr(&st->range_err, 1u);
+            if (bad) atomicOr(&st->range_err, 1u);   // every transformed bin checks its rows
             __syncthreads();
             dif_axis<R, N, 0, BS, false, LB>(lds, tw);
             for (int q = threadIdx.x; q < LB * N; q += BS) {

@@ -387,10 +387,12 @@ def test_errors(dev):
     img = torch.from_numpy(job.img).to(dev)
     bad = img.clone()
     bad[3, 5] = 16
-    for opts in (FFT32, FFT64, DIRECT):
+    # the range check on every transform form: LDS-resident tiles and the
+    # large-tile passes (whose bin-0 items are written in closed form)
+    for opts in (FFT32, FFT64, DIRECT, dict(FFT32, tile=256), dict(FFT64, tile=128), dict(FFT64, tile=256)):
         with md.options(**opts), pytest.raises(md.MDError) as ei:
             md.dilate(bad, job.mask, job.off, 16)
-        assert ei.value.code == -2
+        assert ei.value.code == -2, opts
     neg = job.off.copy()
     neg[0, 0] = -1
     with pytest.raises(md.MDError) as ei:
@@ -450,16 +452,20 @@ def test_spectrum_error_report(dev, nr):
     img = torch.from_numpy(job.img).to(dev)
     for nt in (64, 128):   # four and (FP32) eight lanes per tile line
         T = nt - job.k + 1
-        ty, tx = 2, 3
-        ys, xs = np.divmod(np.arange(T * T), T)
-        counts = oracle.counts_at(job.img, job.mask, job.off, ty * T + ys, tx * T + xs, nr)
-        ref = oracle.range_spectrum_ref(counts, nr).T           # (bins, T*T)
-        for prec, tol in ((0, 2e-5), (1, 1e-12)):
-            got = md.debug_tile_values(img, job.mask, job.off, job.L, nt, nr, prec, ty, tx)
-            rel = np.linalg.norm(got - ref) / np.linalg.norm(ref)
-            mx = np.abs(got - ref).max()
-            _say(f"  nt={nt} precision={prec}: relative L2 {rel:.3e}, max abs {mx:.3e}")
-            assert rel < tol
+        for ty, tx in ((2, 3), (0, 0)):   # an inner tile and a corner tile (partial windows)
+            ys, xs = np.divmod(np.arange(T * T), T)
+            counts = oracle.counts_at(job.img, job.mask, job.off, ty * T + ys, tx * T + xs, nr)
+            ref = oracle.range_spectrum_ref(counts, nr).T           # (bins, T*T)
+            for prec, tol in ((0, 2e-5), (1, 1e-12)):
+                got = md.debug_tile_values(img, job.mask, job.off, job.L, nt, nr, prec, ty, tx)
+                rel = np.linalg.norm(got - ref) / np.linalg.norm(ref)
+                mx = np.abs(got - ref).max()
+                _say(f"  nt={nt} tile=({ty},{tx}) precision={prec}: relative L2 {rel:.3e}, max abs {mx:.3e}")
+                assert rel < tol
+                # bin 0 is the sum of the pixel's exact coefficients (the DFT at
+                # m = 0), written in closed form: equal in every precision
+                assert np.array_equal(got[0].real, counts.sum(axis=1).astype(np.float64))
+                assert not got[0].imag.any()
 
 
 def test_ntt_exact_counts(dev):
