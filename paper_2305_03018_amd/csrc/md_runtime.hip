@@ -1732,8 +1732,11 @@ int autotune_body() {
         g.cost.dir_cell[1] = y3 > 0 ? y3 / s15.dir_cells[1] : 2 * cc;
     }
     // FFT lengths: SE side nt/8*2+1 up to 33 (the item cost does not depend
-    // on it; the spectrum build does)
-    auto side_for = [](int nt, int prec) { return nt >= 512 ? 4096 : nt > (prec ? kMaxLdsN64 : kMaxLdsN32) ? 2048 : 1024; };
+    // on it; the spectrum build does), on images that give every resident
+    // block many items (2048^2: at 128 points about 40 per CU; on 1024^2
+    // the last round's tail inflated the 128-point cost against the 64-point
+    // one by some 5%, which sent jobs to the slower 64-point plans)
+    auto side_for = [](int nt, int prec) { return (void)prec, nt >= 512 ? 4096 : 2048; };
     for (int prec = 0; prec < 2; ++prec) {
         const std::string pre = prec ? "fft64_n" : "fft32_n";
         for (int nt = 16; nt <= kMaxN; nt *= 2) {
