@@ -1733,7 +1733,7 @@ int autotune_body() {
     }
     // FFT lengths: SE side nt/8*2+1 up to 33 (the item cost does not depend
     // on it; the spectrum build does), on images that give every resident
-    // block many items (2048^2: at 128 points about 40 per CU; on 1024^2
+    // block many items (2048^2: at 128 points tens per CU; on 1024^2
     // the last round's tail inflated the 128-point cost against the 64-point
     // one by some 5%, which sent jobs to the slower 64-point plans)
     auto side_for = [](int nt, int prec) { return (void)prec, nt >= 512 ? 4096 : 2048; };
