@@ -1428,7 +1428,8 @@ __device__ __forceinline__ bool px_ambiguous(const PxDecode<R> &dd, float band, 
 //         order out) and the T x T valid outputs; the batches past the last
 //         kept row return at once.
 // Every LDS walk outside the butterflies is in column order: a bit-reversed
-// LDS index would put the lanes of a wavefront on a few banks.
+// LDS index would put the lanes of a wavefront on a few banks.  Bin-0 items
+// skip PH 0 and 1; PH 2 writes their closed-form plane (dc_plane_value).
 // Work units are (item, batch) pairs, walked per XCD (XcdWalk): item-major
 // in PH 0 and 2, so that the blocks of one XCD share an item's image rows
 // and intermediate lines in their L2; in PH 1 in pairs of batches, each
@@ -1452,9 +1453,10 @@ __global__ __launch_bounds__(kBigThreads) void k_fft_big(const JobDev *__restric
     for (long long u = walk.it; u < walk.end; u += walk.step) {
         int i, b;
         if constexpr (PH == 1) {
-            // pairs of column batches (whole 128-byte lines of the
-            // intermediate rows), every item of the chunk per pair: an XCD's
-            // blocks then share each pair's slice of the spectra in their L2
+            // pairs of column batches (at 512 points in FP32, whole 128-byte
+            // lines of the intermediate rows), every item of the chunk per
+            // pair: an XCD's blocks then share each pair's slice of the
+            // spectra in their L2
             const long long pr = u / (2 * cn);
             const int rem = (int)(u - pr * 2 * cn);
             i = rem >> 1;
