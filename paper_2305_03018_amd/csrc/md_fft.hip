@@ -1448,11 +1448,26 @@ __global__ __launch_bounds__(kBigThreads) void k_fft_big(const JobDev *__restric
     __shared__ C lds[LB * P];
     typename TwSel<R>::T tw;
     if constexpr (sizeof(R) == 4) tw.p = tw32; else tw.p = tw64;
-    const long long units = (long long)cn * NB;
-    XcdWalk walk(units);
+    // PH 0 and 2 deal the items to the XCDs in turn (item s to XCD s mod 8,
+    // its NB batches consecutive there): items are bin-major, so contiguous
+    // ranges would leave the XCDs holding the bin-0 items (no transform)
+    // idle.  PH 1 walks contiguous ranges of its batch-pair order, which
+    // spans every item.
+    const int grid = gridDim.x, xcd = blockIdx.x & 7;
+    const bool deal = PH != 1 && grid % 8 == 0;
+    XcdWalk walk((long long)cn * NB);
+    if (deal) {
+        walk.it = blockIdx.x >> 3;
+        walk.end = (long long)((cn - xcd + 7) / 8) * NB;   // items xcd + 8 q
+        walk.step = grid >> 3;
+    }
     for (long long u = walk.it; u < walk.end; u += walk.step) {
         int i, b;
-        if constexpr (PH == 1) {
+        if (deal) {
+            const long long q = u / NB;
+            i = xcd + 8 * (int)q;
+            b = (int)(u - q * NB);
+        } else if constexpr (PH == 1) {
             // pairs of column batches (at 512 points in FP32, whole 128-byte
             // lines of the intermediate rows), every item of the chunk per
             // pair: an XCD's blocks then share each pair's slice of the
