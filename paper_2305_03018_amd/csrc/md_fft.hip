@@ -1208,6 +1208,10 @@ __global__ __launch_bounds__(G * N) __attribute__((amdgpu_waves_per_eu(fft_reg_w
         const Seg S = segs[find_seg(segs, nseg, it)];
         const JobDev &J = jobs[S.job];
         const int local = (int)(it - S.item0);   // a segment holds fewer than 2^31 items
+        // bin 0 of a tile is an item of its own, written in closed form:
+        // the blocks walk the items in a fixed stride, so a cheap item only
+        // lets its block finish early (bin 0 written with bin 1 made that
+        // block the last one)
         int m, tl;
         tile_group_item(local, S.ntiles, J.bins, tgw, m, tl);
         const int tile = S.tile0 + tl;
@@ -1428,8 +1432,9 @@ __device__ __forceinline__ bool px_ambiguous(const PxDecode<R> &dd, float band, 
 //         order out) and the T x T valid outputs; the batches past the last
 //         kept row return at once.
 // Every LDS walk outside the butterflies is in column order: a bit-reversed
-// LDS index would put the lanes of a wavefront on a few banks.  Bin-0 items
-// skip PH 0 and 1; PH 2 writes their closed-form plane (dc_plane_value).
+// LDS index would put the lanes of a wavefront on a few banks.  The items
+// are bins 1 .. bins - 1; PH 2 writes bin 0's closed-form plane
+// (dc_plane_value) with bin 1.
 // Work units are (item, batch) pairs, walked per XCD (XcdWalk): item-major
 // in PH 0 and 2, so that the blocks of one XCD share an item's image rows
 // and intermediate lines in their L2; in PH 1 in pairs of batches, each
@@ -1449,10 +1454,10 @@ __global__ __launch_bounds__(kBigThreads) void k_fft_big(const JobDev *__restric
     typename TwSel<R>::T tw;
     if constexpr (sizeof(R) == 4) tw.p = tw32; else tw.p = tw64;
     // PH 0 and 2 deal the items to the XCDs in turn (item s to XCD s mod 8,
-    // its NB batches consecutive there): items are bin-major, so contiguous
-    // ranges would leave the XCDs holding the bin-0 items (no transform)
-    // idle.  PH 1 walks contiguous ranges of its batch-pair order, which
-    // spans every item.
+    // its NB batches consecutive there), so that items of unequal cost (PH 2
+    // writes bin 0's plane with bin 1; edge tiles keep fewer rows) spread
+    // over all of them.  PH 1 walks contiguous ranges of its batch-pair
+    // order, which spans every item.
     const int grid = gridDim.x, xcd = blockIdx.x & 7;
     const bool deal = PH != 1 && grid % 8 == 0;
     XcdWalk walk((long long)cn * NB);
@@ -1484,29 +1489,13 @@ __global__ __launch_bounds__(kBigThreads) void k_fft_big(const JobDev *__restric
         const Seg S = segs[find_seg(segs, nseg, it)];
         const JobDev &J = jobs[S.job];
         const int local = (int)(it - S.item0);   // a segment holds fewer than 2^31 items
-        const int m = local / S.ntiles, tl = local - m * S.ntiles;
+        // the items are bins 1 .. bins - 1 of each tile (bin-major); bin 0,
+        // in closed form, is written by PH 2 with bin 1
+        const int mi = local / S.ntiles, tl = local - mi * S.ntiles, m = mi + 1;
         const int tile = S.tile0 + tl;
         const int ty = tile / J.tiles_x, tx = tile - ty * J.tiles_x;
         const int k = J.k, r = (k - 1) >> 1, T = N - k + 1;
         C *slab = (C *)mid + (size_t)i * N * N;
-        if (m == 0) {
-            // bin 0 in closed form, written by the row pass (block-uniform;
-            // no LDS use, so the next unit needs no barrier after it)
-            if constexpr (PH == 2) {
-                const int y0 = k - 1 + b * LB;
-                C *ydst = (C *)S.y + (size_t)tl * ytile_elems(J.bins, J.T, J.ybs) + ybin_offset(0, J.T, J.ybs);
-                const R bump = perturb_bump<R>(perturb, J, tile, 0, kPerturbFirst);
-                for (int q = threadIdx.x; q < LB * T; q += BS) {
-                    const int l = q / T, xo = q - l * T, y = y0 + l;
-                    if (y < N) {
-                        const int yo = y - (k - 1);
-                        stg(ydst, ypix((size_t)yo * T + xo, J.ybs),
-                            dc_plane_value<R>(J, N, ty * J.T + yo, tx * J.T + xo, bump));
-                    }
-                }
-            }
-            continue;
-        }
         if constexpr (PH == 0) {
             const int rb = b * LB;
             const C *enc_m = (const C *)J.enc + (size_t)m * J.L;
@@ -1547,6 +1536,19 @@ __global__ __launch_bounds__(kBigThreads) void k_fft_big(const JobDev *__restric
             // and are not stored
             const int y0 = k - 1 + b * LB;
             if (y0 >= N) continue;   // block-uniform: the whole block skips the unit
+            if (m == 1) {
+                // the same rows of bin 0's plane (global stores only)
+                C *d0 = (C *)S.y + (size_t)tl * ytile_elems(J.bins, J.T, J.ybs) + ybin_offset(0, J.T, J.ybs);
+                const R bump0 = perturb_bump<R>(perturb, J, tile, 0, kPerturbFirst);
+                for (int q = threadIdx.x; q < LB * T; q += BS) {
+                    const int l = q / T, xo = q - l * T, y = y0 + l;
+                    if (y < N) {
+                        const int yo = y - (k - 1);
+                        stg(d0, ypix((size_t)yo * T + xo, J.ybs),
+                            dc_plane_value<R>(J, N, ty * J.T + yo, tx * J.T + xo, bump0));
+                    }
+                }
+            }
             C *ydst = (C *)S.y + (size_t)tl * ytile_elems(J.bins, J.T, J.ybs) + ybin_offset(m, J.T, J.ybs);
             const R bump = perturb_bump<R>(perturb, J, tile, m, kPerturbFirst);
             batched<BS, CH>(

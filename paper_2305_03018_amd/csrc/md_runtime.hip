@@ -1341,7 +1341,9 @@ int build_exec(const md_job *jobs, int n, const std::vector<SEData> &ses, Exec &
             Group *gf = find_group(wv.fft, p.nt, p.dbl, 0);
             s.item0 = gf->nitems;
             gf->segs.push_back(s);
-            gf->nitems += (long long)nt_ * p.bins;
+            // the large-tile kernel has no bin-0 items (it writes bin 0 with
+            // bin 1); the LDS-resident one keeps them as cheap items
+            gf->nitems += (long long)nt_ * (!ntt && big_tile(p.nt, p.dbl) ? p.bins - 1 : p.bins);
             // HBM bytes the transform must move: the valid outputs of every
             // item out, and in the int32 tile once and the SE spectrum of
             // each transformed bin once (each then serves its other items
