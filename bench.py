@@ -151,11 +151,13 @@ def kernel_of(stage):
     return stage
 
 
-def measured_traffic(kernel, workload):
+def measured_traffic(kernel, workload, with_alg=False):
     """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
     record (FETCH_SIZE and WRITE_SIZE, scaled by the copy-probe factors), or
     None when there is no record or the kernel source changed since it was
-    taken."""
+    taken.  With `with_alg`, (bytes, algorithmic bytes of the profiled
+    launch or None): the autotuner's tile mix, and so the bytes per launch,
+    follow each box's calibration, so the ratio is what carries over."""
     import hashlib
 
     inst = kernel.replace("<", "_").replace(">", "").replace(", ", "_")
@@ -172,9 +174,12 @@ def measured_traffic(kernel, workload):
             rec[key] = val
     src = os.path.join(ROOT, rec["source"])
     if not os.path.exists(src) or hashlib.sha256(open(src, "rb").read()).hexdigest() != rec["source_sha256"]:
-        return None
-    return 1024.0 * (float(rec["fetch_kib"]) * float(rec["fetch_scale"]) +
-                     float(rec["write_kib"]) * float(rec["write_scale"]))
+        return (None, None) if with_alg else None
+    b = 1024.0 * (float(rec["fetch_kib"]) * float(rec["fetch_scale"]) +
+                  float(rec["write_kib"]) * float(rec["write_scale"]))
+    if with_alg:
+        return b, (float(rec["alg_bytes"]) if "alg_bytes" in rec else None)
+    return b
 
 
 def roofline_for(stage, prof, workload, launch_ms=None):
@@ -185,9 +190,15 @@ def roofline_for(stage, prof, workload, launch_ms=None):
     ops = rec["alg_ops"] / rec["launches"]
     achieved = ops / (per_launch_ms * 1e-3) / 1e12
     kernel = kernel_of(stage)
-    base = {"achieved": achieved, "traffic": measured_traffic(kernel, workload), "kernel": kernel,
+    traffic, traffic_alg = measured_traffic(kernel, workload, with_alg=True)
+    base = {"achieved": achieved, "traffic": traffic, "kernel": kernel,
             "stage": stage, "avg_launch_ms": per_launch_ms,
             "alg_bytes_per_launch": rec["alg_bytes"] / rec["launches"]}
+    if traffic is not None and traffic_alg:
+        # the profiled launch's algorithmic bytes and the counted/algorithmic
+        # ratio (the tile mix of this run may differ)
+        base["traffic_alg_bytes"] = traffic_alg
+        base["traffic_ratio"] = traffic / traffic_alg
     if stage.startswith("direct"):
         peak = (F16X2_ADDMAX_TOPS if stage in ("direct16", "direct3_16") else
                 INT16X2_ALU_TOPS if stage in ("direct16i", "direct3_16i") else INT32_ALU_TOPS)
@@ -260,7 +271,7 @@ def volume_leg(md, torch, dev, stream, steps):
             raise SystemExit(f"bench: volume parity failure ({name})")
         res[name] = {"ms": ms, "mvoxels_s": nvox / (ms * 1e-3) / 1e6, "path": "direct" if st["path"] == 2 else "ntt",
                      "n_t": st["n_t"], "n_r": st["n_r"],
-                     "stages": {k: {q: v for q, v in roofline_for(k, sp, "volume").items() if q != "traffic"}
+                     "stages": {k: {q: v for q, v in roofline_for(k, sp, "volume").items() if not q.startswith("traffic")}
                                 for k in sp if sp[k]["alg_ops"] > 0}}
         log(f"bench: volume {name} {ms:.3f} ms ({res[name]['mvoxels_s']:.0f} Mvoxel/s)")
     return res
@@ -635,7 +646,7 @@ def main():
                              "stats": {k: st[k] for k in ("fft_jobs", "direct_jobs", "tiles", "fallback_tiles",
                                                           "window_tiles", "max_residual")},
                              "stages": {q: {k: v for k, v in roofline_for(q, sp, args.workload).items()
-                                            if k != "traffic"} for q in sp if sp[q]["alg_ops"] > 0}}
+                                            if not k.startswith("traffic")} for q in sp if sp[q]["alg_ops"] > 0}}
                 if name == "fft32_recompute_all":
                     rec = {q: v for q, v in sp.items() if q.startswith("recompute")}
                     ms_rec = sum(v["ms"] for v in rec.values()) / 2
@@ -672,7 +683,7 @@ def main():
                    "precision": "fp32 split twiddles; exact tiers: fp64 recompute, then integer window",
                    "launch": "hipGraph replay of stage-wise persistent kernels"},
         "fp64_fft": {"ms_per_step": ms64, "mpx_s": total_px / (ms64 * 1e-3) / 1e6,
-                     "stages": {k: {q: v for q, v in roofline_for(k, prof64, args.workload).items() if q != "traffic"}
+                     "stages": {k: {q: v for q, v in roofline_for(k, prof64, args.workload).items() if not q.startswith("traffic")}
                                 for k in prof64 if prof64[k]["alg_ops"] > 0}},
         "speedup_vs_fp64_fft": ms64 / ms,
         "roofline": roof,
