@@ -165,7 +165,7 @@ def measured_traffic(kernel, workload, with_alg=False):
     if not os.path.exists(path):
         path = os.path.join(ROOT, "profiles", f"{kernel.split('<')[0]}_{workload}_traffic.txt")
     if not os.path.exists(path):
-        return None
+        return (None, None) if with_alg else None
     rec = {}
     for line in open(path):
         line = line.strip()
