@@ -1220,10 +1220,11 @@ __global__ __launch_bounds__(G * N) __attribute__((amdgpu_waves_per_eu(fft_reg_w
         const int iy0 = ty * J.T - r, ix0 = tx * J.T - r;
         if (m == 0) {
             // bin 0 in closed form (block-uniform; no LDS use, so the next
-            // item needs no barrier after it)
+            // item needs no barrier after it); left to the decode for dc_dec
+            // jobs
             C *yt = (C *)S.y + (size_t)tl * ytile_elems(J.bins, J.T, J.ybs) + ybin_offset(0, J.T, J.ybs);
             const R bump = perturb_bump<R>(perturb, J, tile, 0, kPerturbFirst);
-            for (int q = threadIdx.x; q < T * T; q += G * N) {
+            for (int q = threadIdx.x; q < (J.dc_dec ? 0 : T * T); q += G * N) {
                 const int i = q / T, j = q - i * T;
                 stg(yt, ypix(q, J.ybs), dc_plane_value<R>(J, N, ty * J.T + i, tx * J.T + j, bump));
             }
@@ -1536,8 +1537,9 @@ __global__ __launch_bounds__(kBigThreads) void k_fft_big(const JobDev *__restric
             // and are not stored
             const int y0 = k - 1 + b * LB;
             if (y0 >= N) continue;   // block-uniform: the whole block skips the unit
-            if (m == 1) {
-                // the same rows of bin 0's plane (global stores only)
+            if (m == 1 && !J.dc_dec) {
+                // the same rows of bin 0's plane (global stores only; for
+                // dc_dec jobs the decode takes bin 0 in closed form)
                 C *d0 = (C *)S.y + (size_t)tl * ytile_elems(J.bins, J.T, J.ybs) + ybin_offset(0, J.T, J.ybs);
                 const R bump0 = perturb_bump<R>(perturb, J, tile, 0, kPerturbFirst);
                 for (int q = threadIdx.x; q < LB * T; q += BS) {
@@ -1708,7 +1710,8 @@ __global__ __launch_bounds__(kDecThreads) void k_decode(const JobDev *__restrict
                                                         const Seg *__restrict__ segs, int nseg,
                                                         long long nitems, float band,
                                                         unsigned int *tile_flags, int2 *fb_list,
-                                                        int2 *win_list, StatsDev *st) {
+                                                        int2 *win_list, StatsDev *st,
+                                                        const uint8_t *__restrict__ perturb) {
     using C = typename Cx<R>::T;
     __shared__ float s_red[kDecThreads / 64];
     float run_max = 0.f;          // largest residual this thread has seen (stats)
@@ -1742,7 +1745,13 @@ __global__ __launch_bounds__(kDecThreads) void k_decode(const JobDev *__restrict
                 unroll_c<MB>([&](auto mq) {
                     constexpr int MM = decltype(mq)::value;
                     xs[Q][MM] = czero<C>();
-                    if (vals[Q] && MM < J.bins) xs[Q][MM] = ldg(X, (size_t)MM * mstride + b0);
+                    if (vals[Q] && MM < J.bins) {
+                        if (MM == 0 && J.dc_dec)   // bin 0 in closed form; the transforms left it unwritten
+                            xs[Q][0] = dc_plane_value<R>(J, J.nt, gys[Q], gxs[Q],
+                                                         perturb_bump<R>(perturb, J, tile, 0, kPerturbFirst));
+                        else
+                            xs[Q][MM] = ldg(X, (size_t)MM * mstride + b0);
+                    }
                 });
             });
             unroll_c<kDecPixPerThread>([&](auto qq) {
@@ -2860,7 +2869,7 @@ hipError_t launch_fft(int nt, int dbl, const JobDev *jobs, const Seg *segs, int 
 
 hipError_t launch_decode(int var, int dbl, const JobDev *jobs, const Seg *segs, int nseg, long long nitems,
                          int grid, float band, unsigned int *tile_flags, int2 *fb_list, int2 *win_list,
-                         StatsDev *st, hipStream_t s) {
+                         StatsDev *st, const uint8_t *perturb, hipStream_t s) {
     if (nitems <= 0) return hipSuccess;
     if (var >= kDecFftVar) {
 #define MD_DFFT(R, M) \
@@ -2937,7 +2946,8 @@ hipError_t launch_decode(int var, int dbl, const JobDev *jobs, const Seg *segs, 
         return hipGetLastError();
     }
 #define MD_DEC(R, V) \
-    k_decode<R, V><<<grid, kDecThreads, 0, s>>>(jobs, segs, nseg, nitems, band, tile_flags, fb_list, win_list, st); \
+    k_decode<R, V><<<grid, kDecThreads, 0, s>>>(jobs, segs, nseg, nitems, band, tile_flags, fb_list, win_list, st, \
+                                                perturb);                                                       \
     break
     if (!dbl) {
         switch (var) {

@@ -85,6 +85,8 @@ struct JobDev {
     int ybs;                     // transform-domain layout of a tile: 0 = [bins][T*T]; else blocks of
                                  // 16 pixels, [ceil(T*T/16)][bins][16], and ybs = bins * 16
     long long flag0;             // first entry of this job in the tile-flag array
+    int dc_dec;                  // 1: the decode computes bin 0 in closed form and the transforms
+                                 // leave its plane unwritten (dense register decodes, bins <= 8)
     // exact recompute of ambiguous tiles
     int fb_mode;                 // kFbNone / kFbFFT64
     int nt64, T64;
@@ -244,9 +246,11 @@ constexpr int decode_fft_pixels(int nr, int dbl) {
 int dec_pitch(int nr);
 // Flagged tiles of FP32 jobs go to fb_list (the FP64 recompute), those of
 // FP64 jobs to win_list (the exact window).
+// perturb: as for launch_fft (the decodes that take bin 0 in closed form,
+// JobDev::dc_dec, add its bump).
 hipError_t launch_decode(int var, int dbl, const JobDev *jobs, const Seg *segs, int nseg,
                          long long nitems, int grid, float band, unsigned int *tile_flags,
-                         int2 *fb_list, int2 *win_list, StatsDev *st, hipStream_t s);
+                         int2 *fb_list, int2 *win_list, StatsDev *st, const uint8_t *perturb, hipStream_t s);
 // vol: volume jobs (a window pass per active SE slab, JobDev::slabs);
 // pack: direct_form()
 hipError_t launch_direct(int pack, int sel, const JobDev *jobs, const Seg *segs, int nseg, long long nitems,

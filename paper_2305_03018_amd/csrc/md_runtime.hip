@@ -64,6 +64,7 @@ struct Options {
     int stream_rows = 0;
     double stream_mb = 2048.0;
     double cache_mb = 16384.0;
+    int dc_plane = 0;   // internal: every job's bin-0 plane is written (md_debug_tile_values reads it)
 };
 
 // Device buffer that only grows; freed when it is destroyed (a cache entry
@@ -1221,6 +1222,9 @@ int build_exec(const md_job *jobs, int n, const std::vector<SEData> &ses, Exec &
         d.scale = 1.0 / ((double)p.nt * p.nt * p.nr);
         d.dec_pitch = dec_pitch(p.nr);
         d.ybs = plan_ybs(p);
+        // the dense register decodes (at most 8 bins) take bin 0 in closed
+        // form: its plane would be a large share of what they read
+        d.dc_dec = !p.dec_fft && p.bins <= 8 && !g.opt.dc_plane;
         d.flag0 = flag_total;
         flag_total += (long long)p.tiles_x * p.tiles_y;
         ex.fft_tiles += (long long)p.tiles_x * p.tiles_y;
@@ -1626,7 +1630,7 @@ int enqueue(Exec &ex, hipStream_t s, bool skip_decode = false, bool capturing = 
             ProfScope ps(prof, s, gr.dbl ? (dfft ? "decode64_fft" : "decode64") : (dfft ? "decode32_fft" : "decode32"),
                          gr.alg_bytes, gr.alg_ops, gr.units);
             MD_HIP(launch_decode(gr.big, gr.dbl, ex.jobs_d, gr.segs_d, (int)gr.segs.size(), gr.nitems, gr.grid,
-                                 band, ex.flags, ex.list, ex.wlist, g.st_d, s));
+                                 band, ex.flags, ex.list, ex.wlist, g.st_d, perturb, s));
             ps.done();
         }
     }
@@ -3053,6 +3057,7 @@ int md_debug_tile_values(const int32_t *img, int H, int W, int L, const uint8_t 
     g.opt.nr = n_r;
     g.opt.precision = precision;
     g.opt.ws_mb = 1e9;
+    g.opt.dc_plane = 1;   // the read-back includes bin 0
     md_job j{img, H, W, L, se_mask, se_offsets, k, nullptr, 0};
     int32_t dummy_out_marker = 0;
     (void)dummy_out_marker;

@@ -149,6 +149,11 @@ def test_perturbed_large_tiles_and_every_decode(dev):
         (180, 170, 64, 9, 16, 64, 0),     # bins 40
         (150, 160, 100, 7, 40, 64, 192),
         (150, 160, 100, 7, 40, 64, 160),
+        # dense register decodes (n_r without an FFT decode, at most 8 bins),
+        # which take bin 0 in closed form and so add the bump themselves
+        (200, 190, 4, 9, 1, 64, 5),       # bins 3
+        (300, 330, 4, 41, 1, 256, 5),     # bins 3, large tiles
+        (200, 190, 8, 9, 4, 64, 15),      # bins 8
     ]
     for H, W, L, k, max_off, tile, nr in cases:
         job = synthetic.random_job(rng, H, W, L, k, p=0.6, max_off=max_off, op=int(rng.integers(0, 2)))

@@ -468,6 +468,32 @@ def test_spectrum_error_report(dev, nr):
                 assert not got[0].imag.any()
 
 
+def test_tile_values_dense_decode_plan(dev):
+    """A plan whose decode takes bin 0 in closed form (n_r = 5, 3 bins): the
+    read-back still holds bin 0's plane, the exact coefficient sums, and the
+    other bins within the spectrum tolerance."""
+    import torch
+
+    rng = np.random.default_rng(41)
+    job = synthetic.random_job(rng, 160, 150, 4, 9, p=0.6, max_off=1)
+    img = torch.from_numpy(job.img).to(dev)
+    nt, nr = 64, 5
+    T = nt - job.k + 1
+    for ty, tx in ((0, 0), (1, 2)):
+        ys, xs = np.divmod(np.arange(T * T), T)
+        counts = oracle.counts_at(job.img, job.mask, job.off, ty * T + ys, tx * T + xs, nr)
+        ref = oracle.range_spectrum_ref(counts, nr).T
+        for prec, tol in ((0, 2e-5), (1, 1e-12)):
+            got = md.debug_tile_values(img, job.mask, job.off, job.L, nt, nr, prec, ty, tx)
+            assert np.linalg.norm(got - ref) / np.linalg.norm(ref) < tol
+            assert np.array_equal(got[0].real, counts.sum(axis=1).astype(np.float64))
+    want = oracle.run_job(job)
+    for opts in (FFT32, FFT64):
+        for t in (64, 256):
+            st = assert_parity(job, dev, want=want, tile=t, nr=nr, **opts)
+            assert st["n_r"] == nr, st
+
+
 def test_ntt_exact_counts(dev):
     """The exact path's transform-domain values of one tile, inverted over
     the range axis on the host with Python integers, are the exact polynomial
