@@ -1336,6 +1336,9 @@ int build_exec(const md_job *jobs, int n, const std::vector<SEData> &ses, Exec &
             // items the transform kernels transform: bin 0 of the floating-
             // point paths is written in closed form instead
             const double fitems = ntt ? items : (double)nt_ * (p.bins - 1);
+            // planes stored in the transform-domain buffer: every bin, but
+            // bin 0 where the decode takes it in closed form (JobDev::dc_dec)
+            const double planes = ex.jobs_h[i].dc_dec ? (double)nt_ * (p.bins - 1) : items;
             // pixels of these tiles that lie inside the image
             double inside = 0;
             for (int t = tile0; t < tile0 + nt_; ++t) {
@@ -1352,7 +1355,7 @@ int build_exec(const md_job *jobs, int n, const std::vector<SEData> &ses, Exec &
             // item out, and in the int32 tile once and the SE spectrum of
             // each transformed bin once (each then serves its other items
             // from L2/MALL)
-            gf->alg_bytes += items * TT * esz + (fitems > 0 ? (double)nt_ * N2 * 4.0 : 0.0) +
+            gf->alg_bytes += planes * TT * esz + (fitems > 0 ? (double)nt_ * N2 * 4.0 : 0.0) +
                              (fitems / nt_) * N2 * esz;
             // FP: flops of the forward and inverse 2-D FFTs and the product;
             // exact: modular products (one per butterfly and per point)
@@ -1365,7 +1368,7 @@ int build_exec(const md_job *jobs, int n, const std::vector<SEData> &ses, Exec &
             s.item0 = gd->nitems;
             gd->segs.push_back(s);
             gd->nitems += (long long)nt_ * s.pblocks;
-            gd->alg_bytes += inside * (p.bins * esz + 4.0);
+            gd->alg_bytes += inside * ((ex.jobs_h[i].dc_dec ? p.bins - 1 : p.bins) * esz + 4.0);
             gd->pixels += inside;
             if (ntt) {
                 // one block of 8 degrees per pixel, over all n bins
