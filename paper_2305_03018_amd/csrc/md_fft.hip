@@ -2277,7 +2277,8 @@ __global__ __launch_bounds__(kDecThreads) void k_decode_small(const JobDev *__re
                                                               const Seg *__restrict__ segs, int nseg,
                                                               long long nitems, float band,
                                                               unsigned int *tile_flags, int2 *fb_list,
-                                                              int2 *win_list, StatsDev *st) {
+                                                              int2 *win_list, StatsDev *st,
+                                                              const uint8_t *__restrict__ perturb) {
     using C = typename Cx<R>::T;
     constexpr int PPT = kDecSmallPix / kDecThreads;   // pixels per thread per item
     __shared__ float s_red[kDecThreads / 64];
@@ -2298,7 +2299,7 @@ __global__ __launch_bounds__(kDecThreads) void k_decode_small(const JobDev *__re
         constexpr int PF = (M + 1) * (int)sizeof(C) / 4 * PPT <= 96 ? PPT : 1;
 #pragma unroll 1
         for (int q0 = 0; q0 < PPT; q0 += PF) {
-            int gy[PF], gx[PF];
+            int gy[PF], gx[PF], wc[PF];
             bool valid[PF];
             C x[PF][M + 1];
             unroll_c<PF>([&](auto qq) {
@@ -2309,9 +2310,18 @@ __global__ __launch_bounds__(kDecThreads) void k_decode_small(const JobDev *__re
                 gx[Q] = tx * T + lx;
                 valid[Q] = p < TT && gy[Q] < J.H && gx[Q] < J.W;
                 const size_t b0 = ypix(valid[Q] ? p : 0, J.ybs);
+                // bin 0 in closed form for dc_dec jobs (the transforms left
+                // its plane unwritten); the count also serves the DC check
+                wc[Q] = valid[Q] ? window_cells(J, gy[Q], gx[Q]) : 0;
                 unroll_c<M + 1>([&](auto m) {
                     constexpr int MM = decltype(m)::value;
-                    x[Q][MM] = ldg(X, b0 + 16 * MM);
+                    if (MM == 0 && J.dc_dec) {
+                        x[Q][0].x = (R)((double)J.nt * J.nt) * (R)wc[Q] +
+                                    perturb_bump<R>(perturb, J, tile, 0, kPerturbFirst);
+                        x[Q][0].y = R(0);
+                    } else {
+                        x[Q][MM] = ldg(X, b0 + 16 * MM);
+                    }
                 });
             });
             unroll_c<PF>([&](auto qq) {
@@ -2338,7 +2348,7 @@ __global__ __launch_bounds__(kDecThreads) void k_decode_small(const JobDev *__re
                     const int d = dd.top < 0 ? 0 : dd.top;
                     gst(J.out)[(size_t)gy[Q] * J.W + gx[Q]] = J.op ? (J.L - 1 - d) : d;
                     run_max = fmaxf(run_max, (float)dd.res);
-                    hit |= px_ambiguous(dd, band, J, gy[Q], gx[Q]);
+                    hit |= (float)dd.res >= band || dd.neg || (int)dd.sum != wc[Q];   // px_ambiguous
                 }
             });
         }
@@ -2879,7 +2889,7 @@ hipError_t launch_decode(int var, int dbl, const JobDev *jobs, const Seg *segs, 
         if (decode_small_m(dm, dbl)) {
 #define MD_DSMALL(R, M) \
     k_decode_small<R, M><<<grid, kDecThreads, 0, s>>>(jobs, segs, nseg, nitems, band, tile_flags, fb_list, win_list, \
-                                                       st); break
+                                                       st, perturb); break
             switch ((dbl ? 100000 : 0) + dm) {
                 case 4: MD_DSMALL(float, 4);
                 case 5: MD_DSMALL(float, 5);

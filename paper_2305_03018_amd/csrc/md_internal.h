@@ -86,7 +86,8 @@ struct JobDev {
                                  // 16 pixels, [ceil(T*T/16)][bins][16], and ybs = bins * 16
     long long flag0;             // first entry of this job in the tile-flag array
     int dc_dec;                  // 1: the decode computes bin 0 in closed form and the transforms
-                                 // leave its plane unwritten (dense register decodes, bins <= 8)
+                                 // leave its plane unwritten (the register decodes: dense with
+                                 // bins <= 8, and the short-length FFT decode)
     // exact recompute of ambiguous tiles
     int fb_mode;                 // kFbNone / kFbFFT64
     int nt64, T64;

@@ -1222,9 +1222,11 @@ int build_exec(const md_job *jobs, int n, const std::vector<SEData> &ses, Exec &
         d.scale = 1.0 / ((double)p.nt * p.nt * p.nr);
         d.dec_pitch = dec_pitch(p.nr);
         d.ybs = plan_ybs(p);
-        // the dense register decodes (at most 8 bins) take bin 0 in closed
-        // form: its plane would be a large share of what they read
-        d.dc_dec = !p.dec_fft && p.bins <= 8 && !g.opt.dc_plane;
+        // the register decodes (the dense ones of at most 8 bins and the
+        // short-length FFT ones) take bin 0 in closed form: its plane need
+        // not be written or read
+        d.dc_dec = ((!p.dec_fft && p.bins <= 8) || (p.dec_fft && decode_small_m(p.nr / 2, p.dbl))) &&
+                   !g.opt.dc_plane;
         d.flag0 = flag_total;
         flag_total += (long long)p.tiles_x * p.tiles_y;
         ex.fft_tiles += (long long)p.tiles_x * p.tiles_y;
